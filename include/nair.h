@@ -1,0 +1,158 @@
+/*
+ * nair.h -- C ABI of the MI355X (gfx950) nAIR library.
+ *
+ * nAIR: reduction-based algebraic multigrid with Neumann approximate ideal
+ * restriction, for block lower triangular (in an unknown order) systems such
+ * as upwind discontinuous-Galerkin discretisations of steady transport
+ * (Manteuffel, Muenzenmaier, Ruge, Southworth, "Nonsymmetric Reduction-based
+ * Algebraic Multigrid"; problem statement in sections 1 and 2.1, method in
+ * sections 4.1 and 5).
+ *
+ * Conventions for every entry point:
+ *   - Matrices are block CSR ("BSR"): nb block rows of bs x bs blocks,
+ *     rowptr[nb+1] and colidx[nnzb] (int32, column indices sorted ascending
+ *     and unique within a row, diagonal block present in every row), vals
+ *     [nnzb][bs][bs] double, each block row-major.
+ *   - Array arguments are DEVICE pointers (memory on the current HIP device),
+ *     unless the comment says "host".  The caller owns them; the library
+ *     never frees or keeps them past the call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is enqueued on it; every call returns only when its device
+ *     work is complete, so outputs may be read right after the call.
+ *   - Errors are return codes; no exception crosses the ABI.  After an error
+ *     the handle (if any) stays valid; nair_last_error gives a message.
+ *   - The library runs one call at a time: calls from several host threads
+ *     must be serialised by the caller (temporary device memory is reused in
+ *     stream order).
+ */
+#ifndef NAIR_H
+#define NAIR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NAIR_OK = 0,
+    NAIR_EINVAL = 1,      /* bad sizes/parameters, unsorted/duplicate columns, missing diagonal */
+    NAIR_ESINGULAR = 2,   /* a diagonal block (or the coarsest operator) has a zero pivot */
+    NAIR_ENOCONV = 3,     /* max_iter reached; output holds the last iterate */
+    NAIR_ENUMERIC = 4,    /* a residual norm is not finite */
+    NAIR_ENOMEM = 5,      /* device allocation failed, or a row exceeds the kernels' limits */
+    NAIR_EDEVICE = 6,     /* a HIP runtime call failed */
+    NAIR_ECOARSEN = 7     /* the splitting stalled on a level too large to solve densely */
+} nair_status;
+
+typedef struct nair_hier_s *nair_hier;
+
+/* Setup parameters (section 5.1 and 5.2 of the paper for the defaults). */
+typedef struct {
+    int32_t degree;           /* Neumann degree k >= 0 of the restriction (section 4.1);
+                                 the F-relaxation does nu = k+1 Jacobi sweeps (section 5.1) */
+    double theta;             /* strength threshold of the C/F splitting, in [0,1): 0.25 */
+    double phi;               /* strength threshold of the Neumann expansion, in [0,1): 0.025 */
+    double drop;              /* drop tolerance of coarse operators, in [0,1): 1e-3 (section 5.2) */
+    int32_t relax;            /* 0: F-relaxation; 1: F then one C sweep (FC) */
+    int32_t max_levels;       /* 1..64, default 30 */
+    int32_t max_coarse_dofs;  /* a level with nb*bs <= this is solved densely; default 512 */
+    uint64_t seed;            /* seed of the splitting's tie-break hash, default 0 */
+    const int8_t *cf_override_host; /* optional, host, [nb] level-0 splitting (1 = C, 0 = F) */
+} nair_params;
+
+typedef struct {
+    int32_t iters;            /* iterations done */
+    int32_t converged;        /* 1 if ||b - A x||_2 / ||b||_2 <= rtol */
+    double relres;            /* final relative residual */
+    double rho_avg;           /* relres^(1/iters) */
+    double rho_last5;         /* (h_K / h_{K-5})^(1/5), or rho_avg if iters <= 5 */
+} nair_result;
+
+/* Device views of one level, for inspection and parity checks.  Pointers stay
+ * valid until nair_destroy.  Arrays a level does not have are NULL. */
+typedef struct {
+    int32_t nb, bs, nnzb, coarsest;
+    const int32_t *rowptr, *colidx;
+    const double *vals;       /* A_l, [nnzb][bs][bs] */
+    const double *dinv;       /* [nb][bs][bs] inverses of the diagonal blocks */
+    const double *bnorm;      /* [nnzb] max-abs size of each block */
+    const uint8_t *mask;      /* [nnzb] bit 0: theta-strong, bit 1: phi-strong */
+    const int32_t *lambda;    /* [nb] number of rows depending theta-strongly on each block */
+    const int8_t *cf;         /* [nb] 1 = C, 0 = F */
+    const int32_t *cidx;      /* [nb] coarse index of C blocks, -1 for F */
+    const int32_t *pmap;      /* [nb] one-point interpolation source (coarse index) or -1 */
+    const int32_t *dround;    /* [nb] splitting round that decided each block (0 = start) */
+    int32_t nc;               /* number of C blocks */
+    int32_t pmis_rounds;
+    int32_t z_nnzb;
+    const int32_t *z_rowptr, *z_colidx;  /* Z of R = [Z I]: nc rows, fine F columns */
+    const double *z_vals;
+    int32_t dense_n;          /* coarsest level: order of the dense operator */
+    const double *dense_inv;  /* coarsest level: its inverse, row-major [dense_n][dense_n] */
+} nair_level_view;
+
+/* Fill *p with the defaults (degree 1, theta 0.25, phi 0.025, drop 1e-3, F
+ * relaxation, 30 levels, 512 dense DOFs, seed 0).  Host only. */
+nair_status nair_default_params(nair_params *p);
+
+/*
+ * Build the nAIR hierarchy of A (sections 2.2, 4.1, 5.1, 5.2): per level,
+ * block-diagonal inverses by batched LU, strength and a seeded parallel C/F
+ * splitting, one-point interpolation, the degree-k Neumann restriction
+ * Z = -A_cf sum_{i<=k} (D_ff^-1 L_ff)^i D_ff^-1 on phi-strong F-F blocks, and
+ * the filtered Galerkin operator K = R A P; the coarsest level is inverted
+ * densely.  A is copied; the caller may free it on return.  *out receives
+ * the handle (NULL on error).
+ */
+nair_status nair_setup(int32_t nb, int32_t bs, const int32_t *rowptr, const int32_t *colidx,
+                       const double *vals, const nair_params *p, void *stream, nair_hier *out);
+
+/*
+ * Solve A x = b by the stationary iteration x += B (b - A x), x_0 = 0, with B
+ * one V-cycle (no pre-relaxation, section 5), until ||b - A x||_2 / ||b||_2 <=
+ * rtol or max_iter iterations.  b and x are device vectors of nb*bs doubles;
+ * x is overwritten.  res (host, may be NULL) receives the statistics.
+ * Returns NAIR_OK, NAIR_ENOCONV (x = last iterate) or NAIR_ENUMERIC.
+ */
+nair_status nair_solve(nair_hier h, const double *b, double *x, double rtol, int32_t max_iter,
+                       nair_result *res, void *stream);
+
+/*
+ * Solve A^T y = g with the transposed cycle B^T: pre-relaxation with D^-T on
+ * F points, restriction by P^T and interpolation by R^T (the ideal
+ * interpolation dual of the paper's section 2.2 corollary).  The transposed
+ * operators are built on the first call.
+ */
+nair_status nair_solve_T(nair_hier h, const double *g, double *y, double rtol, int32_t max_iter,
+                         nair_result *res, void *stream);
+
+/* One cycle application e = B r (resp. y = B^T g), zero initial guess. */
+nair_status nair_vcycle(nair_hier h, const double *r, double *e, void *stream);
+nair_status nair_vcycle_T(nair_hier h, const double *g, double *y, void *stream);
+
+/* Relative residual history of the last solve: buf (host) gets min(cap, n). */
+nair_status nair_history(nair_hier h, double *buf, int32_t cap, int32_t *n);
+
+/* Hierarchy statistics (host outputs; per-level arrays hold up to 64 entries;
+ * any pointer may be NULL).  oc/cc: operator and cycle complexity in work
+ * units of one level-0 SpMV (section 6). */
+nair_status nair_info(nair_hier h, int32_t *levels, int32_t *nb_per_level, int64_t *nnzb_per_level,
+                      double *oc, double *cc);
+
+/* Device views of level lvl (0 = finest). */
+nair_status nair_get_level(nair_hier h, int32_t lvl, nair_level_view *v);
+
+/* Last error message of h (or of the last failed setup if h is NULL). Host string. */
+const char *nair_last_error(nair_hier h);
+
+/* Free the hierarchy (its memory returns to the library's device pool). */
+void nair_destroy(nair_hier h);
+
+/* Return all cached, unused device memory of the pool to HIP. */
+nair_status nair_pool_trim(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

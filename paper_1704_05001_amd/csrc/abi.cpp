@@ -1,0 +1,221 @@
+// The C ABI: argument checks, device selection, error capture.
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+
+#include "hier.h"
+
+struct nair_hier_s {
+    nair::Hier h;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename F>
+nair_status guarded(nair_hier h, F &&body) {
+    try {
+        return body();
+    } catch (const nair::Error &e) {
+        g_last_error = e.msg;
+        if (h) h->h.err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        if (h) h->h.err = g_last_error;
+        return NAIR_ENOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        if (h) h->h.err = g_last_error;
+        return NAIR_EDEVICE;
+    }
+}
+
+nair_status bad(nair_hier h, const std::string &msg) {
+    g_last_error = msg;
+    if (h) h->h.err = msg;
+    return NAIR_EINVAL;
+}
+
+bool unit_interval(double v) { return v >= 0.0 && v < 1.0; }
+
+}  // namespace
+
+extern "C" {
+
+nair_status nair_default_params(nair_params *p) {
+    if (!p) return NAIR_EINVAL;
+    p->degree = 1;
+    p->theta = 0.25;
+    p->phi = 0.025;
+    p->drop = 1e-3;
+    p->relax = 0;
+    p->max_levels = 30;
+    p->max_coarse_dofs = 512;
+    p->seed = 0;
+    p->cf_override_host = nullptr;
+    return NAIR_OK;
+}
+
+nair_status nair_setup(int32_t nb, int32_t bs, const int32_t *rowptr, const int32_t *colidx, const double *vals,
+                       const nair_params *p, void *stream, nair_hier *out) {
+    if (!out) return bad(nullptr, "out is NULL");
+    *out = nullptr;
+    if (!p) return bad(nullptr, "params is NULL");
+    if (nb < 1 || bs < 1 || bs > nair::kMaxBs)
+        return bad(nullptr, "need nb >= 1 and 1 <= bs <= " + std::to_string(nair::kMaxBs));
+    if (static_cast<int64_t>(nb) * bs > 0x7fffffffLL) return bad(nullptr, "nb*bs exceeds int32");
+    if (!rowptr || !colidx || !vals) return bad(nullptr, "NULL matrix array");
+    if (p->degree < 0 || p->degree > 16) return bad(nullptr, "degree must be in [0, 16]");
+    if (!unit_interval(p->theta) || !unit_interval(p->phi) || !unit_interval(p->drop))
+        return bad(nullptr, "theta, phi and drop must lie in [0, 1)");
+    if (p->relax != 0 && p->relax != 1) return bad(nullptr, "relax must be 0 (F) or 1 (FC)");
+    if (p->max_levels < 1 || p->max_levels > nair::kMaxLevels) return bad(nullptr, "max_levels must be in [1, 64]");
+    if (p->max_coarse_dofs < 0 || p->max_coarse_dofs > nair::kStallDenseDofs)
+        return bad(nullptr, "max_coarse_dofs must be in [0, 4096]");
+    nair_hier h = new (std::nothrow) nair_hier_s();
+    if (!h) return NAIR_ENOMEM;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    nair_status st = guarded(h, [&]() -> nair_status {
+        NAIR_HIP(hipGetDevice(&h->h.device));
+        h->h.prm = *p;
+        nair::build_hierarchy(h->h, nb, bs, rowptr, colidx, vals, s);
+        h->h.prm.cf_override_host = nullptr;   // host pointer not kept past the call
+        return NAIR_OK;
+    });
+    if (st != NAIR_OK) {
+        (void)hipStreamSynchronize(s);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return NAIR_OK;
+}
+
+static nair_status solve_common(nair_hier h, bool trans, const double *b, double *x, double rtol, int32_t max_iter,
+                                nair_result *res, void *stream) {
+    if (!h) return bad(nullptr, "handle is NULL");
+    if (!b || !x) return bad(h, "NULL vector");
+    if (!(rtol >= 0.0) || max_iter < 0) return bad(h, "need rtol >= 0 and max_iter >= 0");
+    DeviceGuard dg(h->h.device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return guarded(h, [&]() { return nair::run_solve(h->h, trans, b, x, rtol, max_iter, res, s); });
+}
+
+nair_status nair_solve(nair_hier h, const double *b, double *x, double rtol, int32_t max_iter, nair_result *res,
+                       void *stream) {
+    return solve_common(h, false, b, x, rtol, max_iter, res, stream);
+}
+
+nair_status nair_solve_T(nair_hier h, const double *g, double *y, double rtol, int32_t max_iter, nair_result *res,
+                         void *stream) {
+    return solve_common(h, true, g, y, rtol, max_iter, res, stream);
+}
+
+static nair_status vcycle_common(nair_hier h, bool trans, const double *r, double *e, void *stream) {
+    if (!h) return bad(nullptr, "handle is NULL");
+    if (!r || !e) return bad(h, "NULL vector");
+    DeviceGuard dg(h->h.device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return guarded(h, [&]() {
+        nair::run_vcycle(h->h, trans, r, e, s);
+        return NAIR_OK;
+    });
+}
+
+nair_status nair_vcycle(nair_hier h, const double *r, double *e, void *stream) {
+    return vcycle_common(h, false, r, e, stream);
+}
+
+nair_status nair_vcycle_T(nair_hier h, const double *g, double *y, void *stream) {
+    return vcycle_common(h, true, g, y, stream);
+}
+
+nair_status nair_history(nair_hier h, double *buf, int32_t cap, int32_t *n) {
+    if (!h) return bad(nullptr, "handle is NULL");
+    const int32_t total = static_cast<int32_t>(h->h.hist.size());
+    if (n) *n = total;
+    if (buf)
+        for (int32_t i = 0; i < total && i < cap; ++i) buf[i] = h->h.hist[i];
+    return NAIR_OK;
+}
+
+nair_status nair_info(nair_hier h, int32_t *levels, int32_t *nb_per_level, int64_t *nnzb_per_level, double *oc,
+                      double *cc) {
+    if (!h) return bad(nullptr, "handle is NULL");
+    DeviceGuard dg(h->h.device);
+    return guarded(h, [&]() {
+        const int L = static_cast<int>(h->h.lv.size());
+        if (levels) *levels = L;
+        for (int l = 0; l < L && l < nair::kMaxLevels; ++l) {
+            if (nb_per_level) nb_per_level[l] = h->h.lv[l]->A.nb;
+            if (nnzb_per_level) nnzb_per_level[l] = h->h.lv[l]->A.nnzb;
+        }
+        if (oc || cc) nair::complexity(h->h, oc, cc, nullptr);
+        return NAIR_OK;
+    });
+}
+
+nair_status nair_get_level(nair_hier h, int32_t lvl, nair_level_view *v) {
+    if (!h) return bad(nullptr, "handle is NULL");
+    if (!v || lvl < 0 || lvl >= static_cast<int32_t>(h->h.lv.size())) return bad(h, "bad level or view");
+    const nair::Level &L = *h->h.lv[lvl];
+    std::memset(v, 0, sizeof(*v));
+    v->nb = L.A.nb;
+    v->bs = L.A.bs;
+    v->nnzb = static_cast<int32_t>(L.A.nnzb);
+    v->coarsest = L.coarsest ? 1 : 0;
+    v->rowptr = L.A.rowptr.get();
+    v->colidx = L.A.colidx.get();
+    v->vals = L.A.vals.get();
+    v->dinv = L.dinv.get();
+    v->bnorm = L.bnorm.get();
+    v->mask = L.mask.get();
+    v->lambda = L.lambda.get();
+    v->cf = L.cf.get();
+    v->cidx = L.cidx.get();
+    v->dround = L.dround.get();
+    v->pmis_rounds = L.rounds;
+    if (!L.coarsest) {
+        v->pmap = L.pmap.get();
+        v->nc = L.nc;
+        v->z_nnzb = static_cast<int32_t>(L.Z.nnzb);
+        v->z_rowptr = L.Z.rowptr.get();
+        v->z_colidx = L.Z.colidx.get();
+        v->z_vals = L.Z.vals.get();
+    }
+    v->dense_n = L.dense_n;
+    v->dense_inv = L.dense_inv.get();
+    return NAIR_OK;
+}
+
+const char *nair_last_error(nair_hier h) { return h ? h->h.err.c_str() : g_last_error.c_str(); }
+
+void nair_destroy(nair_hier h) {
+    if (!h) return;
+    DeviceGuard dg(h->h.device);
+    delete h;
+}
+
+nair_status nair_pool_trim(void) {
+    return guarded(nullptr, []() {
+        nair::pool_trim();
+        return NAIR_OK;
+    });
+}
+
+}  // extern "C"

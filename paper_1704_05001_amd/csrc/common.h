@@ -1,0 +1,173 @@
+// Internal declarations of the nAIR HIP library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "nair.h"
+
+namespace nair {
+
+constexpr int kMaxBs = 32;          // largest block size the kernels accept
+constexpr int kMaxLevels = 64;
+constexpr int kStallDenseDofs = 4096;
+constexpr int kHashSmall = 2048;    // LDS hash slots of the per-wave symbolic kernels
+constexpr int kHashLarge = 8192;    // LDS hash slots of the per-workgroup fallback
+
+// ------------------------------------------------------------------ errors
+struct Error {
+    nair_status code;
+    std::string msg;
+};
+
+// Throws nair::Error; caught at the ABI boundary.
+[[noreturn]] void fail(nair_status code, const std::string &msg);
+void check_hip(hipError_t e, const char *what);
+#define NAIR_HIP(call) ::nair::check_hip((call), #call)
+
+// ------------------------------------------------------------ device pool
+// Caching device allocator: freed blocks are kept per size class for reuse,
+// so repeated setups do not call hipMalloc.  Thread safe.
+void *pool_alloc(size_t bytes);
+void pool_free(void *p);
+void pool_trim();
+
+template <typename T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    explicit DBuf(size_t count) { alloc(count); }
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p;
+            n = o.n;
+            o.p = nullptr;
+            o.n = 0;
+        }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        n = count;
+        p = static_cast<T *>(pool_alloc(sizeof(T) * (count ? count : 1)));
+    }
+    void release() {
+        if (p) pool_free(p);
+        p = nullptr;
+        n = 0;
+    }
+    T *get() const { return p; }
+};
+
+// Device block-CSR matrix: nb rows, ncols block columns, bs x bs row-major blocks.
+struct DevBSR {
+    int nb = 0, ncols = 0, bs = 0;
+    int64_t nnzb = 0;
+    DBuf<int> rowptr, colidx;
+    DBuf<double> vals;
+    void alloc(int nb_, int ncols_, int bs_, int64_t nnzb_) {
+        nb = nb_;
+        ncols = ncols_;
+        bs = bs_;
+        nnzb = nnzb_;
+        rowptr.alloc(static_cast<size_t>(nb_) + 1);
+        colidx.alloc(static_cast<size_t>(nnzb_));
+        vals.alloc(static_cast<size_t>(nnzb_) * bs_ * bs_);
+    }
+};
+
+// ------------------------------------------------------------- utilities
+inline unsigned grid_for(int64_t n, int per_block) {
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 2147483647LL) g = 2147483647LL;
+    return static_cast<unsigned>(g);
+}
+
+int read_int(const int *dptr, hipStream_t s);       // synchronous D2H of one int
+void read_ints(const int *dptr, int *host, int n, hipStream_t s);
+
+// Exclusive scan of n ints: out[0..n], out[n] = total.  in may alias nothing in out.
+void scan_exclusive(const int *in, int *out, int n, hipStream_t s);
+
+// ---------------------------------------------------------- setup kernels
+void launch_block_maxabs(const double *vals, int64_t nnzb, int bs, double *out, hipStream_t s);
+void launch_block_inverse(const int *rowptr, const int *colidx, const double *vals, int nb, int bs,
+                          double *dinv, int *singular_min, hipStream_t s);
+void launch_strength(const int *rowptr, const int *colidx, const double *bnorm, int nb, double theta,
+                     double phi, uint8_t *mask, int *lambda, hipStream_t s);
+void launch_strong_transpose(const int *rowptr, const int *colidx, const uint8_t *mask, int nb,
+                             const int *stptr, int *fill, int *stidx, hipStream_t s);
+void launch_pmis_init(const int *lambda, int nb, int8_t *state, int *dround, int *undecided0, hipStream_t s);
+void launch_pmis_round(const int *rowptr, const int *colidx, const uint8_t *mask, const int *stptr,
+                       const int *stidx, const int *lambda, int nb, uint64_t seed, int level, int round,
+                       int8_t *state, int8_t *newc, int *dround, int *undecided, hipStream_t s);
+void launch_cf_flags(const int8_t *state, int nb, int *flags, hipStream_t s);
+void launch_cf_index(const int8_t *cf, const int *cscan, int nb, int *cidx, int *cpts, int *flist,
+                     hipStream_t s);
+void launch_one_point(const int *rowptr, const int *colidx, const double *bnorm, const int8_t *cf,
+                      const int *cidx, int nb, int *pmap, hipStream_t s);
+// T = -(Dinv_I A_IJ) over phi-strong F-F blocks (fine row numbering, C rows empty)
+void launch_count_T(const int *rowptr, const int *colidx, const uint8_t *mask, const int8_t *cf, int nb,
+                    int *cnt, hipStream_t s);
+void launch_fill_T(const int *rowptr, const int *colidx, const uint8_t *mask, const int8_t *cf, int nb,
+                   const int *trowptr, int *tcol, int *trow, int *tsrc, hipStream_t s);
+// W0 = A_cf (coarse rows)
+void launch_count_Acf(const int *rowptr, const int *colidx, const int8_t *cf, const int *cpts, int nc,
+                      int *cnt, hipStream_t s);
+void launch_fill_Acf(const int *rowptr, const int *colidx, const int8_t *cf, const int *cpts, int nc,
+                     const int *wrowptr, int *wcol, int *wsrc, hipStream_t s);
+// out[t] = sign * (X[xi[t]] * Y[yi[t]]) for n blocks (fma chain, c ascending)
+void launch_block_product(int64_t n, int bs, const double *X, const int *xi, const double *Y, const int *yi,
+                          double sign, double *out, hipStream_t s);
+// out[t] = Y[src[t]]
+void launch_block_gather(int64_t n, int bs, const double *Y, const int *src, double *out, hipStream_t s);
+void launch_rows_of(const int *rowptr, int nrows, int *rowid, hipStream_t s);
+
+// ------------------------------------------------------------------ SpGEMM
+// C = X * Y (+ optional implicit identity block of X at column xdiag[i]).
+// Fixed accumulation order: inner index ascending, c ascending, one fma chain.
+void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipStream_t s);
+// O = S + W (union pattern, S's value first)
+void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s);
+// K = RA * P (P one-point through pmap), filtered by drop; returns the filtered K
+void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevBSR &K, hipStream_t s);
+
+// ------------------------------------------------------------------ dense
+// Inverse of the dense operator assembled from a BSR; returns false if singular.
+bool dense_inverse_from_bsr(const DevBSR &A, double *inv, hipStream_t s);
+void launch_dense_matvec(const double *M, const double *x, double *y, int n, bool trans, hipStream_t s);
+
+// -------------------------------------------------------------- transpose
+void bsr_transpose(const DevBSR &A, DevBSR &AT, hipStream_t s);   // blocks transposed too
+void pmap_transpose(const int *pmap, int nb, int nc, DBuf<int> &ptptr, DBuf<int> &ptidx, hipStream_t s);
+
+// ------------------------------------------------------------------ cycle
+void launch_residual(const DevBSR &A, const double *b, const double *x, double *r, double *partials,
+                     int npart, hipStream_t s);
+int residual_partials_count(const DevBSR &A);
+void launch_sumsq(const double *v, int64_t n, double *partials, int npart, hipStream_t s);
+void launch_reduce_partials(const double *partials, int npart, double *out, hipStream_t s);
+// Jacobi sweep over `list` rows (list == nullptr: all rows; then rows with cf != only_cf are copied)
+void launch_relax(const DevBSR &A, const double *dinv, bool dinv_trans, const double *r, const double *ein,
+                  double *eout, const int *list, int nlist, const int8_t *cf, int only_cf, hipStream_t s);
+void launch_restrict(const DevBSR &Z, const double *r, const int *cpts, double *rc, hipStream_t s);
+void launch_interp(const int *pmap, const double *ec, double *e0, double *e1, int nb, int bs, hipStream_t s);
+void launch_restrict_T(const int *ptptr, const int *ptidx, const double *s, double *sc, int nc, int bs,
+                       hipStream_t st);
+void launch_interp_T(const DevBSR &ZT, const int *cidx, const double *yc, double *y, hipStream_t s);
+void launch_init_T(const double *dinv, const double *g, const int8_t *cf, int fc, double *y0, double *y1,
+                   int nb, int bs, hipStream_t s);
+void launch_axpy(double *x, const double *e, int64_t n, hipStream_t s);
+
+}  // namespace nair

@@ -1,0 +1,142 @@
+// Coarsest level: dense operator, its inverse by Gauss-Jordan elimination with
+// partial pivoting (one 1024-thread workgroup; the operator has at most a few
+// thousand unknowns), and the dense matrix-vector products of the cycle.
+#include "common.h"
+
+namespace nair {
+namespace {
+
+constexpr int kGJThreads = 1024;
+
+__global__ __launch_bounds__(256) void k_bsr_to_dense(const int *__restrict__ rowptr, const int *__restrict__ colidx,
+                                                     const double *__restrict__ vals, int nb, int bs,
+                                                     double *__restrict__ M, int n) {
+    const int I = blockIdx.x;
+    if (I >= nb) return;
+    const int bb = bs * bs;
+    for (int t = rowptr[I]; t < rowptr[I + 1]; ++t) {
+        const int J = colidx[t];
+        for (int e = threadIdx.x; e < bb; e += blockDim.x) {
+            const int a = e / bs, b = e - a * bs;
+            M[static_cast<int64_t>(I * bs + a) * n + J * bs + b] = vals[static_cast<int64_t>(t) * bb + e];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kGJThreads) void k_gauss_jordan(double *__restrict__ M, double *__restrict__ Inv, int n,
+                                                            double *__restrict__ colk, int *__restrict__ singular) {
+    __shared__ double rv[kGJThreads];
+    __shared__ int ri[kGJThreads];
+    const int tid = threadIdx.x;
+    const int64_t nn = static_cast<int64_t>(n) * n;
+    for (int64_t e = tid; e < nn; e += kGJThreads) Inv[e] = (e / n == e % n) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        double v = -1.0;
+        int idx = n;
+        for (int i = k + tid; i < n; i += kGJThreads) {
+            const double av = fabs(M[static_cast<int64_t>(i) * n + k]);
+            if (av > v || (av == v && i < idx)) {
+                v = av;
+                idx = i;
+            }
+        }
+        rv[tid] = v;
+        ri[tid] = idx;
+        __syncthreads();
+        for (int s = kGJThreads / 2; s > 0; s >>= 1) {
+            if (tid < s) {
+                const double ov = rv[tid + s];
+                const int oi = ri[tid + s];
+                if (ov > rv[tid] || (ov == rv[tid] && oi < ri[tid])) {
+                    rv[tid] = ov;
+                    ri[tid] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        const double best = rv[0];
+        const int p = ri[0];
+        __syncthreads();
+        if (!(best > 0.0)) {
+            if (tid == 0) *singular = 1;
+            return;
+        }
+        if (p != k) {
+            for (int j = tid; j < n; j += kGJThreads) {
+                double t = M[static_cast<int64_t>(k) * n + j];
+                M[static_cast<int64_t>(k) * n + j] = M[static_cast<int64_t>(p) * n + j];
+                M[static_cast<int64_t>(p) * n + j] = t;
+                t = Inv[static_cast<int64_t>(k) * n + j];
+                Inv[static_cast<int64_t>(k) * n + j] = Inv[static_cast<int64_t>(p) * n + j];
+                Inv[static_cast<int64_t>(p) * n + j] = t;
+            }
+        }
+        __syncthreads();
+        const double piv = M[static_cast<int64_t>(k) * n + k];
+        __syncthreads();
+        for (int j = tid; j < n; j += kGJThreads) {
+            M[static_cast<int64_t>(k) * n + j] /= piv;
+            Inv[static_cast<int64_t>(k) * n + j] /= piv;
+        }
+        __syncthreads();
+        for (int i = tid; i < n; i += kGJThreads) colk[i] = M[static_cast<int64_t>(i) * n + k];
+        __syncthreads();
+        for (int64_t e = tid; e < nn; e += kGJThreads) {
+            const int i = static_cast<int>(e / n);
+            if (i == k) continue;
+            const int j = static_cast<int>(e - static_cast<int64_t>(i) * n);
+            const double f = colk[i];
+            if (f == 0.0) continue;
+            if (j > k) M[e] -= f * M[static_cast<int64_t>(k) * n + j];
+            Inv[e] -= f * Inv[static_cast<int64_t>(k) * n + j];
+        }
+        __syncthreads();
+    }
+}
+
+// y = M x: one wave per row.
+__global__ __launch_bounds__(256) void k_dense_mv(const double *__restrict__ M, const double *__restrict__ x,
+                                                 double *__restrict__ y, int n) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= n) return;
+    const double *m = M + static_cast<int64_t>(row) * n;
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64) s += m[j] * x[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) y[row] = s;
+}
+
+// y = M^T x: one thread per column (coalesced along rows).
+__global__ __launch_bounds__(256) void k_dense_mtv(const double *__restrict__ M, const double *__restrict__ x,
+                                                  double *__restrict__ y, int n) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += M[static_cast<int64_t>(i) * n + j] * x[i];
+    y[j] = s;
+}
+
+}  // namespace
+
+bool dense_inverse_from_bsr(const DevBSR &A, double *inv, hipStream_t s) {
+    const int n = A.nb * A.bs;
+    DBuf<double> M(static_cast<size_t>(n) * n), colk(n);
+    DBuf<int> sing(1);
+    NAIR_HIP(hipMemsetAsync(M.get(), 0, sizeof(double) * static_cast<size_t>(n) * n, s));
+    NAIR_HIP(hipMemsetAsync(sing.get(), 0, sizeof(int), s));
+    k_bsr_to_dense<<<A.nb, 256, 0, s>>>(A.rowptr.get(), A.colidx.get(), A.vals.get(), A.nb, A.bs, M.get(), n);
+    k_gauss_jordan<<<1, kGJThreads, 0, s>>>(M.get(), inv, n, colk.get(), sing.get());
+    NAIR_HIP(hipGetLastError());
+    return read_int(sing.get(), s) == 0;
+}
+
+void launch_dense_matvec(const double *M, const double *x, double *y, int n, bool trans, hipStream_t s) {
+    if (trans) k_dense_mtv<<<grid_for(n, 256), 256, 0, s>>>(M, x, y, n);
+    else k_dense_mv<<<grid_for(n, 4), 256, 0, s>>>(M, x, y, n);
+    NAIR_HIP(hipGetLastError());
+}
+
+}  // namespace nair

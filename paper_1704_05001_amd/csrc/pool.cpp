@@ -1,0 +1,114 @@
+// Caching device allocator and small host/device helpers.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "common.h"
+
+namespace nair {
+
+void fail(nair_status code, const std::string &msg) { throw Error{code, msg}; }
+
+void check_hip(hipError_t e, const char *what) {
+    if (e != hipSuccess) {
+        nair_status code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? NAIR_ENOMEM : NAIR_EDEVICE;
+        fail(code, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+namespace {
+
+// Size classes: multiples of 256 B up to 64 KiB, then 8 classes per power of two
+// (at most 12.5% slack).  Freed blocks are kept per (device, class).
+size_t size_class(size_t bytes) {
+    if (bytes <= 65536) return (bytes + 255) & ~static_cast<size_t>(255);
+    int lg = 63 - __builtin_clzll(bytes);
+    size_t step = static_cast<size_t>(1) << (lg - 3);
+    return (bytes + step - 1) / step * step;
+}
+
+struct Pool {
+    std::mutex mu;
+    std::unordered_map<void *, std::pair<int, size_t>> live;         // ptr -> (device, class)
+    std::map<std::pair<int, size_t>, std::vector<void *>> free_list;  // (device, class) -> ptrs
+};
+
+Pool &pool() {
+    static Pool *p = new Pool();   // never destroyed: frees at exit would race the runtime teardown
+    return *p;
+}
+
+}  // namespace
+
+void *pool_alloc(size_t bytes) {
+    int dev = 0;
+    NAIR_HIP(hipGetDevice(&dev));
+    size_t cls = size_class(bytes ? bytes : 1);
+    Pool &P = pool();
+    {
+        std::lock_guard<std::mutex> lk(P.mu);
+        auto it = P.free_list.find({dev, cls});
+        if (it != P.free_list.end() && !it->second.empty()) {
+            void *p = it->second.back();
+            it->second.pop_back();
+            P.live[p] = {dev, cls};
+            return p;
+        }
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, cls);
+    if (e != hipSuccess) {
+        // release cached blocks and retry once
+        (void)hipGetLastError();
+        pool_trim();
+        e = hipMalloc(&p, cls);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(NAIR_ENOMEM, "device allocation of " + std::to_string(cls) + " bytes failed");
+        }
+    }
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.live[p] = {dev, cls};
+    return p;
+}
+
+void pool_free(void *p) {
+    if (!p) return;
+    Pool &P = pool();
+    std::lock_guard<std::mutex> lk(P.mu);
+    auto it = P.live.find(p);
+    if (it == P.live.end()) return;
+    P.free_list[it->second].push_back(p);
+    P.live.erase(it);
+}
+
+void pool_trim() {
+    Pool &P = pool();
+    std::lock_guard<std::mutex> lk(P.mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : P.free_list) {
+        (void)hipSetDevice(kv.first.first);
+        for (void *p : kv.second) (void)hipFree(p);
+        kv.second.clear();
+    }
+    (void)hipSetDevice(cur);
+}
+
+int read_int(const int *dptr, hipStream_t s) {
+    int v = 0;
+    NAIR_HIP(hipMemcpyAsync(&v, dptr, sizeof(int), hipMemcpyDeviceToHost, s));
+    NAIR_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+void read_ints(const int *dptr, int *host, int n, hipStream_t s) {
+    NAIR_HIP(hipMemcpyAsync(host, dptr, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+    NAIR_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace nair

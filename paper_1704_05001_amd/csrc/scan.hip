@@ -1,0 +1,106 @@
+// Exclusive prefix sums of int32 arrays (three-phase: tile scan, tile-offset scan, add).
+#include "common.h"
+
+namespace nair {
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// Exclusive scan of one value per thread over a 256-thread block; returns the
+// prefix and writes the block total to *total.
+__device__ int block_exclusive_scan(int v, int *lds_waves, int *total) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds_waves[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) {
+            int t = lds_waves[w];
+            lds_waves[w] = run;
+            run += t;
+        }
+        lds_waves[kScanThreads / 64] = run;
+    }
+    __syncthreads();
+    int res = x - v + lds_waves[wave];
+    *total = lds_waves[kScanThreads / 64];
+    __syncthreads();
+    return res;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int *__restrict__ in, int *__restrict__ out,
+                                                            int n, int *__restrict__ tile_sums) {
+    __shared__ int lds[kScanThreads / 64 + 1];
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        v[k] = (i < n) ? in[i] : 0;
+        s += v[k];
+    }
+    int total;
+    int pre = block_exclusive_scan(s, lds, &total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        if (i < n) out[i] = pre;
+        pre += v[k];
+    }
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+// One block scans the tile sums in chunks of 256 with a running carry.
+__global__ __launch_bounds__(kScanThreads) void k_scan_tile_sums(int *__restrict__ tile_sums, int ntiles,
+                                                                int *__restrict__ grand_total) {
+    __shared__ int lds[kScanThreads / 64 + 1];
+    int carry = 0;
+    for (int c0 = 0; c0 < ntiles; c0 += kScanThreads) {
+        int i = c0 + threadIdx.x;
+        int v = (i < ntiles) ? tile_sums[i] : 0;
+        int total;
+        int pre = block_exclusive_scan(v, lds, &total);
+        if (i < ntiles) tile_sums[i] = pre + carry;
+        carry += total;
+    }
+    if (threadIdx.x == 0) *grand_total = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(int *__restrict__ out, int n,
+                                                          const int *__restrict__ tile_sums) {
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
+    const int add = tile_sums[blockIdx.x];
+    for (int k = threadIdx.x; k < kScanTile; k += kScanThreads) {
+        int64_t i = base + k;
+        if (i < n) out[i] += add;
+    }
+}
+
+}  // namespace
+
+void scan_exclusive(const int *in, int *out, int n, hipStream_t s) {
+    if (n <= 0) {
+        NAIR_HIP(hipMemsetAsync(out, 0, sizeof(int), s));
+        return;
+    }
+    const int ntiles = static_cast<int>((static_cast<int64_t>(n) + kScanTile - 1) / kScanTile);
+    DBuf<int> tiles(ntiles);
+    k_scan_tiles<<<ntiles, kScanThreads, 0, s>>>(in, out, n, tiles.get());
+    k_scan_tile_sums<<<1, kScanThreads, 0, s>>>(tiles.get(), ntiles, out + n);
+    k_scan_add<<<ntiles, kScanThreads, 0, s>>>(out, n, tiles.get());
+    NAIR_HIP(hipGetLastError());
+    // `tiles` returns to the pool now; any later user of that memory is ordered after
+    // these kernels on the same stream (the library runs one call at a time).
+}
+
+}  // namespace nair

@@ -1,0 +1,286 @@
+// Hierarchy build (host orchestration of the setup kernels).
+//
+// Per level (sections 4.1, 5.1, 5.2 of the paper):
+//   block sizes and block-diagonal inverses -> strength -> C/F splitting ->
+//   coarse numbering -> one-point interpolation -> Neumann restriction
+//   Z = -(sum_{i<=k} A_cf T^i) D_ff^{-1} with T = -D_ff^{-1} A_ff^phi ->
+//   R A by SpGEMM -> K = (R A) P through the one-point map, drop filter.
+// The coarsest level (or a level whose splitting stalls) is inverted densely.
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <initializer_list>
+#include <utility>
+
+#include "hier.h"
+
+namespace nair {
+namespace {
+
+constexpr int kRoundBatch = 4;
+constexpr int kMaxRounds = 4096;
+constexpr int kNoSingular = 0x7f7f7f7f;   // memset(0x7f) pattern
+
+void read_many(std::initializer_list<std::pair<const int *, int *>> items, hipStream_t s) {
+    for (auto &it : items) NAIR_HIP(hipMemcpyAsync(it.second, it.first, sizeof(int), hipMemcpyDeviceToHost, s));
+    NAIR_HIP(hipStreamSynchronize(s));
+}
+
+void alloc_vectors(Level &L, int bs) {
+    const size_t n = static_cast<size_t>(L.A.nb) * bs;
+    L.r.alloc(n);
+    L.e0.alloc(n);
+    L.e1.alloc(n);
+    L.tmp.alloc(n);
+}
+
+void make_coarsest(Level &L, int lvl, hipStream_t s) {
+    L.coarsest = true;
+    L.dense_n = L.A.nb * L.A.bs;
+    L.dense_inv.alloc(static_cast<size_t>(L.dense_n) * L.dense_n);
+    if (!dense_inverse_from_bsr(L.A, L.dense_inv.get(), s))
+        fail(NAIR_ESINGULAR, "coarsest operator (level " + std::to_string(lvl) + ", " +
+                                 std::to_string(L.dense_n) + " unknowns) is singular");
+}
+
+// C/F splitting by independent-set rounds; state ends as 1 (C) / 0 (F) in L.cf.
+void split(Hier &h, Level &L, int lvl, hipStream_t s) {
+    const int n = L.A.nb;
+    const int64_t nz = L.A.nnzb;
+    DBuf<int> stptr(static_cast<size_t>(n) + 1), fill(n), stidx(nz > 0 ? nz : 1);
+    scan_exclusive(L.lambda.get(), stptr.get(), n, s);
+    NAIR_HIP(hipMemsetAsync(fill.get(), 0, sizeof(int) * n, s));
+    launch_strong_transpose(L.A.rowptr.get(), L.A.colidx.get(), L.mask.get(), n, stptr.get(), fill.get(),
+                            stidx.get(), s);
+    DBuf<int8_t> newc(n);
+    DBuf<int> counts(kMaxRounds + 1);
+    NAIR_HIP(hipMemsetAsync(counts.get(), 0, sizeof(int) * (kMaxRounds + 1), s));
+    launch_pmis_init(L.lambda.get(), n, L.cf.get(), L.dround.get(), counts.get(), s);
+    int undecided0 = read_int(counts.get(), s);
+    L.rounds = 0;
+    if (undecided0 == 0) return;
+    int r = 0;
+    while (true) {
+        for (int b = 0; b < kRoundBatch; ++b) {
+            ++r;
+            launch_pmis_round(L.A.rowptr.get(), L.A.colidx.get(), L.mask.get(), stptr.get(), stidx.get(),
+                              L.lambda.get(), n, h.prm.seed, lvl, r, L.cf.get(), newc.get(), L.dround.get(),
+                              counts.get() + r, s);
+        }
+        int hc[kRoundBatch];
+        read_ints(counts.get() + r - kRoundBatch + 1, hc, kRoundBatch, s);
+        for (int b = 0; b < kRoundBatch; ++b)
+            if (hc[b] == 0) {
+                L.rounds = r - kRoundBatch + 1 + b;
+                return;
+            }
+        if (r + kRoundBatch > kMaxRounds) fail(NAIR_ECOARSEN, "splitting did not finish");
+    }
+}
+
+}  // namespace
+
+void build_hierarchy(Hier &h, int nb, int bs, const int *rowptr, const int *colidx, const double *vals,
+                     hipStream_t s) {
+    const nair_params &p = h.prm;
+    h.bs = bs;
+    const int bb = bs * bs;
+    const int nnzb = read_int(rowptr + nb, s);
+    if (nnzb < nb) fail(NAIR_EINVAL, "rowptr[nb] < nb: every row needs its diagonal block");
+    {
+        DBuf<int> bad(1);
+        NAIR_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), s));
+        launch_validate(rowptr, colidx, nb, nnzb, bad.get(), s);
+        const int vb = read_int(bad.get(), s);
+        if (vb & 1) fail(NAIR_EINVAL, "rowptr is not a non-decreasing offset array from 0 to nnzb");
+        if (vb & 2) fail(NAIR_EINVAL, "column index out of range");
+        if (vb & 4) fail(NAIR_EINVAL, "block columns of a row are not strictly increasing");
+        if (vb & 8) fail(NAIR_EINVAL, "a row has no diagonal block");
+    }
+    {
+        auto L0 = std::make_unique<Level>();
+        L0->A.alloc(nb, nb, bs, nnzb);
+        NAIR_HIP(hipMemcpyAsync(L0->A.rowptr.get(), rowptr, sizeof(int) * (static_cast<size_t>(nb) + 1),
+                                hipMemcpyDeviceToDevice, s));
+        NAIR_HIP(hipMemcpyAsync(L0->A.colidx.get(), colidx, sizeof(int) * static_cast<size_t>(nnzb),
+                                hipMemcpyDeviceToDevice, s));
+        NAIR_HIP(hipMemcpyAsync(L0->A.vals.get(), vals, sizeof(double) * static_cast<size_t>(nnzb) * bb,
+                                hipMemcpyDeviceToDevice, s));
+        h.lv.push_back(std::move(L0));
+    }
+    for (int l = 0;; ++l) {
+        Level &L = *h.lv[l];
+        const int n = L.A.nb;
+        alloc_vectors(L, bs);
+        if (static_cast<int64_t>(n) * bs <= p.max_coarse_dofs || l == p.max_levels - 1) {
+            make_coarsest(L, l, s);
+            break;
+        }
+        const int64_t nz = L.A.nnzb;
+        L.dinv.alloc(static_cast<size_t>(n) * bb);
+        L.bnorm.alloc(nz);
+        L.mask.alloc(nz);
+        L.lambda.alloc(n);
+        L.cf.alloc(n);
+        L.cidx.alloc(n);
+        L.pmap.alloc(n);
+        L.dround.alloc(n);
+        DBuf<int> sing(1);
+        NAIR_HIP(hipMemsetAsync(sing.get(), 0x7f, sizeof(int), s));
+        NAIR_HIP(hipMemsetAsync(L.lambda.get(), 0, sizeof(int) * n, s));
+        launch_block_maxabs(L.A.vals.get(), nz, bs, L.bnorm.get(), s);
+        launch_block_inverse(L.A.rowptr.get(), L.A.colidx.get(), L.A.vals.get(), n, bs, L.dinv.get(), sing.get(), s);
+        launch_strength(L.A.rowptr.get(), L.A.colidx.get(), L.bnorm.get(), n, p.theta, p.phi, L.mask.get(),
+                        L.lambda.get(), s);
+        if (l == 0 && p.cf_override_host) {
+            std::vector<int8_t> cfh(n);
+            for (int I = 0; I < n; ++I) cfh[I] = p.cf_override_host[I] ? 1 : 0;
+            NAIR_HIP(hipMemcpyAsync(L.cf.get(), cfh.data(), n, hipMemcpyHostToDevice, s));
+            NAIR_HIP(hipMemsetAsync(L.dround.get(), 0, sizeof(int) * n, s));
+            NAIR_HIP(hipStreamSynchronize(s));   // cfh is pageable host memory
+            L.rounds = 0;
+        } else {
+            split(h, L, l, s);
+        }
+        DBuf<int> cflag(n), cscan(static_cast<size_t>(n) + 1);
+        launch_cf_flags(L.cf.get(), n, cflag.get(), s);
+        scan_exclusive(cflag.get(), cscan.get(), n, s);
+        int hsing = 0, nc = 0;
+        read_many({{sing.get(), &hsing}, {cscan.get() + n, &nc}}, s);
+        if (hsing != kNoSingular)
+            fail(NAIR_ESINGULAR, "diagonal block " + std::to_string(hsing) + " of level " + std::to_string(l) +
+                                     " is singular");
+        if (nc == 0 || nc == n) {
+            if (static_cast<int64_t>(n) * bs <= kStallDenseDofs) {
+                make_coarsest(L, l, s);
+                break;
+            }
+            fail(NAIR_ECOARSEN, "splitting of level " + std::to_string(l) + " (" + std::to_string(n) +
+                                    " blocks) gave " + std::to_string(nc) + " C blocks");
+        }
+        L.nc = nc;
+        L.nF = n - nc;
+        L.cpts.alloc(nc);
+        L.flist.alloc(L.nF);
+        launch_cf_index(L.cf.get(), cscan.get(), n, L.cidx.get(), L.cpts.get(), L.flist.get(), s);
+        launch_one_point(L.A.rowptr.get(), L.A.colidx.get(), L.bnorm.get(), L.cf.get(), L.cidx.get(), n,
+                         L.pmap.get(), s);
+
+        // Neumann operands: T (phi-strong F-F, scaled by -D_ff^{-1}) and W_0 = A_cf
+        DevBSR T, W0;
+        T.nb = n;
+        T.ncols = n;
+        T.bs = bs;
+        T.rowptr.alloc(static_cast<size_t>(n) + 1);
+        W0.nb = nc;
+        W0.ncols = n;
+        W0.bs = bs;
+        W0.rowptr.alloc(static_cast<size_t>(nc) + 1);
+        {
+            DBuf<int> cntT(n), cntW(nc);
+            launch_count_T(L.A.rowptr.get(), L.A.colidx.get(), L.mask.get(), L.cf.get(), n, cntT.get(), s);
+            scan_exclusive(cntT.get(), T.rowptr.get(), n, s);
+            launch_count_Acf(L.A.rowptr.get(), L.A.colidx.get(), L.cf.get(), L.cpts.get(), nc, cntW.get(), s);
+            scan_exclusive(cntW.get(), W0.rowptr.get(), nc, s);
+        }
+        int nT = 0, nW = 0;
+        read_many({{T.rowptr.get() + n, &nT}, {W0.rowptr.get() + nc, &nW}}, s);
+        T.nnzb = nT;
+        T.colidx.alloc(nT);
+        T.vals.alloc(static_cast<size_t>(nT) * bb);
+        {
+            DBuf<int> trow(nT), tsrc(nT);
+            launch_fill_T(L.A.rowptr.get(), L.A.colidx.get(), L.mask.get(), L.cf.get(), n, T.rowptr.get(),
+                          T.colidx.get(), trow.get(), tsrc.get(), s);
+            launch_block_product(nT, bs, L.dinv.get(), trow.get(), L.A.vals.get(), tsrc.get(), -1.0, T.vals.get(),
+                                 s);
+        }
+        W0.nnzb = nW;
+        W0.colidx.alloc(nW);
+        W0.vals.alloc(static_cast<size_t>(nW) * bb);
+        {
+            DBuf<int> wsrc(nW);
+            launch_fill_Acf(L.A.rowptr.get(), L.A.colidx.get(), L.cf.get(), L.cpts.get(), nc, W0.rowptr.get(),
+                            W0.colidx.get(), wsrc.get(), s);
+            launch_block_gather(nW, bs, L.A.vals.get(), wsrc.get(), W0.vals.get(), s);
+        }
+        // S = ((W_0 + W_1) + W_2) + ...,  W_i = W_{i-1} T
+        DevBSR Wprev = std::move(W0);
+        DevBSR S;
+        bool s_is_wprev = true;
+        for (int d = 1; d <= p.degree; ++d) {
+            DevBSR Wd;
+            spgemm(Wprev, nullptr, T, Wd, s);
+            DevBSR Snew;
+            bsr_add(s_is_wprev ? Wprev : S, Wd, Snew, s);
+            S = std::move(Snew);
+            s_is_wprev = false;
+            Wprev = std::move(Wd);
+        }
+        DevBSR &Ssum = s_is_wprev ? Wprev : S;
+        // Z_IJ = -(S_IJ Dinv_J)
+        L.Z.nb = nc;
+        L.Z.ncols = n;
+        L.Z.bs = bs;
+        L.Z.nnzb = Ssum.nnzb;
+        L.Z.rowptr = std::move(Ssum.rowptr);
+        L.Z.colidx = std::move(Ssum.colidx);
+        L.Z.vals.alloc(static_cast<size_t>(L.Z.nnzb) * bb);
+        launch_block_product(L.Z.nnzb, bs, Ssum.vals.get(), nullptr, L.dinv.get(), L.Z.colidx.get(), -1.0,
+                             L.Z.vals.get(), s);
+        // Galerkin: R A with R = [Z I], then K = (R A) P, filtered
+        DevBSR RA;
+        spgemm(L.Z, L.cpts.get(), L.A, RA, s);
+        auto next = std::make_unique<Level>();
+        rap_merge_drop(RA, L.pmap.get(), nc, p.drop, next->A, s);
+        h.lv.push_back(std::move(next));
+    }
+    NAIR_HIP(hipStreamSynchronize(s));
+}
+
+void ensure_transposes(Hier &h, hipStream_t s) {
+    for (auto &Lp : h.lv) {
+        Level &L = *Lp;
+        if (L.have_T) continue;
+        bsr_transpose(L.A, L.AT, s);
+        if (!L.coarsest) {
+            bsr_transpose(L.Z, L.ZT, s);
+            pmap_transpose(L.pmap.get(), L.A.nb, L.nc, L.ptptr, L.ptidx, s);
+        }
+        L.have_T = true;
+    }
+    NAIR_HIP(hipStreamSynchronize(s));
+}
+
+void complexity(Hier &h, double *oc, double *cc, hipStream_t s) {
+    const double nnz0 = static_cast<double>(h.lv[0]->A.nnzb);
+    const int nu = h.prm.degree + 1;
+    double o = 0.0, c = 1.0;
+    for (auto &Lp : h.lv) {
+        Level &L = *Lp;
+        o += static_cast<double>(L.A.nnzb) / nnz0;
+        if (L.coarsest) {
+            c += static_cast<double>(L.dense_n) * L.dense_n / (static_cast<double>(L.A.bs) * L.A.bs) / nnz0;
+            continue;
+        }
+        std::vector<int> rp(L.A.nb + 1);
+        std::vector<int8_t> cfh(L.A.nb);
+        NAIR_HIP(hipMemcpyAsync(rp.data(), L.A.rowptr.get(), sizeof(int) * rp.size(), hipMemcpyDeviceToHost, s));
+        NAIR_HIP(hipMemcpyAsync(cfh.data(), L.cf.get(), cfh.size(), hipMemcpyDeviceToHost, s));
+        NAIR_HIP(hipStreamSynchronize(s));
+        double nzF = 0, nzC = 0, nbF = 0;
+        for (int I = 0; I < L.A.nb; ++I) {
+            const double rn = rp[I + 1] - rp[I];
+            if (cfh[I] == 1) nzC += rn;
+            else {
+                nzF += rn;
+                nbF += 1;
+            }
+        }
+        c += (nu * nzF + (h.prm.relax == 1 ? nzC : 0.0) + static_cast<double>(L.Z.nnzb) + nbF) / nnz0;
+    }
+    if (oc) *oc = o;
+    if (cc) *cc = c;
+}
+
+}  // namespace nair

@@ -1,0 +1,552 @@
+// Setup-phase kernels: block sizes, block-diagonal inverses, strength, C/F
+// splitting, one-point interpolation and the block products of the Neumann
+// restriction.  Values that feed later comparisons are computed in one fixed
+// order (fma chains, c ascending), with no implicit contraction.
+#include "common.h"
+
+#pragma clang fp contract(off)
+
+namespace nair {
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// ----------------------------------------------------------- block sizes
+
+// out[b] = max_e |vals[b][e]|; one wave per block, four blocks per workgroup.
+__global__ __launch_bounds__(256) void k_block_maxabs(const double *__restrict__ vals, int64_t nnzb, int bb,
+                                                     double *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * 4;
+    for (int64_t blk = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6); blk < nnzb; blk += stride) {
+        const double *p = vals + blk * bb;
+        double m = 0.0;
+        for (int e = lane; e < bb; e += kWave) m = fmax(m, fabs(p[e]));
+        m = wave_max(m);
+        if (lane == 0) out[blk] = m;
+    }
+}
+
+// -------------------------------------------------- diagonal block inverse
+
+// One wave per block row.  LU with partial pivoting (first row of largest
+// |a_ik|, whole-row exchange), multipliers by division, trailing update
+// a_ij = fma(-a_ik, a_kj, a_ij); then column j of the inverse by forward
+// substitution of P e_j (fma, m ascending) and back substitution (fma over
+// m > i ascending, one division by u_ii).  LDS: a[bs*bs], y[bs*bs], perm[bs].
+__global__ __launch_bounds__(64) void k_block_inverse(const int *__restrict__ rowptr, const int *__restrict__ colidx,
+                                                     const double *__restrict__ vals, int nb, int bs,
+                                                     double *__restrict__ dinv, int *__restrict__ singular_min) {
+    extern __shared__ double lds[];
+    const int bb = bs * bs;
+    double *a = lds;
+    double *y = lds + bb;
+    int *perm = reinterpret_cast<int *>(y + bb);
+    __shared__ int dpos;
+    const int lane = threadIdx.x;
+    for (int I = blockIdx.x; I < nb; I += gridDim.x) {
+        if (lane == 0) dpos = -1;
+        __syncthreads();
+        for (int t = rowptr[I] + lane; t < rowptr[I + 1]; t += kWave)
+            if (colidx[t] == I) dpos = t;
+        __syncthreads();
+        if (dpos < 0) {   // validated before; never taken for valid input
+            if (lane == 0) atomicMin(singular_min, I);
+            __syncthreads();
+            continue;
+        }
+        const double *src = vals + static_cast<int64_t>(dpos) * bb;
+        for (int e = lane; e < bb; e += kWave) a[e] = src[e];
+        for (int i = lane; i < bs; i += kWave) perm[i] = i;
+        __syncthreads();
+        bool singular = false;
+        for (int k = 0; k < bs; ++k) {
+            double v = -1.0;
+            int idx = bs;
+            for (int i = k + lane; i < bs; i += kWave) {
+                double av = fabs(a[i * bs + k]);
+                if (av > v || (av == v && i < idx)) {
+                    v = av;
+                    idx = i;
+                }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                double ov = __shfl_xor(v, o, kWave);
+                int oi = __shfl_xor(idx, o, kWave);
+                if (ov > v || (ov == v && oi < idx)) {
+                    v = ov;
+                    idx = oi;
+                }
+            }
+            if (!(v > 0.0)) {
+                singular = true;
+                break;
+            }
+            if (idx != k) {
+                for (int j = lane; j < bs; j += kWave) {
+                    double tmp = a[k * bs + j];
+                    a[k * bs + j] = a[idx * bs + j];
+                    a[idx * bs + j] = tmp;
+                }
+                if (lane == 0) {
+                    int tp = perm[k];
+                    perm[k] = perm[idx];
+                    perm[idx] = tp;
+                }
+            }
+            __syncthreads();
+            const double piv = a[k * bs + k];
+            for (int i = k + 1 + lane; i < bs; i += kWave) a[i * bs + k] = a[i * bs + k] / piv;
+            __syncthreads();
+            const int m = bs - k - 1;
+            for (int e = lane; e < m * m; e += kWave) {
+                const int i = k + 1 + e / m;
+                const int j = k + 1 + e % m;
+                a[i * bs + j] = __builtin_fma(-a[i * bs + k], a[k * bs + j], a[i * bs + j]);
+            }
+            __syncthreads();
+        }
+        if (singular) {
+            if (lane == 0) atomicMin(singular_min, I);
+            __syncthreads();
+            continue;
+        }
+        for (int j = lane; j < bs; j += kWave) {
+            for (int i = 0; i < bs; ++i) y[i * bs + j] = (perm[i] == j) ? 1.0 : 0.0;
+            for (int i = 0; i < bs; ++i) {
+                double s = y[i * bs + j];
+                for (int mm = 0; mm < i; ++mm) s = __builtin_fma(-a[i * bs + mm], y[mm * bs + j], s);
+                y[i * bs + j] = s;
+            }
+            for (int i = bs - 1; i >= 0; --i) {
+                double s = y[i * bs + j];
+                for (int mm = i + 1; mm < bs; ++mm) s = __builtin_fma(-a[i * bs + mm], y[mm * bs + j], s);
+                y[i * bs + j] = s / a[i * bs + i];
+            }
+        }
+        __syncthreads();
+        double *dst = dinv + static_cast<int64_t>(I) * bb;
+        for (int e = lane; e < bb; e += kWave) dst[e] = y[e];
+        __syncthreads();
+    }
+}
+
+// -------------------------------------------------------------- strength
+
+// Row I: m = largest off-diagonal block size; block J != I is theta-strong
+// when size >= theta*m (m > 0), phi-strong likewise; lambda_J counts the rows
+// depending theta-strongly on J.
+__global__ __launch_bounds__(256) void k_strength(const int *__restrict__ rowptr, const int *__restrict__ colidx,
+                                                 const double *__restrict__ bnorm, int nb, double theta, double phi,
+                                                 uint8_t *__restrict__ mask, int *__restrict__ lambda) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nb) return;
+    const int lo = rowptr[I], hi = rowptr[I + 1];
+    double m = 0.0;
+    for (int t = lo; t < hi; ++t)
+        if (colidx[t] != I && bnorm[t] > m) m = bnorm[t];
+    const double tt = theta * m, tp = phi * m;
+    for (int t = lo; t < hi; ++t) {
+        const int J = colidx[t];
+        uint8_t mk = 0;
+        if (J != I && m > 0.0) {
+            if (bnorm[t] >= tt) mk |= 1;
+            if (bnorm[t] >= tp) mk |= 2;
+        }
+        mask[t] = mk;
+        if (mk & 1) atomicAdd(&lambda[J], 1);
+    }
+}
+
+// stidx[stptr[J] ...]: rows that depend theta-strongly on J (any order)
+__global__ __launch_bounds__(256) void k_strong_transpose(const int *__restrict__ rowptr, const int *__restrict__ colidx,
+                                                         const uint8_t *__restrict__ mask, int nb,
+                                                         const int *__restrict__ stptr, int *__restrict__ fill,
+                                                         int *__restrict__ stidx) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nb) return;
+    for (int t = rowptr[I]; t < rowptr[I + 1]; ++t)
+        if (mask[t] & 1) {
+            const int J = colidx[t];
+            const int pos = atomicAdd(&fill[J], 1);
+            stidx[stptr[J] + pos] = I;
+        }
+}
+
+// ------------------------------------------------------------ splitting
+
+constexpr int8_t kUnd = -1, kF = 0, kC = 1;
+
+// splitmix64 finaliser (Steele, Lea and Flood, OOPSLA 2014).
+__device__ inline uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// key (lambda, hash, index) of I beats J's
+__device__ inline bool key_beats(int lamI, uint64_t hI, int I, int lamJ, uint64_t hJ, int J) {
+    if (lamI != lamJ) return lamI > lamJ;
+    if (hI != hJ) return hI > hJ;
+    return I > J;
+}
+
+__global__ __launch_bounds__(256) void k_pmis_init(const int *__restrict__ lambda, int nb, int8_t *__restrict__ state,
+                                                  int *__restrict__ dround, int *__restrict__ undecided0) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nb) return;
+    const bool und = lambda[I] != 0;
+    state[I] = und ? kUnd : kF;
+    dround[I] = 0;
+    if (und) atomicAdd(undecided0, 1);
+}
+
+// New C: undecided blocks whose key beats every undecided neighbour in S u S^T.
+__global__ __launch_bounds__(256) void k_pmis_select(const int *__restrict__ rowptr, const int *__restrict__ colidx,
+                                                    const uint8_t *__restrict__ mask, const int *__restrict__ stptr,
+                                                    const int *__restrict__ stidx, const int *__restrict__ lambda,
+                                                    int nb, uint64_t seed, int level,
+                                                    const int8_t *__restrict__ state, int8_t *__restrict__ newc) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nb) return;
+    if (state[I] != kUnd) {
+        newc[I] = 0;
+        return;
+    }
+    const uint64_t salt = seed ^ (static_cast<uint64_t>(level) << 40);
+    const int lamI = lambda[I];
+    const uint64_t hI = splitmix64(salt ^ static_cast<uint64_t>(I));
+    bool is_max = true;
+    for (int t = rowptr[I]; t < rowptr[I + 1] && is_max; ++t) {
+        if (!(mask[t] & 1)) continue;
+        const int J = colidx[t];
+        if (state[J] == kUnd &&
+            !key_beats(lamI, hI, I, lambda[J], splitmix64(salt ^ static_cast<uint64_t>(J)), J))
+            is_max = false;
+    }
+    for (int t = stptr[I]; t < stptr[I + 1] && is_max; ++t) {
+        const int J = stidx[t];
+        if (state[J] == kUnd &&
+            !key_beats(lamI, hI, I, lambda[J], splitmix64(salt ^ static_cast<uint64_t>(J)), J))
+            is_max = false;
+    }
+    newc[I] = is_max ? 1 : 0;
+}
+
+// New C blocks become C; undecided blocks depending strongly on a new C become F.
+__global__ __launch_bounds__(256) void k_pmis_update(const int *__restrict__ rowptr, const int *__restrict__ colidx,
+                                                    const uint8_t *__restrict__ mask, int nb, int round,
+                                                    int8_t *__restrict__ state, const int8_t *__restrict__ newc,
+                                                    int *__restrict__ dround, int *__restrict__ undecided) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nb) return;
+    if (state[I] != kUnd) return;
+    if (newc[I]) {
+        state[I] = kC;
+        dround[I] = round;
+        return;
+    }
+    for (int t = rowptr[I]; t < rowptr[I + 1]; ++t)
+        if ((mask[t] & 1) && newc[colidx[t]]) {
+            state[I] = kF;
+            dround[I] = round;
+            return;
+        }
+    atomicAdd(undecided, 1);
+}
+
+__global__ __launch_bounds__(256) void k_cf_flags(const int8_t *__restrict__ state, int nb, int *__restrict__ flags) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I < nb) flags[I] = (state[I] == kC) ? 1 : 0;
+}
+
+// cscan[I] = number of C blocks before I.
+__global__ __launch_bounds__(256) void k_cf_index(const int8_t *__restrict__ cf, const int *__restrict__ cscan, int nb,
+                                                 int *__restrict__ cidx, int *__restrict__ cpts,
+                                                 int *__restrict__ flist) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nb) return;
+    const int c = cscan[I];
+    if (cf[I] == kC) {
+        cidx[I] = c;
+        cpts[c] = I;
+    } else {
+        cidx[I] = -1;
+        flist[I - c] = I;
+    }
+}
+
+// ------------------------------------------------------ one-point interpolation
+
+// F block: coarse index of its largest (nonzero) stored C block, lowest column on ties.
+__global__ __launch_bounds__(256) void k_one_point(const int *__restrict__ rowptr, const int *__restrict__ colidx,
+                                                  const double *__restrict__ bnorm, const int8_t *__restrict__ cf,
+                                                  const int *__restrict__ cidx, int nb, int *__restrict__ pmap) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nb) return;
+    if (cf[I] == kC) {
+        pmap[I] = cidx[I];
+        return;
+    }
+    int best = -1;
+    double bestn = 0.0;
+    for (int t = rowptr[I]; t < rowptr[I + 1]; ++t) {
+        const int J = colidx[t];
+        if (J != I && cf[J] == kC && bnorm[t] > bestn) {
+            bestn = bnorm[t];
+            best = J;
+        }
+    }
+    pmap[I] = (best >= 0) ? cidx[best] : -1;
+}
+
+// ----------------------------------------------- Neumann operands (patterns)
+
+__global__ __launch_bounds__(256) void k_count_T(const int *__restrict__ rowptr, const int *__restrict__ colidx,
+                                                const uint8_t *__restrict__ mask, const int8_t *__restrict__ cf,
+                                                int nb, int *__restrict__ cnt) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nb) return;
+    int c = 0;
+    if (cf[I] == kF)
+        for (int t = rowptr[I]; t < rowptr[I + 1]; ++t) {
+            const int J = colidx[t];
+            c += (J != I && cf[J] == kF && (mask[t] & 2)) ? 1 : 0;
+        }
+    cnt[I] = c;
+}
+
+__global__ __launch_bounds__(256) void k_fill_T(const int *__restrict__ rowptr, const int *__restrict__ colidx,
+                                               const uint8_t *__restrict__ mask, const int8_t *__restrict__ cf, int nb,
+                                               const int *__restrict__ trowptr, int *__restrict__ tcol,
+                                               int *__restrict__ trow, int *__restrict__ tsrc) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nb || cf[I] != kF) return;
+    int o = trowptr[I];
+    for (int t = rowptr[I]; t < rowptr[I + 1]; ++t) {
+        const int J = colidx[t];
+        if (J != I && cf[J] == kF && (mask[t] & 2)) {
+            tcol[o] = J;
+            trow[o] = I;
+            tsrc[o] = t;
+            ++o;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_count_Acf(const int *__restrict__ rowptr, const int *__restrict__ colidx,
+                                                  const int8_t *__restrict__ cf, const int *__restrict__ cpts, int nc,
+                                                  int *__restrict__ cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nc) return;
+    const int I = cpts[i];
+    int c = 0;
+    for (int t = rowptr[I]; t < rowptr[I + 1]; ++t) c += (cf[colidx[t]] == kF) ? 1 : 0;
+    cnt[i] = c;
+}
+
+__global__ __launch_bounds__(256) void k_fill_Acf(const int *__restrict__ rowptr, const int *__restrict__ colidx,
+                                                 const int8_t *__restrict__ cf, const int *__restrict__ cpts, int nc,
+                                                 const int *__restrict__ wrowptr, int *__restrict__ wcol,
+                                                 int *__restrict__ wsrc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nc) return;
+    const int I = cpts[i];
+    int o = wrowptr[i];
+    for (int t = rowptr[I]; t < rowptr[I + 1]; ++t)
+        if (cf[colidx[t]] == kF) {
+            wcol[o] = colidx[t];
+            wsrc[o] = t;
+            ++o;
+        }
+}
+
+// out[t] = sign * (X[xi[t]] Y[yi[t]]): entry (a,b) = fma chain over c ascending
+// from +0.  One wave per block; xi == nullptr means xi[t] = t.
+__global__ __launch_bounds__(256) void k_block_product(int64_t n, int bs, const double *__restrict__ X,
+                                                      const int *__restrict__ xi, const double *__restrict__ Y,
+                                                      const int *__restrict__ yi, double sign,
+                                                      double *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int bb = bs * bs;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * 4;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6); t < n; t += stride) {
+        const double *x = X + static_cast<int64_t>(xi ? xi[t] : t) * bb;
+        const double *y = Y + static_cast<int64_t>(yi[t]) * bb;
+        for (int e = lane; e < bb; e += kWave) {
+            const int a = e / bs, b = e % bs;
+            double acc = 0.0;
+            for (int c = 0; c < bs; ++c) acc = __builtin_fma(x[a * bs + c], y[c * bs + b], acc);
+            out[t * bb + e] = sign * acc;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_block_gather(int64_t n, int bb, const double *__restrict__ Y,
+                                                     const int *__restrict__ src, double *__restrict__ out) {
+    const int64_t total = n * bb;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t t = g / bb;
+        const int e = static_cast<int>(g - t * bb);
+        out[g] = Y[static_cast<int64_t>(src[t]) * bb + e];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rows_of(const int *__restrict__ rowptr, int nrows, int *__restrict__ rowid) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows) return;
+    for (int t = rowptr[i]; t < rowptr[i + 1]; ++t) rowid[t] = i;
+}
+
+unsigned cap_grid(int64_t g) { return static_cast<unsigned>(g > 65536 * 16 ? 65536 * 16 : (g < 1 ? 1 : g)); }
+
+}  // namespace
+
+void launch_block_maxabs(const double *vals, int64_t nnzb, int bs, double *out, hipStream_t s) {
+    if (nnzb <= 0) return;
+    k_block_maxabs<<<cap_grid((nnzb + 3) / 4), 256, 0, s>>>(vals, nnzb, bs * bs, out);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_block_inverse(const int *rowptr, const int *colidx, const double *vals, int nb, int bs, double *dinv,
+                          int *singular_min, hipStream_t s) {
+    if (nb <= 0) return;
+    const size_t lds = sizeof(double) * 2 * bs * bs + sizeof(int) * bs;
+    k_block_inverse<<<cap_grid(nb), 64, lds, s>>>(rowptr, colidx, vals, nb, bs, dinv, singular_min);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_strength(const int *rowptr, const int *colidx, const double *bnorm, int nb, double theta, double phi,
+                     uint8_t *mask, int *lambda, hipStream_t s) {
+    k_strength<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, bnorm, nb, theta, phi, mask, lambda);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_strong_transpose(const int *rowptr, const int *colidx, const uint8_t *mask, int nb, const int *stptr,
+                             int *fill, int *stidx, hipStream_t s) {
+    k_strong_transpose<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, mask, nb, stptr, fill, stidx);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_pmis_init(const int *lambda, int nb, int8_t *state, int *dround, int *undecided0, hipStream_t s) {
+    k_pmis_init<<<grid_for(nb, 256), 256, 0, s>>>(lambda, nb, state, dround, undecided0);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_pmis_round(const int *rowptr, const int *colidx, const uint8_t *mask, const int *stptr, const int *stidx,
+                       const int *lambda, int nb, uint64_t seed, int level, int round, int8_t *state, int8_t *newc,
+                       int *dround, int *undecided, hipStream_t s) {
+    k_pmis_select<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, mask, stptr, stidx, lambda, nb, seed, level,
+                                                    state, newc);
+    k_pmis_update<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, mask, nb, round, state, newc, dround,
+                                                    undecided);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_cf_flags(const int8_t *state, int nb, int *flags, hipStream_t s) {
+    k_cf_flags<<<grid_for(nb, 256), 256, 0, s>>>(state, nb, flags);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_cf_index(const int8_t *cf, const int *cscan, int nb, int *cidx, int *cpts, int *flist, hipStream_t s) {
+    k_cf_index<<<grid_for(nb, 256), 256, 0, s>>>(cf, cscan, nb, cidx, cpts, flist);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_one_point(const int *rowptr, const int *colidx, const double *bnorm, const int8_t *cf, const int *cidx,
+                      int nb, int *pmap, hipStream_t s) {
+    k_one_point<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, bnorm, cf, cidx, nb, pmap);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_count_T(const int *rowptr, const int *colidx, const uint8_t *mask, const int8_t *cf, int nb, int *cnt,
+                    hipStream_t s) {
+    k_count_T<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, mask, cf, nb, cnt);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_fill_T(const int *rowptr, const int *colidx, const uint8_t *mask, const int8_t *cf, int nb,
+                   const int *trowptr, int *tcol, int *trow, int *tsrc, hipStream_t s) {
+    k_fill_T<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, mask, cf, nb, trowptr, tcol, trow, tsrc);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_count_Acf(const int *rowptr, const int *colidx, const int8_t *cf, const int *cpts, int nc, int *cnt,
+                      hipStream_t s) {
+    if (nc <= 0) return;
+    k_count_Acf<<<grid_for(nc, 256), 256, 0, s>>>(rowptr, colidx, cf, cpts, nc, cnt);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_fill_Acf(const int *rowptr, const int *colidx, const int8_t *cf, const int *cpts, int nc,
+                     const int *wrowptr, int *wcol, int *wsrc, hipStream_t s) {
+    if (nc <= 0) return;
+    k_fill_Acf<<<grid_for(nc, 256), 256, 0, s>>>(rowptr, colidx, cf, cpts, nc, wrowptr, wcol, wsrc);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_block_product(int64_t n, int bs, const double *X, const int *xi, const double *Y, const int *yi,
+                          double sign, double *out, hipStream_t s) {
+    if (n <= 0) return;
+    k_block_product<<<cap_grid((n + 3) / 4), 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_block_gather(int64_t n, int bs, const double *Y, const int *src, double *out, hipStream_t s) {
+    if (n <= 0) return;
+    k_block_gather<<<cap_grid((n * bs * bs + 255) / 256), 256, 0, s>>>(n, bs * bs, Y, src, out);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_rows_of(const int *rowptr, int nrows, int *rowid, hipStream_t s) {
+    if (nrows <= 0) return;
+    k_rows_of<<<grid_for(nrows, 256), 256, 0, s>>>(rowptr, nrows, rowid);
+    NAIR_HIP(hipGetLastError());
+}
+
+}  // namespace nair
+
+namespace nair {
+namespace {
+
+// bad |= 1: rowptr not monotone/out of range; 2: column out of range;
+// 4: columns not strictly increasing; 8: missing diagonal block.
+__global__ __launch_bounds__(256) void k_validate(const int *__restrict__ rowptr, const int *__restrict__ colidx, int nb,
+                                                 int64_t nnzb, int *__restrict__ bad) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nb) return;
+    const int lo = rowptr[I], hi = rowptr[I + 1];
+    if ((I == 0 && lo != 0) || lo < 0 || hi < lo || hi > nnzb) {
+        atomicOr(bad, 1);
+        return;
+    }
+    bool diag = false;
+    for (int t = lo; t < hi; ++t) {
+        const int J = colidx[t];
+        if (J < 0 || J >= nb) {
+            atomicOr(bad, 2);
+            return;
+        }
+        if (t > lo && J <= colidx[t - 1]) atomicOr(bad, 4);
+        if (J == I) diag = true;
+    }
+    if (!diag) atomicOr(bad, 8);
+}
+
+}  // namespace
+
+void launch_validate(const int *rowptr, const int *colidx, int nb, int64_t nnzb, int *bad, hipStream_t s) {
+    k_validate<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, nb, nnzb, bad);
+    NAIR_HIP(hipGetLastError());
+}
+
+}  // namespace nair

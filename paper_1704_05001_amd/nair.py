@@ -1,0 +1,296 @@
+"""ctypes binding of libnair_hip.so (argument marshalling only).
+
+Every step of the setup and solve runs in the library's HIP kernels; this
+module passes torch device tensors' pointers and the current stream through
+the C ABI declared in include/nair.h, and fails loudly if the library is
+missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnair_hip.so")
+
+STATUS = {0: "OK", 1: "EINVAL", 2: "ESINGULAR", 3: "ENOCONV", 4: "ENUMERIC", 5: "ENOMEM",
+          6: "EDEVICE", 7: "ECOARSEN"}
+
+EXPORTED = ["nair_default_params", "nair_setup", "nair_solve", "nair_solve_T", "nair_vcycle",
+            "nair_vcycle_T", "nair_history", "nair_info", "nair_get_level", "nair_last_error",
+            "nair_destroy", "nair_pool_trim"]
+
+
+class NairError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str = ""):
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+        super().__init__(f"{where}: {self.status}" + (f" ({msg})" if msg else ""))
+
+
+class _Params(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("theta", C.c_double), ("phi", C.c_double),
+                ("drop", C.c_double), ("relax", C.c_int32), ("max_levels", C.c_int32),
+                ("max_coarse_dofs", C.c_int32), ("seed", C.c_uint64),
+                ("cf_override_host", C.c_void_p)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("relres", C.c_double),
+                ("rho_avg", C.c_double), ("rho_last5", C.c_double)]
+
+
+class _LevelView(C.Structure):
+    _fields_ = [("nb", C.c_int32), ("bs", C.c_int32), ("nnzb", C.c_int32), ("coarsest", C.c_int32),
+                ("rowptr", C.c_void_p), ("colidx", C.c_void_p), ("vals", C.c_void_p),
+                ("dinv", C.c_void_p), ("bnorm", C.c_void_p), ("mask", C.c_void_p),
+                ("lam", C.c_void_p), ("cf", C.c_void_p), ("cidx", C.c_void_p),
+                ("pmap", C.c_void_p), ("dround", C.c_void_p), ("nc", C.c_int32),
+                ("pmis_rounds", C.c_int32), ("z_nnzb", C.c_int32), ("z_rowptr", C.c_void_p),
+                ("z_colidx", C.c_void_p), ("z_vals", C.c_void_p), ("dense_n", C.c_int32),
+                ("dense_inv", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build() or python paper_1704_05001_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
+        L.nair_default_params.argtypes = [C.POINTER(_Params)]
+        L.nair_default_params.restype = C.c_int
+        L.nair_setup.argtypes = [i32, i32, vp, vp, vp, C.POINTER(_Params), vp, C.POINTER(vp)]
+        L.nair_setup.restype = C.c_int
+        for f in (L.nair_solve, L.nair_solve_T):
+            f.argtypes = [vp, vp, vp, dbl, i32, C.POINTER(_Result), vp]
+            f.restype = C.c_int
+        for f in (L.nair_vcycle, L.nair_vcycle_T):
+            f.argtypes = [vp, vp, vp, vp]
+            f.restype = C.c_int
+        L.nair_history.argtypes = [vp, vp, i32, C.POINTER(i32)]
+        L.nair_history.restype = C.c_int
+        L.nair_info.argtypes = [vp, C.POINTER(i32), vp, vp, C.POINTER(dbl), C.POINTER(dbl)]
+        L.nair_info.restype = C.c_int
+        L.nair_get_level.argtypes = [vp, i32, C.POINTER(_LevelView)]
+        L.nair_get_level.restype = C.c_int
+        L.nair_last_error.argtypes = [vp]
+        L.nair_last_error.restype = C.c_char_p
+        L.nair_destroy.argtypes = [vp]
+        L.nair_destroy.restype = None
+        L.nair_pool_trim.argtypes = []
+        L.nair_pool_trim.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dcopy(ptr: int, dtype, count: int, device):
+    """Copy `count` elements at device pointer `ptr` into a new torch tensor."""
+    import torch
+    out = torch.empty(int(count), dtype=dtype, device=device)
+    if count > 0 and ptr:
+        nbytes = int(count) * out.element_size()
+        _hip().hipMemcpy(C.c_void_p(out.data_ptr()), C.c_void_p(ptr), C.c_size_t(nbytes), 3)
+    return out
+
+
+_hip_lib = None
+
+
+def _hip():
+    global _hip_lib
+    if _hip_lib is None:
+        _hip_lib = C.CDLL("libamdhip64.so")
+        _hip_lib.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip_lib.hipMemcpy.restype = C.c_int
+    return _hip_lib
+
+
+@dataclass
+class Params:
+    degree: int = 1
+    theta: float = 0.25
+    phi: float = 0.025
+    drop: float = 1e-3
+    relax: int = 0
+    max_levels: int = 30
+    max_coarse_dofs: int = 512
+    seed: int = 0
+    cf_override: Optional[np.ndarray] = None
+
+
+@dataclass
+class Result:
+    status: str
+    iters: int
+    converged: bool
+    relres: float
+    rho_avg: float
+    rho_last5: float
+
+
+class Hierarchy:
+    """nAIR hierarchy on the GPU.  rowptr/colidx (int32) and vals (float64,
+    [nnzb, bs, bs]) are torch tensors on the current HIP device."""
+
+    def __init__(self, rowptr, colidx, vals, bs: int, params: Params | None = None, stream=None):
+        import torch
+        params = params or Params()
+        L = lib()
+        for t, dt in ((rowptr, torch.int32), (colidx, torch.int32), (vals, torch.float64)):
+            if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+                raise ValueError("rowptr/colidx must be contiguous int32 and vals float64 device tensors")
+        self.nb = rowptr.numel() - 1
+        self.bs = int(bs)
+        self.device = rowptr.device
+        self.params = params
+        p = _Params()
+        L.nair_default_params(C.byref(p))
+        p.degree, p.theta, p.phi, p.drop = params.degree, params.theta, params.phi, params.drop
+        p.relax, p.max_levels, p.max_coarse_dofs = params.relax, params.max_levels, params.max_coarse_dofs
+        p.seed = params.seed
+        cf = None
+        if params.cf_override is not None:
+            cf = np.ascontiguousarray(params.cf_override, dtype=np.int8)
+            p.cf_override_host = cf.ctypes.data
+        h = C.c_void_p()
+        st = L.nair_setup(self.nb, self.bs, C.c_void_p(rowptr.data_ptr()), C.c_void_p(colidx.data_ptr()),
+                          C.c_void_p(vals.data_ptr()), C.byref(p), _stream_ptr(stream), C.byref(h))
+        if st != 0:
+            raise NairError(st, "nair_setup", L.nair_last_error(None).decode())
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().nair_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n(self):
+        return self.nb * self.bs
+
+    def _err(self):
+        return lib().nair_last_error(self._h).decode()
+
+    def _solve(self, fn, name, b, x, rtol, max_iter, stream, raise_on):
+        import torch
+        if x is None:
+            x = torch.empty_like(b)
+        res = _Result()
+        st = fn(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), float(rtol), int(max_iter),
+                C.byref(res), _stream_ptr(stream))
+        status = STATUS.get(st, str(st))
+        if st != 0 and status in raise_on:
+            raise NairError(st, name, self._err())
+        return x, Result(status, res.iters, bool(res.converged), res.relres, res.rho_avg, res.rho_last5)
+
+    def solve(self, b, x=None, rtol=1e-10, max_iter=200, stream=None,
+              raise_on=("EINVAL", "EDEVICE", "ENOMEM")):
+        """x = A^{-1} b by nAIR V-cycles.  Returns (x, Result)."""
+        return self._solve(lib().nair_solve, "nair_solve", b, x, rtol, max_iter, stream, raise_on)
+
+    def solve_T(self, g, y=None, rtol=1e-10, max_iter=200, stream=None,
+                raise_on=("EINVAL", "EDEVICE", "ENOMEM")):
+        """y = A^{-T} g by transposed nAIR V-cycles.  Returns (y, Result)."""
+        return self._solve(lib().nair_solve_T, "nair_solve_T", g, y, rtol, max_iter, stream, raise_on)
+
+    def vcycle(self, r, stream=None):
+        import torch
+        e = torch.empty_like(r)
+        st = lib().nair_vcycle(self._h, C.c_void_p(r.data_ptr()), C.c_void_p(e.data_ptr()), _stream_ptr(stream))
+        if st != 0:
+            raise NairError(st, "nair_vcycle", self._err())
+        return e
+
+    def vcycle_T(self, g, stream=None):
+        import torch
+        y = torch.empty_like(g)
+        st = lib().nair_vcycle_T(self._h, C.c_void_p(g.data_ptr()), C.c_void_p(y.data_ptr()), _stream_ptr(stream))
+        if st != 0:
+            raise NairError(st, "nair_vcycle_T", self._err())
+        return y
+
+    def history(self):
+        n = C.c_int32()
+        lib().nair_history(self._h, None, 0, C.byref(n))
+        buf = np.zeros(max(1, n.value))
+        lib().nair_history(self._h, buf.ctypes.data_as(C.c_void_p), n.value, C.byref(n))
+        return buf[:n.value].copy()
+
+    def info(self):
+        lv = C.c_int32()
+        nbl = np.zeros(64, dtype=np.int32)
+        nnz = np.zeros(64, dtype=np.int64)
+        oc, cc = C.c_double(), C.c_double()
+        st = lib().nair_info(self._h, C.byref(lv), nbl.ctypes.data_as(C.c_void_p), nnz.ctypes.data_as(C.c_void_p),
+                             C.byref(oc), C.byref(cc))
+        if st != 0:
+            raise NairError(st, "nair_info", self._err())
+        L = lv.value
+        return dict(levels=L, nb=nbl[:L].tolist(), nnzb=nnz[:L].tolist(), oc=oc.value, cc=cc.value)
+
+    @property
+    def num_levels(self):
+        return self.info()["levels"]
+
+    def level(self, l: int) -> dict:
+        """Copies of level l's device arrays (torch tensors on the device)."""
+        import torch
+        v = _LevelView()
+        st = lib().nair_get_level(self._h, l, C.byref(v))
+        if st != 0:
+            raise NairError(st, "nair_get_level", self._err())
+        torch.cuda.synchronize(self.device)
+        dev = self.device
+        nb, bs, nnzb = v.nb, v.bs, v.nnzb
+        bb = bs * bs
+        out = dict(nb=nb, bs=bs, nnzb=nnzb, coarsest=bool(v.coarsest), nc=v.nc, pmis_rounds=v.pmis_rounds,
+                   rowptr=_dcopy(v.rowptr, torch.int32, nb + 1, dev),
+                   colidx=_dcopy(v.colidx, torch.int32, nnzb, dev),
+                   vals=_dcopy(v.vals, torch.float64, nnzb * bb, dev).view(nnzb, bs, bs))
+        if v.dinv:
+            out.update(dinv=_dcopy(v.dinv, torch.float64, nb * bb, dev).view(nb, bs, bs),
+                       bnorm=_dcopy(v.bnorm, torch.float64, nnzb, dev),
+                       mask=_dcopy(v.mask, torch.uint8, nnzb, dev),
+                       lam=_dcopy(v.lam, torch.int32, nb, dev),
+                       cf=_dcopy(v.cf, torch.int8, nb, dev),
+                       cidx=_dcopy(v.cidx, torch.int32, nb, dev),
+                       dround=_dcopy(v.dround, torch.int32, nb, dev))
+        if v.pmap:
+            out.update(pmap=_dcopy(v.pmap, torch.int32, nb, dev),
+                       z_rowptr=_dcopy(v.z_rowptr, torch.int32, v.nc + 1, dev),
+                       z_colidx=_dcopy(v.z_colidx, torch.int32, v.z_nnzb, dev),
+                       z_vals=_dcopy(v.z_vals, torch.float64, v.z_nnzb * bb, dev).view(v.z_nnzb, bs, bs))
+        if v.dense_inv:
+            n = v.dense_n
+            out.update(dense_inv=_dcopy(v.dense_inv, torch.float64, n * n, dev).view(n, n))
+        torch.cuda.synchronize(self.device)
+        return out
+
+
+def pool_trim():
+    st = lib().nair_pool_trim()
+    if st != 0:
+        raise NairError(st, "nair_pool_trim")
