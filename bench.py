@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the nAIR hot path on one MI355X.
+
+One step = the whole hot path on one synthetic upwind-DG transport system
+already resident in HBM: hierarchy setup, solve A x = b to 1e-10 relative
+residual, and the transposed solve A^T y = g to 1e-10.  `value` is DOFs/s of
+setup + solve (the metric's definition: n / (t_setup + t_solve)); the
+transposed solve is timed in the same steps and reported beside it, and
+`ms_per_step` covers all three phases.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Prints one JSON line.  The CPU-baseline leg times the plain CPU oracle (one
+thread) on the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "DOFs/s setup+solve to 1e-10 rel. residual, FP64 vs batched FP32-hier; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def relax_level_bytes(lv: dict) -> dict:
+    """Algorithmic HBM bytes of one F-relaxation sweep on a level: each operand
+    read once, each output written once (int32 indices, FP64 values)."""
+    import numpy as np
+    rp = lv["rowptr"].cpu().numpy().astype(np.int64)
+    cf = lv["cf"].cpu().numpy()
+    bs = lv["bs"]
+    bb = bs * bs
+    rowlen = np.diff(rp)
+    F = cf == 0
+    nF = int(F.sum())
+    nnzF = int(rowlen[F].sum())
+    n = lv["nb"] * bs
+    bytes_A = nnzF * (bb * 8 + 4)          # F rows of A (values + column indices)
+    bytes_D = nF * bb * 8                  # D_F^{-1}
+    bytes_idx = nF * 4 + nF * 8            # F list, rowptr pairs
+    bytes_vec = n * 8 + nF * bs * 8 * 2    # e_in (gathered, read once), r_F, e_out_F
+    return dict(bytes=bytes_A + bytes_D + bytes_idx + bytes_vec, nF=nF, nnzF=nnzF,
+                bytes_true_blocks=bytes_A + bytes_D)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="dg_q2_256_curved")
+    ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--roofline-kernel", default="relax")
+    ap.add_argument("--roofline-level", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", default="full", help="'full' or a mesh size N for the oracle sample")
+    args = ap.parse_args(argv)
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU; run with --gpus 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not run)"}), flush=True)
+        return 2
+
+    import numpy as np
+    import torch
+    import paper_1704_05001_amd as P
+    from nair_inputs import make_config
+
+    if not os.path.exists(P.LIB_PATH):
+        from paper_1704_05001_amd.build import build
+        build()
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        return 3
+
+    t0 = time.time()
+    S, degree = make_config(args.workload)
+    log(f"workload {args.workload}: {S.n} DOFs, nb={S.nb}, bs={S.bs}, nnzb={S.nnzb}, degree={degree} "
+        f"({time.time() - t0:.1f}s to generate)")
+    dev = torch.device("cuda", 0)
+    rp = torch.from_numpy(S.rowptr).to(dev)
+    ci = torch.from_numpy(S.colidx).to(dev)
+    va = torch.from_numpy(S.vals).to(dev)
+    b = torch.from_numpy(S.rhs).to(dev)
+    g = torch.from_numpy(np.random.Generator(np.random.PCG64(300)).uniform(-1, 1, S.n)).to(dev)
+    x = torch.empty_like(b)
+    y = torch.empty_like(g)
+    params = P.Params(degree=degree)
+    stream = torch.cuda.current_stream()
+
+    def step(record):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        H = P.Hierarchy(rp, ci, va, S.bs, params)
+        ev[1].record(stream)
+        _, r = H.solve(b, x=x, rtol=args.rtol)
+        ev[2].record(stream)
+        _, rT = H.solve_T(g, y=y, rtol=args.rtol)
+        ev[3].record(stream)
+        if r.status != "OK" or rT.status != "OK":
+            raise RuntimeError(f"solve status {r.status} / {rT.status}")
+        if record is not None:
+            record.append((ev, r, rT))
+        return H
+
+    for i in range(args.warmup):
+        H = step(None)
+        if i == 0:
+            info = H.info()
+            lvl = H.level(args.roofline_level)
+            log(f"levels {info['levels']} nb {info['nb']} OC {info['oc']:.2f} CC {info['cc']:.2f}")
+        H.close()
+    if args.warmup == 0:
+        H = step(None)
+        info = H.info()
+        lvl = H.level(args.roofline_level)
+        H.close()
+
+    P.timer_select(args.roofline_kernel, args.roofline_level)
+    recs = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        H = step(recs)
+        H.close()
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    launches, kernel_ms = P.timer_read()
+    P.timer_select(None)
+    log(f"timed {args.steps} steps in {t_end - t_start:.3f}s")
+
+    setup_ms = np.mean([e[0].elapsed_time(e[1]) for e, _, _ in recs])
+    solve_ms = np.mean([e[1].elapsed_time(e[2]) for e, _, _ in recs])
+    solveT_ms = np.mean([e[2].elapsed_time(e[3]) for e, _, _ in recs])
+    wall_ms = (t_end - t_start) * 1e3 / args.steps
+    iters = recs[-1][1].iters
+    itersT = recs[-1][2].iters
+    value = S.n / ((setup_ms + solve_ms) * 1e-3)
+
+    roof = None
+    if args.roofline_kernel == "relax" and launches > 0:
+        rb = relax_level_bytes(lvl)
+        avg_ms = kernel_ms / launches
+        achieved = rb["bytes"] / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": f"k_relax (level {args.roofline_level} F sweep)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": rb["bytes"], "avg_launch_us": round(avg_ms * 1e3, 2),
+                "launches": launches}
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "DOFs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall_ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "mesh": f"{S.N}x{S.N} quads", "dg_order": S.p,
+                   "dofs": S.n, "block": S.bs, "nnzb": S.nnzb, "neumann_degree": degree,
+                   "rtol": args.rtol, "levels": info["levels"], "oc": round(info["oc"], 3),
+                   "cc": round(info["cc"], 3)},
+        "setup_ms": round(float(setup_ms), 3), "solve_ms": round(float(solve_ms), 3),
+        "solve_T_ms": round(float(solveT_ms), 3), "iters": iters, "iters_T": itersT,
+        "step": "setup + solve + transposed solve; value = dofs / (setup + solve)",
+        "roofline": roof,
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        if args.cpu_sample == "full":
+            So, dego = S, degree
+            sample = f"full {args.workload} ({S.n} DOFs): one oracle setup + solve to {args.rtol:g}"
+        else:
+            So, dego = make_config(args.workload, N=int(args.cpu_sample))
+            sample = f"{args.workload} at N={args.cpu_sample} ({So.n} DOFs): one oracle setup + solve"
+        log(f"cpu baseline: {sample}")
+        c0 = time.perf_counter()
+        O = oracle.Hierarchy(So.nb, So.bs, So.rowptr, So.colidx, So.vals, oracle.Params(degree=dego))
+        c1 = time.perf_counter()
+        xo, ho, so = O.solve(So.rhs, args.rtol, 500)
+        c2 = time.perf_counter()
+        out["cpu_baseline"] = {"value": round(So.n / (c2 - c0), 1), "unit": "DOFs/s", "cores": 1,
+                               "kind": "oracle", "sample": sample,
+                               "setup_s": round(c1 - c0, 3), "solve_s": round(c2 - c1, 3),
+                               "iters": len(ho), "cpu": cpu_model(), "nproc": os.cpu_count()}
+        if So is S:
+            xg = x.cpu().numpy()
+            out["cpu_baseline"]["max_rel_diff_x"] = float(np.abs(xg - xo).max() / np.abs(xo).max())
+            out["cpu_baseline"]["same_iters"] = bool(len(ho) == iters)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -152,6 +152,20 @@ void nair_destroy(nair_hier h);
 /* Return all cached, unused device memory of the pool to HIP. */
 nair_status nair_pool_trim(void);
 
+/*
+ * Kernel timer (profiling).  nair_timer_select(kernel, level) makes the
+ * library bracket every later launch of that kernel on that level (-1: all
+ * levels) with a pair of HIP events on the launch's stream; kernel = -1 turns
+ * the timer off.  Kernels: 0 F/FC relaxation sweep, 1 residual, 2 restriction,
+ * 3 interpolation, 4 SpGEMM numeric, 5 SpGEMM symbolic, 6 block inverse,
+ * 7 Galerkin merge, 8 dense coarsest product.  nair_timer_read (host outputs)
+ * synchronises the device and returns the number of timed launches and their
+ * total duration in milliseconds, then resets the counters.  Host only; one
+ * timed kernel at a time.
+ */
+nair_status nair_timer_select(int32_t kernel, int32_t level);
+nair_status nair_timer_read(int64_t *launches, double *total_ms);
+
 #ifdef __cplusplus
 }
 #endif

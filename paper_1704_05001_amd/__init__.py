@@ -4,6 +4,8 @@ The hierarchy build and the V-cycle solve run in the HIP kernels of
 libnair_hip.so, reached through the C ABI of include/nair.h; `nair` is the
 ctypes binding.
 """
-from .nair import Hierarchy, Params, Result, NairError, lib, LIB_PATH, EXPORTED, STATUS, pool_trim
+from .nair import (Hierarchy, Params, Result, NairError, lib, LIB_PATH, EXPORTED, STATUS, KERNELS, pool_trim,
+                   timer_select, timer_read)
 
-__all__ = ["Hierarchy", "Params", "Result", "NairError", "lib", "LIB_PATH", "EXPORTED", "STATUS", "pool_trim"]
+__all__ = ["Hierarchy", "Params", "Result", "NairError", "lib", "LIB_PATH", "EXPORTED", "STATUS", "KERNELS",
+           "pool_trim", "timer_select", "timer_read"]

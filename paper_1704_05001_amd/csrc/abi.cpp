@@ -211,6 +211,19 @@ void nair_destroy(nair_hier h) {
     delete h;
 }
 
+nair_status nair_timer_select(int32_t kernel, int32_t level) {
+    if (kernel < -1 || kernel > nair::TK_DENSE) return bad(nullptr, "unknown kernel id");
+    nair::timer_select(kernel, level);
+    return NAIR_OK;
+}
+
+nair_status nair_timer_read(int64_t *launches, double *total_ms) {
+    return guarded(nullptr, [&]() {
+        nair::timer_read(launches, total_ms);
+        return NAIR_OK;
+    });
+}
+
 nair_status nair_pool_trim(void) {
     return guarded(nullptr, []() {
         nair::pool_trim();

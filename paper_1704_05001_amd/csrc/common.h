@@ -86,6 +86,20 @@ struct DevBSR {
     }
 };
 
+// ----------------------------------------------------------- kernel timer
+enum TimedKernel { TK_RELAX = 0, TK_RESIDUAL = 1, TK_RESTRICT = 2, TK_INTERP = 3, TK_SPGEMM_NUM = 4,
+                   TK_SPGEMM_SYM = 5, TK_BLOCKINV = 6, TK_RAP = 7, TK_DENSE = 8 };
+// Brackets launches of the selected (kernel, level) with events; no-ops otherwise.
+struct TimerScope {
+    bool on;
+    hipStream_t s;
+    TimerScope(int kernel, int level, hipStream_t stream);
+    ~TimerScope();
+};
+void timer_select(int kernel, int level);
+void timer_read(int64_t *launches, double *total_ms);
+extern thread_local int g_timer_level;   // level the host code is working on
+
 // ------------------------------------------------------------- utilities
 inline unsigned grid_for(int64_t n, int per_block) {
     int64_t g = (n + per_block - 1) / per_block;

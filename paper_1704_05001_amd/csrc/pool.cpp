@@ -99,6 +99,74 @@ void pool_trim() {
     (void)hipSetDevice(cur);
 }
 
+// ------------------------------------------------------------ kernel timer
+
+thread_local int g_timer_level = 0;
+
+namespace {
+struct Timer {
+    std::mutex mu;
+    int kernel = -1, level = -1;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> spare;
+    int64_t launches = 0;
+    double total_ms = 0.0;
+};
+Timer &timer() {
+    static Timer *t = new Timer();
+    return *t;
+}
+}  // namespace
+
+TimerScope::TimerScope(int kernel, int level, hipStream_t stream) : on(false), s(stream) {
+    Timer &T = timer();
+    if (T.kernel != kernel || (T.level >= 0 && T.level != level)) return;
+    std::lock_guard<std::mutex> lk(T.mu);
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    if (!T.spare.empty()) {
+        ev = T.spare.back();
+        T.spare.pop_back();
+    } else {
+        NAIR_HIP(hipEventCreate(&ev.first));
+        NAIR_HIP(hipEventCreate(&ev.second));
+    }
+    NAIR_HIP(hipEventRecord(ev.first, s));
+    T.pending.push_back(ev);
+    on = true;
+}
+
+TimerScope::~TimerScope() {
+    if (!on) return;
+    Timer &T = timer();
+    std::lock_guard<std::mutex> lk(T.mu);
+    (void)hipEventRecord(T.pending.back().second, s);
+}
+
+void timer_select(int kernel, int level) {
+    Timer &T = timer();
+    std::lock_guard<std::mutex> lk(T.mu);
+    T.kernel = kernel;
+    T.level = level;
+}
+
+void timer_read(int64_t *launches, double *total_ms) {
+    Timer &T = timer();
+    std::lock_guard<std::mutex> lk(T.mu);
+    for (auto &ev : T.pending) {
+        NAIR_HIP(hipEventSynchronize(ev.second));
+        float ms = 0.0f;
+        NAIR_HIP(hipEventElapsedTime(&ms, ev.first, ev.second));
+        T.total_ms += ms;
+        T.launches += 1;
+        T.spare.push_back(ev);
+    }
+    T.pending.clear();
+    if (launches) *launches = T.launches;
+    if (total_ms) *total_ms = T.total_ms;
+    T.launches = 0;
+    T.total_ms = 0.0;
+}
+
 int read_int(const int *dptr, hipStream_t s) {
     int v = 0;
     NAIR_HIP(hipMemcpyAsync(&v, dptr, sizeof(int), hipMemcpyDeviceToHost, s));

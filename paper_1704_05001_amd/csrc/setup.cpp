@@ -111,6 +111,7 @@ void build_hierarchy(Hier &h, int nb, int bs, const int *rowptr, const int *coli
     for (int l = 0;; ++l) {
         Level &L = *h.lv[l];
         const int n = L.A.nb;
+        g_timer_level = l;
         alloc_vectors(L, bs);
         if (static_cast<int64_t>(n) * bs <= p.max_coarse_dofs || l == p.max_levels - 1) {
             make_coarsest(L, l, s);
@@ -129,7 +130,11 @@ void build_hierarchy(Hier &h, int nb, int bs, const int *rowptr, const int *coli
         NAIR_HIP(hipMemsetAsync(sing.get(), 0x7f, sizeof(int), s));
         NAIR_HIP(hipMemsetAsync(L.lambda.get(), 0, sizeof(int) * n, s));
         launch_block_maxabs(L.A.vals.get(), nz, bs, L.bnorm.get(), s);
-        launch_block_inverse(L.A.rowptr.get(), L.A.colidx.get(), L.A.vals.get(), n, bs, L.dinv.get(), sing.get(), s);
+        {
+            TimerScope ts(TK_BLOCKINV, l, s);
+            launch_block_inverse(L.A.rowptr.get(), L.A.colidx.get(), L.A.vals.get(), n, bs, L.dinv.get(), sing.get(),
+                                 s);
+        }
         launch_strength(L.A.rowptr.get(), L.A.colidx.get(), L.bnorm.get(), n, p.theta, p.phi, L.mask.get(),
                         L.lambda.get(), s);
         if (l == 0 && p.cf_override_host) {

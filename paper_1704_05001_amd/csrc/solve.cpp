@@ -21,20 +21,33 @@ const double *vcycle(Hier &h, int l, hipStream_t s) {
     Level &L = *h.lv[l];
     const int bs = h.bs;
     if (L.coarsest) {
+        TimerScope ts(TK_DENSE, l, s);
         launch_dense_matvec(L.dense_inv.get(), L.r.get(), L.e0.get(), L.dense_n, false, s);
         return L.e0.get();
     }
     Level &C = *h.lv[l + 1];
-    launch_restrict(L.Z, L.r.get(), L.cpts.get(), C.r.get(), s);
+    {
+        TimerScope ts(TK_RESTRICT, l, s);
+        launch_restrict(L.Z, L.r.get(), L.cpts.get(), C.r.get(), s);
+    }
     const double *ec = vcycle(h, l + 1, s);
-    launch_interp(L.pmap.get(), ec, L.e0.get(), L.e1.get(), L.A.nb, bs, s);
+    {
+        TimerScope ts(TK_INTERP, l, s);
+        launch_interp(L.pmap.get(), ec, L.e0.get(), L.e1.get(), L.A.nb, bs, s);
+    }
     double *cur = L.e0.get(), *oth = L.e1.get();
     for (int k = 0; k <= h.prm.degree; ++k) {
-        launch_relax(L.A, L.dinv.get(), false, L.r.get(), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s);
+        {
+            TimerScope ts(TK_RELAX, l, s);
+            launch_relax(L.A, L.dinv.get(), false, L.r.get(), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s);
+        }
         std::swap(cur, oth);
     }
     if (h.prm.relax == 1) {
-        launch_relax(L.A, L.dinv.get(), false, L.r.get(), cur, oth, nullptr, 0, L.cf.get(), 1, s);
+        {
+            TimerScope ts(TK_RELAX, l, s);
+            launch_relax(L.A, L.dinv.get(), false, L.r.get(), cur, oth, nullptr, 0, L.cf.get(), 1, s);
+        }
         std::swap(cur, oth);
     }
     return cur;
@@ -47,6 +60,7 @@ const double *vcycle_T(Hier &h, int l, hipStream_t s) {
     Level &L = *h.lv[l];
     const int bs = h.bs;
     if (L.coarsest) {
+        TimerScope ts(TK_DENSE, l, s);
         launch_dense_matvec(L.dense_inv.get(), L.r.get(), L.e0.get(), L.dense_n, true, s);
         return L.e0.get();
     }
@@ -101,7 +115,10 @@ nair_status run_solve(Hier &h, bool trans, const double *b, double *x, double rt
         for (int it = 0; it < max_iter; ++it) {
             const double *e = trans ? vcycle_T(h, 0, s) : vcycle(h, 0, s);
             launch_axpy(x, e, n, s);
-            launch_residual(Aop, b, x, L0.r.get(), h.partials.get(), h.npart, s);
+            {
+                TimerScope ts(TK_RESIDUAL, 0, s);
+                launch_residual(Aop, b, x, L0.r.get(), h.partials.get(), h.npart, s);
+            }
             launch_reduce_partials(h.partials.get(), residual_partials_count(L0.A), h.scal.get(), s);
             rel = std::sqrt(read_double(h.scal.get(), s)) / bn;
             h.hist.push_back(rel);

@@ -498,6 +498,7 @@ void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipSt
     if (tile_blocks < 1) tile_blocks = 1;
     const size_t lds = sizeof(double) * (static_cast<size_t>(tile_blocks) * bb + bb) +
                        sizeof(int) * (kOutColsLds + kPosLds);
+    TimerScope ts(TK_SPGEMM_NUM, g_timer_level, s);
     k_spgemm_numeric<<<cap_grid(m), kNumThreads, lds, s>>>(X.rowptr.get(), X.colidx.get(), X.vals.get(), xdiag,
                                                           Y.rowptr.get(), Y.colidx.get(), Y.vals.get(), m,
                                                           C.rowptr.get(), C.colidx.get(), C.vals.get(), bs,
@@ -553,9 +554,12 @@ void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevB
     DBuf<int> kept(m);
     k_rap_symbolic<<<gs, 256, 0, s>>>(RA.rowptr.get(), RA.colidx.get(), pmap, m, 1, nullptr, krp.get(), kcol.get(),
                                       flags.get());
-    k_rap_numeric<<<cap_grid(m), kNumThreads, 0, s>>>(RA.rowptr.get(), RA.colidx.get(), RA.vals.get(), pmap, m,
-                                                      krp.get(), kcol.get(), kval.get(), bs, drop, keep.get(),
-                                                      kept.get());
+    {
+        TimerScope ts(TK_RAP, g_timer_level, s);
+        k_rap_numeric<<<cap_grid(m), kNumThreads, 0, s>>>(RA.rowptr.get(), RA.colidx.get(), RA.vals.get(), pmap, m,
+                                                          krp.get(), kcol.get(), kval.get(), bs, drop, keep.get(),
+                                                          kept.get());
+    }
     NAIR_HIP(hipGetLastError());
     K.nb = nc;
     K.ncols = nc;

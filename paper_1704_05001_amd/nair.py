@@ -22,7 +22,10 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ESINGULAR", 3: "ENOCONV", 4: "ENUMERIC", 5: 
 
 EXPORTED = ["nair_default_params", "nair_setup", "nair_solve", "nair_solve_T", "nair_vcycle",
             "nair_vcycle_T", "nair_history", "nair_info", "nair_get_level", "nair_last_error",
-            "nair_destroy", "nair_pool_trim"]
+            "nair_destroy", "nair_pool_trim", "nair_timer_select", "nair_timer_read"]
+
+KERNELS = {"relax": 0, "residual": 1, "restrict": 2, "interp": 3, "spgemm_numeric": 4,
+           "spgemm_symbolic": 5, "block_inverse": 6, "galerkin": 7, "dense": 8}
 
 
 class NairError(RuntimeError):
@@ -89,6 +92,10 @@ def lib():
         L.nair_destroy.restype = None
         L.nair_pool_trim.argtypes = []
         L.nair_pool_trim.restype = C.c_int
+        L.nair_timer_select.argtypes = [i32, i32]
+        L.nair_timer_select.restype = C.c_int
+        L.nair_timer_read.argtypes = [C.POINTER(C.c_int64), C.POINTER(dbl)]
+        L.nair_timer_read.restype = C.c_int
         _lib = L
     return _lib
 
@@ -294,3 +301,21 @@ def pool_trim():
     st = lib().nair_pool_trim()
     if st != 0:
         raise NairError(st, "nair_pool_trim")
+
+
+def timer_select(kernel, level=-1):
+    """Time every later launch of `kernel` (name or id; None = off) on `level` (-1 = all)."""
+    kid = -1 if kernel is None else (KERNELS[kernel] if isinstance(kernel, str) else int(kernel))
+    st = lib().nair_timer_select(kid, level)
+    if st != 0:
+        raise NairError(st, "nair_timer_select")
+
+
+def timer_read():
+    """(number of timed launches, total milliseconds) since the last read."""
+    n = C.c_int64()
+    ms = C.c_double()
+    st = lib().nair_timer_read(C.byref(n), C.byref(ms))
+    if st != 0:
+        raise NairError(st, "nair_timer_read")
+    return n.value, ms.value
