@@ -56,7 +56,7 @@ typedef struct {
     double drop;              /* drop tolerance of coarse operators, in [0,1): 1e-3 (section 5.2) */
     int32_t relax;            /* 0: F-relaxation; 1: F then one C sweep (FC) */
     int32_t max_levels;       /* 1..64, default 30 */
-    int32_t max_coarse_dofs;  /* a level with nb*bs <= this is solved densely; default 512 */
+    int32_t max_coarse_dofs;  /* a level with nb*bs <= this is solved densely; default 128 */
     uint64_t seed;            /* seed of the splitting's tie-break hash, default 0 */
     const int8_t *cf_override_host; /* optional, host, [nb] level-0 splitting (1 = C, 0 = F) */
 } nair_params;
@@ -93,7 +93,7 @@ typedef struct {
 } nair_level_view;
 
 /* Fill *p with the defaults (degree 1, theta 0.25, phi 0.025, drop 1e-3, F
- * relaxation, 30 levels, 512 dense DOFs, seed 0).  Host only. */
+ * relaxation, 30 levels, 128 dense DOFs, seed 0).  Host only. */
 nair_status nair_default_params(nair_params *p);
 
 /*
@@ -155,8 +155,9 @@ nair_status nair_pool_trim(void);
 /*
  * Kernel timer (profiling).  nair_timer_select(kernel, level) makes the
  * library bracket every later launch of that kernel on that level (-1: all
- * levels) with a pair of HIP events on the launch's stream; kernel = -1 turns
- * the timer off.  Kernels: 0 F/FC relaxation sweep, 1 residual, 2 restriction,
+ * levels) with a pair of HIP events on the launch's stream (the nu F sweeps
+ * of one cycle visit run back to back and are bracketed as one group of nu
+ * launches); kernel = -1 turns the timer off.  Kernels: 0 F/FC relaxation sweep, 1 residual, 2 restriction,
  * 3 interpolation, 4 SpGEMM numeric, 5 SpGEMM symbolic, 6 block inverse,
  * 7 Galerkin merge, 8 dense coarsest product.  nair_timer_read (host outputs)
  * synchronises the device and returns the number of timed launches and their

@@ -769,7 +769,7 @@ void ora_default_params(ora_params *p) {
     p->drop = 1e-3;
     p->relax = 0;
     p->max_levels = 30;
-    p->max_coarse_dofs = 512;
+    p->max_coarse_dofs = 128;
     p->seed = 0;
     p->cf_override = NULL;
 }

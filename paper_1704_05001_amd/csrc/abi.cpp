@@ -65,7 +65,7 @@ nair_status nair_default_params(nair_params *p) {
     p->drop = 1e-3;
     p->relax = 0;
     p->max_levels = 30;
-    p->max_coarse_dofs = 512;
+    p->max_coarse_dofs = 128;
     p->seed = 0;
     p->cf_override_host = nullptr;
     return NAIR_OK;

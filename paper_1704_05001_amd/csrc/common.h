@@ -93,7 +93,8 @@ enum TimedKernel { TK_RELAX = 0, TK_RESIDUAL = 1, TK_RESTRICT = 2, TK_INTERP = 3
 struct TimerScope {
     bool on;
     hipStream_t s;
-    TimerScope(int kernel, int level, hipStream_t stream);
+    // `launches`: number of back-to-back launches of the kernel inside the scope
+    TimerScope(int kernel, int level, hipStream_t stream, int launches = 1);
     ~TimerScope();
 };
 void timer_select(int kernel, int level);
@@ -159,8 +160,8 @@ void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevB
 
 // ------------------------------------------------------------------ dense
 // Inverse of the dense operator assembled from a BSR; returns false if singular.
-bool dense_inverse_from_bsr(const DevBSR &A, double *inv, hipStream_t s);
-void launch_dense_matvec(const double *M, const double *x, double *y, int n, bool trans, hipStream_t s);
+bool dense_inverse_from_bsr(const DevBSR &A, double *inv, double *invT, hipStream_t s);
+void launch_dense_matvec(const double *M, const double *x, double *y, int n, hipStream_t s);
 
 // -------------------------------------------------------------- transpose
 void bsr_transpose(const DevBSR &A, DevBSR &AT, hipStream_t s);   // blocks transposed too
@@ -171,6 +172,7 @@ void launch_residual(const DevBSR &A, const double *b, const double *x, double *
                      int npart, hipStream_t s);
 int residual_partials_count(const DevBSR &A);
 void launch_sumsq(const double *v, int64_t n, double *partials, int npart, hipStream_t s);
+int sumsq_partials_count(int64_t n);
 void launch_reduce_partials(const double *partials, int npart, double *out, hipStream_t s);
 // Jacobi sweep over `list` rows (list == nullptr: all rows; then rows with cf != only_cf are copied)
 void launch_relax(const DevBSR &A, const double *dinv, bool dinv_trans, const double *r, const double *ein,

@@ -1,7 +1,15 @@
 // Cycle kernels: block residual r = b - A x with fused squared norm, fused
-// block-Jacobi sweep (residual of the block row, then D^-1 or D^-T in LDS),
+// block-Jacobi sweep (residual of the block row, then D^-1 or D^-T from LDS),
 // restriction r_c = r_C + Z r_F, one-point interpolation, and the transposed
-// counterparts (P^T gather, R^T = [Z^T; I] scatter-free update).
+// counterparts (P^T gather, R^T = [Z^T; I] update).
+//
+// Mapping: a workgroup of 256 threads holds floor(256 / (G*bs)) block rows;
+// each block row gets G groups of bs lanes, lane (g, a) accumulating scalar row
+// a over the row's blocks g, g+G, ...; the G partial sums meet in LDS.  G is
+// picked per level from the average row length, so short rows (the fine level)
+// waste no lanes and long rows (coarse levels) are not serial.  The block size
+// is a template parameter for the common sizes, so a block row's loads issue
+// together; other sizes use the runtime-bs instance (bs <= 32).
 #include "common.h"
 
 namespace nair {
@@ -9,10 +17,71 @@ namespace {
 
 constexpr int kThreads = 256;
 
+template <int BS>
+struct Bs {
+    __device__ static constexpr int get(int) { return BS; }
+};
+template <>
+struct Bs<0> {
+    __device__ static int get(int bs) { return bs; }
+};
+
+// sum over blocks t = lo+g, lo+g+G, ... < hi of (block t row a) . x[col t]
+template <int BS>
+__device__ inline double row_part(const int *__restrict__ colidx, const double *__restrict__ vals, int lo, int hi,
+                                  int g, int G, int a, int bs_rt, const double *__restrict__ x) {
+    const int bs = Bs<BS>::get(bs_rt);
+    const int64_t bb = static_cast<int64_t>(bs) * bs;
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int t = lo + g; t < hi; t += G) {
+        const double *blk = vals + t * bb + a * bs;
+        const double *xj = x + static_cast<int64_t>(colidx[t]) * bs;
+        if constexpr (BS > 0) {
+#pragma unroll
+            for (int c = 0; c < BS; c += 2) {
+                acc0 += blk[c] * xj[c];
+                if (c + 1 < BS) acc1 += blk[c + 1] * xj[c + 1];
+            }
+        } else {
+#pragma unroll 4
+            for (int c = 0; c < bs; ++c) acc0 += blk[c] * xj[c];
+        }
+    }
+    return acc0 + acc1;
+}
+
+struct Lane {
+    int lr, g, a;   // local row, group, scalar row in block
+    bool valid;     // lr < rows per workgroup
+};
+
+__device__ inline Lane lane_of(int G, int bs) {
+    Lane L;
+    const int per_row = G * bs;
+    L.lr = threadIdx.x / per_row;
+    const int rem = threadIdx.x - L.lr * per_row;
+    L.g = rem / bs;
+    L.a = rem - L.g * bs;
+    L.valid = L.lr < kThreads / per_row;
+    return L;
+}
+
+// Sum the G partials of (lr, a) into the g == 0 lane (returns the total there).
+__device__ inline double reduce_groups(double v, const Lane &L, int G, int bs, double *part) {
+    if (G == 1) return v;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    double s = v;
+    if (L.valid && L.g == 0)
+        for (int g = 1; g < G; ++g) s += part[threadIdx.x + g * bs];
+    return s;
+}
+
 __device__ inline double block_reduce_sum(double v, double *lds) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
     if (lane == 0) lds[w] = v;
     __syncthreads();
     double s = 0.0;
@@ -21,32 +90,118 @@ __device__ inline double block_reduce_sum(double v, double *lds) {
     return s;   // valid in thread 0
 }
 
-// r = b - A x, one thread per scalar row; partials[block] = sum of r^2 over the block.
+// r = b - A x; partials[block] = sum of r^2 over the workgroup (if partials)
+template <int BS>
 __global__ __launch_bounds__(kThreads) void k_residual(const int *__restrict__ rowptr, const int *__restrict__ colidx,
-                                                      const double *__restrict__ vals, int nb, int bs,
+                                                      const double *__restrict__ vals, int nb, int bs_rt, int G,
                                                       const double *__restrict__ b, const double *__restrict__ x,
                                                       double *__restrict__ r, double *__restrict__ partials) {
-    __shared__ double lds[kThreads / 64];
-    const int64_t n = static_cast<int64_t>(nb) * bs;
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    __shared__ double part[kThreads];
+    __shared__ double red[kThreads / 64];
+    const int bs = Bs<BS>::get(bs_rt);
+    const Lane L = lane_of(G, bs);
+    const int I = blockIdx.x * (kThreads / (G * bs)) + L.lr;
+    const bool act = L.valid && I < nb;
+    double acc = act ? row_part<BS>(colidx, vals, rowptr[I], rowptr[I + 1], L.g, G, L.a, bs, x) : 0.0;
+    acc = reduce_groups(acc, L, G, bs, part);
     double v = 0.0;
-    if (g < n) {
-        const int I = static_cast<int>(g / bs);
-        const int a = static_cast<int>(g - static_cast<int64_t>(I) * bs);
-        const int bb = bs * bs;
-        double acc = 0.0;
-        for (int t = rowptr[I]; t < rowptr[I + 1]; ++t) {
-            const double *blk = vals + static_cast<int64_t>(t) * bb + a * bs;
-            const double *xj = x + static_cast<int64_t>(colidx[t]) * bs;
-            for (int c = 0; c < bs; ++c) acc += blk[c] * xj[c];
-        }
-        const double rv = b[g] - acc;
-        r[g] = rv;
+    if (act && L.g == 0) {
+        const int64_t o = static_cast<int64_t>(I) * bs + L.a;
+        const double rv = b[o] - acc;
+        r[o] = rv;
         v = rv * rv;
     }
     if (partials) {
-        const double s = block_reduce_sum(v, lds);
+        const double s = block_reduce_sum(v, red);
         if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    }
+}
+
+// One Jacobi sweep over the listed rows (list == nullptr: rows with cf == only_cf;
+// the other rows copy e_in): e_out_I = e_in_I + D_I^{-1} (r_I - (A e_in)_I).
+template <int BS>
+__global__ __launch_bounds__(kThreads) void k_relax(const int *__restrict__ rowptr, const int *__restrict__ colidx,
+                                                   const double *__restrict__ vals, const double *__restrict__ dinv,
+                                                   int dinv_trans, int nb, int bs_rt, int G,
+                                                   const double *__restrict__ r, const double *__restrict__ ein,
+                                                   double *__restrict__ eout, const int *__restrict__ list, int nlist,
+                                                   const int8_t *__restrict__ cf, int only_cf) {
+    __shared__ double part[kThreads];
+    __shared__ double tb[kThreads];
+    const int bs = Bs<BS>::get(bs_rt);
+    const Lane L = lane_of(G, bs);
+    const int idx = blockIdx.x * (kThreads / (G * bs)) + L.lr;
+    const int N = list ? nlist : nb;
+    int I = -1;
+    if (L.valid && idx < N) I = list ? list[idx] : idx;
+    const bool upd = I >= 0 && (list != nullptr || cf[I] == only_cf);
+    double acc = upd ? row_part<BS>(colidx, vals, rowptr[I], rowptr[I + 1], L.g, G, L.a, bs, ein) : 0.0;
+    acc = reduce_groups(acc, L, G, bs, part);
+    const int64_t o = static_cast<int64_t>(I) * bs + L.a;
+    if (upd && L.g == 0) tb[L.lr * bs + L.a] = r[o] - acc;
+    __syncthreads();
+    if (I >= 0 && L.g == 0) {
+        if (upd) {
+            const double *D = dinv + static_cast<int64_t>(I) * bs * bs;
+            const double *t = tb + L.lr * bs;
+            double d0 = 0.0, d1 = 0.0;
+            if (dinv_trans) {
+#pragma unroll
+                for (int c = 0; c < (BS > 0 ? BS : kMaxBs); c += 2) {
+                    if (BS == 0 && c >= bs) break;
+                    d0 += D[c * bs + L.a] * t[c];
+                    if (c + 1 < bs) d1 += D[(c + 1) * bs + L.a] * t[c + 1];
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < (BS > 0 ? BS : kMaxBs); c += 2) {
+                    if (BS == 0 && c >= bs) break;
+                    d0 += D[L.a * bs + c] * t[c];
+                    if (c + 1 < bs) d1 += D[L.a * bs + c + 1] * t[c + 1];
+                }
+            }
+            eout[o] = ein[o] + (d0 + d1);
+        } else {
+            eout[o] = ein[o];
+        }
+    }
+}
+
+// rc_i = r_{cpts[i]} + sum_t Z_it r_{col t}
+template <int BS>
+__global__ __launch_bounds__(kThreads) void k_restrict(const int *__restrict__ zrp, const int *__restrict__ zcol,
+                                                      const double *__restrict__ zval, int nc, int bs_rt, int G,
+                                                      const double *__restrict__ r, const int *__restrict__ cpts,
+                                                      double *__restrict__ rc) {
+    __shared__ double part[kThreads];
+    const int bs = Bs<BS>::get(bs_rt);
+    const Lane L = lane_of(G, bs);
+    const int i = blockIdx.x * (kThreads / (G * bs)) + L.lr;
+    const bool act = L.valid && i < nc;
+    double acc = act ? row_part<BS>(zcol, zval, zrp[i], zrp[i + 1], L.g, G, L.a, bs, r) : 0.0;
+    acc = reduce_groups(acc, L, G, bs, part);
+    if (act && L.g == 0)
+        rc[static_cast<int64_t>(i) * bs + L.a] = r[static_cast<int64_t>(cpts[i]) * bs + L.a] + acc;
+}
+
+// y_I += [I is C] yc_{cidx I} + sum_t (Z^T)_It yc_{col t}
+template <int BS>
+__global__ __launch_bounds__(kThreads) void k_interp_T(const int *__restrict__ ztrp, const int *__restrict__ ztcol,
+                                                      const double *__restrict__ ztval, int nb, int bs_rt, int G,
+                                                      const int *__restrict__ cidx, const double *__restrict__ yc,
+                                                      double *__restrict__ y) {
+    __shared__ double part[kThreads];
+    const int bs = Bs<BS>::get(bs_rt);
+    const Lane L = lane_of(G, bs);
+    const int I = blockIdx.x * (kThreads / (G * bs)) + L.lr;
+    const bool act = L.valid && I < nb;
+    double acc = act ? row_part<BS>(ztcol, ztval, ztrp[I], ztrp[I + 1], L.g, G, L.a, bs, yc) : 0.0;
+    acc = reduce_groups(acc, L, G, bs, part);
+    if (act && L.g == 0) {
+        const int64_t o = static_cast<int64_t>(I) * bs + L.a;
+        const int ci = cidx[I];
+        if (ci >= 0) acc += yc[static_cast<int64_t>(ci) * bs + L.a];
+        y[o] += acc;
     }
 }
 
@@ -66,71 +221,6 @@ __global__ __launch_bounds__(1024) void k_reduce_partials(const double *__restri
     for (int i = threadIdx.x; i < npart; i += 1024) s += partials[i];
     const double t = block_reduce_sum(s, lds);
     if (threadIdx.x == 0) *out = t;
-}
-
-// One Jacobi sweep: e_out_I = e_in_I + D_I^{-1} (r_I - (A e_in)_I) for the listed rows
-// (list == nullptr: every row with cf == only_cf; other rows copy e_in).
-// floor(256/bs) block rows per workgroup, bs threads per block row.
-__global__ __launch_bounds__(kThreads) void k_relax(const int *__restrict__ rowptr, const int *__restrict__ colidx,
-                                                   const double *__restrict__ vals, const double *__restrict__ dinv,
-                                                   int dinv_trans, int nb, int bs, const double *__restrict__ r,
-                                                   const double *__restrict__ ein, double *__restrict__ eout,
-                                                   const int *__restrict__ list, int nlist,
-                                                   const int8_t *__restrict__ cf, int only_cf) {
-    __shared__ double tb[kThreads];
-    const int rows = kThreads / bs;
-    const int lr = threadIdx.x / bs;
-    const int a = threadIdx.x - lr * bs;
-    const int idx = blockIdx.x * rows + lr;
-    const int N = list ? nlist : nb;
-    int I = -1;
-    if (lr < rows && idx < N) I = list ? list[idx] : idx;
-    const bool upd = I >= 0 && (list != nullptr || cf[I] == only_cf);
-    const int bb = bs * bs;
-    if (upd) {
-        double acc = 0.0;
-        for (int t = rowptr[I]; t < rowptr[I + 1]; ++t) {
-            const double *blk = vals + static_cast<int64_t>(t) * bb + a * bs;
-            const double *xj = ein + static_cast<int64_t>(colidx[t]) * bs;
-            for (int c = 0; c < bs; ++c) acc += blk[c] * xj[c];
-        }
-        tb[threadIdx.x] = r[static_cast<int64_t>(I) * bs + a] - acc;
-    }
-    __syncthreads();
-    if (I >= 0) {
-        const int64_t o = static_cast<int64_t>(I) * bs + a;
-        if (upd) {
-            const double *D = dinv + static_cast<int64_t>(I) * bb;
-            const double *t = tb + lr * bs;
-            double d = 0.0;
-            if (dinv_trans)
-                for (int c = 0; c < bs; ++c) d += D[c * bs + a] * t[c];
-            else
-                for (int c = 0; c < bs; ++c) d += D[a * bs + c] * t[c];
-            eout[o] = ein[o] + d;
-        } else {
-            eout[o] = ein[o];
-        }
-    }
-}
-
-// rc_i = r_{cpts[i]} + sum_t Z_it r_{col t}
-__global__ __launch_bounds__(kThreads) void k_restrict(const int *__restrict__ zrp, const int *__restrict__ zcol,
-                                                      const double *__restrict__ zval, int nc, int bs,
-                                                      const double *__restrict__ r, const int *__restrict__ cpts,
-                                                      double *__restrict__ rc) {
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-    if (g >= static_cast<int64_t>(nc) * bs) return;
-    const int i = static_cast<int>(g / bs);
-    const int a = static_cast<int>(g - static_cast<int64_t>(i) * bs);
-    const int bb = bs * bs;
-    double acc = 0.0;
-    for (int t = zrp[i]; t < zrp[i + 1]; ++t) {
-        const double *blk = zval + static_cast<int64_t>(t) * bb + a * bs;
-        const double *rj = r + static_cast<int64_t>(zcol[t]) * bs;
-        for (int c = 0; c < bs; ++c) acc += blk[c] * rj[c];
-    }
-    rc[g] = r[static_cast<int64_t>(cpts[i]) * bs + a] + acc;
 }
 
 __global__ __launch_bounds__(kThreads) void k_interp(const int *__restrict__ pmap, const double *__restrict__ ec,
@@ -158,27 +248,6 @@ __global__ __launch_bounds__(kThreads) void k_restrict_T(const int *__restrict__
     sc[g] = acc;
 }
 
-// y_I += [I is C] yc_{cidx I} + sum_t (Z^T)_It yc_{col t}
-__global__ __launch_bounds__(kThreads) void k_interp_T(const int *__restrict__ ztrp, const int *__restrict__ ztcol,
-                                                      const double *__restrict__ ztval, int nb, int bs,
-                                                      const int *__restrict__ cidx, const double *__restrict__ yc,
-                                                      double *__restrict__ y) {
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-    if (g >= static_cast<int64_t>(nb) * bs) return;
-    const int I = static_cast<int>(g / bs);
-    const int a = static_cast<int>(g - static_cast<int64_t>(I) * bs);
-    const int bb = bs * bs;
-    double acc = 0.0;
-    const int ci = cidx[I];
-    if (ci >= 0) acc = yc[static_cast<int64_t>(ci) * bs + a];
-    for (int t = ztrp[I]; t < ztrp[I + 1]; ++t) {
-        const double *blk = ztval + static_cast<int64_t>(t) * bb + a * bs;
-        const double *yj = yc + static_cast<int64_t>(ztcol[t]) * bs;
-        for (int c = 0; c < bs; ++c) acc += blk[c] * yj[c];
-    }
-    y[g] += acc;
-}
-
 // y0 = y1 = (FC ? [D_C^{-T} g_C ; 0] : 0)
 __global__ __launch_bounds__(kThreads) void k_init_T(const double *__restrict__ dinv, const double *__restrict__ g,
                                                     const int8_t *__restrict__ cf, int fc, double *__restrict__ y0,
@@ -202,18 +271,43 @@ __global__ __launch_bounds__(kThreads) void k_axpy(double *__restrict__ x, const
     if (g < n) x[g] += e[g];
 }
 
+// Lane groups per block row from the average row length (at most 256 lanes per row).
+int groups_for(int64_t nnz, int rows, int bs) {
+    const double avg = rows > 0 ? static_cast<double>(nnz) / rows : 1.0;
+    int G = avg <= 3.5 ? 1 : (avg <= 7.0 ? 2 : (avg <= 14.0 ? 4 : 8));
+    while (G > 1 && G * bs > kThreads) G >>= 1;
+    return G;
+}
+
+unsigned grid_rows(int64_t rows, int G, int bs) { return grid_for(rows, kThreads / (G * bs)); }
+
 }  // namespace
 
+#define NAIR_BS_DISPATCH(bs, KERNEL, ...)            \
+    switch (bs) {                                    \
+        case 2: KERNEL<2> __VA_ARGS__; break;        \
+        case 3: KERNEL<3> __VA_ARGS__; break;        \
+        case 4: KERNEL<4> __VA_ARGS__; break;        \
+        case 6: KERNEL<6> __VA_ARGS__; break;        \
+        case 9: KERNEL<9> __VA_ARGS__; break;        \
+        case 10: KERNEL<10> __VA_ARGS__; break;      \
+        case 16: KERNEL<16> __VA_ARGS__; break;      \
+        case 25: KERNEL<25> __VA_ARGS__; break;      \
+        default: KERNEL<0> __VA_ARGS__; break;       \
+    }
+
 int residual_partials_count(const DevBSR &A) {
-    return static_cast<int>(grid_for(static_cast<int64_t>(A.nb) * A.bs, kThreads));
+    const int G = groups_for(A.nnzb, A.nb, A.bs);
+    return static_cast<int>(grid_rows(A.nb, G, A.bs));
 }
 
 void launch_residual(const DevBSR &A, const double *b, const double *x, double *r, double *partials, int npart,
                      hipStream_t s) {
-    const int64_t n = static_cast<int64_t>(A.nb) * A.bs;
     (void)npart;
-    k_residual<<<grid_for(n, kThreads), kThreads, 0, s>>>(A.rowptr.get(), A.colidx.get(), A.vals.get(), A.nb, A.bs, b,
-                                                         x, r, partials);
+    const int G = groups_for(A.nnzb, A.nb, A.bs);
+    const unsigned grid = grid_rows(A.nb, G, A.bs);
+    NAIR_BS_DISPATCH(A.bs, k_residual, <<<grid, kThreads, 0, s>>>(A.rowptr.get(), A.colidx.get(), A.vals.get(),
+                                                                  A.nb, A.bs, G, b, x, r, partials));
     NAIR_HIP(hipGetLastError());
 }
 
@@ -223,6 +317,8 @@ void launch_sumsq(const double *v, int64_t n, double *partials, int npart, hipSt
     NAIR_HIP(hipGetLastError());
 }
 
+int sumsq_partials_count(int64_t n) { return static_cast<int>(grid_for(n, kThreads)); }
+
 void launch_reduce_partials(const double *partials, int npart, double *out, hipStream_t s) {
     k_reduce_partials<<<1, 1024, 0, s>>>(partials, npart, out);
     NAIR_HIP(hipGetLastError());
@@ -230,20 +326,22 @@ void launch_reduce_partials(const double *partials, int npart, double *out, hipS
 
 void launch_relax(const DevBSR &A, const double *dinv, bool dinv_trans, const double *r, const double *ein,
                   double *eout, const int *list, int nlist, const int8_t *cf, int only_cf, hipStream_t s) {
-    const int rows = kThreads / A.bs;
     const int N = list ? nlist : A.nb;
     if (N <= 0) return;
-    k_relax<<<grid_for(N, rows), kThreads, 0, s>>>(A.rowptr.get(), A.colidx.get(), A.vals.get(), dinv,
-                                                  dinv_trans ? 1 : 0, A.nb, A.bs, r, ein, eout, list, nlist, cf,
-                                                  only_cf);
+    const int G = groups_for(A.nnzb, A.nb, A.bs);
+    const unsigned grid = grid_rows(N, G, A.bs);
+    NAIR_BS_DISPATCH(A.bs, k_relax, <<<grid, kThreads, 0, s>>>(A.rowptr.get(), A.colidx.get(), A.vals.get(), dinv,
+                                                               dinv_trans ? 1 : 0, A.nb, A.bs, G, r, ein, eout, list,
+                                                               nlist, cf, only_cf));
     NAIR_HIP(hipGetLastError());
 }
 
 void launch_restrict(const DevBSR &Z, const double *r, const int *cpts, double *rc, hipStream_t s) {
-    const int64_t n = static_cast<int64_t>(Z.nb) * Z.bs;
-    if (n <= 0) return;
-    k_restrict<<<grid_for(n, kThreads), kThreads, 0, s>>>(Z.rowptr.get(), Z.colidx.get(), Z.vals.get(), Z.nb, Z.bs, r,
-                                                         cpts, rc);
+    if (Z.nb <= 0) return;
+    const int G = groups_for(Z.nnzb, Z.nb, Z.bs);
+    const unsigned grid = grid_rows(Z.nb, G, Z.bs);
+    NAIR_BS_DISPATCH(Z.bs, k_restrict, <<<grid, kThreads, 0, s>>>(Z.rowptr.get(), Z.colidx.get(), Z.vals.get(), Z.nb,
+                                                                  Z.bs, G, r, cpts, rc));
     NAIR_HIP(hipGetLastError());
 }
 
@@ -261,8 +359,10 @@ void launch_restrict_T(const int *ptptr, const int *ptidx, const double *sv, dou
 }
 
 void launch_interp_T(const DevBSR &ZT, const int *cidx, const double *yc, double *y, hipStream_t s) {
-    k_interp_T<<<grid_for(static_cast<int64_t>(ZT.nb) * ZT.bs, kThreads), kThreads, 0, s>>>(
-        ZT.rowptr.get(), ZT.colidx.get(), ZT.vals.get(), ZT.nb, ZT.bs, cidx, yc, y);
+    const int G = groups_for(ZT.nnzb, ZT.nb, ZT.bs);
+    const unsigned grid = grid_rows(ZT.nb, G, ZT.bs);
+    NAIR_BS_DISPATCH(ZT.bs, k_interp_T, <<<grid, kThreads, 0, s>>>(ZT.rowptr.get(), ZT.colidx.get(), ZT.vals.get(),
+                                                                   ZT.nb, ZT.bs, G, cidx, yc, y));
     NAIR_HIP(hipGetLastError());
 }
 

@@ -21,7 +21,7 @@ struct Level {
     DevBSR Z;                       // R = [Z I]: nc rows, fine F columns
     // coarsest level
     int dense_n = 0;
-    DBuf<double> dense_inv;
+    DBuf<double> dense_inv, dense_invT;
     // transposed cycle (built on first use)
     bool have_T = false;
     DevBSR AT, ZT;

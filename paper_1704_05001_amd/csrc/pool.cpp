@@ -108,6 +108,7 @@ struct Timer {
     std::mutex mu;
     int kernel = -1, level = -1;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    std::vector<int> pending_count;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> spare;
     int64_t launches = 0;
     double total_ms = 0.0;
@@ -118,7 +119,7 @@ Timer &timer() {
 }
 }  // namespace
 
-TimerScope::TimerScope(int kernel, int level, hipStream_t stream) : on(false), s(stream) {
+TimerScope::TimerScope(int kernel, int level, hipStream_t stream, int launches) : on(false), s(stream) {
     Timer &T = timer();
     if (T.kernel != kernel || (T.level >= 0 && T.level != level)) return;
     std::lock_guard<std::mutex> lk(T.mu);
@@ -132,6 +133,7 @@ TimerScope::TimerScope(int kernel, int level, hipStream_t stream) : on(false), s
     }
     NAIR_HIP(hipEventRecord(ev.first, s));
     T.pending.push_back(ev);
+    T.pending_count.push_back(launches);
     on = true;
 }
 
@@ -152,15 +154,17 @@ void timer_select(int kernel, int level) {
 void timer_read(int64_t *launches, double *total_ms) {
     Timer &T = timer();
     std::lock_guard<std::mutex> lk(T.mu);
-    for (auto &ev : T.pending) {
+    for (size_t k = 0; k < T.pending.size(); ++k) {
+        auto &ev = T.pending[k];
         NAIR_HIP(hipEventSynchronize(ev.second));
         float ms = 0.0f;
         NAIR_HIP(hipEventElapsedTime(&ms, ev.first, ev.second));
         T.total_ms += ms;
-        T.launches += 1;
+        T.launches += T.pending_count[k];
         T.spare.push_back(ev);
     }
     T.pending.clear();
+    T.pending_count.clear();
     if (launches) *launches = T.launches;
     if (total_ms) *total_ms = T.total_ms;
     T.launches = 0;

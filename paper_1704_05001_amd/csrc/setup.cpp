@@ -38,7 +38,8 @@ void make_coarsest(Level &L, int lvl, hipStream_t s) {
     L.coarsest = true;
     L.dense_n = L.A.nb * L.A.bs;
     L.dense_inv.alloc(static_cast<size_t>(L.dense_n) * L.dense_n);
-    if (!dense_inverse_from_bsr(L.A, L.dense_inv.get(), s))
+    L.dense_invT.alloc(static_cast<size_t>(L.dense_n) * L.dense_n);
+    if (!dense_inverse_from_bsr(L.A, L.dense_inv.get(), L.dense_invT.get(), s))
         fail(NAIR_ESINGULAR, "coarsest operator (level " + std::to_string(lvl) + ", " +
                                  std::to_string(L.dense_n) + " unknowns) is singular");
 }

@@ -370,23 +370,38 @@ __global__ __launch_bounds__(256) void k_fill_Acf(const int *__restrict__ rowptr
 }
 
 // out[t] = sign * (X[xi[t]] Y[yi[t]]): entry (a,b) = fma chain over c ascending
-// from +0.  One wave per block; xi == nullptr means xi[t] = t.
-__global__ __launch_bounds__(256) void k_block_product(int64_t n, int bs, const double *__restrict__ X,
+// from +0.  One thread per (block, row a) with the row's accumulators in
+// registers; xi == nullptr means xi[t] = t.
+template <int BS>
+__global__ __launch_bounds__(256) void k_block_product(int64_t n, int bs_rt, const double *__restrict__ X,
                                                       const int *__restrict__ xi, const double *__restrict__ Y,
                                                       const int *__restrict__ yi, double sign,
                                                       double *__restrict__ out) {
-    const int lane = threadIdx.x & 63;
+    constexpr int NB = BS > 0 ? BS : kMaxBs;
+    const int bs = BS > 0 ? BS : bs_rt;
     const int bb = bs * bs;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * 4;
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6); t < n; t += stride) {
-        const double *x = X + static_cast<int64_t>(xi ? xi[t] : t) * bb;
+    const int64_t total = n * bs;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t t = g / bs;
+        const int a = static_cast<int>(g - t * bs);
+        const double *x = X + static_cast<int64_t>(xi ? xi[t] : t) * bb + a * bs;
         const double *y = Y + static_cast<int64_t>(yi[t]) * bb;
-        for (int e = lane; e < bb; e += kWave) {
-            const int a = e / bs, b = e % bs;
-            double acc = 0.0;
-            for (int c = 0; c < bs; ++c) acc = __builtin_fma(x[a * bs + c], y[c * bs + b], acc);
-            out[t * bb + e] = sign * acc;
+        double acc[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[b] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            if (BS == 0 && c >= bs) break;
+            const double xc = x[c];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                if (BS > 0 || b < bs) acc[b] = __builtin_fma(xc, y[c * bs + b], acc[b]);
         }
+        double *o = out + t * bb + a * bs;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            if (BS > 0 || b < bs) o[b] = sign * acc[b];
     }
 }
 
@@ -497,7 +512,14 @@ void launch_fill_Acf(const int *rowptr, const int *colidx, const int8_t *cf, con
 void launch_block_product(int64_t n, int bs, const double *X, const int *xi, const double *Y, const int *yi,
                           double sign, double *out, hipStream_t s) {
     if (n <= 0) return;
-    k_block_product<<<cap_grid((n + 3) / 4), 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out);
+    const unsigned grid = cap_grid((n * bs + 255) / 256);
+    switch (bs) {
+        case 4: k_block_product<4><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out); break;
+        case 9: k_block_product<9><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out); break;
+        case 16: k_block_product<16><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out); break;
+        case 25: k_block_product<25><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out); break;
+        default: k_block_product<0><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out); break;
+    }
     NAIR_HIP(hipGetLastError());
 }
 

@@ -1,4 +1,5 @@
 // Solve phase: the V-cycle and its transpose, and the stationary iteration.
+#include <algorithm>
 #include <cmath>
 #include <utility>
 
@@ -22,7 +23,7 @@ const double *vcycle(Hier &h, int l, hipStream_t s) {
     const int bs = h.bs;
     if (L.coarsest) {
         TimerScope ts(TK_DENSE, l, s);
-        launch_dense_matvec(L.dense_inv.get(), L.r.get(), L.e0.get(), L.dense_n, false, s);
+        launch_dense_matvec(L.dense_inv.get(), L.r.get(), L.e0.get(), L.dense_n, s);
         return L.e0.get();
     }
     Level &C = *h.lv[l + 1];
@@ -36,18 +37,16 @@ const double *vcycle(Hier &h, int l, hipStream_t s) {
         launch_interp(L.pmap.get(), ec, L.e0.get(), L.e1.get(), L.A.nb, bs, s);
     }
     double *cur = L.e0.get(), *oth = L.e1.get();
-    for (int k = 0; k <= h.prm.degree; ++k) {
-        {
-            TimerScope ts(TK_RELAX, l, s);
+    {
+        // the nu sweeps run back to back; the timer brackets them as one group
+        TimerScope ts(TK_RELAX, l, s, h.prm.degree + 1);
+        for (int k = 0; k <= h.prm.degree; ++k) {
             launch_relax(L.A, L.dinv.get(), false, L.r.get(), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s);
+            std::swap(cur, oth);
         }
-        std::swap(cur, oth);
     }
     if (h.prm.relax == 1) {
-        {
-            TimerScope ts(TK_RELAX, l, s);
-            launch_relax(L.A, L.dinv.get(), false, L.r.get(), cur, oth, nullptr, 0, L.cf.get(), 1, s);
-        }
+        launch_relax(L.A, L.dinv.get(), false, L.r.get(), cur, oth, nullptr, 0, L.cf.get(), 1, s);
         std::swap(cur, oth);
     }
     return cur;
@@ -61,7 +60,7 @@ const double *vcycle_T(Hier &h, int l, hipStream_t s) {
     const int bs = h.bs;
     if (L.coarsest) {
         TimerScope ts(TK_DENSE, l, s);
-        launch_dense_matvec(L.dense_inv.get(), L.r.get(), L.e0.get(), L.dense_n, true, s);
+        launch_dense_matvec(L.dense_invT.get(), L.r.get(), L.e0.get(), L.dense_n, s);
         return L.e0.get();
     }
     Level &C = *h.lv[l + 1];
@@ -80,7 +79,9 @@ const double *vcycle_T(Hier &h, int l, hipStream_t s) {
 }
 
 void ensure_work(Hier &h) {
-    const int np = residual_partials_count(h.lv[0]->A);
+    const Level &L0 = *h.lv[0];
+    const int np = std::max(residual_partials_count(L0.A),
+                            sumsq_partials_count(static_cast<int64_t>(L0.A.nb) * h.bs));
     if (h.npart < np) {
         h.partials.alloc(np);
         h.npart = np;
@@ -100,7 +101,7 @@ nair_status run_solve(Hier &h, bool trans, const double *b, double *x, double rt
     nair_result rr{0, 0, 0.0, 0.0, 0.0};
     NAIR_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
     launch_sumsq(b, n, h.partials.get(), h.npart, s);
-    launch_reduce_partials(h.partials.get(), residual_partials_count(L0.A), h.scal.get(), s);
+    launch_reduce_partials(h.partials.get(), sumsq_partials_count(n), h.scal.get(), s);
     const double bn = std::sqrt(read_double(h.scal.get(), s));
     nair_status st = NAIR_ENOCONV;
     if (!std::isfinite(bn)) {

@@ -114,11 +114,15 @@ __global__ __launch_bounds__(256) void k_symbolic_small(const int *__restrict__ 
     for (int i0 = blockIdx.x * 4; i0 < m; i0 += gridDim.x * 4) {
         const int i = i0 + w;
         const bool active = i < m && ub[i] <= small_cap;
-        for (int s = lane; s < kHashSmall; s += kWave) table[s] = kEmpty;
+        // table of the next power of two >= 2 ub slots (at least one per lane)
+        int slots = kWave;
+        if (active)
+            while (slots < 2 * ub[i]) slots <<= 1;
+        for (int s = lane; s < slots; s += kWave) table[s] = kEmpty;
         if (lane == 0) counts[w] = 0;
         __syncthreads();
         int added = 0;
-        if (active) added = insert_row_keys(i, xrowptr, xcol, xdiag, yrowptr, ycol, table, kHashSmall - 1, lane, kWave);
+        if (active) added = insert_row_keys(i, xrowptr, xcol, xdiag, yrowptr, ycol, table, slots - 1, lane, kWave);
         __syncthreads();
         if (mode == 0) {
 #pragma unroll
@@ -128,7 +132,7 @@ __global__ __launch_bounds__(256) void k_symbolic_small(const int *__restrict__ 
             // emit_sorted synchronises the whole workgroup, so every wave runs it
             int *list = lists[w];
             int *dst = active ? ccol + crowptr[i] : nullptr;
-            for (int s = lane; s < kHashSmall; s += kWave) {
+            for (int s = lane; s < slots; s += kWave) {
                 const int k = table[s];
                 if (active && k != kEmpty) list[atomicAdd(&counts[w], 1)] = k;
             }
@@ -177,76 +181,6 @@ __global__ __launch_bounds__(256) void k_symbolic_large(const int *__restrict__ 
             emit_sorted(table, kHashLarge, list, &nlist, ccol + crowptr[i], threadIdx.x, blockDim.x);
         }
         __syncthreads();
-    }
-}
-
-// ----------------------------------------------------- SpGEMM numeric phase
-
-__global__ __launch_bounds__(kNumThreads) void k_spgemm_numeric(
-    const int *__restrict__ xrowptr, const int *__restrict__ xcol, const double *__restrict__ xval,
-    const int *__restrict__ xdiag, const int *__restrict__ yrowptr, const int *__restrict__ ycol,
-    const double *__restrict__ yval, int m, const int *__restrict__ crowptr, const int *__restrict__ ccol,
-    double *__restrict__ cval, int bs, int tile_blocks) {
-    extern __shared__ double lds_d[];
-    const int bb = bs * bs;
-    double *acc = lds_d;                                  // tile_blocks * bb
-    double *xblk = acc + static_cast<size_t>(tile_blocks) * bb;   // bb
-    int *cols = reinterpret_cast<int *>(xblk + bb);       // kOutColsLds
-    int *ypos = cols + kOutColsLds;                       // kPosLds
-    const int tid = threadIdx.x;
-    for (int i = blockIdx.x; i < m; i += gridDim.x) {
-        const int c0 = crowptr[i];
-        const int nout = crowptr[i + 1] - c0;
-        const bool cols_in_lds = nout <= kOutColsLds;
-        if (cols_in_lds)
-            for (int p = tid; p < nout; p += kNumThreads) cols[p] = ccol[c0 + p];
-        const int *colsrc = cols_in_lds ? cols : ccol + c0;
-        for (int p0 = 0; p0 < nout; p0 += tile_blocks) {
-            const int pt = min(tile_blocks, nout - p0);
-            for (int e = tid; e < pt * bb; e += kNumThreads) acc[e] = 0.0;
-            __syncthreads();
-            const int q0 = xrowptr[i], q1 = xrowptr[i + 1];
-            int q = q0;
-            bool diag_pending = xdiag != nullptr;
-            while (q < q1 || diag_pending) {
-                const bool take_diag = diag_pending && (q >= q1 || xdiag[i] < xcol[q]);
-                const int K = take_diag ? xdiag[i] : xcol[q];
-                if (!take_diag)
-                    for (int e = tid; e < bb; e += kNumThreads) xblk[e] = xval[static_cast<int64_t>(q) * bb + e];
-                const int ylo = yrowptr[K];
-                const int yn = yrowptr[K + 1] - ylo;
-                for (int u0 = 0; u0 < yn; u0 += kPosLds) {
-                    const int un = min(kPosLds, yn - u0);
-                    for (int u = tid; u < un; u += kNumThreads) {
-                        const int p = find_pos(colsrc, nout, ycol[ylo + u0 + u]);
-                        ypos[u] = (p >= p0 && p < p0 + pt) ? p - p0 : -1;
-                    }
-                    __syncthreads();
-                    for (int wi = tid; wi < un * bb; wi += kNumThreads) {
-                        const int u = wi / bb;
-                        const int lp = ypos[u];
-                        if (lp < 0) continue;
-                        const int e = wi - u * bb;
-                        const double *y = yval + static_cast<int64_t>(ylo + u0 + u) * bb;
-                        double s = acc[lp * bb + e];
-                        if (take_diag) {
-                            s = s + y[e];
-                        } else {
-                            const int a = e / bs, b = e - a * bs;
-                            const double *xr = xblk + a * bs;
-                            for (int c = 0; c < bs; ++c) s = __builtin_fma(xr[c], y[c * bs + b], s);
-                        }
-                        acc[lp * bb + e] = s;
-                    }
-                    __syncthreads();
-                }
-                if (take_diag) diag_pending = false;
-                else ++q;
-            }
-            double *dst = cval + static_cast<int64_t>(c0 + p0) * bb;
-            for (int e = tid; e < pt * bb; e += kNumThreads) dst[e] = acc[e];
-            __syncthreads();
-        }
     }
 }
 
@@ -332,14 +266,17 @@ __global__ __launch_bounds__(256) void k_rap_symbolic(const int *__restrict__ ra
         const int i = i0 + w;
         const bool active = i < m && (rarp[i + 1] - rarp[i]) <= kHashSmall / 2;
         if (i < m && !active && lane == 0) atomicMax(too_dense, rarp[i + 1] - rarp[i]);
-        for (int s = lane; s < kHashSmall; s += kWave) table[s] = kEmpty;
+        int slots = kWave;
+        if (active)
+            while (slots < 2 * (rarp[i + 1] - rarp[i])) slots <<= 1;
+        for (int s = lane; s < slots; s += kWave) table[s] = kEmpty;
         if (lane == 0) counts[w] = 0;
         __syncthreads();
         int added = 0;
         if (active)
             for (int u = rarp[i] + lane; u < rarp[i + 1]; u += kWave) {
                 const int t = pmap[racol[u]];
-                if (t >= 0) added += hash_insert(table, kHashSmall - 1, t) ? 1 : 0;
+                if (t >= 0) added += hash_insert(table, slots - 1, t) ? 1 : 0;
             }
         __syncthreads();
         if (mode == 0) {
@@ -348,7 +285,7 @@ __global__ __launch_bounds__(256) void k_rap_symbolic(const int *__restrict__ ra
             if (active && lane == 0) cnt[i] = added;
         } else {
             int *list = lists[w];
-            for (int s = lane; s < kHashSmall; s += kWave) {
+            for (int s = lane; s < slots; s += kWave) {
                 const int k = table[s];
                 if (active && k != kEmpty) list[atomicAdd(&counts[w], 1)] = k;
             }
@@ -362,67 +299,6 @@ __global__ __launch_bounds__(256) void k_rap_symbolic(const int *__restrict__ ra
                 dst[r] = k;
             }
         }
-        __syncthreads();
-    }
-}
-
-// K_{i,p} = sum over RA blocks u (ascending column) with pmap(col u) = kcol[p] of RA_u,
-// then block sizes, the diagonal's size and the keep flags of the drop filter.
-__global__ __launch_bounds__(kNumThreads) void k_rap_numeric(const int *__restrict__ rarp, const int *__restrict__ racol,
-                                                            const double *__restrict__ raval,
-                                                            const int *__restrict__ pmap, int m,
-                                                            const int *__restrict__ krp, const int *__restrict__ kcol,
-                                                            double *__restrict__ kval, int bs, double drop,
-                                                            uint8_t *__restrict__ keep, int *__restrict__ kept_cnt) {
-    __shared__ int tpos[kHashSmall / 2];
-    __shared__ int kc[kHashSmall / 2];
-    __shared__ double bn[kHashSmall / 2];
-    __shared__ double dnorm;
-    __shared__ int nkept;
-    const int bb = bs * bs;
-    const int tid = threadIdx.x;
-    for (int i = blockIdx.x; i < m; i += gridDim.x) {
-        const int r0 = rarp[i], nra = rarp[i + 1] - r0;
-        const int k0 = krp[i], nk = krp[i + 1] - k0;
-        if (nra > kHashSmall / 2) continue;   // reported by the symbolic phase
-        for (int p = tid; p < nk; p += kNumThreads) kc[p] = kcol[k0 + p];
-        if (tid == 0) {
-            dnorm = 0.0;
-            nkept = 0;
-        }
-        __syncthreads();
-        for (int u = tid; u < nra; u += kNumThreads) {
-            const int t = pmap[racol[r0 + u]];
-            tpos[u] = (t >= 0) ? find_pos(kc, nk, t) : -1;
-        }
-        __syncthreads();
-        for (int w = tid; w < nk * bb; w += kNumThreads) {
-            const int p = w / bb;
-            const int e = w - p * bb;
-            double s = 0.0;
-            for (int u = 0; u < nra; ++u)
-                if (tpos[u] == p) s = s + raval[static_cast<int64_t>(r0 + u) * bb + e];
-            kval[static_cast<int64_t>(k0) * bb + w] = s;
-        }
-        __syncthreads();
-        for (int p = tid; p < nk; p += kNumThreads) {
-            const double *blk = kval + static_cast<int64_t>(k0 + p) * bb;
-            double mx = 0.0;
-            for (int e = 0; e < bb; ++e) mx = fmax(mx, fabs(blk[e]));
-            bn[p] = mx;
-            if (kc[p] == i) dnorm = mx;
-        }
-        __syncthreads();
-        const double thr = drop * dnorm;
-        int mine = 0;
-        for (int p = tid; p < nk; p += kNumThreads) {
-            const bool kp = (kc[p] == i) || (bn[p] > thr);
-            keep[k0 + p] = kp ? 1 : 0;
-            mine += kp ? 1 : 0;
-        }
-        if (mine) atomicAdd(&nkept, mine);
-        __syncthreads();
-        if (tid == 0) kept_cnt[i] = nkept;
         __syncthreads();
     }
 }
@@ -446,6 +322,271 @@ unsigned cap_grid(int64_t g) { return static_cast<unsigned>(g > 65536 * 16 ? 655
 
 }  // namespace
 
+namespace {
+
+// Position of the implicit identity column among X's sorted row [q0, q1).
+__device__ inline int identity_slot(const int *__restrict__ xcol, int q0, int q1, int dcol) {
+    int lo = q0, hi = q1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (xcol[mid] < dcol) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo - q0;
+}
+
+// Exclusive scan of cnt[0..n) in place by the first wave of the workgroup.
+__device__ inline void wave0_scan(int *cnt, int n) {
+    if (threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
+    int carry = 0;
+    for (int base = 0; base < n; base += 64) {
+        const int v = (base + lane < n) ? cnt[base + lane] : 0;
+        int x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (base + lane < n) cnt[base + lane] = carry + x - v;
+        carry += __shfl(x, 63, 64);
+    }
+}
+
+// Contribution lists of one output row: for every output block, the (X block,
+// Y block) pairs that feed it, in ascending inner index (X's sorted row with the
+// identity merged in; the identity is X block -1).  `cols` (LDS) holds the row's
+// sorted output columns, `cnt` (LDS) gets per-block counts, then offsets.
+__device__ inline void row_pairs(int i, const int *__restrict__ xrowptr, const int *__restrict__ xcol,
+                                 const int *__restrict__ xdiag, const int *__restrict__ yrowptr,
+                                 const int *__restrict__ ycol, int c0, int nout, int P0, const int *cols, int *cnt,
+                                 int *__restrict__ pairptr, int2 *__restrict__ pairs) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int q0 = xrowptr[i], q1 = xrowptr[i + 1];
+    const int nx = q1 - q0;
+    const int dslot = xdiag ? identity_slot(xcol, q0, q1, xdiag[i]) : -1;
+    const int nk = nx + (xdiag ? 1 : 0);
+    for (int qq = 0; qq < nk; ++qq) {
+        const int K = (qq == dslot) ? xdiag[i] : xcol[q0 + qq - ((dslot >= 0 && qq > dslot) ? 1 : 0)];
+        for (int u = yrowptr[K] + tid; u < yrowptr[K + 1]; u += nthr) atomicAdd(&cnt[find_pos(cols, nout, ycol[u])], 1);
+    }
+    __syncthreads();
+    wave0_scan(cnt, nout);
+    __syncthreads();
+    for (int p = tid; p < nout; p += nthr) pairptr[c0 + p] = P0 + cnt[p];
+    __syncthreads();
+    for (int qq = 0; qq < nk; ++qq) {
+        const bool ident = qq == dslot;
+        const int q = ident ? -1 : q0 + qq - ((dslot >= 0 && qq > dslot) ? 1 : 0);
+        const int K = ident ? xdiag[i] : xcol[q];
+        for (int u = yrowptr[K] + tid; u < yrowptr[K + 1]; u += nthr) {
+            const int p = find_pos(cols, nout, ycol[u]);
+            const int pos = cnt[p];     // one writer per block within an inner step
+            cnt[p] = pos + 1;
+            pairs[P0 + pos] = make_int2(q, u);
+        }
+        __syncthreads();
+    }
+}
+
+// Rows with ub <= small cap: one 64-thread workgroup per row.
+__global__ __launch_bounds__(64) void k_pairs_small(const int *__restrict__ xrowptr, const int *__restrict__ xcol,
+                                                   const int *__restrict__ xdiag, const int *__restrict__ yrowptr,
+                                                   const int *__restrict__ ycol, int m, const int *__restrict__ ub,
+                                                   int small_cap, const int *__restrict__ crowptr,
+                                                   const int *__restrict__ ccol, const int *__restrict__ prow,
+                                                   int *__restrict__ pairptr, int2 *__restrict__ pairs) {
+    __shared__ int cols[kHashSmall / 2];
+    __shared__ int cnt[kHashSmall / 2];
+    for (int i = blockIdx.x; i < m; i += gridDim.x) {
+        if (ub[i] > small_cap) continue;
+        const int c0 = crowptr[i], nout = crowptr[i + 1] - c0;
+        for (int p = threadIdx.x; p < nout; p += 64) {
+            cols[p] = ccol[c0 + p];
+            cnt[p] = 0;
+        }
+        __syncthreads();
+        row_pairs(i, xrowptr, xcol, xdiag, yrowptr, ycol, c0, nout, prow[i], cols, cnt, pairptr, pairs);
+        __syncthreads();
+    }
+}
+
+// Rows listed in big_list: one 256-thread workgroup per row.
+__global__ __launch_bounds__(256) void k_pairs_large(const int *__restrict__ xrowptr, const int *__restrict__ xcol,
+                                                    const int *__restrict__ xdiag, const int *__restrict__ yrowptr,
+                                                    const int *__restrict__ ycol, const int *__restrict__ big_list,
+                                                    const int *__restrict__ big_count, const int *__restrict__ crowptr,
+                                                    const int *__restrict__ ccol, const int *__restrict__ prow,
+                                                    int *__restrict__ pairptr, int2 *__restrict__ pairs) {
+    __shared__ int cols[kHashLarge / 2];
+    __shared__ int cnt[kHashLarge / 2];
+    const int nbig = *big_count;
+    for (int bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
+        const int i = big_list[bi];
+        const int c0 = crowptr[i], nout = crowptr[i + 1] - c0;
+        for (int p = threadIdx.x; p < nout; p += blockDim.x) {
+            cols[p] = ccol[c0 + p];
+            cnt[p] = 0;
+        }
+        __syncthreads();
+        row_pairs(i, xrowptr, xcol, xdiag, yrowptr, ycol, c0, nout, prow[i], cols, cnt, pairptr, pairs);
+        __syncthreads();
+    }
+}
+
+// C[t] entry (a,b) = fma chain over the pairs of block t (ascending inner index)
+// and c ascending, from +0; identity pairs add Y's entry plainly.  One thread
+// per (output block, block row a) keeps the row's bs accumulators in registers
+// and reads contiguous rows of X and Y.
+template <int BS>
+__global__ __launch_bounds__(256) void k_spgemm_pairs(int64_t nnz, int bs_rt, const int *__restrict__ pairptr,
+                                                     const int2 *__restrict__ pairs, const double *__restrict__ X,
+                                                     const double *__restrict__ Y, double *__restrict__ C) {
+    constexpr int NB = BS > 0 ? BS : kMaxBs;
+    const int bs = BS > 0 ? BS : bs_rt;
+    const int bb = bs * bs;
+    const int64_t total = nnz * bs;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t t = g / bs;
+        const int a = static_cast<int>(g - t * bs);
+        double acc[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[b] = 0.0;
+        for (int k = pairptr[t]; k < pairptr[t + 1]; ++k) {
+            const int2 pr = pairs[k];
+            const double *y = Y + static_cast<int64_t>(pr.y) * bb;
+            if (pr.x < 0) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    if (BS > 0 || b < bs) acc[b] = acc[b] + y[a * bs + b];
+            } else {
+                const double *x = X + static_cast<int64_t>(pr.x) * bb + a * bs;
+#pragma unroll
+                for (int c = 0; c < NB; ++c) {
+                    if (BS == 0 && c >= bs) break;
+                    const double xc = x[c];
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        if (BS > 0 || b < bs) acc[b] = __builtin_fma(xc, y[c * bs + b], acc[b]);
+                }
+            }
+        }
+        double *out = C + t * bb + a * bs;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            if (BS > 0 || b < bs) out[b] = acc[b];
+    }
+}
+
+// ---------------------------------------------------- Galerkin merge lists
+
+__global__ __launch_bounds__(256) void k_rap_count_contrib(const int *__restrict__ rarp, const int *__restrict__ racol,
+                                                          const int *__restrict__ pmap, int m, int *__restrict__ cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int c = 0;
+    for (int u = rarp[i]; u < rarp[i + 1]; ++u) c += (pmap[racol[u]] >= 0) ? 1 : 0;
+    cnt[i] = c;
+}
+
+// For K's row i: the RA blocks of row i merged into each K block, in ascending
+// RA column.  One 64-thread workgroup per row (rows have <= 1024 RA blocks).
+__global__ __launch_bounds__(64) void k_rap_contrib(const int *__restrict__ rarp, const int *__restrict__ racol,
+                                                   const int *__restrict__ pmap, int m, const int *__restrict__ krp,
+                                                   const int *__restrict__ kcol, const int *__restrict__ crow,
+                                                   int *__restrict__ kptr, int *__restrict__ klist) {
+    __shared__ int kc[kHashSmall / 2];
+    __shared__ int off[kHashSmall / 2];
+    const int lane = threadIdx.x;
+    for (int i = blockIdx.x; i < m; i += gridDim.x) {
+        const int r0 = rarp[i], nra = rarp[i + 1] - r0;
+        const int k0 = krp[i], nk = krp[i + 1] - k0;
+        const int R0 = crow[i];
+        for (int p = lane; p < nk; p += 64) {
+            kc[p] = kcol[k0 + p];
+            off[p] = 0;
+        }
+        __syncthreads();
+        for (int u = lane; u < nra; u += 64) {
+            const int t = pmap[racol[r0 + u]];
+            if (t >= 0) atomicAdd(&off[find_pos(kc, nk, t)], 1);
+        }
+        __syncthreads();
+        wave0_scan(off, nk);
+        __syncthreads();
+        for (int p = lane; p < nk; p += 64) kptr[k0 + p] = R0 + off[p];
+        __syncthreads();
+        for (int u0 = 0; u0 < nra; u0 += 64) {
+            const int u = u0 + lane;
+            int p = -1;
+            if (u < nra) {
+                const int t = pmap[racol[r0 + u]];
+                if (t >= 0) p = find_pos(kc, nk, t);
+            }
+            int rank = 0;
+            for (int l = 0; l < 64; ++l) {
+                const int pl = __shfl(p, l, 64);
+                rank += (l < lane && pl == p) ? 1 : 0;
+            }
+            if (p >= 0) klist[R0 + off[p] + rank] = r0 + u;
+            __syncthreads();
+            if (p >= 0) atomicAdd(&off[p], 1);
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rap_values(int64_t nnz, int bb, const int *__restrict__ kptr,
+                                                   const int *__restrict__ klist, const double *__restrict__ RA,
+                                                   double *__restrict__ K) {
+    const int64_t total = nnz * bb;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t t = g / bb;
+        const int e = static_cast<int>(g - t * bb);
+        double s = 0.0;
+        for (int k = kptr[t]; k < kptr[t + 1]; ++k) s = s + RA[static_cast<int64_t>(klist[k]) * bb + e];
+        K[g] = s;
+    }
+}
+
+// Drop filter: keep the diagonal and blocks with size > drop * size(diagonal).
+__global__ __launch_bounds__(256) void k_drop_mark(const int *__restrict__ krp, const int *__restrict__ kcol,
+                                                  const double *__restrict__ knorm, int m, double drop,
+                                                  uint8_t *__restrict__ keep, int *__restrict__ kept) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double dn = 0.0;
+    for (int t = krp[i]; t < krp[i + 1]; ++t)
+        if (kcol[t] == i) dn = knorm[t];
+    const double thr = drop * dn;
+    int c = 0;
+    for (int t = krp[i]; t < krp[i + 1]; ++t) {
+        const bool k = (kcol[t] == i) || (knorm[t] > thr);
+        keep[t] = k ? 1 : 0;
+        c += k ? 1 : 0;
+    }
+    kept[i] = c;
+}
+
+__global__ void k_set_int(int *__restrict__ p, const int *__restrict__ v) { *p = *v; }
+
+}  // namespace
+
+#define NAIR_BS_DISPATCH(bs, KERNEL, ...)            \
+    switch (bs) {                                    \
+        case 2: KERNEL<2> __VA_ARGS__; break;        \
+        case 3: KERNEL<3> __VA_ARGS__; break;        \
+        case 4: KERNEL<4> __VA_ARGS__; break;        \
+        case 6: KERNEL<6> __VA_ARGS__; break;        \
+        case 9: KERNEL<9> __VA_ARGS__; break;        \
+        case 10: KERNEL<10> __VA_ARGS__; break;      \
+        case 16: KERNEL<16> __VA_ARGS__; break;      \
+        case 25: KERNEL<25> __VA_ARGS__; break;      \
+        default: KERNEL<0> __VA_ARGS__; break;       \
+    }
+
 void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipStream_t s) {
     const int m = X.nb;
     const int bs = X.bs;
@@ -461,7 +602,7 @@ void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipSt
         return;
     }
     const int small_cap = kHashSmall / 2, large_cap = kHashLarge / 2;
-    DBuf<int> ub(m), cnt(m), big_list(m), flags(2);
+    DBuf<int> ub(m), cnt(m), big_list(m), flags(2), prow(static_cast<size_t>(m) + 1);
     NAIR_HIP(hipMemsetAsync(flags.get(), 0, sizeof(int) * 2, s));
     int *big_count = flags.get(), *too_dense = flags.get() + 1;
     k_row_upper_bound<<<grid_for(m, 256), 256, 0, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(), m,
@@ -471,38 +612,49 @@ void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipSt
     const size_t lds_large = sizeof(int) * (kHashLarge + kHashLarge / 2);
     k_symbolic_small<<<gs, 256, 0, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(), Y.colidx.get(), m,
                                         ub.get(), small_cap, 0, cnt.get(), nullptr, nullptr);
-    k_symbolic_large<<<256, 256, lds_large, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(),
-                                                 Y.colidx.get(), big_list.get(), big_count, large_cap, 0, cnt.get(),
-                                                 nullptr, nullptr, ub.get());
+    {
+        TimerScope ts(TK_SPGEMM_SYM, g_timer_level, s);
+        k_symbolic_large<<<256, 256, lds_large, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(),
+                                                     Y.colidx.get(), big_list.get(), big_count, large_cap, 0,
+                                                     cnt.get(), nullptr, nullptr, ub.get());
+    }
     NAIR_HIP(hipGetLastError());
     scan_exclusive(cnt.get(), C.rowptr.get(), m, s);
-    int hflags[2];
-    read_ints(flags.get(), hflags, 2, s);
+    scan_exclusive(ub.get(), prow.get(), m, s);
+    int hflags[2] = {0, 0}, nnz = 0, npairs = 0;
+    NAIR_HIP(hipMemcpyAsync(hflags, flags.get(), sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+    NAIR_HIP(hipMemcpyAsync(&nnz, C.rowptr.get() + m, sizeof(int), hipMemcpyDeviceToHost, s));
+    NAIR_HIP(hipMemcpyAsync(&npairs, prow.get() + m, sizeof(int), hipMemcpyDeviceToHost, s));
+    NAIR_HIP(hipStreamSynchronize(s));
     if (hflags[1] > 0)
         fail(NAIR_ENOMEM, "sparse product row has " + std::to_string(hflags[1]) + " candidate blocks (limit " +
                               std::to_string(large_cap) + ")");
-    const int nnz = read_int(C.rowptr.get() + m, s);
     C.nnzb = nnz;
     C.colidx.alloc(nnz);
     C.vals.alloc(static_cast<size_t>(nnz) * bs * bs);
+    if (nnz == 0) return;
+    DBuf<int> pairptr(static_cast<size_t>(nnz) + 1);
+    DBuf<int2> pairs(npairs);
     k_symbolic_small<<<gs, 256, 0, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(), Y.colidx.get(), m,
                                         ub.get(), small_cap, 1, nullptr, C.rowptr.get(), C.colidx.get());
     if (hflags[0] > 0)
         k_symbolic_large<<<256, 256, lds_large, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(),
                                                      Y.colidx.get(), big_list.get(), big_count, large_cap, 1, nullptr,
                                                      C.rowptr.get(), C.colidx.get(), ub.get());
+    k_pairs_small<<<cap_grid(m), 64, 0, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(), Y.colidx.get(), m,
+                                             ub.get(), small_cap, C.rowptr.get(), C.colidx.get(), prow.get(),
+                                             pairptr.get(), pairs.get());
+    if (hflags[0] > 0)
+        k_pairs_large<<<256, 256, 0, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(), Y.colidx.get(),
+                                          big_list.get(), big_count, C.rowptr.get(), C.colidx.get(), prow.get(),
+                                          pairptr.get(), pairs.get());
+    k_set_int<<<1, 1, 0, s>>>(pairptr.get() + nnz, prow.get() + m);
     NAIR_HIP(hipGetLastError());
-    if (nnz == 0) return;
-    const int bb = bs * bs;
-    int tile_blocks = kAccBytes / (8 * bb);
-    if (tile_blocks < 1) tile_blocks = 1;
-    const size_t lds = sizeof(double) * (static_cast<size_t>(tile_blocks) * bb + bb) +
-                       sizeof(int) * (kOutColsLds + kPosLds);
+    const int64_t total = static_cast<int64_t>(nnz) * bs;
+    const unsigned grid = cap_grid((total + 255) / 256);
     TimerScope ts(TK_SPGEMM_NUM, g_timer_level, s);
-    k_spgemm_numeric<<<cap_grid(m), kNumThreads, lds, s>>>(X.rowptr.get(), X.colidx.get(), X.vals.get(), xdiag,
-                                                          Y.rowptr.get(), Y.colidx.get(), Y.vals.get(), m,
-                                                          C.rowptr.get(), C.colidx.get(), C.vals.get(), bs,
-                                                          tile_blocks);
+    NAIR_BS_DISPATCH(bs, k_spgemm_pairs, <<<grid, 256, 0, s>>>(nnz, bs, pairptr.get(), pairs.get(), X.vals.get(),
+                                                               Y.vals.get(), C.vals.get()));
     NAIR_HIP(hipGetLastError());
 }
 
@@ -536,30 +688,41 @@ void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevB
     const int m = RA.nb;
     const int bs = RA.bs;
     const int bb = bs * bs;
-    DBuf<int> cnt(m), krp(static_cast<size_t>(m) + 1), flags(1);
+    DBuf<int> cnt(m), ccnt(m), krp(static_cast<size_t>(m) + 1), crow(static_cast<size_t>(m) + 1), flags(1);
     NAIR_HIP(hipMemsetAsync(flags.get(), 0, sizeof(int), s));
     const unsigned gs = cap_grid((m + 3) / 4);
     k_rap_symbolic<<<gs, 256, 0, s>>>(RA.rowptr.get(), RA.colidx.get(), pmap, m, 0, cnt.get(), nullptr, nullptr,
                                       flags.get());
+    k_rap_count_contrib<<<grid_for(m, 256), 256, 0, s>>>(RA.rowptr.get(), RA.colidx.get(), pmap, m, ccnt.get());
     NAIR_HIP(hipGetLastError());
     scan_exclusive(cnt.get(), krp.get(), m, s);
-    const int too_dense = read_int(flags.get(), s);
+    scan_exclusive(ccnt.get(), crow.get(), m, s);
+    int too_dense = 0, nnz = 0, ncontrib = 0;
+    NAIR_HIP(hipMemcpyAsync(&too_dense, flags.get(), sizeof(int), hipMemcpyDeviceToHost, s));
+    NAIR_HIP(hipMemcpyAsync(&nnz, krp.get() + m, sizeof(int), hipMemcpyDeviceToHost, s));
+    NAIR_HIP(hipMemcpyAsync(&ncontrib, crow.get() + m, sizeof(int), hipMemcpyDeviceToHost, s));
+    NAIR_HIP(hipStreamSynchronize(s));
     if (too_dense > 0)
         fail(NAIR_ENOMEM, "Galerkin row has " + std::to_string(too_dense) + " blocks (limit " +
                               std::to_string(kHashSmall / 2) + ")");
-    const int nnz = read_int(krp.get() + m, s);
-    DBuf<int> kcol(nnz);
-    DBuf<double> kval(static_cast<size_t>(nnz) * bb);
+    DBuf<int> kcol(nnz), kptr(static_cast<size_t>(nnz) + 1), klist(ncontrib);
+    DBuf<double> kval(static_cast<size_t>(nnz) * bb), knorm(nnz);
     DBuf<uint8_t> keep(nnz);
     DBuf<int> kept(m);
     k_rap_symbolic<<<gs, 256, 0, s>>>(RA.rowptr.get(), RA.colidx.get(), pmap, m, 1, nullptr, krp.get(), kcol.get(),
                                       flags.get());
-    {
+    k_rap_contrib<<<cap_grid(m), 64, 0, s>>>(RA.rowptr.get(), RA.colidx.get(), pmap, m, krp.get(), kcol.get(),
+                                             crow.get(), kptr.get(), klist.get());
+    k_set_int<<<1, 1, 0, s>>>(kptr.get() + nnz, crow.get() + m);
+    NAIR_HIP(hipGetLastError());
+    if (nnz > 0) {
         TimerScope ts(TK_RAP, g_timer_level, s);
-        k_rap_numeric<<<cap_grid(m), kNumThreads, 0, s>>>(RA.rowptr.get(), RA.colidx.get(), RA.vals.get(), pmap, m,
-                                                          krp.get(), kcol.get(), kval.get(), bs, drop, keep.get(),
-                                                          kept.get());
+        const int64_t total = static_cast<int64_t>(nnz) * bb;
+        k_rap_values<<<cap_grid((total + 255) / 256), 256, 0, s>>>(nnz, bb, kptr.get(), klist.get(), RA.vals.get(),
+                                                                  kval.get());
     }
+    launch_block_maxabs(kval.get(), nnz, bs, knorm.get(), s);
+    k_drop_mark<<<grid_for(m, 256), 256, 0, s>>>(krp.get(), kcol.get(), knorm.get(), m, drop, keep.get(), kept.get());
     NAIR_HIP(hipGetLastError());
     K.nb = nc;
     K.ncols = nc;

@@ -136,7 +136,7 @@ class Params:
     drop: float = 1e-3
     relax: int = 0
     max_levels: int = 30
-    max_coarse_dofs: int = 512
+    max_coarse_dofs: int = 128
     seed: int = 0
     cf_override: Optional[np.ndarray] = None
 

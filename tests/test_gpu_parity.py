@@ -185,6 +185,11 @@ def test_edge_cases():
     G, O = build_pair(S.nb, S.bs, S.rowptr, S.colidx, S.vals, max_coarse_dofs=1000)
     compare_hierarchies(G, O)
     check_solve(G, O, S.rhs)
+    # one level larger than the in-LDS dense inverse (576 unknowns: global-memory path)
+    S = small_dg(8, 2)
+    G, O = build_pair(S.nb, S.bs, S.rowptr, S.colidx, S.vals, max_coarse_dofs=600)
+    compare_hierarchies(G, O)
+    check_solve(G, O, S.rhs)
     # a single block
     va = np.array([[[4.0, 1.0], [0.5, 3.0]]])
     G, O = build_pair(1, 2, np.array([0, 1]), np.array([0]), va, max_coarse_dofs=0)
