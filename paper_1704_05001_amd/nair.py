@@ -262,8 +262,9 @@ class Hierarchy:
     def num_levels(self):
         return self.info()["levels"]
 
-    def level(self, l: int) -> dict:
-        """Copies of level l's device arrays (torch tensors on the device)."""
+    def level(self, l: int, fields=None) -> dict:
+        """Copies of level l's device arrays (torch tensors on the device);
+        `fields` (names) restricts which arrays are copied."""
         import torch
         v = _LevelView()
         st = lib().nair_get_level(self._h, l, C.byref(v))
@@ -273,26 +274,31 @@ class Hierarchy:
         dev = self.device
         nb, bs, nnzb = v.nb, v.bs, v.nnzb
         bb = bs * bs
-        out = dict(nb=nb, bs=bs, nnzb=nnzb, coarsest=bool(v.coarsest), nc=v.nc, pmis_rounds=v.pmis_rounds,
-                   rowptr=_dcopy(v.rowptr, torch.int32, nb + 1, dev),
-                   colidx=_dcopy(v.colidx, torch.int32, nnzb, dev),
-                   vals=_dcopy(v.vals, torch.float64, nnzb * bb, dev).view(nnzb, bs, bs))
+        want = (lambda k: True) if fields is None else (lambda k: k in fields)
+        out = dict(nb=nb, bs=bs, nnzb=nnzb, coarsest=bool(v.coarsest), nc=v.nc, pmis_rounds=v.pmis_rounds)
+        spec = [("rowptr", v.rowptr, torch.int32, nb + 1, None),
+                ("colidx", v.colidx, torch.int32, nnzb, None),
+                ("vals", v.vals, torch.float64, nnzb * bb, (nnzb, bs, bs))]
         if v.dinv:
-            out.update(dinv=_dcopy(v.dinv, torch.float64, nb * bb, dev).view(nb, bs, bs),
-                       bnorm=_dcopy(v.bnorm, torch.float64, nnzb, dev),
-                       mask=_dcopy(v.mask, torch.uint8, nnzb, dev),
-                       lam=_dcopy(v.lam, torch.int32, nb, dev),
-                       cf=_dcopy(v.cf, torch.int8, nb, dev),
-                       cidx=_dcopy(v.cidx, torch.int32, nb, dev),
-                       dround=_dcopy(v.dround, torch.int32, nb, dev))
+            spec += [("dinv", v.dinv, torch.float64, nb * bb, (nb, bs, bs)),
+                     ("bnorm", v.bnorm, torch.float64, nnzb, None),
+                     ("mask", v.mask, torch.uint8, nnzb, None),
+                     ("lam", v.lam, torch.int32, nb, None),
+                     ("cf", v.cf, torch.int8, nb, None),
+                     ("cidx", v.cidx, torch.int32, nb, None),
+                     ("dround", v.dround, torch.int32, nb, None)]
         if v.pmap:
-            out.update(pmap=_dcopy(v.pmap, torch.int32, nb, dev),
-                       z_rowptr=_dcopy(v.z_rowptr, torch.int32, v.nc + 1, dev),
-                       z_colidx=_dcopy(v.z_colidx, torch.int32, v.z_nnzb, dev),
-                       z_vals=_dcopy(v.z_vals, torch.float64, v.z_nnzb * bb, dev).view(v.z_nnzb, bs, bs))
+            spec += [("pmap", v.pmap, torch.int32, nb, None),
+                     ("z_rowptr", v.z_rowptr, torch.int32, v.nc + 1, None),
+                     ("z_colidx", v.z_colidx, torch.int32, v.z_nnzb, None),
+                     ("z_vals", v.z_vals, torch.float64, v.z_nnzb * bb, (v.z_nnzb, bs, bs))]
         if v.dense_inv:
             n = v.dense_n
-            out.update(dense_inv=_dcopy(v.dense_inv, torch.float64, n * n, dev).view(n, n))
+            spec += [("dense_inv", v.dense_inv, torch.float64, n * n, (n, n))]
+        for name, ptr, dt, cnt, shape in spec:
+            if want(name):
+                t = _dcopy(ptr, dt, cnt, dev)
+                out[name] = t.view(*shape) if shape else t
         torch.cuda.synchronize(self.device)
         return out
 
