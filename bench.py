@@ -75,6 +75,7 @@ def main(argv=None):
     ap.add_argument("--roofline-kernel", default="relax")
     ap.add_argument("--roofline-level", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-hierarchy leg")
     ap.add_argument("--cpu-sample", default="full", help="'full' or a mesh size N for the oracle sample")
     args = ap.parse_args(argv)
 
@@ -111,14 +112,14 @@ def main(argv=None):
     params = P.Params(degree=degree)
     stream = torch.cuda.current_stream()
 
-    def step(record):
+    def step(record, prm=params, xo=x, yo=y):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record(stream)
-        H = P.Hierarchy(rp, ci, va, S.bs, params)
+        H = P.Hierarchy(rp, ci, va, S.bs, prm)
         ev[1].record(stream)
-        _, r = H.solve(b, x=x, rtol=args.rtol)
+        _, r = H.solve(b, x=xo, rtol=args.rtol)
         ev[2].record(stream)
-        _, rT = H.solve_T(g, y=y, rtol=args.rtol)
+        _, rT = H.solve_T(g, y=yo, rtol=args.rtol)
         ev[3].record(stream)
         if r.status != "OK" or rT.status != "OK":
             raise RuntimeError(f"solve status {r.status} / {rT.status}")
@@ -186,6 +187,33 @@ def main(argv=None):
         "roofline": roof,
     }
 
+    if not args.no_fp32:
+        # the same steps with the FP32-stored hierarchy (FP64 setup, refinement and residuals)
+        p32 = P.Params(degree=degree, precision="fp32")
+        x32, y32 = torch.empty_like(b), torch.empty_like(g)
+        for _ in range(max(1, args.warmup)):
+            step(None, p32, x32, y32).close()
+        recs32 = []
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(recs32, p32, x32, y32).close()
+        torch.cuda.synchronize()
+        f1 = time.perf_counter()
+        s32 = np.mean([e[0].elapsed_time(e[1]) for e, _, _ in recs32])
+        v32 = np.mean([e[1].elapsed_time(e[2]) for e, _, _ in recs32])
+        t32 = np.mean([e[2].elapsed_time(e[3]) for e, _, _ in recs32])
+        err_x = float((x32 - x).abs().max() / x.abs().max())
+        err_y = float((y32 - y).abs().max() / y.abs().max())
+        out["fp32_hier"] = {"value": round(S.n / ((s32 + v32) * 1e-3), 1), "unit": "DOFs/s",
+                            "ms_per_step": round((f1 - f0) * 1e3 / args.steps, 3),
+                            "setup_ms": round(float(s32), 3), "solve_ms": round(float(v32), 3),
+                            "solve_T_ms": round(float(t32), 3), "iters": recs32[-1][1].iters,
+                            "iters_T": recs32[-1][2].iters, "relres": recs32[-1][1].relres,
+                            "max_rel_diff_x_vs_fp64": err_x, "max_rel_diff_y_vs_fp64": err_y,
+                            "speedup_vs_fp64": round((setup_ms + solve_ms) / (s32 + v32), 3)}
+        log(f"fp32 hierarchy: {out['fp32_hier']['value']:.0f} DOFs/s, {out['fp32_hier']['iters']} iterations")
+
     if not args.no_cpu_baseline:
         import oracle
         if args.cpu_sample == "full":
@@ -208,6 +236,9 @@ def main(argv=None):
             xg = x.cpu().numpy()
             out["cpu_baseline"]["max_rel_diff_x"] = float(np.abs(xg - xo).max() / np.abs(xo).max())
             out["cpu_baseline"]["same_iters"] = bool(len(ho) == iters)
+            if "fp32_hier" in out:
+                out["fp32_hier"]["max_rel_err_x_vs_fp64_oracle"] = float(
+                    np.abs(x32.cpu().numpy() - xo).max() / np.abs(xo).max())
     print(json.dumps(out), flush=True)
     return 0
 

@@ -59,6 +59,10 @@ typedef struct {
     int32_t max_coarse_dofs;  /* a level with nb*bs <= this is solved densely; default 128 */
     uint64_t seed;            /* seed of the splitting's tie-break hash, default 0 */
     const int8_t *cf_override_host; /* optional, host, [nb] level-0 splitting (1 = C, 0 = F) */
+    int32_t precision;        /* 0: FP64 cycle; 1: FP32-stored hierarchy (operators, Z and cycle
+                                 vectors in float; FP64 block inverses, accumulation, outer
+                                 residual and update: FP64 iterative refinement).  The setup and
+                                 its decisions are FP64 either way. */
 } nair_params;
 
 typedef struct {
@@ -93,7 +97,7 @@ typedef struct {
 } nair_level_view;
 
 /* Fill *p with the defaults (degree 1, theta 0.25, phi 0.025, drop 1e-3, F
- * relaxation, 30 levels, 128 dense DOFs, seed 0).  Host only. */
+ * relaxation, 30 levels, 128 dense DOFs, seed 0, FP64 cycle).  Host only. */
 nair_status nair_default_params(nair_params *p);
 
 /*

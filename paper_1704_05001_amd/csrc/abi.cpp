@@ -68,6 +68,7 @@ nair_status nair_default_params(nair_params *p) {
     p->max_coarse_dofs = 128;
     p->seed = 0;
     p->cf_override_host = nullptr;
+    p->precision = 0;
     return NAIR_OK;
 }
 
@@ -84,6 +85,7 @@ nair_status nair_setup(int32_t nb, int32_t bs, const int32_t *rowptr, const int3
     if (!unit_interval(p->theta) || !unit_interval(p->phi) || !unit_interval(p->drop))
         return bad(nullptr, "theta, phi and drop must lie in [0, 1)");
     if (p->relax != 0 && p->relax != 1) return bad(nullptr, "relax must be 0 (F) or 1 (FC)");
+    if (p->precision != 0 && p->precision != 1) return bad(nullptr, "precision must be 0 (FP64) or 1 (FP32 hierarchy)");
     if (p->max_levels < 1 || p->max_levels > nair::kMaxLevels) return bad(nullptr, "max_levels must be in [1, 64]");
     if (p->max_coarse_dofs < 0 || p->max_coarse_dofs > nair::kStallDenseDofs)
         return bad(nullptr, "max_coarse_dofs must be in [0, 4096]");

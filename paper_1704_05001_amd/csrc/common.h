@@ -159,31 +159,59 @@ void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s);
 void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevBSR &K, hipStream_t s);
 
 // ------------------------------------------------------------------ dense
-// Inverse of the dense operator assembled from a BSR; returns false if singular.
+// Inverse of the dense operator assembled from a BSR (and its transpose);
+// returns false if singular.
 bool dense_inverse_from_bsr(const DevBSR &A, double *inv, double *invT, hipStream_t s);
-void launch_dense_matvec(const double *M, const double *x, double *y, int n, hipStream_t s);
 
 // -------------------------------------------------------------- transpose
 void bsr_transpose(const DevBSR &A, DevBSR &AT, hipStream_t s);   // blocks transposed too
 void pmap_transpose(const int *pmap, int nb, int nc, DBuf<int> &ptptr, DBuf<int> &ptidx, hipStream_t s);
 
 // ------------------------------------------------------------------ cycle
-void launch_residual(const DevBSR &A, const double *b, const double *x, double *r, double *partials,
-                     int npart, hipStream_t s);
-int residual_partials_count(const DevBSR &A);
-void launch_sumsq(const double *v, int64_t n, double *partials, int npart, hipStream_t s);
+// Read-only view of a BSR matrix with values of type MT (double, or float for
+// the FP32-stored hierarchy).
+template <typename MT>
+struct MatView {
+    int nb = 0, ncols = 0, bs = 0;
+    int64_t nnzb = 0;
+    const int *rowptr = nullptr, *colidx = nullptr;
+    const MT *vals = nullptr;
+};
+inline MatView<double> view(const DevBSR &A) {
+    return MatView<double>{A.nb, A.ncols, A.bs, A.nnzb, A.rowptr.get(), A.colidx.get(), A.vals.get()};
+}
+inline MatView<float> view(const DevBSR &A, const float *vals32) {
+    return MatView<float>{A.nb, A.ncols, A.bs, A.nnzb, A.rowptr.get(), A.colidx.get(), vals32};
+}
+
+template <typename MT>
+int residual_partials_count(const MatView<MT> &A);
+// r = b - A x (+ squared-norm partials per workgroup if partials, + float copy if r_lo)
+template <typename MT, typename VT>
+void launch_residual(const MatView<MT> &A, const VT *b, const VT *x, VT *r, double *partials, float *r_lo,
+                     hipStream_t s);
+void launch_sumsq(const double *v, int64_t n, double *partials, hipStream_t s);
 int sumsq_partials_count(int64_t n);
 void launch_reduce_partials(const double *partials, int npart, double *out, hipStream_t s);
 // Jacobi sweep over `list` rows (list == nullptr: all rows; then rows with cf != only_cf are copied)
-void launch_relax(const DevBSR &A, const double *dinv, bool dinv_trans, const double *r, const double *ein,
-                  double *eout, const int *list, int nlist, const int8_t *cf, int only_cf, hipStream_t s);
-void launch_restrict(const DevBSR &Z, const double *r, const int *cpts, double *rc, hipStream_t s);
-void launch_interp(const int *pmap, const double *ec, double *e0, double *e1, int nb, int bs, hipStream_t s);
-void launch_restrict_T(const int *ptptr, const int *ptidx, const double *s, double *sc, int nc, int bs,
-                       hipStream_t st);
-void launch_interp_T(const DevBSR &ZT, const int *cidx, const double *yc, double *y, hipStream_t s);
-void launch_init_T(const double *dinv, const double *g, const int8_t *cf, int fc, double *y0, double *y1,
-                   int nb, int bs, hipStream_t s);
-void launch_axpy(double *x, const double *e, int64_t n, hipStream_t s);
+template <typename MT, typename VT>
+void launch_relax(const MatView<MT> &A, const double *dinv, bool dinv_trans, const VT *r, const VT *ein, VT *eout,
+                  const int *list, int nlist, const int8_t *cf, int only_cf, hipStream_t s);
+template <typename MT, typename VT>
+void launch_restrict(const MatView<MT> &Z, const VT *r, const int *cpts, VT *rc, hipStream_t s);
+template <typename VT>
+void launch_interp(const int *pmap, const VT *ec, VT *e0, VT *e1, int nb, int bs, hipStream_t s);
+template <typename VT>
+void launch_restrict_T(const int *ptptr, const int *ptidx, const VT *s, VT *sc, int nc, int bs, hipStream_t st);
+template <typename MT, typename VT>
+void launch_interp_T(const MatView<MT> &ZT, const int *cidx, const VT *yc, VT *y, hipStream_t s);
+template <typename VT>
+void launch_init_T(const double *dinv, const VT *g, const int8_t *cf, int fc, VT *y0, VT *y1, int nb, int bs,
+                   hipStream_t s);
+template <typename VT>
+void launch_axpy(double *x, const VT *e, int64_t n, hipStream_t s);
+template <typename VT>
+void launch_dense_matvec(const double *M, const VT *x, VT *y, int n, hipStream_t s);
+void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s);
 
 }  // namespace nair

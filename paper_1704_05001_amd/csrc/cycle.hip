@@ -10,6 +10,10 @@
 // waste no lanes and long rows (coarse levels) are not serial.  The block size
 // is a template parameter for the common sizes, so a block row's loads issue
 // together; other sizes use the runtime-bs instance (bs <= 32).
+//
+// Precision: matrices (MT) and cycle vectors (VT) are double, or float for the
+// FP32-stored hierarchy; accumulation and the block-diagonal inverses are
+// always double.
 #include "common.h"
 
 namespace nair {
@@ -27,24 +31,24 @@ struct Bs<0> {
 };
 
 // sum over blocks t = lo+g, lo+g+G, ... < hi of (block t row a) . x[col t]
-template <int BS>
-__device__ inline double row_part(const int *__restrict__ colidx, const double *__restrict__ vals, int lo, int hi,
-                                  int g, int G, int a, int bs_rt, const double *__restrict__ x) {
+template <int BS, typename MT, typename VT>
+__device__ inline double row_part(const int *__restrict__ colidx, const MT *__restrict__ vals, int lo, int hi, int g,
+                                  int G, int a, int bs_rt, const VT *__restrict__ x) {
     const int bs = Bs<BS>::get(bs_rt);
     const int64_t bb = static_cast<int64_t>(bs) * bs;
     double acc0 = 0.0, acc1 = 0.0;
     for (int t = lo + g; t < hi; t += G) {
-        const double *blk = vals + t * bb + a * bs;
-        const double *xj = x + static_cast<int64_t>(colidx[t]) * bs;
+        const MT *blk = vals + t * bb + a * bs;
+        const VT *xj = x + static_cast<int64_t>(colidx[t]) * bs;
         if constexpr (BS > 0) {
 #pragma unroll
             for (int c = 0; c < BS; c += 2) {
-                acc0 += blk[c] * xj[c];
-                if (c + 1 < BS) acc1 += blk[c + 1] * xj[c + 1];
+                acc0 += static_cast<double>(blk[c]) * static_cast<double>(xj[c]);
+                if (c + 1 < BS) acc1 += static_cast<double>(blk[c + 1]) * static_cast<double>(xj[c + 1]);
             }
         } else {
 #pragma unroll 4
-            for (int c = 0; c < bs; ++c) acc0 += blk[c] * xj[c];
+            for (int c = 0; c < bs; ++c) acc0 += static_cast<double>(blk[c]) * static_cast<double>(xj[c]);
         }
     }
     return acc0 + acc1;
@@ -90,12 +94,14 @@ __device__ inline double block_reduce_sum(double v, double *lds) {
     return s;   // valid in thread 0
 }
 
-// r = b - A x; partials[block] = sum of r^2 over the workgroup (if partials)
-template <int BS>
+// r = b - A x; partials[block] = sum of r^2 over the workgroup (if partials);
+// r_lo (if given) receives r rounded to float.
+template <int BS, typename MT, typename VT>
 __global__ __launch_bounds__(kThreads) void k_residual(const int *__restrict__ rowptr, const int *__restrict__ colidx,
-                                                      const double *__restrict__ vals, int nb, int bs_rt, int G,
-                                                      const double *__restrict__ b, const double *__restrict__ x,
-                                                      double *__restrict__ r, double *__restrict__ partials) {
+                                                      const MT *__restrict__ vals, int nb, int bs_rt, int G,
+                                                      const VT *__restrict__ b, const VT *__restrict__ x,
+                                                      VT *__restrict__ r, double *__restrict__ partials,
+                                                      float *__restrict__ r_lo) {
     __shared__ double part[kThreads];
     __shared__ double red[kThreads / 64];
     const int bs = Bs<BS>::get(bs_rt);
@@ -107,8 +113,9 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int *__restrict__ r
     double v = 0.0;
     if (act && L.g == 0) {
         const int64_t o = static_cast<int64_t>(I) * bs + L.a;
-        const double rv = b[o] - acc;
-        r[o] = rv;
+        const double rv = static_cast<double>(b[o]) - acc;
+        r[o] = static_cast<VT>(rv);
+        if (r_lo) r_lo[o] = static_cast<float>(rv);
         v = rv * rv;
     }
     if (partials) {
@@ -119,12 +126,12 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int *__restrict__ r
 
 // One Jacobi sweep over the listed rows (list == nullptr: rows with cf == only_cf;
 // the other rows copy e_in): e_out_I = e_in_I + D_I^{-1} (r_I - (A e_in)_I).
-template <int BS>
+template <int BS, typename MT, typename VT>
 __global__ __launch_bounds__(kThreads) void k_relax(const int *__restrict__ rowptr, const int *__restrict__ colidx,
-                                                   const double *__restrict__ vals, const double *__restrict__ dinv,
+                                                   const MT *__restrict__ vals, const double *__restrict__ dinv,
                                                    int dinv_trans, int nb, int bs_rt, int G,
-                                                   const double *__restrict__ r, const double *__restrict__ ein,
-                                                   double *__restrict__ eout, const int *__restrict__ list, int nlist,
+                                                   const VT *__restrict__ r, const VT *__restrict__ ein,
+                                                   VT *__restrict__ eout, const int *__restrict__ list, int nlist,
                                                    const int8_t *__restrict__ cf, int only_cf) {
     __shared__ double part[kThreads];
     __shared__ double tb[kThreads];
@@ -138,7 +145,7 @@ __global__ __launch_bounds__(kThreads) void k_relax(const int *__restrict__ rowp
     double acc = upd ? row_part<BS>(colidx, vals, rowptr[I], rowptr[I + 1], L.g, G, L.a, bs, ein) : 0.0;
     acc = reduce_groups(acc, L, G, bs, part);
     const int64_t o = static_cast<int64_t>(I) * bs + L.a;
-    if (upd && L.g == 0) tb[L.lr * bs + L.a] = r[o] - acc;
+    if (upd && L.g == 0) tb[L.lr * bs + L.a] = static_cast<double>(r[o]) - acc;
     __syncthreads();
     if (I >= 0 && L.g == 0) {
         if (upd) {
@@ -160,7 +167,7 @@ __global__ __launch_bounds__(kThreads) void k_relax(const int *__restrict__ rowp
                     if (c + 1 < bs) d1 += D[L.a * bs + c + 1] * t[c + 1];
                 }
             }
-            eout[o] = ein[o] + (d0 + d1);
+            eout[o] = static_cast<VT>(static_cast<double>(ein[o]) + (d0 + d1));
         } else {
             eout[o] = ein[o];
         }
@@ -168,11 +175,11 @@ __global__ __launch_bounds__(kThreads) void k_relax(const int *__restrict__ rowp
 }
 
 // rc_i = r_{cpts[i]} + sum_t Z_it r_{col t}
-template <int BS>
+template <int BS, typename MT, typename VT>
 __global__ __launch_bounds__(kThreads) void k_restrict(const int *__restrict__ zrp, const int *__restrict__ zcol,
-                                                      const double *__restrict__ zval, int nc, int bs_rt, int G,
-                                                      const double *__restrict__ r, const int *__restrict__ cpts,
-                                                      double *__restrict__ rc) {
+                                                      const MT *__restrict__ zval, int nc, int bs_rt, int G,
+                                                      const VT *__restrict__ r, const int *__restrict__ cpts,
+                                                      VT *__restrict__ rc) {
     __shared__ double part[kThreads];
     const int bs = Bs<BS>::get(bs_rt);
     const Lane L = lane_of(G, bs);
@@ -181,15 +188,16 @@ __global__ __launch_bounds__(kThreads) void k_restrict(const int *__restrict__ z
     double acc = act ? row_part<BS>(zcol, zval, zrp[i], zrp[i + 1], L.g, G, L.a, bs, r) : 0.0;
     acc = reduce_groups(acc, L, G, bs, part);
     if (act && L.g == 0)
-        rc[static_cast<int64_t>(i) * bs + L.a] = r[static_cast<int64_t>(cpts[i]) * bs + L.a] + acc;
+        rc[static_cast<int64_t>(i) * bs + L.a] =
+            static_cast<VT>(static_cast<double>(r[static_cast<int64_t>(cpts[i]) * bs + L.a]) + acc);
 }
 
 // y_I += [I is C] yc_{cidx I} + sum_t (Z^T)_It yc_{col t}
-template <int BS>
+template <int BS, typename MT, typename VT>
 __global__ __launch_bounds__(kThreads) void k_interp_T(const int *__restrict__ ztrp, const int *__restrict__ ztcol,
-                                                      const double *__restrict__ ztval, int nb, int bs_rt, int G,
-                                                      const int *__restrict__ cidx, const double *__restrict__ yc,
-                                                      double *__restrict__ y) {
+                                                      const MT *__restrict__ ztval, int nb, int bs_rt, int G,
+                                                      const int *__restrict__ cidx, const VT *__restrict__ yc,
+                                                      VT *__restrict__ y) {
     __shared__ double part[kThreads];
     const int bs = Bs<BS>::get(bs_rt);
     const Lane L = lane_of(G, bs);
@@ -200,8 +208,8 @@ __global__ __launch_bounds__(kThreads) void k_interp_T(const int *__restrict__ z
     if (act && L.g == 0) {
         const int64_t o = static_cast<int64_t>(I) * bs + L.a;
         const int ci = cidx[I];
-        if (ci >= 0) acc += yc[static_cast<int64_t>(ci) * bs + L.a];
-        y[o] += acc;
+        if (ci >= 0) acc += static_cast<double>(yc[static_cast<int64_t>(ci) * bs + L.a]);
+        y[o] = static_cast<VT>(static_cast<double>(y[o]) + acc);
     }
 }
 
@@ -223,35 +231,38 @@ __global__ __launch_bounds__(1024) void k_reduce_partials(const double *__restri
     if (threadIdx.x == 0) *out = t;
 }
 
-__global__ __launch_bounds__(kThreads) void k_interp(const int *__restrict__ pmap, const double *__restrict__ ec,
-                                                    double *__restrict__ e0, double *__restrict__ e1, int nb, int bs) {
+template <typename VT>
+__global__ __launch_bounds__(kThreads) void k_interp(const int *__restrict__ pmap, const VT *__restrict__ ec,
+                                                    VT *__restrict__ e0, VT *__restrict__ e1, int nb, int bs) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
     if (g >= static_cast<int64_t>(nb) * bs) return;
     const int I = static_cast<int>(g / bs);
     const int a = static_cast<int>(g - static_cast<int64_t>(I) * bs);
     const int p = pmap[I];
-    const double v = (p >= 0) ? ec[static_cast<int64_t>(p) * bs + a] : 0.0;
+    const VT v = (p >= 0) ? ec[static_cast<int64_t>(p) * bs + a] : VT(0);
     e0[g] = v;
     e1[g] = v;
 }
 
 // sc_j = sum over fine blocks I with pmap(I) = j of s_I
+template <typename VT>
 __global__ __launch_bounds__(kThreads) void k_restrict_T(const int *__restrict__ ptptr, const int *__restrict__ ptidx,
-                                                        const double *__restrict__ s, double *__restrict__ sc, int nc,
+                                                        const VT *__restrict__ s, VT *__restrict__ sc, int nc,
                                                         int bs) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
     if (g >= static_cast<int64_t>(nc) * bs) return;
     const int j = static_cast<int>(g / bs);
     const int a = static_cast<int>(g - static_cast<int64_t>(j) * bs);
     double acc = 0.0;
-    for (int t = ptptr[j]; t < ptptr[j + 1]; ++t) acc += s[static_cast<int64_t>(ptidx[t]) * bs + a];
-    sc[g] = acc;
+    for (int t = ptptr[j]; t < ptptr[j + 1]; ++t) acc += static_cast<double>(s[static_cast<int64_t>(ptidx[t]) * bs + a]);
+    sc[g] = static_cast<VT>(acc);
 }
 
 // y0 = y1 = (FC ? [D_C^{-T} g_C ; 0] : 0)
-__global__ __launch_bounds__(kThreads) void k_init_T(const double *__restrict__ dinv, const double *__restrict__ g,
-                                                    const int8_t *__restrict__ cf, int fc, double *__restrict__ y0,
-                                                    double *__restrict__ y1, int nb, int bs) {
+template <typename VT>
+__global__ __launch_bounds__(kThreads) void k_init_T(const double *__restrict__ dinv, const VT *__restrict__ g,
+                                                    const int8_t *__restrict__ cf, int fc, VT *__restrict__ y0,
+                                                    VT *__restrict__ y1, int nb, int bs) {
     const int64_t gi = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
     if (gi >= static_cast<int64_t>(nb) * bs) return;
     const int I = static_cast<int>(gi / bs);
@@ -259,16 +270,38 @@ __global__ __launch_bounds__(kThreads) void k_init_T(const double *__restrict__ 
     double v = 0.0;
     if (fc && cf[I] == 1) {
         const double *D = dinv + static_cast<int64_t>(I) * bs * bs;
-        const double *gI = g + static_cast<int64_t>(I) * bs;
-        for (int c = 0; c < bs; ++c) v += D[c * bs + a] * gI[c];
+        const VT *gI = g + static_cast<int64_t>(I) * bs;
+        for (int c = 0; c < bs; ++c) v += D[c * bs + a] * static_cast<double>(gI[c]);
     }
-    y0[gi] = v;
-    y1[gi] = v;
+    y0[gi] = static_cast<VT>(v);
+    y1[gi] = static_cast<VT>(v);
 }
 
-__global__ __launch_bounds__(kThreads) void k_axpy(double *__restrict__ x, const double *__restrict__ e, int64_t n) {
+template <typename VT>
+__global__ __launch_bounds__(kThreads) void k_axpy(double *__restrict__ x, const VT *__restrict__ e, int64_t n) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-    if (g < n) x[g] += e[g];
+    if (g < n) x[g] += static_cast<double>(e[g]);
+}
+
+// y = M x with a double M: one wave per row.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_dense_mv(const double *__restrict__ M, const VT *__restrict__ x,
+                                                 VT *__restrict__ y, int n) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= n) return;
+    const double *m = M + static_cast<int64_t>(row) * n;
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64) s += m[j] * static_cast<double>(x[j]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) y[row] = static_cast<VT>(s);
+}
+
+__global__ __launch_bounds__(256) void k_to_float(const double *__restrict__ in, float *__restrict__ out, int64_t n) {
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        out[g] = static_cast<float>(in[g]);
 }
 
 // Lane groups per block row from the average row length (at most 256 lanes per row).
@@ -283,36 +316,36 @@ unsigned grid_rows(int64_t rows, int G, int bs) { return grid_for(rows, kThreads
 
 }  // namespace
 
-#define NAIR_BS_DISPATCH(bs, KERNEL, ...)            \
-    switch (bs) {                                    \
-        case 2: KERNEL<2> __VA_ARGS__; break;        \
-        case 3: KERNEL<3> __VA_ARGS__; break;        \
-        case 4: KERNEL<4> __VA_ARGS__; break;        \
-        case 6: KERNEL<6> __VA_ARGS__; break;        \
-        case 9: KERNEL<9> __VA_ARGS__; break;        \
-        case 10: KERNEL<10> __VA_ARGS__; break;      \
-        case 16: KERNEL<16> __VA_ARGS__; break;      \
-        case 25: KERNEL<25> __VA_ARGS__; break;      \
-        default: KERNEL<0> __VA_ARGS__; break;       \
+#define NAIR_BS_DISPATCH(bs, KERNEL, ...)                    \
+    switch (bs) {                                            \
+        case 2: KERNEL<2, MT, VT> __VA_ARGS__; break;        \
+        case 3: KERNEL<3, MT, VT> __VA_ARGS__; break;        \
+        case 4: KERNEL<4, MT, VT> __VA_ARGS__; break;        \
+        case 6: KERNEL<6, MT, VT> __VA_ARGS__; break;        \
+        case 9: KERNEL<9, MT, VT> __VA_ARGS__; break;        \
+        case 10: KERNEL<10, MT, VT> __VA_ARGS__; break;      \
+        case 16: KERNEL<16, MT, VT> __VA_ARGS__; break;      \
+        case 25: KERNEL<25, MT, VT> __VA_ARGS__; break;      \
+        default: KERNEL<0, MT, VT> __VA_ARGS__; break;       \
     }
 
-int residual_partials_count(const DevBSR &A) {
+template <typename MT>
+int residual_partials_count(const MatView<MT> &A) {
     const int G = groups_for(A.nnzb, A.nb, A.bs);
     return static_cast<int>(grid_rows(A.nb, G, A.bs));
 }
 
-void launch_residual(const DevBSR &A, const double *b, const double *x, double *r, double *partials, int npart,
+template <typename MT, typename VT>
+void launch_residual(const MatView<MT> &A, const VT *b, const VT *x, VT *r, double *partials, float *r_lo,
                      hipStream_t s) {
-    (void)npart;
     const int G = groups_for(A.nnzb, A.nb, A.bs);
     const unsigned grid = grid_rows(A.nb, G, A.bs);
-    NAIR_BS_DISPATCH(A.bs, k_residual, <<<grid, kThreads, 0, s>>>(A.rowptr.get(), A.colidx.get(), A.vals.get(),
-                                                                  A.nb, A.bs, G, b, x, r, partials));
+    NAIR_BS_DISPATCH(A.bs, k_residual, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, A.nb, A.bs, G, b, x, r,
+                                                                  partials, r_lo));
     NAIR_HIP(hipGetLastError());
 }
 
-void launch_sumsq(const double *v, int64_t n, double *partials, int npart, hipStream_t s) {
-    (void)npart;
+void launch_sumsq(const double *v, int64_t n, double *partials, hipStream_t s) {
     k_sumsq<<<grid_for(n, kThreads), kThreads, 0, s>>>(v, n, partials);
     NAIR_HIP(hipGetLastError());
 }
@@ -324,57 +357,95 @@ void launch_reduce_partials(const double *partials, int npart, double *out, hipS
     NAIR_HIP(hipGetLastError());
 }
 
-void launch_relax(const DevBSR &A, const double *dinv, bool dinv_trans, const double *r, const double *ein,
-                  double *eout, const int *list, int nlist, const int8_t *cf, int only_cf, hipStream_t s) {
+template <typename MT, typename VT>
+void launch_relax(const MatView<MT> &A, const double *dinv, bool dinv_trans, const VT *r, const VT *ein, VT *eout,
+                  const int *list, int nlist, const int8_t *cf, int only_cf, hipStream_t s) {
     const int N = list ? nlist : A.nb;
     if (N <= 0) return;
     const int G = groups_for(A.nnzb, A.nb, A.bs);
     const unsigned grid = grid_rows(N, G, A.bs);
-    NAIR_BS_DISPATCH(A.bs, k_relax, <<<grid, kThreads, 0, s>>>(A.rowptr.get(), A.colidx.get(), A.vals.get(), dinv,
-                                                               dinv_trans ? 1 : 0, A.nb, A.bs, G, r, ein, eout, list,
-                                                               nlist, cf, only_cf));
+    NAIR_BS_DISPATCH(A.bs, k_relax, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, dinv, dinv_trans ? 1 : 0,
+                                                               A.nb, A.bs, G, r, ein, eout, list, nlist, cf, only_cf));
     NAIR_HIP(hipGetLastError());
 }
 
-void launch_restrict(const DevBSR &Z, const double *r, const int *cpts, double *rc, hipStream_t s) {
+template <typename MT, typename VT>
+void launch_restrict(const MatView<MT> &Z, const VT *r, const int *cpts, VT *rc, hipStream_t s) {
     if (Z.nb <= 0) return;
     const int G = groups_for(Z.nnzb, Z.nb, Z.bs);
     const unsigned grid = grid_rows(Z.nb, G, Z.bs);
-    NAIR_BS_DISPATCH(Z.bs, k_restrict, <<<grid, kThreads, 0, s>>>(Z.rowptr.get(), Z.colidx.get(), Z.vals.get(), Z.nb,
-                                                                  Z.bs, G, r, cpts, rc));
+    NAIR_BS_DISPATCH(Z.bs, k_restrict, <<<grid, kThreads, 0, s>>>(Z.rowptr, Z.colidx, Z.vals, Z.nb, Z.bs, G, r, cpts,
+                                                                  rc));
     NAIR_HIP(hipGetLastError());
 }
 
-void launch_interp(const int *pmap, const double *ec, double *e0, double *e1, int nb, int bs, hipStream_t s) {
-    k_interp<<<grid_for(static_cast<int64_t>(nb) * bs, kThreads), kThreads, 0, s>>>(pmap, ec, e0, e1, nb, bs);
+template <typename VT>
+void launch_interp(const int *pmap, const VT *ec, VT *e0, VT *e1, int nb, int bs, hipStream_t s) {
+    k_interp<VT><<<grid_for(static_cast<int64_t>(nb) * bs, kThreads), kThreads, 0, s>>>(pmap, ec, e0, e1, nb, bs);
     NAIR_HIP(hipGetLastError());
 }
 
-void launch_restrict_T(const int *ptptr, const int *ptidx, const double *sv, double *sc, int nc, int bs,
-                       hipStream_t st) {
+template <typename VT>
+void launch_restrict_T(const int *ptptr, const int *ptidx, const VT *sv, VT *sc, int nc, int bs, hipStream_t st) {
     if (nc <= 0) return;
-    k_restrict_T<<<grid_for(static_cast<int64_t>(nc) * bs, kThreads), kThreads, 0, st>>>(ptptr, ptidx, sv, sc, nc,
-                                                                                          bs);
+    k_restrict_T<VT><<<grid_for(static_cast<int64_t>(nc) * bs, kThreads), kThreads, 0, st>>>(ptptr, ptidx, sv, sc,
+                                                                                              nc, bs);
     NAIR_HIP(hipGetLastError());
 }
 
-void launch_interp_T(const DevBSR &ZT, const int *cidx, const double *yc, double *y, hipStream_t s) {
+template <typename MT, typename VT>
+void launch_interp_T(const MatView<MT> &ZT, const int *cidx, const VT *yc, VT *y, hipStream_t s) {
     const int G = groups_for(ZT.nnzb, ZT.nb, ZT.bs);
     const unsigned grid = grid_rows(ZT.nb, G, ZT.bs);
-    NAIR_BS_DISPATCH(ZT.bs, k_interp_T, <<<grid, kThreads, 0, s>>>(ZT.rowptr.get(), ZT.colidx.get(), ZT.vals.get(),
-                                                                   ZT.nb, ZT.bs, G, cidx, yc, y));
+    NAIR_BS_DISPATCH(ZT.bs, k_interp_T, <<<grid, kThreads, 0, s>>>(ZT.rowptr, ZT.colidx, ZT.vals, ZT.nb, ZT.bs, G,
+                                                                   cidx, yc, y));
     NAIR_HIP(hipGetLastError());
 }
 
-void launch_init_T(const double *dinv, const double *g, const int8_t *cf, int fc, double *y0, double *y1, int nb,
-                   int bs, hipStream_t s) {
-    k_init_T<<<grid_for(static_cast<int64_t>(nb) * bs, kThreads), kThreads, 0, s>>>(dinv, g, cf, fc, y0, y1, nb, bs);
+template <typename VT>
+void launch_init_T(const double *dinv, const VT *g, const int8_t *cf, int fc, VT *y0, VT *y1, int nb, int bs,
+                   hipStream_t s) {
+    k_init_T<VT><<<grid_for(static_cast<int64_t>(nb) * bs, kThreads), kThreads, 0, s>>>(dinv, g, cf, fc, y0, y1, nb,
+                                                                                         bs);
     NAIR_HIP(hipGetLastError());
 }
 
-void launch_axpy(double *x, const double *e, int64_t n, hipStream_t s) {
-    k_axpy<<<grid_for(n, kThreads), kThreads, 0, s>>>(x, e, n);
+template <typename VT>
+void launch_axpy(double *x, const VT *e, int64_t n, hipStream_t s) {
+    k_axpy<VT><<<grid_for(n, kThreads), kThreads, 0, s>>>(x, e, n);
     NAIR_HIP(hipGetLastError());
 }
+
+template <typename VT>
+void launch_dense_matvec(const double *M, const VT *x, VT *y, int n, hipStream_t s) {
+    k_dense_mv<VT><<<grid_for(n, 4), 256, 0, s>>>(M, x, y, n);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    const int64_t g = (n + 255) / 256;
+    k_to_float<<<static_cast<unsigned>(g > 1048576 ? 1048576 : g), 256, 0, s>>>(in, out, n);
+    NAIR_HIP(hipGetLastError());
+}
+
+// instantiations: the FP64 cycle and the FP32-stored cycle
+#define NAIR_CYCLE_INST(MT, VT)                                                                                      \
+    template int residual_partials_count<MT>(const MatView<MT> &);                                                   \
+    template void launch_residual<MT, VT>(const MatView<MT> &, const VT *, const VT *, VT *, double *, float *,     \
+                                          hipStream_t);                                                              \
+    template void launch_relax<MT, VT>(const MatView<MT> &, const double *, bool, const VT *, const VT *, VT *,      \
+                                       const int *, int, const int8_t *, int, hipStream_t);                          \
+    template void launch_restrict<MT, VT>(const MatView<MT> &, const VT *, const int *, VT *, hipStream_t);          \
+    template void launch_interp<VT>(const int *, const VT *, VT *, VT *, int, int, hipStream_t);                     \
+    template void launch_restrict_T<VT>(const int *, const int *, const VT *, VT *, int, int, hipStream_t);          \
+    template void launch_interp_T<MT, VT>(const MatView<MT> &, const int *, const VT *, VT *, hipStream_t);          \
+    template void launch_init_T<VT>(const double *, const VT *, const int8_t *, int, VT *, VT *, int, int,           \
+                                    hipStream_t);                                                                    \
+    template void launch_axpy<VT>(double *, const VT *, int64_t, hipStream_t);                                       \
+    template void launch_dense_matvec<VT>(const double *, const VT *, VT *, int, hipStream_t);
+
+NAIR_CYCLE_INST(double, double)
+NAIR_CYCLE_INST(float, float)
 
 }  // namespace nair

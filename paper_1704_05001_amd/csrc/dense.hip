@@ -189,20 +189,6 @@ __global__ __launch_bounds__(256) void k_transpose_dense(const double *__restric
     MT[static_cast<int64_t>(j) * n + i] = M[e];
 }
 
-// y = M x: one wave per row.
-__global__ __launch_bounds__(256) void k_dense_mv(const double *__restrict__ M, const double *__restrict__ x,
-                                                 double *__restrict__ y, int n) {
-    const int lane = threadIdx.x & 63;
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= n) return;
-    const double *m = M + static_cast<int64_t>(row) * n;
-    double s = 0.0;
-    for (int j = lane; j < n; j += 64) s += m[j] * x[j];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) y[row] = s;
-}
-
 }  // namespace
 
 bool dense_inverse_from_bsr(const DevBSR &A, double *inv, double *invT, hipStream_t s) {
@@ -239,11 +225,6 @@ bool dense_inverse_from_bsr(const DevBSR &A, double *inv, double *invT, hipStrea
     k_transpose_dense<<<grid_for(static_cast<int64_t>(n) * n, 256), 256, 0, s>>>(inv, invT, n);
     NAIR_HIP(hipGetLastError());
     return true;
-}
-
-void launch_dense_matvec(const double *M, const double *x, double *y, int n, hipStream_t s) {
-    k_dense_mv<<<grid_for(n, 4), 256, 0, s>>>(M, x, y, n);
-    NAIR_HIP(hipGetLastError());
 }
 
 }  // namespace nair

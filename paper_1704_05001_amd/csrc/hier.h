@@ -28,6 +28,10 @@ struct Level {
     DBuf<int> ptptr, ptidx;
     // cycle vectors
     DBuf<double> r, e0, e1, tmp;
+    // FP32-stored hierarchy (precision 1): operator, Z and transposes in float,
+    // and the cycle vectors
+    DBuf<float> vals32, z32, at32, zt32;
+    DBuf<float> r32, e0_32, e1_32, tmp32;
 };
 
 struct Hier {
@@ -47,6 +51,7 @@ nair_status run_solve(Hier &h, bool trans, const double *b, double *x, double rt
                       nair_result *res, hipStream_t s);
 void run_vcycle(Hier &h, bool trans, const double *r, double *e, hipStream_t s);
 void ensure_transposes(Hier &h, hipStream_t s);
+void make_fp32_copies(Hier &h, hipStream_t s);
 void complexity(Hier &h, double *oc, double *cc, hipStream_t s);
 
 // validation of the input pattern (device): sets *bad != 0 on error

@@ -241,7 +241,37 @@ void build_hierarchy(Hier &h, int nb, int bs, const int *rowptr, const int *coli
         rap_merge_drop(RA, L.pmap.get(), nc, p.drop, next->A, s);
         h.lv.push_back(std::move(next));
     }
+    if (p.precision == 1) make_fp32_copies(h, s);
     NAIR_HIP(hipStreamSynchronize(s));
+}
+
+// FP32 copies of what the cycle reads (operators and Z of the non-coarsest
+// levels, and their transposes once built), plus FP32 cycle vectors.
+void make_fp32_copies(Hier &h, hipStream_t s) {
+    for (auto &Lp : h.lv) {
+        Level &L = *Lp;
+        const size_t n = static_cast<size_t>(L.A.nb) * L.A.bs;
+        const int64_t bb = static_cast<int64_t>(L.A.bs) * L.A.bs;
+        if (!L.r32.get()) {
+            L.r32.alloc(n);
+            L.e0_32.alloc(n);
+            L.e1_32.alloc(n);
+            L.tmp32.alloc(n);
+        }
+        if (L.coarsest) continue;
+        if (!L.vals32.get()) {
+            L.vals32.alloc(static_cast<size_t>(L.A.nnzb * bb));
+            launch_to_float(L.A.vals.get(), L.vals32.get(), L.A.nnzb * bb, s);
+            L.z32.alloc(static_cast<size_t>(L.Z.nnzb * bb));
+            launch_to_float(L.Z.vals.get(), L.z32.get(), L.Z.nnzb * bb, s);
+        }
+        if (L.have_T && !L.at32.get()) {
+            L.at32.alloc(static_cast<size_t>(L.AT.nnzb * bb));
+            launch_to_float(L.AT.vals.get(), L.at32.get(), L.AT.nnzb * bb, s);
+            L.zt32.alloc(static_cast<size_t>(L.ZT.nnzb * bb));
+            launch_to_float(L.ZT.vals.get(), L.zt32.get(), L.ZT.nnzb * bb, s);
+        }
+    }
 }
 
 void ensure_transposes(Hier &h, hipStream_t s) {
@@ -255,6 +285,7 @@ void ensure_transposes(Hier &h, hipStream_t s) {
         }
         L.have_T = true;
     }
+    if (h.prm.precision == 1) make_fp32_copies(h, s);
     NAIR_HIP(hipStreamSynchronize(s));
 }
 

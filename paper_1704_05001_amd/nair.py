@@ -39,7 +39,7 @@ class _Params(C.Structure):
     _fields_ = [("degree", C.c_int32), ("theta", C.c_double), ("phi", C.c_double),
                 ("drop", C.c_double), ("relax", C.c_int32), ("max_levels", C.c_int32),
                 ("max_coarse_dofs", C.c_int32), ("seed", C.c_uint64),
-                ("cf_override_host", C.c_void_p)]
+                ("cf_override_host", C.c_void_p), ("precision", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -139,6 +139,7 @@ class Params:
     max_coarse_dofs: int = 128
     seed: int = 0
     cf_override: Optional[np.ndarray] = None
+    precision: str = "fp64"      # "fp64" or "fp32" (FP32-stored hierarchy, FP64 refinement)
 
 
 @dataclass
@@ -171,6 +172,9 @@ class Hierarchy:
         p.degree, p.theta, p.phi, p.drop = params.degree, params.theta, params.phi, params.drop
         p.relax, p.max_levels, p.max_coarse_dofs = params.relax, params.max_levels, params.max_coarse_dofs
         p.seed = params.seed
+        if params.precision not in ("fp64", "fp32"):
+            raise ValueError("precision must be 'fp64' or 'fp32'")
+        p.precision = 1 if params.precision == "fp32" else 0
         cf = None
         if params.cf_override is not None:
             cf = np.ascontiguousarray(params.cf_override, dtype=np.int8)

@@ -42,11 +42,11 @@ def to_dev(rp, ci, va):
             torch.from_numpy(np.ascontiguousarray(va, dtype=np.float64)).to(dev))
 
 
-def build_pair(nb, bs, rp, ci, va, **kw):
+def build_pair(nb, bs, rp, ci, va, gpu_kw=None, **kw):
     import paper_1704_05001_amd as P
     _need_gpu()
     d_rp, d_ci, d_va = to_dev(rp, ci, va)
-    G = P.Hierarchy(d_rp, d_ci, d_va, bs, P.Params(**kw))
+    G = P.Hierarchy(d_rp, d_ci, d_va, bs, P.Params(**kw, **(gpu_kw or {})))
     O = oracle.Hierarchy(nb, bs, rp, ci, va, oracle.Params(**kw))
     return G, O
 
