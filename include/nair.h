@@ -135,6 +135,16 @@ nair_status nair_solve_T(nair_hier h, const double *g, double *y, double rtol, i
 nair_status nair_vcycle(nair_hier h, const double *r, double *e, void *stream);
 nair_status nair_vcycle_T(nair_hier h, const double *g, double *y, void *stream);
 
+/*
+ * Gradient of a solve with respect to the matrix entries, on A's block pattern:
+ * for x = A^{-1} b and ybar = A^{-T} xbar (the adjoint solve, nair_solve_T),
+ * dL/dA_IJ = -ybar_I x_J^T for every stored block (I,J).  rowptr/colidx are the
+ * pattern (as for nair_setup); ybar and x are device vectors of nb*bs doubles;
+ * grad_vals (device, [nnzb][bs][bs]) is written.  Needs no handle.
+ */
+nair_status nair_grad_vals(int32_t nb, int32_t bs, const int32_t *rowptr, const int32_t *colidx,
+                           const double *ybar, const double *x, double *grad_vals, void *stream);
+
 /* Relative residual history of the last solve: buf (host) gets min(cap, n). */
 nair_status nair_history(nair_hier h, double *buf, int32_t cap, int32_t *n);
 

@@ -6,8 +6,8 @@ results section, equation "transport") on quadrilateral meshes, and the named
 workload configurations.  It contains none of the solver's arithmetic, and
 imports neither the oracle nor the HIP library.
 """
-from .dg_quad import dg_quad, DGSystem, topo_sort_blocks, gauss_lobatto_nodes
+from .dg_quad import dg_quad, DGSystem, topo_sort_blocks, gauss_lobatto_nodes, sigma_q_model
 from .configs import CONFIGS, make_config, config_names
 
-__all__ = ["dg_quad", "DGSystem", "topo_sort_blocks", "gauss_lobatto_nodes",
+__all__ = ["dg_quad", "DGSystem", "topo_sort_blocks", "gauss_lobatto_nodes", "sigma_q_model",
            "CONFIGS", "make_config", "config_names"]

@@ -172,7 +172,7 @@ def dg_quad(N: int, p: int, b: Union[tuple, FlowFn], sigma: Union[float, np.ndar
             jitter: float = 0.0, seed_perm: Optional[int] = 101, seed_q: int = 102,
             seed_jitter: int = 103, q_nodal: Optional[np.ndarray] = None,
             q_fn: Optional[FlowFn] = None, g_fn: Optional[FlowFn] = None,
-            check_acyclic: bool = True, chunk: int = 8192) -> DGSystem:
+            check_acyclic: bool = True, chunk: int = 8192, return_mass: bool = False) -> DGSystem:
     """Assemble the upwind DG-Q_p system on an N x N quad mesh of [0,1]^2.
 
     b         : constant (bx, by) or callable (x, y) -> (bx, by) on arrays.
@@ -182,6 +182,7 @@ def dg_quad(N: int, p: int, b: Union[tuple, FlowFn], sigma: Union[float, np.ndar
     q_nodal   : nodal source values [N*N, (p+1)^2] in cell order; default U[-1,1] from seed_q.
     q_fn      : source function; if given, rhs_i = int q phi_i (overrides q_nodal).
     g_fn      : inflow boundary data; default g = 0.
+    return_mass: also return the cell mass matrices (block order) in meta["mass"].
     """
     if N < 1:
         raise ValueError("N >= 1 required")
@@ -220,6 +221,7 @@ def dg_quad(N: int, p: int, b: Union[tuple, FlowFn], sigma: Union[float, np.ndar
 
     diag = np.empty((ncell, bs, bs))
     rhs_cell = np.zeros((ncell, bs))
+    mass_cell = np.empty((ncell, bs, bs)) if return_mass else None
 
     # ---- volume terms, chunked over cells
     for c0 in range(0, ncell, chunk):
@@ -248,8 +250,11 @@ def dg_quad(N: int, p: int, b: Union[tuple, FlowFn], sigma: Union[float, np.ndar
         G = (W2[None, :, None] * (c_xi[:, :, None] * Pxi[None] + c_et[:, :, None] * Peta[None]
                                   + sd[:, :, None] * Phi[None]))
         diag[c0:c1] = np.matmul(Phi.T[None], G)
-        if q_fn is None:
+        if q_fn is None or return_mass:
             M = np.matmul(Phi.T[None], (W2[None, :] * det)[:, :, None] * Phi[None])
+            if return_mass:
+                mass_cell[c0:c1] = M
+        if q_fn is None:
             rhs_cell[c0:c1] = np.einsum("cij,cj->ci", M, q_nodal[c0:c1])
         else:
             qv = np.broadcast_to(q_fn(px, py), px.shape)
@@ -348,7 +353,37 @@ def dg_quad(N: int, p: int, b: Union[tuple, FlowFn], sigma: Union[float, np.ndar
     colidx32 = cols.astype(np.int32)
     topo = (topo_sort_blocks(nb, rowptr32, colidx32) if check_acyclic
             else np.zeros(0, dtype=np.int64))
+    meta = {"jitter": jitter, "sigma_is_array": np.ndim(sigma) != 0}
+    if return_mass:
+        mass = np.empty_like(mass_cell)
+        mass[perm] = mass_cell
+        meta["mass"] = mass
     return DGSystem(nb=nb, bs=bs, rowptr=rowptr32, colidx=colidx32,
                     vals=np.ascontiguousarray(vals), rhs=rhs.reshape(-1),
-                    perm=perm, topo_order=topo, N=N, p=p,
-                    meta={"jitter": jitter, "sigma_is_array": np.ndim(sigma) != 0})
+                    perm=perm, topo_order=topo, N=N, p=p, meta=meta)
+
+
+def sigma_q_model(N: int, p: int, b, jitter: float = 0.0, seed_perm: Optional[int] = 101,
+                  seed_sigma: int = 105, seed_q: int = 102, seed_xstar: int = 104):
+    """Parts of the differentiable model A(sigma) x = M q of the Q_p transport system.
+
+    The upwind DG matrix is affine in the per-cell reaction coefficient:
+    A(sigma) = A(0) + sum_K sigma_K E_KK (x) M_K, and the right-hand side is
+    b(q) = M q (M the block-diagonal mass matrix, q nodal).  Returns a dict with
+    the sigma = 0 system, the cell mass matrices and the diagonal block positions
+    (block order), seeded sigma ~ U[0.5, 2] per cell, q ~ U[-1, 1] per node and a
+    target x* ~ U[-1, 1].
+    """
+    S0 = dg_quad(N, p, b, sigma=0.0, jitter=jitter, seed_perm=seed_perm, return_mass=True,
+                 q_nodal=np.zeros((N * N, (p + 1) ** 2)))
+    nb, bs = S0.nb, S0.bs
+    rows = np.repeat(np.arange(nb), np.diff(S0.rowptr))
+    diag_pos = np.nonzero(rows == S0.colidx)[0]
+    sig_cell = np.random.Generator(np.random.PCG64(seed_sigma)).uniform(0.5, 2.0, size=N * N)
+    q_cell = np.random.Generator(np.random.PCG64(seed_q)).uniform(-1.0, 1.0, size=(N * N, bs))
+    sigma = np.empty(nb)
+    sigma[S0.perm] = sig_cell
+    q = np.empty((nb, bs))
+    q[S0.perm] = q_cell
+    xstar = np.random.Generator(np.random.PCG64(seed_xstar)).uniform(-1.0, 1.0, size=nb * bs)
+    return dict(system=S0, mass=S0.meta["mass"], diag_pos=diag_pos, sigma=sigma, q=q.reshape(-1), xstar=xstar)

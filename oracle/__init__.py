@@ -285,3 +285,27 @@ def rho_stats(hist):
 def wpd(cc: float, rho: float) -> float:
     """Work units per digit of accuracy, -CC / log10(rho) (section 6)."""
     return -cc / np.log10(rho)
+
+
+def adjoint_gradients(H: "Hierarchy", rowptr, colidx, b, xbar, rtol=1e-12, max_iter=200):
+    """Gradients of a loss L(x) of the solution x = A^{-1} b by the adjoint method.
+
+    Given xbar = dL/dx, the oracle solves A x = b and the adjoint system
+    A^T ybar = xbar (its transposed cycle, section 5), then dL/db = ybar and,
+    because dx = -A^{-1} (dA) x, dL/dA_IJ = -ybar_I x_J^T for every stored block
+    (I, J) of A.  Returns (x, ybar, grad_vals [nnzb, bs, bs]).
+    """
+    bs = H.bs
+    x, h, st = H.solve(b, rtol, max_iter)
+    if st != "OK":
+        raise OracleError(3, "adjoint_gradients: forward solve")
+    ybar, hT, stT = H.solve_T(xbar, rtol, max_iter)
+    if stT != "OK":
+        raise OracleError(3, "adjoint_gradients: adjoint solve")
+    nb = len(rowptr) - 1
+    g = np.zeros((int(rowptr[nb]), bs, bs))
+    for I in range(nb):
+        for t in range(rowptr[I], rowptr[I + 1]):
+            J = colidx[t]
+            g[t] = -np.outer(ybar[I * bs:(I + 1) * bs], x[J * bs:(J + 1) * bs])
+    return x, ybar, g

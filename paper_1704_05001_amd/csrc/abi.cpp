@@ -147,6 +147,16 @@ nair_status nair_vcycle_T(nair_hier h, const double *g, double *y, void *stream)
     return vcycle_common(h, true, g, y, stream);
 }
 
+nair_status nair_grad_vals(int32_t nb, int32_t bs, const int32_t *rowptr, const int32_t *colidx, const double *ybar,
+                           const double *x, double *grad_vals, void *stream) {
+    if (nb < 1 || bs < 1 || bs > nair::kMaxBs) return bad(nullptr, "need nb >= 1 and 1 <= bs <= 32");
+    if (!rowptr || !colidx || !ybar || !x || !grad_vals) return bad(nullptr, "NULL array");
+    return guarded(nullptr, [&]() {
+        nair::grad_vals(nb, bs, rowptr, colidx, ybar, x, grad_vals, static_cast<hipStream_t>(stream));
+        return NAIR_OK;
+    });
+}
+
 nair_status nair_history(nair_hier h, double *buf, int32_t cap, int32_t *n) {
     if (!h) return bad(nullptr, "handle is NULL");
     const int32_t total = static_cast<int32_t>(h->h.hist.size());

@@ -214,4 +214,8 @@ template <typename VT>
 void launch_dense_matvec(const double *M, const VT *x, VT *y, int n, hipStream_t s);
 void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s);
 
+// ------------------------------------------------------------------- grad
+void grad_vals(int nb, int bs, const int *rowptr, const int *colidx, const double *ybar, const double *x,
+               double *gvals, hipStream_t s);
+
 }  // namespace nair

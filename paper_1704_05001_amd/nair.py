@@ -22,7 +22,7 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ESINGULAR", 3: "ENOCONV", 4: "ENUMERIC", 5: 
 
 EXPORTED = ["nair_default_params", "nair_setup", "nair_solve", "nair_solve_T", "nair_vcycle",
             "nair_vcycle_T", "nair_history", "nair_info", "nair_get_level", "nair_last_error",
-            "nair_destroy", "nair_pool_trim", "nair_timer_select", "nair_timer_read"]
+            "nair_destroy", "nair_pool_trim", "nair_timer_select", "nair_timer_read", "nair_grad_vals"]
 
 KERNELS = {"relax": 0, "residual": 1, "restrict": 2, "interp": 3, "spgemm_numeric": 4,
            "spgemm_symbolic": 5, "block_inverse": 6, "galerkin": 7, "dense": 8}
@@ -96,6 +96,8 @@ def lib():
         L.nair_timer_select.restype = C.c_int
         L.nair_timer_read.argtypes = [C.POINTER(C.c_int64), C.POINTER(dbl)]
         L.nair_timer_read.restype = C.c_int
+        L.nair_grad_vals.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
+        L.nair_grad_vals.restype = C.c_int
         _lib = L
     return _lib
 
@@ -329,3 +331,17 @@ def timer_read():
     if st != 0:
         raise NairError(st, "nair_timer_read")
     return n.value, ms.value
+
+
+def grad_vals(rowptr, colidx, ybar, x, bs: int, stream=None):
+    """-ybar_I x_J^T on the block pattern (device tensors), as [nnzb, bs, bs]."""
+    import torch
+    nb = rowptr.numel() - 1
+    nnzb = colidx.numel()
+    out = torch.empty((nnzb, bs, bs), dtype=torch.float64, device=x.device)
+    st = lib().nair_grad_vals(nb, bs, C.c_void_p(rowptr.data_ptr()), C.c_void_p(colidx.data_ptr()),
+                              C.c_void_p(ybar.data_ptr()), C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
+                              _stream_ptr(stream))
+    if st != 0:
+        raise NairError(st, "nair_grad_vals", lib().nair_last_error(None).decode())
+    return out

@@ -108,3 +108,21 @@ def test_random_generators_shapes():
     assert rp[-1] == len(ci) == va.shape[0]
     rows = np.repeat(np.arange(12), np.diff(rp))
     assert np.all(np.isin(np.arange(12), ci[rows == ci]))
+
+
+def test_sigma_q_model_is_affine_in_sigma():
+    """A(sigma) = A(0) + sigma_K M_K on the diagonal blocks and b = M q reproduce
+    the direct assembly with that sigma and nodal q."""
+    from nair_inputs import sigma_q_model
+    import math
+    bfun = lambda x, y: (y + 0.25, -(x + 0.25))
+    m = sigma_q_model(5, 2, bfun, seed_perm=3)
+    S0 = m["system"]
+    vals = S0.vals.copy()
+    vals[m["diag_pos"]] += m["sigma"][:, None, None] * m["mass"]
+    b = np.einsum("kij,kj->ki", m["mass"], m["q"].reshape(S0.nb, S0.bs)).reshape(-1)
+    sig_cell = m["sigma"][S0.perm]
+    q_cell = m["q"].reshape(S0.nb, S0.bs)[S0.perm]
+    S = dg_quad(5, 2, bfun, sigma=sig_cell, seed_perm=3, q_nodal=q_cell)
+    assert np.allclose(vals, S.vals, rtol=0, atol=1e-14)
+    assert np.allclose(b, S.rhs, rtol=0, atol=1e-14)

@@ -587,6 +587,34 @@ def test_transposed_cycle_is_adjoint(relax):
     assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+def test_adjoint_gradients_match_finite_differences():
+    """dL/db and dL/dA of L = w . A^{-1} b against central differences of dense
+    solves (a perturbation of one stored entry or of one b component)."""
+    S = small_dg(5, 2, seed=21, sigma=0.8)
+    H = hier(S, degree=2, max_coarse_dofs=30)
+    assert H.num_levels > 1
+    rng = np.random.default_rng(5)
+    w = rng.uniform(-1, 1, S.n)
+    x, ybar, g = oracle.adjoint_gradients(H, S.rowptr, S.colidx, S.rhs, w, rtol=1e-14)
+    D = S.to_dense()
+    L = lambda M, b: w @ np.linalg.solve(M, b)
+    h = 1e-6
+    gscale = np.abs(g).max()
+    rows = np.repeat(np.arange(S.nb), np.diff(S.rowptr))
+    for t in rng.choice(S.nnzb, 6, replace=False):
+        I, J = rows[t], S.colidx[t]
+        a, c = rng.integers(S.bs, size=2)
+        E = np.zeros_like(D)
+        E[I * S.bs + a, J * S.bs + c] = 1.0
+        fd = (L(D + h * E, S.rhs) - L(D - h * E, S.rhs)) / (2 * h)
+        assert abs(fd - g[t, a, c]) <= 1e-7 * gscale, (t, a, c, fd, g[t, a, c])
+    for i in rng.choice(S.n, 6, replace=False):
+        e = np.zeros(S.n)
+        e[i] = 1.0
+        fd = (L(D, S.rhs + h * e) - L(D, S.rhs - h * e)) / (2 * h)
+        assert abs(fd - ybar[i]) <= 1e-7 * np.abs(ybar).max()
+
+
 def test_single_level_is_a_direct_solve():
     S = small_dg(3, 1, seed=1)
     H = hier(S, max_coarse_dofs=1000)
