@@ -92,8 +92,9 @@ typedef struct {
     int32_t z_nnzb;
     const int32_t *z_rowptr, *z_colidx;  /* Z of R = [Z I]: nc rows, fine F columns */
     const double *z_vals;
-    int32_t dense_n;          /* coarsest level: order of the dense operator */
-    const double *dense_inv;  /* coarsest level: its inverse, row-major [dense_n][dense_n] */
+    int32_t dense_n;          /* one system solved directly on this level: order of its dense operator */
+    const double *dense_inv;  /* dense inverses of the systems solved directly on this level, row-major,
+                                 each at its offset from nair_get_systems ([dense_n][dense_n] for one) */
 } nair_level_view;
 
 /* Fill *p with the defaults (degree 1, theta 0.25, phi 0.025, drop 1e-3, F
@@ -113,6 +114,23 @@ nair_status nair_setup(int32_t nb, int32_t bs, const int32_t *rowptr, const int3
                        const double *vals, const nair_params *p, void *stream, nair_hier *out);
 
 /*
+ * One hierarchy for nsys independent systems (many discrete-ordinate angles of
+ * the transport problem, each its own block triangular system; the paper's
+ * introduction and numerical results motivate the method by such sweeps).
+ * System k owns block rows [o_k, o_k + sys_nb[k]) with o_k = sum_{j<k}
+ * sys_nb[j]; rowptr/colidx/vals hold them one after another in one BSR
+ * (global column indices; a block coupling two systems is NAIR_EINVAL).
+ * Every system gets exactly the hierarchy nair_setup would build for it alone
+ * (splitting hashes use indices within the system); a system at its coarsest
+ * size is inverted densely on that level while the others keep coarsening.
+ * sys_nb is host memory (every entry >= 1).  Solve with nair_solve_batch;
+ * nair_vcycle / nair_vcycle_T apply all systems' cycles at once.
+ */
+nair_status nair_setup_batch(int32_t nsys, const int32_t *sys_nb, int32_t bs, const int32_t *rowptr,
+                             const int32_t *colidx, const double *vals, const nair_params *p, void *stream,
+                             nair_hier *out);
+
+/*
  * Solve A x = b by the stationary iteration x += B (b - A x), x_0 = 0, with B
  * one V-cycle (no pre-relaxation, section 5), until ||b - A x||_2 / ||b||_2 <=
  * rtol or max_iter iterations.  b and x are device vectors of nb*bs doubles;
@@ -130,6 +148,35 @@ nair_status nair_solve(nair_hier h, const double *b, double *x, double rtol, int
  */
 nair_status nair_solve_T(nair_hier h, const double *g, double *y, double rtol, int32_t max_iter,
                          nair_result *res, void *stream);
+
+/*
+ * Solve every system of a handle (batched or not) to its own relative residual:
+ * A x = b (trans = 0) or A^T x = b (trans = 1), the same stationary iteration
+ * as nair_solve / nair_solve_T, with each system's norm, convergence test and
+ * history kept on the device; a converged system's x stops changing.  With
+ * use_graph != 0 one iteration of all systems is captured once into a HIP
+ * graph (per operand pair) and replayed; the host only checks the number of
+ * systems still iterating every few iterations.  b, x: device vectors of all
+ * systems' dofs one after another.  res (host, may be NULL) gets nsys results.
+ * Returns NAIR_OK when every system converged, else NAIR_ENUMERIC if any
+ * residual turned non-finite, else NAIR_ENOCONV.  nair_solve and nair_solve_T
+ * reject handles with more than one system.
+ */
+nair_status nair_solve_batch(nair_hier h, int32_t trans, const double *b, double *x, double rtol,
+                             int32_t max_iter, int32_t use_graph, nair_result *res, void *stream);
+
+/* Relative residual history of system sys in the last nair_solve_batch (host buf, min(cap, n)). */
+nair_status nair_batch_history(nair_hier h, int32_t sys, double *buf, int32_t cap, int32_t *n);
+
+/*
+ * The systems on level lvl (host outputs, each may be NULL; cap = entries the
+ * arrays hold, at least nsys, seg one more): seg = block offsets of each system
+ * on this level, mode = 0 (no blocks left), 1 (coarsened here), 2 (solved
+ * directly here), dense_off = offset of its dense inverse in the level view's
+ * dense_inv (-1 unless mode 2).
+ */
+nair_status nair_get_systems(nair_hier h, int32_t lvl, int32_t cap, int32_t *nsys, int32_t *seg, int8_t *mode,
+                             int64_t *dense_off);
 
 /* One cycle application e = B r (resp. y = B^T g), zero initial guess. */
 nair_status nair_vcycle(nair_hier h, const double *r, double *e, void *stream);

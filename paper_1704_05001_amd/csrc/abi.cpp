@@ -4,6 +4,7 @@
 #include <exception>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "hier.h"
 
@@ -72,8 +73,11 @@ nair_status nair_default_params(nair_params *p) {
     return NAIR_OK;
 }
 
-nair_status nair_setup(int32_t nb, int32_t bs, const int32_t *rowptr, const int32_t *colidx, const double *vals,
-                       const nair_params *p, void *stream, nair_hier *out) {
+}  // extern "C"
+
+static nair_status setup_common(int32_t nsys, const int32_t *sys_nb, int32_t nb, int32_t bs, const int32_t *rowptr,
+                                const int32_t *colidx, const double *vals, const nair_params *p, void *stream,
+                                nair_hier *out) {
     if (!out) return bad(nullptr, "out is NULL");
     *out = nullptr;
     if (!p) return bad(nullptr, "params is NULL");
@@ -95,7 +99,7 @@ nair_status nair_setup(int32_t nb, int32_t bs, const int32_t *rowptr, const int3
     nair_status st = guarded(h, [&]() -> nair_status {
         NAIR_HIP(hipGetDevice(&h->h.device));
         h->h.prm = *p;
-        nair::build_hierarchy(h->h, nb, bs, rowptr, colidx, vals, s);
+        nair::build_hierarchy(h->h, nsys, sys_nb, nb, bs, rowptr, colidx, vals, s);
         h->h.prm.cf_override_host = nullptr;   // host pointer not kept past the call
         return NAIR_OK;
     });
@@ -108,14 +112,82 @@ nair_status nair_setup(int32_t nb, int32_t bs, const int32_t *rowptr, const int3
     return NAIR_OK;
 }
 
+extern "C" {
+
+nair_status nair_setup(int32_t nb, int32_t bs, const int32_t *rowptr, const int32_t *colidx, const double *vals,
+                       const nair_params *p, void *stream, nair_hier *out) {
+    const int32_t one[1] = {nb};
+    return setup_common(1, one, nb, bs, rowptr, colidx, vals, p, stream, out);
+}
+
+nair_status nair_setup_batch(int32_t nsys, const int32_t *sys_nb, int32_t bs, const int32_t *rowptr,
+                             const int32_t *colidx, const double *vals, const nair_params *p, void *stream,
+                             nair_hier *out) {
+    if (out) *out = nullptr;
+    if (nsys < 1 || !sys_nb) return bad(nullptr, "need nsys >= 1 and a system size array");
+    int64_t nb = 0;
+    for (int32_t k = 0; k < nsys; ++k) {
+        if (sys_nb[k] < 1) return bad(nullptr, "every system needs at least one block row");
+        nb += sys_nb[k];
+    }
+    if (nb > 0x7fffffffLL) return bad(nullptr, "total block rows exceed int32");
+    return setup_common(nsys, sys_nb, static_cast<int32_t>(nb), bs, rowptr, colidx, vals, p, stream, out);
+}
+
 static nair_status solve_common(nair_hier h, bool trans, const double *b, double *x, double rtol, int32_t max_iter,
                                 nair_result *res, void *stream) {
     if (!h) return bad(nullptr, "handle is NULL");
     if (!b || !x) return bad(h, "NULL vector");
     if (!(rtol >= 0.0) || max_iter < 0) return bad(h, "need rtol >= 0 and max_iter >= 0");
+    if (h->h.nsys != 1) return bad(h, "the handle holds several systems: use nair_solve_batch");
     DeviceGuard dg(h->h.device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     return guarded(h, [&]() { return nair::run_solve(h->h, trans, b, x, rtol, max_iter, res, s); });
+}
+
+nair_status nair_solve_batch(nair_hier h, int32_t trans, const double *b, double *x, double rtol, int32_t max_iter,
+                             int32_t use_graph, nair_result *res, void *stream) {
+    if (!h) return bad(nullptr, "handle is NULL");
+    if (!b || !x) return bad(h, "NULL vector");
+    if (!(rtol >= 0.0) || max_iter < 0) return bad(h, "need rtol >= 0 and max_iter >= 0");
+    if (trans != 0 && trans != 1) return bad(h, "trans must be 0 or 1");
+    DeviceGuard dg(h->h.device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return guarded(h, [&]() {
+        return nair::run_solve_batch(h->h, trans != 0, b, x, rtol, max_iter, use_graph != 0, res, s);
+    });
+}
+
+nair_status nair_batch_history(nair_hier h, int32_t sys, double *buf, int32_t cap, int32_t *n) {
+    if (!h) return bad(nullptr, "handle is NULL");
+    const auto &hh = h->h.batch.hist_host;
+    if (sys < 0 || sys >= h->h.nsys) return bad(h, "system index out of range");
+    const std::vector<double> empty;
+    const std::vector<double> &v = sys < static_cast<int32_t>(hh.size()) ? hh[sys] : empty;
+    const int32_t total = static_cast<int32_t>(v.size());
+    if (n) *n = total;
+    if (buf)
+        for (int32_t i = 0; i < total && i < cap; ++i) buf[i] = v[i];
+    return NAIR_OK;
+}
+
+nair_status nair_get_systems(nair_hier h, int32_t lvl, int32_t cap, int32_t *nsys, int32_t *seg, int8_t *mode,
+                             int64_t *dense_off) {
+    if (!h) return bad(nullptr, "handle is NULL");
+    if (lvl < 0 || lvl >= static_cast<int32_t>(h->h.lv.size())) return bad(h, "bad level");
+    const nair::Level &L = *h->h.lv[lvl];
+    const int32_t ns = h->h.nsys;
+    if (nsys) *nsys = ns;
+    if ((seg || mode || dense_off) && cap < ns) return bad(h, "arrays hold fewer entries than systems");
+    for (int32_t k = 0; k < ns; ++k) {
+        if (seg) seg[k] = L.seg[k];
+        if (mode) mode[k] = L.mode[k];
+        if (dense_off) dense_off[k] = -1;
+    }
+    if (seg) seg[ns] = L.seg[ns];
+    if (dense_off)
+        for (int k = 0; k < L.ndseg; ++k) dense_off[L.dsys[k]] = L.doff[k];
+    return NAIR_OK;
 }
 
 nair_status nair_solve(nair_hier h, const double *b, double *x, double rtol, int32_t max_iter, nair_result *res,

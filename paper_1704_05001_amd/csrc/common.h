@@ -100,6 +100,7 @@ struct TimerScope {
 void timer_select(int kernel, int level);
 void timer_read(int64_t *launches, double *total_ms);
 extern thread_local int g_timer_level;   // level the host code is working on
+extern thread_local bool g_capturing;    // launches are being captured into a graph (timer off)
 
 // ------------------------------------------------------------- utilities
 inline unsigned grid_for(int64_t n, int per_block) {
@@ -117,19 +118,29 @@ void scan_exclusive(const int *in, int *out, int n, hipStream_t s);
 
 // ---------------------------------------------------------- setup kernels
 void launch_block_maxabs(const double *vals, int64_t nnzb, int bs, double *out, hipStream_t s);
+// skip (nullable): blocks whose inverse is not needed (directly solved systems)
 void launch_block_inverse(const int *rowptr, const int *colidx, const double *vals, int nb, int bs,
-                          double *dinv, int *singular_min, hipStream_t s);
+                          const int8_t *skip, double *dinv, int *singular_min, hipStream_t s);
 void launch_strength(const int *rowptr, const int *colidx, const double *bnorm, int nb, double theta,
                      double phi, uint8_t *mask, int *lambda, hipStream_t s);
 void launch_strong_transpose(const int *rowptr, const int *colidx, const uint8_t *mask, int nb,
                              const int *stptr, int *fill, int *stidx, hipStream_t s);
-void launch_pmis_init(const int *lambda, int nb, int8_t *state, int *dround, int *undecided0, hipStream_t s);
+// splitting states: -1 undecided, 0 F, 1 C, 2 block of a directly solved system
+void launch_pmis_init(const int *lambda, const int8_t *direct, int nb, int8_t *state, int *dround,
+                      int *undecided0, hipStream_t s);
+// lbase (nullable): first block of each block's system; hashes use the index within the system
 void launch_pmis_round(const int *rowptr, const int *colidx, const uint8_t *mask, const int *stptr,
-                       const int *stidx, const int *lambda, int nb, uint64_t seed, int level, int round,
-                       int8_t *state, int8_t *newc, int *dround, int *undecided, hipStream_t s);
-void launch_cf_flags(const int8_t *state, int nb, int *flags, hipStream_t s);
-void launch_cf_index(const int8_t *cf, const int *cscan, int nb, int *cidx, int *cpts, int *flist,
+                       const int *stidx, const int *lambda, const int *lbase, int nb, uint64_t seed, int level,
+                       int round, int8_t *state, int8_t *newc, int *dround, int *undecided, hipStream_t s);
+void launch_cf_flags(const int8_t *state, int nb, int want, int *flags, hipStream_t s);
+// fscan (nullable): F-block exclusive scan when some blocks are neither F nor C
+void launch_cf_index(const int8_t *cf, const int *cscan, const int *fscan, int nb, int *cidx, int *cpts,
+                     int *flist, hipStream_t s);
+// per block: lbase (first block of its system), direct (its system has mode 2), bsys (its system); each nullable
+void launch_seg_info(const int *seg, const int8_t *mode, int nsys, int nb, int *lbase, int8_t *direct, int *bsys,
                      hipStream_t s);
+void launch_mark_direct(const int8_t *direct, int nb, int8_t *state, hipStream_t s);
+void launch_gather_int(const int *v, const int *idx, int n, int *out, hipStream_t s);
 void launch_one_point(const int *rowptr, const int *colidx, const double *bnorm, const int8_t *cf,
                       const int *cidx, int nb, int *pmap, hipStream_t s);
 // T = -(Dinv_I A_IJ) over phi-strong F-F blocks (fine row numbering, C rows empty)
@@ -159,9 +170,12 @@ void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s);
 void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevBSR &K, hipStream_t s);
 
 // ------------------------------------------------------------------ dense
-// Inverse of the dense operator assembled from a BSR (and its transpose);
-// returns false if singular.
-bool dense_inverse_from_bsr(const DevBSR &A, double *inv, double *invT, hipStream_t s);
+// For each segment k < nseg (host arrays): the dense operator of A's block rows
+// [blk0[k], blk0[k] + nbk[k]) (no block outside the range), inverted into
+// inv + off[k] and transposed into invT + off[k] (order n = nbk[k] * bs,
+// row-major).  Returns -1, or the first segment whose operator is singular.
+int dense_inverse_segments(const DevBSR &A, int nseg, const int *blk0_h, const int *nbk_h, const int64_t *off_h,
+                           double *inv, double *invT, hipStream_t s);
 
 // -------------------------------------------------------------- transpose
 void bsr_transpose(const DevBSR &A, DevBSR &AT, hipStream_t s);   // blocks transposed too
@@ -210,8 +224,24 @@ void launch_init_T(const double *dinv, const VT *g, const int8_t *cf, int fc, VT
                    hipStream_t s);
 template <typename VT>
 void launch_axpy(double *x, const VT *e, int64_t n, hipStream_t s);
+// y_k = M_k x_k for nseg dense segments: M_k at M + off[k], order n[k], vectors at dof0[k]
 template <typename VT>
-void launch_dense_matvec(const double *M, const VT *x, VT *y, int n, hipStream_t s);
+void launch_dense_matvec(const double *M, const int64_t *off, const int *dof0, const int *n, int nseg, int max_n,
+                         const VT *x, VT *y, hipStream_t s);
+// x += e on the dofs of systems still iterating (active[bsys[block]]; bsys == nullptr: system 0)
+template <typename VT>
+void launch_axpy_active(double *x, const VT *e, int64_t n, int bs, const int *bsys, const int *active,
+                        hipStream_t s);
+// per-chunk sums of squares (chunk c: dofs [clo[c], clo[c] + clen[c]))
+void launch_seg_sumsq(const double *v, const int64_t *clo, const int *clen, int nchunk, double *part,
+                      hipStream_t s);
+// start of a batched solve: per-system ||b|| from the chunk sums; activity, status, counters
+void launch_seg_init(const double *part, const int *cptr, int nsys, double *bn, double *last, int *active,
+                     int *status, int *iters, int *it, int *nact, hipStream_t s);
+// end of one batched iteration: per-system relative residual, history, convergence, counters
+void launch_seg_check(const double *part, const int *cptr, int nsys, const double *bn, const double *rtol,
+                      int hist_cap, double *hist, double *last, int *active, int *status, int *iters, int *it,
+                      int *nact, hipStream_t s);
 void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s);
 
 // ------------------------------------------------------------------- grad

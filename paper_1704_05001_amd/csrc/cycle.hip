@@ -283,19 +283,129 @@ __global__ __launch_bounds__(kThreads) void k_axpy(double *__restrict__ x, const
     if (g < n) x[g] += static_cast<double>(e[g]);
 }
 
-// y = M x with a double M: one wave per row.
 template <typename VT>
-__global__ __launch_bounds__(256) void k_dense_mv(const double *__restrict__ M, const VT *__restrict__ x,
-                                                 VT *__restrict__ y, int n) {
+__global__ __launch_bounds__(kThreads) void k_axpy_active(double *__restrict__ x, const VT *__restrict__ e, int64_t n,
+                                                         int bs, const int *__restrict__ bsys,
+                                                         const int *__restrict__ active) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (g >= n) return;
+    const int sys = bsys ? bsys[g / bs] : 0;
+    if (active[sys]) x[g] += static_cast<double>(e[g]);
+}
+
+// y_k = M_k x_k for dense segment k = blockIdx.y (order n[k], at M + off[k],
+// vectors at dof0[k]) with a double M: one wave per row.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_dense_mv(const double *__restrict__ M, const int64_t *__restrict__ off,
+                                                 const int *__restrict__ dof0, const int *__restrict__ nn,
+                                                 const VT *__restrict__ x, VT *__restrict__ y) {
+    const int k = blockIdx.y;
+    const int n = nn[k];
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= n) return;
-    const double *m = M + static_cast<int64_t>(row) * n;
+    const double *m = M + off[k] + static_cast<int64_t>(row) * n;
+    const VT *xk = x + dof0[k];
     double s = 0.0;
-    for (int j = lane; j < n; j += 64) s += m[j] * static_cast<double>(x[j]);
+    for (int j = lane; j < n; j += 64) s += m[j] * static_cast<double>(xk[j]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) y[row] = static_cast<VT>(s);
+    if (lane == 0) y[dof0[k] + row] = static_cast<VT>(s);
+}
+
+// part[c] = sum of v^2 over chunk c (dofs clo[c] .. clo[c] + clen[c] - 1)
+__global__ __launch_bounds__(kThreads) void k_seg_sumsq(const double *__restrict__ v, const int64_t *__restrict__ clo,
+                                                       const int *__restrict__ clen, double *__restrict__ part) {
+    __shared__ double lds[kThreads / 64];
+    const int c = blockIdx.x;
+    const double *p = v + clo[c];
+    const int len = clen[c];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < len; i += kThreads) acc += p[i] * p[i];
+    const double t = block_reduce_sum(acc, lds);
+    if (threadIdx.x == 0) part[c] = t;
+}
+
+// sum of the chunk sums of system sys, in chunk order
+__device__ inline double seg_total(const double *__restrict__ part, const int *__restrict__ cptr, int sys) {
+    double ss = 0.0;
+    for (int c = cptr[sys]; c < cptr[sys + 1]; ++c) ss += part[c];
+    return ss;
+}
+
+// status codes as in the public header: 0 OK, 3 not converged, 4 non-finite
+constexpr int kStOk = 0, kStNoConv = 3, kStNumeric = 4;
+
+__global__ __launch_bounds__(kThreads) void k_seg_init(const double *__restrict__ part, const int *__restrict__ cptr,
+                                                      int nsys, double *__restrict__ bn, double *__restrict__ last,
+                                                      int *__restrict__ active, int *__restrict__ status,
+                                                      int *__restrict__ iters, int *__restrict__ it,
+                                                      int *__restrict__ nact) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int sys = threadIdx.x; sys < nsys; sys += kThreads) {
+        const double b = sqrt(seg_total(part, cptr, sys));
+        bn[sys] = b;
+        last[sys] = 1.0;
+        iters[sys] = 0;
+        if (!isfinite(b)) {
+            active[sys] = 0;
+            status[sys] = kStNumeric;
+        } else if (b == 0.0) {   // x = 0 solves it
+            active[sys] = 0;
+            status[sys] = kStOk;
+            last[sys] = 0.0;
+        } else {
+            active[sys] = 1;
+            status[sys] = kStNoConv;
+            atomicAdd(&cnt, 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *it = 0;
+        *nact = cnt;
+    }
+}
+
+// After iteration *it: relative residuals of the active systems, recorded in
+// hist[sys * hist_cap + it]; converged or non-finite systems stop.
+__global__ __launch_bounds__(kThreads) void k_seg_check(const double *__restrict__ part, const int *__restrict__ cptr,
+                                                       int nsys, const double *__restrict__ bn,
+                                                       const double *__restrict__ rtol, int hist_cap,
+                                                       double *__restrict__ hist, double *__restrict__ last,
+                                                       int *__restrict__ active, int *__restrict__ status,
+                                                       int *__restrict__ iters, int *__restrict__ it,
+                                                       int *__restrict__ nact) {
+    __shared__ int cnt;
+    const int k = *it;
+    const double tol = *rtol;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int sys = threadIdx.x; sys < nsys; sys += kThreads) {
+        if (!active[sys]) continue;
+        const double rel = sqrt(seg_total(part, cptr, sys)) / bn[sys];
+        if (k < hist_cap) hist[static_cast<int64_t>(sys) * hist_cap + k] = rel;
+        last[sys] = rel;
+        if (!isfinite(rel)) {
+            active[sys] = 0;
+            status[sys] = kStNumeric;
+            iters[sys] = k + 1;
+        } else if (rel <= tol) {
+            active[sys] = 0;
+            status[sys] = kStOk;
+            iters[sys] = k + 1;
+        } else {
+            iters[sys] = k + 1;
+            atomicAdd(&cnt, 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *nact = cnt;
+        *it = k + 1;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_to_float(const double *__restrict__ in, float *__restrict__ out, int64_t n) {
@@ -417,8 +527,38 @@ void launch_axpy(double *x, const VT *e, int64_t n, hipStream_t s) {
 }
 
 template <typename VT>
-void launch_dense_matvec(const double *M, const VT *x, VT *y, int n, hipStream_t s) {
-    k_dense_mv<VT><<<grid_for(n, 4), 256, 0, s>>>(M, x, y, n);
+void launch_dense_matvec(const double *M, const int64_t *off, const int *dof0, const int *n, int nseg, int max_n,
+                         const VT *x, VT *y, hipStream_t s) {
+    if (nseg <= 0) return;
+    k_dense_mv<VT><<<dim3(grid_for(max_n, 4), static_cast<unsigned>(nseg)), 256, 0, s>>>(M, off, dof0, n, x, y);
+    NAIR_HIP(hipGetLastError());
+}
+
+template <typename VT>
+void launch_axpy_active(double *x, const VT *e, int64_t n, int bs, const int *bsys, const int *active,
+                        hipStream_t s) {
+    k_axpy_active<VT><<<grid_for(n, kThreads), kThreads, 0, s>>>(x, e, n, bs, bsys, active);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_seg_sumsq(const double *v, const int64_t *clo, const int *clen, int nchunk, double *part,
+                      hipStream_t s) {
+    if (nchunk <= 0) return;
+    k_seg_sumsq<<<static_cast<unsigned>(nchunk), kThreads, 0, s>>>(v, clo, clen, part);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_seg_init(const double *part, const int *cptr, int nsys, double *bn, double *last, int *active,
+                     int *status, int *iters, int *it, int *nact, hipStream_t s) {
+    k_seg_init<<<1, kThreads, 0, s>>>(part, cptr, nsys, bn, last, active, status, iters, it, nact);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_seg_check(const double *part, const int *cptr, int nsys, const double *bn, const double *rtol,
+                      int hist_cap, double *hist, double *last, int *active, int *status, int *iters, int *it,
+                      int *nact, hipStream_t s) {
+    k_seg_check<<<1, kThreads, 0, s>>>(part, cptr, nsys, bn, rtol, hist_cap, hist, last, active, status, iters, it,
+                                       nact);
     NAIR_HIP(hipGetLastError());
 }
 
@@ -443,7 +583,9 @@ void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s) {
     template void launch_init_T<VT>(const double *, const VT *, const int8_t *, int, VT *, VT *, int, int,           \
                                     hipStream_t);                                                                    \
     template void launch_axpy<VT>(double *, const VT *, int64_t, hipStream_t);                                       \
-    template void launch_dense_matvec<VT>(const double *, const VT *, VT *, int, hipStream_t);
+    template void launch_axpy_active<VT>(double *, const VT *, int64_t, int, const int *, const int *, hipStream_t); \
+    template void launch_dense_matvec<VT>(const double *, const int64_t *, const int *, const int *, int, int,       \
+                                          const VT *, VT *, hipStream_t);
 
 NAIR_CYCLE_INST(double, double)
 NAIR_CYCLE_INST(float, float)

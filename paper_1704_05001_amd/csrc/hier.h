@@ -11,7 +11,19 @@ namespace nair {
 
 struct Level {
     DevBSR A;                       // level operator (A_0 = copy of the input, then K = R A P)
-    bool coarsest = false;
+    bool coarsest = false;          // every system left is solved directly here
+    // systems on this level: a batched hierarchy holds several independent
+    // systems, each a contiguous range of block rows (one system otherwise)
+    std::vector<int> seg;           // nsys + 1 block offsets
+    std::vector<int8_t> mode;       // per system: 0 no blocks left, 1 coarsened, 2 solved directly here
+    DBuf<int> seg_d, lbase;         // device copy of seg; first block of each block's system
+    DBuf<int8_t> mode_d, direct;    // device copy of mode; blocks of directly solved systems
+    // direct solves: one dense inverse (and its transpose) per system with mode 2
+    int ndseg = 0, dmax_n = 0;
+    std::vector<int> dsys, dblk0, dnb;
+    std::vector<int64_t> doff;
+    DBuf<int> ddof0_d, dn_d;
+    DBuf<int64_t> doff_d;
     // setup products
     DBuf<double> dinv, bnorm;
     DBuf<uint8_t> mask;
@@ -19,8 +31,7 @@ struct Level {
     DBuf<int8_t> cf;
     int nc = 0, nF = 0, rounds = 0;
     DevBSR Z;                       // R = [Z I]: nc rows, fine F columns
-    // coarsest level
-    int dense_n = 0;
+    int dense_n = 0;                // order of the dense inverse when one system covers the level
     DBuf<double> dense_inv, dense_invT;
     // transposed cycle (built on first use)
     bool have_T = false;
@@ -34,27 +45,55 @@ struct Level {
     DBuf<float> r32, e0_32, e1_32, tmp32;
 };
 
+// Per-system solve state of the batched iteration (device-side convergence).
+struct BatchSolve {
+    bool ready = false;
+    DBuf<int> bsys;                 // level-0 block -> system
+    DBuf<int64_t> clo;              // norm chunks: first dof, length, per-system chunk ranges
+    DBuf<int> clen, cptr;
+    int nchunk = 0;
+    DBuf<double> part, bn, last, rtol;
+    DBuf<double> hist;              // [nsys][hist_cap] relative residuals
+    int hist_cap = 0;
+    DBuf<int> active, status, iters, it, nact;
+    double rtol_host = 0.0;
+    std::vector<std::vector<double>> hist_host;
+    // captured iteration (slot 0: A, slot 1: A^T), replayed per step
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    const void *key_b[2] = {nullptr, nullptr}, *key_x[2] = {nullptr, nullptr};
+    ~BatchSolve();
+};
+
 struct Hier {
     nair_params prm{};
     int bs = 0;
     int device = 0;
+    int nsys = 1;
     std::vector<std::unique_ptr<Level>> lv;
     std::vector<double> hist;
     std::string err;
     DBuf<double> partials, scal;
     int npart = 0;
+    BatchSolve batch;
 };
 
-void build_hierarchy(Hier &h, int nb, int bs, const int *rowptr, const int *colidx, const double *vals,
-                     hipStream_t s);
+// nsys systems of sys_nb[s] block rows each (host array), stored one after the
+// other in one BSR matrix with no block coupling two systems.
+void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const int *rowptr, const int *colidx,
+                     const double *vals, hipStream_t s);
 nair_status run_solve(Hier &h, bool trans, const double *b, double *x, double rtol, int max_iter,
                       nair_result *res, hipStream_t s);
+// Every system iterated to its own relative residual; res[s] per system (host).
+nair_status run_solve_batch(Hier &h, bool trans, const double *b, double *x, double rtol, int max_iter,
+                            bool use_graph, nair_result *res, hipStream_t s);
 void run_vcycle(Hier &h, bool trans, const double *r, double *e, hipStream_t s);
 void ensure_transposes(Hier &h, hipStream_t s);
 void make_fp32_copies(Hier &h, hipStream_t s);
 void complexity(Hier &h, double *oc, double *cc, hipStream_t s);
 
 // validation of the input pattern (device): sets *bad != 0 on error
-void launch_validate(const int *rowptr, const int *colidx, int nb, int64_t nnzb, int *bad, hipStream_t s);
+void launch_validate(const int *rowptr, const int *colidx, int nb, int64_t nnzb, const int *seg, int nsys, int *bad,
+                     hipStream_t s);
 
 }  // namespace nair

@@ -102,6 +102,7 @@ void pool_trim() {
 // ------------------------------------------------------------ kernel timer
 
 thread_local int g_timer_level = 0;
+thread_local bool g_capturing = false;
 
 namespace {
 struct Timer {
@@ -120,6 +121,7 @@ Timer &timer() {
 }  // namespace
 
 TimerScope::TimerScope(int kernel, int level, hipStream_t stream, int launches) : on(false), s(stream) {
+    if (g_capturing) return;
     Timer &T = timer();
     if (T.kernel != kernel || (T.level >= 0 && T.level != level)) return;
     std::lock_guard<std::mutex> lk(T.mu);

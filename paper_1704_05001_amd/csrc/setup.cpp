@@ -6,6 +6,12 @@
 //   Z = -(sum_{i<=k} A_cf T^i) D_ff^{-1} with T = -D_ff^{-1} A_ff^phi ->
 //   R A by SpGEMM -> K = (R A) P through the one-point map, drop filter.
 // The coarsest level (or a level whose splitting stalls) is inverted densely.
+//
+// A batched hierarchy holds independent systems side by side (contiguous block
+// ranges, no coupling): every step above is local to a system's blocks, the
+// splitting hashes use indices within the system, and a system that reaches
+// its coarsest size is inverted densely on that level while the others go on
+// coarsening, so each system's hierarchy equals the one it would get alone.
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -34,14 +40,58 @@ void alloc_vectors(Level &L, int bs) {
     L.tmp.alloc(n);
 }
 
-void make_coarsest(Level &L, int lvl, hipStream_t s) {
-    L.coarsest = true;
-    L.dense_n = L.A.nb * L.A.bs;
-    L.dense_inv.alloc(static_cast<size_t>(L.dense_n) * L.dense_n);
-    L.dense_invT.alloc(static_cast<size_t>(L.dense_n) * L.dense_n);
-    if (!dense_inverse_from_bsr(L.A, L.dense_inv.get(), L.dense_invT.get(), s))
-        fail(NAIR_ESINGULAR, "coarsest operator (level " + std::to_string(lvl) + ", " +
-                                 std::to_string(L.dense_n) + " unknowns) is singular");
+void upload_systems(Level &L, hipStream_t s) {
+    const int nsys = static_cast<int>(L.mode.size());
+    if (!L.seg_d.get()) L.seg_d.alloc(nsys + 1);
+    if (!L.mode_d.get()) L.mode_d.alloc(nsys);
+    NAIR_HIP(hipMemcpyAsync(L.seg_d.get(), L.seg.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice, s));
+    NAIR_HIP(hipMemcpyAsync(L.mode_d.get(), L.mode.data(), nsys, hipMemcpyHostToDevice, s));
+    NAIR_HIP(hipStreamSynchronize(s));   // seg and mode may change on the host afterwards
+}
+
+// Dense inverses of the systems solved directly on this level (mode 2).
+void make_direct(Level &L, int lvl, hipStream_t s) {
+    const int bs = L.A.bs;
+    L.dsys.clear();
+    L.dblk0.clear();
+    L.dnb.clear();
+    L.doff.clear();
+    int64_t off = 0;
+    L.dmax_n = 0;
+    for (size_t k = 0; k < L.mode.size(); ++k)
+        if (L.mode[k] == 2) {
+            const int nbk = L.seg[k + 1] - L.seg[k];
+            const int64_t n = static_cast<int64_t>(nbk) * bs;
+            L.dsys.push_back(static_cast<int>(k));
+            L.dblk0.push_back(L.seg[k]);
+            L.dnb.push_back(nbk);
+            L.doff.push_back(off);
+            off += n * n;
+            L.dmax_n = std::max(L.dmax_n, static_cast<int>(n));
+        }
+    L.ndseg = static_cast<int>(L.dsys.size());
+    if (L.ndseg == 0) return;
+    L.dense_n = (L.ndseg == 1 && L.dnb[0] == L.A.nb) ? L.A.nb * bs : 0;
+    L.dense_inv.alloc(static_cast<size_t>(off));
+    L.dense_invT.alloc(static_cast<size_t>(off));
+    const int bad = dense_inverse_segments(L.A, L.ndseg, L.dblk0.data(), L.dnb.data(), L.doff.data(),
+                                           L.dense_inv.get(), L.dense_invT.get(), s);
+    if (bad >= 0)
+        fail(NAIR_ESINGULAR, "coarsest operator of system " + std::to_string(L.dsys[bad]) + " (level " +
+                                 std::to_string(lvl) + ", " + std::to_string(L.dnb[bad] * bs) +
+                                 " unknowns) is singular");
+    std::vector<int> dof0(L.ndseg), nn(L.ndseg);
+    for (int k = 0; k < L.ndseg; ++k) {
+        dof0[k] = L.dblk0[k] * bs;
+        nn[k] = L.dnb[k] * bs;
+    }
+    L.ddof0_d.alloc(L.ndseg);
+    L.dn_d.alloc(L.ndseg);
+    L.doff_d.alloc(L.ndseg);
+    NAIR_HIP(hipMemcpyAsync(L.ddof0_d.get(), dof0.data(), sizeof(int) * L.ndseg, hipMemcpyHostToDevice, s));
+    NAIR_HIP(hipMemcpyAsync(L.dn_d.get(), nn.data(), sizeof(int) * L.ndseg, hipMemcpyHostToDevice, s));
+    NAIR_HIP(hipMemcpyAsync(L.doff_d.get(), L.doff.data(), sizeof(int64_t) * L.ndseg, hipMemcpyHostToDevice, s));
+    NAIR_HIP(hipStreamSynchronize(s));   // dof0 and nn are pageable host memory
 }
 
 // C/F splitting by independent-set rounds; state ends as 1 (C) / 0 (F) in L.cf.
@@ -56,7 +106,7 @@ void split(Hier &h, Level &L, int lvl, hipStream_t s) {
     DBuf<int8_t> newc(n);
     DBuf<int> counts(kMaxRounds + 1);
     NAIR_HIP(hipMemsetAsync(counts.get(), 0, sizeof(int) * (kMaxRounds + 1), s));
-    launch_pmis_init(L.lambda.get(), n, L.cf.get(), L.dround.get(), counts.get(), s);
+    launch_pmis_init(L.lambda.get(), L.direct.get(), n, L.cf.get(), L.dround.get(), counts.get(), s);
     int undecided0 = read_int(counts.get(), s);
     L.rounds = 0;
     if (undecided0 == 0) return;
@@ -65,8 +115,8 @@ void split(Hier &h, Level &L, int lvl, hipStream_t s) {
         for (int b = 0; b < kRoundBatch; ++b) {
             ++r;
             launch_pmis_round(L.A.rowptr.get(), L.A.colidx.get(), L.mask.get(), stptr.get(), stidx.get(),
-                              L.lambda.get(), n, h.prm.seed, lvl, r, L.cf.get(), newc.get(), L.dround.get(),
-                              counts.get() + r, s);
+                              L.lambda.get(), L.lbase.get(), n, h.prm.seed, lvl, r, L.cf.get(), newc.get(),
+                              L.dround.get(), counts.get() + r, s);
         }
         int hc[kRoundBatch];
         read_ints(counts.get() + r - kRoundBatch + 1, hc, kRoundBatch, s);
@@ -81,42 +131,68 @@ void split(Hier &h, Level &L, int lvl, hipStream_t s) {
 
 }  // namespace
 
-void build_hierarchy(Hier &h, int nb, int bs, const int *rowptr, const int *colidx, const double *vals,
-                     hipStream_t s) {
+void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const int *rowptr, const int *colidx,
+                     const double *vals, hipStream_t s) {
     const nair_params &p = h.prm;
     h.bs = bs;
+    h.nsys = nsys;
     const int bb = bs * bs;
     const int nnzb = read_int(rowptr + nb, s);
     if (nnzb < nb) fail(NAIR_EINVAL, "rowptr[nb] < nb: every row needs its diagonal block");
+    auto L0 = std::make_unique<Level>();
+    L0->seg.assign(nsys + 1, 0);
+    for (int k = 0; k < nsys; ++k) L0->seg[k + 1] = L0->seg[k] + sys_nb[k];
+    L0->mode.assign(nsys, 0);
+    upload_systems(*L0, s);
     {
         DBuf<int> bad(1);
         NAIR_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), s));
-        launch_validate(rowptr, colidx, nb, nnzb, bad.get(), s);
+        launch_validate(rowptr, colidx, nb, nnzb, nsys > 1 ? L0->seg_d.get() : nullptr, nsys, bad.get(), s);
         const int vb = read_int(bad.get(), s);
         if (vb & 1) fail(NAIR_EINVAL, "rowptr is not a non-decreasing offset array from 0 to nnzb");
         if (vb & 2) fail(NAIR_EINVAL, "column index out of range");
         if (vb & 4) fail(NAIR_EINVAL, "block columns of a row are not strictly increasing");
         if (vb & 8) fail(NAIR_EINVAL, "a row has no diagonal block");
+        if (vb & 16) fail(NAIR_EINVAL, "a block couples two systems of the batch");
     }
-    {
-        auto L0 = std::make_unique<Level>();
-        L0->A.alloc(nb, nb, bs, nnzb);
-        NAIR_HIP(hipMemcpyAsync(L0->A.rowptr.get(), rowptr, sizeof(int) * (static_cast<size_t>(nb) + 1),
-                                hipMemcpyDeviceToDevice, s));
-        NAIR_HIP(hipMemcpyAsync(L0->A.colidx.get(), colidx, sizeof(int) * static_cast<size_t>(nnzb),
-                                hipMemcpyDeviceToDevice, s));
-        NAIR_HIP(hipMemcpyAsync(L0->A.vals.get(), vals, sizeof(double) * static_cast<size_t>(nnzb) * bb,
-                                hipMemcpyDeviceToDevice, s));
-        h.lv.push_back(std::move(L0));
-    }
+    L0->A.alloc(nb, nb, bs, nnzb);
+    NAIR_HIP(hipMemcpyAsync(L0->A.rowptr.get(), rowptr, sizeof(int) * (static_cast<size_t>(nb) + 1),
+                            hipMemcpyDeviceToDevice, s));
+    NAIR_HIP(hipMemcpyAsync(L0->A.colidx.get(), colidx, sizeof(int) * static_cast<size_t>(nnzb),
+                            hipMemcpyDeviceToDevice, s));
+    NAIR_HIP(hipMemcpyAsync(L0->A.vals.get(), vals, sizeof(double) * static_cast<size_t>(nnzb) * bb,
+                            hipMemcpyDeviceToDevice, s));
+    h.lv.push_back(std::move(L0));
+
     for (int l = 0;; ++l) {
         Level &L = *h.lv[l];
         const int n = L.A.nb;
         g_timer_level = l;
         alloc_vectors(L, bs);
-        if (static_cast<int64_t>(n) * bs <= p.max_coarse_dofs || l == p.max_levels - 1) {
-            make_coarsest(L, l, s);
+        // systems at their coarsest size (or the last allowed level) are solved directly here
+        int ncont = 0, ndir = 0;
+        for (int k = 0; k < nsys; ++k) {
+            const int len = L.seg[k + 1] - L.seg[k];
+            if (len == 0) {
+                L.mode[k] = 0;
+            } else if (static_cast<int64_t>(len) * bs <= p.max_coarse_dofs || l == p.max_levels - 1) {
+                L.mode[k] = 2;
+                ++ndir;
+            } else {
+                L.mode[k] = 1;
+                ++ncont;
+            }
+        }
+        upload_systems(L, s);
+        if (ncont == 0) {
+            L.coarsest = true;
+            make_direct(L, l, s);
             break;
+        }
+        if (nsys > 1) {
+            L.lbase.alloc(n);
+            if (ndir > 0) L.direct.alloc(n);
+            launch_seg_info(L.seg_d.get(), L.mode_d.get(), nsys, n, L.lbase.get(), L.direct.get(), nullptr, s);
         }
         const int64_t nz = L.A.nnzb;
         L.dinv.alloc(static_cast<size_t>(n) * bb);
@@ -133,8 +209,8 @@ void build_hierarchy(Hier &h, int nb, int bs, const int *rowptr, const int *coli
         launch_block_maxabs(L.A.vals.get(), nz, bs, L.bnorm.get(), s);
         {
             TimerScope ts(TK_BLOCKINV, l, s);
-            launch_block_inverse(L.A.rowptr.get(), L.A.colidx.get(), L.A.vals.get(), n, bs, L.dinv.get(), sing.get(),
-                                 s);
+            launch_block_inverse(L.A.rowptr.get(), L.A.colidx.get(), L.A.vals.get(), n, bs, L.direct.get(),
+                                 L.dinv.get(), sing.get(), s);
         }
         launch_strength(L.A.rowptr.get(), L.A.colidx.get(), L.bnorm.get(), n, p.theta, p.phi, L.mask.get(),
                         L.lambda.get(), s);
@@ -143,35 +219,71 @@ void build_hierarchy(Hier &h, int nb, int bs, const int *rowptr, const int *coli
             for (int I = 0; I < n; ++I) cfh[I] = p.cf_override_host[I] ? 1 : 0;
             NAIR_HIP(hipMemcpyAsync(L.cf.get(), cfh.data(), n, hipMemcpyHostToDevice, s));
             NAIR_HIP(hipMemsetAsync(L.dround.get(), 0, sizeof(int) * n, s));
+            if (L.direct.get()) launch_mark_direct(L.direct.get(), n, L.cf.get(), s);
             NAIR_HIP(hipStreamSynchronize(s));   // cfh is pageable host memory
             L.rounds = 0;
         } else {
             split(h, L, l, s);
         }
         DBuf<int> cflag(n), cscan(static_cast<size_t>(n) + 1);
-        launch_cf_flags(L.cf.get(), n, cflag.get(), s);
-        scan_exclusive(cflag.get(), cscan.get(), n, s);
-        int hsing = 0, nc = 0;
-        read_many({{sing.get(), &hsing}, {cscan.get() + n, &nc}}, s);
+        std::vector<int> cseg(nsys + 1);   // coarse blocks per system, as offsets
+        DBuf<int> cseg_d(nsys + 1);
+        auto count_c = [&]() {
+            launch_cf_flags(L.cf.get(), n, 1, cflag.get(), s);
+            scan_exclusive(cflag.get(), cscan.get(), n, s);
+            launch_gather_int(cscan.get(), L.seg_d.get(), nsys + 1, cseg_d.get(), s);
+            read_ints(cseg_d.get(), cseg.data(), nsys + 1, s);
+        };
+        count_c();
+        const int hsing = read_int(sing.get(), s);
         if (hsing != kNoSingular)
             fail(NAIR_ESINGULAR, "diagonal block " + std::to_string(hsing) + " of level " + std::to_string(l) +
                                      " is singular");
-        if (nc == 0 || nc == n) {
-            if (static_cast<int64_t>(n) * bs <= kStallDenseDofs) {
-                make_coarsest(L, l, s);
+        // a system whose splitting stalls (no C or no F block) is solved directly here
+        bool stalled = false;
+        for (int k = 0; k < nsys; ++k) {
+            if (L.mode[k] != 1) continue;
+            const int len = L.seg[k + 1] - L.seg[k];
+            const int nck = cseg[k + 1] - cseg[k];
+            if (nck != 0 && nck != len) continue;
+            if (static_cast<int64_t>(len) * bs > kStallDenseDofs)
+                fail(NAIR_ECOARSEN, "splitting of level " + std::to_string(l) + " (" + std::to_string(len) +
+                                        " blocks" + (nsys > 1 ? ", system " + std::to_string(k) : std::string()) +
+                                        ") gave " + std::to_string(nck) + " C blocks");
+            L.mode[k] = 2;
+            --ncont;
+            ++ndir;
+            stalled = true;
+        }
+        if (stalled) {
+            upload_systems(L, s);
+            if (ncont == 0) {
+                L.coarsest = true;
+                make_direct(L, l, s);
                 break;
             }
-            fail(NAIR_ECOARSEN, "splitting of level " + std::to_string(l) + " (" + std::to_string(n) +
-                                    " blocks) gave " + std::to_string(nc) + " C blocks");
+            if (!L.direct.get()) L.direct.alloc(n);
+            launch_seg_info(L.seg_d.get(), L.mode_d.get(), nsys, n, nullptr, L.direct.get(), nullptr, s);
+            launch_mark_direct(L.direct.get(), n, L.cf.get(), s);
+            count_c();
         }
+        if (ndir > 0) make_direct(L, l, s);
+        const int nc = cseg[nsys];
         L.nc = nc;
-        L.nF = n - nc;
+        DBuf<int> fscan;
+        if (ndir > 0) {
+            fscan.alloc(static_cast<size_t>(n) + 1);
+            launch_cf_flags(L.cf.get(), n, 0, cflag.get(), s);
+            scan_exclusive(cflag.get(), fscan.get(), n, s);
+            L.nF = read_int(fscan.get() + n, s);
+        } else {
+            L.nF = n - nc;
+        }
         L.cpts.alloc(nc);
         L.flist.alloc(L.nF);
-        launch_cf_index(L.cf.get(), cscan.get(), n, L.cidx.get(), L.cpts.get(), L.flist.get(), s);
+        launch_cf_index(L.cf.get(), cscan.get(), fscan.get(), n, L.cidx.get(), L.cpts.get(), L.flist.get(), s);
         launch_one_point(L.A.rowptr.get(), L.A.colidx.get(), L.bnorm.get(), L.cf.get(), L.cidx.get(), n,
                          L.pmap.get(), s);
-
         // Neumann operands: T (phi-strong F-F, scaled by -D_ff^{-1}) and W_0 = A_cf
         DevBSR T, W0;
         T.nb = n;
@@ -239,6 +351,8 @@ void build_hierarchy(Hier &h, int nb, int bs, const int *rowptr, const int *coli
         spgemm(L.Z, L.cpts.get(), L.A, RA, s);
         auto next = std::make_unique<Level>();
         rap_merge_drop(RA, L.pmap.get(), nc, p.drop, next->A, s);
+        next->seg = cseg;
+        next->mode.assign(nsys, 0);
         h.lv.push_back(std::move(next));
     }
     if (p.precision == 1) make_fp32_copies(h, s);
@@ -296,10 +410,10 @@ void complexity(Hier &h, double *oc, double *cc, hipStream_t s) {
     for (auto &Lp : h.lv) {
         Level &L = *Lp;
         o += static_cast<double>(L.A.nnzb) / nnz0;
-        if (L.coarsest) {
-            c += static_cast<double>(L.dense_n) * L.dense_n / (static_cast<double>(L.A.bs) * L.A.bs) / nnz0;
-            continue;
-        }
+        // dense solves count their n^2 entries in block units
+        for (int k = 0; k < L.ndseg; ++k)
+            c += static_cast<double>(L.dnb[k]) * L.dnb[k] / nnz0;
+        if (L.coarsest) continue;
         std::vector<int> rp(L.A.nb + 1);
         std::vector<int8_t> cfh(L.A.nb);
         NAIR_HIP(hipMemcpyAsync(rp.data(), L.A.rowptr.get(), sizeof(int) * rp.size(), hipMemcpyDeviceToHost, s));
@@ -308,8 +422,9 @@ void complexity(Hier &h, double *oc, double *cc, hipStream_t s) {
         double nzF = 0, nzC = 0, nbF = 0;
         for (int I = 0; I < L.A.nb; ++I) {
             const double rn = rp[I + 1] - rp[I];
-            if (cfh[I] == 1) nzC += rn;
-            else {
+            if (cfh[I] == 1) {
+                nzC += rn;
+            } else if (cfh[I] == 0) {
                 nzF += rn;
                 nbF += 1;
             }

@@ -42,7 +42,8 @@ __global__ __launch_bounds__(256) void k_block_maxabs(const double *__restrict__
 // m > i ascending, one division by u_ii).  LDS: a[bs*bs], y[bs*bs], perm[bs].
 __global__ __launch_bounds__(64) void k_block_inverse(const int *__restrict__ rowptr, const int *__restrict__ colidx,
                                                      const double *__restrict__ vals, int nb, int bs,
-                                                     double *__restrict__ dinv, int *__restrict__ singular_min) {
+                                                     const int8_t *__restrict__ skip, double *__restrict__ dinv,
+                                                     int *__restrict__ singular_min) {
     extern __shared__ double lds[];
     const int bb = bs * bs;
     double *a = lds;
@@ -51,6 +52,7 @@ __global__ __launch_bounds__(64) void k_block_inverse(const int *__restrict__ ro
     __shared__ int dpos;
     const int lane = threadIdx.x;
     for (int I = blockIdx.x; I < nb; I += gridDim.x) {
+        if (skip && skip[I]) continue;   // uniform over the workgroup
         if (lane == 0) dpos = -1;
         __syncthreads();
         for (int t = rowptr[I] + lane; t < rowptr[I + 1]; t += kWave)
@@ -182,7 +184,9 @@ __global__ __launch_bounds__(256) void k_strong_transpose(const int *__restrict_
 
 // ------------------------------------------------------------ splitting
 
-constexpr int8_t kUnd = -1, kF = 0, kC = 1;
+// kD: a block of a system that is solved directly on this level (batched
+// hierarchies); it takes no part in the splitting.
+constexpr int8_t kUnd = -1, kF = 0, kC = 1, kD = 2;
 
 // splitmix64 finaliser (Steele, Lea and Flood, OOPSLA 2014).
 __device__ inline uint64_t splitmix64(uint64_t x) {
@@ -199,21 +203,29 @@ __device__ inline bool key_beats(int lamI, uint64_t hI, int I, int lamJ, uint64_
     return I > J;
 }
 
-__global__ __launch_bounds__(256) void k_pmis_init(const int *__restrict__ lambda, int nb, int8_t *__restrict__ state,
-                                                  int *__restrict__ dround, int *__restrict__ undecided0) {
+__global__ __launch_bounds__(256) void k_pmis_init(const int *__restrict__ lambda, const int8_t *__restrict__ direct,
+                                                  int nb, int8_t *__restrict__ state, int *__restrict__ dround,
+                                                  int *__restrict__ undecided0) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= nb) return;
+    dround[I] = 0;
+    if (direct && direct[I]) {
+        state[I] = kD;
+        return;
+    }
     const bool und = lambda[I] != 0;
     state[I] = und ? kUnd : kF;
-    dround[I] = 0;
     if (und) atomicAdd(undecided0, 1);
 }
 
 // New C: undecided blocks whose key beats every undecided neighbour in S u S^T.
+// The hash takes the block's index within its own system (I - lbase[I]; lbase
+// == nullptr: one system), so a batched hierarchy splits every system exactly
+// as it would alone; neighbours always share the system.
 __global__ __launch_bounds__(256) void k_pmis_select(const int *__restrict__ rowptr, const int *__restrict__ colidx,
                                                     const uint8_t *__restrict__ mask, const int *__restrict__ stptr,
                                                     const int *__restrict__ stidx, const int *__restrict__ lambda,
-                                                    int nb, uint64_t seed, int level,
+                                                    const int *__restrict__ lbase, int nb, uint64_t seed, int level,
                                                     const int8_t *__restrict__ state, int8_t *__restrict__ newc) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= nb) return;
@@ -222,20 +234,21 @@ __global__ __launch_bounds__(256) void k_pmis_select(const int *__restrict__ row
         return;
     }
     const uint64_t salt = seed ^ (static_cast<uint64_t>(level) << 40);
+    const int base = lbase ? lbase[I] : 0;
     const int lamI = lambda[I];
-    const uint64_t hI = splitmix64(salt ^ static_cast<uint64_t>(I));
+    const uint64_t hI = splitmix64(salt ^ static_cast<uint64_t>(I - base));
     bool is_max = true;
     for (int t = rowptr[I]; t < rowptr[I + 1] && is_max; ++t) {
         if (!(mask[t] & 1)) continue;
         const int J = colidx[t];
         if (state[J] == kUnd &&
-            !key_beats(lamI, hI, I, lambda[J], splitmix64(salt ^ static_cast<uint64_t>(J)), J))
+            !key_beats(lamI, hI, I, lambda[J], splitmix64(salt ^ static_cast<uint64_t>(J - base)), J))
             is_max = false;
     }
     for (int t = stptr[I]; t < stptr[I + 1] && is_max; ++t) {
         const int J = stidx[t];
         if (state[J] == kUnd &&
-            !key_beats(lamI, hI, I, lambda[J], splitmix64(salt ^ static_cast<uint64_t>(J)), J))
+            !key_beats(lamI, hI, I, lambda[J], splitmix64(salt ^ static_cast<uint64_t>(J - base)), J))
             is_max = false;
     }
     newc[I] = is_max ? 1 : 0;
@@ -263,15 +276,17 @@ __global__ __launch_bounds__(256) void k_pmis_update(const int *__restrict__ row
     atomicAdd(undecided, 1);
 }
 
-__global__ __launch_bounds__(256) void k_cf_flags(const int8_t *__restrict__ state, int nb, int *__restrict__ flags) {
+__global__ __launch_bounds__(256) void k_cf_flags(const int8_t *__restrict__ state, int nb, int8_t want,
+                                                 int *__restrict__ flags) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I < nb) flags[I] = (state[I] == kC) ? 1 : 0;
+    if (I < nb) flags[I] = (state[I] == want) ? 1 : 0;
 }
 
-// cscan[I] = number of C blocks before I.
-__global__ __launch_bounds__(256) void k_cf_index(const int8_t *__restrict__ cf, const int *__restrict__ cscan, int nb,
-                                                 int *__restrict__ cidx, int *__restrict__ cpts,
-                                                 int *__restrict__ flist) {
+// cscan[I] = number of C blocks before I; fscan[I] = number of F blocks before
+// I (fscan == nullptr: every non-C block is F).
+__global__ __launch_bounds__(256) void k_cf_index(const int8_t *__restrict__ cf, const int *__restrict__ cscan,
+                                                 const int *__restrict__ fscan, int nb, int *__restrict__ cidx,
+                                                 int *__restrict__ cpts, int *__restrict__ flist) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= nb) return;
     const int c = cscan[I];
@@ -280,8 +295,40 @@ __global__ __launch_bounds__(256) void k_cf_index(const int8_t *__restrict__ cf,
         cpts[c] = I;
     } else {
         cidx[I] = -1;
-        flist[I - c] = I;
+        if (cf[I] == kF) flist[fscan ? fscan[I] : I - c] = I;
     }
+}
+
+// Per block: first block of its system (lbase) and whether the system is
+// solved directly on this level (direct); seg holds nsys + 1 block offsets.
+__global__ __launch_bounds__(256) void k_seg_info(const int *__restrict__ seg, const int8_t *__restrict__ mode,
+                                                 int nsys, int nb, int *__restrict__ lbase,
+                                                 int8_t *__restrict__ direct, int *__restrict__ bsys) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nb) return;
+    int lo = 0, hi = nsys;   // the largest s < nsys with seg[s] <= I (skips empty systems)
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (seg[mid] <= I) lo = mid;
+        else hi = mid;
+    }
+    if (lbase) lbase[I] = seg[lo];
+    if (direct) direct[I] = mode[lo] == 2 ? 1 : 0;
+    if (bsys) bsys[I] = lo;
+}
+
+// Blocks of systems switched to a direct solve after their splitting stalled.
+__global__ __launch_bounds__(256) void k_mark_direct(const int8_t *__restrict__ direct, int nb,
+                                                    int8_t *__restrict__ state) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I < nb && direct[I]) state[I] = kD;
+}
+
+// out[i] = v[idx[i]] for i < n
+__global__ __launch_bounds__(256) void k_gather_int(const int *__restrict__ v, const int *__restrict__ idx, int n,
+                                                   int *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = v[idx[i]];
 }
 
 // ------------------------------------------------------ one-point interpolation
@@ -432,11 +479,11 @@ void launch_block_maxabs(const double *vals, int64_t nnzb, int bs, double *out, 
     NAIR_HIP(hipGetLastError());
 }
 
-void launch_block_inverse(const int *rowptr, const int *colidx, const double *vals, int nb, int bs, double *dinv,
-                          int *singular_min, hipStream_t s) {
+void launch_block_inverse(const int *rowptr, const int *colidx, const double *vals, int nb, int bs,
+                          const int8_t *skip, double *dinv, int *singular_min, hipStream_t s) {
     if (nb <= 0) return;
     const size_t lds = sizeof(double) * 2 * bs * bs + sizeof(int) * bs;
-    k_block_inverse<<<cap_grid(nb), 64, lds, s>>>(rowptr, colidx, vals, nb, bs, dinv, singular_min);
+    k_block_inverse<<<cap_grid(nb), 64, lds, s>>>(rowptr, colidx, vals, nb, bs, skip, dinv, singular_min);
     NAIR_HIP(hipGetLastError());
 }
 
@@ -452,28 +499,49 @@ void launch_strong_transpose(const int *rowptr, const int *colidx, const uint8_t
     NAIR_HIP(hipGetLastError());
 }
 
-void launch_pmis_init(const int *lambda, int nb, int8_t *state, int *dround, int *undecided0, hipStream_t s) {
-    k_pmis_init<<<grid_for(nb, 256), 256, 0, s>>>(lambda, nb, state, dround, undecided0);
+void launch_pmis_init(const int *lambda, const int8_t *direct, int nb, int8_t *state, int *dround, int *undecided0,
+                      hipStream_t s) {
+    k_pmis_init<<<grid_for(nb, 256), 256, 0, s>>>(lambda, direct, nb, state, dround, undecided0);
     NAIR_HIP(hipGetLastError());
 }
 
 void launch_pmis_round(const int *rowptr, const int *colidx, const uint8_t *mask, const int *stptr, const int *stidx,
-                       const int *lambda, int nb, uint64_t seed, int level, int round, int8_t *state, int8_t *newc,
-                       int *dround, int *undecided, hipStream_t s) {
-    k_pmis_select<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, mask, stptr, stidx, lambda, nb, seed, level,
-                                                    state, newc);
+                       const int *lambda, const int *lbase, int nb, uint64_t seed, int level, int round,
+                       int8_t *state, int8_t *newc, int *dround, int *undecided, hipStream_t s) {
+    k_pmis_select<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, mask, stptr, stidx, lambda, lbase, nb, seed,
+                                                    level, state, newc);
     k_pmis_update<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, mask, nb, round, state, newc, dround,
                                                     undecided);
     NAIR_HIP(hipGetLastError());
 }
 
-void launch_cf_flags(const int8_t *state, int nb, int *flags, hipStream_t s) {
-    k_cf_flags<<<grid_for(nb, 256), 256, 0, s>>>(state, nb, flags);
+void launch_cf_flags(const int8_t *state, int nb, int want, int *flags, hipStream_t s) {
+    k_cf_flags<<<grid_for(nb, 256), 256, 0, s>>>(state, nb, static_cast<int8_t>(want), flags);
     NAIR_HIP(hipGetLastError());
 }
 
-void launch_cf_index(const int8_t *cf, const int *cscan, int nb, int *cidx, int *cpts, int *flist, hipStream_t s) {
-    k_cf_index<<<grid_for(nb, 256), 256, 0, s>>>(cf, cscan, nb, cidx, cpts, flist);
+void launch_cf_index(const int8_t *cf, const int *cscan, const int *fscan, int nb, int *cidx, int *cpts, int *flist,
+                     hipStream_t s) {
+    k_cf_index<<<grid_for(nb, 256), 256, 0, s>>>(cf, cscan, fscan, nb, cidx, cpts, flist);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_seg_info(const int *seg, const int8_t *mode, int nsys, int nb, int *lbase, int8_t *direct, int *bsys,
+                     hipStream_t s) {
+    if (nb <= 0) return;
+    k_seg_info<<<grid_for(nb, 256), 256, 0, s>>>(seg, mode, nsys, nb, lbase, direct, bsys);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_mark_direct(const int8_t *direct, int nb, int8_t *state, hipStream_t s) {
+    if (nb <= 0) return;
+    k_mark_direct<<<grid_for(nb, 256), 256, 0, s>>>(direct, nb, state);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_gather_int(const int *v, const int *idx, int n, int *out, hipStream_t s) {
+    if (n <= 0) return;
+    k_gather_int<<<grid_for(n, 256), 256, 0, s>>>(v, idx, n, out);
     NAIR_HIP(hipGetLastError());
 }
 
@@ -541,15 +609,28 @@ namespace nair {
 namespace {
 
 // bad |= 1: rowptr not monotone/out of range; 2: column out of range;
-// 4: columns not strictly increasing; 8: missing diagonal block.
+// 4: columns not strictly increasing; 8: missing diagonal block; 16: a block
+// couples two systems (seg: nsys + 1 block offsets, or nullptr for one system).
 __global__ __launch_bounds__(256) void k_validate(const int *__restrict__ rowptr, const int *__restrict__ colidx, int nb,
-                                                 int64_t nnzb, int *__restrict__ bad) {
+                                                 int64_t nnzb, const int *__restrict__ seg, int nsys,
+                                                 int *__restrict__ bad) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= nb) return;
     const int lo = rowptr[I], hi = rowptr[I + 1];
     if ((I == 0 && lo != 0) || lo < 0 || hi < lo || hi > nnzb) {
         atomicOr(bad, 1);
         return;
+    }
+    int s_lo = 0, s_hi = nb;   // block range of I's system
+    if (seg) {
+        int a = 0, b = nsys;
+        while (b - a > 1) {
+            const int mid = (a + b) >> 1;
+            if (seg[mid] <= I) a = mid;
+            else b = mid;
+        }
+        s_lo = seg[a];
+        s_hi = seg[a + 1];
     }
     bool diag = false;
     for (int t = lo; t < hi; ++t) {
@@ -558,6 +639,7 @@ __global__ __launch_bounds__(256) void k_validate(const int *__restrict__ rowptr
             atomicOr(bad, 2);
             return;
         }
+        if (J < s_lo || J >= s_hi) atomicOr(bad, 16);
         if (t > lo && J <= colidx[t - 1]) atomicOr(bad, 4);
         if (J == I) diag = true;
     }
@@ -566,8 +648,9 @@ __global__ __launch_bounds__(256) void k_validate(const int *__restrict__ rowptr
 
 }  // namespace
 
-void launch_validate(const int *rowptr, const int *colidx, int nb, int64_t nnzb, int *bad, hipStream_t s) {
-    k_validate<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, nb, nnzb, bad);
+void launch_validate(const int *rowptr, const int *colidx, int nb, int64_t nnzb, const int *seg, int nsys, int *bad,
+                     hipStream_t s) {
+    k_validate<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, nb, nnzb, seg, nsys, bad);
     NAIR_HIP(hipGetLastError());
 }
 

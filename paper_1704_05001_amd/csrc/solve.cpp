@@ -7,7 +7,9 @@
 // an FP32-stored hierarchy.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <utility>
+#include <vector>
 
 #include "hier.h"
 
@@ -49,6 +51,15 @@ struct Store<float> {
     static float *tmp(Level &L) { return L.tmp32.get(); }
 };
 
+// Dense solves of the systems that end on level l: e = A_k^{-1} r (or A_k^{-T} r).
+template <typename T>
+void direct_solves(const Level &L, bool trans, const T *r, T *e, hipStream_t s) {
+    if (L.ndseg == 0) return;
+    TimerScope ts(TK_DENSE, g_timer_level, s);
+    launch_dense_matvec<T>(trans ? L.dense_invT.get() : L.dense_inv.get(), L.doff_d.get(), L.ddof0_d.get(),
+                           L.dn_d.get(), L.ndseg, L.dmax_n, r, e, s);
+}
+
 // V-cycle on level l with right-hand side r_l and zero initial guess, no
 // pre-relaxation (section 5): restrict, recurse, interpolate, nu = k+1 Jacobi
 // F sweeps (section 5.1), optionally one C sweep.  Returns the correction.
@@ -57,9 +68,9 @@ const T *vcycle(Hier &h, int l, hipStream_t s) {
     using S = Store<T>;
     Level &L = *h.lv[l];
     const int bs = h.bs;
+    g_timer_level = l;
     if (L.coarsest) {
-        TimerScope ts(TK_DENSE, l, s);
-        launch_dense_matvec<T>(L.dense_inv.get(), S::r(L), S::e0(L), L.dense_n, s);
+        direct_solves<T>(L, false, S::r(L), S::e0(L), s);
         return S::e0(L);
     }
     Level &C = *h.lv[l + 1];
@@ -86,6 +97,8 @@ const T *vcycle(Hier &h, int l, hipStream_t s) {
         launch_relax<T, T>(A, L.dinv.get(), false, S::r(L), cur, oth, nullptr, 0, L.cf.get(), 1, s);
         std::swap(cur, oth);
     }
+    g_timer_level = l;
+    direct_solves<T>(L, false, S::r(L), cur, s);   // systems that end on this level
     return cur;
 }
 
@@ -97,9 +110,9 @@ const T *vcycle_T(Hier &h, int l, hipStream_t s) {
     using S = Store<T>;
     Level &L = *h.lv[l];
     const int bs = h.bs;
+    g_timer_level = l;
     if (L.coarsest) {
-        TimerScope ts(TK_DENSE, l, s);
-        launch_dense_matvec<T>(L.dense_invT.get(), S::r(L), S::e0(L), L.dense_n, s);
+        direct_solves<T>(L, true, S::r(L), S::e0(L), s);
         return S::e0(L);
     }
     Level &C = *h.lv[l + 1];
@@ -117,6 +130,8 @@ const T *vcycle_T(Hier &h, int l, hipStream_t s) {
     launch_restrict_T<T>(L.ptptr.get(), L.ptidx.get(), S::tmp(L), S::r(C), L.nc, bs, s);
     const T *yc = vcycle_T<T>(h, l + 1, s);
     launch_interp_T<T, T>(S::ZT(L), L.cidx.get(), yc, cur, s);
+    g_timer_level = l;
+    direct_solves<T>(L, true, S::r(L), cur, s);   // systems that end on this level
     return cur;
 }
 
@@ -194,6 +209,213 @@ nair_status run_solve(Hier &h, bool trans, const double *b, double *x, double rt
     if (res) *res = rr;
     NAIR_HIP(hipStreamSynchronize(s));
     return st;
+}
+
+namespace {
+
+constexpr int kChunk = 4096;        // dofs per norm chunk
+constexpr int kFirstPoll = 4;       // iterations before the first host check
+constexpr int kMaxRun = 64;         // most iterations launched between checks
+
+// Chunk tables, per-system state and history storage of the batched iteration.
+void ensure_batch(Hier &h, int max_iter, hipStream_t s) {
+    BatchSolve &B = h.batch;
+    Level &L0 = *h.lv[0];
+    const int nsys = h.nsys;
+    if (!B.ready) {
+        std::vector<int64_t> clo;
+        std::vector<int> clen, cptr(nsys + 1, 0);
+        for (int k = 0; k < nsys; ++k) {
+            const int64_t d0 = static_cast<int64_t>(L0.seg[k]) * h.bs, d1 = static_cast<int64_t>(L0.seg[k + 1]) * h.bs;
+            for (int64_t d = d0; d < d1; d += kChunk) {
+                clo.push_back(d);
+                clen.push_back(static_cast<int>(std::min<int64_t>(kChunk, d1 - d)));
+            }
+            cptr[k + 1] = static_cast<int>(clo.size());
+        }
+        B.nchunk = static_cast<int>(clo.size());
+        const int nch = std::max(B.nchunk, 1);
+        B.clo.alloc(nch);
+        B.clen.alloc(nch);
+        B.cptr.alloc(nsys + 1);
+        B.part.alloc(nch);
+        if (B.nchunk > 0) {
+            NAIR_HIP(hipMemcpyAsync(B.clo.get(), clo.data(), sizeof(int64_t) * B.nchunk, hipMemcpyHostToDevice, s));
+            NAIR_HIP(hipMemcpyAsync(B.clen.get(), clen.data(), sizeof(int) * B.nchunk, hipMemcpyHostToDevice, s));
+        }
+        NAIR_HIP(hipMemcpyAsync(B.cptr.get(), cptr.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice, s));
+        if (nsys > 1) {
+            B.bsys.alloc(L0.A.nb);
+            launch_seg_info(L0.seg_d.get(), L0.mode_d.get(), nsys, L0.A.nb, nullptr, nullptr, B.bsys.get(), s);
+        }
+        B.bn.alloc(nsys);
+        B.last.alloc(nsys);
+        B.rtol.alloc(1);
+        B.active.alloc(nsys);
+        B.status.alloc(nsys);
+        B.iters.alloc(nsys);
+        B.it.alloc(1);
+        B.nact.alloc(1);
+        NAIR_HIP(hipStreamSynchronize(s));   // the host tables end here
+        B.ready = true;
+    }
+    if (B.hist_cap < max_iter) {
+        B.hist.alloc(static_cast<size_t>(nsys) * max_iter);
+        B.hist_cap = max_iter;
+        for (auto &ex : B.exec)   // captured iterations write the old history buffer
+            if (ex) {
+                (void)hipGraphExecDestroy(ex);
+                ex = nullptr;
+            }
+    }
+}
+
+// One iteration of every system: x += B r on the active systems, r = b - A x,
+// per-system norms and convergence.  Launch-only (capturable).
+template <typename T>
+void batch_iteration(Hier &h, bool trans, const double *b, double *x, hipStream_t s) {
+    BatchSolve &B = h.batch;
+    Level &L0 = *h.lv[0];
+    const int64_t n = static_cast<int64_t>(L0.A.nb) * h.bs;
+    const bool fp32 = std::is_same<T, float>::value;
+    const T *e = trans ? vcycle_T<T>(h, 0, s) : vcycle<T>(h, 0, s);
+    launch_axpy_active<T>(x, e, n, h.bs, B.bsys.get(), B.active.get(), s);
+    const MatView<double> Aop = trans ? view(L0.AT) : view(L0.A);
+    {
+        TimerScope ts(TK_RESIDUAL, 0, s);
+        launch_residual<double, double>(Aop, b, x, L0.r.get(), nullptr, fp32 ? L0.r32.get() : nullptr, s);
+    }
+    launch_seg_sumsq(L0.r.get(), B.clo.get(), B.clen.get(), B.nchunk, B.part.get(), s);
+    launch_seg_check(B.part.get(), B.cptr.get(), h.nsys, B.bn.get(), B.rtol.get(), B.hist_cap, B.hist.get(),
+                     B.last.get(), B.active.get(), B.status.get(), B.iters.get(), B.it.get(), B.nact.get(), s);
+}
+
+void run_iteration(Hier &h, bool trans, const double *b, double *x, hipStream_t s) {
+    if (h.prm.precision == 1) batch_iteration<float>(h, trans, b, x, s);
+    else batch_iteration<double>(h, trans, b, x, s);
+}
+
+// The iteration captured once into a graph for these operands, replayed per step.
+hipGraphExec_t batch_graph(Hier &h, bool trans, const double *b, double *x) {
+    BatchSolve &B = h.batch;
+    const int slot = trans ? 1 : 0;
+    if (B.exec[slot] && B.key_b[slot] == b && B.key_x[slot] == x) return B.exec[slot];
+    if (B.exec[slot]) {
+        NAIR_HIP(hipGraphExecDestroy(B.exec[slot]));
+        B.exec[slot] = nullptr;
+    }
+    if (!B.cap) NAIR_HIP(hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking));
+    NAIR_HIP(hipStreamBeginCapture(B.cap, hipStreamCaptureModeThreadLocal));
+    g_capturing = true;
+    try {
+        run_iteration(h, trans, b, x, B.cap);
+    } catch (...) {
+        g_capturing = false;
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(B.cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    g_capturing = false;
+    hipGraph_t g = nullptr;
+    NAIR_HIP(hipStreamEndCapture(B.cap, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t st = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    NAIR_HIP(st);
+    B.exec[slot] = ex;
+    B.key_b[slot] = b;
+    B.key_x[slot] = x;
+    return ex;
+}
+
+}  // namespace
+
+BatchSolve::~BatchSolve() {
+    for (auto ex : exec)
+        if (ex) (void)hipGraphExecDestroy(ex);
+    if (cap) (void)hipStreamDestroy(cap);
+}
+
+nair_status run_solve_batch(Hier &h, bool trans, const double *b, double *x, double rtol, int max_iter,
+                            bool use_graph, nair_result *res, hipStream_t s) {
+    Level &L0 = *h.lv[0];
+    BatchSolve &B = h.batch;
+    const int nsys = h.nsys;
+    const int64_t n = static_cast<int64_t>(L0.A.nb) * h.bs;
+    const bool fp32 = h.prm.precision == 1;
+    if (trans) ensure_transposes(h, s);
+    ensure_work(h);
+    ensure_batch(h, max_iter, s);
+    B.rtol_host = rtol;
+    NAIR_HIP(hipMemcpyAsync(B.rtol.get(), &B.rtol_host, sizeof(double), hipMemcpyHostToDevice, s));
+    NAIR_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+    launch_seg_sumsq(b, B.clo.get(), B.clen.get(), B.nchunk, B.part.get(), s);
+    launch_seg_init(B.part.get(), B.cptr.get(), nsys, B.bn.get(), B.last.get(), B.active.get(), B.status.get(),
+                    B.iters.get(), B.it.get(), B.nact.get(), s);
+    NAIR_HIP(hipMemcpyAsync(L0.r.get(), b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    if (fp32) launch_to_float(b, L0.r32.get(), n, s);
+    hipGraphExec_t ex = use_graph ? batch_graph(h, trans, b, x) : nullptr;
+
+    std::vector<double> last(nsys), prev(nsys, 1.0);
+    int done = 0;        // iterations launched
+    int run = std::min(kFirstPoll, max_iter);
+    int nact = read_int(B.nact.get(), s);
+    while (nact > 0 && done < max_iter) {
+        for (int i = 0; i < run; ++i) {
+            if (ex) NAIR_HIP(hipGraphLaunch(ex, s));
+            else run_iteration(h, trans, b, x, s);
+        }
+        done += run;
+        NAIR_HIP(hipMemcpyAsync(last.data(), B.last.get(), sizeof(double) * nsys, hipMemcpyDeviceToHost, s));
+        nact = read_int(B.nact.get(), s);
+        if (nact == 0 || done >= max_iter) break;
+        // iterations still needed by the slowest system, from its rate over the last run
+        double need = 1.0;
+        for (int k = 0; k < nsys; ++k) {
+            if (!(last[k] > rtol)) continue;
+            const double rho = std::pow(last[k] / prev[k], 1.0 / run);
+            const double nk = (rho > 0.0 && rho < 1.0) ? std::log(rtol / last[k]) / std::log(rho) : run;
+            need = std::max(need, nk);
+        }
+        prev = last;
+        run = static_cast<int>(std::min<double>(std::ceil(need), std::min(kMaxRun, max_iter - done)));
+        run = std::max(run, 1);
+    }
+
+    std::vector<int> st(nsys), it(nsys);
+    read_ints(B.status.get(), st.data(), nsys, s);
+    read_ints(B.iters.get(), it.data(), nsys, s);
+    int itmax = 0;
+    for (int k = 0; k < nsys; ++k) itmax = std::max(itmax, it[k]);
+    std::vector<double> hist(static_cast<size_t>(nsys) * B.hist_cap);
+    if (itmax > 0) {
+        NAIR_HIP(hipMemcpyAsync(hist.data(), B.hist.get(), sizeof(double) * hist.size(), hipMemcpyDeviceToHost, s));
+        NAIR_HIP(hipStreamSynchronize(s));
+    }
+    B.hist_host.assign(nsys, {});
+    nair_status worst = NAIR_OK;
+    for (int k = 0; k < nsys; ++k) {
+        auto &hk = B.hist_host[k];
+        hk.assign(hist.begin() + static_cast<size_t>(k) * B.hist_cap,
+                  hist.begin() + static_cast<size_t>(k) * B.hist_cap + std::min(it[k], B.hist_cap));
+        nair_result rr{0, 0, 0.0, 0.0, 0.0};
+        rr.iters = static_cast<int32_t>(hk.size());
+        rr.converged = st[k] == 0 ? 1 : 0;
+        rr.relres = hk.empty() ? 0.0 : hk.back();
+        if (rr.iters > 0) {
+            const double hK = hk.back();
+            rr.rho_avg = std::pow(hK, 1.0 / rr.iters);
+            rr.rho_last5 = rr.iters > 5 ? std::pow(hK / hk[rr.iters - 6], 0.2) : rr.rho_avg;
+        }
+        if (res) res[k] = rr;
+        const nair_status sk = static_cast<nair_status>(st[k]);
+        if (sk == NAIR_ENUMERIC) worst = NAIR_ENUMERIC;
+        else if (sk == NAIR_ENOCONV && worst == NAIR_OK) worst = NAIR_ENOCONV;
+    }
+    h.hist = B.hist_host.empty() ? std::vector<double>() : B.hist_host[0];
+    NAIR_HIP(hipStreamSynchronize(s));
+    return worst;
 }
 
 void run_vcycle(Hier &h, bool trans, const double *r, double *e, hipStream_t s) {

@@ -22,7 +22,8 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ESINGULAR", 3: "ENOCONV", 4: "ENUMERIC", 5: 
 
 EXPORTED = ["nair_default_params", "nair_setup", "nair_solve", "nair_solve_T", "nair_vcycle",
             "nair_vcycle_T", "nair_history", "nair_info", "nair_get_level", "nair_last_error",
-            "nair_destroy", "nair_pool_trim", "nair_timer_select", "nair_timer_read", "nair_grad_vals"]
+            "nair_destroy", "nair_pool_trim", "nair_timer_select", "nair_timer_read", "nair_grad_vals",
+            "nair_setup_batch", "nair_solve_batch", "nair_batch_history", "nair_get_systems"]
 
 KERNELS = {"relax": 0, "residual": 1, "restrict": 2, "interp": 3, "spgemm_numeric": 4,
            "spgemm_symbolic": 5, "block_inverse": 6, "galerkin": 7, "dense": 8}
@@ -98,6 +99,14 @@ def lib():
         L.nair_timer_read.restype = C.c_int
         L.nair_grad_vals.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
         L.nair_grad_vals.restype = C.c_int
+        L.nair_setup_batch.argtypes = [i32, vp, i32, vp, vp, vp, C.POINTER(_Params), vp, C.POINTER(vp)]
+        L.nair_setup_batch.restype = C.c_int
+        L.nair_solve_batch.argtypes = [vp, i32, vp, vp, dbl, i32, i32, vp, vp]
+        L.nair_solve_batch.restype = C.c_int
+        L.nair_batch_history.argtypes = [vp, i32, vp, i32, C.POINTER(i32)]
+        L.nair_batch_history.restype = C.c_int
+        L.nair_get_systems.argtypes = [vp, i32, i32, C.POINTER(i32), vp, vp, vp]
+        L.nair_get_systems.restype = C.c_int
         _lib = L
     return _lib
 
@@ -156,9 +165,12 @@ class Result:
 
 class Hierarchy:
     """nAIR hierarchy on the GPU.  rowptr/colidx (int32) and vals (float64,
-    [nnzb, bs, bs]) are torch tensors on the current HIP device."""
+    [nnzb, bs, bs]) are torch tensors on the current HIP device.  With
+    `sys_nb` (block rows per system) the matrix holds independent systems one
+    after another and one batched hierarchy is built for all of them."""
 
-    def __init__(self, rowptr, colidx, vals, bs: int, params: Params | None = None, stream=None):
+    def __init__(self, rowptr, colidx, vals, bs: int, params: Params | None = None, stream=None,
+                 sys_nb=None):
         import torch
         params = params or Params()
         L = lib()
@@ -182,10 +194,23 @@ class Hierarchy:
             cf = np.ascontiguousarray(params.cf_override, dtype=np.int8)
             p.cf_override_host = cf.ctypes.data
         h = C.c_void_p()
-        st = L.nair_setup(self.nb, self.bs, C.c_void_p(rowptr.data_ptr()), C.c_void_p(colidx.data_ptr()),
-                          C.c_void_p(vals.data_ptr()), C.byref(p), _stream_ptr(stream), C.byref(h))
+        if sys_nb is None:
+            self.nsys = 1
+            self.sys_nb = np.array([self.nb], dtype=np.int32)
+            st = L.nair_setup(self.nb, self.bs, C.c_void_p(rowptr.data_ptr()), C.c_void_p(colidx.data_ptr()),
+                              C.c_void_p(vals.data_ptr()), C.byref(p), _stream_ptr(stream), C.byref(h))
+            where = "nair_setup"
+        else:
+            self.sys_nb = np.ascontiguousarray(sys_nb, dtype=np.int32)
+            self.nsys = int(self.sys_nb.size)
+            if int(self.sys_nb.sum()) != self.nb:
+                raise ValueError("sys_nb must add up to the number of block rows")
+            st = L.nair_setup_batch(self.nsys, self.sys_nb.ctypes.data_as(C.c_void_p), self.bs,
+                                    C.c_void_p(rowptr.data_ptr()), C.c_void_p(colidx.data_ptr()),
+                                    C.c_void_p(vals.data_ptr()), C.byref(p), _stream_ptr(stream), C.byref(h))
+            where = "nair_setup_batch"
         if st != 0:
-            raise NairError(st, "nair_setup", L.nair_last_error(None).decode())
+            raise NairError(st, where, L.nair_last_error(None).decode())
         self._h = h
 
     def close(self):
@@ -228,6 +253,54 @@ class Hierarchy:
                 raise_on=("EINVAL", "EDEVICE", "ENOMEM")):
         """y = A^{-T} g by transposed nAIR V-cycles.  Returns (y, Result)."""
         return self._solve(lib().nair_solve_T, "nair_solve_T", g, y, rtol, max_iter, stream, raise_on)
+
+    def solve_batch(self, b, x=None, rtol=1e-10, max_iter=200, trans=False, graph=True, stream=None,
+                    raise_on=("EINVAL", "EDEVICE", "ENOMEM")):
+        """Every system to its own relative residual (A x = b, or A^T x = b with
+        trans), one graph-captured iteration replayed.  Returns (x, [Result per system])."""
+        import torch
+        if x is None:
+            x = torch.empty_like(b)
+        res = (_Result * self.nsys)()
+        st = lib().nair_solve_batch(self._h, 1 if trans else 0, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                    float(rtol), int(max_iter), 1 if graph else 0, C.cast(res, C.c_void_p),
+                                    _stream_ptr(stream))
+        status = STATUS.get(st, str(st))
+        if st != 0 and status in raise_on:
+            raise NairError(st, "nair_solve_batch", self._err())
+        out = []
+        for r in res:
+            if r.converged:
+                s_k = "OK"
+            elif r.iters == 0 or not np.isfinite(r.relres):   # non-finite ||b|| or residual
+                s_k = "ENUMERIC"
+            else:
+                s_k = "ENOCONV"
+            out.append(Result(s_k, r.iters, bool(r.converged), r.relres, r.rho_avg, r.rho_last5))
+        return x, out
+
+    def batch_history(self, sys: int):
+        n = C.c_int32()
+        st = lib().nair_batch_history(self._h, int(sys), None, 0, C.byref(n))
+        if st != 0:
+            raise NairError(st, "nair_batch_history", self._err())
+        buf = np.zeros(max(1, n.value))
+        lib().nair_batch_history(self._h, int(sys), buf.ctypes.data_as(C.c_void_p), n.value, C.byref(n))
+        return buf[:n.value].copy()
+
+    def systems(self, l: int) -> dict:
+        """Block offsets (seg), modes (0 none left, 1 coarsened, 2 direct) and
+        dense-inverse offsets (-1 unless direct) of the systems on level l."""
+        ns = self.nsys
+        seg = np.zeros(ns + 1, dtype=np.int32)
+        mode = np.zeros(ns, dtype=np.int8)
+        off = np.zeros(ns, dtype=np.int64)
+        n = C.c_int32()
+        st = lib().nair_get_systems(self._h, int(l), ns, C.byref(n), seg.ctypes.data_as(C.c_void_p),
+                                    mode.ctypes.data_as(C.c_void_p), off.ctypes.data_as(C.c_void_p))
+        if st != 0:
+            raise NairError(st, "nair_get_systems", self._err())
+        return dict(seg=seg, mode=mode, dense_off=off)
 
     def vcycle(self, r, stream=None):
         import torch
@@ -298,9 +371,14 @@ class Hierarchy:
                      ("z_rowptr", v.z_rowptr, torch.int32, v.nc + 1, None),
                      ("z_colidx", v.z_colidx, torch.int32, v.z_nnzb, None),
                      ("z_vals", v.z_vals, torch.float64, v.z_nnzb * bb, (v.z_nnzb, bs, bs))]
-        if v.dense_inv:
+        if v.dense_inv and v.dense_n > 0:
             n = v.dense_n
             spec += [("dense_inv", v.dense_inv, torch.float64, n * n, (n, n))]
+        elif v.dense_inv:   # several systems solved directly on this level: packed inverses
+            sy = self.systems(l)
+            d = [(int(o), int(sy["seg"][k + 1] - sy["seg"][k]) * bs) for k, o in enumerate(sy["dense_off"]) if o >= 0]
+            total = max(o + m * m for o, m in d)
+            spec += [("dense_inv", v.dense_inv, torch.float64, total, None)]
         for name, ptr, dt, cnt, shape in spec:
             if want(name):
                 t = _dcopy(ptr, dt, cnt, dev)
