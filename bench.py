@@ -11,7 +11,10 @@ transposed solve is timed in the same steps and reported beside it, and
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
 Prints one JSON line.  The CPU-baseline leg times the plain CPU oracle (one
-thread) on the same workload.
+thread) on the same workload.  The batched leg ("batched") sets up and solves
+64 discrete-ordinate systems on uneven meshes (17.7M DOFs) as one batched
+hierarchy with a graph-replayed iteration, with the FP32-stored and the FP64
+hierarchy, beside the same systems set up and solved one after another.
 """
 from __future__ import annotations
 
@@ -65,6 +68,93 @@ def relax_level_bytes(lv: dict) -> dict:
                 bytes_true_blocks=bytes_A + bytes_D)
 
 
+def batched_leg(args, P, torch, np):
+    """Many discrete-ordinate systems in one hierarchy and one graph-replayed
+    solve, FP32-stored and FP64, against the same systems set up and solved
+    one after another."""
+    from nair_inputs import make_batch, concat_systems
+    t0 = time.time()
+    workers = max(1, min(16, os.cpu_count() or 1))
+    systems, degree = make_batch(args.batch_workload, workers=workers, check_acyclic=False)
+    rp, ci, va, rhs, sys_nb = concat_systems(systems)
+    ndof = int(rhs.size)
+    log(f"batch {args.batch_workload}: {len(systems)} systems, {ndof} DOFs, nnzb {ci.size} "
+        f"({time.time() - t0:.1f}s to generate)")
+    dev = torch.device("cuda", 0)
+    d_rp, d_ci, d_va = (torch.from_numpy(a).to(dev) for a in (rp, ci, va))
+    d_b = torch.from_numpy(rhs).to(dev)
+    x = torch.empty_like(d_b)
+    stream = torch.cuda.current_stream()
+    res = {"workload": args.batch_workload, "systems": len(systems), "dofs": ndof, "nnzb": int(ci.size),
+           "meshes": sorted({int(S.N) for S in systems}), "steps": args.batch_steps,
+           "step": "one batched setup + one batched solve of every system to 1e-10; value = dofs / (setup + solve)"}
+
+    def run(prec, graph):
+        prm = P.Params(degree=degree, precision=prec)
+        times, iters = [], None
+        for i in range(1 + args.batch_steps):        # first step untimed (warm-up)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record(stream)
+            H = P.Hierarchy(d_rp, d_ci, d_va, 9, prm, sys_nb=sys_nb)
+            ev[1].record(stream)
+            _, rr = H.solve_batch(d_b, x=x, rtol=args.rtol, graph=graph)
+            ev[2].record(stream)
+            torch.cuda.synchronize()
+            if any(r.status != "OK" for r in rr):
+                raise RuntimeError(f"batched solve: {[r.status for r in rr if r.status != 'OK'][:3]}")
+            if i > 0:
+                times.append((ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])))
+            iters = [r.iters for r in rr]
+            levels = H.info()["levels"]
+            H.close()
+        st = float(np.mean([t[0] for t in times]))
+        sv = float(np.mean([t[1] for t in times]))
+        return {"value": round(ndof / ((st + sv) * 1e-3), 1), "unit": "DOFs/s", "setup_ms": round(st, 3),
+                "solve_ms": round(sv, 3), "iters_min": min(iters), "iters_max": max(iters), "levels": levels}
+
+    res["fp32_hier_graph"] = run("fp32", True)
+    x32 = x.clone()
+    res["fp64_graph"] = run("fp64", True)
+    res["fp64_eager"] = run("fp64", False)
+    res["fp32_hier_max_rel_diff_vs_fp64"] = float((x32 - x).abs().max() / x.abs().max())
+    log(f"batched: fp32 graph {res['fp32_hier_graph']['value']:.0f}, fp64 graph {res['fp64_graph']['value']:.0f}, "
+        f"fp64 eager {res['fp64_eager']['value']:.0f} DOFs/s")
+
+    # the same systems one after another: setup + solve each with the plain entry points
+    prm = P.Params(degree=degree)
+    per = []
+    offs = np.concatenate(([0], np.cumsum([S.nnzb for S in systems])))
+    boff = np.concatenate(([0], np.cumsum(sys_nb)))
+    subs = []
+    for k, S in enumerate(systems):
+        subs.append((torch.from_numpy(S.rowptr).to(dev), torch.from_numpy(S.colidx).to(dev),
+                     d_va[offs[k]:offs[k + 1]], d_b[boff[k] * 9:boff[k + 1] * 9], x[boff[k] * 9:boff[k + 1] * 9]))
+    for i in range(1 + args.batch_steps):
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for (srp, sci, sva, sb, sx) in subs:
+            H = P.Hierarchy(srp, sci, sva, 9, prm)
+            _, r = H.solve(sb, x=sx, rtol=args.rtol)
+            if r.status != "OK":
+                raise RuntimeError(f"sequential solve {r.status}")
+            H.close()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        if i > 0:
+            per.append(ev[0].elapsed_time(ev[1]))
+    seq_ms = float(np.mean(per))
+    res["fp64_sequential"] = {"value": round(ndof / (seq_ms * 1e-3), 1), "unit": "DOFs/s", "ms": round(seq_ms, 3),
+                              "what": "nair_setup + nair_solve per system, one after another"}
+    res["speedup_fp32_graph_vs_fp64_sequential"] = round(res["fp32_hier_graph"]["value"] /
+                                                         res["fp64_sequential"]["value"], 3)
+    res["speedup_fp32_graph_vs_fp64_graph"] = round(res["fp32_hier_graph"]["value"] / res["fp64_graph"]["value"], 3)
+    del d_rp, d_ci, d_va, d_b, x, subs
+    torch.cuda.empty_cache()
+    P.pool_trim()
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +167,9 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-hierarchy leg")
     ap.add_argument("--cpu-sample", default="full", help="'full' or a mesh size N for the oracle sample")
+    ap.add_argument("--batch-workload", default="dg_q2_angles64_uneven")
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-angles leg")
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -213,6 +306,9 @@ def main(argv=None):
                             "max_rel_diff_x_vs_fp64": err_x, "max_rel_diff_y_vs_fp64": err_y,
                             "speedup_vs_fp64": round((setup_ms + solve_ms) / (s32 + v32), 3)}
         log(f"fp32 hierarchy: {out['fp32_hier']['value']:.0f} DOFs/s, {out['fp32_hier']['iters']} iterations")
+
+    if not args.no_batch:
+        out["batched"] = batched_leg(args, P, torch, np)
 
     if not args.no_cpu_baseline:
         import oracle

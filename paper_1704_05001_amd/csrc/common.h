@@ -198,36 +198,49 @@ inline MatView<float> view(const DevBSR &A, const float *vals32) {
     return MatView<float>{A.nb, A.ncols, A.bs, A.nnzb, A.rowptr.get(), A.colidx.get(), vals32};
 }
 
+// Rows of systems that have stopped iterating are skipped in batched solves:
+// row r is live when active == nullptr or active[bsys ? bsys[r] : 0] != 0.
+struct Gate {
+    const int *bsys = nullptr;
+    const int *active = nullptr;
+};
+__device__ inline bool live(const Gate &g, int row) {
+    return g.active == nullptr || g.active[g.bsys ? g.bsys[row] : 0] != 0;
+}
+
 template <typename MT>
 int residual_partials_count(const MatView<MT> &A);
 // r = b - A x (+ squared-norm partials per workgroup if partials, + float copy if r_lo)
 template <typename MT, typename VT>
 void launch_residual(const MatView<MT> &A, const VT *b, const VT *x, VT *r, double *partials, float *r_lo,
-                     hipStream_t s);
+                     hipStream_t s, Gate g = Gate());
 void launch_sumsq(const double *v, int64_t n, double *partials, hipStream_t s);
 int sumsq_partials_count(int64_t n);
 void launch_reduce_partials(const double *partials, int npart, double *out, hipStream_t s);
 // Jacobi sweep over `list` rows (list == nullptr: all rows; then rows with cf != only_cf are copied)
 template <typename MT, typename VT>
 void launch_relax(const MatView<MT> &A, const double *dinv, bool dinv_trans, const VT *r, const VT *ein, VT *eout,
-                  const int *list, int nlist, const int8_t *cf, int only_cf, hipStream_t s);
+                  const int *list, int nlist, const int8_t *cf, int only_cf, hipStream_t s, Gate g = Gate());
+// gate of the coarse rows (coarse-level system ids)
 template <typename MT, typename VT>
-void launch_restrict(const MatView<MT> &Z, const VT *r, const int *cpts, VT *rc, hipStream_t s);
+void launch_restrict(const MatView<MT> &Z, const VT *r, const int *cpts, VT *rc, hipStream_t s, Gate g = Gate());
 template <typename VT>
-void launch_interp(const int *pmap, const VT *ec, VT *e0, VT *e1, int nb, int bs, hipStream_t s);
+void launch_interp(const int *pmap, const VT *ec, VT *e0, VT *e1, int nb, int bs, hipStream_t s, Gate g = Gate());
 template <typename VT>
-void launch_restrict_T(const int *ptptr, const int *ptidx, const VT *s, VT *sc, int nc, int bs, hipStream_t st);
+void launch_restrict_T(const int *ptptr, const int *ptidx, const VT *s, VT *sc, int nc, int bs, hipStream_t st,
+                       Gate g = Gate());
 template <typename MT, typename VT>
-void launch_interp_T(const MatView<MT> &ZT, const int *cidx, const VT *yc, VT *y, hipStream_t s);
+void launch_interp_T(const MatView<MT> &ZT, const int *cidx, const VT *yc, VT *y, hipStream_t s, Gate g = Gate());
 template <typename VT>
 void launch_init_T(const double *dinv, const VT *g, const int8_t *cf, int fc, VT *y0, VT *y1, int nb, int bs,
-                   hipStream_t s);
+                   hipStream_t s, Gate gate = Gate());
 template <typename VT>
 void launch_axpy(double *x, const VT *e, int64_t n, hipStream_t s);
-// y_k = M_k x_k for nseg dense segments: M_k at M + off[k], order n[k], vectors at dof0[k]
+// y_k = M_k x_k for nseg dense segments: M_k at M + off[k], order n[k], vectors at dof0[k];
+// segments of stopped systems (active[sys[k]] == 0; active nullable) are skipped
 template <typename VT>
 void launch_dense_matvec(const double *M, const int64_t *off, const int *dof0, const int *n, int nseg, int max_n,
-                         const VT *x, VT *y, hipStream_t s);
+                         const VT *x, VT *y, hipStream_t s, const int *sys = nullptr, const int *active = nullptr);
 // x += e on the dofs of systems still iterating (active[bsys[block]]; bsys == nullptr: system 0)
 template <typename VT>
 void launch_axpy_active(double *x, const VT *e, int64_t n, int bs, const int *bsys, const int *active,

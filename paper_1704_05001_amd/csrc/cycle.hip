@@ -101,13 +101,13 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int *__restrict__ r
                                                       const MT *__restrict__ vals, int nb, int bs_rt, int G,
                                                       const VT *__restrict__ b, const VT *__restrict__ x,
                                                       VT *__restrict__ r, double *__restrict__ partials,
-                                                      float *__restrict__ r_lo) {
+                                                      float *__restrict__ r_lo, Gate gate) {
     __shared__ double part[kThreads];
     __shared__ double red[kThreads / 64];
     const int bs = Bs<BS>::get(bs_rt);
     const Lane L = lane_of(G, bs);
     const int I = blockIdx.x * (kThreads / (G * bs)) + L.lr;
-    const bool act = L.valid && I < nb;
+    const bool act = L.valid && I < nb && live(gate, I);
     double acc = act ? row_part<BS>(colidx, vals, rowptr[I], rowptr[I + 1], L.g, G, L.a, bs, x) : 0.0;
     acc = reduce_groups(acc, L, G, bs, part);
     double v = 0.0;
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kThreads) void k_relax(const int *__restrict__ rowp
                                                    int dinv_trans, int nb, int bs_rt, int G,
                                                    const VT *__restrict__ r, const VT *__restrict__ ein,
                                                    VT *__restrict__ eout, const int *__restrict__ list, int nlist,
-                                                   const int8_t *__restrict__ cf, int only_cf) {
+                                                   const int8_t *__restrict__ cf, int only_cf, Gate gate) {
     __shared__ double part[kThreads];
     __shared__ double tb[kThreads];
     const int bs = Bs<BS>::get(bs_rt);
@@ -141,6 +141,7 @@ __global__ __launch_bounds__(kThreads) void k_relax(const int *__restrict__ rowp
     const int N = list ? nlist : nb;
     int I = -1;
     if (L.valid && idx < N) I = list ? list[idx] : idx;
+    if (I >= 0 && !live(gate, I)) I = -1;   // a stopped system: nothing to do
     const bool upd = I >= 0 && (list != nullptr || cf[I] == only_cf);
     double acc = upd ? row_part<BS>(colidx, vals, rowptr[I], rowptr[I + 1], L.g, G, L.a, bs, ein) : 0.0;
     acc = reduce_groups(acc, L, G, bs, part);
@@ -179,12 +180,12 @@ template <int BS, typename MT, typename VT>
 __global__ __launch_bounds__(kThreads) void k_restrict(const int *__restrict__ zrp, const int *__restrict__ zcol,
                                                       const MT *__restrict__ zval, int nc, int bs_rt, int G,
                                                       const VT *__restrict__ r, const int *__restrict__ cpts,
-                                                      VT *__restrict__ rc) {
+                                                      VT *__restrict__ rc, Gate gate) {
     __shared__ double part[kThreads];
     const int bs = Bs<BS>::get(bs_rt);
     const Lane L = lane_of(G, bs);
     const int i = blockIdx.x * (kThreads / (G * bs)) + L.lr;
-    const bool act = L.valid && i < nc;
+    const bool act = L.valid && i < nc && live(gate, i);
     double acc = act ? row_part<BS>(zcol, zval, zrp[i], zrp[i + 1], L.g, G, L.a, bs, r) : 0.0;
     acc = reduce_groups(acc, L, G, bs, part);
     if (act && L.g == 0)
@@ -197,12 +198,12 @@ template <int BS, typename MT, typename VT>
 __global__ __launch_bounds__(kThreads) void k_interp_T(const int *__restrict__ ztrp, const int *__restrict__ ztcol,
                                                       const MT *__restrict__ ztval, int nb, int bs_rt, int G,
                                                       const int *__restrict__ cidx, const VT *__restrict__ yc,
-                                                      VT *__restrict__ y) {
+                                                      VT *__restrict__ y, Gate gate) {
     __shared__ double part[kThreads];
     const int bs = Bs<BS>::get(bs_rt);
     const Lane L = lane_of(G, bs);
     const int I = blockIdx.x * (kThreads / (G * bs)) + L.lr;
-    const bool act = L.valid && I < nb;
+    const bool act = L.valid && I < nb && live(gate, I);
     double acc = act ? row_part<BS>(ztcol, ztval, ztrp[I], ztrp[I + 1], L.g, G, L.a, bs, yc) : 0.0;
     acc = reduce_groups(acc, L, G, bs, part);
     if (act && L.g == 0) {
@@ -233,10 +234,12 @@ __global__ __launch_bounds__(1024) void k_reduce_partials(const double *__restri
 
 template <typename VT>
 __global__ __launch_bounds__(kThreads) void k_interp(const int *__restrict__ pmap, const VT *__restrict__ ec,
-                                                    VT *__restrict__ e0, VT *__restrict__ e1, int nb, int bs) {
+                                                    VT *__restrict__ e0, VT *__restrict__ e1, int nb, int bs,
+                                                    Gate gate) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
     if (g >= static_cast<int64_t>(nb) * bs) return;
     const int I = static_cast<int>(g / bs);
+    if (!live(gate, I)) return;
     const int a = static_cast<int>(g - static_cast<int64_t>(I) * bs);
     const int p = pmap[I];
     const VT v = (p >= 0) ? ec[static_cast<int64_t>(p) * bs + a] : VT(0);
@@ -248,10 +251,11 @@ __global__ __launch_bounds__(kThreads) void k_interp(const int *__restrict__ pma
 template <typename VT>
 __global__ __launch_bounds__(kThreads) void k_restrict_T(const int *__restrict__ ptptr, const int *__restrict__ ptidx,
                                                         const VT *__restrict__ s, VT *__restrict__ sc, int nc,
-                                                        int bs) {
+                                                        int bs, Gate gate) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
     if (g >= static_cast<int64_t>(nc) * bs) return;
     const int j = static_cast<int>(g / bs);
+    if (!live(gate, j)) return;
     const int a = static_cast<int>(g - static_cast<int64_t>(j) * bs);
     double acc = 0.0;
     for (int t = ptptr[j]; t < ptptr[j + 1]; ++t) acc += static_cast<double>(s[static_cast<int64_t>(ptidx[t]) * bs + a]);
@@ -262,10 +266,11 @@ __global__ __launch_bounds__(kThreads) void k_restrict_T(const int *__restrict__
 template <typename VT>
 __global__ __launch_bounds__(kThreads) void k_init_T(const double *__restrict__ dinv, const VT *__restrict__ g,
                                                     const int8_t *__restrict__ cf, int fc, VT *__restrict__ y0,
-                                                    VT *__restrict__ y1, int nb, int bs) {
+                                                    VT *__restrict__ y1, int nb, int bs, Gate gate) {
     const int64_t gi = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
     if (gi >= static_cast<int64_t>(nb) * bs) return;
     const int I = static_cast<int>(gi / bs);
+    if (!live(gate, I)) return;
     const int a = static_cast<int>(gi - static_cast<int64_t>(I) * bs);
     double v = 0.0;
     if (fc && cf[I] == 1) {
@@ -298,8 +303,10 @@ __global__ __launch_bounds__(kThreads) void k_axpy_active(double *__restrict__ x
 template <typename VT>
 __global__ __launch_bounds__(256) void k_dense_mv(const double *__restrict__ M, const int64_t *__restrict__ off,
                                                  const int *__restrict__ dof0, const int *__restrict__ nn,
-                                                 const VT *__restrict__ x, VT *__restrict__ y) {
+                                                 const VT *__restrict__ x, VT *__restrict__ y,
+                                                 const int *__restrict__ sys, const int *__restrict__ active) {
     const int k = blockIdx.y;
+    if (active && !active[sys ? sys[k] : 0]) return;
     const int n = nn[k];
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -447,11 +454,11 @@ int residual_partials_count(const MatView<MT> &A) {
 
 template <typename MT, typename VT>
 void launch_residual(const MatView<MT> &A, const VT *b, const VT *x, VT *r, double *partials, float *r_lo,
-                     hipStream_t s) {
+                     hipStream_t s, Gate gate) {
     const int G = groups_for(A.nnzb, A.nb, A.bs);
     const unsigned grid = grid_rows(A.nb, G, A.bs);
     NAIR_BS_DISPATCH(A.bs, k_residual, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, A.nb, A.bs, G, b, x, r,
-                                                                  partials, r_lo));
+                                                                  partials, r_lo, gate));
     NAIR_HIP(hipGetLastError());
 }
 
@@ -469,54 +476,57 @@ void launch_reduce_partials(const double *partials, int npart, double *out, hipS
 
 template <typename MT, typename VT>
 void launch_relax(const MatView<MT> &A, const double *dinv, bool dinv_trans, const VT *r, const VT *ein, VT *eout,
-                  const int *list, int nlist, const int8_t *cf, int only_cf, hipStream_t s) {
+                  const int *list, int nlist, const int8_t *cf, int only_cf, hipStream_t s, Gate gate) {
     const int N = list ? nlist : A.nb;
     if (N <= 0) return;
     const int G = groups_for(A.nnzb, A.nb, A.bs);
     const unsigned grid = grid_rows(N, G, A.bs);
     NAIR_BS_DISPATCH(A.bs, k_relax, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, dinv, dinv_trans ? 1 : 0,
-                                                               A.nb, A.bs, G, r, ein, eout, list, nlist, cf, only_cf));
+                                                               A.nb, A.bs, G, r, ein, eout, list, nlist, cf, only_cf,
+                                                               gate));
     NAIR_HIP(hipGetLastError());
 }
 
 template <typename MT, typename VT>
-void launch_restrict(const MatView<MT> &Z, const VT *r, const int *cpts, VT *rc, hipStream_t s) {
+void launch_restrict(const MatView<MT> &Z, const VT *r, const int *cpts, VT *rc, hipStream_t s, Gate gate) {
     if (Z.nb <= 0) return;
     const int G = groups_for(Z.nnzb, Z.nb, Z.bs);
     const unsigned grid = grid_rows(Z.nb, G, Z.bs);
     NAIR_BS_DISPATCH(Z.bs, k_restrict, <<<grid, kThreads, 0, s>>>(Z.rowptr, Z.colidx, Z.vals, Z.nb, Z.bs, G, r, cpts,
-                                                                  rc));
+                                                                  rc, gate));
     NAIR_HIP(hipGetLastError());
 }
 
 template <typename VT>
-void launch_interp(const int *pmap, const VT *ec, VT *e0, VT *e1, int nb, int bs, hipStream_t s) {
-    k_interp<VT><<<grid_for(static_cast<int64_t>(nb) * bs, kThreads), kThreads, 0, s>>>(pmap, ec, e0, e1, nb, bs);
+void launch_interp(const int *pmap, const VT *ec, VT *e0, VT *e1, int nb, int bs, hipStream_t s, Gate gate) {
+    k_interp<VT><<<grid_for(static_cast<int64_t>(nb) * bs, kThreads), kThreads, 0, s>>>(pmap, ec, e0, e1, nb, bs,
+                                                                                         gate);
     NAIR_HIP(hipGetLastError());
 }
 
 template <typename VT>
-void launch_restrict_T(const int *ptptr, const int *ptidx, const VT *sv, VT *sc, int nc, int bs, hipStream_t st) {
+void launch_restrict_T(const int *ptptr, const int *ptidx, const VT *sv, VT *sc, int nc, int bs, hipStream_t st,
+                       Gate gate) {
     if (nc <= 0) return;
     k_restrict_T<VT><<<grid_for(static_cast<int64_t>(nc) * bs, kThreads), kThreads, 0, st>>>(ptptr, ptidx, sv, sc,
-                                                                                              nc, bs);
+                                                                                              nc, bs, gate);
     NAIR_HIP(hipGetLastError());
 }
 
 template <typename MT, typename VT>
-void launch_interp_T(const MatView<MT> &ZT, const int *cidx, const VT *yc, VT *y, hipStream_t s) {
+void launch_interp_T(const MatView<MT> &ZT, const int *cidx, const VT *yc, VT *y, hipStream_t s, Gate gate) {
     const int G = groups_for(ZT.nnzb, ZT.nb, ZT.bs);
     const unsigned grid = grid_rows(ZT.nb, G, ZT.bs);
     NAIR_BS_DISPATCH(ZT.bs, k_interp_T, <<<grid, kThreads, 0, s>>>(ZT.rowptr, ZT.colidx, ZT.vals, ZT.nb, ZT.bs, G,
-                                                                   cidx, yc, y));
+                                                                   cidx, yc, y, gate));
     NAIR_HIP(hipGetLastError());
 }
 
 template <typename VT>
 void launch_init_T(const double *dinv, const VT *g, const int8_t *cf, int fc, VT *y0, VT *y1, int nb, int bs,
-                   hipStream_t s) {
+                   hipStream_t s, Gate gate) {
     k_init_T<VT><<<grid_for(static_cast<int64_t>(nb) * bs, kThreads), kThreads, 0, s>>>(dinv, g, cf, fc, y0, y1, nb,
-                                                                                         bs);
+                                                                                         bs, gate);
     NAIR_HIP(hipGetLastError());
 }
 
@@ -528,9 +538,10 @@ void launch_axpy(double *x, const VT *e, int64_t n, hipStream_t s) {
 
 template <typename VT>
 void launch_dense_matvec(const double *M, const int64_t *off, const int *dof0, const int *n, int nseg, int max_n,
-                         const VT *x, VT *y, hipStream_t s) {
+                         const VT *x, VT *y, hipStream_t s, const int *sys, const int *active) {
     if (nseg <= 0) return;
-    k_dense_mv<VT><<<dim3(grid_for(max_n, 4), static_cast<unsigned>(nseg)), 256, 0, s>>>(M, off, dof0, n, x, y);
+    k_dense_mv<VT><<<dim3(grid_for(max_n, 4), static_cast<unsigned>(nseg)), 256, 0, s>>>(M, off, dof0, n, x, y, sys,
+                                                                                         active);
     NAIR_HIP(hipGetLastError());
 }
 
@@ -573,19 +584,19 @@ void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s) {
 #define NAIR_CYCLE_INST(MT, VT)                                                                                      \
     template int residual_partials_count<MT>(const MatView<MT> &);                                                   \
     template void launch_residual<MT, VT>(const MatView<MT> &, const VT *, const VT *, VT *, double *, float *,     \
-                                          hipStream_t);                                                              \
+                                          hipStream_t, Gate);                                                        \
     template void launch_relax<MT, VT>(const MatView<MT> &, const double *, bool, const VT *, const VT *, VT *,      \
-                                       const int *, int, const int8_t *, int, hipStream_t);                          \
-    template void launch_restrict<MT, VT>(const MatView<MT> &, const VT *, const int *, VT *, hipStream_t);          \
-    template void launch_interp<VT>(const int *, const VT *, VT *, VT *, int, int, hipStream_t);                     \
-    template void launch_restrict_T<VT>(const int *, const int *, const VT *, VT *, int, int, hipStream_t);          \
-    template void launch_interp_T<MT, VT>(const MatView<MT> &, const int *, const VT *, VT *, hipStream_t);          \
+                                       const int *, int, const int8_t *, int, hipStream_t, Gate);                    \
+    template void launch_restrict<MT, VT>(const MatView<MT> &, const VT *, const int *, VT *, hipStream_t, Gate);    \
+    template void launch_interp<VT>(const int *, const VT *, VT *, VT *, int, int, hipStream_t, Gate);               \
+    template void launch_restrict_T<VT>(const int *, const int *, const VT *, VT *, int, int, hipStream_t, Gate);    \
+    template void launch_interp_T<MT, VT>(const MatView<MT> &, const int *, const VT *, VT *, hipStream_t, Gate);    \
     template void launch_init_T<VT>(const double *, const VT *, const int8_t *, int, VT *, VT *, int, int,           \
-                                    hipStream_t);                                                                    \
+                                    hipStream_t, Gate);                                                              \
     template void launch_axpy<VT>(double *, const VT *, int64_t, hipStream_t);                                       \
     template void launch_axpy_active<VT>(double *, const VT *, int64_t, int, const int *, const int *, hipStream_t); \
     template void launch_dense_matvec<VT>(const double *, const int64_t *, const int *, const int *, int, int,       \
-                                          const VT *, VT *, hipStream_t);
+                                          const VT *, VT *, hipStream_t, const int *, const int *);
 
 NAIR_CYCLE_INST(double, double)
 NAIR_CYCLE_INST(float, float)

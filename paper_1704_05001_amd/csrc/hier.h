@@ -16,13 +16,13 @@ struct Level {
     // systems, each a contiguous range of block rows (one system otherwise)
     std::vector<int> seg;           // nsys + 1 block offsets
     std::vector<int8_t> mode;       // per system: 0 no blocks left, 1 coarsened, 2 solved directly here
-    DBuf<int> seg_d, lbase;         // device copy of seg; first block of each block's system
+    DBuf<int> seg_d, lbase, bsys;   // device copy of seg; per block: first block of its system, its system
     DBuf<int8_t> mode_d, direct;    // device copy of mode; blocks of directly solved systems
     // direct solves: one dense inverse (and its transpose) per system with mode 2
     int ndseg = 0, dmax_n = 0;
     std::vector<int> dsys, dblk0, dnb;
     std::vector<int64_t> doff;
-    DBuf<int> ddof0_d, dn_d;
+    DBuf<int> ddof0_d, dn_d, dsys_d;
     DBuf<int64_t> doff_d;
     // setup products
     DBuf<double> dinv, bnorm;
@@ -48,7 +48,6 @@ struct Level {
 // Per-system solve state of the batched iteration (device-side convergence).
 struct BatchSolve {
     bool ready = false;
-    DBuf<int> bsys;                 // level-0 block -> system
     DBuf<int64_t> clo;              // norm chunks: first dof, length, per-system chunk ranges
     DBuf<int> clen, cptr;
     int nchunk = 0;
@@ -76,6 +75,7 @@ struct Hier {
     DBuf<double> partials, scal;
     int npart = 0;
     BatchSolve batch;
+    const int *active = nullptr;    // during a batched solve: per-system "still iterating" flags
 };
 
 // nsys systems of sys_nb[s] block rows each (host array), stored one after the

@@ -87,7 +87,9 @@ void make_direct(Level &L, int lvl, hipStream_t s) {
     }
     L.ddof0_d.alloc(L.ndseg);
     L.dn_d.alloc(L.ndseg);
+    L.dsys_d.alloc(L.ndseg);
     L.doff_d.alloc(L.ndseg);
+    NAIR_HIP(hipMemcpyAsync(L.dsys_d.get(), L.dsys.data(), sizeof(int) * L.ndseg, hipMemcpyHostToDevice, s));
     NAIR_HIP(hipMemcpyAsync(L.ddof0_d.get(), dof0.data(), sizeof(int) * L.ndseg, hipMemcpyHostToDevice, s));
     NAIR_HIP(hipMemcpyAsync(L.dn_d.get(), nn.data(), sizeof(int) * L.ndseg, hipMemcpyHostToDevice, s));
     NAIR_HIP(hipMemcpyAsync(L.doff_d.get(), L.doff.data(), sizeof(int64_t) * L.ndseg, hipMemcpyHostToDevice, s));
@@ -184,15 +186,16 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
             }
         }
         upload_systems(L, s);
+        if (nsys > 1) {
+            L.bsys.alloc(n);
+            if (ncont > 0) L.lbase.alloc(n);
+            if (ncont > 0 && ndir > 0) L.direct.alloc(n);
+            launch_seg_info(L.seg_d.get(), L.mode_d.get(), nsys, n, L.lbase.get(), L.direct.get(), L.bsys.get(), s);
+        }
         if (ncont == 0) {
             L.coarsest = true;
             make_direct(L, l, s);
             break;
-        }
-        if (nsys > 1) {
-            L.lbase.alloc(n);
-            if (ndir > 0) L.direct.alloc(n);
-            launch_seg_info(L.seg_d.get(), L.mode_d.get(), nsys, n, L.lbase.get(), L.direct.get(), nullptr, s);
         }
         const int64_t nz = L.A.nnzb;
         L.dinv.alloc(static_cast<size_t>(n) * bb);

@@ -53,12 +53,15 @@ struct Store<float> {
 
 // Dense solves of the systems that end on level l: e = A_k^{-1} r (or A_k^{-T} r).
 template <typename T>
-void direct_solves(const Level &L, bool trans, const T *r, T *e, hipStream_t s) {
+void direct_solves(const Hier &h, const Level &L, bool trans, const T *r, T *e, hipStream_t s) {
     if (L.ndseg == 0) return;
     TimerScope ts(TK_DENSE, g_timer_level, s);
     launch_dense_matvec<T>(trans ? L.dense_invT.get() : L.dense_inv.get(), L.doff_d.get(), L.ddof0_d.get(),
-                           L.dn_d.get(), L.ndseg, L.dmax_n, r, e, s);
+                           L.dn_d.get(), L.ndseg, L.dmax_n, r, e, s, L.dsys_d.get(), h.active);
 }
+
+// Rows of the level's systems that are still iterating (all rows outside batched solves).
+Gate gate(const Hier &h, const Level &L) { return Gate{L.bsys.get(), h.active}; }
 
 // V-cycle on level l with right-hand side r_l and zero initial guess, no
 // pre-relaxation (section 5): restrict, recurse, interpolate, nu = k+1 Jacobi
@@ -70,18 +73,18 @@ const T *vcycle(Hier &h, int l, hipStream_t s) {
     const int bs = h.bs;
     g_timer_level = l;
     if (L.coarsest) {
-        direct_solves<T>(L, false, S::r(L), S::e0(L), s);
+        direct_solves<T>(h, L, false, S::r(L), S::e0(L), s);
         return S::e0(L);
     }
     Level &C = *h.lv[l + 1];
     {
         TimerScope ts(TK_RESTRICT, l, s);
-        launch_restrict<T, T>(S::Z(L), S::r(L), L.cpts.get(), S::r(C), s);
+        launch_restrict<T, T>(S::Z(L), S::r(L), L.cpts.get(), S::r(C), s, gate(h, C));
     }
     const T *ec = vcycle<T>(h, l + 1, s);
     {
         TimerScope ts(TK_INTERP, l, s);
-        launch_interp<T>(L.pmap.get(), ec, S::e0(L), S::e1(L), L.A.nb, bs, s);
+        launch_interp<T>(L.pmap.get(), ec, S::e0(L), S::e1(L), L.A.nb, bs, s, gate(h, L));
     }
     T *cur = S::e0(L), *oth = S::e1(L);
     const MatView<T> A = S::A(L);
@@ -89,16 +92,17 @@ const T *vcycle(Hier &h, int l, hipStream_t s) {
         // the nu sweeps run back to back; the timer brackets them as one group
         TimerScope ts(TK_RELAX, l, s, h.prm.degree + 1);
         for (int k = 0; k <= h.prm.degree; ++k) {
-            launch_relax<T, T>(A, L.dinv.get(), false, S::r(L), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s);
+            launch_relax<T, T>(A, L.dinv.get(), false, S::r(L), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s,
+                               gate(h, L));
             std::swap(cur, oth);
         }
     }
     if (h.prm.relax == 1) {
-        launch_relax<T, T>(A, L.dinv.get(), false, S::r(L), cur, oth, nullptr, 0, L.cf.get(), 1, s);
+        launch_relax<T, T>(A, L.dinv.get(), false, S::r(L), cur, oth, nullptr, 0, L.cf.get(), 1, s, gate(h, L));
         std::swap(cur, oth);
     }
     g_timer_level = l;
-    direct_solves<T>(L, false, S::r(L), cur, s);   // systems that end on this level
+    direct_solves<T>(h, L, false, S::r(L), cur, s);   // systems that end on this level
     return cur;
 }
 
@@ -112,26 +116,28 @@ const T *vcycle_T(Hier &h, int l, hipStream_t s) {
     const int bs = h.bs;
     g_timer_level = l;
     if (L.coarsest) {
-        direct_solves<T>(L, true, S::r(L), S::e0(L), s);
+        direct_solves<T>(h, L, true, S::r(L), S::e0(L), s);
         return S::e0(L);
     }
     Level &C = *h.lv[l + 1];
-    launch_init_T<T>(L.dinv.get(), S::r(L), L.cf.get(), h.prm.relax == 1 ? 1 : 0, S::e0(L), S::e1(L), L.A.nb, bs, s);
+    launch_init_T<T>(L.dinv.get(), S::r(L), L.cf.get(), h.prm.relax == 1 ? 1 : 0, S::e0(L), S::e1(L), L.A.nb, bs, s,
+                     gate(h, L));
     T *cur = S::e0(L), *oth = S::e1(L);
     const MatView<T> AT = S::AT(L);
     {
         TimerScope ts(TK_RELAX, l, s, h.prm.degree + 1);
         for (int k = 0; k <= h.prm.degree; ++k) {
-            launch_relax<T, T>(AT, L.dinv.get(), true, S::r(L), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s);
+            launch_relax<T, T>(AT, L.dinv.get(), true, S::r(L), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s,
+                               gate(h, L));
             std::swap(cur, oth);
         }
     }
-    launch_residual<T, T>(AT, S::r(L), cur, S::tmp(L), nullptr, nullptr, s);
-    launch_restrict_T<T>(L.ptptr.get(), L.ptidx.get(), S::tmp(L), S::r(C), L.nc, bs, s);
+    launch_residual<T, T>(AT, S::r(L), cur, S::tmp(L), nullptr, nullptr, s, gate(h, L));
+    launch_restrict_T<T>(L.ptptr.get(), L.ptidx.get(), S::tmp(L), S::r(C), L.nc, bs, s, gate(h, C));
     const T *yc = vcycle_T<T>(h, l + 1, s);
-    launch_interp_T<T, T>(S::ZT(L), L.cidx.get(), yc, cur, s);
+    launch_interp_T<T, T>(S::ZT(L), L.cidx.get(), yc, cur, s, gate(h, L));
     g_timer_level = l;
-    direct_solves<T>(L, true, S::r(L), cur, s);   // systems that end on this level
+    direct_solves<T>(h, L, true, S::r(L), cur, s);   // systems that end on this level
     return cur;
 }
 
@@ -244,10 +250,6 @@ void ensure_batch(Hier &h, int max_iter, hipStream_t s) {
             NAIR_HIP(hipMemcpyAsync(B.clen.get(), clen.data(), sizeof(int) * B.nchunk, hipMemcpyHostToDevice, s));
         }
         NAIR_HIP(hipMemcpyAsync(B.cptr.get(), cptr.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice, s));
-        if (nsys > 1) {
-            B.bsys.alloc(L0.A.nb);
-            launch_seg_info(L0.seg_d.get(), L0.mode_d.get(), nsys, L0.A.nb, nullptr, nullptr, B.bsys.get(), s);
-        }
         B.bn.alloc(nsys);
         B.last.alloc(nsys);
         B.rtol.alloc(1);
@@ -279,18 +281,25 @@ void batch_iteration(Hier &h, bool trans, const double *b, double *x, hipStream_
     const int64_t n = static_cast<int64_t>(L0.A.nb) * h.bs;
     const bool fp32 = std::is_same<T, float>::value;
     const T *e = trans ? vcycle_T<T>(h, 0, s) : vcycle<T>(h, 0, s);
-    launch_axpy_active<T>(x, e, n, h.bs, B.bsys.get(), B.active.get(), s);
+    launch_axpy_active<T>(x, e, n, h.bs, L0.bsys.get(), B.active.get(), s);
     const MatView<double> Aop = trans ? view(L0.AT) : view(L0.A);
     {
         TimerScope ts(TK_RESIDUAL, 0, s);
-        launch_residual<double, double>(Aop, b, x, L0.r.get(), nullptr, fp32 ? L0.r32.get() : nullptr, s);
+        launch_residual<double, double>(Aop, b, x, L0.r.get(), nullptr, fp32 ? L0.r32.get() : nullptr, s,
+                                        gate(h, L0));
     }
     launch_seg_sumsq(L0.r.get(), B.clo.get(), B.clen.get(), B.nchunk, B.part.get(), s);
     launch_seg_check(B.part.get(), B.cptr.get(), h.nsys, B.bn.get(), B.rtol.get(), B.hist_cap, B.hist.get(),
                      B.last.get(), B.active.get(), B.status.get(), B.iters.get(), B.it.get(), B.nact.get(), s);
 }
 
+// Cycles of stopped systems are skipped: the kernels read the activity flags.
 void run_iteration(Hier &h, bool trans, const double *b, double *x, hipStream_t s) {
+    struct Scope {
+        Hier &h;
+        Scope(Hier &hh, const int *a) : h(hh) { h.active = a; }
+        ~Scope() { h.active = nullptr; }
+    } scope(h, h.batch.active.get());
     if (h.prm.precision == 1) batch_iteration<float>(h, trans, b, x, s);
     else batch_iteration<double>(h, trans, b, x, s);
 }
