@@ -170,12 +170,20 @@ def main(argv=None):
     ap.add_argument("--batch-workload", default="dg_q2_angles64_uneven")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-angles leg")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched leg and print its JSON (for profiling it alone)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="after the timed steps, fill, sum and copy a BYTES buffer (reference kernels of "
+                         "known traffic for hardware counters)")
+    ap.add_argument("--skip-transposed", action="store_true",
+                    help="leave the transposed solve out of every step (for counter runs of the forward "
+                         "cycle only; not a benchmark configuration)")
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU; run with --gpus 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not run)"}), flush=True)
+        print(json.dumps({"error": "one GPU only: run with --gpus 1 (the path is not sharded across GPUs)"}),
+              flush=True)
         return 2
 
     import numpy as np
@@ -189,6 +197,10 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}), flush=True)
         return 3
+
+    if args.batch_only:
+        print(json.dumps(batched_leg(args, P, torch, np)), flush=True)
+        return 0
 
     t0 = time.time()
     S, degree = make_config(args.workload)
@@ -205,14 +217,21 @@ def main(argv=None):
     params = P.Params(degree=degree)
     stream = torch.cuda.current_stream()
 
-    def step(record, prm=params, xo=x, yo=y):
+    def step(record, prm=params, xo=x, yo=y, timed=False):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record(stream)
         H = P.Hierarchy(rp, ci, va, S.bs, prm)
         ev[1].record(stream)
+        if timed:   # the kernel timer brackets the forward solve's launches of the roofline kernel
+            P.timer_select(args.roofline_kernel, args.roofline_level)
         _, r = H.solve(b, x=xo, rtol=args.rtol)
+        if timed:
+            P.timer_select(None)
         ev[2].record(stream)
-        _, rT = H.solve_T(g, y=yo, rtol=args.rtol)
+        if args.skip_transposed:
+            rT = r
+        else:
+            _, rT = H.solve_T(g, y=yo, rtol=args.rtol)
         ev[3].record(stream)
         if r.status != "OK" or rT.status != "OK":
             raise RuntimeError(f"solve status {r.status} / {rT.status}")
@@ -233,18 +252,25 @@ def main(argv=None):
         lvl = H.level(args.roofline_level)
         H.close()
 
-    P.timer_select(args.roofline_kernel, args.roofline_level)
     recs = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
-        H = step(recs)
+        H = step(recs, timed=True)
         H.close()
     torch.cuda.synchronize()
     t_end = time.perf_counter()
     launches, kernel_ms = P.timer_read()
-    P.timer_select(None)
     log(f"timed {args.steps} steps in {t_end - t_start:.3f}s")
+    if args.copy_probe > 0:
+        src = torch.empty(args.copy_probe // 8, dtype=torch.float64, device=dev)
+        src.fill_(1.0)                       # writes BYTES
+        total = float(src.sum())             # reads BYTES
+        dst = torch.empty_like(src)
+        dst.copy_(src)                       # reads and writes BYTES
+        torch.cuda.synchronize()
+        log(f"copy probe: fill, sum ({total:.0f}) and copy of {src.numel() * 8} bytes")
+        del src, dst
 
     setup_ms = np.mean([e[0].elapsed_time(e[1]) for e, _, _ in recs])
     solve_ms = np.mean([e[1].elapsed_time(e[2]) for e, _, _ in recs])

@@ -249,12 +249,13 @@ void launch_axpy_active(double *x, const VT *e, int64_t n, int bs, const int *bs
 void launch_seg_sumsq(const double *v, const int64_t *clo, const int *clen, int nchunk, double *part,
                       hipStream_t s);
 // start of a batched solve: per-system ||b|| from the chunk sums; activity, status, counters
+// (nact_acc: a scratch counter)
 void launch_seg_init(const double *part, const int *cptr, int nsys, double *bn, double *last, int *active,
-                     int *status, int *iters, int *it, int *nact, hipStream_t s);
+                     int *status, int *iters, int *it, int *nact, int *nact_acc, hipStream_t s);
 // end of one batched iteration: per-system relative residual, history, convergence, counters
 void launch_seg_check(const double *part, const int *cptr, int nsys, const double *bn, const double *rtol,
                       int hist_cap, double *hist, double *last, int *active, int *status, int *iters, int *it,
-                      int *nact, hipStream_t s);
+                      int *nact, int *nact_acc, hipStream_t s);
 void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s);
 
 // ------------------------------------------------------------------- grad

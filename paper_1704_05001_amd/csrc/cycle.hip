@@ -333,86 +333,80 @@ __global__ __launch_bounds__(kThreads) void k_seg_sumsq(const double *__restrict
     if (threadIdx.x == 0) part[c] = t;
 }
 
-// sum of the chunk sums of system sys, in chunk order
+// Sum of the chunk sums of system blockIdx.x (fixed order: lane-strided, then
+// a wave reduction tree), valid in thread 0.  One wave per system.
 __device__ inline double seg_total(const double *__restrict__ part, const int *__restrict__ cptr, int sys) {
     double ss = 0.0;
-    for (int c = cptr[sys]; c < cptr[sys + 1]; ++c) ss += part[c];
+    for (int c = cptr[sys] + static_cast<int>(threadIdx.x); c < cptr[sys + 1]; c += 64) ss += part[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
     return ss;
 }
 
 // status codes as in the public header: 0 OK, 3 not converged, 4 non-finite
 constexpr int kStOk = 0, kStNoConv = 3, kStNumeric = 4;
 
-__global__ __launch_bounds__(kThreads) void k_seg_init(const double *__restrict__ part, const int *__restrict__ cptr,
-                                                      int nsys, double *__restrict__ bn, double *__restrict__ last,
-                                                      int *__restrict__ active, int *__restrict__ status,
-                                                      int *__restrict__ iters, int *__restrict__ it,
-                                                      int *__restrict__ nact) {
-    __shared__ int cnt;
-    if (threadIdx.x == 0) cnt = 0;
-    __syncthreads();
-    for (int sys = threadIdx.x; sys < nsys; sys += kThreads) {
-        const double b = sqrt(seg_total(part, cptr, sys));
-        bn[sys] = b;
-        last[sys] = 1.0;
-        iters[sys] = 0;
-        if (!isfinite(b)) {
-            active[sys] = 0;
-            status[sys] = kStNumeric;
-        } else if (b == 0.0) {   // x = 0 solves it
-            active[sys] = 0;
-            status[sys] = kStOk;
-            last[sys] = 0.0;
-        } else {
-            active[sys] = 1;
-            status[sys] = kStNoConv;
-            atomicAdd(&cnt, 1);
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        *it = 0;
-        *nact = cnt;
+// Start of a batched solve, one wave per system: ||b_sys||, activity, status.
+__global__ __launch_bounds__(64) void k_seg_init(const double *__restrict__ part, const int *__restrict__ cptr,
+                                                double *__restrict__ bn, double *__restrict__ last,
+                                                int *__restrict__ active, int *__restrict__ status,
+                                                int *__restrict__ iters, int *__restrict__ nact_acc) {
+    const int sys = blockIdx.x;
+    const double b = sqrt(seg_total(part, cptr, sys));
+    if (threadIdx.x != 0) return;
+    bn[sys] = b;
+    last[sys] = 1.0;
+    iters[sys] = 0;
+    if (!isfinite(b)) {
+        active[sys] = 0;
+        status[sys] = kStNumeric;
+    } else if (b == 0.0) {   // x = 0 solves it
+        active[sys] = 0;
+        status[sys] = kStOk;
+        last[sys] = 0.0;
+    } else {
+        active[sys] = 1;
+        status[sys] = kStNoConv;
+        atomicAdd(nact_acc, 1);
     }
 }
 
-// After iteration *it: relative residuals of the active systems, recorded in
-// hist[sys * hist_cap + it]; converged or non-finite systems stop.
-__global__ __launch_bounds__(kThreads) void k_seg_check(const double *__restrict__ part, const int *__restrict__ cptr,
-                                                       int nsys, const double *__restrict__ bn,
-                                                       const double *__restrict__ rtol, int hist_cap,
-                                                       double *__restrict__ hist, double *__restrict__ last,
-                                                       int *__restrict__ active, int *__restrict__ status,
-                                                       int *__restrict__ iters, int *__restrict__ it,
-                                                       int *__restrict__ nact) {
-    __shared__ int cnt;
+// After iteration *it, one wave per system: relative residual of an active
+// system, recorded in hist[sys * hist_cap + it]; converged or non-finite
+// systems stop.
+__global__ __launch_bounds__(64) void k_seg_check(const double *__restrict__ part, const int *__restrict__ cptr,
+                                                 const double *__restrict__ bn, const double *__restrict__ rtol,
+                                                 int hist_cap, double *__restrict__ hist, double *__restrict__ last,
+                                                 int *__restrict__ active, int *__restrict__ status,
+                                                 int *__restrict__ iters, const int *__restrict__ it,
+                                                 int *__restrict__ nact_acc) {
+    const int sys = blockIdx.x;
+    if (!active[sys]) return;   // uniform over the wave
+    const double ss = seg_total(part, cptr, sys);
+    if (threadIdx.x != 0) return;
     const int k = *it;
-    const double tol = *rtol;
-    if (threadIdx.x == 0) cnt = 0;
-    __syncthreads();
-    for (int sys = threadIdx.x; sys < nsys; sys += kThreads) {
-        if (!active[sys]) continue;
-        const double rel = sqrt(seg_total(part, cptr, sys)) / bn[sys];
-        if (k < hist_cap) hist[static_cast<int64_t>(sys) * hist_cap + k] = rel;
-        last[sys] = rel;
-        if (!isfinite(rel)) {
-            active[sys] = 0;
-            status[sys] = kStNumeric;
-            iters[sys] = k + 1;
-        } else if (rel <= tol) {
-            active[sys] = 0;
-            status[sys] = kStOk;
-            iters[sys] = k + 1;
-        } else {
-            iters[sys] = k + 1;
-            atomicAdd(&cnt, 1);
-        }
+    const double rel = sqrt(ss) / bn[sys];
+    if (k < hist_cap) hist[static_cast<int64_t>(sys) * hist_cap + k] = rel;
+    last[sys] = rel;
+    iters[sys] = k + 1;
+    if (!isfinite(rel)) {
+        active[sys] = 0;
+        status[sys] = kStNumeric;
+    } else if (rel <= *rtol) {
+        active[sys] = 0;
+        status[sys] = kStOk;
+    } else {
+        atomicAdd(nact_acc, 1);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        *nact = cnt;
-        *it = k + 1;
-    }
+}
+
+// Counters after k_seg_init (reset: it = 0) or k_seg_check (it += 1): the
+// number of systems still iterating, and a cleared accumulator.
+__global__ void k_seg_tick(int reset, int *__restrict__ it, int *__restrict__ nact, int *__restrict__ nact_acc) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    *it = reset ? 0 : *it + 1;
+    *nact = *nact_acc;
+    *nact_acc = 0;
 }
 
 __global__ __launch_bounds__(256) void k_to_float(const double *__restrict__ in, float *__restrict__ out, int64_t n) {
@@ -560,16 +554,19 @@ void launch_seg_sumsq(const double *v, const int64_t *clo, const int *clen, int 
 }
 
 void launch_seg_init(const double *part, const int *cptr, int nsys, double *bn, double *last, int *active,
-                     int *status, int *iters, int *it, int *nact, hipStream_t s) {
-    k_seg_init<<<1, kThreads, 0, s>>>(part, cptr, nsys, bn, last, active, status, iters, it, nact);
+                     int *status, int *iters, int *it, int *nact, int *nact_acc, hipStream_t s) {
+    k_seg_tick<<<1, 64, 0, s>>>(1, it, nact, nact_acc);   // clears the accumulator
+    k_seg_init<<<static_cast<unsigned>(nsys), 64, 0, s>>>(part, cptr, bn, last, active, status, iters, nact_acc);
+    k_seg_tick<<<1, 64, 0, s>>>(1, it, nact, nact_acc);
     NAIR_HIP(hipGetLastError());
 }
 
 void launch_seg_check(const double *part, const int *cptr, int nsys, const double *bn, const double *rtol,
                       int hist_cap, double *hist, double *last, int *active, int *status, int *iters, int *it,
-                      int *nact, hipStream_t s) {
-    k_seg_check<<<1, kThreads, 0, s>>>(part, cptr, nsys, bn, rtol, hist_cap, hist, last, active, status, iters, it,
-                                       nact);
+                      int *nact, int *nact_acc, hipStream_t s) {
+    k_seg_check<<<static_cast<unsigned>(nsys), 64, 0, s>>>(part, cptr, bn, rtol, hist_cap, hist, last, active, status,
+                                                           iters, it, nact_acc);
+    k_seg_tick<<<1, 64, 0, s>>>(0, it, nact, nact_acc);
     NAIR_HIP(hipGetLastError());
 }
 

@@ -54,7 +54,7 @@ struct BatchSolve {
     DBuf<double> part, bn, last, rtol;
     DBuf<double> hist;              // [nsys][hist_cap] relative residuals
     int hist_cap = 0;
-    DBuf<int> active, status, iters, it, nact;
+    DBuf<int> active, status, iters, it, nact, nact_acc;
     double rtol_host = 0.0;
     std::vector<std::vector<double>> hist_host;
     // captured iteration (slot 0: A, slot 1: A^T), replayed per step

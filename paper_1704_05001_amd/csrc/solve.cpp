@@ -258,6 +258,7 @@ void ensure_batch(Hier &h, int max_iter, hipStream_t s) {
         B.iters.alloc(nsys);
         B.it.alloc(1);
         B.nact.alloc(1);
+        B.nact_acc.alloc(1);
         NAIR_HIP(hipStreamSynchronize(s));   // the host tables end here
         B.ready = true;
     }
@@ -290,16 +291,19 @@ void batch_iteration(Hier &h, bool trans, const double *b, double *x, hipStream_
     }
     launch_seg_sumsq(L0.r.get(), B.clo.get(), B.clen.get(), B.nchunk, B.part.get(), s);
     launch_seg_check(B.part.get(), B.cptr.get(), h.nsys, B.bn.get(), B.rtol.get(), B.hist_cap, B.hist.get(),
-                     B.last.get(), B.active.get(), B.status.get(), B.iters.get(), B.it.get(), B.nact.get(), s);
+                     B.last.get(), B.active.get(), B.status.get(), B.iters.get(), B.it.get(), B.nact.get(),
+                     B.nact_acc.get(), s);
 }
 
 // Cycles of stopped systems are skipped: the kernels read the activity flags.
 void run_iteration(Hier &h, bool trans, const double *b, double *x, hipStream_t s) {
+    // (one system: the cycle needs no gate, the loop ends when it stops; the
+    // update and the norm check still read the flag)
     struct Scope {
         Hier &h;
         Scope(Hier &hh, const int *a) : h(hh) { h.active = a; }
         ~Scope() { h.active = nullptr; }
-    } scope(h, h.batch.active.get());
+    } scope(h, h.nsys > 1 ? h.batch.active.get() : nullptr);
     if (h.prm.precision == 1) batch_iteration<float>(h, trans, b, x, s);
     else batch_iteration<double>(h, trans, b, x, s);
 }
@@ -361,7 +365,7 @@ nair_status run_solve_batch(Hier &h, bool trans, const double *b, double *x, dou
     NAIR_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
     launch_seg_sumsq(b, B.clo.get(), B.clen.get(), B.nchunk, B.part.get(), s);
     launch_seg_init(B.part.get(), B.cptr.get(), nsys, B.bn.get(), B.last.get(), B.active.get(), B.status.get(),
-                    B.iters.get(), B.it.get(), B.nact.get(), s);
+                    B.iters.get(), B.it.get(), B.nact.get(), B.nact_acc.get(), s);
     NAIR_HIP(hipMemcpyAsync(L0.r.get(), b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     if (fp32) launch_to_float(b, L0.r32.get(), n, s);
     hipGraphExec_t ex = use_graph ? batch_graph(h, trans, b, x) : nullptr;
