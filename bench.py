@@ -89,8 +89,16 @@ def batched_leg(args, P, torch, np):
            "meshes": sorted({int(S.N) for S in systems}), "steps": args.batch_steps,
            "step": "one batched setup + one batched solve of every system to 1e-10; value = dofs / (setup + solve)"}
 
+    tables = {}
+
     def run(prec, graph):
         prm = P.Params(degree=degree, precision=prec)
+        if not args.no_tune:
+            if prec not in tables:   # lane groups tuned once per precision on the batch hierarchy
+                Ht = P.Hierarchy(d_rp, d_ci, d_va, 9, prm, sys_nb=sys_nb)
+                tables[prec] = Ht.autotune(reps=10)
+                Ht.close()
+            prm = P.Params(degree=degree, precision=prec, tuning=tables[prec])
         times, iters = [], None
         for i in range(1 + args.batch_steps):        # first step untimed (warm-up)
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -120,7 +128,9 @@ def batched_leg(args, P, torch, np):
     log(f"batched: fp32 graph {res['fp32_hier_graph']['value']:.0f}, fp64 graph {res['fp64_graph']['value']:.0f}, "
         f"fp64 eager {res['fp64_eager']['value']:.0f} DOFs/s")
 
+    res["tuned"] = not args.no_tune
     # the same systems one after another: setup + solve each with the plain entry points
+    # (default lane groups: a tuning table fits one hierarchy structure)
     prm = P.Params(degree=degree)
     per = []
     offs = np.concatenate(([0], np.cumsum([S.nnzb for S in systems])))
@@ -170,6 +180,7 @@ def main(argv=None):
     ap.add_argument("--batch-workload", default="dg_q2_angles64_uneven")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-angles leg")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default lane groups (no autotuning)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched leg and print its JSON (for profiling it alone)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -252,11 +263,21 @@ def main(argv=None):
         lvl = H.level(args.roofline_level)
         H.close()
 
+    tuning = None
+    if not args.no_tune:
+        # lane groups of the cycle kernels, tuned once on this matrix's hierarchy
+        Ht = P.Hierarchy(rp, ci, va, S.bs, params)
+        tuning = Ht.autotune(reps=20)
+        Ht.close()
+        params = P.Params(degree=degree, tuning=tuning)
+        for _ in range(max(1, args.warmup)):
+            step(None, params).close()
+
     recs = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
-        H = step(recs, timed=True)
+        H = step(recs, params, timed=True)
         H.close()
     torch.cuda.synchronize()
     t_end = time.perf_counter()
@@ -304,11 +325,18 @@ def main(argv=None):
         "solve_T_ms": round(float(solveT_ms), 3), "iters": iters, "iters_T": itersT,
         "step": "setup + solve + transposed solve; value = dofs / (setup + solve)",
         "roofline": roof,
+        "tuned": tuning is not None,
+        "tuning": tuning.tolist() if tuning is not None else None,
+        "tuning_kinds": list(P.TUNE_KINDS),
     }
 
     if not args.no_fp32:
         # the same steps with the FP32-stored hierarchy (FP64 setup, refinement and residuals)
         p32 = P.Params(degree=degree, precision="fp32")
+        if not args.no_tune:
+            Ht = P.Hierarchy(rp, ci, va, S.bs, p32)
+            p32 = P.Params(degree=degree, precision="fp32", tuning=Ht.autotune(reps=20))
+            Ht.close()
         x32, y32 = torch.empty_like(b), torch.empty_like(g)
         for _ in range(max(1, args.warmup)):
             step(None, p32, x32, y32).close()

@@ -63,6 +63,8 @@ typedef struct {
                                  vectors in float; FP64 block inverses, accumulation, outer
                                  residual and update: FP64 iterative refinement).  The setup and
                                  its decisions are FP64 either way. */
+    const int8_t *tuning;     /* optional, host, [64][6] lane-group choices from nair_autotune for a
+                                 hierarchy of the same structure (copied at setup); NULL: defaults */
 } nair_params;
 
 typedef struct {
@@ -177,6 +179,19 @@ nair_status nair_batch_history(nair_hier h, int32_t sys, double *buf, int32_t ca
  */
 nair_status nair_get_systems(nair_hier h, int32_t lvl, int32_t cap, int32_t *nsys, int32_t *seg, int8_t *mode,
                              int64_t *dense_off);
+
+/*
+ * Autotune the cycle kernels of this hierarchy: every cycle kernel maps a block
+ * row onto G groups of bs lanes; for each level and each kernel (0 Jacobi
+ * sweep with A, 1 with A^T, 2 transposed residual, 3 restriction, 4 transposed
+ * interpolation, 5 outer residual) each power of two G with G*bs <= 256 is
+ * timed over reps launches on the level's own operands and the fastest kept
+ * (it must beat the row-length default by 3%).  Results do not change: only
+ * the launch shape does.  table (host, may be NULL) receives [64][6] choices
+ * (0 = default) that nair_params.tuning applies to later hierarchies of the
+ * same structure.  Builds the transposed operators.
+ */
+nair_status nair_autotune(nair_hier h, int32_t reps, int8_t *table, void *stream);
 
 /* One cycle application e = B r (resp. y = B^T g), zero initial guess. */
 nair_status nair_vcycle(nair_hier h, const double *r, double *e, void *stream);

@@ -70,6 +70,7 @@ nair_status nair_default_params(nair_params *p) {
     p->seed = 0;
     p->cf_override_host = nullptr;
     p->precision = 0;
+    p->tuning = nullptr;
     return NAIR_OK;
 }
 
@@ -100,7 +101,9 @@ static nair_status setup_common(int32_t nsys, const int32_t *sys_nb, int32_t nb,
         NAIR_HIP(hipGetDevice(&h->h.device));
         h->h.prm = *p;
         nair::build_hierarchy(h->h, nsys, sys_nb, nb, bs, rowptr, colidx, vals, s);
-        h->h.prm.cf_override_host = nullptr;   // host pointer not kept past the call
+        if (p->tuning) nair::apply_tuning(h->h, p->tuning);
+        h->h.prm.cf_override_host = nullptr;   // host pointers not kept past the call
+        h->h.prm.tuning = nullptr;
         return NAIR_OK;
     });
     if (st != NAIR_OK) {
@@ -155,6 +158,16 @@ nair_status nair_solve_batch(nair_hier h, int32_t trans, const double *b, double
     hipStream_t s = static_cast<hipStream_t>(stream);
     return guarded(h, [&]() {
         return nair::run_solve_batch(h->h, trans != 0, b, x, rtol, max_iter, use_graph != 0, res, s);
+    });
+}
+
+nair_status nair_autotune(nair_hier h, int32_t reps, int8_t *table, void *stream) {
+    if (!h) return bad(nullptr, "handle is NULL");
+    if (reps < 1 || reps > 10000) return bad(h, "reps must be in [1, 10000]");
+    DeviceGuard dg(h->h.device);
+    return guarded(h, [&]() {
+        nair::autotune(h->h, reps, table, static_cast<hipStream_t>(stream));
+        return NAIR_OK;
     });
 }
 

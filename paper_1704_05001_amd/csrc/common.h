@@ -190,13 +190,21 @@ struct MatView {
     int64_t nnzb = 0;
     const int *rowptr = nullptr, *colidx = nullptr;
     const MT *vals = nullptr;
+    int groups = 0;   // lane groups per block row for the kernel reading it (0: from the row length)
+    MatView with_groups(int g) const {
+        MatView v = *this;
+        v.groups = g;
+        return v;
+    }
 };
 inline MatView<double> view(const DevBSR &A) {
-    return MatView<double>{A.nb, A.ncols, A.bs, A.nnzb, A.rowptr.get(), A.colidx.get(), A.vals.get()};
+    return MatView<double>{A.nb, A.ncols, A.bs, A.nnzb, A.rowptr.get(), A.colidx.get(), A.vals.get(), 0};
 }
 inline MatView<float> view(const DevBSR &A, const float *vals32) {
-    return MatView<float>{A.nb, A.ncols, A.bs, A.nnzb, A.rowptr.get(), A.colidx.get(), vals32};
+    return MatView<float>{A.nb, A.ncols, A.bs, A.nnzb, A.rowptr.get(), A.colidx.get(), vals32, 0};
 }
+// lane-group counts a kernel may use for block size bs (powers of two, G * bs <= 256)
+int max_groups(int bs);
 
 // Rows of systems that have stopped iterating are skipped in batched solves:
 // row r is live when active == nullptr or active[bsys ? bsys[r] : 0] != 0.
@@ -210,6 +218,8 @@ __device__ inline bool live(const Gate &g, int row) {
 
 template <typename MT>
 int residual_partials_count(const MatView<MT> &A);
+// the most partials any lane-group choice produces for a residual of nb block rows
+int residual_partials_max(int nb, int bs);
 // r = b - A x (+ squared-norm partials per workgroup if partials, + float copy if r_lo)
 template <typename MT, typename VT>
 void launch_residual(const MatView<MT> &A, const VT *b, const VT *x, VT *r, double *partials, float *r_lo,

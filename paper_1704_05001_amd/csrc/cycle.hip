@@ -415,11 +415,18 @@ __global__ __launch_bounds__(256) void k_to_float(const double *__restrict__ in,
         out[g] = static_cast<float>(in[g]);
 }
 
-// Lane groups per block row from the average row length (at most 256 lanes per row).
-int groups_for(int64_t nnz, int rows, int bs) {
-    const double avg = rows > 0 ? static_cast<double>(nnz) / rows : 1.0;
-    int G = avg <= 3.5 ? 1 : (avg <= 7.0 ? 2 : (avg <= 14.0 ? 4 : 8));
-    while (G > 1 && G * bs > kThreads) G >>= 1;
+// Lane groups per block row: the tuned count if the view carries one, else
+// from the average row length (at most 256 lanes per row either way).
+template <typename MT>
+int groups_for(const MatView<MT> &A) {
+    int G;
+    if (A.groups > 0) {
+        G = A.groups;
+    } else {
+        const double avg = A.nb > 0 ? static_cast<double>(A.nnzb) / A.nb : 1.0;
+        G = avg <= 3.5 ? 1 : (avg <= 7.0 ? 2 : (avg <= 14.0 ? 4 : 8));
+    }
+    while (G > 1 && G * A.bs > kThreads) G >>= 1;
     return G;
 }
 
@@ -442,14 +449,23 @@ unsigned grid_rows(int64_t rows, int G, int bs) { return grid_for(rows, kThreads
 
 template <typename MT>
 int residual_partials_count(const MatView<MT> &A) {
-    const int G = groups_for(A.nnzb, A.nb, A.bs);
+    const int G = groups_for(A);
     return static_cast<int>(grid_rows(A.nb, G, A.bs));
+}
+
+// more lane groups put fewer rows in a workgroup: the largest G gives the most workgroups
+int residual_partials_max(int nb, int bs) { return static_cast<int>(grid_rows(nb, max_groups(bs), bs)); }
+
+int max_groups(int bs) {
+    int G = 1;
+    while (2 * G * bs <= kThreads && G < 32) G *= 2;
+    return G;
 }
 
 template <typename MT, typename VT>
 void launch_residual(const MatView<MT> &A, const VT *b, const VT *x, VT *r, double *partials, float *r_lo,
                      hipStream_t s, Gate gate) {
-    const int G = groups_for(A.nnzb, A.nb, A.bs);
+    const int G = groups_for(A);
     const unsigned grid = grid_rows(A.nb, G, A.bs);
     NAIR_BS_DISPATCH(A.bs, k_residual, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, A.nb, A.bs, G, b, x, r,
                                                                   partials, r_lo, gate));
@@ -473,7 +489,7 @@ void launch_relax(const MatView<MT> &A, const double *dinv, bool dinv_trans, con
                   const int *list, int nlist, const int8_t *cf, int only_cf, hipStream_t s, Gate gate) {
     const int N = list ? nlist : A.nb;
     if (N <= 0) return;
-    const int G = groups_for(A.nnzb, A.nb, A.bs);
+    const int G = groups_for(A);
     const unsigned grid = grid_rows(N, G, A.bs);
     NAIR_BS_DISPATCH(A.bs, k_relax, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, dinv, dinv_trans ? 1 : 0,
                                                                A.nb, A.bs, G, r, ein, eout, list, nlist, cf, only_cf,
@@ -484,7 +500,7 @@ void launch_relax(const MatView<MT> &A, const double *dinv, bool dinv_trans, con
 template <typename MT, typename VT>
 void launch_restrict(const MatView<MT> &Z, const VT *r, const int *cpts, VT *rc, hipStream_t s, Gate gate) {
     if (Z.nb <= 0) return;
-    const int G = groups_for(Z.nnzb, Z.nb, Z.bs);
+    const int G = groups_for(Z);
     const unsigned grid = grid_rows(Z.nb, G, Z.bs);
     NAIR_BS_DISPATCH(Z.bs, k_restrict, <<<grid, kThreads, 0, s>>>(Z.rowptr, Z.colidx, Z.vals, Z.nb, Z.bs, G, r, cpts,
                                                                   rc, gate));
@@ -509,7 +525,7 @@ void launch_restrict_T(const int *ptptr, const int *ptidx, const VT *sv, VT *sc,
 
 template <typename MT, typename VT>
 void launch_interp_T(const MatView<MT> &ZT, const int *cidx, const VT *yc, VT *y, hipStream_t s, Gate gate) {
-    const int G = groups_for(ZT.nnzb, ZT.nb, ZT.bs);
+    const int G = groups_for(ZT);
     const unsigned grid = grid_rows(ZT.nb, G, ZT.bs);
     NAIR_BS_DISPATCH(ZT.bs, k_interp_T, <<<grid, kThreads, 0, s>>>(ZT.rowptr, ZT.colidx, ZT.vals, ZT.nb, ZT.bs, G,
                                                                    cidx, yc, y, gate));

@@ -9,9 +9,22 @@
 
 namespace nair {
 
+// Cycle kernels with a tunable lane-group count, per level.
+enum TuneKind {
+    TU_RELAX = 0,       // Jacobi sweeps with A (F rows; also the C sweep)
+    TU_RELAX_T = 1,     // transposed sweeps with A^T
+    TU_RESIDUAL_T = 2,  // s = g - A^T y in the transposed cycle (and the outer transposed residual)
+    TU_RESTRICT = 3,    // r_c = r_C + Z r_F
+    TU_INTERP_T = 4,    // y += R^T y_c
+    TU_RESIDUAL = 5,    // outer residual b - A x (level 0)
+    TU_KINDS = 6
+};
+constexpr int kTuneLevels = 64;
+
 struct Level {
     DevBSR A;                       // level operator (A_0 = copy of the input, then K = R A P)
     bool coarsest = false;          // every system left is solved directly here
+    int8_t tune[TU_KINDS] = {0, 0, 0, 0, 0, 0};   // lane groups per kernel (0: from the row length)
     // systems on this level: a batched hierarchy holds several independent
     // systems, each a contiguous range of block rows (one system otherwise)
     std::vector<int> seg;           // nsys + 1 block offsets
@@ -89,6 +102,12 @@ nair_status run_solve_batch(Hier &h, bool trans, const double *b, double *x, dou
                             bool use_graph, nair_result *res, hipStream_t s);
 void run_vcycle(Hier &h, bool trans, const double *r, double *e, hipStream_t s);
 void ensure_transposes(Hier &h, hipStream_t s);
+// Time every feasible lane-group count of each cycle kernel on each level and
+// keep the fastest (reps launches per candidate); table (host, may be null)
+// receives [kTuneLevels][TU_KINDS].
+void autotune(Hier &h, int reps, int8_t *table, hipStream_t s);
+void apply_tuning(Hier &h, const int8_t *table);
+void drop_graphs(Hier &h);
 void make_fp32_copies(Hier &h, hipStream_t s);
 void complexity(Hier &h, double *oc, double *cc, hipStream_t s);
 

@@ -29,10 +29,10 @@ struct Store;
 
 template <>
 struct Store<double> {
-    static MatView<double> A(const Level &L) { return view(L.A); }
-    static MatView<double> Z(const Level &L) { return view(L.Z); }
-    static MatView<double> AT(const Level &L) { return view(L.AT); }
-    static MatView<double> ZT(const Level &L) { return view(L.ZT); }
+    static MatView<double> A(const Level &L) { return view(L.A).with_groups(L.tune[TU_RELAX]); }
+    static MatView<double> Z(const Level &L) { return view(L.Z).with_groups(L.tune[TU_RESTRICT]); }
+    static MatView<double> AT(const Level &L) { return view(L.AT).with_groups(L.tune[TU_RELAX_T]); }
+    static MatView<double> ZT(const Level &L) { return view(L.ZT).with_groups(L.tune[TU_INTERP_T]); }
     static double *r(Level &L) { return L.r.get(); }
     static double *e0(Level &L) { return L.e0.get(); }
     static double *e1(Level &L) { return L.e1.get(); }
@@ -41,10 +41,10 @@ struct Store<double> {
 
 template <>
 struct Store<float> {
-    static MatView<float> A(const Level &L) { return view(L.A, L.vals32.get()); }
-    static MatView<float> Z(const Level &L) { return view(L.Z, L.z32.get()); }
-    static MatView<float> AT(const Level &L) { return view(L.AT, L.at32.get()); }
-    static MatView<float> ZT(const Level &L) { return view(L.ZT, L.zt32.get()); }
+    static MatView<float> A(const Level &L) { return view(L.A, L.vals32.get()).with_groups(L.tune[TU_RELAX]); }
+    static MatView<float> Z(const Level &L) { return view(L.Z, L.z32.get()).with_groups(L.tune[TU_RESTRICT]); }
+    static MatView<float> AT(const Level &L) { return view(L.AT, L.at32.get()).with_groups(L.tune[TU_RELAX_T]); }
+    static MatView<float> ZT(const Level &L) { return view(L.ZT, L.zt32.get()).with_groups(L.tune[TU_INTERP_T]); }
     static float *r(Level &L) { return L.r32.get(); }
     static float *e0(Level &L) { return L.e0_32.get(); }
     static float *e1(Level &L) { return L.e1_32.get(); }
@@ -132,7 +132,8 @@ const T *vcycle_T(Hier &h, int l, hipStream_t s) {
             std::swap(cur, oth);
         }
     }
-    launch_residual<T, T>(AT, S::r(L), cur, S::tmp(L), nullptr, nullptr, s, gate(h, L));
+    launch_residual<T, T>(AT.with_groups(L.tune[TU_RESIDUAL_T]), S::r(L), cur, S::tmp(L), nullptr, nullptr, s,
+                          gate(h, L));
     launch_restrict_T<T>(L.ptptr.get(), L.ptidx.get(), S::tmp(L), S::r(C), L.nc, bs, s, gate(h, C));
     const T *yc = vcycle_T<T>(h, l + 1, s);
     launch_interp_T<T, T>(S::ZT(L), L.cidx.get(), yc, cur, s, gate(h, L));
@@ -143,7 +144,7 @@ const T *vcycle_T(Hier &h, int l, hipStream_t s) {
 
 void ensure_work(Hier &h) {
     const Level &L0 = *h.lv[0];
-    const int np = std::max(residual_partials_count(view(L0.A)),
+    const int np = std::max(residual_partials_max(L0.A.nb, h.bs),
                             sumsq_partials_count(static_cast<int64_t>(L0.A.nb) * h.bs));
     if (h.npart < np) {
         h.partials.alloc(np);
@@ -176,7 +177,8 @@ nair_status run_solve(Hier &h, bool trans, const double *b, double *x, double rt
     } else {
         NAIR_HIP(hipMemcpyAsync(L0.r.get(), b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
         if (fp32) launch_to_float(b, L0.r32.get(), n, s);
-        const MatView<double> Aop = trans ? view(L0.AT) : view(L0.A);
+        const MatView<double> Aop = trans ? view(L0.AT).with_groups(L0.tune[TU_RESIDUAL_T])
+                                          : view(L0.A).with_groups(L0.tune[TU_RESIDUAL]);
         double rel = 1.0;
         for (int it = 0; it < max_iter; ++it) {
             if (fp32) {
@@ -186,6 +188,7 @@ nair_status run_solve(Hier &h, bool trans, const double *b, double *x, double rt
                 const double *e = trans ? vcycle_T<double>(h, 0, s) : vcycle<double>(h, 0, s);
                 launch_axpy<double>(x, e, n, s);
             }
+            if (residual_partials_count(Aop) > h.npart) fail(NAIR_EDEVICE, "residual partials buffer too small");
             {
                 TimerScope ts(TK_RESIDUAL, 0, s);
                 launch_residual<double, double>(Aop, b, x, L0.r.get(), h.partials.get(),
@@ -283,7 +286,8 @@ void batch_iteration(Hier &h, bool trans, const double *b, double *x, hipStream_
     const bool fp32 = std::is_same<T, float>::value;
     const T *e = trans ? vcycle_T<T>(h, 0, s) : vcycle<T>(h, 0, s);
     launch_axpy_active<T>(x, e, n, h.bs, L0.bsys.get(), B.active.get(), s);
-    const MatView<double> Aop = trans ? view(L0.AT) : view(L0.A);
+    const MatView<double> Aop = trans ? view(L0.AT).with_groups(L0.tune[TU_RESIDUAL_T])
+                                      : view(L0.A).with_groups(L0.tune[TU_RESIDUAL]);
     {
         TimerScope ts(TK_RESIDUAL, 0, s);
         launch_residual<double, double>(Aop, b, x, L0.r.get(), nullptr, fp32 ? L0.r32.get() : nullptr, s,

@@ -23,7 +23,10 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ESINGULAR", 3: "ENOCONV", 4: "ENUMERIC", 5: 
 EXPORTED = ["nair_default_params", "nair_setup", "nair_solve", "nair_solve_T", "nair_vcycle",
             "nair_vcycle_T", "nair_history", "nair_info", "nair_get_level", "nair_last_error",
             "nair_destroy", "nair_pool_trim", "nair_timer_select", "nair_timer_read", "nair_grad_vals",
-            "nair_setup_batch", "nair_solve_batch", "nair_batch_history", "nair_get_systems"]
+            "nair_setup_batch", "nair_solve_batch", "nair_batch_history", "nair_get_systems",
+            "nair_autotune"]
+
+TUNE_KINDS = ("relax", "relax_T", "residual_T", "restrict", "interp_T", "residual")
 
 KERNELS = {"relax": 0, "residual": 1, "restrict": 2, "interp": 3, "spgemm_numeric": 4,
            "spgemm_symbolic": 5, "block_inverse": 6, "galerkin": 7, "dense": 8}
@@ -40,7 +43,7 @@ class _Params(C.Structure):
     _fields_ = [("degree", C.c_int32), ("theta", C.c_double), ("phi", C.c_double),
                 ("drop", C.c_double), ("relax", C.c_int32), ("max_levels", C.c_int32),
                 ("max_coarse_dofs", C.c_int32), ("seed", C.c_uint64),
-                ("cf_override_host", C.c_void_p), ("precision", C.c_int32)]
+                ("cf_override_host", C.c_void_p), ("precision", C.c_int32), ("tuning", C.c_void_p)]
 
 
 class _Result(C.Structure):
@@ -107,6 +110,8 @@ def lib():
         L.nair_batch_history.restype = C.c_int
         L.nair_get_systems.argtypes = [vp, i32, i32, C.POINTER(i32), vp, vp, vp]
         L.nair_get_systems.restype = C.c_int
+        L.nair_autotune.argtypes = [vp, i32, vp, vp]
+        L.nair_autotune.restype = C.c_int
         _lib = L
     return _lib
 
@@ -151,6 +156,7 @@ class Params:
     seed: int = 0
     cf_override: Optional[np.ndarray] = None
     precision: str = "fp64"      # "fp64" or "fp32" (FP32-stored hierarchy, FP64 refinement)
+    tuning: Optional[np.ndarray] = None   # [levels, 6] lane groups from Hierarchy.autotune
 
 
 @dataclass
@@ -193,6 +199,12 @@ class Hierarchy:
         if params.cf_override is not None:
             cf = np.ascontiguousarray(params.cf_override, dtype=np.int8)
             p.cf_override_host = cf.ctypes.data
+        tune = None
+        if params.tuning is not None:
+            t = np.asarray(params.tuning, dtype=np.int8)
+            tune = np.zeros((64, len(TUNE_KINDS)), dtype=np.int8)
+            tune[:t.shape[0]] = t
+            p.tuning = tune.ctypes.data
         h = C.c_void_p()
         if sys_nb is None:
             self.nsys = 1
@@ -278,6 +290,16 @@ class Hierarchy:
                 s_k = "ENOCONV"
             out.append(Result(s_k, r.iters, bool(r.converged), r.relres, r.rho_avg, r.rho_last5))
         return x, out
+
+    def autotune(self, reps: int = 20, stream=None) -> np.ndarray:
+        """Time the lane-group choices of every cycle kernel on every level and
+        keep the fastest; returns the [levels, 6] table (0 = default) for
+        Params(tuning=...) of later hierarchies of the same structure."""
+        table = np.zeros((64, len(TUNE_KINDS)), dtype=np.int8)
+        st = lib().nair_autotune(self._h, int(reps), table.ctypes.data_as(C.c_void_p), _stream_ptr(stream))
+        if st != 0:
+            raise NairError(st, "nair_autotune", self._err())
+        return table[:self.num_levels].copy()
 
     def batch_history(self, sys: int):
         n = C.c_int32()
