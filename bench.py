@@ -47,6 +47,22 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
+def measured_traffic(workload: str, grid_threads: int):
+    """HBM bytes per launch of the level-0 sweep from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE runs, scaled by reference kernels), or
+    None when there is none for this launch shape or the kernel source has
+    changed since it was measured."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_relax_traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_1704_05001_amd", "csrc", "cycle.hip"), "rb").read()
+    if d.get("cycle_hip_sha256") != hashlib.sha256(src).hexdigest() or d.get("grid") != grid_threads:
+        return None
+    return float(d["traffic_bytes"])
+
+
 def relax_level_bytes(lv: dict) -> dict:
     """Algorithmic HBM bytes of one F-relaxation sweep on a level: each operand
     read once, each output written once (int32 indices, FP64 values)."""
@@ -306,11 +322,21 @@ def main(argv=None):
         rb = relax_level_bytes(lvl)
         avg_ms = kernel_ms / launches
         achieved = rb["bytes"] / (avg_ms * 1e-3) / 1e9
+        # launch shape of the timed kernel: G lane groups of bs lanes per block row, 256-thread workgroups
+        G = int(tuning[args.roofline_level][0]) if tuning is not None and len(tuning) > args.roofline_level else 0
+        if G <= 0:
+            avg_row = lvl["nnzb"] / max(1, lvl["nb"])
+            G = 1 if avg_row <= 3.5 else (2 if avg_row <= 7.0 else (4 if avg_row <= 14.0 else 8))
+        while G > 1 and G * lvl["bs"] > 256:
+            G //= 2
+        rows_per_wg = 256 // (G * lvl["bs"])
+        grid_threads = -(-rb["nF"] // rows_per_wg) * 256
         roof = {"bound": "hbm", "kernel": f"k_relax (level {args.roofline_level} F sweep)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(args.workload, grid_threads),
                 "bytes_per_launch": rb["bytes"], "avg_launch_us": round(avg_ms * 1e3, 2),
-                "launches": launches}
+                "launches": launches, "lane_groups": G, "grid_threads": grid_threads}
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "DOFs/s", "n_gpus": 1,

@@ -125,14 +125,14 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int *__restrict__ r
 }
 
 // One Jacobi sweep over the listed rows (list == nullptr: rows with cf == only_cf;
-// the other rows copy e_in): e_out_I = e_in_I + D_I^{-1} (r_I - (A e_in)_I).
-template <int BS, typename MT, typename VT>
-__global__ __launch_bounds__(kThreads) void k_relax(const int *__restrict__ rowptr, const int *__restrict__ colidx,
-                                                   const MT *__restrict__ vals, const double *__restrict__ dinv,
-                                                   int dinv_trans, int nb, int bs_rt, int G,
-                                                   const VT *__restrict__ r, const VT *__restrict__ ein,
-                                                   VT *__restrict__ eout, const int *__restrict__ list, int nlist,
-                                                   const int8_t *__restrict__ cf, int only_cf, Gate gate) {
+// the other rows copy e_in): e_out_I = e_in_I + D_I^{-1} (r_I - (A e_in)_I), or
+// with D_I^{-T} (TRANS: the sweeps of the transposed cycle, with A^T's rows).
+template <int BS, typename MT, typename VT, bool TRANS>
+__device__ inline void relax_rows(const int *__restrict__ rowptr, const int *__restrict__ colidx,
+                                  const MT *__restrict__ vals, const double *__restrict__ dinv, int nb, int bs_rt,
+                                  int G, const VT *__restrict__ r, const VT *__restrict__ ein, VT *__restrict__ eout,
+                                  const int *__restrict__ list, int nlist, const int8_t *__restrict__ cf, int only_cf,
+                                  Gate gate) {
     __shared__ double part[kThreads];
     __shared__ double tb[kThreads];
     const int bs = Bs<BS>::get(bs_rt);
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kThreads) void k_relax(const int *__restrict__ rowp
             const double *D = dinv + static_cast<int64_t>(I) * bs * bs;
             const double *t = tb + L.lr * bs;
             double d0 = 0.0, d1 = 0.0;
-            if (dinv_trans) {
+            if (TRANS) {
 #pragma unroll
                 for (int c = 0; c < (BS > 0 ? BS : kMaxBs); c += 2) {
                     if (BS == 0 && c >= bs) break;
@@ -173,6 +173,28 @@ __global__ __launch_bounds__(kThreads) void k_relax(const int *__restrict__ rowp
             eout[o] = ein[o];
         }
     }
+}
+
+template <int BS, typename MT, typename VT>
+__global__ __launch_bounds__(kThreads) void k_relax(const int *__restrict__ rowptr, const int *__restrict__ colidx,
+                                                   const MT *__restrict__ vals, const double *__restrict__ dinv,
+                                                   int nb, int bs_rt, int G, const VT *__restrict__ r,
+                                                   const VT *__restrict__ ein, VT *__restrict__ eout,
+                                                   const int *__restrict__ list, int nlist,
+                                                   const int8_t *__restrict__ cf, int only_cf, Gate gate) {
+    relax_rows<BS, MT, VT, false>(rowptr, colidx, vals, dinv, nb, bs_rt, G, r, ein, eout, list, nlist, cf, only_cf,
+                                  gate);
+}
+
+template <int BS, typename MT, typename VT>
+__global__ __launch_bounds__(kThreads) void k_relax_T(const int *__restrict__ rowptr, const int *__restrict__ colidx,
+                                                     const MT *__restrict__ vals, const double *__restrict__ dinv,
+                                                     int nb, int bs_rt, int G, const VT *__restrict__ r,
+                                                     const VT *__restrict__ ein, VT *__restrict__ eout,
+                                                     const int *__restrict__ list, int nlist,
+                                                     const int8_t *__restrict__ cf, int only_cf, Gate gate) {
+    relax_rows<BS, MT, VT, true>(rowptr, colidx, vals, dinv, nb, bs_rt, G, r, ein, eout, list, nlist, cf, only_cf,
+                                 gate);
 }
 
 // rc_i = r_{cpts[i]} + sum_t Z_it r_{col t}
@@ -491,9 +513,13 @@ void launch_relax(const MatView<MT> &A, const double *dinv, bool dinv_trans, con
     if (N <= 0) return;
     const int G = groups_for(A);
     const unsigned grid = grid_rows(N, G, A.bs);
-    NAIR_BS_DISPATCH(A.bs, k_relax, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, dinv, dinv_trans ? 1 : 0,
-                                                               A.nb, A.bs, G, r, ein, eout, list, nlist, cf, only_cf,
-                                                               gate));
+    if (dinv_trans) {
+        NAIR_BS_DISPATCH(A.bs, k_relax_T, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, dinv, A.nb, A.bs, G,
+                                                                     r, ein, eout, list, nlist, cf, only_cf, gate));
+    } else {
+        NAIR_BS_DISPATCH(A.bs, k_relax, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, dinv, A.nb, A.bs, G,
+                                                                   r, ein, eout, list, nlist, cf, only_cf, gate));
+    }
     NAIR_HIP(hipGetLastError());
 }
 

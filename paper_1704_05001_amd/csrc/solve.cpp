@@ -88,14 +88,11 @@ const T *vcycle(Hier &h, int l, hipStream_t s) {
     }
     T *cur = S::e0(L), *oth = S::e1(L);
     const MatView<T> A = S::A(L);
-    {
-        // the nu sweeps run back to back; the timer brackets them as one group
-        TimerScope ts(TK_RELAX, l, s, h.prm.degree + 1);
-        for (int k = 0; k <= h.prm.degree; ++k) {
-            launch_relax<T, T>(A, L.dinv.get(), false, S::r(L), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s,
-                               gate(h, L));
-            std::swap(cur, oth);
-        }
+    for (int k = 0; k <= h.prm.degree; ++k) {
+        TimerScope ts(TK_RELAX, l, s);
+        launch_relax<T, T>(A, L.dinv.get(), false, S::r(L), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s,
+                           gate(h, L));
+        std::swap(cur, oth);
     }
     if (h.prm.relax == 1) {
         launch_relax<T, T>(A, L.dinv.get(), false, S::r(L), cur, oth, nullptr, 0, L.cf.get(), 1, s, gate(h, L));
@@ -124,13 +121,11 @@ const T *vcycle_T(Hier &h, int l, hipStream_t s) {
                      gate(h, L));
     T *cur = S::e0(L), *oth = S::e1(L);
     const MatView<T> AT = S::AT(L);
-    {
-        TimerScope ts(TK_RELAX, l, s, h.prm.degree + 1);
-        for (int k = 0; k <= h.prm.degree; ++k) {
-            launch_relax<T, T>(AT, L.dinv.get(), true, S::r(L), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s,
-                               gate(h, L));
-            std::swap(cur, oth);
-        }
+    for (int k = 0; k <= h.prm.degree; ++k) {
+        TimerScope ts(TK_RELAX, l, s);
+        launch_relax<T, T>(AT, L.dinv.get(), true, S::r(L), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s,
+                           gate(h, L));
+        std::swap(cur, oth);
     }
     launch_residual<T, T>(AT.with_groups(L.tune[TU_RESIDUAL_T]), S::r(L), cur, S::tmp(L), nullptr, nullptr, s,
                           gate(h, L));
