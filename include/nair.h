@@ -231,10 +231,13 @@ nair_status nair_pool_trim(void);
 /*
  * Kernel timer (profiling).  nair_timer_select(kernel, level) makes the
  * library bracket every later launch of that kernel on that level (-1: all
- * levels) with a pair of HIP events on the launch's stream (the nu F sweeps
- * of one cycle visit run back to back and are bracketed as one group of nu
- * launches); kernel = -1 turns the timer off.  Kernels: 0 F/FC relaxation sweep, 1 residual, 2 restriction,
- * 3 interpolation, 4 SpGEMM numeric, 5 SpGEMM symbolic, 6 block inverse,
+ * levels) with a pair of HIP events on the launch's stream (the F sweeps of
+ * one cycle visit run back to back and are bracketed as one group);
+ * kernel = -1 turns the timer off.  Kernels: 0 Jacobi F sweep over
+ * the F-row list (both cycles; the FC C sweep and the transposed cycle's first
+ * sweep from zero, which reads no matrix, are not timed), 1 outer residual,
+ * 2 restriction, 3 interpolation, 4 SpGEMM numeric, 5 SpGEMM symbolic,
+ * 6 block inverse,
  * 7 Galerkin merge, 8 dense coarsest product.  nair_timer_read (host outputs)
  * synchronises the device and returns the number of timed launches and their
  * total duration in milliseconds, then resets the counters.  Host only; one

@@ -216,26 +216,24 @@ __device__ inline bool live(const Gate &g, int row) {
     return g.active == nullptr || g.active[g.bsys ? g.bsys[row] : 0] != 0;
 }
 
-template <typename MT>
-int residual_partials_count(const MatView<MT> &A);
-// the most partials any lane-group choice produces for a residual of nb block rows
-int residual_partials_max(int nb, int bs);
-// r = b - A x (+ squared-norm partials per workgroup if partials, + float copy if r_lo)
+// r = b - A x (+ a float copy if r_lo)
 template <typename MT, typename VT>
-void launch_residual(const MatView<MT> &A, const VT *b, const VT *x, VT *r, double *partials, float *r_lo,
-                     hipStream_t s, Gate g = Gate());
-void launch_sumsq(const double *v, int64_t n, double *partials, hipStream_t s);
-int sumsq_partials_count(int64_t n);
-void launch_reduce_partials(const double *partials, int npart, double *out, hipStream_t s);
+void launch_residual(const MatView<MT> &A, const VT *b, const VT *x, VT *r, float *r_lo, hipStream_t s,
+                     Gate g = Gate());
 // Jacobi sweep over `list` rows (list == nullptr: all rows; then rows with cf != only_cf are copied)
 template <typename MT, typename VT>
 void launch_relax(const MatView<MT> &A, const double *dinv, bool dinv_trans, const VT *r, const VT *ein, VT *eout,
                   const int *list, int nlist, const int8_t *cf, int only_cf, hipStream_t s, Gate g = Gate());
+// The first transposed F sweep from a zero guess: e1_F = D_F^{-T} r_F, other rows 0 in e0 and e1
+template <typename VT>
+void launch_relax_T_first(const double *dinv, const VT *r, const int8_t *cf, VT *e0, VT *e1, int nb, int bs,
+                          hipStream_t s, Gate g = Gate());
+// e0 = e1 = P e_c (one-point: block I takes e_c[pmap I], or zero)
+template <typename VT>
+void launch_interp(const int *pmap, const VT *ec, VT *e0, VT *e1, int nb, int bs, hipStream_t s, Gate g = Gate());
 // gate of the coarse rows (coarse-level system ids)
 template <typename MT, typename VT>
 void launch_restrict(const MatView<MT> &Z, const VT *r, const int *cpts, VT *rc, hipStream_t s, Gate g = Gate());
-template <typename VT>
-void launch_interp(const int *pmap, const VT *ec, VT *e0, VT *e1, int nb, int bs, hipStream_t s, Gate g = Gate());
 template <typename VT>
 void launch_restrict_T(const int *ptptr, const int *ptidx, const VT *s, VT *sc, int nc, int bs, hipStream_t st,
                        Gate g = Gate());

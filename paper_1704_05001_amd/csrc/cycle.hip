@@ -30,16 +30,27 @@ struct Bs<0> {
     __device__ static int get(int bs) { return bs; }
 };
 
+// Where a row product reads the block vector of column J.
+template <typename VT>
+struct PlainSrc {
+    const VT *x;
+    int bs;
+    static constexpr bool kMaySkip = false;
+    __device__ const VT *row(int j) const { return x + static_cast<int64_t>(j) * bs; }
+};
 // sum over blocks t = lo+g, lo+g+G, ... < hi of (block t row a) . x[col t]
-template <int BS, typename MT, typename VT>
-__device__ inline double row_part(const int *__restrict__ colidx, const MT *__restrict__ vals, int lo, int hi, int g,
-                                  int G, int a, int bs_rt, const VT *__restrict__ x) {
+template <int BS, typename MT, typename VT, typename SRC>
+__device__ inline double row_part_src(const int *__restrict__ colidx, const MT *__restrict__ vals, int lo, int hi,
+                                      int g, int G, int a, int bs_rt, const SRC &src) {
     const int bs = Bs<BS>::get(bs_rt);
     const int64_t bb = static_cast<int64_t>(bs) * bs;
     double acc0 = 0.0, acc1 = 0.0;
     for (int t = lo + g; t < hi; t += G) {
         const MT *blk = vals + t * bb + a * bs;
-        const VT *xj = x + static_cast<int64_t>(colidx[t]) * bs;
+        const VT *xj = src.row(colidx[t]);
+        if constexpr (SRC::kMaySkip) {
+            if (xj == nullptr) continue;
+        }
         if constexpr (BS > 0) {
 #pragma unroll
             for (int c = 0; c < BS; c += 2) {
@@ -52,6 +63,30 @@ __device__ inline double row_part(const int *__restrict__ colidx, const MT *__re
         }
     }
     return acc0 + acc1;
+}
+
+template <int BS, typename MT, typename VT>
+__device__ inline double row_part(const int *__restrict__ colidx, const MT *__restrict__ vals, int lo, int hi, int g,
+                                  int G, int a, int bs_rt, const VT *__restrict__ x) {
+    return row_part_src<BS, MT, VT>(colidx, vals, lo, hi, g, G, a, bs_rt, PlainSrc<VT>{x, Bs<BS>::get(bs_rt)});
+}
+
+// D_I^{-1} t (TRANS: D_I^{-T} t) for scalar row a, with t in LDS.
+template <int BS, bool TRANS>
+__device__ inline double apply_dinv(const double *__restrict__ D, const double *t, int a, int bs) {
+    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+    for (int c = 0; c < (BS > 0 ? BS : kMaxBs); c += 2) {
+        if (BS == 0 && c >= bs) break;
+        if (TRANS) {
+            d0 += D[c * bs + a] * t[c];
+            if (c + 1 < bs) d1 += D[(c + 1) * bs + a] * t[c + 1];
+        } else {
+            d0 += D[a * bs + c] * t[c];
+            if (c + 1 < bs) d1 += D[a * bs + c + 1] * t[c + 1];
+        }
+    }
+    return d0 + d1;
 }
 
 struct Lane {
@@ -94,33 +129,24 @@ __device__ inline double block_reduce_sum(double v, double *lds) {
     return s;   // valid in thread 0
 }
 
-// r = b - A x; partials[block] = sum of r^2 over the workgroup (if partials);
-// r_lo (if given) receives r rounded to float.
+// r = b - A x; r_lo (if given) receives r rounded to float.
 template <int BS, typename MT, typename VT>
 __global__ __launch_bounds__(kThreads) void k_residual(const int *__restrict__ rowptr, const int *__restrict__ colidx,
                                                       const MT *__restrict__ vals, int nb, int bs_rt, int G,
                                                       const VT *__restrict__ b, const VT *__restrict__ x,
-                                                      VT *__restrict__ r, double *__restrict__ partials,
-                                                      float *__restrict__ r_lo, Gate gate) {
+                                                      VT *__restrict__ r, float *__restrict__ r_lo, Gate gate) {
     __shared__ double part[kThreads];
-    __shared__ double red[kThreads / 64];
     const int bs = Bs<BS>::get(bs_rt);
     const Lane L = lane_of(G, bs);
     const int I = blockIdx.x * (kThreads / (G * bs)) + L.lr;
     const bool act = L.valid && I < nb && live(gate, I);
     double acc = act ? row_part<BS>(colidx, vals, rowptr[I], rowptr[I + 1], L.g, G, L.a, bs, x) : 0.0;
     acc = reduce_groups(acc, L, G, bs, part);
-    double v = 0.0;
     if (act && L.g == 0) {
         const int64_t o = static_cast<int64_t>(I) * bs + L.a;
         const double rv = static_cast<double>(b[o]) - acc;
         r[o] = static_cast<VT>(rv);
         if (r_lo) r_lo[o] = static_cast<float>(rv);
-        v = rv * rv;
-    }
-    if (partials) {
-        const double s = block_reduce_sum(v, red);
-        if (threadIdx.x == 0) partials[blockIdx.x] = s;
     }
 }
 
@@ -150,28 +176,39 @@ __device__ inline void relax_rows(const int *__restrict__ rowptr, const int *__r
     __syncthreads();
     if (I >= 0 && L.g == 0) {
         if (upd) {
-            const double *D = dinv + static_cast<int64_t>(I) * bs * bs;
-            const double *t = tb + L.lr * bs;
-            double d0 = 0.0, d1 = 0.0;
-            if (TRANS) {
-#pragma unroll
-                for (int c = 0; c < (BS > 0 ? BS : kMaxBs); c += 2) {
-                    if (BS == 0 && c >= bs) break;
-                    d0 += D[c * bs + L.a] * t[c];
-                    if (c + 1 < bs) d1 += D[(c + 1) * bs + L.a] * t[c + 1];
-                }
-            } else {
-#pragma unroll
-                for (int c = 0; c < (BS > 0 ? BS : kMaxBs); c += 2) {
-                    if (BS == 0 && c >= bs) break;
-                    d0 += D[L.a * bs + c] * t[c];
-                    if (c + 1 < bs) d1 += D[L.a * bs + c + 1] * t[c + 1];
-                }
-            }
-            eout[o] = static_cast<VT>(static_cast<double>(ein[o]) + (d0 + d1));
+            const double d = apply_dinv<BS, TRANS>(dinv + static_cast<int64_t>(I) * bs * bs, tb + L.lr * bs, L.a, bs);
+            eout[o] = static_cast<VT>(static_cast<double>(ein[o]) + d);
         } else {
             eout[o] = ein[o];
         }
+    }
+}
+
+// The first transposed F sweep from a zero guess (F relaxation only): e1_F =
+// D_F^{-T} r_F; every other row is zero in e0 and e1.  No matrix entries are
+// read: the sweep's product with A^T is a product with zero.
+template <typename VT>
+__global__ __launch_bounds__(kThreads) void k_relax_T_first(const double *__restrict__ dinv,
+                                                           const VT *__restrict__ r, const int8_t *__restrict__ cf,
+                                                           VT *__restrict__ e0, VT *__restrict__ e1, int nb, int bs,
+                                                           Gate gate) {
+    const int64_t gi = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (gi >= static_cast<int64_t>(nb) * bs) return;
+    const int I = static_cast<int>(gi / bs);
+    const int a = static_cast<int>(gi - static_cast<int64_t>(I) * bs);
+    if (!live(gate, I)) return;
+    if (cf[I] == 0) {
+        const double *D = dinv + static_cast<int64_t>(I) * bs * bs;
+        const VT *rI = r + static_cast<int64_t>(I) * bs;
+        double d0 = 0.0, d1 = 0.0;
+        for (int c = 0; c < bs; c += 2) {
+            d0 += D[c * bs + a] * static_cast<double>(rI[c]);
+            if (c + 1 < bs) d1 += D[(c + 1) * bs + a] * static_cast<double>(rI[c + 1]);
+        }
+        e1[gi] = static_cast<VT>(d0 + d1);
+    } else {
+        e0[gi] = VT(0);
+        e1[gi] = VT(0);
     }
 }
 
@@ -234,24 +271,6 @@ __global__ __launch_bounds__(kThreads) void k_interp_T(const int *__restrict__ z
         if (ci >= 0) acc += static_cast<double>(yc[static_cast<int64_t>(ci) * bs + L.a]);
         y[o] = static_cast<VT>(static_cast<double>(y[o]) + acc);
     }
-}
-
-__global__ __launch_bounds__(kThreads) void k_sumsq(const double *__restrict__ v, int64_t n,
-                                                   double *__restrict__ partials) {
-    __shared__ double lds[kThreads / 64];
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-    const double x = (g < n) ? v[g] : 0.0;
-    const double s = block_reduce_sum(x * x, lds);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
-__global__ __launch_bounds__(1024) void k_reduce_partials(const double *__restrict__ partials, int npart,
-                                                         double *__restrict__ out) {
-    __shared__ double lds[1024 / 64];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < npart; i += 1024) s += partials[i];
-    const double t = block_reduce_sum(s, lds);
-    if (threadIdx.x == 0) *out = t;
 }
 
 template <typename VT>
@@ -469,15 +488,6 @@ unsigned grid_rows(int64_t rows, int G, int bs) { return grid_for(rows, kThreads
         default: KERNEL<0, MT, VT> __VA_ARGS__; break;       \
     }
 
-template <typename MT>
-int residual_partials_count(const MatView<MT> &A) {
-    const int G = groups_for(A);
-    return static_cast<int>(grid_rows(A.nb, G, A.bs));
-}
-
-// more lane groups put fewer rows in a workgroup: the largest G gives the most workgroups
-int residual_partials_max(int nb, int bs) { return static_cast<int>(grid_rows(nb, max_groups(bs), bs)); }
-
 int max_groups(int bs) {
     int G = 1;
     while (2 * G * bs <= kThreads && G < 32) G *= 2;
@@ -485,24 +495,12 @@ int max_groups(int bs) {
 }
 
 template <typename MT, typename VT>
-void launch_residual(const MatView<MT> &A, const VT *b, const VT *x, VT *r, double *partials, float *r_lo,
-                     hipStream_t s, Gate gate) {
+void launch_residual(const MatView<MT> &A, const VT *b, const VT *x, VT *r, float *r_lo, hipStream_t s,
+                     Gate gate) {
     const int G = groups_for(A);
     const unsigned grid = grid_rows(A.nb, G, A.bs);
     NAIR_BS_DISPATCH(A.bs, k_residual, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, A.nb, A.bs, G, b, x, r,
-                                                                  partials, r_lo, gate));
-    NAIR_HIP(hipGetLastError());
-}
-
-void launch_sumsq(const double *v, int64_t n, double *partials, hipStream_t s) {
-    k_sumsq<<<grid_for(n, kThreads), kThreads, 0, s>>>(v, n, partials);
-    NAIR_HIP(hipGetLastError());
-}
-
-int sumsq_partials_count(int64_t n) { return static_cast<int>(grid_for(n, kThreads)); }
-
-void launch_reduce_partials(const double *partials, int npart, double *out, hipStream_t s) {
-    k_reduce_partials<<<1, 1024, 0, s>>>(partials, npart, out);
+                                                                  r_lo, gate));
     NAIR_HIP(hipGetLastError());
 }
 
@@ -520,6 +518,15 @@ void launch_relax(const MatView<MT> &A, const double *dinv, bool dinv_trans, con
         NAIR_BS_DISPATCH(A.bs, k_relax, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, dinv, A.nb, A.bs, G,
                                                                    r, ein, eout, list, nlist, cf, only_cf, gate));
     }
+    NAIR_HIP(hipGetLastError());
+}
+
+template <typename VT>
+void launch_relax_T_first(const double *dinv, const VT *r, const int8_t *cf, VT *e0, VT *e1, int nb, int bs,
+                          hipStream_t s, Gate gate) {
+    if (nb <= 0) return;
+    k_relax_T_first<VT><<<grid_for(static_cast<int64_t>(nb) * bs, kThreads), kThreads, 0, s>>>(dinv, r, cf, e0, e1,
+                                                                                                 nb, bs, gate);
     NAIR_HIP(hipGetLastError());
 }
 
@@ -621,13 +628,14 @@ void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s) {
 
 // instantiations: the FP64 cycle and the FP32-stored cycle
 #define NAIR_CYCLE_INST(MT, VT)                                                                                      \
-    template int residual_partials_count<MT>(const MatView<MT> &);                                                   \
-    template void launch_residual<MT, VT>(const MatView<MT> &, const VT *, const VT *, VT *, double *, float *,     \
-                                          hipStream_t, Gate);                                                        \
+    template void launch_residual<MT, VT>(const MatView<MT> &, const VT *, const VT *, VT *, float *, hipStream_t,  \
+                                          Gate);                                                                     \
     template void launch_relax<MT, VT>(const MatView<MT> &, const double *, bool, const VT *, const VT *, VT *,      \
                                        const int *, int, const int8_t *, int, hipStream_t, Gate);                    \
     template void launch_restrict<MT, VT>(const MatView<MT> &, const VT *, const int *, VT *, hipStream_t, Gate);    \
     template void launch_interp<VT>(const int *, const VT *, VT *, VT *, int, int, hipStream_t, Gate);               \
+    template void launch_relax_T_first<VT>(const double *, const VT *, const int8_t *, VT *, VT *, int, int,         \
+                                           hipStream_t, Gate);                                                       \
     template void launch_restrict_T<VT>(const int *, const int *, const VT *, VT *, int, int, hipStream_t, Gate);    \
     template void launch_interp_T<MT, VT>(const MatView<MT> &, const int *, const VT *, VT *, hipStream_t, Gate);    \
     template void launch_init_T<VT>(const double *, const VT *, const int8_t *, int, VT *, VT *, int, int,           \

@@ -85,8 +85,6 @@ struct Hier {
     std::vector<std::unique_ptr<Level>> lv;
     std::vector<double> hist;
     std::string err;
-    DBuf<double> partials, scal;
-    int npart = 0;
     BatchSolve batch;
     const int *active = nullptr;    // during a batched solve: per-system "still iterating" flags
 };

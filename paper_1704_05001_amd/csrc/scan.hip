@@ -1,4 +1,5 @@
-// Exclusive prefix sums of int32 arrays (three-phase: tile scan, tile-offset scan, add).
+// Exclusive prefix sums of int32 arrays: one workgroup for small arrays, else three
+// phases (tile scan, tile-offset scan, add).
 #include "common.h"
 
 namespace nair {
@@ -86,11 +87,65 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(int *__restrict__ out
     }
 }
 
+// Small arrays: one 1024-thread workgroup, each thread a contiguous run of at
+// most kSmallItems values.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallItems = 16;
+constexpr int kSmallMax = kSmallThreads * kSmallItems;
+
+__global__ __launch_bounds__(kSmallThreads) void k_scan_small(const int *__restrict__ in, int *__restrict__ out,
+                                                             int n) {
+    __shared__ int wsum[kSmallThreads / 64 + 1];
+    const int per = (n + kSmallThreads - 1) / kSmallThreads;
+    const int lo = threadIdx.x * per;
+    int v[kSmallItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kSmallItems; ++k) {
+        const int i = lo + k;
+        v[k] = (k < per && i < n) ? in[i] : 0;
+        s += v[k];
+    }
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    int x = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int w = 0; w < kSmallThreads / 64; ++w) {
+            const int t = wsum[w];
+            wsum[w] = run;
+            run += t;
+        }
+        wsum[kSmallThreads / 64] = run;
+    }
+    __syncthreads();
+    int pre = x - s + wsum[wave];
+#pragma unroll
+    for (int k = 0; k < kSmallItems; ++k) {
+        const int i = lo + k;
+        if (k < per && i < n) out[i] = pre;
+        pre += v[k];
+    }
+    if (threadIdx.x == 0) out[n] = wsum[kSmallThreads / 64];
+}
+
 }  // namespace
 
 void scan_exclusive(const int *in, int *out, int n, hipStream_t s) {
     if (n <= 0) {
         NAIR_HIP(hipMemsetAsync(out, 0, sizeof(int), s));
+        return;
+    }
+    if (n <= kSmallMax) {
+        k_scan_small<<<1, kSmallThreads, 0, s>>>(in, out, n);
+        NAIR_HIP(hipGetLastError());
         return;
     }
     const int ntiles = static_cast<int>((static_cast<int64_t>(n) + kScanTile - 1) / kScanTile);

@@ -229,16 +229,17 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
             split(h, L, l, s);
         }
         DBuf<int> cflag(n), cscan(static_cast<size_t>(n) + 1);
-        std::vector<int> cseg(nsys + 1);   // coarse blocks per system, as offsets
-        DBuf<int> cseg_d(nsys + 1);
+        std::vector<int> cseg(nsys + 2);   // coarse blocks per system, as offsets; then the singular flag
+        DBuf<int> cseg_d(nsys + 2);
         auto count_c = [&]() {
             launch_cf_flags(L.cf.get(), n, 1, cflag.get(), s);
             scan_exclusive(cflag.get(), cscan.get(), n, s);
             launch_gather_int(cscan.get(), L.seg_d.get(), nsys + 1, cseg_d.get(), s);
-            read_ints(cseg_d.get(), cseg.data(), nsys + 1, s);
+            NAIR_HIP(hipMemcpyAsync(cseg_d.get() + nsys + 1, sing.get(), sizeof(int), hipMemcpyDeviceToDevice, s));
+            read_ints(cseg_d.get(), cseg.data(), nsys + 2, s);
         };
         count_c();
-        const int hsing = read_int(sing.get(), s);
+        const int hsing = cseg[nsys + 1];
         if (hsing != kNoSingular)
             fail(NAIR_ESINGULAR, "diagonal block " + std::to_string(hsing) + " of level " + std::to_string(l) +
                                      " is singular");
@@ -354,7 +355,7 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         spgemm(L.Z, L.cpts.get(), L.A, RA, s);
         auto next = std::make_unique<Level>();
         rap_merge_drop(RA, L.pmap.get(), nc, p.drop, next->A, s);
-        next->seg = cseg;
+        next->seg.assign(cseg.begin(), cseg.begin() + nsys + 1);
         next->mode.assign(nsys, 0);
         h.lv.push_back(std::move(next));
     }

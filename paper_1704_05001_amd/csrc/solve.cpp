@@ -16,12 +16,6 @@
 namespace nair {
 namespace {
 
-double read_double(const double *d, hipStream_t s) {
-    double v = 0.0;
-    NAIR_HIP(hipMemcpyAsync(&v, d, sizeof(double), hipMemcpyDeviceToHost, s));
-    NAIR_HIP(hipStreamSynchronize(s));
-    return v;
-}
 
 // Per-precision access to a level's matrices and cycle vectors.
 template <typename T>
@@ -86,13 +80,16 @@ const T *vcycle(Hier &h, int l, hipStream_t s) {
         TimerScope ts(TK_INTERP, l, s);
         launch_interp<T>(L.pmap.get(), ec, S::e0(L), S::e1(L), L.A.nb, bs, s, gate(h, L));
     }
-    T *cur = S::e0(L), *oth = S::e1(L);
     const MatView<T> A = S::A(L);
-    for (int k = 0; k <= h.prm.degree; ++k) {
-        TimerScope ts(TK_RELAX, l, s);
-        launch_relax<T, T>(A, L.dinv.get(), false, S::r(L), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s,
-                           gate(h, L));
-        std::swap(cur, oth);
+    T *cur = S::e0(L), *oth = S::e1(L);
+    {
+        // the nu sweeps run back to back; one event pair brackets the group
+        TimerScope ts(TK_RELAX, l, s, h.prm.degree + 1);
+        for (int k = 0; k <= h.prm.degree; ++k) {
+            launch_relax<T, T>(A, L.dinv.get(), false, S::r(L), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s,
+                               gate(h, L));
+            std::swap(cur, oth);
+        }
     }
     if (h.prm.relax == 1) {
         launch_relax<T, T>(A, L.dinv.get(), false, S::r(L), cur, oth, nullptr, 0, L.cf.get(), 1, s, gate(h, L));
@@ -117,17 +114,25 @@ const T *vcycle_T(Hier &h, int l, hipStream_t s) {
         return S::e0(L);
     }
     Level &C = *h.lv[l + 1];
-    launch_init_T<T>(L.dinv.get(), S::r(L), L.cf.get(), h.prm.relax == 1 ? 1 : 0, S::e0(L), S::e1(L), L.A.nb, bs, s,
-                     gate(h, L));
-    T *cur = S::e0(L), *oth = S::e1(L);
     const MatView<T> AT = S::AT(L);
-    for (int k = 0; k <= h.prm.degree; ++k) {
-        TimerScope ts(TK_RELAX, l, s);
-        launch_relax<T, T>(AT, L.dinv.get(), true, S::r(L), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s,
-                           gate(h, L));
+    T *cur = S::e0(L), *oth = S::e1(L);
+    int k0 = 0;
+    if (h.prm.relax == 1) {   // C sweep first: y_C = D_C^{-T} g_C
+        launch_init_T<T>(L.dinv.get(), S::r(L), L.cf.get(), 1, S::e0(L), S::e1(L), L.A.nb, bs, s, gate(h, L));
+    } else {                  // the first F sweep from zero needs no product with A^T
+        launch_relax_T_first<T>(L.dinv.get(), S::r(L), L.cf.get(), S::e0(L), S::e1(L), L.A.nb, bs, s, gate(h, L));
         std::swap(cur, oth);
+        k0 = 1;
     }
-    launch_residual<T, T>(AT.with_groups(L.tune[TU_RESIDUAL_T]), S::r(L), cur, S::tmp(L), nullptr, nullptr, s,
+    {
+        TimerScope ts(TK_RELAX, l, s, h.prm.degree + 1 - k0);
+        for (int k = k0; k <= h.prm.degree; ++k) {
+            launch_relax<T, T>(AT, L.dinv.get(), true, S::r(L), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s,
+                               gate(h, L));
+            std::swap(cur, oth);
+        }
+    }
+    launch_residual<T, T>(AT.with_groups(L.tune[TU_RESIDUAL_T]), S::r(L), cur, S::tmp(L), nullptr, s,
                           gate(h, L));
     launch_restrict_T<T>(L.ptptr.get(), L.ptidx.get(), S::tmp(L), S::r(C), L.nc, bs, s, gate(h, C));
     const T *yc = vcycle_T<T>(h, l + 1, s);
@@ -137,89 +142,15 @@ const T *vcycle_T(Hier &h, int l, hipStream_t s) {
     return cur;
 }
 
-void ensure_work(Hier &h) {
-    const Level &L0 = *h.lv[0];
-    const int np = std::max(residual_partials_max(L0.A.nb, h.bs),
-                            sumsq_partials_count(static_cast<int64_t>(L0.A.nb) * h.bs));
-    if (h.npart < np) {
-        h.partials.alloc(np);
-        h.npart = np;
-    }
-    if (!h.scal.get()) h.scal.alloc(2);
-}
 
 }  // namespace
-
-nair_status run_solve(Hier &h, bool trans, const double *b, double *x, double rtol, int max_iter, nair_result *res,
-                      hipStream_t s) {
-    Level &L0 = *h.lv[0];
-    const int64_t n = static_cast<int64_t>(L0.A.nb) * h.bs;
-    const bool fp32 = h.prm.precision == 1;
-    if (trans) ensure_transposes(h, s);
-    ensure_work(h);
-    h.hist.clear();
-    nair_result rr{0, 0, 0.0, 0.0, 0.0};
-    NAIR_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
-    launch_sumsq(b, n, h.partials.get(), s);
-    launch_reduce_partials(h.partials.get(), sumsq_partials_count(n), h.scal.get(), s);
-    const double bn = std::sqrt(read_double(h.scal.get(), s));
-    nair_status st = NAIR_ENOCONV;
-    if (!std::isfinite(bn)) {
-        st = NAIR_ENUMERIC;
-    } else if (bn == 0.0) {
-        rr.converged = 1;
-        st = NAIR_OK;
-    } else {
-        NAIR_HIP(hipMemcpyAsync(L0.r.get(), b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-        if (fp32) launch_to_float(b, L0.r32.get(), n, s);
-        const MatView<double> Aop = trans ? view(L0.AT).with_groups(L0.tune[TU_RESIDUAL_T])
-                                          : view(L0.A).with_groups(L0.tune[TU_RESIDUAL]);
-        double rel = 1.0;
-        for (int it = 0; it < max_iter; ++it) {
-            if (fp32) {
-                const float *e = trans ? vcycle_T<float>(h, 0, s) : vcycle<float>(h, 0, s);
-                launch_axpy<float>(x, e, n, s);
-            } else {
-                const double *e = trans ? vcycle_T<double>(h, 0, s) : vcycle<double>(h, 0, s);
-                launch_axpy<double>(x, e, n, s);
-            }
-            if (residual_partials_count(Aop) > h.npart) fail(NAIR_EDEVICE, "residual partials buffer too small");
-            {
-                TimerScope ts(TK_RESIDUAL, 0, s);
-                launch_residual<double, double>(Aop, b, x, L0.r.get(), h.partials.get(),
-                                                fp32 ? L0.r32.get() : nullptr, s);
-            }
-            launch_reduce_partials(h.partials.get(), residual_partials_count(Aop), h.scal.get(), s);
-            rel = std::sqrt(read_double(h.scal.get(), s)) / bn;
-            h.hist.push_back(rel);
-            if (!std::isfinite(rel)) {
-                st = NAIR_ENUMERIC;
-                break;
-            }
-            if (rel <= rtol) {
-                st = NAIR_OK;
-                rr.converged = 1;
-                break;
-            }
-        }
-        rr.relres = rel;
-    }
-    rr.iters = static_cast<int32_t>(h.hist.size());
-    if (rr.iters > 0) {
-        const double hK = h.hist.back();
-        rr.rho_avg = std::pow(hK, 1.0 / rr.iters);
-        rr.rho_last5 = rr.iters > 5 ? std::pow(hK / h.hist[rr.iters - 6], 0.2) : rr.rho_avg;
-    }
-    if (res) *res = rr;
-    NAIR_HIP(hipStreamSynchronize(s));
-    return st;
-}
 
 namespace {
 
 constexpr int kChunk = 4096;        // dofs per norm chunk
 constexpr int kFirstPoll = 4;       // iterations before the first host check
 constexpr int kMaxRun = 64;         // most iterations launched between checks
+constexpr double kAim = 0.8;        // fraction of the predicted remaining iterations launched before a check
 
 // Chunk tables, per-system state and history storage of the batched iteration.
 void ensure_batch(Hier &h, int max_iter, hipStream_t s) {
@@ -285,7 +216,7 @@ void batch_iteration(Hier &h, bool trans, const double *b, double *x, hipStream_
                                       : view(L0.A).with_groups(L0.tune[TU_RESIDUAL]);
     {
         TimerScope ts(TK_RESIDUAL, 0, s);
-        launch_residual<double, double>(Aop, b, x, L0.r.get(), nullptr, fp32 ? L0.r32.get() : nullptr, s,
+        launch_residual<double, double>(Aop, b, x, L0.r.get(), fp32 ? L0.r32.get() : nullptr, s,
                                         gate(h, L0));
     }
     launch_seg_sumsq(L0.r.get(), B.clo.get(), B.clen.get(), B.nchunk, B.part.get(), s);
@@ -357,7 +288,6 @@ nair_status run_solve_batch(Hier &h, bool trans, const double *b, double *x, dou
     const int64_t n = static_cast<int64_t>(L0.A.nb) * h.bs;
     const bool fp32 = h.prm.precision == 1;
     if (trans) ensure_transposes(h, s);
-    ensure_work(h);
     ensure_batch(h, max_iter, s);
     B.rtol_host = rtol;
     NAIR_HIP(hipMemcpyAsync(B.rtol.get(), &B.rtol_host, sizeof(double), hipMemcpyHostToDevice, s));
@@ -391,8 +321,13 @@ nair_status run_solve_batch(Hier &h, bool trans, const double *b, double *x, dou
             need = std::max(need, nk);
         }
         prev = last;
-        run = static_cast<int>(std::min<double>(std::ceil(need), std::min(kMaxRun, max_iter - done)));
-        run = std::max(run, 1);
+        // aim a little short of the prediction and at most double the
+        // iterations done (early iterations converge slower than later ones, so
+        // an early prediction runs long): an iteration launched after every
+        // system has stopped costs its launches, one more check one round trip
+        const double cap = std::min<double>({static_cast<double>(kMaxRun), static_cast<double>(max_iter - done),
+                                             static_cast<double>(done)});
+        run = std::max(1, static_cast<int>(std::min(std::floor(kAim * need), cap)));
     }
 
     std::vector<int> st(nsys), it(nsys);
@@ -428,6 +363,13 @@ nair_status run_solve_batch(Hier &h, bool trans, const double *b, double *x, dou
     h.hist = B.hist_host.empty() ? std::vector<double>() : B.hist_host[0];
     NAIR_HIP(hipStreamSynchronize(s));
     return worst;
+}
+
+// One system: the same device-side iteration, launched eagerly (a graph
+// capture per call would cost more than it saves on one solve).
+nair_status run_solve(Hier &h, bool trans, const double *b, double *x, double rtol, int max_iter, nair_result *res,
+                      hipStream_t s) {
+    return run_solve_batch(h, trans, b, x, rtol, max_iter, false, res, s);
 }
 
 void run_vcycle(Hier &h, bool trans, const double *r, double *e, hipStream_t s) {

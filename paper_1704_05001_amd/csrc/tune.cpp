@@ -114,7 +114,7 @@ void tune_levels(Hier &h, int reps, hipStream_t s) {
             bs, reps, ev, s);
         L.tune[TU_RESIDUAL_T] = pick(
             [&](int G) {
-                launch_residual<T, T>(AT.with_groups(G), V::r(L), V::e0(L), V::tmp(L), nullptr, nullptr, s);
+                launch_residual<T, T>(AT.with_groups(G), V::r(L), V::e0(L), V::tmp(L), nullptr, s);
             },
             bs, reps, ev, s);
         L.tune[TU_RESTRICT] = pick(
@@ -130,9 +130,7 @@ void tune_levels(Hier &h, int reps, hipStream_t s) {
         clear_vectors<double>(L0, s);
         L0.tune[TU_RESIDUAL] = pick(
             [&](int G) {
-                const MatView<double> A0 = view(L0.A).with_groups(G);
-                if (residual_partials_count(A0) > h.npart) fail(NAIR_EDEVICE, "residual partials buffer too small");
-                launch_residual<double, double>(A0, L0.r.get(), L0.e0.get(), L0.tmp.get(), h.partials.get(),
+                launch_residual<double, double>(view(L0.A).with_groups(G), L0.r.get(), L0.e0.get(), L0.tmp.get(),
                                                 nullptr, s);
             },
             L0.A.bs, reps, ev, s);
@@ -151,14 +149,6 @@ void drop_graphs(Hier &h) {
 
 void autotune(Hier &h, int reps, int8_t *table, hipStream_t s) {
     ensure_transposes(h, s);
-    {   // partials for the outer residual
-        Level &L0 = *h.lv[0];
-        const int np = residual_partials_max(L0.A.nb, h.bs);
-        if (h.npart < np) {
-            h.partials.alloc(np);
-            h.npart = np;
-        }
-    }
     for (auto &Lp : h.lv) std::fill(Lp->tune, Lp->tune + TU_KINDS, static_cast<int8_t>(0));
     if (h.prm.precision == 1) tune_levels<float>(h, reps, s);
     else tune_levels<double>(h, reps, s);
