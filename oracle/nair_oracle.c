@@ -54,6 +54,9 @@ struct ora_hier {
     ora_params prm;
     int32_t nlev;
     level_t lv[ORA_MAX_LEVELS];
+    /* scalar form: the caller's block system and its block-diagonal inverse */
+    bsr_t A0;
+    double *d0inv;
 };
 
 /* ------------------------------------------------------------------ utils */
@@ -772,6 +775,7 @@ void ora_default_params(ora_params *p) {
     p->max_coarse_dofs = 128;
     p->seed = 0;
     p->cf_override = NULL;
+    p->form = 0;
 }
 
 static int validate(int32_t nb, int32_t bs, const int32_t *rowptr, const int32_t *colidx) {
@@ -810,7 +814,62 @@ static void level_free(level_t *L) {
 void ora_free(ora_hier *h) {
     if (!h) return;
     for (int32_t l = 0; l < ORA_MAX_LEVELS; ++l) level_free(&h->lv[l]);
+    bsr_free(&h->A0);
+    free(h->d0inv);
     free(h);
+}
+
+/*
+ * Scalar form (section "Blocks, filtering, and parallelization": most of the
+ * paper's results scale the system by the inverse of its block diagonal and
+ * run scalar nAIR on it).  S = D^{-1} A as a scalar CSR (1 x 1 blocks): the
+ * diagonal blocks of D^{-1} A are the identity by definition and are taken
+ * exactly (one entry 1 per row); an off-diagonal block is D_I^{-1} A_IJ (fma
+ * chains, c ascending from +0) and contributes every entry that is not exactly
+ * zero.  Columns ascend within each row.
+ */
+static int scaled_scalar(const bsr_t *A, const double *dinv, bsr_t *S) {
+    const int32_t bs = A->bs, bb = bs * bs;
+    const int64_t n = (int64_t)A->nb * bs;
+    double *M = (double *)malloc(sizeof(double) * (size_t)bb);
+    int64_t nnz = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        int64_t o = 0;
+        for (int32_t I = 0; I < A->nb; ++I)
+            for (int32_t a = 0; a < bs; ++a) {
+                for (int32_t t = A->rowptr[I]; t < A->rowptr[I + 1]; ++t) {
+                    const int32_t J = A->colidx[t];
+                    if (J == I) {
+                        if (pass) {
+                            S->colidx[o] = I * bs + a;
+                            S->vals[o] = 1.0;
+                        }
+                        ++o;
+                        continue;
+                    }
+                    block_mul(bs, dinv + (size_t)I * bb, A->vals + (size_t)t * bb, M);
+                    for (int32_t b = 0; b < bs; ++b)
+                        if (M[a * bs + b] != 0.0) {
+                            if (pass) {
+                                S->colidx[o] = J * bs + b;
+                                S->vals[o] = M[a * bs + b];
+                            }
+                            ++o;
+                        }
+                }
+                if (pass) S->rowptr[(int64_t)I * bs + a + 1] = (int32_t)o;
+            }
+        if (!pass) {
+            nnz = o;
+            if (nnz > 2147483647LL || bsr_alloc(S, (int32_t)n, (int32_t)n, 1, nnz) != ORA_OK) {
+                free(M);
+                return ORA_ENOMEM;
+            }
+            S->rowptr[0] = 0;
+        }
+    }
+    free(M);
+    return ORA_OK;
 }
 
 int ora_setup(int32_t nb, int32_t bs, const int32_t *rowptr, const int32_t *colidx,
@@ -829,10 +888,34 @@ int ora_setup(int32_t nb, int32_t bs, const int32_t *rowptr, const int32_t *coli
     int32_t bb = bs * bs;
     int64_t nnzb = rowptr[nb];
     level_t *L0 = &h->lv[0];
-    if ((st = bsr_alloc(&L0->A, nb, nb, bs, nnzb)) != ORA_OK) goto fail;
-    memcpy(L0->A.rowptr, rowptr, sizeof(int32_t) * ((size_t)nb + 1));
-    memcpy(L0->A.colidx, colidx, sizeof(int32_t) * (size_t)nnzb);
-    memcpy(L0->A.vals, vals, sizeof(double) * (size_t)nnzb * bb);
+    if (prm->form == 1) {
+        /* the caller's system, its block-diagonal inverse, and S = D^{-1} A as level 0 */
+        if ((st = bsr_alloc(&h->A0, nb, nb, bs, nnzb)) != ORA_OK) goto fail;
+        memcpy(h->A0.rowptr, rowptr, sizeof(int32_t) * ((size_t)nb + 1));
+        memcpy(h->A0.colidx, colidx, sizeof(int32_t) * (size_t)nnzb);
+        memcpy(h->A0.vals, vals, sizeof(double) * (size_t)nnzb * bb);
+        h->d0inv = (double *)xcalloc((size_t)nb * bb, sizeof(double));
+        if (!h->d0inv) {
+            st = ORA_ENOMEM;
+            goto fail;
+        }
+        for (int32_t I = 0; I < nb; ++I) {
+            int32_t t = rowptr[I];
+            while (colidx[t] != I) ++t;
+            if ((st = ora_block_inverse(bs, vals + (size_t)t * bb, h->d0inv + (size_t)I * bb)) != ORA_OK) goto fail;
+        }
+        if ((st = scaled_scalar(&h->A0, h->d0inv, &L0->A)) != ORA_OK) goto fail;
+        bs = 1;   /* the hierarchy is scalar */
+        bb = 1;
+    } else if (prm->form != 0) {
+        st = ORA_EINVAL;
+        goto fail;
+    } else {
+        if ((st = bsr_alloc(&L0->A, nb, nb, bs, nnzb)) != ORA_OK) goto fail;
+        memcpy(L0->A.rowptr, rowptr, sizeof(int32_t) * ((size_t)nb + 1));
+        memcpy(L0->A.colidx, colidx, sizeof(int32_t) * (size_t)nnzb);
+        memcpy(L0->A.vals, vals, sizeof(double) * (size_t)nnzb * bb);
+    }
 
     for (int32_t l = 0;; ++l) {
         level_t *L = &h->lv[l];
@@ -1056,15 +1139,17 @@ static void vcycle_T(const ora_hier *h, int32_t l, const double *g, double *y) {
     free(tmp);
 }
 
+static void precondition(const ora_hier *h, int trans, const double *r, double *e);
+
 int ora_vcycle(ora_hier *h, const double *r, double *e) {
     if (!h) return ORA_EINVAL;
-    vcycle(h, 0, r, e);
+    precondition(h, 0, r, e);
     return ORA_OK;
 }
 
 int ora_vcycle_T(ora_hier *h, const double *g, double *y) {
     if (!h) return ORA_EINVAL;
-    vcycle_T(h, 0, g, y);
+    precondition(h, 1, g, y);
     return ORA_OK;
 }
 
@@ -1076,10 +1161,34 @@ static double norm2(const double *v, int64_t n) {
 
 /* Stationary iteration x += B(b - A x) (or its transpose) from x = 0 with the
  * relative residual ||b - A x||_2 / ||b||_2 as the stopping test. */
+/* The preconditioner applied to a residual: B r, or for the scalar form
+ * B_S D^{-1} r (B_S the cycle of the scaled system); transposed: B^T r, or
+ * D^{-T} B_S^T r. */
+static void precondition(const ora_hier *h, int trans, const double *r, double *e) {
+    if (h->prm.form != 1) {
+        if (trans) vcycle_T(h, 0, r, e);
+        else vcycle(h, 0, r, e);
+        return;
+    }
+    const int32_t bs = h->A0.bs, bb = bs * bs;
+    const int64_t n = (int64_t)h->A0.nb * bs;
+    double *w = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!trans) {
+        for (int32_t I = 0; I < h->A0.nb; ++I)
+            block_apply(bs, h->d0inv + (size_t)I * bb, r + (size_t)I * bs, w + (size_t)I * bs, 0);
+        vcycle(h, 0, w, e);
+    } else {
+        vcycle_T(h, 0, r, w);
+        for (int32_t I = 0; I < h->A0.nb; ++I)
+            block_apply(bs, h->d0inv + (size_t)I * bb, w + (size_t)I * bs, e + (size_t)I * bs, 1);
+    }
+    free(w);
+}
+
 static int solve_impl(ora_hier *h, int trans, const double *b, double *x, double rtol, int32_t max_iter,
                       double *hist, int32_t *iters, double *relres) {
     if (!h || !b || !x) return ORA_EINVAL;
-    const bsr_t *A = &h->lv[0].A;
+    const bsr_t *A = h->prm.form == 1 ? &h->A0 : &h->lv[0].A;
     int64_t n = (int64_t)A->nb * A->bs;
     for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
     if (iters) *iters = 0;
@@ -1094,8 +1203,7 @@ static int solve_impl(ora_hier *h, int trans, const double *b, double *x, double
     double rel = 1.0;
     int32_t it = 0;
     while (it < max_iter) {
-        if (trans) vcycle_T(h, 0, r, e);
-        else vcycle(h, 0, r, e);
+        precondition(h, trans, r, e);
         for (int64_t i = 0; i < n; ++i) x[i] += e[i];
         if (trans) residual_T(A, b, x, r);
         else

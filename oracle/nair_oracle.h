@@ -50,6 +50,8 @@ typedef struct {
     int32_t max_coarse_dofs;  /* dense LU once nb*bs <= this */
     uint64_t seed;            /* seed of the independent-set tie-break hash */
     const int8_t *cf_override;/* optional level-0 splitting (1 = C, 0 = F), NULL = computed */
+    int32_t form;             /* 0: block nAIR; 1: scalar nAIR of the system scaled by the
+                                 block-diagonal inverse (the paper's default form) */
 } ora_params;
 
 /* A view of one level, valid until ora_free.  Arrays that do not exist on a

@@ -688,3 +688,84 @@ def test_convergence_sanity_band():
     assert st == "OK"
     avg, last5 = oracle.rho_stats(hist)
     assert last5 < 0.35 and len(hist) < 40
+
+
+# ------------------------------------------------ scalar form (scaled system)
+
+def _scaled_dense(S):
+    """D^{-1} A with D the block diagonal (numpy), and its expected pattern."""
+    A = S.to_dense()
+    bs = S.bs
+    D = np.zeros_like(A)
+    for I in range(S.nb):
+        sl = slice(I * bs, (I + 1) * bs)
+        D[sl, sl] = A[sl, sl]
+    M = np.linalg.solve(D, A)
+    pat = np.zeros(A.shape, dtype=bool)
+    rows = row_blocks(S.rowptr)
+    for t, (I, J) in enumerate(zip(rows, S.colidx)):
+        if I == J:
+            pat[np.arange(I * bs, (I + 1) * bs), np.arange(I * bs, (I + 1) * bs)] = True
+        else:
+            nzcols = np.nonzero(np.any(S.vals[t] != 0.0, axis=0))[0]
+            for a in range(bs):
+                pat[I * bs + a, J * bs + nzcols] = True
+    return M, pat
+
+
+def test_scalar_form_level0_is_the_scaled_system():
+    """Section "Blocks, filtering, and parallelization": the scalar form runs on
+    D^{-1} A.  Level 0 must equal numpy's D^{-1} A entry by entry (1e-13), hold
+    exactly the entries that can be nonzero (unit diagonal; columns of A_IJ that
+    are not all zero), and be unit lower triangular in the flow order."""
+    S = small_dg(5, 2, seed=31, sigma=0.7)
+    H = hier(S, degree=1, form=1, max_coarse_dofs=30)
+    L0 = H.level(0)
+    assert L0.bs == 1 and L0.nb == S.n
+    G = bsr_dense(L0.nb, 1, L0.rowptr, L0.colidx, L0.vals)
+    M, pat = _scaled_dense(S)
+    Gpat = np.zeros_like(pat)
+    rows = row_blocks(L0.rowptr)
+    Gpat[rows, L0.colidx] = True
+    assert np.array_equal(Gpat, pat)
+    assert np.abs(G - M).max() <= 1e-13 * np.abs(M).max()
+    assert np.array_equal(np.diag(G), np.ones(S.n))
+    idx = dof_index(S.topo_order, S.bs)
+    Gp = G[np.ix_(idx, idx)]
+    assert not np.any(np.triu(Gp, 1))
+
+
+@pytest.mark.parametrize("relax", [0, 1])
+def test_scalar_form_solves_and_is_adjoint(relax):
+    S = small_dg(6, 2, seed=32)
+    H = hier(S, degree=2, relax=relax, form=1, max_coarse_dofs=40)
+    assert H.num_levels >= 3
+    x, hist, st = H.solve(S.rhs, 1e-13, 300)
+    assert st == "OK"
+    ref = np.linalg.solve(S.to_dense(), S.rhs)
+    assert np.abs(x - ref).max() <= 1e-11 * np.abs(ref).max()
+    g = np.random.default_rng(2).uniform(-1, 1, S.n)
+    y, hT, stT = H.solve_T(g, 1e-13, 300)
+    assert stT == "OK"
+    refT = np.linalg.solve(S.to_dense().T, g)
+    assert np.abs(y - refT).max() <= 1e-11 * np.abs(refT).max()
+    B = dense_B(H.vcycle, S.n)
+    BT = dense_B(H.vcycle_T, S.n)
+    assert np.abs(B.T - BT).max() < 1e-13 * np.abs(B).max()
+
+
+def test_scalar_form_iteration_is_exact_on_triangular_systems():
+    """Remark "nilpotent error propagation" for the scaled (scalar triangular)
+    system: the iteration is exact after at most (longest dependency path + 1)
+    iterations."""
+    S = small_dg(5, 1, seed=33)
+    H = hier(S, degree=1, form=1, max_coarse_dofs=8)
+    assert H.num_levels >= 3
+    rows = row_blocks(S.rowptr)
+    adj = {}
+    for I, J in zip(rows, S.colidx):
+        if I != J:
+            adj.setdefault(int(J), []).append(int(I))
+    depth = longest_path_edges(range(S.nb), adj)
+    x, hist, st = H.solve(S.rhs, 1e-300, depth + 1)
+    assert hist[-1] < 1e-13
