@@ -65,6 +65,12 @@ typedef struct {
                                  its decisions are FP64 either way. */
     const int8_t *tuning;     /* optional, host, [64][6] lane-group choices from nair_autotune for a
                                  hierarchy of the same structure (copied at setup); NULL: defaults */
+    int32_t form;             /* 0: block nAIR (default); 1: scalar nAIR of the system scaled by the
+                                 inverse of its block diagonal (section "Blocks, filtering, and
+                                 parallelization"): the hierarchy is built on S = D^{-1} A as a
+                                 scalar matrix (identity diagonal blocks exact, zeros dropped) and
+                                 the solve preconditions A with B_S D^{-1} (transposed: D^{-T}
+                                 B_S^T), stopping on the unscaled residual.  Levels are scalar. */
 } nair_params;
 
 typedef struct {

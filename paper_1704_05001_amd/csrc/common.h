@@ -266,6 +266,15 @@ void launch_seg_check(const double *part, const int *cptr, int nsys, const doubl
                       int *nact, int *nact_acc, hipStream_t s);
 void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s);
 
+// ------------------------------------------------------------ scalar form
+// S = D^{-1} A as a scalar matrix (bs 1): identity diagonal blocks exact,
+// off-diagonal blocks D_I^{-1} A_IJ (fma chains), exact zeros dropped.
+void build_scaled(const DevBSR &A, const double *dinv, DevBSR &S, hipStream_t s);
+// out (and out32 if given) = D^{-1} v blockwise (trans: D^{-T} v), rows of live systems
+template <typename VT>
+void launch_block_diag_apply(const double *dinv, const VT *v, double *out, float *out32, int nb, int bs, bool trans,
+                             hipStream_t s, Gate g = Gate());
+
 // ------------------------------------------------------------------- grad
 void grad_vals(int nb, int bs, const int *rowptr, const int *colidx, const double *ybar, const double *x,
                double *gvals, hipStream_t s);

@@ -79,10 +79,18 @@ struct BatchSolve {
 
 struct Hier {
     nair_params prm{};
-    int bs = 0;
+    int bs = 0;                     // block size of the hierarchy (1 for the scalar form)
     int device = 0;
     int nsys = 1;
     std::vector<std::unique_ptr<Level>> lv;
+    // scalar form (prm.form == 1): the caller's block system, its block-diagonal
+    // inverse, A0^T for the transposed residual, per-block system ids, and a
+    // residual buffer; the hierarchy is built on S = D^{-1} A0
+    int bs0 = 0;
+    DevBSR A0, A0T;
+    bool have_A0T = false;
+    DBuf<double> d0inv, rres;
+    DBuf<int> bsys0;
     std::vector<double> hist;
     std::string err;
     BatchSolve batch;

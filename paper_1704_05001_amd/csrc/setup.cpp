@@ -137,8 +137,9 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
                      const double *vals, hipStream_t s) {
     const nair_params &p = h.prm;
     h.bs = bs;
+    h.bs0 = bs;
     h.nsys = nsys;
-    const int bb = bs * bs;
+    int bb = bs * bs;
     const int nnzb = read_int(rowptr + nb, s);
     if (nnzb < nb) fail(NAIR_EINVAL, "rowptr[nb] < nb: every row needs its diagonal block");
     auto L0 = std::make_unique<Level>();
@@ -157,13 +158,35 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         if (vb & 8) fail(NAIR_EINVAL, "a row has no diagonal block");
         if (vb & 16) fail(NAIR_EINVAL, "a block couples two systems of the batch");
     }
-    L0->A.alloc(nb, nb, bs, nnzb);
-    NAIR_HIP(hipMemcpyAsync(L0->A.rowptr.get(), rowptr, sizeof(int) * (static_cast<size_t>(nb) + 1),
+    DevBSR &Ain = (p.form == 1) ? h.A0 : L0->A;   // the caller's system
+    Ain.alloc(nb, nb, bs, nnzb);
+    NAIR_HIP(hipMemcpyAsync(Ain.rowptr.get(), rowptr, sizeof(int) * (static_cast<size_t>(nb) + 1),
                             hipMemcpyDeviceToDevice, s));
-    NAIR_HIP(hipMemcpyAsync(L0->A.colidx.get(), colidx, sizeof(int) * static_cast<size_t>(nnzb),
+    NAIR_HIP(hipMemcpyAsync(Ain.colidx.get(), colidx, sizeof(int) * static_cast<size_t>(nnzb),
                             hipMemcpyDeviceToDevice, s));
-    NAIR_HIP(hipMemcpyAsync(L0->A.vals.get(), vals, sizeof(double) * static_cast<size_t>(nnzb) * bb,
+    NAIR_HIP(hipMemcpyAsync(Ain.vals.get(), vals, sizeof(double) * static_cast<size_t>(nnzb) * bb,
                             hipMemcpyDeviceToDevice, s));
+    if (p.form == 1) {
+        // scalar form: D^{-1} of the caller's blocks, S = D^{-1} A as the scalar level 0
+        h.d0inv.alloc(static_cast<size_t>(nb) * bb);
+        DBuf<int> sing(1);
+        NAIR_HIP(hipMemsetAsync(sing.get(), 0x7f, sizeof(int), s));
+        launch_block_inverse(h.A0.rowptr.get(), h.A0.colidx.get(), h.A0.vals.get(), nb, bs, nullptr, h.d0inv.get(),
+                             sing.get(), s);
+        const int hs = read_int(sing.get(), s);
+        if (hs != kNoSingular)
+            fail(NAIR_ESINGULAR, "diagonal block " + std::to_string(hs) + " of the system is singular");
+        if (nsys > 1) {
+            h.bsys0.alloc(nb);
+            launch_seg_info(L0->seg_d.get(), L0->mode_d.get(), nsys, nb, nullptr, nullptr, h.bsys0.get(), s);
+        }
+        build_scaled(h.A0, h.d0inv.get(), L0->A, s);
+        h.rres.alloc(static_cast<size_t>(nb) * bs);
+        for (auto &o : L0->seg) o *= bs;   // systems in scalar rows
+        bs = 1;
+        bb = 1;
+        h.bs = 1;
+    }
     h.lv.push_back(std::move(L0));
 
     for (int l = 0;; ++l) {
@@ -393,6 +416,10 @@ void make_fp32_copies(Hier &h, hipStream_t s) {
 }
 
 void ensure_transposes(Hier &h, hipStream_t s) {
+    if (h.prm.form == 1 && !h.have_A0T) {   // the transposed outer residual uses A0^T
+        bsr_transpose(h.A0, h.A0T, s);
+        h.have_A0T = true;
+    }
     for (auto &Lp : h.lv) {
         Level &L = *Lp;
         if (L.have_T) continue;

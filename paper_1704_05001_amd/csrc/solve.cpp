@@ -211,15 +211,36 @@ void batch_iteration(Hier &h, bool trans, const double *b, double *x, hipStream_
     const int64_t n = static_cast<int64_t>(L0.A.nb) * h.bs;
     const bool fp32 = std::is_same<T, float>::value;
     const T *e = trans ? vcycle_T<T>(h, 0, s) : vcycle<T>(h, 0, s);
-    launch_axpy_active<T>(x, e, n, h.bs, L0.bsys.get(), B.active.get(), s);
-    const MatView<double> Aop = trans ? view(L0.AT).with_groups(L0.tune[TU_RESIDUAL_T])
-                                      : view(L0.A).with_groups(L0.tune[TU_RESIDUAL]);
-    {
-        TimerScope ts(TK_RESIDUAL, 0, s);
-        launch_residual<double, double>(Aop, b, x, L0.r.get(), fp32 ? L0.r32.get() : nullptr, s,
-                                        gate(h, L0));
+    if (h.prm.form == 1) {
+        // scalar form: x += B_S D^{-1} r (transposed: x += D^{-T} B_S^T r) on the caller's block system
+        const Gate g0{h.bsys0.get(), h.active};
+        if (trans) {
+            launch_block_diag_apply<T>(h.d0inv.get(), e, h.rres.get(), nullptr, h.A0.nb, h.bs0, true, s, g0);
+            launch_axpy_active<double>(x, h.rres.get(), n, h.bs0, h.bsys0.get(), B.active.get(), s);
+        } else {
+            launch_axpy_active<T>(x, e, n, h.bs0, h.bsys0.get(), B.active.get(), s);
+        }
+        double *rout = trans ? L0.r.get() : h.rres.get();
+        {
+            TimerScope ts(TK_RESIDUAL, 0, s);
+            launch_residual<double, double>(trans ? view(h.A0T) : view(h.A0), b, x, rout,
+                                            (trans && fp32) ? L0.r32.get() : nullptr, s, g0);
+        }
+        launch_seg_sumsq(rout, B.clo.get(), B.clen.get(), B.nchunk, B.part.get(), s);
+        if (!trans)
+            launch_block_diag_apply<double>(h.d0inv.get(), h.rres.get(), L0.r.get(), fp32 ? L0.r32.get() : nullptr,
+                                            h.A0.nb, h.bs0, false, s, g0);
+    } else {
+        launch_axpy_active<T>(x, e, n, h.bs, L0.bsys.get(), B.active.get(), s);
+        const MatView<double> Aop = trans ? view(L0.AT).with_groups(L0.tune[TU_RESIDUAL_T])
+                                          : view(L0.A).with_groups(L0.tune[TU_RESIDUAL]);
+        {
+            TimerScope ts(TK_RESIDUAL, 0, s);
+            launch_residual<double, double>(Aop, b, x, L0.r.get(), fp32 ? L0.r32.get() : nullptr, s,
+                                            gate(h, L0));
+        }
+        launch_seg_sumsq(L0.r.get(), B.clo.get(), B.clen.get(), B.nchunk, B.part.get(), s);
     }
-    launch_seg_sumsq(L0.r.get(), B.clo.get(), B.clen.get(), B.nchunk, B.part.get(), s);
     launch_seg_check(B.part.get(), B.cptr.get(), h.nsys, B.bn.get(), B.rtol.get(), B.hist_cap, B.hist.get(),
                      B.last.get(), B.active.get(), B.status.get(), B.iters.get(), B.it.get(), B.nact.get(),
                      B.nact_acc.get(), s);
@@ -295,8 +316,13 @@ nair_status run_solve_batch(Hier &h, bool trans, const double *b, double *x, dou
     launch_seg_sumsq(b, B.clo.get(), B.clen.get(), B.nchunk, B.part.get(), s);
     launch_seg_init(B.part.get(), B.cptr.get(), nsys, B.bn.get(), B.last.get(), B.active.get(), B.status.get(),
                     B.iters.get(), B.it.get(), B.nact.get(), B.nact_acc.get(), s);
-    NAIR_HIP(hipMemcpyAsync(L0.r.get(), b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    if (fp32) launch_to_float(b, L0.r32.get(), n, s);
+    if (h.prm.form == 1 && !trans) {   // the scaled cycle's first right-hand side: D^{-1} b
+        launch_block_diag_apply<double>(h.d0inv.get(), b, L0.r.get(), fp32 ? L0.r32.get() : nullptr, h.A0.nb, h.bs0,
+                                        false, s);
+    } else {
+        NAIR_HIP(hipMemcpyAsync(L0.r.get(), b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        if (fp32) launch_to_float(b, L0.r32.get(), n, s);
+    }
     hipGraphExec_t ex = use_graph ? batch_graph(h, trans, b, x) : nullptr;
 
     std::vector<double> last(nsys), prev(nsys, 1.0);
@@ -375,16 +401,30 @@ nair_status run_solve(Hier &h, bool trans, const double *b, double *x, double rt
 void run_vcycle(Hier &h, bool trans, const double *r, double *e, hipStream_t s) {
     Level &L0 = *h.lv[0];
     const int64_t n = static_cast<int64_t>(L0.A.nb) * h.bs;
+    const bool fp32 = h.prm.precision == 1;
+    const bool scaled = h.prm.form == 1;
     if (trans) ensure_transposes(h, s);
-    NAIR_HIP(hipMemcpyAsync(L0.r.get(), r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    if (h.prm.precision == 1) {
-        launch_to_float(r, L0.r32.get(), n, s);
+    if (scaled && !trans) {   // the scaled cycle reads D^{-1} r
+        launch_block_diag_apply<double>(h.d0inv.get(), r, L0.r.get(), fp32 ? L0.r32.get() : nullptr, h.A0.nb, h.bs0,
+                                        false, s);
+    } else {
+        NAIR_HIP(hipMemcpyAsync(L0.r.get(), r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        if (fp32) launch_to_float(r, L0.r32.get(), n, s);
+    }
+    if (fp32) {
         const float *out = trans ? vcycle_T<float>(h, 0, s) : vcycle<float>(h, 0, s);
-        NAIR_HIP(hipMemsetAsync(e, 0, sizeof(double) * n, s));
-        launch_axpy<float>(e, out, n, s);
+        if (scaled && trans) {
+            launch_block_diag_apply<float>(h.d0inv.get(), out, e, nullptr, h.A0.nb, h.bs0, true, s);
+        } else {
+            NAIR_HIP(hipMemsetAsync(e, 0, sizeof(double) * n, s));
+            launch_axpy<float>(e, out, n, s);
+        }
     } else {
         const double *out = trans ? vcycle_T<double>(h, 0, s) : vcycle<double>(h, 0, s);
-        NAIR_HIP(hipMemcpyAsync(e, out, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        if (scaled && trans)
+            launch_block_diag_apply<double>(h.d0inv.get(), out, e, nullptr, h.A0.nb, h.bs0, true, s);
+        else
+            NAIR_HIP(hipMemcpyAsync(e, out, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     }
     NAIR_HIP(hipStreamSynchronize(s));
 }

@@ -124,9 +124,9 @@ void tune_levels(Hier &h, int reps, hipStream_t s) {
             [&](int G) { launch_interp_T<T, T>(ZT.with_groups(G), L.cidx.get(), V::e0(C), V::e1(L), s); }, bs,
             reps, ev, s);
     }
-    // the outer residual is FP64 in both precisions
+    // the outer residual is FP64 in both precisions (the scalar form's runs on the caller's blocks, untuned)
     Level &L0 = *h.lv[0];
-    if (!L0.coarsest) {
+    if (!L0.coarsest && h.prm.form == 0) {
         clear_vectors<double>(L0, s);
         L0.tune[TU_RESIDUAL] = pick(
             [&](int G) {

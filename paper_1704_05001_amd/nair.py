@@ -43,7 +43,8 @@ class _Params(C.Structure):
     _fields_ = [("degree", C.c_int32), ("theta", C.c_double), ("phi", C.c_double),
                 ("drop", C.c_double), ("relax", C.c_int32), ("max_levels", C.c_int32),
                 ("max_coarse_dofs", C.c_int32), ("seed", C.c_uint64),
-                ("cf_override_host", C.c_void_p), ("precision", C.c_int32), ("tuning", C.c_void_p)]
+                ("cf_override_host", C.c_void_p), ("precision", C.c_int32), ("tuning", C.c_void_p),
+                ("form", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -157,6 +158,7 @@ class Params:
     cf_override: Optional[np.ndarray] = None
     precision: str = "fp64"      # "fp64" or "fp32" (FP32-stored hierarchy, FP64 refinement)
     tuning: Optional[np.ndarray] = None   # [levels, 6] lane groups from Hierarchy.autotune
+    form: str = "block"          # "block" or "scalar" (scalar nAIR of D^{-1} A, D the block diagonal)
 
 
 @dataclass
@@ -195,6 +197,9 @@ class Hierarchy:
         if params.precision not in ("fp64", "fp32"):
             raise ValueError("precision must be 'fp64' or 'fp32'")
         p.precision = 1 if params.precision == "fp32" else 0
+        if params.form not in ("block", "scalar"):
+            raise ValueError("form must be 'block' or 'scalar'")
+        p.form = 1 if params.form == "scalar" else 0
         cf = None
         if params.cf_override is not None:
             cf = np.ascontiguousarray(params.cf_override, dtype=np.int8)

@@ -23,13 +23,14 @@ pytestmark = pytest.mark.gpu
 BATCH = "dg_q2_angles64_uneven"
 
 
-def build_batch(systems, gpu_kw=None, oracles=True, **kw):
+def build_batch(systems, gpu_kw=None, oracles=True, form_oracle=0, **kw):
     rp, ci, va, rhs, sys_nb = concat_systems(systems)
     d_rp, d_ci, d_va = to_dev(rp, ci, va)
     G = P.Hierarchy(d_rp, d_ci, d_va, systems[0].bs, P.Params(**kw, **(gpu_kw or {})), sys_nb=sys_nb)
     Os = None
     if oracles:
-        Os = [oracle.Hierarchy(S.nb, S.bs, S.rowptr, S.colidx, S.vals, oracle.Params(**kw)) for S in systems]
+        Os = [oracle.Hierarchy(S.nb, S.bs, S.rowptr, S.colidx, S.vals, oracle.Params(form=form_oracle, **kw))
+              for S in systems]
     return G, Os, rhs
 
 

@@ -43,11 +43,17 @@ def to_dev(rp, ci, va):
 
 
 def build_pair(nb, bs, rp, ci, va, gpu_kw=None, **kw):
+    """GPU and oracle hierarchies of one matrix; gpu_kw holds GPU-only parameters
+    (form="scalar" also selects the oracle's form 1)."""
     import paper_1704_05001_amd as P
     _need_gpu()
     d_rp, d_ci, d_va = to_dev(rp, ci, va)
-    G = P.Hierarchy(d_rp, d_ci, d_va, bs, P.Params(**kw, **(gpu_kw or {})))
-    O = oracle.Hierarchy(nb, bs, rp, ci, va, oracle.Params(**kw))
+    gpu_kw = dict(gpu_kw or {})
+    G = P.Hierarchy(d_rp, d_ci, d_va, bs, P.Params(**kw, **gpu_kw))
+    okw = dict(kw)
+    if gpu_kw.get("form") == "scalar":
+        okw["form"] = 1
+    O = oracle.Hierarchy(nb, bs, rp, ci, va, oracle.Params(**okw))
     return G, O
 
 
