@@ -776,6 +776,7 @@ void ora_default_params(ora_params *p) {
     p->seed = 0;
     p->cf_override = NULL;
     p->form = 0;
+    p->cycle = 0;
 }
 
 static int validate(int32_t nb, int32_t bs, const int32_t *rowptr, const int32_t *colidx) {
@@ -877,6 +878,7 @@ int ora_setup(int32_t nb, int32_t bs, const int32_t *rowptr, const int32_t *coli
     if (!prm || !out || !vals) return ORA_EINVAL;
     *out = NULL;
     if (prm->degree < 0 || prm->max_levels < 1 || prm->max_levels > ORA_MAX_LEVELS) return ORA_EINVAL;
+    if (prm->cycle != 0 && prm->cycle != 1) return ORA_EINVAL;
     if (!(prm->theta >= 0.0 && prm->theta < 1.0) || !(prm->phi >= 0.0 && prm->phi < 1.0) ||
         !(prm->drop >= 0.0 && prm->drop < 1.0))
         return ORA_EINVAL;
@@ -1063,9 +1065,17 @@ static void jacobi_sweep_T(const level_t *L, int8_t which, const double *g, doub
 /*
  * V-cycle from a zero initial guess with no pre-relaxation (section 5):
  * restrict r_c = r_C + Z r_F, recurse, interpolate e = P e_c, then nu = k+1
- * Jacobi F sweeps (section 5.1) and, for FC, one Jacobi C sweep.
+ * Jacobi F sweeps (section 5.1) and, for FC, one Jacobi C sweep.  The F-cycle
+ * (compared with V-cycles in the section "Scaling in h and element order")
+ * differs only in its coarse solve, an F-cycle followed by a V-cycle.
  */
-static void vcycle(const ora_hier *h, int32_t l, const double *r, double *e) {
+/* The coarse-grid correction's coarse solve on level l: one V-cycle, or (fcyc)
+ * one F-cycle followed by one V-cycle on its residual,
+ * e_c = F r_c + V (r_c - A_c F r_c). */
+static void coarse_solve(const ora_hier *h, int32_t l, int fcyc, const double *rc, double *ec);
+
+/* fcyc = 0: V-cycle; 1: F-cycle (its coarse solve is an F-cycle then a V-cycle). */
+static void cycle(const ora_hier *h, int32_t l, int fcyc, const double *r, double *e) {
     const level_t *L = &h->lv[l];
     int32_t bs = L->A.bs;
     int64_t n = (int64_t)L->A.nb * bs;
@@ -1085,7 +1095,7 @@ static void vcycle(const ora_hier *h, int32_t l, const double *r, double *e) {
             for (int32_t a = 0; a < bs; ++a) rc[(size_t)i * bs + a] += tmp[a];
         }
     }
-    vcycle(h, l + 1, rc, ec);
+    coarse_solve(h, l + 1, fcyc, rc, ec);
     for (int32_t I = 0; I < L->A.nb; ++I)
         for (int32_t a = 0; a < bs; ++a)
             e[(size_t)I * bs + a] = (L->pmap[I] >= 0) ? ec[(size_t)L->pmap[I] * bs + a] : 0.0;
@@ -1103,7 +1113,9 @@ static void vcycle(const ora_hier *h, int32_t l, const double *r, double *e) {
  * ideal interpolation, section 2.2 corollary and section 3.1 remark); then
  * s = g - A^T y, s_c = P^T s, recurse, and y += R^T y_c = [Z^T y_c; y_c].
  */
-static void vcycle_T(const ora_hier *h, int32_t l, const double *g, double *y) {
+static void coarse_solve_T(const ora_hier *h, int32_t l, int fcyc, const double *sc, double *yc);
+
+static void cycle_T(const ora_hier *h, int32_t l, int fcyc, const double *g, double *y) {
     const level_t *L = &h->lv[l];
     int32_t bs = L->A.bs;
     int64_t n = (int64_t)L->A.nb * bs;
@@ -1125,7 +1137,7 @@ static void vcycle_T(const ora_hier *h, int32_t l, const double *g, double *y) {
     for (int32_t I = 0; I < L->A.nb; ++I)
         if (L->pmap[I] >= 0)
             for (int32_t a = 0; a < bs; ++a) sc[(size_t)L->pmap[I] * bs + a] += work[(size_t)I * bs + a];
-    vcycle_T(h, l + 1, sc, yc);
+    coarse_solve_T(h, l + 1, fcyc, sc, yc);
     for (int32_t i = 0; i < L->nc; ++i) {
         for (int32_t a = 0; a < bs; ++a) y[(size_t)L->cpts[i] * bs + a] += yc[(size_t)i * bs + a];
         for (int32_t t = L->Z.rowptr[i]; t < L->Z.rowptr[i + 1]; ++t) {
@@ -1137,6 +1149,41 @@ static void vcycle_T(const ora_hier *h, int32_t l, const double *g, double *y) {
     free(yc);
     free(work);
     free(tmp);
+}
+
+static void coarse_solve(const ora_hier *h, int32_t l, int fcyc, const double *rc, double *ec) {
+    if (!fcyc) {
+        cycle(h, l, 0, rc, ec);
+        return;
+    }
+    const bsr_t *A = &h->lv[l].A;
+    const int64_t n = (int64_t)A->nb * A->bs;
+    double *res = (double *)malloc(sizeof(double) * (size_t)n);
+    double *e2 = (double *)malloc(sizeof(double) * (size_t)n);
+    cycle(h, l, 1, rc, ec);
+    for (int32_t I = 0; I < A->nb; ++I) block_row_residual(A, I, rc, ec, res + (size_t)I * A->bs);
+    cycle(h, l, 0, res, e2);
+    for (int64_t i = 0; i < n; ++i) ec[i] += e2[i];
+    free(res);
+    free(e2);
+}
+
+/* The transpose of coarse_solve: y_c = V^T s_c + F^T (s_c - A_c^T V^T s_c). */
+static void coarse_solve_T(const ora_hier *h, int32_t l, int fcyc, const double *sc, double *yc) {
+    if (!fcyc) {
+        cycle_T(h, l, 0, sc, yc);
+        return;
+    }
+    const bsr_t *A = &h->lv[l].A;
+    const int64_t n = (int64_t)A->nb * A->bs;
+    double *res = (double *)malloc(sizeof(double) * (size_t)n);
+    double *y2 = (double *)malloc(sizeof(double) * (size_t)n);
+    cycle_T(h, l, 0, sc, yc);
+    residual_T(A, sc, yc, res);
+    cycle_T(h, l, 1, res, y2);
+    for (int64_t i = 0; i < n; ++i) yc[i] += y2[i];
+    free(res);
+    free(y2);
 }
 
 static void precondition(const ora_hier *h, int trans, const double *r, double *e);
@@ -1165,9 +1212,10 @@ static double norm2(const double *v, int64_t n) {
  * B_S D^{-1} r (B_S the cycle of the scaled system); transposed: B^T r, or
  * D^{-T} B_S^T r. */
 static void precondition(const ora_hier *h, int trans, const double *r, double *e) {
+    const int f = h->prm.cycle == 1;
     if (h->prm.form != 1) {
-        if (trans) vcycle_T(h, 0, r, e);
-        else vcycle(h, 0, r, e);
+        if (trans) cycle_T(h, 0, f, r, e);
+        else cycle(h, 0, f, r, e);
         return;
     }
     const int32_t bs = h->A0.bs, bb = bs * bs;
@@ -1176,9 +1224,9 @@ static void precondition(const ora_hier *h, int trans, const double *r, double *
     if (!trans) {
         for (int32_t I = 0; I < h->A0.nb; ++I)
             block_apply(bs, h->d0inv + (size_t)I * bb, r + (size_t)I * bs, w + (size_t)I * bs, 0);
-        vcycle(h, 0, w, e);
+        cycle(h, 0, f, w, e);
     } else {
-        vcycle_T(h, 0, r, w);
+        cycle_T(h, 0, f, r, w);
         for (int32_t I = 0; I < h->A0.nb; ++I)
             block_apply(bs, h->d0inv + (size_t)I * bb, w + (size_t)I * bs, e + (size_t)I * bs, 1);
     }
@@ -1283,15 +1331,16 @@ int ora_level(const ora_hier *h, int32_t lvl, ora_level_view *v) {
  */
 void ora_complexity(const ora_hier *h, double *oc, double *cc) {
     double nnz0 = (double)h->lv[0].A.rowptr[h->lv[0].A.nb];
-    double o = 0.0, c = 1.0;
+    double o = 0.0;
     int32_t nu = h->prm.degree + 1;
+    double w[ORA_MAX_LEVELS], nz[ORA_MAX_LEVELS];   /* per-level V-cycle work, operator size */
     for (int32_t l = 0; l < h->nlev; ++l) {
         const level_t *L = &h->lv[l];
-        double nz = (double)L->A.rowptr[L->A.nb];
-        o += nz / nnz0;
+        nz[l] = (double)L->A.rowptr[L->A.nb] / nnz0;
+        o += nz[l];
         if (L->coarsest) {
             double bb = (double)L->A.bs * L->A.bs;
-            c += (double)L->dense_n * L->dense_n / bb / nnz0;
+            w[l] = (double)L->dense_n * L->dense_n / bb / nnz0;
             continue;
         }
         double nzF = 0.0, nzC = 0.0, nbF = 0.0;
@@ -1303,8 +1352,20 @@ void ora_complexity(const ora_hier *h, double *oc, double *cc) {
                 nbF += 1.0;
             }
         }
-        c += (nu * nzF + (h->prm.relax == 1 ? nzC : 0.0) + (double)L->Z.rowptr[L->Z.nb] + nbF) / nnz0;
+        w[l] = (nu * nzF + (h->prm.relax == 1 ? nzC : 0.0) + (double)L->Z.rowptr[L->Z.nb] + nbF) / nnz0;
+    }
+    /* V: each level once.  F: a level's coarse solve is an F-cycle, a residual
+     * with the coarse operator and a V-cycle, recursively. */
+    double cv = 0.0, cf = 0.0;
+    for (int32_t l = h->nlev - 1; l >= 0; --l) {
+        if (l == h->nlev - 1) {
+            cv = w[l];
+            cf = w[l];
+        } else {
+            cf = w[l] + cf + nz[l + 1] + cv;
+            cv = w[l] + cv;
+        }
     }
     if (oc) *oc = o;
-    if (cc) *cc = c;
+    if (cc) *cc = 1.0 + (h->prm.cycle == 1 ? cf : cv);
 }

@@ -52,6 +52,7 @@ typedef struct {
     const int8_t *cf_override;/* optional level-0 splitting (1 = C, 0 = F), NULL = computed */
     int32_t form;             /* 0: block nAIR; 1: scalar nAIR of the system scaled by the
                                  block-diagonal inverse (the paper's default form) */
+    int32_t cycle;            /* 0: V-cycle; 1: F-cycle (section "Scaling in h and element order") */
 } ora_params;
 
 /* A view of one level, valid until ora_free.  Arrays that do not exist on a

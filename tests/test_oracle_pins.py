@@ -769,3 +769,62 @@ def test_scalar_form_iteration_is_exact_on_triangular_systems():
     depth = longest_path_edges(range(S.nb), adj)
     x, hist, st = H.solve(S.rhs, 1e-300, depth + 1)
     assert hist[-1] < 1e-13
+
+
+# ------------------------------------------------------------------ F-cycle
+
+def test_fcycle_equals_vcycle_on_two_levels():
+    """With two levels the coarse solve is exact, so the F-cycle's second
+    (V-cycle) coarse solve sees a zero residual: B_F = B_V up to rounding."""
+    S = small_dg(4, 1, seed=41)
+    HV = hier(S, degree=1, max_coarse_dofs=40)
+    HF = hier(S, degree=1, max_coarse_dofs=40, cycle=1)
+    assert HV.num_levels == 2
+    BV, BF = dense_B(HV.vcycle, S.n), dense_B(HF.vcycle, S.n)
+    assert np.abs(BF - BV).max() <= 1e-12 * np.abs(BV).max()
+
+
+@pytest.mark.parametrize("relax", [0, 1])
+def test_fcycle_solves_and_is_adjoint(relax):
+    S = small_dg(6, 2, seed=42)
+    H = hier(S, degree=1, relax=relax, max_coarse_dofs=20, cycle=1)
+    assert H.num_levels >= 4
+    n = S.n
+    B, BT = dense_B(H.vcycle, n), dense_B(H.vcycle_T, n)
+    assert np.abs(B.T - BT).max() < 1e-13 * np.abs(B).max()
+    HV = hier(S, degree=1, relax=relax, max_coarse_dofs=20)
+    assert np.abs(B - dense_B(HV.vcycle, n)).max() > 1e-6 * np.abs(B).max()   # a different operator
+    x, hist, st = H.solve(S.rhs, 1e-13, 200)
+    assert st == "OK"
+    ref = np.linalg.solve(S.to_dense(), S.rhs)
+    assert np.abs(x - ref).max() <= 1e-11 * np.abs(ref).max()
+    g = np.random.default_rng(3).uniform(-1, 1, n)
+    y, hT, stT = H.solve_T(g, 1e-13, 200)
+    refT = np.linalg.solve(S.to_dense().T, g)
+    assert stT == "OK" and np.abs(y - refT).max() <= 1e-11 * np.abs(refT).max()
+
+
+def test_fcycle_exact_on_triangular_and_no_slower():
+    """On a block-triangular system the F-cycle iteration is exact within the
+    longest dependency path plus one, like the V-cycle (its parts are
+    compositions of the same triangular operations), and it converges at least
+    as fast as the V-cycle (the section "Scaling in h and element order" uses
+    it for robustness)."""
+    S = small_dg(6, 1, seed=43)
+    HF = hier(S, degree=1, max_coarse_dofs=8, cycle=1)
+    HV = hier(S, degree=1, max_coarse_dofs=8)
+    assert HF.num_levels >= 3
+    rows = row_blocks(S.rowptr)
+    adj = {}
+    for I, J in zip(rows, S.colidx):
+        if I != J:
+            adj.setdefault(int(J), []).append(int(I))
+    depth = longest_path_edges(range(S.nb), adj)
+    x, hist, st = HF.solve(S.rhs, 1e-300, depth + 1)
+    assert hist[-1] < 1e-13
+    xf, hf, _ = HF.solve(S.rhs, 1e-12, 200)
+    xv, hv, _ = HV.solve(S.rhs, 1e-12, 200)
+    assert len(hf) <= len(hv)
+    ocf, ccf = HF.complexity()
+    ocv, ccv = HV.complexity()
+    assert ocf == ocv and ccf > ccv
