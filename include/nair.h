@@ -71,6 +71,10 @@ typedef struct {
                                  scalar matrix (identity diagonal blocks exact, zeros dropped) and
                                  the solve preconditions A with B_S D^{-1} (transposed: D^{-T}
                                  B_S^T), stopping on the unscaled residual.  Levels are scalar. */
+    int32_t cycle;            /* 0: V-cycle (default); 1: F-cycle -- every coarse solve is an F-cycle
+                                 followed by a V-cycle on its residual (the F-cycles of the section
+                                 "Scaling in h and element order"); the transposed solve applies the
+                                 exact transpose */
 } nair_params;
 
 typedef struct {

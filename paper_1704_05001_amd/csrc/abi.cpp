@@ -72,6 +72,7 @@ nair_status nair_default_params(nair_params *p) {
     p->precision = 0;
     p->tuning = nullptr;
     p->form = 0;
+    p->cycle = 0;
     return NAIR_OK;
 }
 
@@ -93,6 +94,7 @@ static nair_status setup_common(int32_t nsys, const int32_t *sys_nb, int32_t nb,
     if (p->relax != 0 && p->relax != 1) return bad(nullptr, "relax must be 0 (F) or 1 (FC)");
     if (p->precision != 0 && p->precision != 1) return bad(nullptr, "precision must be 0 (FP64) or 1 (FP32 hierarchy)");
     if (p->form != 0 && p->form != 1) return bad(nullptr, "form must be 0 (block) or 1 (scalar after scaling)");
+    if (p->cycle != 0 && p->cycle != 1) return bad(nullptr, "cycle must be 0 (V) or 1 (F)");
     if (p->max_levels < 1 || p->max_levels > nair::kMaxLevels) return bad(nullptr, "max_levels must be in [1, 64]");
     if (p->max_coarse_dofs < 0 || p->max_coarse_dofs > nair::kStallDenseDofs)
         return bad(nullptr, "max_coarse_dofs must be in [0, 4096]");

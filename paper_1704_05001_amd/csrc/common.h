@@ -249,6 +249,11 @@ void launch_axpy(double *x, const VT *e, int64_t n, hipStream_t s);
 template <typename VT>
 void launch_dense_matvec(const double *M, const int64_t *off, const int *dof0, const int *n, int nseg, int max_n,
                          const VT *x, VT *y, hipStream_t s, const int *sys = nullptr, const int *active = nullptr);
+// dst = src / dst += src on the block rows of live systems
+template <typename VT>
+void launch_copy_vec(VT *dst, const VT *src, int nb, int bs, hipStream_t s, Gate g = Gate());
+template <typename VT>
+void launch_add_vec(VT *dst, const VT *src, int nb, int bs, hipStream_t s, Gate g = Gate());
 // x += e on the dofs of systems still iterating (active[bsys[block]]; bsys == nullptr: system 0)
 template <typename VT>
 void launch_axpy_active(double *x, const VT *e, int64_t n, int bs, const int *bsys, const int *active,

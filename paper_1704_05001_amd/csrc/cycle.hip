@@ -14,6 +14,8 @@
 // Precision: matrices (MT) and cycle vectors (VT) are double, or float for the
 // FP32-stored hierarchy; accumulation and the block-diagonal inverses are
 // always double.
+#include <string>
+
 #include "common.h"
 
 namespace nair {
@@ -384,6 +386,17 @@ __device__ inline double seg_total(const double *__restrict__ part, const int *_
     return ss;
 }
 
+// dst = src (ADD: dst += src) on the rows of live systems
+template <typename VT, bool ADD>
+__global__ __launch_bounds__(kThreads) void k_vec_copy(VT *__restrict__ dst, const VT *__restrict__ src, int nb,
+                                                      int bs, Gate gate) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (g >= static_cast<int64_t>(nb) * bs) return;
+    if (!live(gate, static_cast<int>(g / bs))) return;
+    if (ADD) dst[g] = static_cast<VT>(static_cast<double>(dst[g]) + static_cast<double>(src[g]));
+    else dst[g] = src[g];
+}
+
 // status codes as in the public header: 0 OK, 3 not converged, 4 non-finite
 constexpr int kStOk = 0, kStNoConv = 3, kStNumeric = 4;
 
@@ -473,6 +486,13 @@ int groups_for(const MatView<MT> &A) {
 
 unsigned grid_rows(int64_t rows, int G, int bs) { return grid_for(rows, kThreads / (G * bs)); }
 
+// A launch must not read an operator the level does not hold.
+template <typename MT>
+void need(const MatView<MT> &A, const char *what) {
+    if (A.nb > 0 && (!A.rowptr || !A.colidx || !A.vals))
+        fail(NAIR_EDEVICE, std::string(what) + ": the level holds no such operator");
+}
+
 }  // namespace
 
 #define NAIR_BS_DISPATCH(bs, KERNEL, ...)                    \
@@ -497,6 +517,7 @@ int max_groups(int bs) {
 template <typename MT, typename VT>
 void launch_residual(const MatView<MT> &A, const VT *b, const VT *x, VT *r, float *r_lo, hipStream_t s,
                      Gate gate) {
+    need(A, "launch_residual");
     const int G = groups_for(A);
     const unsigned grid = grid_rows(A.nb, G, A.bs);
     NAIR_BS_DISPATCH(A.bs, k_residual, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, A.nb, A.bs, G, b, x, r,
@@ -507,6 +528,7 @@ void launch_residual(const MatView<MT> &A, const VT *b, const VT *x, VT *r, floa
 template <typename MT, typename VT>
 void launch_relax(const MatView<MT> &A, const double *dinv, bool dinv_trans, const VT *r, const VT *ein, VT *eout,
                   const int *list, int nlist, const int8_t *cf, int only_cf, hipStream_t s, Gate gate) {
+    need(A, "launch_relax");
     const int N = list ? nlist : A.nb;
     if (N <= 0) return;
     const int G = groups_for(A);
@@ -532,6 +554,7 @@ void launch_relax_T_first(const double *dinv, const VT *r, const int8_t *cf, VT 
 
 template <typename MT, typename VT>
 void launch_restrict(const MatView<MT> &Z, const VT *r, const int *cpts, VT *rc, hipStream_t s, Gate gate) {
+    need(Z, "launch_restrict");
     if (Z.nb <= 0) return;
     const int G = groups_for(Z);
     const unsigned grid = grid_rows(Z.nb, G, Z.bs);
@@ -558,6 +581,7 @@ void launch_restrict_T(const int *ptptr, const int *ptidx, const VT *sv, VT *sc,
 
 template <typename MT, typename VT>
 void launch_interp_T(const MatView<MT> &ZT, const int *cidx, const VT *yc, VT *y, hipStream_t s, Gate gate) {
+    need(ZT, "launch_interp_T");
     const int G = groups_for(ZT);
     const unsigned grid = grid_rows(ZT.nb, G, ZT.bs);
     NAIR_BS_DISPATCH(ZT.bs, k_interp_T, <<<grid, kThreads, 0, s>>>(ZT.rowptr, ZT.colidx, ZT.vals, ZT.nb, ZT.bs, G,
@@ -585,6 +609,22 @@ void launch_dense_matvec(const double *M, const int64_t *off, const int *dof0, c
     if (nseg <= 0) return;
     k_dense_mv<VT><<<dim3(grid_for(max_n, 4), static_cast<unsigned>(nseg)), 256, 0, s>>>(M, off, dof0, n, x, y, sys,
                                                                                          active);
+    NAIR_HIP(hipGetLastError());
+}
+
+template <typename VT>
+void launch_copy_vec(VT *dst, const VT *src, int nb, int bs, hipStream_t s, Gate gate) {
+    if (nb <= 0) return;
+    k_vec_copy<VT, false><<<grid_for(static_cast<int64_t>(nb) * bs, kThreads), kThreads, 0, s>>>(dst, src, nb, bs,
+                                                                                                gate);
+    NAIR_HIP(hipGetLastError());
+}
+
+template <typename VT>
+void launch_add_vec(VT *dst, const VT *src, int nb, int bs, hipStream_t s, Gate gate) {
+    if (nb <= 0) return;
+    k_vec_copy<VT, true><<<grid_for(static_cast<int64_t>(nb) * bs, kThreads), kThreads, 0, s>>>(dst, src, nb, bs,
+                                                                                               gate);
     NAIR_HIP(hipGetLastError());
 }
 
@@ -642,6 +682,8 @@ void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s) {
                                     hipStream_t, Gate);                                                              \
     template void launch_axpy<VT>(double *, const VT *, int64_t, hipStream_t);                                       \
     template void launch_axpy_active<VT>(double *, const VT *, int64_t, int, const int *, const int *, hipStream_t); \
+    template void launch_copy_vec<VT>(VT *, const VT *, int, int, hipStream_t, Gate);                                \
+    template void launch_add_vec<VT>(VT *, const VT *, int, int, hipStream_t, Gate);                                 \
     template void launch_dense_matvec<VT>(const double *, const int64_t *, const int *, const int *, int, int,       \
                                           const VT *, VT *, hipStream_t, const int *, const int *);
 

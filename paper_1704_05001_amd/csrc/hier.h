@@ -56,6 +56,9 @@ struct Level {
     // and the cycle vectors
     DBuf<float> vals32, z32, at32, zt32;
     DBuf<float> r32, e0_32, e1_32, tmp32;
+    // F-cycle: the first coarse correction while the second is computed
+    DBuf<double> fsave;
+    DBuf<float> fsave32;
 };
 
 // Per-system solve state of the batched iteration (device-side convergence).

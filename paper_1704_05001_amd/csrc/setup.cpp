@@ -399,18 +399,23 @@ void make_fp32_copies(Hier &h, hipStream_t s) {
             L.e1_32.alloc(n);
             L.tmp32.alloc(n);
         }
-        if (L.coarsest) continue;
+        // every level's operator (the F-cycle's coarse solve takes a residual
+        // on the coarsest level too); Z only where the level coarsens
         if (!L.vals32.get()) {
             L.vals32.alloc(static_cast<size_t>(L.A.nnzb * bb));
             launch_to_float(L.A.vals.get(), L.vals32.get(), L.A.nnzb * bb, s);
-            L.z32.alloc(static_cast<size_t>(L.Z.nnzb * bb));
-            launch_to_float(L.Z.vals.get(), L.z32.get(), L.Z.nnzb * bb, s);
+            if (!L.coarsest) {
+                L.z32.alloc(static_cast<size_t>(L.Z.nnzb * bb));
+                launch_to_float(L.Z.vals.get(), L.z32.get(), L.Z.nnzb * bb, s);
+            }
         }
         if (L.have_T && !L.at32.get()) {
             L.at32.alloc(static_cast<size_t>(L.AT.nnzb * bb));
             launch_to_float(L.AT.vals.get(), L.at32.get(), L.AT.nnzb * bb, s);
-            L.zt32.alloc(static_cast<size_t>(L.ZT.nnzb * bb));
-            launch_to_float(L.ZT.vals.get(), L.zt32.get(), L.ZT.nnzb * bb, s);
+            if (!L.coarsest) {
+                L.zt32.alloc(static_cast<size_t>(L.ZT.nnzb * bb));
+                launch_to_float(L.ZT.vals.get(), L.zt32.get(), L.ZT.nnzb * bb, s);
+            }
         }
     }
 }
@@ -437,13 +442,15 @@ void ensure_transposes(Hier &h, hipStream_t s) {
 void complexity(Hier &h, double *oc, double *cc, hipStream_t s) {
     const double nnz0 = static_cast<double>(h.lv[0]->A.nnzb);
     const int nu = h.prm.degree + 1;
-    double o = 0.0, c = 1.0;
-    for (auto &Lp : h.lv) {
-        Level &L = *Lp;
-        o += static_cast<double>(L.A.nnzb) / nnz0;
+    const size_t nl = h.lv.size();
+    std::vector<double> w(nl, 0.0), nz(nl, 0.0);   // per-level V-cycle work, operator size
+    double o = 0.0;
+    for (size_t l = 0; l < nl; ++l) {
+        Level &L = *h.lv[l];
+        nz[l] = static_cast<double>(L.A.nnzb) / nnz0;
+        o += nz[l];
         // dense solves count their n^2 entries in block units
-        for (int k = 0; k < L.ndseg; ++k)
-            c += static_cast<double>(L.dnb[k]) * L.dnb[k] / nnz0;
+        for (int k = 0; k < L.ndseg; ++k) w[l] += static_cast<double>(L.dnb[k]) * L.dnb[k] / nnz0;
         if (L.coarsest) continue;
         std::vector<int> rp(L.A.nb + 1);
         std::vector<int8_t> cfh(L.A.nb);
@@ -460,10 +467,22 @@ void complexity(Hier &h, double *oc, double *cc, hipStream_t s) {
                 nbF += 1;
             }
         }
-        c += (nu * nzF + (h.prm.relax == 1 ? nzC : 0.0) + static_cast<double>(L.Z.nnzb) + nbF) / nnz0;
+        w[l] += (nu * nzF + (h.prm.relax == 1 ? nzC : 0.0) + static_cast<double>(L.Z.nnzb) + nbF) / nnz0;
+    }
+    // V: each level once.  F: a level's coarse solve is an F-cycle, a residual
+    // with the coarse operator and a V-cycle, recursively.
+    double cv = 0.0, cf = 0.0;
+    for (size_t i = nl; i-- > 0;) {
+        if (i == nl - 1) {
+            cv = w[i];
+            cf = w[i];
+        } else {
+            cf = w[i] + cf + nz[i + 1] + cv;
+            cv = w[i] + cv;
+        }
     }
     if (oc) *oc = o;
-    if (cc) *cc = c;
+    if (cc) *cc = 1.0 + (h.prm.cycle == 1 ? cf : cv);
 }
 
 }  // namespace nair

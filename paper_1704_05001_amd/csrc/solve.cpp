@@ -31,6 +31,7 @@ struct Store<double> {
     static double *e0(Level &L) { return L.e0.get(); }
     static double *e1(Level &L) { return L.e1.get(); }
     static double *tmp(Level &L) { return L.tmp.get(); }
+    static double *fsave(Level &L) { return L.fsave.get(); }
 };
 
 template <>
@@ -43,6 +44,7 @@ struct Store<float> {
     static float *e0(Level &L) { return L.e0_32.get(); }
     static float *e1(Level &L) { return L.e1_32.get(); }
     static float *tmp(Level &L) { return L.tmp32.get(); }
+    static float *fsave(Level &L) { return L.fsave32.get(); }
 };
 
 // Dense solves of the systems that end on level l: e = A_k^{-1} r (or A_k^{-T} r).
@@ -57,11 +59,18 @@ void direct_solves(const Hier &h, const Level &L, bool trans, const T *r, T *e, 
 // Rows of the level's systems that are still iterating (all rows outside batched solves).
 Gate gate(const Hier &h, const Level &L) { return Gate{L.bsys.get(), h.active}; }
 
-// V-cycle on level l with right-hand side r_l and zero initial guess, no
-// pre-relaxation (section 5): restrict, recurse, interpolate, nu = k+1 Jacobi
-// F sweeps (section 5.1), optionally one C sweep.  Returns the correction.
 template <typename T>
-const T *vcycle(Hier &h, int l, hipStream_t s) {
+const T *coarse_solve(Hier &h, int l, bool fcyc, hipStream_t s);
+template <typename T>
+const T *coarse_solve_T(Hier &h, int l, bool fcyc, hipStream_t s);
+
+// V-cycle on level l with right-hand side r_l and zero initial guess, no
+// pre-relaxation (section 5): restrict, coarse solve, interpolate, nu = k+1
+// Jacobi F sweeps (section 5.1), optionally one C sweep.  Returns the
+// correction.  The coarse solve is a V-cycle, or for the F-cycle (fcyc) an
+// F-cycle followed by a V-cycle on its residual.
+template <typename T>
+const T *cycle(Hier &h, int l, bool fcyc, hipStream_t s) {
     using S = Store<T>;
     Level &L = *h.lv[l];
     const int bs = h.bs;
@@ -75,7 +84,7 @@ const T *vcycle(Hier &h, int l, hipStream_t s) {
         TimerScope ts(TK_RESTRICT, l, s);
         launch_restrict<T, T>(S::Z(L), S::r(L), L.cpts.get(), S::r(C), s, gate(h, C));
     }
-    const T *ec = vcycle<T>(h, l + 1, s);
+    const T *ec = coarse_solve<T>(h, l + 1, fcyc, s);
     {
         TimerScope ts(TK_INTERP, l, s);
         launch_interp<T>(L.pmap.get(), ec, S::e0(L), S::e1(L), L.A.nb, bs, s, gate(h, L));
@@ -104,7 +113,7 @@ const T *vcycle(Hier &h, int l, hipStream_t s) {
 // F sweeps (pre-relaxation), s = g - A^T y, restrict by P^T, recurse, and
 // y += R^T y_c = [Z^T y_c ; y_c].
 template <typename T>
-const T *vcycle_T(Hier &h, int l, hipStream_t s) {
+const T *cycle_T(Hier &h, int l, bool fcyc, hipStream_t s) {
     using S = Store<T>;
     Level &L = *h.lv[l];
     const int bs = h.bs;
@@ -135,11 +144,60 @@ const T *vcycle_T(Hier &h, int l, hipStream_t s) {
     launch_residual<T, T>(AT.with_groups(L.tune[TU_RESIDUAL_T]), S::r(L), cur, S::tmp(L), nullptr, s,
                           gate(h, L));
     launch_restrict_T<T>(L.ptptr.get(), L.ptidx.get(), S::tmp(L), S::r(C), L.nc, bs, s, gate(h, C));
-    const T *yc = vcycle_T<T>(h, l + 1, s);
+    const T *yc = coarse_solve_T<T>(h, l + 1, fcyc, s);
     launch_interp_T<T, T>(S::ZT(L), L.cidx.get(), yc, cur, s, gate(h, L));
     g_timer_level = l;
     direct_solves<T>(h, L, true, S::r(L), cur, s);   // systems that end on this level
     return cur;
+}
+
+// Coarse solve on level l (its right-hand side in r_l): a V-cycle, or for the
+// F-cycle e = F r + V (r - A F r): the F-cycle's correction is kept, the
+// residual replaces r_l, and the V-cycle's correction is added.
+template <typename T>
+const T *coarse_solve(Hier &h, int l, bool fcyc, hipStream_t s) {
+    if (!fcyc) return cycle<T>(h, l, false, s);
+    using S = Store<T>;
+    Level &L = *h.lv[l];
+    const Gate g = gate(h, L);
+    const T *e1 = cycle<T>(h, l, true, s);
+    launch_copy_vec<T>(S::fsave(L), e1, L.A.nb, h.bs, s, g);
+    launch_residual<T, T>(S::A(L), S::r(L), S::fsave(L), S::tmp(L), nullptr, s, g);
+    launch_copy_vec<T>(S::r(L), S::tmp(L), L.A.nb, h.bs, s, g);
+    const T *e2 = cycle<T>(h, l, false, s);
+    launch_add_vec<T>(S::fsave(L), e2, L.A.nb, h.bs, s, g);
+    return S::fsave(L);
+}
+
+// Its transpose: y = V^T r + F^T (r - A^T V^T r).
+template <typename T>
+const T *coarse_solve_T(Hier &h, int l, bool fcyc, hipStream_t s) {
+    if (!fcyc) return cycle_T<T>(h, l, false, s);
+    using S = Store<T>;
+    Level &L = *h.lv[l];
+    const Gate g = gate(h, L);
+    const T *y1 = cycle_T<T>(h, l, false, s);
+    launch_copy_vec<T>(S::fsave(L), y1, L.A.nb, h.bs, s, g);
+    launch_residual<T, T>(S::AT(L).with_groups(L.tune[TU_RESIDUAL_T]), S::r(L), S::fsave(L), S::tmp(L), nullptr, s,
+                          g);
+    launch_copy_vec<T>(S::r(L), S::tmp(L), L.A.nb, h.bs, s, g);
+    const T *y2 = cycle_T<T>(h, l, true, s);
+    launch_add_vec<T>(S::fsave(L), y2, L.A.nb, h.bs, s, g);
+    return S::fsave(L);
+}
+
+// Buffers the F-cycle's coarse solves keep their first correction in.
+void ensure_fcycle(Hier &h) {
+    if (h.prm.cycle != 1) return;
+    for (size_t l = 1; l < h.lv.size(); ++l) {
+        Level &L = *h.lv[l];
+        const size_t n = static_cast<size_t>(L.A.nb) * h.bs;
+        if (h.prm.precision == 1) {
+            if (!L.fsave32.get()) L.fsave32.alloc(n);
+        } else if (!L.fsave.get()) {
+            L.fsave.alloc(n);
+        }
+    }
 }
 
 
@@ -210,7 +268,7 @@ void batch_iteration(Hier &h, bool trans, const double *b, double *x, hipStream_
     Level &L0 = *h.lv[0];
     const int64_t n = static_cast<int64_t>(L0.A.nb) * h.bs;
     const bool fp32 = std::is_same<T, float>::value;
-    const T *e = trans ? vcycle_T<T>(h, 0, s) : vcycle<T>(h, 0, s);
+    const T *e = trans ? cycle_T<T>(h, 0, h.prm.cycle == 1, s) : cycle<T>(h, 0, h.prm.cycle == 1, s);
     if (h.prm.form == 1) {
         // scalar form: x += B_S D^{-1} r (transposed: x += D^{-T} B_S^T r) on the caller's block system
         const Gate g0{h.bsys0.get(), h.active};
@@ -310,6 +368,7 @@ nair_status run_solve_batch(Hier &h, bool trans, const double *b, double *x, dou
     const bool fp32 = h.prm.precision == 1;
     if (trans) ensure_transposes(h, s);
     ensure_batch(h, max_iter, s);
+    ensure_fcycle(h);
     B.rtol_host = rtol;
     NAIR_HIP(hipMemcpyAsync(B.rtol.get(), &B.rtol_host, sizeof(double), hipMemcpyHostToDevice, s));
     NAIR_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
@@ -404,6 +463,7 @@ void run_vcycle(Hier &h, bool trans, const double *r, double *e, hipStream_t s) 
     const bool fp32 = h.prm.precision == 1;
     const bool scaled = h.prm.form == 1;
     if (trans) ensure_transposes(h, s);
+    ensure_fcycle(h);
     if (scaled && !trans) {   // the scaled cycle reads D^{-1} r
         launch_block_diag_apply<double>(h.d0inv.get(), r, L0.r.get(), fp32 ? L0.r32.get() : nullptr, h.A0.nb, h.bs0,
                                         false, s);
@@ -412,7 +472,7 @@ void run_vcycle(Hier &h, bool trans, const double *r, double *e, hipStream_t s) 
         if (fp32) launch_to_float(r, L0.r32.get(), n, s);
     }
     if (fp32) {
-        const float *out = trans ? vcycle_T<float>(h, 0, s) : vcycle<float>(h, 0, s);
+        const float *out = trans ? cycle_T<float>(h, 0, h.prm.cycle == 1, s) : cycle<float>(h, 0, h.prm.cycle == 1, s);
         if (scaled && trans) {
             launch_block_diag_apply<float>(h.d0inv.get(), out, e, nullptr, h.A0.nb, h.bs0, true, s);
         } else {
@@ -420,7 +480,7 @@ void run_vcycle(Hier &h, bool trans, const double *r, double *e, hipStream_t s) 
             launch_axpy<float>(e, out, n, s);
         }
     } else {
-        const double *out = trans ? vcycle_T<double>(h, 0, s) : vcycle<double>(h, 0, s);
+        const double *out = trans ? cycle_T<double>(h, 0, h.prm.cycle == 1, s) : cycle<double>(h, 0, h.prm.cycle == 1, s);
         if (scaled && trans)
             launch_block_diag_apply<double>(h.d0inv.get(), out, e, nullptr, h.A0.nb, h.bs0, true, s);
         else

@@ -44,7 +44,7 @@ class _Params(C.Structure):
                 ("drop", C.c_double), ("relax", C.c_int32), ("max_levels", C.c_int32),
                 ("max_coarse_dofs", C.c_int32), ("seed", C.c_uint64),
                 ("cf_override_host", C.c_void_p), ("precision", C.c_int32), ("tuning", C.c_void_p),
-                ("form", C.c_int32)]
+                ("form", C.c_int32), ("cycle", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -159,6 +159,7 @@ class Params:
     precision: str = "fp64"      # "fp64" or "fp32" (FP32-stored hierarchy, FP64 refinement)
     tuning: Optional[np.ndarray] = None   # [levels, 6] lane groups from Hierarchy.autotune
     form: str = "block"          # "block" or "scalar" (scalar nAIR of D^{-1} A, D the block diagonal)
+    cycle: str = "V"             # "V" or "F"
 
 
 @dataclass
@@ -200,6 +201,9 @@ class Hierarchy:
         if params.form not in ("block", "scalar"):
             raise ValueError("form must be 'block' or 'scalar'")
         p.form = 1 if params.form == "scalar" else 0
+        if params.cycle not in ("V", "F"):
+            raise ValueError("cycle must be 'V' or 'F'")
+        p.cycle = 1 if params.cycle == "F" else 0
         cf = None
         if params.cf_override is not None:
             cf = np.ascontiguousarray(params.cf_override, dtype=np.int8)

@@ -14,7 +14,7 @@ torch = pytest.importorskip("torch")
 
 import oracle
 from nair_inputs import make_batch, concat_systems
-from test_gpu_parity import np_, _say, to_dev
+from test_gpu_parity import np_, _say, to_dev, oracle_kw
 
 import paper_1704_05001_amd as P
 
@@ -23,14 +23,14 @@ pytestmark = pytest.mark.gpu
 BATCH = "dg_q2_angles64_uneven"
 
 
-def build_batch(systems, gpu_kw=None, oracles=True, form_oracle=0, **kw):
+def build_batch(systems, gpu_kw=None, oracles=True, **kw):
     rp, ci, va, rhs, sys_nb = concat_systems(systems)
     d_rp, d_ci, d_va = to_dev(rp, ci, va)
     G = P.Hierarchy(d_rp, d_ci, d_va, systems[0].bs, P.Params(**kw, **(gpu_kw or {})), sys_nb=sys_nb)
     Os = None
     if oracles:
-        Os = [oracle.Hierarchy(S.nb, S.bs, S.rowptr, S.colidx, S.vals, oracle.Params(form=form_oracle, **kw))
-              for S in systems]
+        okw = oracle_kw(gpu_kw, kw)
+        Os = [oracle.Hierarchy(S.nb, S.bs, S.rowptr, S.colidx, S.vals, oracle.Params(**okw)) for S in systems]
     return G, Os, rhs
 
 

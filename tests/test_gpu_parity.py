@@ -50,11 +50,19 @@ def build_pair(nb, bs, rp, ci, va, gpu_kw=None, **kw):
     d_rp, d_ci, d_va = to_dev(rp, ci, va)
     gpu_kw = dict(gpu_kw or {})
     G = P.Hierarchy(d_rp, d_ci, d_va, bs, P.Params(**kw, **gpu_kw))
-    okw = dict(kw)
-    if gpu_kw.get("form") == "scalar":
-        okw["form"] = 1
-    O = oracle.Hierarchy(nb, bs, rp, ci, va, oracle.Params(**okw))
+    O = oracle.Hierarchy(nb, bs, rp, ci, va, oracle.Params(**oracle_kw(gpu_kw, kw)))
     return G, O
+
+
+def oracle_kw(gpu_kw, kw):
+    """Oracle parameters for GPU parameters: form "scalar" is the oracle's form 1,
+    cycle "F" its cycle 1; precision and tuning have no oracle counterpart."""
+    okw = dict(kw)
+    if (gpu_kw or {}).get("form") == "scalar":
+        okw["form"] = 1
+    if (gpu_kw or {}).get("cycle") == "F":
+        okw["cycle"] = 1
+    return okw
 
 
 def np_(t):

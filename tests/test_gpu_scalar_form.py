@@ -45,7 +45,7 @@ def test_scalar_form_fp32_and_tuned():
 def test_scalar_form_batched():
     _say("test: scalar form, batch of angles")
     systems, k = make_batch("dg_q2_angles64_uneven", sizes=(4, 9, 7), nang=4)
-    G, Os, rhs = build_batch(systems, gpu_kw=dict(form="scalar"), degree=k, form_oracle=1)
+    G, Os, rhs = build_batch(systems, gpu_kw=dict(form="scalar"), degree=k)
     compare_batch(G, Os)
     check_batch_solve(G, Os, systems, rhs)
     g = np.random.default_rng(8).uniform(-1, 1, rhs.size)
