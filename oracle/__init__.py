@@ -36,7 +36,8 @@ class _Params(C.Structure):
     _fields_ = [("degree", C.c_int32), ("theta", C.c_double), ("phi", C.c_double),
                 ("drop", C.c_double), ("relax", C.c_int32), ("max_levels", C.c_int32),
                 ("max_coarse_dofs", C.c_int32), ("seed", C.c_uint64),
-                ("cf_override", C.c_void_p), ("form", C.c_int32), ("cycle", C.c_int32)]
+                ("cf_override", C.c_void_p), ("form", C.c_int32), ("cycle", C.c_int32),
+                ("gmres", C.c_int32)]
 
 
 class _LevelView(C.Structure):
@@ -114,6 +115,7 @@ class Params:
     cf_override: Optional[np.ndarray] = None
     form: int = 0             # 0 = block nAIR, 1 = scalar nAIR after block-diagonal scaling
     cycle: int = 0            # 0 = V-cycle, 1 = F-cycle
+    gmres: int = 0            # 0 = stationary iteration, m > 0 = GMRES(m) preconditioned by the cycle
 
 
 @dataclass
@@ -158,6 +160,7 @@ class Hierarchy:
         p.seed = params.seed
         p.form = params.form
         p.cycle = params.cycle
+        p.gmres = params.gmres
         self._cf = None
         if params.cf_override is not None:
             self._cf = np.ascontiguousarray(params.cf_override, dtype=np.int8)

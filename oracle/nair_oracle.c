@@ -777,6 +777,7 @@ void ora_default_params(ora_params *p) {
     p->cf_override = NULL;
     p->form = 0;
     p->cycle = 0;
+    p->gmres = 0;
 }
 
 static int validate(int32_t nb, int32_t bs, const int32_t *rowptr, const int32_t *colidx) {
@@ -879,6 +880,7 @@ int ora_setup(int32_t nb, int32_t bs, const int32_t *rowptr, const int32_t *coli
     *out = NULL;
     if (prm->degree < 0 || prm->max_levels < 1 || prm->max_levels > ORA_MAX_LEVELS) return ORA_EINVAL;
     if (prm->cycle != 0 && prm->cycle != 1) return ORA_EINVAL;
+    if (prm->gmres < 0 || prm->gmres > 200) return ORA_EINVAL;
     if (!(prm->theta >= 0.0 && prm->theta < 1.0) || !(prm->phi >= 0.0 && prm->phi < 1.0) ||
         !(prm->drop >= 0.0 && prm->drop < 1.0))
         return ORA_EINVAL;
@@ -1233,9 +1235,137 @@ static void precondition(const ora_hier *h, int trans, const double *r, double *
     free(w);
 }
 
+static double dot(const double *u, const double *v, int64_t n) {
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += u[i] * v[i];
+    return s;
+}
+
+/* y = A v (trans: A^T v) */
+static void matvec(const bsr_t *A, int trans, const double *v, double *y) {
+    const int64_t n = (int64_t)A->nb * A->bs;
+    double *zero = (double *)calloc((size_t)n, sizeof(double));
+    if (trans) residual_T(A, zero, v, y);
+    else
+        for (int32_t I = 0; I < A->nb; ++I) block_row_residual(A, I, zero, v, y + (size_t)I * A->bs);
+    for (int64_t i = 0; i < n; ++i) y[i] = -y[i];
+    free(zero);
+}
+
+/*
+ * Right-preconditioned restarted GMRES(m) (Saad and Schultz) with the cycle B
+ * as preconditioner: Arnoldi on A B with modified Gram-Schmidt, Givens
+ * rotations of the Hessenberg matrix, x = x_0 + Z y with Z = B V kept.  The
+ * history is the least-squares residual |g_{j+1}| / ||b|| of every inner step
+ * (the true relative residual in exact arithmetic); each restart starts from
+ * the true residual.
+ */
+static int gmres_impl(ora_hier *h, int trans, const double *b, double *x, double rtol, int32_t max_iter,
+                      double *hist, int32_t *iters, double *relres) {
+    const bsr_t *A = h->prm.form == 1 ? &h->A0 : &h->lv[0].A;
+    const int64_t n = (int64_t)A->nb * A->bs;
+    const int32_t m = h->prm.gmres;
+    for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+    if (iters) *iters = 0;
+    if (relres) *relres = 0.0;
+    double bn = norm2(b, n);
+    if (!isfinite(bn)) return ORA_ENUMERIC;
+    if (bn == 0.0) return ORA_OK;
+    double *V = (double *)malloc(sizeof(double) * (size_t)n * (m + 1));
+    double *Z = (double *)malloc(sizeof(double) * (size_t)n * m);
+    double *w = (double *)malloc(sizeof(double) * (size_t)n);
+    double *H = (double *)calloc((size_t)(m + 1) * m, sizeof(double));   /* H[i*m + j] */
+    double *cs = (double *)malloc(sizeof(double) * m), *sn = (double *)malloc(sizeof(double) * m);
+    double *g = (double *)malloc(sizeof(double) * (m + 1)), *y = (double *)malloc(sizeof(double) * m);
+    int st = ORA_ENOCONV;
+    double rel = 1.0;
+    int32_t it = 0;
+    memcpy(w, b, sizeof(double) * (size_t)n);   /* r_0 = b (x_0 = 0) */
+    while (it < max_iter) {
+        const double beta = norm2(w, n);
+        if (!isfinite(beta)) {
+            st = ORA_ENUMERIC;
+            break;
+        }
+        for (int64_t i = 0; i < n; ++i) V[i] = w[i] / beta;
+        for (int32_t i = 0; i <= m; ++i) g[i] = 0.0;
+        g[0] = beta;
+        int32_t j = 0, done = 0;
+        for (; j < m && it < max_iter; ++j) {
+            precondition(h, trans, V + (size_t)j * n, Z + (size_t)j * n);
+            matvec(A, trans, Z + (size_t)j * n, w);
+            for (int32_t i = 0; i <= j; ++i) {
+                const double hij = dot(w, V + (size_t)i * n, n);
+                H[i * m + j] = hij;
+                for (int64_t k = 0; k < n; ++k) w[k] -= hij * V[(size_t)i * n + k];
+            }
+            const double hn = norm2(w, n);
+            H[(j + 1) * m + j] = hn;
+            if (hn != 0.0)
+                for (int64_t k = 0; k < n; ++k) V[(size_t)(j + 1) * n + k] = w[k] / hn;
+            for (int32_t i = 0; i < j; ++i) {   /* earlier rotations */
+                const double a = H[i * m + j], c = H[(i + 1) * m + j];
+                H[i * m + j] = cs[i] * a + sn[i] * c;
+                H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+            }
+            const double a = H[j * m + j], c = H[(j + 1) * m + j];
+            const double rho = sqrt(a * a + c * c);
+            cs[j] = rho == 0.0 ? 1.0 : a / rho;
+            sn[j] = rho == 0.0 ? 0.0 : c / rho;
+            H[j * m + j] = rho;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            rel = fabs(g[j + 1]) / bn;
+            if (hist) hist[it] = rel;
+            ++it;
+            if (!isfinite(rel)) {
+                st = ORA_ENUMERIC;
+                done = 1;
+                ++j;
+                break;
+            }
+            if (rel <= rtol || hn == 0.0) {
+                done = 1;
+                ++j;
+                break;
+            }
+        }
+        /* x += Z y, H[0:j, 0:j] y = g[0:j] (back substitution) */
+        for (int32_t i = j - 1; i >= 0; --i) {
+            double sacc = g[i];
+            for (int32_t k = i + 1; k < j; ++k) sacc -= H[i * m + k] * y[k];
+            y[i] = sacc / H[i * m + i];
+        }
+        for (int32_t i = 0; i < j; ++i)
+            for (int64_t k = 0; k < n; ++k) x[k] += y[i] * Z[(size_t)i * n + k];
+        if (st == ORA_ENUMERIC) break;
+        /* the true residual for the restart (and the final status) */
+        matvec(A, trans, x, w);
+        for (int64_t k = 0; k < n; ++k) w[k] = b[k] - w[k];
+        if (done) {
+            st = (rel <= rtol) ? ORA_OK : ORA_ENOCONV;
+            if (st != ORA_OK && norm2(w, n) / bn <= rtol) st = ORA_OK;
+            break;
+        }
+    }
+    if (iters) *iters = it;
+    if (relres) *relres = rel;
+    free(V);
+    free(Z);
+    free(w);
+    free(H);
+    free(cs);
+    free(sn);
+    free(g);
+    free(y);
+    return st;
+}
+
 static int solve_impl(ora_hier *h, int trans, const double *b, double *x, double rtol, int32_t max_iter,
                       double *hist, int32_t *iters, double *relres) {
     if (!h || !b || !x) return ORA_EINVAL;
+    if (h->prm.gmres > 0) return gmres_impl(h, trans, b, x, rtol, max_iter, hist, iters, relres);
     const bsr_t *A = h->prm.form == 1 ? &h->A0 : &h->lv[0].A;
     int64_t n = (int64_t)A->nb * A->bs;
     for (int64_t i = 0; i < n; ++i) x[i] = 0.0;

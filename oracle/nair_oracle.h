@@ -53,6 +53,9 @@ typedef struct {
     int32_t form;             /* 0: block nAIR; 1: scalar nAIR of the system scaled by the
                                  block-diagonal inverse (the paper's default form) */
     int32_t cycle;            /* 0: V-cycle; 1: F-cycle (section "Scaling in h and element order") */
+    int32_t gmres;            /* 0: stationary iteration; m > 0: right-preconditioned GMRES(m)
+                                 with the cycle as preconditioner (the paper's "nAIR-preconditioned
+                                 GMRES") */
 } ora_params;
 
 /* A view of one level, valid until ora_free.  Arrays that do not exist on a

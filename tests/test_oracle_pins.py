@@ -828,3 +828,57 @@ def test_fcycle_exact_on_triangular_and_no_slower():
     ocf, ccf = HF.complexity()
     ocv, ccv = HV.complexity()
     assert ocf == ocv and ccf > ccv
+
+
+# ------------------------------------------------------------------- GMRES
+
+def test_gmres_minimises_the_residual_over_the_krylov_space():
+    """Right-preconditioned GMRES: after k steps x_k = B U y with U spanning
+    {b, (A B) b, ..., (A B)^{k-1} b} and y minimising ||b - A B U y||; its
+    history entry is that minimum over ||b|| (dense least squares)."""
+    S = small_dg(7, 2, seed=51)
+    H = hier(S, degree=0, max_coarse_dofs=30, gmres=20)
+    A = S.to_dense()
+    B = dense_B(H.vcycle, S.n)
+    x, hist, st = H.solve(S.rhs, 1e-13, 200)
+    assert st == "OK"
+    assert np.all(np.diff(hist[:20]) <= 1e-15)          # non-increasing within a cycle
+    AB = A @ B
+    u = S.rhs / np.linalg.norm(S.rhs)
+    U = [u]
+    checked = 0
+    for k in range(1, 8):
+        if hist[k - 1] < 1e-9:                              # the basis would be too ill-conditioned
+            break
+        checked += 1
+        Uk = np.stack(U, axis=1)
+        y, *_ = np.linalg.lstsq(AB @ Uk, S.rhs, rcond=None)
+        res = np.linalg.norm(S.rhs - AB @ Uk @ y) / np.linalg.norm(S.rhs)
+        assert abs(res - hist[k - 1]) <= 1e-8 * max(res, 1e-14), (k, res, hist[k - 1])
+        nxt = AB @ U[-1]
+        for v in U:                                        # orthonormalise for conditioning
+            nxt -= (nxt @ v) * v
+        U.append(nxt / np.linalg.norm(nxt))
+    assert checked >= 4
+    ref = np.linalg.solve(A, S.rhs)
+    assert np.abs(x - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("m,cycle", [(3, 0), (30, 1)])
+def test_gmres_solves_and_transposed(m, cycle):
+    """Restarted GMRES(m) (also F-cycle preconditioned) reaches the dense
+    solutions of A x = b and A^T y = g."""
+    S = small_dg(6, 2, seed=52)
+    H = hier(S, degree=2, max_coarse_dofs=30, gmres=m, cycle=cycle)
+    x, hist, st = H.solve(S.rhs, 1e-12, 300)
+    assert st == "OK"
+    ref = np.linalg.solve(S.to_dense(), S.rhs)
+    assert np.abs(x - ref).max() <= 1e-10 * np.abs(ref).max()
+    g = np.random.default_rng(4).uniform(-1, 1, S.n)
+    y, hT, stT = H.solve_T(g, 1e-12, 300)
+    refT = np.linalg.solve(S.to_dense().T, g)
+    assert stT == "OK" and np.abs(y - refT).max() <= 1e-10 * np.abs(refT).max()
+    HS = hier(S, degree=2, max_coarse_dofs=30)
+    xs, hs, _ = HS.solve(S.rhs, 1e-12, 300)
+    if m >= 10:
+        assert len(hist) <= len(hs)                       # an accelerator, not a slowdown
