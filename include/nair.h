@@ -75,6 +75,16 @@ typedef struct {
                                  followed by a V-cycle on its residual (the F-cycles of the section
                                  "Scaling in h and element order"); the transposed solve applies the
                                  exact transpose */
+    int32_t gmres;            /* 0: stationary iteration (default); m in [1, 200]: restarted GMRES(m)
+                                 right-preconditioned by one cycle per iteration (the section "Non-
+                                 triangular matrices" uses one nAIR V-cycle as a GMRES
+                                 preconditioner).  The Arnoldi basis is orthogonalised by classical
+                                 Gram-Schmidt applied twice (equal to modified Gram-Schmidt in exact
+                                 arithmetic), the least-squares problem by Givens rotations; each
+                                 restart starts from the true residual.  Iteration j's history entry
+                                 is the least-squares estimate |g_{j+1}| / ||b|| of the relative
+                                 residual.  Single-system handles only (nair_solve_batch returns
+                                 NAIR_EINVAL); takes (2m + 2) n extra doubles on the first solve. */
 } nair_params;
 
 typedef struct {
@@ -147,7 +157,10 @@ nair_status nair_setup_batch(int32_t nsys, const int32_t *sys_nb, int32_t bs, co
  * one V-cycle (no pre-relaxation, section 5), until ||b - A x||_2 / ||b||_2 <=
  * rtol or max_iter iterations.  b and x are device vectors of nb*bs doubles;
  * x is overwritten.  res (host, may be NULL) receives the statistics.
- * Returns NAIR_OK, NAIR_ENOCONV (x = last iterate) or NAIR_ENUMERIC.
+ * Returns NAIR_OK, NAIR_ENOCONV (x = last iterate) or NAIR_ENUMERIC.  With
+ * nair_params.gmres = m > 0 the iteration is GMRES(m) preconditioned by the
+ * cycle instead; it stops when the least-squares estimate reaches rtol and
+ * reports NAIR_OK if the estimate or the true residual of x is within rtol.
  */
 nair_status nair_solve(nair_hier h, const double *b, double *x, double rtol, int32_t max_iter,
                        nair_result *res, void *stream);

@@ -73,6 +73,7 @@ nair_status nair_default_params(nair_params *p) {
     p->tuning = nullptr;
     p->form = 0;
     p->cycle = 0;
+    p->gmres = 0;
     return NAIR_OK;
 }
 
@@ -95,6 +96,8 @@ static nair_status setup_common(int32_t nsys, const int32_t *sys_nb, int32_t nb,
     if (p->precision != 0 && p->precision != 1) return bad(nullptr, "precision must be 0 (FP64) or 1 (FP32 hierarchy)");
     if (p->form != 0 && p->form != 1) return bad(nullptr, "form must be 0 (block) or 1 (scalar after scaling)");
     if (p->cycle != 0 && p->cycle != 1) return bad(nullptr, "cycle must be 0 (V) or 1 (F)");
+    if (p->gmres < 0 || p->gmres > nair::kMaxGmres)
+        return bad(nullptr, "gmres must be 0 (stationary iteration) or a restart length in [1, 200]");
     if (p->max_levels < 1 || p->max_levels > nair::kMaxLevels) return bad(nullptr, "max_levels must be in [1, 64]");
     if (p->max_coarse_dofs < 0 || p->max_coarse_dofs > nair::kStallDenseDofs)
         return bad(nullptr, "max_coarse_dofs must be in [0, 4096]");
@@ -158,6 +161,7 @@ nair_status nair_solve_batch(nair_hier h, int32_t trans, const double *b, double
     if (!b || !x) return bad(h, "NULL vector");
     if (!(rtol >= 0.0) || max_iter < 0) return bad(h, "need rtol >= 0 and max_iter >= 0");
     if (trans != 0 && trans != 1) return bad(h, "trans must be 0 or 1");
+    if (h->h.prm.gmres > 0) return bad(h, "GMRES acceleration solves one system: use nair_solve / nair_solve_T");
     DeviceGuard dg(h->h.device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     return guarded(h, [&]() {

@@ -15,6 +15,7 @@ namespace nair {
 constexpr int kMaxBs = 32;          // largest block size the kernels accept
 constexpr int kMaxLevels = 64;
 constexpr int kStallDenseDofs = 4096;
+constexpr int kMaxGmres = 200;      // longest GMRES restart cycle
 constexpr int kHashSmall = 2048;    // LDS hash slots of the per-wave symbolic kernels
 constexpr int kHashLarge = 8192;    // LDS hash slots of the per-workgroup fallback
 
@@ -216,7 +217,7 @@ __device__ inline bool live(const Gate &g, int row) {
     return g.active == nullptr || g.active[g.bsys ? g.bsys[row] : 0] != 0;
 }
 
-// r = b - A x (+ a float copy if r_lo)
+// r = b - A x (b == nullptr: r = A x), plus a float copy if r_lo
 template <typename MT, typename VT>
 void launch_residual(const MatView<MT> &A, const VT *b, const VT *x, VT *r, float *r_lo, hipStream_t s,
                      Gate g = Gate());
@@ -279,6 +280,18 @@ void build_scaled(const DevBSR &A, const double *dinv, DevBSR &S, hipStream_t s)
 template <typename VT>
 void launch_block_diag_apply(const double *dinv, const VT *v, double *out, float *out32, int nb, int bs, bool trans,
                              hipStream_t s, Gate g = Gate());
+
+// ----------------------------------------------------------------- Krylov
+// V holds nv vectors of n doubles, vector i at V + i * ld.
+// out[i] = <V_i, w> for i < nv (part: mdot_parts(n) * nv doubles of scratch).
+// Deterministic: fixed chunks, fixed reduction order.
+int64_t mdot_parts(int64_t n);
+void launch_mdot(const double *V, int64_t ld, int nv, const double *w, int64_t n, double *part, double *out,
+                 hipStream_t s);
+// w -= sum_i c[i] V_i, i ascending (c on the device)
+void launch_maxpy(const double *V, int64_t ld, int nv, const double *c, double *w, int64_t n, hipStream_t s);
+// v = w / sqrt(*ss) (device scalar)
+void launch_unit(const double *w, const double *ss, double *v, int64_t n, hipStream_t s);
 
 // ------------------------------------------------------------------- grad
 void grad_vals(int nb, int bs, const int *rowptr, const int *colidx, const double *ybar, const double *x,

@@ -131,7 +131,7 @@ __device__ inline double block_reduce_sum(double v, double *lds) {
     return s;   // valid in thread 0
 }
 
-// r = b - A x; r_lo (if given) receives r rounded to float.
+// r = b - A x (b == nullptr: r = A x); r_lo (if given) receives r rounded to float.
 template <int BS, typename MT, typename VT>
 __global__ __launch_bounds__(kThreads) void k_residual(const int *__restrict__ rowptr, const int *__restrict__ colidx,
                                                       const MT *__restrict__ vals, int nb, int bs_rt, int G,
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int *__restrict__ r
     acc = reduce_groups(acc, L, G, bs, part);
     if (act && L.g == 0) {
         const int64_t o = static_cast<int64_t>(I) * bs + L.a;
-        const double rv = static_cast<double>(b[o]) - acc;
+        const double rv = b ? static_cast<double>(b[o]) - acc : acc;
         r[o] = static_cast<VT>(rv);
         if (r_lo) r_lo[o] = static_cast<float>(rv);
     }

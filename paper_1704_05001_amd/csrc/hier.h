@@ -80,6 +80,15 @@ struct BatchSolve {
     ~BatchSolve();
 };
 
+// Vectors of restarted GMRES(m): the Krylov basis V (m+1 vectors), the
+// preconditioned directions Z (m), the work vector w, reduction scratch and
+// the device side of the Hessenberg columns.
+struct Krylov {
+    int m = 0;
+    int64_t n = 0;
+    DBuf<double> V, Z, w, part, hd, c;
+};
+
 struct Hier {
     nair_params prm{};
     int bs = 0;                     // block size of the hierarchy (1 for the scalar form)
@@ -97,6 +106,7 @@ struct Hier {
     std::vector<double> hist;
     std::string err;
     BatchSolve batch;
+    Krylov krylov;
     const int *active = nullptr;    // during a batched solve: per-system "still iterating" flags
 };
 
@@ -110,6 +120,14 @@ nair_status run_solve(Hier &h, bool trans, const double *b, double *x, double rt
 nair_status run_solve_batch(Hier &h, bool trans, const double *b, double *x, double rtol, int max_iter,
                             bool use_graph, nair_result *res, hipStream_t s);
 void run_vcycle(Hier &h, bool trans, const double *r, double *e, hipStream_t s);
+// Operators the cycle (trans: the transposed cycle) needs, built once.
+void prepare_cycle(Hier &h, bool trans, hipStream_t s);
+// e = B r (trans: B^T r) on the stream, no synchronisation; r and e are the
+// caller's dofs (the scalar form's scaling included); prepare_cycle first.
+void apply_cycle(Hier &h, bool trans, const double *r, double *e, hipStream_t s);
+// Restarted GMRES(prm.gmres) right-preconditioned by the cycle (one system).
+nair_status run_gmres(Hier &h, bool trans, const double *b, double *x, double rtol, int max_iter, nair_result *res,
+                      hipStream_t s);
 void ensure_transposes(Hier &h, hipStream_t s);
 // Time every feasible lane-group count of each cycle kernel on each level and
 // keep the fastest (reps launches per candidate); table (host, may be null)

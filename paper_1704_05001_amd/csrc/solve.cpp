@@ -454,16 +454,20 @@ nair_status run_solve_batch(Hier &h, bool trans, const double *b, double *x, dou
 // capture per call would cost more than it saves on one solve).
 nair_status run_solve(Hier &h, bool trans, const double *b, double *x, double rtol, int max_iter, nair_result *res,
                       hipStream_t s) {
+    if (h.prm.gmres > 0) return run_gmres(h, trans, b, x, rtol, max_iter, res, s);
     return run_solve_batch(h, trans, b, x, rtol, max_iter, false, res, s);
 }
 
-void run_vcycle(Hier &h, bool trans, const double *r, double *e, hipStream_t s) {
+void prepare_cycle(Hier &h, bool trans, hipStream_t s) {
+    if (trans) ensure_transposes(h, s);
+    ensure_fcycle(h);
+}
+
+void apply_cycle(Hier &h, bool trans, const double *r, double *e, hipStream_t s) {
     Level &L0 = *h.lv[0];
     const int64_t n = static_cast<int64_t>(L0.A.nb) * h.bs;
     const bool fp32 = h.prm.precision == 1;
     const bool scaled = h.prm.form == 1;
-    if (trans) ensure_transposes(h, s);
-    ensure_fcycle(h);
     if (scaled && !trans) {   // the scaled cycle reads D^{-1} r
         launch_block_diag_apply<double>(h.d0inv.get(), r, L0.r.get(), fp32 ? L0.r32.get() : nullptr, h.A0.nb, h.bs0,
                                         false, s);
@@ -486,6 +490,11 @@ void run_vcycle(Hier &h, bool trans, const double *r, double *e, hipStream_t s) 
         else
             NAIR_HIP(hipMemcpyAsync(e, out, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     }
+}
+
+void run_vcycle(Hier &h, bool trans, const double *r, double *e, hipStream_t s) {
+    prepare_cycle(h, trans, s);
+    apply_cycle(h, trans, r, e, s);
     NAIR_HIP(hipStreamSynchronize(s));
 }
 

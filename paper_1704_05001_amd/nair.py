@@ -44,7 +44,7 @@ class _Params(C.Structure):
                 ("drop", C.c_double), ("relax", C.c_int32), ("max_levels", C.c_int32),
                 ("max_coarse_dofs", C.c_int32), ("seed", C.c_uint64),
                 ("cf_override_host", C.c_void_p), ("precision", C.c_int32), ("tuning", C.c_void_p),
-                ("form", C.c_int32), ("cycle", C.c_int32)]
+                ("form", C.c_int32), ("cycle", C.c_int32), ("gmres", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -160,6 +160,7 @@ class Params:
     tuning: Optional[np.ndarray] = None   # [levels, 6] lane groups from Hierarchy.autotune
     form: str = "block"          # "block" or "scalar" (scalar nAIR of D^{-1} A, D the block diagonal)
     cycle: str = "V"             # "V" or "F"
+    gmres: int = 0               # 0: stationary iteration; m > 0: GMRES(m) preconditioned by the cycle
 
 
 @dataclass
@@ -204,6 +205,7 @@ class Hierarchy:
         if params.cycle not in ("V", "F"):
             raise ValueError("cycle must be 'V' or 'F'")
         p.cycle = 1 if params.cycle == "F" else 0
+        p.gmres = int(params.gmres)
         cf = None
         if params.cf_override is not None:
             cf = np.ascontiguousarray(params.cf_override, dtype=np.int8)
@@ -267,12 +269,14 @@ class Hierarchy:
 
     def solve(self, b, x=None, rtol=1e-10, max_iter=200, stream=None,
               raise_on=("EINVAL", "EDEVICE", "ENOMEM")):
-        """x = A^{-1} b by nAIR V-cycles.  Returns (x, Result)."""
+        """x = A^{-1} b by nAIR cycles (the stationary iteration, or GMRES(m)
+        preconditioned by the cycle when Params.gmres = m > 0).  Returns (x, Result)."""
         return self._solve(lib().nair_solve, "nair_solve", b, x, rtol, max_iter, stream, raise_on)
 
     def solve_T(self, g, y=None, rtol=1e-10, max_iter=200, stream=None,
                 raise_on=("EINVAL", "EDEVICE", "ENOMEM")):
-        """y = A^{-T} g by transposed nAIR V-cycles.  Returns (y, Result)."""
+        """y = A^{-T} g by transposed nAIR cycles (GMRES(m) with Params.gmres = m).
+        Returns (y, Result)."""
         return self._solve(lib().nair_solve_T, "nair_solve_T", g, y, rtol, max_iter, stream, raise_on)
 
     def solve_batch(self, b, x=None, rtol=1e-10, max_iter=200, trans=False, graph=True, stream=None,
