@@ -65,7 +65,10 @@ def measured_traffic(workload: str, grid_threads: int):
 
 def relax_level_bytes(lv: dict) -> dict:
     """Algorithmic HBM bytes of one F-relaxation sweep on a level: each operand
-    read once, each output written once (int32 indices, FP64 values)."""
+    read once, each output written once (int32 indices, FP64 values).  With a
+    face-compressed copy the sweep reads a diagonal block whole and, of an
+    off-diagonal block, its 8-byte row/column masks and the entries on its
+    nonzero rows and columns."""
     import numpy as np
     rp = lv["rowptr"].cpu().numpy().astype(np.int64)
     cf = lv["cf"].cpu().numpy()
@@ -76,7 +79,16 @@ def relax_level_bytes(lv: dict) -> dict:
     nF = int(F.sum())
     nnzF = int(rowlen[F].sum())
     n = lv["nb"] * bs
-    bytes_A = nnzF * (bb * 8 + 4)          # F rows of A (values + column indices)
+    if lv.get("face_meta") is not None:
+        rows = np.repeat(np.arange(lv["nb"]), rowlen)
+        inF = F[rows]
+        diag = lv["colidx"].cpu().numpy() == rows
+        meta = lv["face_meta"].cpu().numpy().view(np.uint64)
+        nr = np.bitwise_count(meta & np.uint64(0xFFFFFFFF)).astype(np.int64)
+        nc = np.bitwise_count(meta >> np.uint64(32)).astype(np.int64)
+        bytes_A = int((inF & diag).sum()) * (bb * 8 + 4) + int((12 + 8 * nr * nc)[inF & ~diag].sum())
+    else:
+        bytes_A = nnzF * (bb * 8 + 4)      # F rows of A (values + column indices)
     bytes_D = nF * bb * 8                  # D_F^{-1}
     bytes_idx = nF * 4 + nF * 8            # F list, rowptr pairs
     bytes_vec = n * 8 + nF * bs * 8 * 2    # e_in (gathered, read once), r_F, e_out_F
@@ -108,13 +120,13 @@ def batched_leg(args, P, torch, np):
     tables = {}
 
     def run(prec, graph):
-        prm = P.Params(degree=degree, precision=prec)
+        prm = P.Params(faces=not args.no_faces, degree=degree, precision=prec)
         if not args.no_tune:
             if prec not in tables:   # lane groups tuned once per precision on the batch hierarchy
                 Ht = P.Hierarchy(d_rp, d_ci, d_va, 9, prm, sys_nb=sys_nb)
                 tables[prec] = Ht.autotune(reps=10)
                 Ht.close()
-            prm = P.Params(degree=degree, precision=prec, tuning=tables[prec])
+            prm = P.Params(faces=not args.no_faces, degree=degree, precision=prec, tuning=tables[prec])
         times, iters = [], None
         for i in range(1 + args.batch_steps):        # first step untimed (warm-up)
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -147,7 +159,7 @@ def batched_leg(args, P, torch, np):
     res["tuned"] = not args.no_tune
     # the same systems one after another: setup + solve each with the plain entry points
     # (default lane groups: a tuning table fits one hierarchy structure)
-    prm = P.Params(degree=degree)
+    prm = P.Params(faces=not args.no_faces, degree=degree)
     per = []
     offs = np.concatenate(([0], np.cumsum([S.nnzb for S in systems])))
     boff = np.concatenate(([0], np.cumsum(sys_nb)))
@@ -197,6 +209,8 @@ def main(argv=None):
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-angles leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default lane groups (no autotuning)")
+    ap.add_argument("--no-faces", action="store_true",
+                    help="read whole blocks of the finest operator (no face-compressed copy)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched leg and print its JSON (for profiling it alone)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -241,7 +255,7 @@ def main(argv=None):
     g = torch.from_numpy(np.random.Generator(np.random.PCG64(300)).uniform(-1, 1, S.n)).to(dev)
     x = torch.empty_like(b)
     y = torch.empty_like(g)
-    params = P.Params(degree=degree)
+    params = P.Params(faces=not args.no_faces, degree=degree)
     stream = torch.cuda.current_stream()
 
     def step(record, prm=params, xo=x, yo=y, timed=False):
@@ -271,12 +285,14 @@ def main(argv=None):
         if i == 0:
             info = H.info()
             lvl = H.level(args.roofline_level)
+            lvl0 = H.level(0, fields=())
             log(f"levels {info['levels']} nb {info['nb']} OC {info['oc']:.2f} CC {info['cc']:.2f}")
         H.close()
     if args.warmup == 0:
         H = step(None)
         info = H.info()
         lvl = H.level(args.roofline_level)
+        lvl0 = H.level(0, fields=())
         H.close()
 
     tuning = None
@@ -285,7 +301,7 @@ def main(argv=None):
         Ht = P.Hierarchy(rp, ci, va, S.bs, params)
         tuning = Ht.autotune(reps=20)
         Ht.close()
-        params = P.Params(degree=degree, tuning=tuning)
+        params = P.Params(faces=not args.no_faces, degree=degree, tuning=tuning)
         for _ in range(max(1, args.warmup)):
             step(None, params).close()
 
@@ -346,7 +362,8 @@ def main(argv=None):
         "config": {"workload": args.workload, "mesh": f"{S.N}x{S.N} quads", "dg_order": S.p,
                    "dofs": S.n, "block": S.bs, "nnzb": S.nnzb, "neumann_degree": degree,
                    "rtol": args.rtol, "levels": info["levels"], "oc": round(info["oc"], 3),
-                   "cc": round(info["cc"], 3)},
+                   "cc": round(info["cc"], 3),
+                   "face_blocks": ([lvl0["face_rmax"], lvl0["face_cmax"]] if lvl0["face_rmax"] > 0 else None)},
         "setup_ms": round(float(setup_ms), 3), "solve_ms": round(float(solve_ms), 3),
         "solve_T_ms": round(float(solveT_ms), 3), "iters": iters, "iters_T": itersT,
         "step": "setup + solve + transposed solve; value = dofs / (setup + solve)",
@@ -358,10 +375,10 @@ def main(argv=None):
 
     if not args.no_fp32:
         # the same steps with the FP32-stored hierarchy (FP64 setup, refinement and residuals)
-        p32 = P.Params(degree=degree, precision="fp32")
+        p32 = P.Params(faces=not args.no_faces, degree=degree, precision="fp32")
         if not args.no_tune:
             Ht = P.Hierarchy(rp, ci, va, S.bs, p32)
-            p32 = P.Params(degree=degree, precision="fp32", tuning=Ht.autotune(reps=20))
+            p32 = P.Params(faces=not args.no_faces, degree=degree, precision="fp32", tuning=Ht.autotune(reps=20))
             Ht.close()
         x32, y32 = torch.empty_like(b), torch.empty_like(g)
         for _ in range(max(1, args.warmup)):

@@ -85,6 +85,14 @@ typedef struct {
                                  is the least-squares estimate |g_{j+1}| / ||b|| of the relative
                                  residual.  Single-system handles only (nair_solve_batch returns
                                  NAIR_EINVAL); takes (2m + 2) n extra doubles on the first solve. */
+    int32_t faces;            /* 1 (default): when the finest operator's off-diagonal blocks are
+                                 nonzero only on a few rows and columns (upwind DG face blocks: the
+                                 two elements' face nodes), keep a compact copy of them (masks of the
+                                 nonzero rows and columns and the dense rectangle they span, diagonal
+                                 blocks whole) and let the cycle's sweeps and residuals read that;
+                                 used when the rectangles hold at most half a block.  Only exact
+                                 zeros are left out: results are bit-identical to faces = 0 for
+                                 finite vectors.  Block form only. */
 } nair_params;
 
 typedef struct {
@@ -117,6 +125,11 @@ typedef struct {
     int32_t dense_n;          /* one system solved directly on this level: order of its dense operator */
     const double *dense_inv;  /* dense inverses of the systems solved directly on this level, row-major,
                                  each at its offset from nair_get_systems ([dense_n][dense_n] for one) */
+    int32_t face_rmax, face_cmax;  /* face-compressed copy (nair_params.faces), else 0 and NULL: */
+    const uint64_t *face_meta;     /* [nnzb] nonzero rows (bits 0..31), columns (bits 32..63); 0 on
+                                      diagonal blocks */
+    const double *face_vals;       /* [nnzb][rmax][cmax] entries on those rows x columns, ascending */
+    const double *face_dvals;      /* [nb][bs][bs] diagonal blocks */
 } nair_level_view;
 
 /* Fill *p with the defaults (degree 1, theta 0.25, phi 0.025, drop 1e-3, F

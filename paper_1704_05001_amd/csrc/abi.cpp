@@ -74,6 +74,7 @@ nair_status nair_default_params(nair_params *p) {
     p->form = 0;
     p->cycle = 0;
     p->gmres = 0;
+    p->faces = 1;
     return NAIR_OK;
 }
 
@@ -96,6 +97,7 @@ static nair_status setup_common(int32_t nsys, const int32_t *sys_nb, int32_t nb,
     if (p->precision != 0 && p->precision != 1) return bad(nullptr, "precision must be 0 (FP64) or 1 (FP32 hierarchy)");
     if (p->form != 0 && p->form != 1) return bad(nullptr, "form must be 0 (block) or 1 (scalar after scaling)");
     if (p->cycle != 0 && p->cycle != 1) return bad(nullptr, "cycle must be 0 (V) or 1 (F)");
+    if (p->faces != 0 && p->faces != 1) return bad(nullptr, "faces must be 0 or 1");
     if (p->gmres < 0 || p->gmres > nair::kMaxGmres)
         return bad(nullptr, "gmres must be 0 (stationary iteration) or a restart length in [1, 200]");
     if (p->max_levels < 1 || p->max_levels > nair::kMaxLevels) return bad(nullptr, "max_levels must be in [1, 64]");
@@ -305,6 +307,13 @@ nair_status nair_get_level(nair_hier h, int32_t lvl, nair_level_view *v) {
     }
     v->dense_n = L.dense_n;
     v->dense_inv = L.dense_inv.get();
+    if (L.face.on) {
+        v->face_rmax = L.face.rmax;
+        v->face_cmax = L.face.cmax;
+        v->face_meta = L.face.meta.get();
+        v->face_vals = L.face.vals.get();
+        v->face_dvals = L.face.dvals.get();
+    }
     return NAIR_OK;
 }
 

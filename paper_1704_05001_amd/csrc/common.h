@@ -182,9 +182,38 @@ int dense_inverse_segments(const DevBSR &A, int nseg, const int *blk0_h, const i
 void bsr_transpose(const DevBSR &A, DevBSR &AT, hipStream_t s);   // blocks transposed too
 void pmap_transpose(const int *pmap, int nb, int nc, DBuf<int> &ptptr, DBuf<int> &ptidx, hipStream_t s);
 
+// ------------------------------------------------------------ face copy
+// Compact copy of a BSR matrix whose off-diagonal blocks are nonzero only on a
+// few rows and columns (upwind DG: the rows and columns of the two elements'
+// nodes on the shared face).  Per block t, meta[t] holds the nonzero rows
+// (bits 0..31) and nonzero columns (bits 32..63); its rmax x cmax rectangle
+// vals[t * rc + p * cmax + q] holds the entry of its p-th nonzero row and q-th
+// nonzero column (zero past its own counts).  Diagonal blocks (meta 0) are
+// kept whole in dvals [nb][bs][bs].  vals32 / dvals32: the same in float.
+struct FaceCopy {
+    bool on = false;
+    int rmax = 0, cmax = 0, rc = 0;
+    DBuf<uint64_t> meta;
+    DBuf<double> vals, dvals;
+    DBuf<float> vals32, dvals32;
+};
+// Build F for A when its off-diagonal blocks' nonzero rectangles hold at most
+// half a block (F.on stays false otherwise).  Synchronises the stream once.
+void build_face(const DevBSR &A, FaceCopy &F, hipStream_t s);
+void face_to_float(const DevBSR &A, FaceCopy &F, hipStream_t s);
+
+// What the face-compressed kernels read (meta == nullptr: the plain BSR values).
+template <typename MT>
+struct FaceView {
+    const uint64_t *meta = nullptr;
+    const MT *vals = nullptr;
+    const MT *dvals = nullptr;
+    int cmax = 0, rc = 0;
+};
+
 // ------------------------------------------------------------------ cycle
 // Read-only view of a BSR matrix with values of type MT (double, or float for
-// the FP32-stored hierarchy).
+// the FP32-stored hierarchy), optionally with its face-compressed copy.
 template <typename MT>
 struct MatView {
     int nb = 0, ncols = 0, bs = 0;
@@ -192,6 +221,7 @@ struct MatView {
     const int *rowptr = nullptr, *colidx = nullptr;
     const MT *vals = nullptr;
     int groups = 0;   // lane groups per block row for the kernel reading it (0: from the row length)
+    FaceView<MT> face{};
     MatView with_groups(int g) const {
         MatView v = *this;
         v.groups = g;

@@ -73,6 +73,57 @@ __device__ inline double row_part(const int *__restrict__ colidx, const MT *__re
     return row_part_src<BS, MT, VT>(colidx, vals, lo, hi, g, G, a, bs_rt, PlainSrc<VT>{x, Bs<BS>::get(bs_rt)});
 }
 
+// The same row product over a face-compressed copy: the diagonal block whole
+// (from dvals), an off-diagonal block only when row a is one of its nonzero
+// rows, and then only over its nonzero columns.  The entries left out are
+// exact zeros and every product kept goes to the accumulator row_part gives
+// it (column parity), in the same order, so for finite x the result equals
+// row_part's bit for bit.
+template <int BS, typename MT, typename VT>
+__device__ inline double row_part_face(const int *__restrict__ colidx, const FaceView<MT> &F, int lo, int hi, int g,
+                                       int G, int a, int I, int bs_rt, const VT *__restrict__ x) {
+    const int bs = Bs<BS>::get(bs_rt);
+    const int64_t bb = static_cast<int64_t>(bs) * bs;
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int t = lo + g; t < hi; t += G) {
+        const int J = colidx[t];
+        const VT *xj = x + static_cast<int64_t>(J) * bs;
+        if (J == I) {
+            const MT *blk = F.dvals + static_cast<int64_t>(I) * bb + a * bs;
+            if constexpr (BS > 0) {
+#pragma unroll
+                for (int c = 0; c < BS; c += 2) {
+                    acc0 += static_cast<double>(blk[c]) * static_cast<double>(xj[c]);
+                    if (c + 1 < BS) acc1 += static_cast<double>(blk[c + 1]) * static_cast<double>(xj[c + 1]);
+                }
+            } else {
+                for (int c = 0; c < bs; ++c) acc0 += static_cast<double>(blk[c]) * static_cast<double>(xj[c]);
+            }
+            continue;
+        }
+        const uint64_t m = F.meta[t];
+        const uint32_t rm = static_cast<uint32_t>(m);
+        if (((rm >> a) & 1u) == 0u) continue;
+        const uint32_t cm = static_cast<uint32_t>(m >> 32);
+        const MT *row = F.vals + static_cast<int64_t>(t) * F.rc + __popc(rm & ((1u << a) - 1u)) * F.cmax;
+        int q = 0;
+        for (uint32_t mm = cm; mm != 0u; mm &= mm - 1u, ++q) {
+            const int c = __ffs(static_cast<int>(mm)) - 1;
+            if (BS > 0 && (c & 1)) acc1 += static_cast<double>(row[q]) * static_cast<double>(xj[c]);
+            else acc0 += static_cast<double>(row[q]) * static_cast<double>(xj[c]);
+        }
+    }
+    return acc0 + acc1;
+}
+
+template <int BS, bool FACE, typename MT, typename VT>
+__device__ inline double row_product(const int *__restrict__ colidx, const MT *__restrict__ vals,
+                                     const FaceView<MT> &F, int lo, int hi, int g, int G, int a, int I, int bs_rt,
+                                     const VT *__restrict__ x) {
+    if constexpr (FACE) return row_part_face<BS, MT, VT>(colidx, F, lo, hi, g, G, a, I, bs_rt, x);
+    else return row_part<BS, MT, VT>(colidx, vals, lo, hi, g, G, a, bs_rt, x);
+}
+
 // D_I^{-1} t (TRANS: D_I^{-T} t) for scalar row a, with t in LDS.
 template <int BS, bool TRANS>
 __device__ inline double apply_dinv(const double *__restrict__ D, const double *t, int a, int bs) {
@@ -132,17 +183,19 @@ __device__ inline double block_reduce_sum(double v, double *lds) {
 }
 
 // r = b - A x (b == nullptr: r = A x); r_lo (if given) receives r rounded to float.
-template <int BS, typename MT, typename VT>
+template <int BS, typename MT, typename VT, bool FACE = false>
 __global__ __launch_bounds__(kThreads) void k_residual(const int *__restrict__ rowptr, const int *__restrict__ colidx,
                                                       const MT *__restrict__ vals, int nb, int bs_rt, int G,
                                                       const VT *__restrict__ b, const VT *__restrict__ x,
-                                                      VT *__restrict__ r, float *__restrict__ r_lo, Gate gate) {
+                                                      VT *__restrict__ r, float *__restrict__ r_lo, Gate gate,
+                                                      FaceView<MT> face) {
     __shared__ double part[kThreads];
     const int bs = Bs<BS>::get(bs_rt);
     const Lane L = lane_of(G, bs);
     const int I = blockIdx.x * (kThreads / (G * bs)) + L.lr;
     const bool act = L.valid && I < nb && live(gate, I);
-    double acc = act ? row_part<BS>(colidx, vals, rowptr[I], rowptr[I + 1], L.g, G, L.a, bs, x) : 0.0;
+    double acc = act ? row_product<BS, FACE>(colidx, vals, face, rowptr[I], rowptr[I + 1], L.g, G, L.a, I, bs, x)
+                     : 0.0;
     acc = reduce_groups(acc, L, G, bs, part);
     if (act && L.g == 0) {
         const int64_t o = static_cast<int64_t>(I) * bs + L.a;
@@ -155,12 +208,12 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int *__restrict__ r
 // One Jacobi sweep over the listed rows (list == nullptr: rows with cf == only_cf;
 // the other rows copy e_in): e_out_I = e_in_I + D_I^{-1} (r_I - (A e_in)_I), or
 // with D_I^{-T} (TRANS: the sweeps of the transposed cycle, with A^T's rows).
-template <int BS, typename MT, typename VT, bool TRANS>
+template <int BS, typename MT, typename VT, bool TRANS, bool FACE>
 __device__ inline void relax_rows(const int *__restrict__ rowptr, const int *__restrict__ colidx,
                                   const MT *__restrict__ vals, const double *__restrict__ dinv, int nb, int bs_rt,
                                   int G, const VT *__restrict__ r, const VT *__restrict__ ein, VT *__restrict__ eout,
                                   const int *__restrict__ list, int nlist, const int8_t *__restrict__ cf, int only_cf,
-                                  Gate gate) {
+                                  Gate gate, const FaceView<MT> &face) {
     __shared__ double part[kThreads];
     __shared__ double tb[kThreads];
     const int bs = Bs<BS>::get(bs_rt);
@@ -171,7 +224,8 @@ __device__ inline void relax_rows(const int *__restrict__ rowptr, const int *__r
     if (L.valid && idx < N) I = list ? list[idx] : idx;
     if (I >= 0 && !live(gate, I)) I = -1;   // a stopped system: nothing to do
     const bool upd = I >= 0 && (list != nullptr || cf[I] == only_cf);
-    double acc = upd ? row_part<BS>(colidx, vals, rowptr[I], rowptr[I + 1], L.g, G, L.a, bs, ein) : 0.0;
+    double acc =
+        upd ? row_product<BS, FACE>(colidx, vals, face, rowptr[I], rowptr[I + 1], L.g, G, L.a, I, bs, ein) : 0.0;
     acc = reduce_groups(acc, L, G, bs, part);
     const int64_t o = static_cast<int64_t>(I) * bs + L.a;
     if (upd && L.g == 0) tb[L.lr * bs + L.a] = static_cast<double>(r[o]) - acc;
@@ -214,26 +268,28 @@ __global__ __launch_bounds__(kThreads) void k_relax_T_first(const double *__rest
     }
 }
 
-template <int BS, typename MT, typename VT>
+template <int BS, typename MT, typename VT, bool FACE = false>
 __global__ __launch_bounds__(kThreads) void k_relax(const int *__restrict__ rowptr, const int *__restrict__ colidx,
                                                    const MT *__restrict__ vals, const double *__restrict__ dinv,
                                                    int nb, int bs_rt, int G, const VT *__restrict__ r,
                                                    const VT *__restrict__ ein, VT *__restrict__ eout,
                                                    const int *__restrict__ list, int nlist,
-                                                   const int8_t *__restrict__ cf, int only_cf, Gate gate) {
-    relax_rows<BS, MT, VT, false>(rowptr, colidx, vals, dinv, nb, bs_rt, G, r, ein, eout, list, nlist, cf, only_cf,
-                                  gate);
+                                                   const int8_t *__restrict__ cf, int only_cf, Gate gate,
+                                                   FaceView<MT> face) {
+    relax_rows<BS, MT, VT, false, FACE>(rowptr, colidx, vals, dinv, nb, bs_rt, G, r, ein, eout, list, nlist, cf,
+                                        only_cf, gate, face);
 }
 
-template <int BS, typename MT, typename VT>
+template <int BS, typename MT, typename VT, bool FACE = false>
 __global__ __launch_bounds__(kThreads) void k_relax_T(const int *__restrict__ rowptr, const int *__restrict__ colidx,
                                                      const MT *__restrict__ vals, const double *__restrict__ dinv,
                                                      int nb, int bs_rt, int G, const VT *__restrict__ r,
                                                      const VT *__restrict__ ein, VT *__restrict__ eout,
                                                      const int *__restrict__ list, int nlist,
-                                                     const int8_t *__restrict__ cf, int only_cf, Gate gate) {
-    relax_rows<BS, MT, VT, true>(rowptr, colidx, vals, dinv, nb, bs_rt, G, r, ein, eout, list, nlist, cf, only_cf,
-                                 gate);
+                                                     const int8_t *__restrict__ cf, int only_cf, Gate gate,
+                                                     FaceView<MT> face) {
+    relax_rows<BS, MT, VT, true, FACE>(rowptr, colidx, vals, dinv, nb, bs_rt, G, r, ein, eout, list, nlist, cf,
+                                       only_cf, gate, face);
 }
 
 // rc_i = r_{cpts[i]} + sum_t Z_it r_{col t}
@@ -491,6 +547,8 @@ template <typename MT>
 void need(const MatView<MT> &A, const char *what) {
     if (A.nb > 0 && (!A.rowptr || !A.colidx || !A.vals))
         fail(NAIR_EDEVICE, std::string(what) + ": the level holds no such operator");
+    if (A.face.meta && (!A.face.vals || !A.face.dvals || A.bs > 32))
+        fail(NAIR_EDEVICE, std::string(what) + ": incomplete face-compressed copy");
 }
 
 }  // namespace
@@ -508,6 +566,16 @@ void need(const MatView<MT> &A, const char *what) {
         default: KERNEL<0, MT, VT> __VA_ARGS__; break;       \
     }
 
+// Face-compressed instances: the block sizes of Q1..Q4 elements, others at run time.
+#define NAIR_FACE_DISPATCH(bs, KERNEL, ...)                    \
+    switch (bs) {                                              \
+        case 4: KERNEL<4, MT, VT, true> __VA_ARGS__; break;    \
+        case 9: KERNEL<9, MT, VT, true> __VA_ARGS__; break;    \
+        case 16: KERNEL<16, MT, VT, true> __VA_ARGS__; break;  \
+        case 25: KERNEL<25, MT, VT, true> __VA_ARGS__; break;  \
+        default: KERNEL<0, MT, VT, true> __VA_ARGS__; break;   \
+    }
+
 int max_groups(int bs) {
     int G = 1;
     while (2 * G * bs <= kThreads && G < 32) G *= 2;
@@ -520,8 +588,12 @@ void launch_residual(const MatView<MT> &A, const VT *b, const VT *x, VT *r, floa
     need(A, "launch_residual");
     const int G = groups_for(A);
     const unsigned grid = grid_rows(A.nb, G, A.bs);
-    NAIR_BS_DISPATCH(A.bs, k_residual, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, A.nb, A.bs, G, b, x, r,
-                                                                  r_lo, gate));
+    if (A.face.meta)
+        NAIR_FACE_DISPATCH(A.bs, k_residual, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, A.nb, A.bs, G, b,
+                                                                        x, r, r_lo, gate, A.face))
+    else
+        NAIR_BS_DISPATCH(A.bs, k_residual, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, A.nb, A.bs, G, b, x,
+                                                                      r, r_lo, gate, A.face))
     NAIR_HIP(hipGetLastError());
 }
 
@@ -533,12 +605,22 @@ void launch_relax(const MatView<MT> &A, const double *dinv, bool dinv_trans, con
     if (N <= 0) return;
     const int G = groups_for(A);
     const unsigned grid = grid_rows(N, G, A.bs);
-    if (dinv_trans) {
+    if (dinv_trans && A.face.meta) {
+        NAIR_FACE_DISPATCH(A.bs, k_relax_T, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, dinv, A.nb, A.bs,
+                                                                       G, r, ein, eout, list, nlist, cf, only_cf,
+                                                                       gate, A.face));
+    } else if (dinv_trans) {
         NAIR_BS_DISPATCH(A.bs, k_relax_T, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, dinv, A.nb, A.bs, G,
-                                                                     r, ein, eout, list, nlist, cf, only_cf, gate));
+                                                                     r, ein, eout, list, nlist, cf, only_cf, gate,
+                                                                     A.face));
+    } else if (A.face.meta) {
+        NAIR_FACE_DISPATCH(A.bs, k_relax, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, dinv, A.nb, A.bs, G,
+                                                                     r, ein, eout, list, nlist, cf, only_cf, gate,
+                                                                     A.face));
     } else {
         NAIR_BS_DISPATCH(A.bs, k_relax, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, dinv, A.nb, A.bs, G,
-                                                                   r, ein, eout, list, nlist, cf, only_cf, gate));
+                                                                   r, ein, eout, list, nlist, cf, only_cf, gate,
+                                                                   A.face));
     }
     NAIR_HIP(hipGetLastError());
 }

@@ -59,7 +59,24 @@ struct Level {
     // F-cycle: the first coarse correction while the second is computed
     DBuf<double> fsave;
     DBuf<float> fsave32;
+    // face-compressed copies of A and A^T (level 0 of a block hierarchy)
+    FaceCopy face, faceT;
 };
+
+// A_l (trans: A_l^T) as the cycle kernels read it: with its face-compressed
+// copy where the level has one.
+inline MatView<double> op_view(const Level &L, bool trans) {
+    MatView<double> v = view(trans ? L.AT : L.A);
+    const FaceCopy &F = trans ? L.faceT : L.face;
+    if (F.on) v.face = FaceView<double>{F.meta.get(), F.vals.get(), F.dvals.get(), F.cmax, F.rc};
+    return v;
+}
+inline MatView<float> op_view32(const Level &L, bool trans) {
+    MatView<float> v = view(trans ? L.AT : L.A, trans ? L.at32.get() : L.vals32.get());
+    const FaceCopy &F = trans ? L.faceT : L.face;
+    if (F.on) v.face = FaceView<float>{F.meta.get(), F.vals32.get(), F.dvals32.get(), F.cmax, F.rc};
+    return v;
+}
 
 // Per-system solve state of the batched iteration (device-side convergence).
 struct BatchSolve {

@@ -48,7 +48,7 @@ nair_status run_gmres(Hier &h, bool trans, const double *b, double *x, double rt
     // A (or A^T) of the system being solved: the caller's blocks in the scalar form
     MatView<double> Aop;
     if (h.prm.form == 1) Aop = trans ? view(h.A0T) : view(h.A0);
-    else Aop = trans ? view(L0.AT).with_groups(L0.tune[TU_RESIDUAL_T]) : view(L0.A).with_groups(L0.tune[TU_RESIDUAL]);
+    else Aop = op_view(L0, trans).with_groups(L0.tune[trans ? TU_RESIDUAL_T : TU_RESIDUAL]);
 
     double *V = K.V.get(), *Z = K.Z.get(), *w = K.w.get(), *hd = K.hd.get();
     auto vec = [n](double *base, int j) { return base + static_cast<int64_t>(j) * n; };

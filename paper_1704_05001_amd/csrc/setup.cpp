@@ -382,6 +382,8 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         next->mode.assign(nsys, 0);
         h.lv.push_back(std::move(next));
     }
+    // the finest operator is read by every cycle: a compact copy of its face blocks
+    if (p.faces == 1 && p.form == 0) build_face(h.lv[0]->A, h.lv[0]->face, s);
     if (p.precision == 1) make_fp32_copies(h, s);
     NAIR_HIP(hipStreamSynchronize(s));
 }
@@ -417,6 +419,8 @@ void make_fp32_copies(Hier &h, hipStream_t s) {
                 launch_to_float(L.ZT.vals.get(), L.zt32.get(), L.ZT.nnzb * bb, s);
             }
         }
+        face_to_float(L.A, L.face, s);
+        if (L.have_T) face_to_float(L.AT, L.faceT, s);
     }
 }
 
@@ -429,6 +433,7 @@ void ensure_transposes(Hier &h, hipStream_t s) {
         Level &L = *Lp;
         if (L.have_T) continue;
         bsr_transpose(L.A, L.AT, s);
+        if (L.face.on) build_face(L.AT, L.faceT, s);   // A^T's blocks have the transposed faces
         if (!L.coarsest) {
             bsr_transpose(L.Z, L.ZT, s);
             pmap_transpose(L.pmap.get(), L.A.nb, L.nc, L.ptptr, L.ptidx, s);

@@ -23,9 +23,9 @@ struct Store;
 
 template <>
 struct Store<double> {
-    static MatView<double> A(const Level &L) { return view(L.A).with_groups(L.tune[TU_RELAX]); }
+    static MatView<double> A(const Level &L) { return op_view(L, false).with_groups(L.tune[TU_RELAX]); }
     static MatView<double> Z(const Level &L) { return view(L.Z).with_groups(L.tune[TU_RESTRICT]); }
-    static MatView<double> AT(const Level &L) { return view(L.AT).with_groups(L.tune[TU_RELAX_T]); }
+    static MatView<double> AT(const Level &L) { return op_view(L, true).with_groups(L.tune[TU_RELAX_T]); }
     static MatView<double> ZT(const Level &L) { return view(L.ZT).with_groups(L.tune[TU_INTERP_T]); }
     static double *r(Level &L) { return L.r.get(); }
     static double *e0(Level &L) { return L.e0.get(); }
@@ -36,9 +36,9 @@ struct Store<double> {
 
 template <>
 struct Store<float> {
-    static MatView<float> A(const Level &L) { return view(L.A, L.vals32.get()).with_groups(L.tune[TU_RELAX]); }
+    static MatView<float> A(const Level &L) { return op_view32(L, false).with_groups(L.tune[TU_RELAX]); }
     static MatView<float> Z(const Level &L) { return view(L.Z, L.z32.get()).with_groups(L.tune[TU_RESTRICT]); }
-    static MatView<float> AT(const Level &L) { return view(L.AT, L.at32.get()).with_groups(L.tune[TU_RELAX_T]); }
+    static MatView<float> AT(const Level &L) { return op_view32(L, true).with_groups(L.tune[TU_RELAX_T]); }
     static MatView<float> ZT(const Level &L) { return view(L.ZT, L.zt32.get()).with_groups(L.tune[TU_INTERP_T]); }
     static float *r(Level &L) { return L.r32.get(); }
     static float *e0(Level &L) { return L.e0_32.get(); }
@@ -290,8 +290,7 @@ void batch_iteration(Hier &h, bool trans, const double *b, double *x, hipStream_
                                             h.A0.nb, h.bs0, false, s, g0);
     } else {
         launch_axpy_active<T>(x, e, n, h.bs, L0.bsys.get(), B.active.get(), s);
-        const MatView<double> Aop = trans ? view(L0.AT).with_groups(L0.tune[TU_RESIDUAL_T])
-                                          : view(L0.A).with_groups(L0.tune[TU_RESIDUAL]);
+        const MatView<double> Aop = op_view(L0, trans).with_groups(L0.tune[trans ? TU_RESIDUAL_T : TU_RESIDUAL]);
         {
             TimerScope ts(TK_RESIDUAL, 0, s);
             launch_residual<double, double>(Aop, b, x, L0.r.get(), fp32 ? L0.r32.get() : nullptr, s,

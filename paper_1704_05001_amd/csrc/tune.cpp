@@ -61,9 +61,9 @@ template <typename T>
 struct Vecs;
 template <>
 struct Vecs<double> {
-    static MatView<double> A(const Level &L) { return view(L.A); }
+    static MatView<double> A(const Level &L) { return op_view(L, false); }
     static MatView<double> Z(const Level &L) { return view(L.Z); }
-    static MatView<double> AT(const Level &L) { return view(L.AT); }
+    static MatView<double> AT(const Level &L) { return op_view(L, true); }
     static MatView<double> ZT(const Level &L) { return view(L.ZT); }
     static double *r(Level &L) { return L.r.get(); }
     static double *e0(Level &L) { return L.e0.get(); }
@@ -72,9 +72,9 @@ struct Vecs<double> {
 };
 template <>
 struct Vecs<float> {
-    static MatView<float> A(const Level &L) { return view(L.A, L.vals32.get()); }
+    static MatView<float> A(const Level &L) { return op_view32(L, false); }
     static MatView<float> Z(const Level &L) { return view(L.Z, L.z32.get()); }
-    static MatView<float> AT(const Level &L) { return view(L.AT, L.at32.get()); }
+    static MatView<float> AT(const Level &L) { return op_view32(L, true); }
     static MatView<float> ZT(const Level &L) { return view(L.ZT, L.zt32.get()); }
     static float *r(Level &L) { return L.r32.get(); }
     static float *e0(Level &L) { return L.e0_32.get(); }
@@ -130,7 +130,7 @@ void tune_levels(Hier &h, int reps, hipStream_t s) {
         clear_vectors<double>(L0, s);
         L0.tune[TU_RESIDUAL] = pick(
             [&](int G) {
-                launch_residual<double, double>(view(L0.A).with_groups(G), L0.r.get(), L0.e0.get(), L0.tmp.get(),
+                launch_residual<double, double>(op_view(L0, false).with_groups(G), L0.r.get(), L0.e0.get(), L0.tmp.get(),
                                                 nullptr, s);
             },
             L0.A.bs, reps, ev, s);

@@ -44,7 +44,7 @@ class _Params(C.Structure):
                 ("drop", C.c_double), ("relax", C.c_int32), ("max_levels", C.c_int32),
                 ("max_coarse_dofs", C.c_int32), ("seed", C.c_uint64),
                 ("cf_override_host", C.c_void_p), ("precision", C.c_int32), ("tuning", C.c_void_p),
-                ("form", C.c_int32), ("cycle", C.c_int32), ("gmres", C.c_int32)]
+                ("form", C.c_int32), ("cycle", C.c_int32), ("gmres", C.c_int32), ("faces", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -60,7 +60,8 @@ class _LevelView(C.Structure):
                 ("pmap", C.c_void_p), ("dround", C.c_void_p), ("nc", C.c_int32),
                 ("pmis_rounds", C.c_int32), ("z_nnzb", C.c_int32), ("z_rowptr", C.c_void_p),
                 ("z_colidx", C.c_void_p), ("z_vals", C.c_void_p), ("dense_n", C.c_int32),
-                ("dense_inv", C.c_void_p)]
+                ("dense_inv", C.c_void_p), ("face_rmax", C.c_int32), ("face_cmax", C.c_int32),
+                ("face_meta", C.c_void_p), ("face_vals", C.c_void_p), ("face_dvals", C.c_void_p)]
 
 
 _lib = None
@@ -161,6 +162,7 @@ class Params:
     form: str = "block"          # "block" or "scalar" (scalar nAIR of D^{-1} A, D the block diagonal)
     cycle: str = "V"             # "V" or "F"
     gmres: int = 0               # 0: stationary iteration; m > 0: GMRES(m) preconditioned by the cycle
+    faces: bool = True           # compact copy of the finest operator's face blocks for the cycle
 
 
 @dataclass
@@ -206,6 +208,7 @@ class Hierarchy:
             raise ValueError("cycle must be 'V' or 'F'")
         p.cycle = 1 if params.cycle == "F" else 0
         p.gmres = int(params.gmres)
+        p.faces = 1 if params.faces else 0
         cf = None
         if params.cf_override is not None:
             cf = np.ascontiguousarray(params.cf_override, dtype=np.int8)
@@ -389,7 +392,8 @@ class Hierarchy:
         nb, bs, nnzb = v.nb, v.bs, v.nnzb
         bb = bs * bs
         want = (lambda k: True) if fields is None else (lambda k: k in fields)
-        out = dict(nb=nb, bs=bs, nnzb=nnzb, coarsest=bool(v.coarsest), nc=v.nc, pmis_rounds=v.pmis_rounds)
+        out = dict(nb=nb, bs=bs, nnzb=nnzb, coarsest=bool(v.coarsest), nc=v.nc, pmis_rounds=v.pmis_rounds,
+                   face_rmax=v.face_rmax, face_cmax=v.face_cmax)
         spec = [("rowptr", v.rowptr, torch.int32, nb + 1, None),
                 ("colidx", v.colidx, torch.int32, nnzb, None),
                 ("vals", v.vals, torch.float64, nnzb * bb, (nnzb, bs, bs))]
@@ -414,6 +418,12 @@ class Hierarchy:
             d = [(int(o), int(sy["seg"][k + 1] - sy["seg"][k]) * bs) for k, o in enumerate(sy["dense_off"]) if o >= 0]
             total = max(o + m * m for o, m in d)
             spec += [("dense_inv", v.dense_inv, torch.float64, total, None)]
+        if v.face_meta:   # meta as int64 bit patterns: rows in bits 0..31, columns in 32..63
+            rc = v.face_rmax * v.face_cmax
+            spec += [("face_meta", v.face_meta, torch.int64, nnzb, None),
+                     ("face_vals", v.face_vals, torch.float64, nnzb * max(rc, 1),
+                      (nnzb, v.face_rmax, v.face_cmax) if rc > 0 else None),
+                     ("face_dvals", v.face_dvals, torch.float64, nb * bb, (nb, bs, bs))]
         for name, ptr, dt, cnt, shape in spec:
             if want(name):
                 t = _dcopy(ptr, dt, cnt, dev)
