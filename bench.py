@@ -67,8 +67,8 @@ def relax_level_bytes(lv: dict) -> dict:
     """Algorithmic HBM bytes of one F-relaxation sweep on a level: each operand
     read once, each output written once (int32 indices, FP64 values).  With a
     face-compressed copy the sweep reads a diagonal block whole and, of an
-    off-diagonal block, its 8-byte row/column masks and the entries on its
-    nonzero rows and columns."""
+    off-diagonal block, the entries on its nonzero rows and columns; every
+    block's 8-byte row/column masks."""
     import numpy as np
     rp = lv["rowptr"].cpu().numpy().astype(np.int64)
     cf = lv["cf"].cpu().numpy()
@@ -86,7 +86,8 @@ def relax_level_bytes(lv: dict) -> dict:
         meta = lv["face_meta"].cpu().numpy().view(np.uint64)
         nr = np.bitwise_count(meta & np.uint64(0xFFFFFFFF)).astype(np.int64)
         nc = np.bitwise_count(meta >> np.uint64(32)).astype(np.int64)
-        bytes_A = int((inF & diag).sum()) * (bb * 8 + 4) + int((12 + 8 * nr * nc)[inF & ~diag].sum())
+        # (the sweep loads every block's masks, the diagonal's too)
+        bytes_A = int((inF & diag).sum()) * (bb * 8 + 12) + int((12 + 8 * nr * nc)[inF & ~diag].sum())
     else:
         bytes_A = nnzF * (bb * 8 + 4)      # F rows of A (values + column indices)
     bytes_D = nF * bb * 8                  # D_F^{-1}

@@ -85,8 +85,19 @@ __device__ inline double row_part_face(const int *__restrict__ colidx, const Fac
     const int bs = Bs<BS>::get(bs_rt);
     const int64_t bb = static_cast<int64_t>(bs) * bs;
     double acc0 = 0.0, acc1 = 0.0;
-    for (int t = lo + g; t < hi; t += G) {
-        const int J = colidx[t];
+    int t = lo + g;
+    if (t >= hi) return acc0 + acc1;
+    // the next block's column and masks load while this block's values and x do
+    int J = colidx[t];
+    uint64_t m = F.meta[t];
+    for (;; t += G) {
+        const int tn = t + G;
+        int Jn = 0;
+        uint64_t mn = 0;
+        if (tn < hi) {
+            Jn = colidx[tn];
+            mn = F.meta[tn];
+        }
         const VT *xj = x + static_cast<int64_t>(J) * bs;
         if (J == I) {
             const MT *blk = F.dvals + static_cast<int64_t>(I) * bb + a * bs;
@@ -99,19 +110,22 @@ __device__ inline double row_part_face(const int *__restrict__ colidx, const Fac
             } else {
                 for (int c = 0; c < bs; ++c) acc0 += static_cast<double>(blk[c]) * static_cast<double>(xj[c]);
             }
-            continue;
+        } else {
+            const uint32_t rm = static_cast<uint32_t>(m);
+            if ((rm >> a) & 1u) {
+                const uint32_t cm = static_cast<uint32_t>(m >> 32);
+                const MT *row = F.vals + static_cast<int64_t>(t) * F.rc + __popc(rm & ((1u << a) - 1u)) * F.cmax;
+                int q = 0;
+                for (uint32_t mm = cm; mm != 0u; mm &= mm - 1u, ++q) {
+                    const int c = __ffs(static_cast<int>(mm)) - 1;
+                    if (BS > 0 && (c & 1)) acc1 += static_cast<double>(row[q]) * static_cast<double>(xj[c]);
+                    else acc0 += static_cast<double>(row[q]) * static_cast<double>(xj[c]);
+                }
+            }
         }
-        const uint64_t m = F.meta[t];
-        const uint32_t rm = static_cast<uint32_t>(m);
-        if (((rm >> a) & 1u) == 0u) continue;
-        const uint32_t cm = static_cast<uint32_t>(m >> 32);
-        const MT *row = F.vals + static_cast<int64_t>(t) * F.rc + __popc(rm & ((1u << a) - 1u)) * F.cmax;
-        int q = 0;
-        for (uint32_t mm = cm; mm != 0u; mm &= mm - 1u, ++q) {
-            const int c = __ffs(static_cast<int>(mm)) - 1;
-            if (BS > 0 && (c & 1)) acc1 += static_cast<double>(row[q]) * static_cast<double>(xj[c]);
-            else acc0 += static_cast<double>(row[q]) * static_cast<double>(xj[c]);
-        }
+        if (tn >= hi) break;
+        J = Jn;
+        m = mn;
     }
     return acc0 + acc1;
 }
@@ -224,18 +238,47 @@ __device__ inline void relax_rows(const int *__restrict__ rowptr, const int *__r
     if (L.valid && idx < N) I = list ? list[idx] : idx;
     if (I >= 0 && !live(gate, I)) I = -1;   // a stopped system: nothing to do
     const bool upd = I >= 0 && (list != nullptr || cf[I] == only_cf);
+    // loads that do not depend on the row product go out first: this lane's
+    // row of D_I^{-1} (column for D^{-T}; small blocks only, in registers),
+    // r and e_in
+    constexpr bool kPre = BS > 0 && BS <= 16;
+    double dreg[kPre ? BS : 1];
+    const int64_t o = static_cast<int64_t>(I) * bs + L.a;
+    double rv = 0.0, ev = 0.0;
+    if (I >= 0 && L.g == 0) {
+        ev = static_cast<double>(ein[o]);
+        if (upd) {
+            rv = static_cast<double>(r[o]);
+            if constexpr (kPre) {
+                const double *D = dinv + static_cast<int64_t>(I) * bs * bs;
+#pragma unroll
+                for (int c = 0; c < BS; ++c) dreg[c] = TRANS ? D[c * BS + L.a] : D[L.a * BS + c];
+            }
+        }
+    }
     double acc =
         upd ? row_product<BS, FACE>(colidx, vals, face, rowptr[I], rowptr[I + 1], L.g, G, L.a, I, bs, ein) : 0.0;
     acc = reduce_groups(acc, L, G, bs, part);
-    const int64_t o = static_cast<int64_t>(I) * bs + L.a;
-    if (upd && L.g == 0) tb[L.lr * bs + L.a] = static_cast<double>(r[o]) - acc;
+    if (upd && L.g == 0) tb[L.lr * bs + L.a] = rv - acc;
     __syncthreads();
     if (I >= 0 && L.g == 0) {
         if (upd) {
-            const double d = apply_dinv<BS, TRANS>(dinv + static_cast<int64_t>(I) * bs * bs, tb + L.lr * bs, L.a, bs);
-            eout[o] = static_cast<VT>(static_cast<double>(ein[o]) + d);
+            double d;
+            if constexpr (kPre) {   // apply_dinv's sums, from the registers
+                const double *tt = tb + L.lr * bs;
+                double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+                for (int c = 0; c < BS; c += 2) {
+                    d0 += dreg[c] * tt[c];
+                    if (c + 1 < BS) d1 += dreg[c + 1] * tt[c + 1];
+                }
+                d = d0 + d1;
+            } else {
+                d = apply_dinv<BS, TRANS>(dinv + static_cast<int64_t>(I) * bs * bs, tb + L.lr * bs, L.a, bs);
+            }
+            eout[o] = static_cast<VT>(ev + d);
         } else {
-            eout[o] = ein[o];
+            eout[o] = static_cast<VT>(ev);
         }
     }
 }

@@ -20,27 +20,37 @@ __device__ inline int nth_set_bit(uint32_t m, int k) {
     return __ffs(static_cast<int>(m)) - 1;
 }
 
-// meta[t] |= (row a has a nonzero) << a | (its nonzero columns) << 32, one
-// thread per row of a block (rows of a block are contiguous in memory).
+// meta[t] = nonzero rows | nonzero columns << 32: one thread per row of a
+// block (a block's rows are contiguous in memory), the rows of a block
+// combined in LDS, one store per block.
 __global__ __launch_bounds__(256) void k_face_masks(const double *__restrict__ vals, int64_t nnzb, int bs,
                                                    unsigned long long *__restrict__ meta) {
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= nnzb * bs) return;
-    const int64_t t = g / bs;
-    const int a = static_cast<int>(g - t * bs);
-    const double *row = vals + g * bs;
-    uint32_t cm = 0u;
-    for (int c = 0; c < bs; ++c)
-        if (row[c] != 0.0) cm |= 1u << c;
-    if (cm != 0u) atomicOr(meta + t, (static_cast<unsigned long long>(cm) << 32) | (1ull << a));
+    __shared__ unsigned long long m[256];
+    const int per = 256 / bs;
+    const int lb = threadIdx.x / bs;
+    const int a = threadIdx.x - lb * bs;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * per + lb;
+    if (threadIdx.x < per) m[threadIdx.x] = 0ull;
+    __syncthreads();
+    if (lb < per && t < nnzb) {
+        const double *row = vals + (t * bs + a) * bs;
+        uint32_t cm = 0u;
+        for (int c = 0; c < bs; ++c)
+            if (row[c] != 0.0) cm |= 1u << c;
+        if (cm != 0u) atomicOr(m + lb, (static_cast<unsigned long long>(cm) << 32) | (1ull << a));
+    }
+    __syncthreads();
+    const int64_t to = static_cast<int64_t>(blockIdx.x) * per + threadIdx.x;
+    if (threadIdx.x < per && to < nnzb) meta[to] = m[threadIdx.x];
 }
 
 // Per block row: where its diagonal block sits (its meta cleared: kept whole),
 // and the largest nonzero row and column counts of its off-diagonal blocks,
-// combined per wave before one atomic each.
+// combined per workgroup before one atomic each.
 __global__ __launch_bounds__(256) void k_face_rows(const int *__restrict__ rowptr, const int *__restrict__ colidx,
                                                   int nb, unsigned long long *__restrict__ meta,
                                                   int *__restrict__ diagpos, int *__restrict__ maxrc) {
+    __shared__ int red[2][4];
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     int rmax = 0, cmax = 0;
     if (I < nb) {
@@ -61,8 +71,13 @@ __global__ __launch_bounds__(256) void k_face_rows(const int *__restrict__ rowpt
         cmax = max(cmax, __shfl_xor(cmax, o, 64));
     }
     if ((threadIdx.x & 63) == 0) {
-        atomicMax(maxrc, rmax);
-        atomicMax(maxrc + 1, cmax);
+        red[0][threadIdx.x >> 6] = rmax;
+        red[1][threadIdx.x >> 6] = cmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicMax(maxrc, max(max(red[0][0], red[0][1]), max(red[0][2], red[0][3])));
+        atomicMax(maxrc + 1, max(max(red[1][0], red[1][1]), max(red[1][2], red[1][3])));
     }
 }
 
@@ -105,11 +120,11 @@ void build_face(const DevBSR &A, FaceCopy &F, hipStream_t s) {
     const int64_t bb = static_cast<int64_t>(bs) * bs;
     DBuf<uint64_t> meta(static_cast<size_t>(A.nnzb));
     DBuf<int> diagpos(static_cast<size_t>(A.nb)), maxrc(2);
-    NAIR_HIP(hipMemsetAsync(meta.get(), 0, sizeof(uint64_t) * A.nnzb, s));
     NAIR_HIP(hipMemsetAsync(maxrc.get(), 0, sizeof(int) * 2, s));
     NAIR_HIP(hipMemsetAsync(diagpos.get(), 0, sizeof(int) * A.nb, s));   // (every validated row has its diagonal)
     auto *m64 = reinterpret_cast<unsigned long long *>(meta.get());
-    k_face_masks<<<blocks_for(A.nnzb * bs), 256, 0, s>>>(A.vals.get(), A.nnzb, bs, m64);
+    const int per = 256 / bs;
+    k_face_masks<<<static_cast<unsigned>((A.nnzb + per - 1) / per), 256, 0, s>>>(A.vals.get(), A.nnzb, bs, m64);
     NAIR_HIP(hipGetLastError());
     k_face_rows<<<blocks_for(A.nb), 256, 0, s>>>(A.rowptr.get(), A.colidx.get(), A.nb, m64, diagpos.get(),
                                                   maxrc.get());

@@ -87,53 +87,58 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(int *__restrict__ out
     }
 }
 
-// Small arrays: one 1024-thread workgroup, each thread a contiguous run of at
-// most kSmallItems values.
+// Small arrays: one 1024-thread workgroup; wave w scans its contiguous chunk
+// in strips of 64 (one coalesced load per lane and strip, a wave scan per
+// strip with a running carry), after the chunk totals are scanned in LDS.
 constexpr int kSmallThreads = 1024;
-constexpr int kSmallItems = 16;
-constexpr int kSmallMax = kSmallThreads * kSmallItems;
+constexpr int kSmallWaves = kSmallThreads / 64;
+constexpr int kSmallStrips = 16;                                  // strips of 64 per wave
+constexpr int kSmallMax = kSmallWaves * kSmallStrips * 64;
 
 __global__ __launch_bounds__(kSmallThreads) void k_scan_small(const int *__restrict__ in, int *__restrict__ out,
                                                              int n) {
-    __shared__ int wsum[kSmallThreads / 64 + 1];
-    const int per = (n + kSmallThreads - 1) / kSmallThreads;
-    const int lo = threadIdx.x * per;
-    int v[kSmallItems];
-    int s = 0;
-#pragma unroll
-    for (int k = 0; k < kSmallItems; ++k) {
-        const int i = lo + k;
-        v[k] = (k < per && i < n) ? in[i] : 0;
-        s += v[k];
-    }
+    __shared__ int wsum[kSmallWaves + 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    int x = s;
+    const int strips = (n + kSmallWaves * 64 - 1) / (kSmallWaves * 64);   // per wave, <= kSmallStrips
+    const int lo = wave * strips * 64;
+    int v[kSmallStrips];
+    int s = 0;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
+    for (int j = 0; j < kSmallStrips; ++j) {
+        const int i = lo + j * 64 + lane;
+        v[j] = (j < strips && i < n) ? in[i] : 0;
+        s += v[j];
     }
-    if (lane == 63) wsum[wave] = x;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) wsum[wave] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         int run = 0;
-        for (int w = 0; w < kSmallThreads / 64; ++w) {
+        for (int w = 0; w < kSmallWaves; ++w) {
             const int t = wsum[w];
             wsum[w] = run;
             run += t;
         }
-        wsum[kSmallThreads / 64] = run;
+        wsum[kSmallWaves] = run;
     }
     __syncthreads();
-    int pre = x - s + wsum[wave];
+    int carry = wsum[wave];
 #pragma unroll
-    for (int k = 0; k < kSmallItems; ++k) {
-        const int i = lo + k;
-        if (k < per && i < n) out[i] = pre;
-        pre += v[k];
+    for (int j = 0; j < kSmallStrips; ++j) {
+        if (j >= strips) break;
+        int x = v[j];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        const int i = lo + j * 64 + lane;
+        if (i < n) out[i] = carry + x - v[j];
+        carry += __shfl(x, 63, 64);
     }
-    if (threadIdx.x == 0) out[n] = wsum[kSmallThreads / 64];
+    if (threadIdx.x == 0) out[n] = wsum[kSmallWaves];
 }
 
 }  // namespace
