@@ -97,6 +97,42 @@ def relax_level_bytes(lv: dict) -> dict:
                 bytes_true_blocks=bytes_A + bytes_D)
 
 
+def restrict_level_bytes(lv: dict) -> int:
+    """Algorithmic HBM bytes of one restriction r_c = r_C + Z r_F on a level:
+    Z's blocks and column indices, its row pointers, the C list, r_C read and
+    r_c written, r_F gathered once."""
+    import numpy as np
+    bs = lv["bs"]
+    nc = int(lv["nc"])
+    znnz = int(lv["z_rowptr"][-1].item()) if nc > 0 else 0
+    nF = int((lv["cf"].cpu().numpy() == 0).sum())
+    return znnz * (bs * bs * 8 + 4) + (nc + 1) * 4 + nc * 4 + nc * bs * 16 + nF * bs * 8
+
+
+def level_bandwidth(P, H, b, levels: int) -> list:
+    """Per level: the forward solve's F sweep and restriction, average launch
+    time from the library's HIP-event timer over one solve each, and the
+    algorithmic GB/s."""
+    out = []
+    for l in range(levels):
+        lv = H.level(l, fields=("rowptr", "colidx", "cf", "z_rowptr"))
+        if lv["coarsest"]:
+            break
+        row = {"level": l, "nb": lv["nb"], "nnzb": lv["nnzb"]}
+        for kind, nbytes in (("relax", relax_level_bytes(H.level(l, fields=("rowptr", "colidx", "cf", "face_meta")))["bytes"]),
+                             ("restrict", restrict_level_bytes(lv))):
+            P.timer_select(kind, l)
+            H.solve(b)
+            P.timer_select(None)
+            n, ms = P.timer_read()
+            us = ms * 1e3 / max(n, 1)
+            row[f"{kind}_us"] = round(us, 2)
+            row[f"{kind}_MB"] = round(nbytes / 1e6, 2)
+            row[f"{kind}_GBs"] = round(nbytes / (us * 1e-6) / 1e9, 1) if n else None
+        out.append(row)
+    return out
+
+
 def batched_leg(args, P, torch, np):
     """Many discrete-ordinate systems in one hierarchy and one graph-replayed
     solve, FP32-stored and FP64, against the same systems set up and solved
@@ -287,6 +323,7 @@ def main(argv=None):
             info = H.info()
             lvl = H.level(args.roofline_level)
             lvl0 = H.level(0, fields=())
+            audit = [int(v) for v in np.sum([H.level(l, fields=())["margin"] for l in range(info["levels"])], axis=0)]
             log(f"levels {info['levels']} nb {info['nb']} OC {info['oc']:.2f} CC {info['cc']:.2f}")
         H.close()
     if args.warmup == 0:
@@ -294,6 +331,7 @@ def main(argv=None):
         info = H.info()
         lvl = H.level(args.roofline_level)
         lvl0 = H.level(0, fields=())
+        audit = [int(v) for v in np.sum([H.level(l, fields=())["margin"] for l in range(info["levels"])], axis=0)]
         H.close()
 
     tuning = None
@@ -355,6 +393,14 @@ def main(argv=None):
                 "bytes_per_launch": rb["bytes"], "avg_launch_us": round(avg_ms * 1e3, 2),
                 "launches": launches, "lane_groups": G, "grid_threads": grid_threads}
 
+    Hl = P.Hierarchy(rp, ci, va, S.bs, params)
+    P.timer_read()
+    levels_bw = level_bandwidth(P, Hl, b, info["levels"])
+    Hl.close()
+    for r in levels_bw:
+        log(f"level {r['level']}: relax {r['relax_us']} us {r['relax_GBs']} GB/s, "
+            f"restrict {r['restrict_us']} us {r['restrict_GBs']} GB/s")
+
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "DOFs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall_ms, 3),
@@ -369,6 +415,8 @@ def main(argv=None):
         "solve_T_ms": round(float(solveT_ms), 3), "iters": iters, "iters_T": itersT,
         "step": "setup + solve + transposed solve; value = dofs / (setup + solve)",
         "roofline": roof,
+        "decision_margin_audit": dict(zip(("theta", "phi", "one_point", "drop"), audit)),
+        "levels_bandwidth": levels_bw,
         "tuned": tuning is not None,
         "tuning": tuning.tolist() if tuning is not None else None,
         "tuning_kinds": list(P.TUNE_KINDS),

@@ -130,6 +130,13 @@ typedef struct {
                                       diagonal blocks */
     const double *face_vals;       /* [nnzb][rmax][cmax] entries on those rows x columns, ascending */
     const double *face_dvals;      /* [nb][bs][bs] diagonal blocks */
+    int32_t margin[4];             /* decision-margin audit (host copy): comparisons whose two sides lie
+                                      within 1e-12 relative in the theta and phi strength tests, F rows
+                                      whose one-point choice has a rival that close, and drop tests of
+                                      the coarse operator built from this level.  Setup decisions are
+                                      bit-exact with the reference arithmetic either way; the counts
+                                      show how close they came to flipping.  A batch counts the rows of
+                                      systems solved directly on the level too. */
 } nair_level_view;
 
 /* Fill *p with the defaults (degree 1, theta 0.25, phi 0.025, drop 1e-3, F

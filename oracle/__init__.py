@@ -48,7 +48,7 @@ class _LevelView(C.Structure):
                 ("pmap", C.c_void_p), ("nc", C.c_int32), ("pmis_rounds", C.c_int32),
                 ("dround", C.c_void_p), ("z_nnzb", C.c_int32), ("z_rowptr", C.c_void_p), ("z_colidx", C.c_void_p),
                 ("z_vals", C.c_void_p), ("dense_n", C.c_int32), ("dense_lu", C.c_void_p),
-                ("dense_piv", C.c_void_p)]
+                ("dense_piv", C.c_void_p), ("margin", C.c_int64 * 4)]
 
 
 _lib = None
@@ -141,6 +141,9 @@ class Level:
     z_vals: Optional[np.ndarray] = None
     dense_lu: Optional[np.ndarray] = None
     dense_piv: Optional[np.ndarray] = None
+    # decision-margin audit: comparisons within 1e-12 relative (theta strength,
+    # phi strength, one-point choice, drop test of the next coarse operator)
+    margin: tuple = (0, 0, 0, 0)
 
 
 class Hierarchy:
@@ -211,6 +214,7 @@ class Hierarchy:
             lv.z_rowptr = _view(v.z_rowptr, np.int32, v.nc + 1)
             lv.z_colidx = _view(v.z_colidx, np.int32, v.z_nnzb)
             lv.z_vals = _view(v.z_vals, np.float64, v.z_nnzb * bb).reshape(v.z_nnzb, bs, bs)
+        lv.margin = tuple(int(m) for m in v.margin)
         if v.dense_lu:
             n = v.dense_n
             lv.dense_lu = _view(v.dense_lu, np.float64, n * n).reshape(n, n)

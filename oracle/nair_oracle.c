@@ -48,7 +48,17 @@ typedef struct {
     int32_t dense_n;
     double *lu;
     int32_t *piv;
+    /* decision-margin audit: comparisons whose two sides lie within 1e-12
+     * relative (theta strength, phi strength, one-point choice, drop filter of
+     * the coarse operator built from this level) */
+    int64_t margin[4];
 } level_t;
+
+/* The two sides of a comparison are within 1e-12 of each other, relative to
+ * the larger (both zero counts as a tie). */
+static int near_tie(double a, double b) {
+    return fabs(a - b) <= 1e-12 * fmax(fabs(a), fabs(b));
+}
 
 struct ora_hier {
     ora_params prm;
@@ -207,6 +217,8 @@ static void strength(level_t *L, double theta, double phi) {
             if (A->colidx[t] != I && m > 0.0) {
                 if (L->bnorm[t] >= thr_theta) mk |= 1;
                 if (L->bnorm[t] >= thr_phi) mk |= 2;
+                L->margin[0] += near_tie(L->bnorm[t], thr_theta);
+                L->margin[1] += near_tie(L->bnorm[t], thr_phi);
             }
             L->mask[t] = mk;
             if (mk & 1) L->lambda[A->colidx[t]] += 1;
@@ -344,6 +356,15 @@ static void one_point(level_t *L) {
             }
         }
         L->pmap[I] = (best >= 0) ? L->cidx[best] : -1;
+        /* audit: another candidate within 1e-12 of the chosen one's size */
+        if (best >= 0)
+            for (int32_t t = A->rowptr[I]; t < A->rowptr[I + 1]; ++t) {
+                int32_t J = A->colidx[t];
+                if (J != I && J != best && L->cf[J] == 1 && L->bnorm[t] > 0.0 && near_tie(L->bnorm[t], bestn)) {
+                    L->margin[2] += 1;
+                    break;
+                }
+            }
     }
 }
 
@@ -656,8 +677,10 @@ static int galerkin(level_t *L, double drop, bsr_t *Kout) {
             if (K.colidx[t] == i) dn = kn[t];
         }
         double thr = drop * dn;
-        for (int32_t t = K.rowptr[i]; t < K.rowptr[i + 1]; ++t)
+        for (int32_t t = K.rowptr[i]; t < K.rowptr[i + 1]; ++t) {
             if (K.colidx[t] == i || kn[t] > thr) kept++;
+            if (K.colidx[t] != i) L->margin[3] += near_tie(kn[t], thr);
+        }
     }
     if ((st = bsr_alloc(Kout, nc, nc, bs, kept)) != ORA_OK) return st;
     o = 0;
@@ -1449,6 +1472,7 @@ int ora_level(const ora_hier *h, int32_t lvl, ora_level_view *v) {
     v->dense_n = L->dense_n;
     v->dense_lu = L->lu;
     v->dense_piv = L->piv;
+    for (int k = 0; k < 4; ++k) v->margin[k] = L->margin[k];
     return ORA_OK;
 }
 

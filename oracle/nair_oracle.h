@@ -80,6 +80,10 @@ typedef struct {
     int32_t dense_n;             /* coarsest: dense order nb*bs */
     const double *dense_lu;      /* coarsest: LU factors with partial pivoting, row-major */
     const int32_t *dense_piv;
+    int64_t margin[4];           /* decision-margin audit: comparisons within 1e-12 relative in the
+                                    theta and phi strength tests, one-point choices with a rival
+                                    candidate that close, and the drop test of the coarse operator
+                                    built from this level */
 } ora_level_view;
 
 typedef struct ora_hier ora_hier;

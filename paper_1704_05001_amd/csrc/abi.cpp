@@ -307,6 +307,9 @@ nair_status nair_get_level(nair_hier h, int32_t lvl, nair_level_view *v) {
     }
     v->dense_n = L.dense_n;
     v->dense_inv = L.dense_inv.get();
+    if (L.margin.get() &&
+        hipMemcpy(v->margin, L.margin.get(), sizeof(v->margin), hipMemcpyDeviceToHost) != hipSuccess)
+        return bad(h, "reading the decision-margin counts failed");
     if (L.face.on) {
         v->face_rmax = L.face.rmax;
         v->face_cmax = L.face.cmax;

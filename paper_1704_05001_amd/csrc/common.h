@@ -122,8 +122,9 @@ void launch_block_maxabs(const double *vals, int64_t nnzb, int bs, double *out, 
 // skip (nullable): blocks whose inverse is not needed (directly solved systems)
 void launch_block_inverse(const int *rowptr, const int *colidx, const double *vals, int nb, int bs,
                           const int8_t *skip, double *dinv, int *singular_min, hipStream_t s);
+// margin[0], margin[1] += comparisons within 1e-12 relative in the theta / phi tests
 void launch_strength(const int *rowptr, const int *colidx, const double *bnorm, int nb, double theta,
-                     double phi, uint8_t *mask, int *lambda, hipStream_t s);
+                     double phi, uint8_t *mask, int *lambda, int *margin, hipStream_t s);
 void launch_strong_transpose(const int *rowptr, const int *colidx, const uint8_t *mask, int nb,
                              const int *stptr, int *fill, int *stidx, hipStream_t s);
 // splitting states: -1 undecided, 0 F, 1 C, 2 block of a directly solved system
@@ -142,8 +143,9 @@ void launch_seg_info(const int *seg, const int8_t *mode, int nsys, int nb, int *
                      hipStream_t s);
 void launch_mark_direct(const int8_t *direct, int nb, int8_t *state, hipStream_t s);
 void launch_gather_int(const int *v, const int *idx, int n, int *out, hipStream_t s);
+// margin[2] += F rows whose chosen C block has a rival within 1e-12 relative
 void launch_one_point(const int *rowptr, const int *colidx, const double *bnorm, const int8_t *cf,
-                      const int *cidx, int nb, int *pmap, hipStream_t s);
+                      const int *cidx, int nb, int *pmap, int *margin, hipStream_t s);
 // T = -(Dinv_I A_IJ) over phi-strong F-F blocks (fine row numbering, C rows empty)
 void launch_count_T(const int *rowptr, const int *colidx, const uint8_t *mask, const int8_t *cf, int nb,
                     int *cnt, hipStream_t s);
@@ -168,7 +170,8 @@ void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipSt
 // O = S + W (union pattern, S's value first)
 void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s);
 // K = RA * P (P one-point through pmap), filtered by drop; returns the filtered K
-void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevBSR &K, hipStream_t s);
+// margin[3] += off-diagonal blocks whose drop test is within 1e-12 relative
+void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevBSR &K, int *margin, hipStream_t s);
 
 // ------------------------------------------------------------------ dense
 // For each segment k < nseg (host arrays): the dense operator of A's block rows

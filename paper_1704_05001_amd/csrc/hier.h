@@ -41,6 +41,7 @@ struct Level {
     DBuf<double> dinv, bnorm;
     DBuf<uint8_t> mask;
     DBuf<int> lambda, cidx, pmap, dround, cpts, flist;
+    DBuf<int> margin;               // decision-margin audit counts (theta, phi, one-point, drop)
     DBuf<int8_t> cf;
     int nc = 0, nF = 0, rounds = 0;
     DevBSR Z;                       // R = [Z I]: nc rows, fine F columns

@@ -232,6 +232,8 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         DBuf<int> sing(1);
         NAIR_HIP(hipMemsetAsync(sing.get(), 0x7f, sizeof(int), s));
         NAIR_HIP(hipMemsetAsync(L.lambda.get(), 0, sizeof(int) * n, s));
+        L.margin.alloc(4);
+        NAIR_HIP(hipMemsetAsync(L.margin.get(), 0, sizeof(int) * 4, s));
         launch_block_maxabs(L.A.vals.get(), nz, bs, L.bnorm.get(), s);
         {
             TimerScope ts(TK_BLOCKINV, l, s);
@@ -239,7 +241,7 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
                                  L.dinv.get(), sing.get(), s);
         }
         launch_strength(L.A.rowptr.get(), L.A.colidx.get(), L.bnorm.get(), n, p.theta, p.phi, L.mask.get(),
-                        L.lambda.get(), s);
+                        L.lambda.get(), L.margin.get(), s);
         if (l == 0 && p.cf_override_host) {
             std::vector<int8_t> cfh(n);
             for (int I = 0; I < n; ++I) cfh[I] = p.cf_override_host[I] ? 1 : 0;
@@ -310,7 +312,7 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         L.flist.alloc(L.nF);
         launch_cf_index(L.cf.get(), cscan.get(), fscan.get(), n, L.cidx.get(), L.cpts.get(), L.flist.get(), s);
         launch_one_point(L.A.rowptr.get(), L.A.colidx.get(), L.bnorm.get(), L.cf.get(), L.cidx.get(), n,
-                         L.pmap.get(), s);
+                         L.pmap.get(), L.margin.get(), s);
         // Neumann operands: T (phi-strong F-F, scaled by -D_ff^{-1}) and W_0 = A_cf
         DevBSR T, W0;
         T.nb = n;
@@ -377,7 +379,7 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         DevBSR RA;
         spgemm(L.Z, L.cpts.get(), L.A, RA, s);
         auto next = std::make_unique<Level>();
-        rap_merge_drop(RA, L.pmap.get(), nc, p.drop, next->A, s);
+        rap_merge_drop(RA, L.pmap.get(), nc, p.drop, next->A, L.margin.get(), s);
         next->seg.assign(cseg.begin(), cseg.begin() + nsys + 1);
         next->mode.assign(nsys, 0);
         h.lv.push_back(std::move(next));

@@ -145,9 +145,14 @@ __global__ __launch_bounds__(64) void k_block_inverse(const int *__restrict__ ro
 // Row I: m = largest off-diagonal block size; block J != I is theta-strong
 // when size >= theta*m (m > 0), phi-strong likewise; lambda_J counts the rows
 // depending theta-strongly on J.
+// The two sides of a comparison are within 1e-12 of each other, relative to
+// the larger (both zero counts as a tie): the decision-margin audit.
+__device__ inline bool near_tie(double a, double b) { return fabs(a - b) <= 1e-12 * fmax(fabs(a), fabs(b)); }
+
 __global__ __launch_bounds__(256) void k_strength(const int *__restrict__ rowptr, const int *__restrict__ colidx,
                                                  const double *__restrict__ bnorm, int nb, double theta, double phi,
-                                                 uint8_t *__restrict__ mask, int *__restrict__ lambda) {
+                                                 uint8_t *__restrict__ mask, int *__restrict__ lambda,
+                                                 int *__restrict__ margin) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= nb) return;
     const int lo = rowptr[I], hi = rowptr[I + 1];
@@ -161,6 +166,8 @@ __global__ __launch_bounds__(256) void k_strength(const int *__restrict__ rowptr
         if (J != I && m > 0.0) {
             if (bnorm[t] >= tt) mk |= 1;
             if (bnorm[t] >= tp) mk |= 2;
+            if (near_tie(bnorm[t], tt)) atomicAdd(margin, 1);
+            if (near_tie(bnorm[t], tp)) atomicAdd(margin + 1, 1);
         }
         mask[t] = mk;
         if (mk & 1) atomicAdd(&lambda[J], 1);
@@ -336,7 +343,8 @@ __global__ __launch_bounds__(256) void k_gather_int(const int *__restrict__ v, c
 // F block: coarse index of its largest (nonzero) stored C block, lowest column on ties.
 __global__ __launch_bounds__(256) void k_one_point(const int *__restrict__ rowptr, const int *__restrict__ colidx,
                                                   const double *__restrict__ bnorm, const int8_t *__restrict__ cf,
-                                                  const int *__restrict__ cidx, int nb, int *__restrict__ pmap) {
+                                                  const int *__restrict__ cidx, int nb, int *__restrict__ pmap,
+                                                  int *__restrict__ margin) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= nb) return;
     if (cf[I] == kC) {
@@ -353,6 +361,14 @@ __global__ __launch_bounds__(256) void k_one_point(const int *__restrict__ rowpt
         }
     }
     pmap[I] = (best >= 0) ? cidx[best] : -1;
+    if (best >= 0)   // audit: another candidate within 1e-12 of the chosen one's size
+        for (int t = rowptr[I]; t < rowptr[I + 1]; ++t) {
+            const int J = colidx[t];
+            if (J != I && J != best && cf[J] == kC && bnorm[t] > 0.0 && near_tie(bnorm[t], bestn)) {
+                atomicAdd(margin + 2, 1);
+                break;
+            }
+        }
 }
 
 // ----------------------------------------------- Neumann operands (patterns)
@@ -488,8 +504,8 @@ void launch_block_inverse(const int *rowptr, const int *colidx, const double *va
 }
 
 void launch_strength(const int *rowptr, const int *colidx, const double *bnorm, int nb, double theta, double phi,
-                     uint8_t *mask, int *lambda, hipStream_t s) {
-    k_strength<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, bnorm, nb, theta, phi, mask, lambda);
+                     uint8_t *mask, int *lambda, int *margin, hipStream_t s) {
+    k_strength<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, bnorm, nb, theta, phi, mask, lambda, margin);
     NAIR_HIP(hipGetLastError());
 }
 
@@ -546,8 +562,8 @@ void launch_gather_int(const int *v, const int *idx, int n, int *out, hipStream_
 }
 
 void launch_one_point(const int *rowptr, const int *colidx, const double *bnorm, const int8_t *cf, const int *cidx,
-                      int nb, int *pmap, hipStream_t s) {
-    k_one_point<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, bnorm, cf, cidx, nb, pmap);
+                      int nb, int *pmap, int *margin, hipStream_t s) {
+    k_one_point<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, bnorm, cf, cidx, nb, pmap, margin);
     NAIR_HIP(hipGetLastError());
 }
 

@@ -554,20 +554,24 @@ __global__ __launch_bounds__(256) void k_rap_values(int64_t nnz, int bb, const i
 // Drop filter: keep the diagonal and blocks with size > drop * size(diagonal).
 __global__ __launch_bounds__(256) void k_drop_mark(const int *__restrict__ krp, const int *__restrict__ kcol,
                                                   const double *__restrict__ knorm, int m, double drop,
-                                                  uint8_t *__restrict__ keep, int *__restrict__ kept) {
+                                                  uint8_t *__restrict__ keep, int *__restrict__ kept,
+                                                  int *__restrict__ margin) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     double dn = 0.0;
     for (int t = krp[i]; t < krp[i + 1]; ++t)
         if (kcol[t] == i) dn = knorm[t];
     const double thr = drop * dn;
-    int c = 0;
+    int c = 0, nties = 0;
     for (int t = krp[i]; t < krp[i + 1]; ++t) {
         const bool k = (kcol[t] == i) || (knorm[t] > thr);
         keep[t] = k ? 1 : 0;
         c += k ? 1 : 0;
+        // audit: the two sides of the drop test within 1e-12 relative
+        if (kcol[t] != i && fabs(knorm[t] - thr) <= 1e-12 * fmax(fabs(knorm[t]), fabs(thr))) ++nties;
     }
     kept[i] = c;
+    if (nties) atomicAdd(margin + 3, nties);
 }
 
 __global__ void k_set_int(int *__restrict__ p, const int *__restrict__ v) { *p = *v; }
@@ -684,7 +688,7 @@ void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s) {
     NAIR_HIP(hipGetLastError());
 }
 
-void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevBSR &K, hipStream_t s) {
+void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevBSR &K, int *margin, hipStream_t s) {
     const int m = RA.nb;
     const int bs = RA.bs;
     const int bb = bs * bs;
@@ -722,7 +726,8 @@ void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevB
                                                                   kval.get());
     }
     launch_block_maxabs(kval.get(), nnz, bs, knorm.get(), s);
-    k_drop_mark<<<grid_for(m, 256), 256, 0, s>>>(krp.get(), kcol.get(), knorm.get(), m, drop, keep.get(), kept.get());
+    k_drop_mark<<<grid_for(m, 256), 256, 0, s>>>(krp.get(), kcol.get(), knorm.get(), m, drop, keep.get(), kept.get(),
+                                                 margin);
     NAIR_HIP(hipGetLastError());
     K.nb = nc;
     K.ncols = nc;

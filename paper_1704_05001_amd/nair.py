@@ -61,7 +61,8 @@ class _LevelView(C.Structure):
                 ("pmis_rounds", C.c_int32), ("z_nnzb", C.c_int32), ("z_rowptr", C.c_void_p),
                 ("z_colidx", C.c_void_p), ("z_vals", C.c_void_p), ("dense_n", C.c_int32),
                 ("dense_inv", C.c_void_p), ("face_rmax", C.c_int32), ("face_cmax", C.c_int32),
-                ("face_meta", C.c_void_p), ("face_vals", C.c_void_p), ("face_dvals", C.c_void_p)]
+                ("face_meta", C.c_void_p), ("face_vals", C.c_void_p), ("face_dvals", C.c_void_p),
+                ("margin", C.c_int32 * 4)]
 
 
 _lib = None
@@ -393,7 +394,7 @@ class Hierarchy:
         bb = bs * bs
         want = (lambda k: True) if fields is None else (lambda k: k in fields)
         out = dict(nb=nb, bs=bs, nnzb=nnzb, coarsest=bool(v.coarsest), nc=v.nc, pmis_rounds=v.pmis_rounds,
-                   face_rmax=v.face_rmax, face_cmax=v.face_cmax)
+                   face_rmax=v.face_rmax, face_cmax=v.face_cmax, margin=tuple(int(m) for m in v.margin))
         spec = [("rowptr", v.rowptr, torch.int32, nb + 1, None),
                 ("colidx", v.colidx, torch.int32, nnzb, None),
                 ("vals", v.vals, torch.float64, nnzb * bb, (nnzb, bs, bs))]

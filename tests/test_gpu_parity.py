@@ -94,6 +94,7 @@ def compare_hierarchies(G, O):
         assert np.array_equal(np_(g["cf"]), o.cf), l
         assert np.array_equal(np_(g["dround"]), o.dround), l
         assert g["pmis_rounds"] == o.pmis_rounds, l
+        assert tuple(g["margin"]) == tuple(o.margin), (l, g["margin"], o.margin)   # decision-margin audit
         assert np.array_equal(np_(g["cidx"]), o.cidx), l
         assert g["nc"] == o.nc
         assert np.array_equal(np_(g["pmap"]), o.pmap), l
@@ -272,3 +273,38 @@ def test_setup_is_deterministic():
         for key in a:
             if isinstance(a[key], torch.Tensor):
                 assert torch.equal(a[key], b[key]), (l, key)
+
+
+def test_margin_audit_matches_oracle():
+    """The decision-margin audit (comparisons within 1e-12 relative in the
+    strength, one-point and drop decisions) counts the same near-ties as the
+    oracle, with ties planted in theta, in the drop tolerance and by a
+    diagonal flow on a uniform grid."""
+    _say("test: decision-margin audit")
+    S = dg_quad(7, 2, (math.cos(0.4), math.sin(0.4)), sigma=1.0, seed_perm=61)
+    O = oracle.Hierarchy(S.nb, S.bs, S.rowptr, S.colidx, S.vals, oracle.Params(degree=1, max_coarse_dofs=20))
+    L0 = O.level(0)
+    rows = np.repeat(np.arange(L0.nb), np.diff(L0.rowptr))
+    off = L0.colidx != rows
+    m = np.zeros(L0.nb)
+    np.maximum.at(m, rows[off], L0.bnorm[off])
+    t = next(t for t in np.flatnonzero(off) if 0 < L0.bnorm[t] < m[rows[t]])
+    theta = float(L0.bnorm[t] / m[rows[t]])
+    K = oracle.Hierarchy(S.nb, S.bs, S.rowptr, S.colidx, S.vals,
+                         oracle.Params(degree=1, max_coarse_dofs=20, drop=0.0)).level(1)
+    kr = np.repeat(np.arange(K.nb), np.diff(K.rowptr))
+    kn = np.abs(K.vals).max(axis=(1, 2))
+    dn = np.zeros(K.nb)
+    dn[kr[K.colidx == kr]] = kn[K.colidx == kr]
+    u = next(u for u in np.flatnonzero(K.colidx != kr) if kn[u] < 0.5 * dn[kr[u]])
+    drop = float(kn[u] / dn[kr[u]])
+    U = dg_quad(6, 1, (math.sqrt(0.5), math.sqrt(0.5)), sigma=1.0, seed_perm=7)
+    totals = []
+    for M, kw in ((S, dict(theta=theta)), (S, dict(drop=drop)), (U, dict(max_coarse_dofs=8)),
+                  (S, dict(drop=0.0))):
+        kw = dict(dict(degree=1, max_coarse_dofs=20), **kw)
+        G, O = build_pair(M.nb, M.bs, M.rowptr, M.colidx, M.vals, **kw)
+        compare_hierarchies(G, O)
+        totals.append(np.sum([O.level(l).margin for l in range(O.num_levels)], axis=0))
+    _say(f"  audit totals (theta, phi, one-point, drop): {[tuple(int(v) for v in x) for x in totals]}")
+    assert totals[0][0] >= 1 and totals[1][3] >= 1 and totals[2][2] >= 1

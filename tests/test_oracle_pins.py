@@ -882,3 +882,86 @@ def test_gmres_solves_and_transposed(m, cycle):
     xs, hs, _ = HS.solve(S.rhs, 1e-12, 300)
     if m >= 10:
         assert len(hist) <= len(hs)                       # an accelerator, not a slowdown
+
+
+# ------------------------------------------------------ decision-margin audit
+
+def _near(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return np.abs(a - b) <= 1e-12 * np.maximum(np.abs(a), np.abs(b))
+
+
+def _audit_brute(L, theta, phi):
+    """Strength and one-point audit counts of a level, re-evaluated from its
+    published block sizes and splitting by the definitions."""
+    rows = row_blocks(L.rowptr)
+    off = L.colidx != rows
+    m = np.zeros(L.nb)
+    np.maximum.at(m, rows[off], L.bnorm[off])
+    tested = off & (m[rows] > 0)
+    n_theta = int(_near(L.bnorm[tested], theta * m[rows[tested]]).sum())
+    n_phi = int(_near(L.bnorm[tested], phi * m[rows[tested]]).sum())
+    n_one = 0
+    for I in np.flatnonzero(L.cf == 0):
+        t = np.arange(L.rowptr[I], L.rowptr[I + 1])
+        cand = t[(L.colidx[t] != I) & (L.cf[L.colidx[t]] == 1) & (L.bnorm[t] > 0)]
+        if len(cand) < 2:
+            continue
+        best = cand[np.argmax(L.bnorm[cand])]          # first maximum = lowest column
+        rivals = cand[cand != best]
+        n_one += int(_near(L.bnorm[rivals], L.bnorm[best]).any())
+    return n_theta, n_phi, n_one
+
+
+def _drop_brute(Kfull, drop):
+    """Drop-test audit count over the off-diagonal blocks of an unfiltered K."""
+    rows = row_blocks(Kfull.rowptr)
+    kn = np.abs(Kfull.vals).max(axis=(1, 2))
+    dn = np.zeros(Kfull.nb)
+    diag = Kfull.colidx == rows
+    dn[rows[diag]] = kn[diag]
+    off = ~diag
+    return int(_near(kn[off], drop * dn[rows[off]]).sum())
+
+
+def test_margin_audit_counts_match_their_definitions():
+    """The audit counts near-ties by the definition, on a DG matrix and with
+    ties planted on purpose: theta chosen so one block's size equals theta
+    times its row maximum, the drop tolerance so one coarse block's size equals
+    drop times its diagonal block's, and a matrix whose F rows see two C
+    blocks of identical size."""
+    S = small_dg(7, 2, seed=61)
+    base = hier(S, degree=1, max_coarse_dofs=20)
+    L0 = base.level(0)
+    assert L0.margin[:3] == _audit_brute(L0, 0.25, 0.025)
+    # theta planted on a block of row I: theta = size / row maximum
+    rows = row_blocks(L0.rowptr)
+    off = L0.colidx != rows
+    m = np.zeros(L0.nb)
+    np.maximum.at(m, rows[off], L0.bnorm[off])
+    t = next(t for t in np.flatnonzero(off) if 0 < L0.bnorm[t] < m[rows[t]])
+    theta = L0.bnorm[t] / m[rows[t]]
+    H = hier(S, degree=1, theta=theta, max_coarse_dofs=20)
+    Lt = H.level(0)
+    bt = _audit_brute(Lt, theta, 0.025)
+    assert Lt.margin[:3] == bt and bt[0] >= 1
+    # drop planted on a block of the unfiltered coarse operator (drop 0 keeps
+    # every nonzero block; the level-0 products do not depend on drop)
+    H0 = hier(S, degree=1, max_coarse_dofs=20, drop=0.0)
+    K = H0.level(1)
+    kr = row_blocks(K.rowptr)
+    kn = np.abs(K.vals).max(axis=(1, 2))
+    dn = np.zeros(K.nb)
+    dn[kr[K.colidx == kr]] = kn[K.colidx == kr]
+    u = next(u for u in np.flatnonzero(K.colidx != kr) if kn[u] < 0.5 * dn[kr[u]])
+    drop = kn[u] / dn[kr[u]]
+    Hd = hier(S, degree=1, max_coarse_dofs=20, drop=drop)
+    assert Hd.level(0).margin[3] == _drop_brute(K, drop) >= 1
+    assert H0.level(0).margin[3] == _drop_brute(K, 0.0)
+    # one-point ties: a uniform grid with constant velocity along a diagonal
+    # couples each cell to its two upwind neighbours by blocks of equal size
+    U = dg_quad(6, 1, (math.sqrt(0.5), math.sqrt(0.5)), sigma=1.0, seed_perm=7)
+    HU = hier(U, degree=1, max_coarse_dofs=8)
+    LU = HU.level(0)
+    bu = _audit_brute(LU, 0.25, 0.025)
+    assert LU.margin[:3] == bu and bu[2] >= 1
