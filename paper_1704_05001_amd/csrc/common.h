@@ -239,6 +239,10 @@ inline MatView<float> view(const DevBSR &A, const float *vals32) {
 }
 // lane-group counts a kernel may use for block size bs (powers of two, G * bs <= 256)
 int max_groups(int bs);
+// a level of `rows` block rows gives fewer than kFewLanes lanes at one group per
+// row: its cycle kernels take more groups by default and are not tuned
+constexpr int64_t kFewLanes = 32768;
+bool few_lanes(int64_t rows, int bs);
 
 // Rows of systems that have stopped iterating are skipped in batched solves:
 // row r is live when active == nullptr or active[bsys ? bsys[r] : 0] != 0.

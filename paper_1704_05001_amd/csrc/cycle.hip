@@ -569,12 +569,21 @@ __global__ __launch_bounds__(256) void k_to_float(const double *__restrict__ in,
 }
 
 // Lane groups per block row: the tuned count if the view carries one, else
-// from the average row length (at most 256 lanes per row either way).
+// from the average row length; on a level too small to fill the chip with one
+// group per row, up to four times the average row length: there each row's
+// chain of dependent loads, not bandwidth, sets the time (at most 256 lanes
+// per row either way).
 template <typename MT>
 int groups_for(const MatView<MT> &A) {
     int G;
     if (A.groups > 0) {
         G = A.groups;
+    } else if (few_lanes(A.nb, A.bs)) {
+        // enough groups for rows several times the average length (the longest
+        // row sets the time), within what a row can take
+        const double avg = A.nb > 0 ? static_cast<double>(A.nnzb) / A.nb : 1.0;
+        G = 1;
+        while (G < max_groups(A.bs) && G < 4.0 * avg) G *= 2;
     } else {
         const double avg = A.nb > 0 ? static_cast<double>(A.nnzb) / A.nb : 1.0;
         G = avg <= 3.5 ? 1 : (avg <= 7.0 ? 2 : (avg <= 14.0 ? 4 : 8));
@@ -624,6 +633,8 @@ int max_groups(int bs) {
     while (2 * G * bs <= kThreads && G < 32) G *= 2;
     return G;
 }
+
+bool few_lanes(int64_t rows, int bs) { return rows * bs < kFewLanes; }
 
 template <typename MT, typename VT>
 void launch_residual(const MatView<MT> &A, const VT *b, const VT *x, VT *r, float *r_lo, hipStream_t s,

@@ -398,6 +398,7 @@ __global__ __launch_bounds__(64) void k_pairs_small(const int *__restrict__ xrow
                                                    int *__restrict__ pairptr, int2 *__restrict__ pairs) {
     __shared__ int cols[kHashSmall / 2];
     __shared__ int cnt[kHashSmall / 2];
+    if (blockIdx.x == 0 && threadIdx.x == 0) pairptr[crowptr[m]] = prow[m];   // the end of the last block's pairs
     for (int i = blockIdx.x; i < m; i += gridDim.x) {
         if (ub[i] > small_cap) continue;
         const int c0 = crowptr[i], nout = crowptr[i + 1] - c0;
@@ -499,6 +500,7 @@ __global__ __launch_bounds__(64) void k_rap_contrib(const int *__restrict__ rarp
     __shared__ int kc[kHashSmall / 2];
     __shared__ int off[kHashSmall / 2];
     const int lane = threadIdx.x;
+    if (blockIdx.x == 0 && lane == 0) kptr[krp[m]] = crow[m];   // the end of the last block's list
     for (int i = blockIdx.x; i < m; i += gridDim.x) {
         const int r0 = rarp[i], nra = rarp[i + 1] - r0;
         const int k0 = krp[i], nk = krp[i + 1] - k0;
@@ -574,7 +576,6 @@ __global__ __launch_bounds__(256) void k_drop_mark(const int *__restrict__ krp, 
     if (nties) atomicAdd(margin + 3, nties);
 }
 
-__global__ void k_set_int(int *__restrict__ p, const int *__restrict__ v) { *p = *v; }
 
 }  // namespace
 
@@ -652,7 +653,6 @@ void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipSt
         k_pairs_large<<<256, 256, 0, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(), Y.colidx.get(),
                                           big_list.get(), big_count, C.rowptr.get(), C.colidx.get(), prow.get(),
                                           pairptr.get(), pairs.get());
-    k_set_int<<<1, 1, 0, s>>>(pairptr.get() + nnz, prow.get() + m);
     NAIR_HIP(hipGetLastError());
     const int64_t total = static_cast<int64_t>(nnz) * bs;
     const unsigned grid = cap_grid((total + 255) / 256);
@@ -717,7 +717,6 @@ void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevB
                                       flags.get());
     k_rap_contrib<<<cap_grid(m), 64, 0, s>>>(RA.rowptr.get(), RA.colidx.get(), pmap, m, krp.get(), kcol.get(),
                                              crow.get(), kptr.get(), klist.get());
-    k_set_int<<<1, 1, 0, s>>>(kptr.get() + nnz, crow.get() + m);
     NAIR_HIP(hipGetLastError());
     if (nnz > 0) {
         TimerScope ts(TK_RAP, g_timer_level, s);

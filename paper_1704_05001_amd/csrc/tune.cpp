@@ -1,11 +1,12 @@
 // Lane-group autotuner of the cycle kernels.
 //
 // Every cycle kernel maps a block row onto G groups of bs lanes (G * bs <= 256).
-// The default G comes from the level's average row length; the best choice
-// also depends on how many rows a level has (how full the chip is) and on the
-// block size, so the tuner times each power-of-two G on the level's own
-// operands and keeps the fastest, per level and per kernel.  A choice must beat
-// the default by 3% to replace it, so timing noise does not flip it.
+// The default G comes from the level's average row length (the most groups on
+// levels too small to fill the chip); the best choice also depends on how many
+// rows a level has and on the block size, so the tuner times each power-of-two
+// G on the level's own operands and keeps the fastest, per level and per
+// kernel.  A choice must beat the default by 3% to replace it, so timing noise
+// does not flip it.  Small levels are left at their default.
 #include <algorithm>
 #include <vector>
 
@@ -98,6 +99,9 @@ void tune_levels(Hier &h, int reps, hipStream_t s) {
         Level &L = *h.lv[l];
         Level &C = *h.lv[l + 1];
         if (L.coarsest) break;
+        // small levels keep their default (the most groups): timing their kernels
+        // back to back with warm caches does not predict them inside a cycle
+        if (few_lanes(L.A.nb, L.A.bs)) continue;
         const int bs = L.A.bs;
         const MatView<T> A = V::A(L), AT = V::AT(L), Z = V::Z(L), ZT = V::ZT(L);
         L.tune[TU_RELAX] = pick(
