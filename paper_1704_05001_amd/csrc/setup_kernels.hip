@@ -20,16 +20,27 @@ __device__ inline double wave_max(double v) {
 // ----------------------------------------------------------- block sizes
 
 // out[b] = max_e |vals[b][e]|; one wave per block, four blocks per workgroup.
-__global__ __launch_bounds__(256) void k_block_maxabs(const double *__restrict__ vals, int64_t nnzb, int bb,
+// ||block||_max: one thread per block row (a row's bs entries are contiguous),
+// the rows of a block combined in LDS.  max is exact, so the order is free.
+__global__ __launch_bounds__(256) void k_block_maxabs(const double *__restrict__ vals, int64_t nnzb, int bs,
                                                      double *__restrict__ out) {
-    const int lane = threadIdx.x & 63;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * 4;
-    for (int64_t blk = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6); blk < nnzb; blk += stride) {
-        const double *p = vals + blk * bb;
-        double m = 0.0;
-        for (int e = lane; e < bb; e += kWave) m = fmax(m, fabs(p[e]));
-        m = wave_max(m);
-        if (lane == 0) out[blk] = m;
+    __shared__ double m[256];
+    const int per = 256 / bs;
+    const int lb = threadIdx.x / bs;
+    const int a = threadIdx.x - lb * bs;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * per + lb;
+    double v = 0.0;
+    if (lb < per && t < nnzb) {
+        const double *row = vals + (t * bs + a) * bs;
+        for (int c = 0; c < bs; ++c) v = fmax(v, fabs(row[c]));
+    }
+    m[threadIdx.x] = v;
+    __syncthreads();
+    const int64_t to = static_cast<int64_t>(blockIdx.x) * per + threadIdx.x;
+    if (threadIdx.x < per && to < nnzb) {
+        double r = 0.0;
+        for (int q = 0; q < bs; ++q) r = fmax(r, m[threadIdx.x * bs + q]);
+        out[to] = r;
     }
 }
 
@@ -137,6 +148,95 @@ __global__ __launch_bounds__(64) void k_block_inverse(const int *__restrict__ ro
         double *dst = dinv + static_cast<int64_t>(I) * bb;
         for (int e = lane; e < bb; e += kWave) dst[e] = y[e];
         __syncthreads();
+    }
+}
+
+// The same recipe with one thread per block row and the block in registers
+// (small blocks, every index known at compile time; the pivot row exchange is
+// a predicated swap with each candidate row).  Many small blocks then run at
+// memory speed instead of one latency-bound wave each.
+template <int BS>
+__global__ __launch_bounds__(64) void k_block_inverse_thread(const int *__restrict__ rowptr,
+                                                            const int *__restrict__ colidx,
+                                                            const double *__restrict__ vals, int nb,
+                                                            const int8_t *__restrict__ skip,
+                                                            double *__restrict__ dinv, int *__restrict__ singular_min) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nb || (skip && skip[I])) return;
+    int dpos = -1;
+    for (int t = rowptr[I]; t < rowptr[I + 1]; ++t)
+        if (colidx[t] == I) dpos = t;
+    if (dpos < 0) {   // validated before; never taken for valid input
+        atomicMin(singular_min, I);
+        return;
+    }
+    double a[BS][BS];
+    int perm[BS];
+    const double *src = vals + static_cast<int64_t>(dpos) * BS * BS;
+#pragma unroll
+    for (int i = 0; i < BS; ++i) {
+        perm[i] = i;
+#pragma unroll
+        for (int j = 0; j < BS; ++j) a[i][j] = src[i * BS + j];
+    }
+#pragma unroll
+    for (int k = 0; k < BS; ++k) {
+        // pivot: the first row i >= k of largest |a_ik|
+        double v = -1.0;
+        int idx = BS;
+#pragma unroll
+        for (int i = k; i < BS; ++i) {
+            const double av = fabs(a[i][k]);
+            if (av > v) {
+                v = av;
+                idx = i;
+            }
+        }
+        if (!(v > 0.0)) {
+            atomicMin(singular_min, I);
+            return;
+        }
+#pragma unroll
+        for (int r = k + 1; r < BS; ++r)
+            if (idx == r) {
+#pragma unroll
+                for (int j = 0; j < BS; ++j) {
+                    const double tmp = a[k][j];
+                    a[k][j] = a[r][j];
+                    a[r][j] = tmp;
+                }
+                const int tp = perm[k];
+                perm[k] = perm[r];
+                perm[r] = tp;
+            }
+        const double piv = a[k][k];
+#pragma unroll
+        for (int i = k + 1; i < BS; ++i) a[i][k] = a[i][k] / piv;
+#pragma unroll
+        for (int i = k + 1; i < BS; ++i)
+#pragma unroll
+            for (int j = k + 1; j < BS; ++j) a[i][j] = __builtin_fma(-a[i][k], a[k][j], a[i][j]);
+    }
+    double *dst = dinv + static_cast<int64_t>(I) * BS * BS;
+#pragma unroll
+    for (int j = 0; j < BS; ++j) {
+        double y[BS];
+#pragma unroll
+        for (int i = 0; i < BS; ++i) {
+            double sacc = (perm[i] == j) ? 1.0 : 0.0;
+#pragma unroll
+            for (int mm = 0; mm < i; ++mm) sacc = __builtin_fma(-a[i][mm], y[mm], sacc);
+            y[i] = sacc;
+        }
+#pragma unroll
+        for (int i = BS - 1; i >= 0; --i) {
+            double sacc = y[i];
+#pragma unroll
+            for (int mm = i + 1; mm < BS; ++mm) sacc = __builtin_fma(-a[i][mm], y[mm], sacc);
+            y[i] = sacc / a[i][i];
+        }
+#pragma unroll
+        for (int i = 0; i < BS; ++i) dst[i * BS + j] = y[i];
     }
 }
 
@@ -491,15 +591,23 @@ unsigned cap_grid(int64_t g) { return static_cast<unsigned>(g > 65536 * 16 ? 655
 
 void launch_block_maxabs(const double *vals, int64_t nnzb, int bs, double *out, hipStream_t s) {
     if (nnzb <= 0) return;
-    k_block_maxabs<<<cap_grid((nnzb + 3) / 4), 256, 0, s>>>(vals, nnzb, bs * bs, out);
+    const int per = 256 / bs;
+    k_block_maxabs<<<static_cast<unsigned>((nnzb + per - 1) / per), 256, 0, s>>>(vals, nnzb, bs, out);
     NAIR_HIP(hipGetLastError());
 }
 
 void launch_block_inverse(const int *rowptr, const int *colidx, const double *vals, int nb, int bs,
                           const int8_t *skip, double *dinv, int *singular_min, hipStream_t s) {
     if (nb <= 0) return;
-    const size_t lds = sizeof(double) * 2 * bs * bs + sizeof(int) * bs;
-    k_block_inverse<<<cap_grid(nb), 64, lds, s>>>(rowptr, colidx, vals, nb, bs, skip, dinv, singular_min);
+    const unsigned grid = static_cast<unsigned>((nb + 63) / 64);
+    if (bs == 9) {
+        k_block_inverse_thread<9><<<grid, 64, 0, s>>>(rowptr, colidx, vals, nb, skip, dinv, singular_min);
+    } else if (bs == 4) {
+        k_block_inverse_thread<4><<<grid, 64, 0, s>>>(rowptr, colidx, vals, nb, skip, dinv, singular_min);
+    } else {
+        const size_t lds = sizeof(double) * 2 * bs * bs + sizeof(int) * bs;
+        k_block_inverse<<<cap_grid(nb), 64, lds, s>>>(rowptr, colidx, vals, nb, bs, skip, dinv, singular_min);
+    }
     NAIR_HIP(hipGetLastError());
 }
 
