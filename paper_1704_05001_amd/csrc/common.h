@@ -275,6 +275,11 @@ void launch_restrict(const MatView<MT> &Z, const VT *r, const int *cpts, VT *rc,
 template <typename VT>
 void launch_restrict_T(const int *ptptr, const int *ptidx, const VT *s, VT *sc, int nc, int bs, hipStream_t st,
                        Gate g = Gate());
+// e0 = P e_c everywhere, e1 = e0 + D^{-1}(r - A e0) on F rows (e0 on C rows):
+// the interpolation and the first F sweep in one launch
+template <typename MT, typename VT>
+void launch_relax_interp(const MatView<MT> &A, const double *dinv, const VT *r, const int *pmap, const VT *ec,
+                         const int8_t *cf, VT *e0, VT *e1, hipStream_t s, Gate gate = Gate());
 template <typename MT, typename VT>
 void launch_interp_T(const MatView<MT> &ZT, const int *cidx, const VT *yc, VT *y, hipStream_t s, Gate g = Gate());
 template <typename VT>

@@ -40,6 +40,19 @@ struct PlainSrc {
     static constexpr bool kMaySkip = false;
     __device__ const VT *row(int j) const { return x + static_cast<int64_t>(j) * bs; }
 };
+// x = P e_c read through the one-point map: block J is e_c's block pmap[J], or
+// zero (skipped: its products would add zeros) when pmap[J] < 0.
+template <typename VT>
+struct PmapSrc {
+    const VT *ec;
+    const int *pmap;
+    int bs;
+    static constexpr bool kMaySkip = true;
+    __device__ const VT *row(int j) const {
+        const int p = pmap[j];
+        return p >= 0 ? ec + static_cast<int64_t>(p) * bs : nullptr;
+    }
+};
 // sum over blocks t = lo+g, lo+g+G, ... < hi of (block t row a) . x[col t]
 template <int BS, typename MT, typename VT, typename SRC>
 __device__ inline double row_part_src(const int *__restrict__ colidx, const MT *__restrict__ vals, int lo, int hi,
@@ -335,6 +348,46 @@ __global__ __launch_bounds__(kThreads) void k_relax_T(const int *__restrict__ ro
                                        only_cf, gate, face);
 }
 
+// The interpolation e = P e_c and the first F sweep in one launch (small
+// levels, where launches cost more than their work): e0 = P e_c on every row;
+// e1 = e0 + D^{-1}(r - A e0) on F rows, e1 = e0 on C rows -- what the two
+// kernels leave, computed in the same order.
+template <int BS, typename MT, typename VT>
+__global__ __launch_bounds__(kThreads) void k_relax_interp(const int *__restrict__ rowptr,
+                                                          const int *__restrict__ colidx, const MT *__restrict__ vals,
+                                                          const double *__restrict__ dinv, int nb, int bs_rt, int G,
+                                                          const VT *__restrict__ r, const int *__restrict__ pmap,
+                                                          const VT *__restrict__ ec, const int8_t *__restrict__ cf,
+                                                          VT *__restrict__ e0, VT *__restrict__ e1, Gate gate) {
+    __shared__ double part[kThreads];
+    __shared__ double tb[kThreads];
+    const int bs = Bs<BS>::get(bs_rt);
+    const Lane L = lane_of(G, bs);
+    int I = blockIdx.x * (kThreads / (G * bs)) + L.lr;
+    if (!L.valid || I >= nb || !live(gate, I)) I = -1;
+    const bool upd = I >= 0 && cf[I] == 0;
+    const PmapSrc<VT> src{ec, pmap, bs};
+    double acc = upd ? row_part_src<BS, MT, VT>(colidx, vals, rowptr[I], rowptr[I + 1], L.g, G, L.a, bs, src) : 0.0;
+    acc = reduce_groups(acc, L, G, bs, part);
+    const int64_t o = static_cast<int64_t>(I) * bs + L.a;
+    VT v = VT(0);
+    if (I >= 0 && L.g == 0) {
+        const int p = pmap[I];
+        v = p >= 0 ? ec[static_cast<int64_t>(p) * bs + L.a] : VT(0);
+        if (upd) tb[L.lr * bs + L.a] = static_cast<double>(r[o]) - acc;
+    }
+    __syncthreads();
+    if (I >= 0 && L.g == 0) {
+        e0[o] = v;
+        if (upd) {
+            const double d = apply_dinv<BS, false>(dinv + static_cast<int64_t>(I) * bs * bs, tb + L.lr * bs, L.a, bs);
+            e1[o] = static_cast<VT>(static_cast<double>(v) + d);
+        } else {
+            e1[o] = v;
+        }
+    }
+}
+
 // rc_i = r_{cpts[i]} + sum_t Z_it r_{col t}
 template <int BS, typename MT, typename VT>
 __global__ __launch_bounds__(kThreads) void k_restrict(const int *__restrict__ zrp, const int *__restrict__ zcol,
@@ -527,29 +580,38 @@ __global__ __launch_bounds__(64) void k_seg_init(const double *__restrict__ part
 // After iteration *it, one wave per system: relative residual of an active
 // system, recorded in hist[sys * hist_cap + it]; converged or non-finite
 // systems stop.
+// With one system (tick != 0) the same wave then advances the counters as
+// k_seg_tick would, saving a launch per iteration.
 __global__ __launch_bounds__(64) void k_seg_check(const double *__restrict__ part, const int *__restrict__ cptr,
                                                  const double *__restrict__ bn, const double *__restrict__ rtol,
                                                  int hist_cap, double *__restrict__ hist, double *__restrict__ last,
                                                  int *__restrict__ active, int *__restrict__ status,
-                                                 int *__restrict__ iters, const int *__restrict__ it,
-                                                 int *__restrict__ nact_acc) {
+                                                 int *__restrict__ iters, int *__restrict__ it,
+                                                 int *__restrict__ nact, int *__restrict__ nact_acc, int tick) {
     const int sys = blockIdx.x;
-    if (!active[sys]) return;   // uniform over the wave
-    const double ss = seg_total(part, cptr, sys);
-    if (threadIdx.x != 0) return;
-    const int k = *it;
-    const double rel = sqrt(ss) / bn[sys];
-    if (k < hist_cap) hist[static_cast<int64_t>(sys) * hist_cap + k] = rel;
-    last[sys] = rel;
-    iters[sys] = k + 1;
-    if (!isfinite(rel)) {
-        active[sys] = 0;
-        status[sys] = kStNumeric;
-    } else if (rel <= *rtol) {
-        active[sys] = 0;
-        status[sys] = kStOk;
-    } else {
-        atomicAdd(nact_acc, 1);
+    if (active[sys]) {   // uniform over the wave
+        const double ss = seg_total(part, cptr, sys);
+        if (threadIdx.x == 0) {
+            const int k = *it;
+            const double rel = sqrt(ss) / bn[sys];
+            if (k < hist_cap) hist[static_cast<int64_t>(sys) * hist_cap + k] = rel;
+            last[sys] = rel;
+            iters[sys] = k + 1;
+            if (!isfinite(rel)) {
+                active[sys] = 0;
+                status[sys] = kStNumeric;
+            } else if (rel <= *rtol) {
+                active[sys] = 0;
+                status[sys] = kStOk;
+            } else {
+                atomicAdd(nact_acc, 1);
+            }
+        }
+    }
+    if (tick && threadIdx.x == 0) {
+        *it = *it + 1;
+        *nact = *nact_acc;
+        *nact_acc = 0;
     }
 }
 
@@ -706,6 +768,18 @@ void launch_interp(const int *pmap, const VT *ec, VT *e0, VT *e1, int nb, int bs
     NAIR_HIP(hipGetLastError());
 }
 
+template <typename MT, typename VT>
+void launch_relax_interp(const MatView<MT> &A, const double *dinv, const VT *r, const int *pmap, const VT *ec,
+                         const int8_t *cf, VT *e0, VT *e1, hipStream_t s, Gate gate) {
+    need(A, "launch_relax_interp");
+    if (A.nb <= 0) return;
+    const int G = groups_for(A);
+    const unsigned grid = grid_rows(A.nb, G, A.bs);
+    NAIR_BS_DISPATCH(A.bs, k_relax_interp, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, dinv, A.nb, A.bs,
+                                                                      G, r, pmap, ec, cf, e0, e1, gate));
+    NAIR_HIP(hipGetLastError());
+}
+
 template <typename VT>
 void launch_restrict_T(const int *ptptr, const int *ptidx, const VT *sv, VT *sc, int nc, int bs, hipStream_t st,
                        Gate gate) {
@@ -789,9 +863,10 @@ void launch_seg_init(const double *part, const int *cptr, int nsys, double *bn, 
 void launch_seg_check(const double *part, const int *cptr, int nsys, const double *bn, const double *rtol,
                       int hist_cap, double *hist, double *last, int *active, int *status, int *iters, int *it,
                       int *nact, int *nact_acc, hipStream_t s) {
+    const int fused = nsys == 1 ? 1 : 0;
     k_seg_check<<<static_cast<unsigned>(nsys), 64, 0, s>>>(part, cptr, bn, rtol, hist_cap, hist, last, active, status,
-                                                           iters, it, nact_acc);
-    k_seg_tick<<<1, 64, 0, s>>>(0, it, nact, nact_acc);
+                                                           iters, it, nact, nact_acc, fused);
+    if (!fused) k_seg_tick<<<1, 64, 0, s>>>(0, it, nact, nact_acc);
     NAIR_HIP(hipGetLastError());
 }
 
@@ -810,6 +885,8 @@ void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s) {
                                        const int *, int, const int8_t *, int, hipStream_t, Gate);                    \
     template void launch_restrict<MT, VT>(const MatView<MT> &, const VT *, const int *, VT *, hipStream_t, Gate);    \
     template void launch_interp<VT>(const int *, const VT *, VT *, VT *, int, int, hipStream_t, Gate);               \
+    template void launch_relax_interp<MT, VT>(const MatView<MT> &, const double *, const VT *, const int *,          \
+                                              const VT *, const int8_t *, VT *, VT *, hipStream_t, Gate);            \
     template void launch_relax_T_first<VT>(const double *, const VT *, const int8_t *, VT *, VT *, int, int,         \
                                            hipStream_t, Gate);                                                       \
     template void launch_restrict_T<VT>(const int *, const int *, const VT *, VT *, int, int, hipStream_t, Gate);    \

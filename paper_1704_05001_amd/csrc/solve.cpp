@@ -85,7 +85,9 @@ const T *cycle(Hier &h, int l, bool fcyc, hipStream_t s) {
         launch_restrict<T, T>(S::Z(L), S::r(L), L.cpts.get(), S::r(C), s, gate(h, C));
     }
     const T *ec = coarse_solve<T>(h, l + 1, fcyc, s);
-    {
+    // on a small level the interpolation rides along with the first sweep
+    const bool fuse = few_lanes(L.A.nb, bs) && !L.face.on;
+    if (!fuse) {
         TimerScope ts(TK_INTERP, l, s);
         launch_interp<T>(L.pmap.get(), ec, S::e0(L), S::e1(L), L.A.nb, bs, s, gate(h, L));
     }
@@ -94,7 +96,14 @@ const T *cycle(Hier &h, int l, bool fcyc, hipStream_t s) {
     {
         // the nu sweeps run back to back; one event pair brackets the group
         TimerScope ts(TK_RELAX, l, s, h.prm.degree + 1);
-        for (int k = 0; k <= h.prm.degree; ++k) {
+        int k = 0;
+        if (fuse) {
+            launch_relax_interp<T, T>(A, L.dinv.get(), S::r(L), L.pmap.get(), ec, L.cf.get(), cur, oth, s,
+                                      gate(h, L));
+            std::swap(cur, oth);
+            k = 1;
+        }
+        for (; k <= h.prm.degree; ++k) {
             launch_relax<T, T>(A, L.dinv.get(), false, S::r(L), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s,
                                gate(h, L));
             std::swap(cur, oth);
