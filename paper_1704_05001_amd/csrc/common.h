@@ -115,7 +115,9 @@ int read_int(const int *dptr, hipStream_t s);       // synchronous D2H of one in
 void read_ints(const int *dptr, int *host, int n, hipStream_t s);
 
 // Exclusive scan of n ints: out[0..n], out[n] = total.  in may alias nothing in out.
-void scan_exclusive(const int *in, int *out, int n, hipStream_t s);
+// total_copy (nullable) receives the total too, so several totals can sit
+// side by side and come back to the host in one copy
+void scan_exclusive(const int *in, int *out, int n, hipStream_t s, int *total_copy = nullptr);
 
 // ---------------------------------------------------------- setup kernels
 void launch_block_maxabs(const double *vals, int64_t nnzb, int bs, double *out, hipStream_t s);

@@ -63,7 +63,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int *__restri
 
 // One block scans the tile sums in chunks of 256 with a running carry.
 __global__ __launch_bounds__(kScanThreads) void k_scan_tile_sums(int *__restrict__ tile_sums, int ntiles,
-                                                                int *__restrict__ grand_total) {
+                                                                int *__restrict__ grand_total,
+                                                                int *__restrict__ total_copy) {
     __shared__ int lds[kScanThreads / 64 + 1];
     int carry = 0;
     for (int c0 = 0; c0 < ntiles; c0 += kScanThreads) {
@@ -74,7 +75,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tile_sums(int *__restrict
         if (i < ntiles) tile_sums[i] = pre + carry;
         carry += total;
     }
-    if (threadIdx.x == 0) *grand_total = carry;
+    if (threadIdx.x == 0) {
+        *grand_total = carry;
+        if (total_copy) *total_copy = carry;
+    }
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_add(int *__restrict__ out, int n,
@@ -96,7 +100,7 @@ constexpr int kSmallStrips = 16;                                  // strips of 6
 constexpr int kSmallMax = kSmallWaves * kSmallStrips * 64;
 
 __global__ __launch_bounds__(kSmallThreads) void k_scan_small(const int *__restrict__ in, int *__restrict__ out,
-                                                             int n) {
+                                                             int n, int *__restrict__ total_copy) {
     __shared__ int wsum[kSmallWaves + 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -138,25 +142,29 @@ __global__ __launch_bounds__(kSmallThreads) void k_scan_small(const int *__restr
         if (i < n) out[i] = carry + x - v[j];
         carry += __shfl(x, 63, 64);
     }
-    if (threadIdx.x == 0) out[n] = wsum[kSmallWaves];
+    if (threadIdx.x == 0) {
+        out[n] = wsum[kSmallWaves];
+        if (total_copy) *total_copy = wsum[kSmallWaves];
+    }
 }
 
 }  // namespace
 
-void scan_exclusive(const int *in, int *out, int n, hipStream_t s) {
+void scan_exclusive(const int *in, int *out, int n, hipStream_t s, int *total_copy) {
     if (n <= 0) {
         NAIR_HIP(hipMemsetAsync(out, 0, sizeof(int), s));
+        if (total_copy) NAIR_HIP(hipMemsetAsync(total_copy, 0, sizeof(int), s));
         return;
     }
     if (n <= kSmallMax) {
-        k_scan_small<<<1, kSmallThreads, 0, s>>>(in, out, n);
+        k_scan_small<<<1, kSmallThreads, 0, s>>>(in, out, n, total_copy);
         NAIR_HIP(hipGetLastError());
         return;
     }
     const int ntiles = static_cast<int>((static_cast<int64_t>(n) + kScanTile - 1) / kScanTile);
     DBuf<int> tiles(ntiles);
     k_scan_tiles<<<ntiles, kScanThreads, 0, s>>>(in, out, n, tiles.get());
-    k_scan_tile_sums<<<1, kScanThreads, 0, s>>>(tiles.get(), ntiles, out + n);
+    k_scan_tile_sums<<<1, kScanThreads, 0, s>>>(tiles.get(), ntiles, out + n, total_copy);
     k_scan_add<<<ntiles, kScanThreads, 0, s>>>(out, n, tiles.get());
     NAIR_HIP(hipGetLastError());
     // `tiles` returns to the pool now; any later user of that memory is ordered after

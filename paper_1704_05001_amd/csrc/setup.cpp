@@ -40,8 +40,11 @@ void alloc_vectors(Level &L, int bs) {
     L.tmp.alloc(n);
 }
 
+// Device copies of the per-system offsets and modes (batches only: one
+// system's kernels never read them).
 void upload_systems(Level &L, hipStream_t s) {
     const int nsys = static_cast<int>(L.mode.size());
+    if (nsys == 1) return;
     if (!L.seg_d.get()) L.seg_d.alloc(nsys + 1);
     if (!L.mode_d.get()) L.mode_d.alloc(nsys);
     NAIR_HIP(hipMemcpyAsync(L.seg_d.get(), L.seg.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice, s));
@@ -259,6 +262,11 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         auto count_c = [&]() {
             launch_cf_flags(L.cf.get(), n, 1, cflag.get(), s);
             scan_exclusive(cflag.get(), cscan.get(), n, s);
+            if (nsys == 1) {   // one system: its C count is the scan's total
+                cseg[0] = 0;
+                read_many({{cscan.get() + n, &cseg[1]}, {sing.get(), &cseg[2]}}, s);
+                return;
+            }
             launch_gather_int(cscan.get(), L.seg_d.get(), nsys + 1, cseg_d.get(), s);
             NAIR_HIP(hipMemcpyAsync(cseg_d.get() + nsys + 1, sing.get(), sizeof(int), hipMemcpyDeviceToDevice, s));
             read_ints(cseg_d.get(), cseg.data(), nsys + 2, s);
@@ -323,15 +331,16 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         W0.ncols = n;
         W0.bs = bs;
         W0.rowptr.alloc(static_cast<size_t>(nc) + 1);
+        int tot[2] = {0, 0};   // blocks of T and of W_0, side by side for one copy
         {
-            DBuf<int> cntT(n), cntW(nc);
+            DBuf<int> cntT(n), cntW(nc), dtot(2);
             launch_count_T(L.A.rowptr.get(), L.A.colidx.get(), L.mask.get(), L.cf.get(), n, cntT.get(), s);
-            scan_exclusive(cntT.get(), T.rowptr.get(), n, s);
+            scan_exclusive(cntT.get(), T.rowptr.get(), n, s, dtot.get());
             launch_count_Acf(L.A.rowptr.get(), L.A.colidx.get(), L.cf.get(), L.cpts.get(), nc, cntW.get(), s);
-            scan_exclusive(cntW.get(), W0.rowptr.get(), nc, s);
+            scan_exclusive(cntW.get(), W0.rowptr.get(), nc, s, dtot.get() + 1);
+            read_ints(dtot.get(), tot, 2, s);
         }
-        int nT = 0, nW = 0;
-        read_many({{T.rowptr.get() + n, &nT}, {W0.rowptr.get() + nc, &nW}}, s);
+        const int nT = tot[0], nW = tot[1];
         T.nnzb = nT;
         T.colidx.alloc(nT);
         T.vals.alloc(static_cast<size_t>(nT) * bb);

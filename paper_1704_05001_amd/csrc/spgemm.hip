@@ -607,7 +607,8 @@ void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipSt
         return;
     }
     const int small_cap = kHashSmall / 2, large_cap = kHashLarge / 2;
-    DBuf<int> ub(m), cnt(m), big_list(m), flags(2), prow(static_cast<size_t>(m) + 1);
+    // flags: big-row count, too-dense row, then the scans' totals (nnz, pairs), read in one copy
+    DBuf<int> ub(m), cnt(m), big_list(m), flags(4), prow(static_cast<size_t>(m) + 1);
     NAIR_HIP(hipMemsetAsync(flags.get(), 0, sizeof(int) * 2, s));
     int *big_count = flags.get(), *too_dense = flags.get() + 1;
     k_row_upper_bound<<<grid_for(m, 256), 256, 0, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(), m,
@@ -624,13 +625,12 @@ void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipSt
                                                      cnt.get(), nullptr, nullptr, ub.get());
     }
     NAIR_HIP(hipGetLastError());
-    scan_exclusive(cnt.get(), C.rowptr.get(), m, s);
-    scan_exclusive(ub.get(), prow.get(), m, s);
-    int hflags[2] = {0, 0}, nnz = 0, npairs = 0;
-    NAIR_HIP(hipMemcpyAsync(hflags, flags.get(), sizeof(int) * 2, hipMemcpyDeviceToHost, s));
-    NAIR_HIP(hipMemcpyAsync(&nnz, C.rowptr.get() + m, sizeof(int), hipMemcpyDeviceToHost, s));
-    NAIR_HIP(hipMemcpyAsync(&npairs, prow.get() + m, sizeof(int), hipMemcpyDeviceToHost, s));
+    scan_exclusive(cnt.get(), C.rowptr.get(), m, s, flags.get() + 2);
+    scan_exclusive(ub.get(), prow.get(), m, s, flags.get() + 3);
+    int hflags[4] = {0, 0, 0, 0};
+    NAIR_HIP(hipMemcpyAsync(hflags, flags.get(), sizeof(hflags), hipMemcpyDeviceToHost, s));
     NAIR_HIP(hipStreamSynchronize(s));
+    const int nnz = hflags[2], npairs = hflags[3];
     if (hflags[1] > 0)
         fail(NAIR_ENOMEM, "sparse product row has " + std::to_string(hflags[1]) + " candidate blocks (limit " +
                               std::to_string(large_cap) + ")");
@@ -692,20 +692,20 @@ void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevB
     const int m = RA.nb;
     const int bs = RA.bs;
     const int bb = bs * bs;
-    DBuf<int> cnt(m), ccnt(m), krp(static_cast<size_t>(m) + 1), crow(static_cast<size_t>(m) + 1), flags(1);
+    // flags: too-dense row, then the scans' totals (blocks, contributions), read in one copy
+    DBuf<int> cnt(m), ccnt(m), krp(static_cast<size_t>(m) + 1), crow(static_cast<size_t>(m) + 1), flags(3);
     NAIR_HIP(hipMemsetAsync(flags.get(), 0, sizeof(int), s));
     const unsigned gs = cap_grid((m + 3) / 4);
     k_rap_symbolic<<<gs, 256, 0, s>>>(RA.rowptr.get(), RA.colidx.get(), pmap, m, 0, cnt.get(), nullptr, nullptr,
                                       flags.get());
     k_rap_count_contrib<<<grid_for(m, 256), 256, 0, s>>>(RA.rowptr.get(), RA.colidx.get(), pmap, m, ccnt.get());
     NAIR_HIP(hipGetLastError());
-    scan_exclusive(cnt.get(), krp.get(), m, s);
-    scan_exclusive(ccnt.get(), crow.get(), m, s);
-    int too_dense = 0, nnz = 0, ncontrib = 0;
-    NAIR_HIP(hipMemcpyAsync(&too_dense, flags.get(), sizeof(int), hipMemcpyDeviceToHost, s));
-    NAIR_HIP(hipMemcpyAsync(&nnz, krp.get() + m, sizeof(int), hipMemcpyDeviceToHost, s));
-    NAIR_HIP(hipMemcpyAsync(&ncontrib, crow.get() + m, sizeof(int), hipMemcpyDeviceToHost, s));
+    scan_exclusive(cnt.get(), krp.get(), m, s, flags.get() + 1);
+    scan_exclusive(ccnt.get(), crow.get(), m, s, flags.get() + 2);
+    int hflags[3] = {0, 0, 0};
+    NAIR_HIP(hipMemcpyAsync(hflags, flags.get(), sizeof(hflags), hipMemcpyDeviceToHost, s));
     NAIR_HIP(hipStreamSynchronize(s));
+    const int too_dense = hflags[0], nnz = hflags[1], ncontrib = hflags[2];
     if (too_dense > 0)
         fail(NAIR_ENOMEM, "Galerkin row has " + std::to_string(too_dense) + " blocks (limit " +
                               std::to_string(kHashSmall / 2) + ")");
