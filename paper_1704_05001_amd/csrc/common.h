@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <initializer_list>
 #include <string>
 #include <vector>
 
@@ -111,7 +112,15 @@ inline unsigned grid_for(int64_t n, int per_block) {
     return static_cast<unsigned>(g);
 }
 
-int read_int(const int *dptr, hipStream_t s);       // synchronous D2H of one int
+// Synchronous device-to-host reads (small ones staged through pinned memory;
+// several items share one synchronisation).
+struct ReadItem {
+    const void *dev;
+    void *host;
+    size_t bytes;
+};
+void read_device(std::initializer_list<ReadItem> items, hipStream_t s);
+int read_int(const int *dptr, hipStream_t s);
 void read_ints(const int *dptr, int *host, int n, hipStream_t s);
 
 // Exclusive scan of n ints: out[0..n], out[n] = total.  in may alias nothing in out.

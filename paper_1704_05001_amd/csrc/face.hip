@@ -130,8 +130,7 @@ void build_face(const DevBSR &A, FaceCopy &F, hipStream_t s) {
                                                   maxrc.get());
     NAIR_HIP(hipGetLastError());
     int rc2[2] = {0, 0};
-    NAIR_HIP(hipMemcpyAsync(rc2, maxrc.get(), sizeof(rc2), hipMemcpyDeviceToHost, s));
-    NAIR_HIP(hipStreamSynchronize(s));
+    read_ints(maxrc.get(), rc2, 2, s);
     const int rmax = rc2[0], cmax = rc2[1];
     if (2 * rmax * cmax > bs * bs) return;   // the rectangles would hold more than half a block
     F.rmax = rmax;

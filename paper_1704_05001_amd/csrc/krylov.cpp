@@ -31,8 +31,7 @@ void ensure_krylov(Hier &h, int m, int64_t n) {
 }
 
 void read_doubles(const double *d, double *hst, int cnt, hipStream_t s) {
-    NAIR_HIP(hipMemcpyAsync(hst, d, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
-    NAIR_HIP(hipStreamSynchronize(s));
+    read_device({{d, hst, sizeof(double) * static_cast<size_t>(cnt)}}, s);
 }
 
 }  // namespace

@@ -2,6 +2,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstring>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -173,16 +175,58 @@ void timer_read(int64_t *launches, double *total_ms) {
     T.total_ms = 0.0;
 }
 
+namespace {
+
+// Small device-to-host reads go through one pinned staging buffer: a copy
+// into pageable memory is staged and waited for one by one, a copy into
+// pinned memory is a plain transfer the stream runs in order.
+constexpr size_t kStageBytes = 64 * 1024;
+
+struct Stage {
+    std::mutex mu;
+    char *buf = nullptr;
+};
+
+Stage &stage() {
+    static Stage st;
+    return st;
+}
+
+}  // namespace
+
+void read_device(std::initializer_list<ReadItem> items, hipStream_t s) {
+    size_t total = 0;
+    for (const ReadItem &it : items) total += (it.bytes + 7) & ~static_cast<size_t>(7);
+    if (total > kStageBytes) {   // large reads copy directly
+        for (const ReadItem &it : items)
+            if (it.bytes) NAIR_HIP(hipMemcpyAsync(it.host, it.dev, it.bytes, hipMemcpyDeviceToHost, s));
+        NAIR_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    Stage &st = stage();
+    std::lock_guard<std::mutex> lk(st.mu);
+    if (!st.buf) NAIR_HIP(hipHostMalloc(reinterpret_cast<void **>(&st.buf), kStageBytes, hipHostMallocPortable));
+    size_t off = 0;
+    for (const ReadItem &it : items) {
+        if (it.bytes) NAIR_HIP(hipMemcpyAsync(st.buf + off, it.dev, it.bytes, hipMemcpyDeviceToHost, s));
+        off += (it.bytes + 7) & ~static_cast<size_t>(7);
+    }
+    NAIR_HIP(hipStreamSynchronize(s));
+    off = 0;
+    for (const ReadItem &it : items) {
+        if (it.bytes) std::memcpy(it.host, st.buf + off, it.bytes);
+        off += (it.bytes + 7) & ~static_cast<size_t>(7);
+    }
+}
+
 int read_int(const int *dptr, hipStream_t s) {
     int v = 0;
-    NAIR_HIP(hipMemcpyAsync(&v, dptr, sizeof(int), hipMemcpyDeviceToHost, s));
-    NAIR_HIP(hipStreamSynchronize(s));
+    read_device({{dptr, &v, sizeof(int)}}, s);
     return v;
 }
 
 void read_ints(const int *dptr, int *host, int n, hipStream_t s) {
-    NAIR_HIP(hipMemcpyAsync(host, dptr, sizeof(int) * n, hipMemcpyDeviceToHost, s));
-    NAIR_HIP(hipStreamSynchronize(s));
+    read_device({{dptr, host, sizeof(int) * static_cast<size_t>(n)}}, s);
 }
 
 }  // namespace nair

@@ -27,11 +27,6 @@ constexpr int kRoundBatch = 4;
 constexpr int kMaxRounds = 4096;
 constexpr int kNoSingular = 0x7f7f7f7f;   // memset(0x7f) pattern
 
-void read_many(std::initializer_list<std::pair<const int *, int *>> items, hipStream_t s) {
-    for (auto &it : items) NAIR_HIP(hipMemcpyAsync(it.second, it.first, sizeof(int), hipMemcpyDeviceToHost, s));
-    NAIR_HIP(hipStreamSynchronize(s));
-}
-
 void alloc_vectors(Level &L, int bs) {
     const size_t n = static_cast<size_t>(L.A.nb) * bs;
     L.r.alloc(n);
@@ -264,7 +259,7 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
             scan_exclusive(cflag.get(), cscan.get(), n, s);
             if (nsys == 1) {   // one system: its C count is the scan's total
                 cseg[0] = 0;
-                read_many({{cscan.get() + n, &cseg[1]}, {sing.get(), &cseg[2]}}, s);
+                read_device({{cscan.get() + n, &cseg[1], sizeof(int)}, {sing.get(), &cseg[2], sizeof(int)}}, s);
                 return;
             }
             launch_gather_int(cscan.get(), L.seg_d.get(), nsys + 1, cseg_d.get(), s);

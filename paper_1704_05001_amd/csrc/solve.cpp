@@ -402,8 +402,7 @@ nair_status run_solve_batch(Hier &h, bool trans, const double *b, double *x, dou
             else run_iteration(h, trans, b, x, s);
         }
         done += run;
-        NAIR_HIP(hipMemcpyAsync(last.data(), B.last.get(), sizeof(double) * nsys, hipMemcpyDeviceToHost, s));
-        nact = read_int(B.nact.get(), s);
+        read_device({{B.last.get(), last.data(), sizeof(double) * nsys}, {B.nact.get(), &nact, sizeof(int)}}, s);
         if (nact == 0 || done >= max_iter) break;
         // iterations still needed by the slowest system, from its rate over the last run
         double need = 1.0;
@@ -423,16 +422,13 @@ nair_status run_solve_batch(Hier &h, bool trans, const double *b, double *x, dou
         run = std::max(1, static_cast<int>(std::min(std::floor(kAim * need), cap)));
     }
 
+    // status, iteration counts and histories in one read
     std::vector<int> st(nsys), it(nsys);
-    read_ints(B.status.get(), st.data(), nsys, s);
-    read_ints(B.iters.get(), it.data(), nsys, s);
-    int itmax = 0;
-    for (int k = 0; k < nsys; ++k) itmax = std::max(itmax, it[k]);
     std::vector<double> hist(static_cast<size_t>(nsys) * B.hist_cap);
-    if (itmax > 0) {
-        NAIR_HIP(hipMemcpyAsync(hist.data(), B.hist.get(), sizeof(double) * hist.size(), hipMemcpyDeviceToHost, s));
-        NAIR_HIP(hipStreamSynchronize(s));
-    }
+    read_device({{B.status.get(), st.data(), sizeof(int) * nsys},
+                 {B.iters.get(), it.data(), sizeof(int) * nsys},
+                 {B.hist.get(), hist.data(), sizeof(double) * hist.size()}},
+                s);
     B.hist_host.assign(nsys, {});
     nair_status worst = NAIR_OK;
     for (int k = 0; k < nsys; ++k) {

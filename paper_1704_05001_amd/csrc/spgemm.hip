@@ -628,8 +628,7 @@ void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipSt
     scan_exclusive(cnt.get(), C.rowptr.get(), m, s, flags.get() + 2);
     scan_exclusive(ub.get(), prow.get(), m, s, flags.get() + 3);
     int hflags[4] = {0, 0, 0, 0};
-    NAIR_HIP(hipMemcpyAsync(hflags, flags.get(), sizeof(hflags), hipMemcpyDeviceToHost, s));
-    NAIR_HIP(hipStreamSynchronize(s));
+    read_ints(flags.get(), hflags, 4, s);
     const int nnz = hflags[2], npairs = hflags[3];
     if (hflags[1] > 0)
         fail(NAIR_ENOMEM, "sparse product row has " + std::to_string(hflags[1]) + " candidate blocks (limit " +
@@ -703,8 +702,7 @@ void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevB
     scan_exclusive(cnt.get(), krp.get(), m, s, flags.get() + 1);
     scan_exclusive(ccnt.get(), crow.get(), m, s, flags.get() + 2);
     int hflags[3] = {0, 0, 0};
-    NAIR_HIP(hipMemcpyAsync(hflags, flags.get(), sizeof(hflags), hipMemcpyDeviceToHost, s));
-    NAIR_HIP(hipStreamSynchronize(s));
+    read_ints(flags.get(), hflags, 3, s);
     const int too_dense = hflags[0], nnz = hflags[1], ncontrib = hflags[2];
     if (too_dense > 0)
         fail(NAIR_ENOMEM, "Galerkin row has " + std::to_string(too_dense) + " blocks (limit " +
