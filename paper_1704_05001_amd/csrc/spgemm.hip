@@ -480,6 +480,54 @@ __global__ __launch_bounds__(256) void k_spgemm_pairs(int64_t nnz, int bs_rt, co
     }
 }
 
+// The same products on the matrix cores (bs <= 16): one wave per output block
+// holds it in a 16x16 FP64 MFMA accumulator (entry (i, j) in lane j + 16 (i%4),
+// register i/4); each pair contributes ceil(bs/4) 16x16x4 steps over c = 4q ..
+// 4q+3, zero beyond bs.  A 16x16x4 FP64 step updates each entry as the fma
+// chain over its four c in ascending order, so the sums are the same, bit for
+// bit, as the per-thread chains (padding adds exact zeros); identity pairs add
+// Y's entries plainly, in their place in the pair order.
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+template <int BS>
+__global__ __launch_bounds__(256) void k_spgemm_mfma(int64_t nnz, const int *__restrict__ pairptr,
+                                                    const int2 *__restrict__ pairs, const double *__restrict__ X,
+                                                    const double *__restrict__ Y, double *__restrict__ C) {
+    constexpr int bb = BS * BS;
+    constexpr int KQ = (BS + 3) / 4;
+    const int lane = threadIdx.x & 63;
+    const int row = lane & 15, kk = lane >> 4;   // A: row i, B: column j; both k = kk
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (t >= nnz) return;   // whole waves
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k = pairptr[t]; k < pairptr[t + 1]; ++k) {
+        const int2 pr = pairs[k];
+        const double *y = Y + static_cast<int64_t>(pr.y) * bb;
+        if (pr.x < 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = kk + 4 * r;
+                if (i < BS && row < BS) acc[r] = acc[r] + y[i * BS + row];
+            }
+        } else {
+            const double *x = X + static_cast<int64_t>(pr.x) * bb;
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) {
+                const int c = 4 * q + kk;
+                const double av = (row < BS && c < BS) ? x[row * BS + c] : 0.0;
+                const double bv = (row < BS && c < BS) ? y[c * BS + row] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            }
+        }
+    }
+    double *out = C + t * bb;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = kk + 4 * r;
+        if (i < BS && row < BS) out[i * BS + row] = acc[r];
+    }
+}
+
 // ---------------------------------------------------- Galerkin merge lists
 
 __global__ __launch_bounds__(256) void k_rap_count_contrib(const int *__restrict__ rarp, const int *__restrict__ racol,
@@ -656,8 +704,17 @@ void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipSt
     const int64_t total = static_cast<int64_t>(nnz) * bs;
     const unsigned grid = cap_grid((total + 255) / 256);
     TimerScope ts(TK_SPGEMM_NUM, g_timer_level, s);
-    NAIR_BS_DISPATCH(bs, k_spgemm_pairs, <<<grid, 256, 0, s>>>(nnz, bs, pairptr.get(), pairs.get(), X.vals.get(),
-                                                               Y.vals.get(), C.vals.get()));
+    const unsigned mgrid = static_cast<unsigned>((static_cast<int64_t>(nnz) + 3) / 4);   // four waves per workgroup
+    if (bs == 9) {
+        k_spgemm_mfma<9><<<mgrid, 256, 0, s>>>(nnz, pairptr.get(), pairs.get(), X.vals.get(), Y.vals.get(),
+                                               C.vals.get());
+    } else if (bs == 16) {
+        k_spgemm_mfma<16><<<mgrid, 256, 0, s>>>(nnz, pairptr.get(), pairs.get(), X.vals.get(), Y.vals.get(),
+                                                C.vals.get());
+    } else {
+        NAIR_BS_DISPATCH(bs, k_spgemm_pairs, <<<grid, 256, 0, s>>>(nnz, bs, pairptr.get(), pairs.get(), X.vals.get(),
+                                                                   Y.vals.get(), C.vals.get()));
+    }
     NAIR_HIP(hipGetLastError());
 }
 
