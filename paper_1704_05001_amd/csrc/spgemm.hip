@@ -500,24 +500,51 @@ __global__ __launch_bounds__(256) void k_spgemm_mfma(int64_t nnz, const int *__r
     const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (t >= nnz) return;   // whole waves
     double4_t acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k = pairptr[t]; k < pairptr[t + 1]; ++k) {
-        const int2 pr = pairs[k];
+    // operands of one pair: A and B fragments per step, or Y's entries for an
+    // identity pair; the next pair's load while this pair's steps run
+    struct Frag {
+        double a[KQ], b[KQ];
+        bool ident;
+    };
+    auto load = [&](const int2 pr) {
+        Frag f;
         const double *y = Y + static_cast<int64_t>(pr.y) * bb;
-        if (pr.x < 0) {
+        f.ident = pr.x < 0;
+        if (f.ident) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = kk + 4 * r;
-                if (i < BS && row < BS) acc[r] = acc[r] + y[i * BS + row];
+            for (int q = 0; q < KQ; ++q) {   // reuse a[] for Y's entries (i, row), i = kk + 4q
+                const int i = kk + 4 * q;
+                f.a[q] = (i < BS && row < BS) ? y[i * BS + row] : 0.0;
+                f.b[q] = 0.0;
             }
         } else {
             const double *x = X + static_cast<int64_t>(pr.x) * bb;
 #pragma unroll
             for (int q = 0; q < KQ; ++q) {
                 const int c = 4 * q + kk;
-                const double av = (row < BS && c < BS) ? x[row * BS + c] : 0.0;
-                const double bv = (row < BS && c < BS) ? y[c * BS + row] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                f.a[q] = (row < BS && c < BS) ? x[row * BS + c] : 0.0;
+                f.b[q] = (row < BS && c < BS) ? y[c * BS + row] : 0.0;
             }
+        }
+        return f;
+    };
+    const int k0 = pairptr[t], k1 = pairptr[t + 1];
+    if (k0 < k1) {
+        Frag cur = load(pairs[k0]);
+        for (int k = k0; k < k1; ++k) {
+            Frag nxt = cur;
+            if (k + 1 < k1) nxt = load(pairs[k + 1]);
+            if (cur.ident) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = kk + 4 * r;
+                    if (r < KQ && i < BS && row < BS) acc[r] = acc[r] + cur.a[r];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < KQ; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.a[q], cur.b[q], acc, 0, 0, 0);
+            }
+            cur = nxt;
         }
     }
     double *out = C + t * bb;
