@@ -568,6 +568,43 @@ __global__ __launch_bounds__(256) void k_block_product(int64_t n, int bs_rt, con
     }
 }
 
+// The same on the FP64 matrix cores (bs 9 and 16): one wave per block, the
+// product in a 16x16 accumulator (entry (i, j) in lane j + 16 (i%4), register
+// i/4) built by ceil(bs/4) 16x16x4 steps, each the ascending fma chain over its
+// four inner indices, from +0; then the sign.  Bit-identical to the chain above.
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+template <int BS>
+__global__ __launch_bounds__(256) void k_block_product_mfma(int64_t n, const double *__restrict__ X,
+                                                           const int *__restrict__ xi, const double *__restrict__ Y,
+                                                           const int *__restrict__ yi, double sign,
+                                                           double *__restrict__ out) {
+    constexpr int bb = BS * BS;
+    constexpr int KQ = (BS + 3) / 4;
+    const int lane = threadIdx.x & 63;
+    const int row = lane & 15, kk = lane >> 4;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (t >= n) return;   // whole waves
+    const double *x = X + static_cast<int64_t>(xi ? xi[t] : t) * bb;
+    const double *y = Y + static_cast<int64_t>(yi[t]) * bb;
+    double a[KQ], b[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+        const int c = 4 * q + kk;
+        a[q] = (row < BS && c < BS) ? x[row * BS + c] : 0.0;
+        b[q] = (row < BS && c < BS) ? y[c * BS + row] : 0.0;
+    }
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc, 0, 0, 0);
+    double *o = out + t * bb;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = kk + 4 * r;
+        if (i < BS && row < BS) o[i * BS + row] = sign * acc[r];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_block_gather(int64_t n, int bb, const double *__restrict__ Y,
                                                      const int *__restrict__ src, double *__restrict__ out) {
     const int64_t total = n * bb;
@@ -704,6 +741,13 @@ void launch_fill_Acf(const int *rowptr, const int *colidx, const int8_t *cf, con
 void launch_block_product(int64_t n, int bs, const double *X, const int *xi, const double *Y, const int *yi,
                           double sign, double *out, hipStream_t s) {
     if (n <= 0) return;
+    if (bs == 9 || bs == 16) {
+        const unsigned mgrid = static_cast<unsigned>((n + 3) / 4);   // four waves (blocks) per workgroup
+        if (bs == 9) k_block_product_mfma<9><<<mgrid, 256, 0, s>>>(n, X, xi, Y, yi, sign, out);
+        else k_block_product_mfma<16><<<mgrid, 256, 0, s>>>(n, X, xi, Y, yi, sign, out);
+        NAIR_HIP(hipGetLastError());
+        return;
+    }
     const unsigned grid = cap_grid((n * bs + 255) / 256);
     switch (bs) {
         case 4: k_block_product<4><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out); break;
