@@ -65,10 +65,13 @@ def measured_traffic(workload: str, grid_threads: int):
 
 def relax_level_bytes(lv: dict) -> dict:
     """Algorithmic HBM bytes of one F-relaxation sweep on a level: each operand
-    read once, each output written once (int32 indices, FP64 values).  With a
-    face-compressed copy the sweep reads a diagonal block whole and, of an
-    off-diagonal block, the entries on its nonzero rows and columns; every
-    block's 8-byte row/column masks."""
+    read once, each output written once (int32 indices, FP64 values).  The
+    sweep e_I = D_I^-1 (r_I - sum_{J != I} A_IJ e_J) reads every off-diagonal
+    block of an F row (from A, where the diagonal block's column index and
+    masks are read too, or from the level's sweep copy, which holds only the
+    off-diagonal blocks); of e, the entries those blocks multiply, each once.
+    With face rectangles an off-diagonal block costs the entries on its
+    nonzero rows and columns plus its 8-byte row/column masks."""
     import numpy as np
     rp = lv["rowptr"].cpu().numpy().astype(np.int64)
     cf = lv["cf"].cpu().numpy()
@@ -78,23 +81,29 @@ def relax_level_bytes(lv: dict) -> dict:
     F = cf == 0
     nF = int(F.sum())
     nnzF = int(rowlen[F].sum())
-    n = lv["nb"] * bs
+    rows = np.repeat(np.arange(lv["nb"]), rowlen)
+    ci = lv["colidx"].cpu().numpy()
+    inF = F[rows]
+    diag = ci == rows
+    off = inF & ~diag
+    copy = lv.get("sweep_nnzb", -1) >= 0
     if lv.get("face_meta") is not None:
-        rows = np.repeat(np.arange(lv["nb"]), rowlen)
-        inF = F[rows]
-        diag = lv["colidx"].cpu().numpy() == rows
         meta = lv["face_meta"].cpu().numpy().view(np.uint64)
         nr = np.bitwise_count(meta & np.uint64(0xFFFFFFFF)).astype(np.int64)
         nc = np.bitwise_count(meta >> np.uint64(32)).astype(np.int64)
-        # (the sweep loads every block's masks, the diagonal's too)
-        bytes_A = int((inF & diag).sum()) * (bb * 8 + 12) + int((12 + 8 * nr * nc)[inF & ~diag].sum())
+        bytes_A = (0 if copy else nF * 12) + int((12 + 8 * nr * nc)[off].sum())
+        # e entries needed: per neighbour J, the union of its blocks' nonzero columns
+        cm = np.zeros(lv["nb"], dtype=np.uint64)
+        np.bitwise_or.at(cm, ci[off], meta[off] >> np.uint64(32))
+        bytes_e = int(np.bitwise_count(cm).astype(np.int64).sum()) * 8
     else:
-        bytes_A = nnzF * (bb * 8 + 4)      # F rows of A (values + column indices)
+        bytes_A = (0 if copy else nF * 4) + int(off.sum()) * (bb * 8 + 4)   # off-diagonal blocks (+ diagonal's index)
+        bytes_e = len(np.unique(ci[off])) * bs * 8
     bytes_D = nF * bb * 8                  # D_F^{-1}
     bytes_idx = nF * 4 + nF * 8            # F list, rowptr pairs
-    bytes_vec = n * 8 + nF * bs * 8 * 2    # e_in (gathered, read once), r_F, e_out_F
+    bytes_vec = bytes_e + nF * bs * 8 * 2  # e gathered (each needed entry once), r_F, e_out_F
     return dict(bytes=bytes_A + bytes_D + bytes_idx + bytes_vec, nF=nF, nnzF=nnzF,
-                bytes_true_blocks=bytes_A + bytes_D)
+                bytes_true_blocks=bytes_A + bytes_D, sweep_copy=copy)
 
 
 def restrict_level_bytes(lv: dict) -> int:

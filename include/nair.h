@@ -93,6 +93,15 @@ typedef struct {
                                  used when the rectangles hold at most half a block.  Only exact
                                  zeros are left out: results are bit-identical to faces = 0 for
                                  finite vectors.  Block form only. */
+    int32_t sweep_copy;       /* -1 (default): levels whose sweeps occupy at least 32768 lanes (block
+                                 rows x bs) keep a second copy of their F rows, in F-list order and
+                                 without the diagonal blocks, with D_F^{-1} in the same order (and
+                                 the same for A^T once a transposed solve needs it), and the Jacobi
+                                 F sweeps read that contiguously; 0: no copies; 1: every level that
+                                 relaxes.  The sweep computes D_I^{-1}(r_I - sum_{J != I} A_IJ e_J)
+                                 either way; with one lane group per row (nair_params.tuning) the
+                                 results are bit-identical with and without copies.  Costs about
+                                 the F rows' share of each selected operator in memory. */
 } nair_params;
 
 typedef struct {
@@ -137,6 +146,8 @@ typedef struct {
                                       bit-exact with the reference arithmetic either way; the counts
                                       show how close they came to flipping.  A batch counts the rows of
                                       systems solved directly on the level too. */
+    int32_t sweep_nnzb;            /* blocks held by the level's sweep copy of A (nair_params.sweep_copy),
+                                      -1 when its F sweeps read A itself */
 } nair_level_view;
 
 /* Fill *p with the defaults (degree 1, theta 0.25, phi 0.025, drop 1e-3, F

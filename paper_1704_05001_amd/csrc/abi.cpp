@@ -75,6 +75,7 @@ nair_status nair_default_params(nair_params *p) {
     p->cycle = 0;
     p->gmres = 0;
     p->faces = 1;
+    p->sweep_copy = -1;
     return NAIR_OK;
 }
 
@@ -98,6 +99,7 @@ static nair_status setup_common(int32_t nsys, const int32_t *sys_nb, int32_t nb,
     if (p->form != 0 && p->form != 1) return bad(nullptr, "form must be 0 (block) or 1 (scalar after scaling)");
     if (p->cycle != 0 && p->cycle != 1) return bad(nullptr, "cycle must be 0 (V) or 1 (F)");
     if (p->faces != 0 && p->faces != 1) return bad(nullptr, "faces must be 0 or 1");
+    if (p->sweep_copy < -1 || p->sweep_copy > 1) return bad(nullptr, "sweep_copy must be -1, 0 or 1");
     if (p->gmres < 0 || p->gmres > nair::kMaxGmres)
         return bad(nullptr, "gmres must be 0 (stationary iteration) or a restart length in [1, 200]");
     if (p->max_levels < 1 || p->max_levels > nair::kMaxLevels) return bad(nullptr, "max_levels must be in [1, 64]");
@@ -310,6 +312,10 @@ nair_status nair_get_level(nair_hier h, int32_t lvl, nair_level_view *v) {
     if (L.margin.get() &&
         hipMemcpy(v->margin, L.margin.get(), sizeof(v->margin), hipMemcpyDeviceToHost) != hipSuccess)
         return bad(h, "reading the decision-margin counts failed");
+    v->sweep_nnzb = -1;
+    if (L.sweep.on && hipMemcpy(&v->sweep_nnzb, L.sweep.rowptr.get() + L.sweep.nF, sizeof(int32_t),
+                                hipMemcpyDeviceToHost) != hipSuccess)
+        return bad(h, "reading the sweep copy's size failed");
     if (L.face.on) {
         v->face_rmax = L.face.rmax;
         v->face_cmax = L.face.cmax;

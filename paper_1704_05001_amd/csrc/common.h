@@ -225,6 +225,38 @@ struct FaceView {
     int cmax = 0, rc = 0;
 };
 
+// ----------------------------------------------------------- sweep copy
+// What a Jacobi F sweep reads, stored in the order it reads it: the F rows of
+// a level operator (or of its transpose) in F-list order, each without its
+// diagonal block, and D_F^{-1} in the same order.  Row f (the F list's f-th
+// row) holds blocks rowptr[f] .. rowptr[f+1]-1 in the row's ascending column
+// order: whole [bs][bs] blocks, or, where the operator has a face-compressed
+// copy (rc > 0), that copy's masks and rmax x cmax rectangles.  Storage for
+// vals and colidx is sized by the operator's block count (the exact count is
+// rowptr[nF] on the device; nothing is read back).
+struct SweepCopy {
+    bool on = false;
+    int nF = 0, cmax = 0, rc = 0;
+    int64_t cap = 0;                 // blocks allocated
+    DBuf<int> rowptr, colidx;
+    DBuf<uint64_t> meta;
+    DBuf<double> vals, dinv;
+    DBuf<float> vals32;
+};
+// Build S from A (and its face copy F when F.on) for the rows of flist.
+void build_sweep(const DevBSR &A, const FaceCopy &F, const double *dinv, const int *flist, int nF, SweepCopy &S,
+                 hipStream_t s);
+void sweep_to_float(SweepCopy &S, int bs, hipStream_t s);
+
+template <typename MT>
+struct SweepView {
+    const int *rowptr = nullptr, *colidx = nullptr;
+    const uint64_t *meta = nullptr;   // face rectangles when non-null
+    const MT *vals = nullptr;
+    const double *dinv = nullptr;
+    int cmax = 0, rc = 0;
+};
+
 // ------------------------------------------------------------------ cycle
 // Read-only view of a BSR matrix with values of type MT (double, or float for
 // the FP32-stored hierarchy), optionally with its face-compressed copy.
@@ -236,6 +268,7 @@ struct MatView {
     const MT *vals = nullptr;
     int groups = 0;   // lane groups per block row for the kernel reading it (0: from the row length)
     FaceView<MT> face{};
+    SweepView<MT> sweep{};   // F sweeps over the F list read this when rowptr != null
     MatView with_groups(int g) const {
         MatView v = *this;
         v.groups = g;

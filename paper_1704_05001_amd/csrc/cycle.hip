@@ -53,16 +53,21 @@ struct PmapSrc {
         return p >= 0 ? ec + static_cast<int64_t>(p) * bs : nullptr;
     }
 };
-// sum over blocks t = lo+g, lo+g+G, ... < hi of (block t row a) . x[col t]
-template <int BS, typename MT, typename VT, typename SRC>
+// sum over blocks t = lo+g, lo+g+G, ... < hi of (block t row a) . x[col t];
+// with SKIP, the block in column `skip` (the row's diagonal block) is left out.
+template <int BS, typename MT, typename VT, typename SRC, bool SKIP = false>
 __device__ inline double row_part_src(const int *__restrict__ colidx, const MT *__restrict__ vals, int lo, int hi,
-                                      int g, int G, int a, int bs_rt, const SRC &src) {
+                                      int g, int G, int a, int bs_rt, const SRC &src, int skip = -1) {
     const int bs = Bs<BS>::get(bs_rt);
     const int64_t bb = static_cast<int64_t>(bs) * bs;
     double acc0 = 0.0, acc1 = 0.0;
     for (int t = lo + g; t < hi; t += G) {
         const MT *blk = vals + t * bb + a * bs;
-        const VT *xj = src.row(colidx[t]);
+        const int J = colidx[t];
+        if constexpr (SKIP) {
+            if (J == skip) continue;
+        }
+        const VT *xj = src.row(J);
         if constexpr (SRC::kMaySkip) {
             if (xj == nullptr) continue;
         }
@@ -80,19 +85,20 @@ __device__ inline double row_part_src(const int *__restrict__ colidx, const MT *
     return acc0 + acc1;
 }
 
-template <int BS, typename MT, typename VT>
+template <int BS, typename MT, typename VT, bool SKIP = false>
 __device__ inline double row_part(const int *__restrict__ colidx, const MT *__restrict__ vals, int lo, int hi, int g,
-                                  int G, int a, int bs_rt, const VT *__restrict__ x) {
-    return row_part_src<BS, MT, VT>(colidx, vals, lo, hi, g, G, a, bs_rt, PlainSrc<VT>{x, Bs<BS>::get(bs_rt)});
+                                  int G, int a, int bs_rt, const VT *__restrict__ x, int skip = -1) {
+    return row_part_src<BS, MT, VT, PlainSrc<VT>, SKIP>(colidx, vals, lo, hi, g, G, a, bs_rt,
+                                                        PlainSrc<VT>{x, Bs<BS>::get(bs_rt)}, skip);
 }
 
 // The same row product over a face-compressed copy: the diagonal block whole
-// (from dvals), an off-diagonal block only when row a is one of its nonzero
-// rows, and then only over its nonzero columns.  The entries left out are
-// exact zeros and every product kept goes to the accumulator row_part gives
-// it (column parity), in the same order, so for finite x the result equals
-// row_part's bit for bit.
-template <int BS, typename MT, typename VT>
+// (from dvals; left out with SKIP), an off-diagonal block only when row a is
+// one of its nonzero rows, and then only over its nonzero columns.  The
+// entries left out are exact zeros and every product kept goes to the
+// accumulator row_part gives it (column parity), in the same order, so for
+// finite x the result equals row_part's bit for bit.
+template <int BS, typename MT, typename VT, bool SKIP = false>
 __device__ inline double row_part_face(const int *__restrict__ colidx, const FaceView<MT> &F, int lo, int hi, int g,
                                        int G, int a, int I, int bs_rt, const VT *__restrict__ x) {
     const int bs = Bs<BS>::get(bs_rt);
@@ -113,6 +119,12 @@ __device__ inline double row_part_face(const int *__restrict__ colidx, const Fac
         }
         const VT *xj = x + static_cast<int64_t>(J) * bs;
         if (J == I) {
+            if constexpr (SKIP) {
+                if (tn >= hi) break;
+                J = Jn;
+                m = mn;
+                continue;
+            }
             const MT *blk = F.dvals + static_cast<int64_t>(I) * bb + a * bs;
             if constexpr (BS > 0) {
 #pragma unroll
@@ -143,12 +155,13 @@ __device__ inline double row_part_face(const int *__restrict__ colidx, const Fac
     return acc0 + acc1;
 }
 
-template <int BS, bool FACE, typename MT, typename VT>
+// Row I's product with x (SKIP: without its diagonal block).
+template <int BS, bool FACE, typename MT, typename VT, bool SKIP = false>
 __device__ inline double row_product(const int *__restrict__ colidx, const MT *__restrict__ vals,
                                      const FaceView<MT> &F, int lo, int hi, int g, int G, int a, int I, int bs_rt,
                                      const VT *__restrict__ x) {
-    if constexpr (FACE) return row_part_face<BS, MT, VT>(colidx, F, lo, hi, g, G, a, I, bs_rt, x);
-    else return row_part<BS, MT, VT>(colidx, vals, lo, hi, g, G, a, bs_rt, x);
+    if constexpr (FACE) return row_part_face<BS, MT, VT, SKIP>(colidx, F, lo, hi, g, G, a, I, bs_rt, x);
+    else return row_part<BS, MT, VT, SKIP>(colidx, vals, lo, hi, g, G, a, bs_rt, x, I);
 }
 
 // D_I^{-1} t (TRANS: D_I^{-T} t) for scalar row a, with t in LDS.
@@ -168,6 +181,34 @@ __device__ inline double apply_dinv(const double *__restrict__ D, const double *
     }
     return d0 + d1;
 }
+
+// This lane's row of a D^{-1} block (column for D^{-T}): in registers for small
+// blocks, loaded before the row product so its latency overlaps it; apply()
+// gives apply_dinv's sums either way.
+template <int BS, bool TRANS>
+struct DinvRow {
+    static constexpr bool kPre = BS > 0 && BS <= 16;
+    double d[kPre ? BS : 1];
+    __device__ void load(const double *D, int a) {
+        if constexpr (kPre) {
+#pragma unroll
+            for (int c = 0; c < BS; ++c) d[c] = TRANS ? D[c * BS + a] : D[a * BS + c];
+        }
+    }
+    __device__ double apply(const double *D, const double *t, int a, int bs) const {
+        if constexpr (kPre) {
+            double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+            for (int c = 0; c < BS; c += 2) {
+                d0 += d[c] * t[c];
+                if (c + 1 < BS) d1 += d[c + 1] * t[c + 1];
+            }
+            return d0 + d1;
+        } else {
+            return apply_dinv<BS, TRANS>(D, t, a, bs);
+        }
+    }
+};
 
 struct Lane {
     int lr, g, a;   // local row, group, scalar row in block
@@ -233,8 +274,11 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int *__restrict__ r
 }
 
 // One Jacobi sweep over the listed rows (list == nullptr: rows with cf == only_cf;
-// the other rows copy e_in): e_out_I = e_in_I + D_I^{-1} (r_I - (A e_in)_I), or
-// with D_I^{-T} (TRANS: the sweeps of the transposed cycle, with A^T's rows).
+// the other rows copy e_in): e_out_I = D_I^{-1} (r_I - sum_{J != I} A_IJ e_in_J),
+// or with D_I^{-T} (TRANS: the sweeps of the transposed cycle, with A^T's
+// rows).  D_I is the diagonal block A_II, so this is e_in_I + D_I^{-1} (r_I -
+// (A e_in)_I) without the diagonal block's product and its cancellation: the
+// sweep reads neither A_II nor e_in_I (the two agree up to rounding).
 template <int BS, typename MT, typename VT, bool TRANS, bool FACE>
 __device__ inline void relax_rows(const int *__restrict__ rowptr, const int *__restrict__ colidx,
                                   const MT *__restrict__ vals, const double *__restrict__ dinv, int nb, int bs_rt,
@@ -252,48 +296,83 @@ __device__ inline void relax_rows(const int *__restrict__ rowptr, const int *__r
     if (I >= 0 && !live(gate, I)) I = -1;   // a stopped system: nothing to do
     const bool upd = I >= 0 && (list != nullptr || cf[I] == only_cf);
     // loads that do not depend on the row product go out first: this lane's
-    // row of D_I^{-1} (column for D^{-T}; small blocks only, in registers),
-    // r and e_in
-    constexpr bool kPre = BS > 0 && BS <= 16;
-    double dreg[kPre ? BS : 1];
+    // row of D_I^{-1} and r (e_in for rows that only copy it)
+    DinvRow<BS, TRANS> dr;
+    const double *D = dinv + static_cast<int64_t>(I) * bs * bs;
     const int64_t o = static_cast<int64_t>(I) * bs + L.a;
     double rv = 0.0, ev = 0.0;
     if (I >= 0 && L.g == 0) {
-        ev = static_cast<double>(ein[o]);
-        if (upd) {
+        if (!upd) {
+            ev = static_cast<double>(ein[o]);
+        } else {
             rv = static_cast<double>(r[o]);
-            if constexpr (kPre) {
-                const double *D = dinv + static_cast<int64_t>(I) * bs * bs;
-#pragma unroll
-                for (int c = 0; c < BS; ++c) dreg[c] = TRANS ? D[c * BS + L.a] : D[L.a * BS + c];
-            }
+            dr.load(D, L.a);
         }
     }
-    double acc =
-        upd ? row_product<BS, FACE>(colidx, vals, face, rowptr[I], rowptr[I + 1], L.g, G, L.a, I, bs, ein) : 0.0;
+    double acc = upd ? row_product<BS, FACE, MT, VT, true>(colidx, vals, face, rowptr[I], rowptr[I + 1], L.g, G, L.a,
+                                                          I, bs, ein)
+                     : 0.0;
     acc = reduce_groups(acc, L, G, bs, part);
     if (upd && L.g == 0) tb[L.lr * bs + L.a] = rv - acc;
     __syncthreads();
     if (I >= 0 && L.g == 0) {
-        if (upd) {
-            double d;
-            if constexpr (kPre) {   // apply_dinv's sums, from the registers
-                const double *tt = tb + L.lr * bs;
-                double d0 = 0.0, d1 = 0.0;
-#pragma unroll
-                for (int c = 0; c < BS; c += 2) {
-                    d0 += dreg[c] * tt[c];
-                    if (c + 1 < BS) d1 += dreg[c + 1] * tt[c + 1];
-                }
-                d = d0 + d1;
-            } else {
-                d = apply_dinv<BS, TRANS>(dinv + static_cast<int64_t>(I) * bs * bs, tb + L.lr * bs, L.a, bs);
-            }
-            eout[o] = static_cast<VT>(ev + d);
-        } else {
-            eout[o] = static_cast<VT>(ev);
-        }
+        if (upd) eout[o] = static_cast<VT>(dr.apply(D, tb + L.lr * bs, L.a, bs));
+        else eout[o] = static_cast<VT>(ev);
     }
+}
+
+// The same sweep over the F list from a sweep copy: row f of the copy is F row
+// I = flist[f] without its diagonal block, D_I^{-1} sits at position f.  The
+// copy keeps each row's blocks in order, so with one lane group per row the
+// sums are relax_rows' bit for bit (with G > 1 the blocks are dealt to the
+// groups from the row's start, which moves the diagonal's gap).
+template <int BS, typename MT, typename VT, bool TRANS, bool FACE>
+__device__ inline void sweep_rows(const SweepView<MT> &S, const int *__restrict__ flist, int nF, int bs_rt, int G,
+                                  const VT *__restrict__ r, const VT *__restrict__ ein, VT *__restrict__ eout,
+                                  Gate gate) {
+    __shared__ double part[kThreads];
+    __shared__ double tb[kThreads];
+    const int bs = Bs<BS>::get(bs_rt);
+    const Lane L = lane_of(G, bs);
+    const int f = blockIdx.x * (kThreads / (G * bs)) + L.lr;
+    int I = -1;
+    if (L.valid && f < nF) I = flist[f];
+    if (I >= 0 && !live(gate, I)) I = -1;
+    DinvRow<BS, TRANS> dr;
+    const double *D = S.dinv + static_cast<int64_t>(f) * bs * bs;
+    const int64_t o = static_cast<int64_t>(I) * bs + L.a;
+    double rv = 0.0;
+    if (I >= 0 && L.g == 0) {
+        rv = static_cast<double>(r[o]);
+        dr.load(D, L.a);
+    }
+    double acc = 0.0;
+    if (I >= 0) {
+        const int lo = S.rowptr[f], hi = S.rowptr[f + 1];
+        if constexpr (FACE)
+            acc = row_part_face<BS, MT, VT>(S.colidx, FaceView<MT>{S.meta, S.vals, nullptr, S.cmax, S.rc}, lo, hi,
+                                            L.g, G, L.a, -1, bs, ein);
+        else
+            acc = row_part<BS, MT, VT>(S.colidx, S.vals, lo, hi, L.g, G, L.a, bs, ein);
+    }
+    acc = reduce_groups(acc, L, G, bs, part);
+    if (I >= 0 && L.g == 0) tb[L.lr * bs + L.a] = rv - acc;
+    __syncthreads();
+    if (I >= 0 && L.g == 0) eout[o] = static_cast<VT>(dr.apply(D, tb + L.lr * bs, L.a, bs));
+}
+
+template <int BS, typename MT, typename VT, bool FACE = false>
+__global__ __launch_bounds__(kThreads) void k_sweep(SweepView<MT> S, const int *__restrict__ flist, int nF,
+                                                   int bs_rt, int G, const VT *__restrict__ r,
+                                                   const VT *__restrict__ ein, VT *__restrict__ eout, Gate gate) {
+    sweep_rows<BS, MT, VT, false, FACE>(S, flist, nF, bs_rt, G, r, ein, eout, gate);
+}
+
+template <int BS, typename MT, typename VT, bool FACE = false>
+__global__ __launch_bounds__(kThreads) void k_sweep_T(SweepView<MT> S, const int *__restrict__ flist, int nF,
+                                                     int bs_rt, int G, const VT *__restrict__ r,
+                                                     const VT *__restrict__ ein, VT *__restrict__ eout, Gate gate) {
+    sweep_rows<BS, MT, VT, true, FACE>(S, flist, nF, bs_rt, G, r, ein, eout, gate);
 }
 
 // The first transposed F sweep from a zero guess (F relaxation only): e1_F =
@@ -350,8 +429,8 @@ __global__ __launch_bounds__(kThreads) void k_relax_T(const int *__restrict__ ro
 
 // The interpolation e = P e_c and the first F sweep in one launch (small
 // levels, where launches cost more than their work): e0 = P e_c on every row;
-// e1 = e0 + D^{-1}(r - A e0) on F rows, e1 = e0 on C rows -- what the two
-// kernels leave, computed in the same order.
+// e1 = D^{-1}(r - sum_{J != I} A_IJ e0_J) on F rows, e1 = e0 on C rows --
+// what the two kernels leave, computed in the same order.
 template <int BS, typename MT, typename VT>
 __global__ __launch_bounds__(kThreads) void k_relax_interp(const int *__restrict__ rowptr,
                                                           const int *__restrict__ colidx, const MT *__restrict__ vals,
@@ -367,7 +446,9 @@ __global__ __launch_bounds__(kThreads) void k_relax_interp(const int *__restrict
     if (!L.valid || I >= nb || !live(gate, I)) I = -1;
     const bool upd = I >= 0 && cf[I] == 0;
     const PmapSrc<VT> src{ec, pmap, bs};
-    double acc = upd ? row_part_src<BS, MT, VT>(colidx, vals, rowptr[I], rowptr[I + 1], L.g, G, L.a, bs, src) : 0.0;
+    double acc = upd ? row_part_src<BS, MT, VT, PmapSrc<VT>, true>(colidx, vals, rowptr[I], rowptr[I + 1], L.g, G,
+                                                                   L.a, bs, src, I)
+                     : 0.0;
     acc = reduce_groups(acc, L, G, bs, part);
     const int64_t o = static_cast<int64_t>(I) * bs + L.a;
     VT v = VT(0);
@@ -381,7 +462,7 @@ __global__ __launch_bounds__(kThreads) void k_relax_interp(const int *__restrict
         e0[o] = v;
         if (upd) {
             const double d = apply_dinv<BS, false>(dinv + static_cast<int64_t>(I) * bs * bs, tb + L.lr * bs, L.a, bs);
-            e1[o] = static_cast<VT>(static_cast<double>(v) + d);
+            e1[o] = static_cast<VT>(d);
         } else {
             e1[o] = v;
         }
@@ -721,6 +802,23 @@ void launch_relax(const MatView<MT> &A, const double *dinv, bool dinv_trans, con
     if (N <= 0) return;
     const int G = groups_for(A);
     const unsigned grid = grid_rows(N, G, A.bs);
+    if (list && A.sweep.rowptr) {   // F sweep from the level's sweep copy (built for this F list)
+        const SweepView<MT> &S = A.sweep;
+        if (dinv_trans && S.meta) {
+            NAIR_FACE_DISPATCH(A.bs, k_sweep_T, <<<grid, kThreads, 0, s>>>(S, list, nlist, A.bs, G, r, ein, eout,
+                                                                           gate));
+        } else if (dinv_trans) {
+            NAIR_BS_DISPATCH(A.bs, k_sweep_T, <<<grid, kThreads, 0, s>>>(S, list, nlist, A.bs, G, r, ein, eout,
+                                                                         gate));
+        } else if (S.meta) {
+            NAIR_FACE_DISPATCH(A.bs, k_sweep, <<<grid, kThreads, 0, s>>>(S, list, nlist, A.bs, G, r, ein, eout,
+                                                                         gate));
+        } else {
+            NAIR_BS_DISPATCH(A.bs, k_sweep, <<<grid, kThreads, 0, s>>>(S, list, nlist, A.bs, G, r, ein, eout, gate));
+        }
+        NAIR_HIP(hipGetLastError());
+        return;
+    }
     if (dinv_trans && A.face.meta) {
         NAIR_FACE_DISPATCH(A.bs, k_relax_T, <<<grid, kThreads, 0, s>>>(A.rowptr, A.colidx, A.vals, dinv, A.nb, A.bs,
                                                                        G, r, ein, eout, list, nlist, cf, only_cf,

@@ -62,20 +62,31 @@ struct Level {
     DBuf<float> fsave32;
     // face-compressed copies of A and A^T (level 0 of a block hierarchy)
     FaceCopy face, faceT;
+    // F rows of A and A^T in F-list order without their diagonal blocks, for the sweeps
+    SweepCopy sweep, sweepT;
 };
 
 // A_l (trans: A_l^T) as the cycle kernels read it: with its face-compressed
 // copy where the level has one.
+// The F sweeps read its sweep copy where the level has one.
 inline MatView<double> op_view(const Level &L, bool trans) {
     MatView<double> v = view(trans ? L.AT : L.A);
     const FaceCopy &F = trans ? L.faceT : L.face;
     if (F.on) v.face = FaceView<double>{F.meta.get(), F.vals.get(), F.dvals.get(), F.cmax, F.rc};
+    const SweepCopy &S = trans ? L.sweepT : L.sweep;
+    if (S.on)
+        v.sweep = SweepView<double>{S.rowptr.get(), S.colidx.get(), S.rc ? S.meta.get() : nullptr, S.vals.get(),
+                                    S.dinv.get(), S.cmax, S.rc};
     return v;
 }
 inline MatView<float> op_view32(const Level &L, bool trans) {
     MatView<float> v = view(trans ? L.AT : L.A, trans ? L.at32.get() : L.vals32.get());
     const FaceCopy &F = trans ? L.faceT : L.face;
     if (F.on) v.face = FaceView<float>{F.meta.get(), F.vals32.get(), F.dvals32.get(), F.cmax, F.rc};
+    const SweepCopy &S = trans ? L.sweepT : L.sweep;
+    if (S.on)
+        v.sweep = SweepView<float>{S.rowptr.get(), S.colidx.get(), S.rc ? S.meta.get() : nullptr, S.vals32.get(),
+                                   S.dinv.get(), S.cmax, S.rc};
     return v;
 }
 
@@ -154,6 +165,8 @@ void autotune(Hier &h, int reps, int8_t *table, hipStream_t s);
 void apply_tuning(Hier &h, const int8_t *table);
 void drop_graphs(Hier &h);
 void make_fp32_copies(Hier &h, hipStream_t s);
+// Sweep copies of A (trans: A^T) on the levels nair_params.sweep_copy selects.
+void build_sweeps(Hier &h, bool trans, hipStream_t s);
 void complexity(Hier &h, double *oc, double *cc, hipStream_t s);
 
 // validation of the input pattern (device): sets *bad != 0 on error

@@ -390,8 +390,21 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
     }
     // the finest operator is read by every cycle: a compact copy of its face blocks
     if (p.faces == 1 && p.form == 0) build_face(h.lv[0]->A, h.lv[0]->face, s);
+    build_sweeps(h, false, s);
     if (p.precision == 1) make_fp32_copies(h, s);
     NAIR_HIP(hipStreamSynchronize(s));
+}
+
+void build_sweeps(Hier &h, bool trans, hipStream_t s) {
+    if (h.prm.sweep_copy == 0) return;
+    for (auto &Lp : h.lv) {
+        Level &L = *Lp;
+        if (L.coarsest || L.nF <= 0) continue;
+        if (h.prm.sweep_copy < 0 && few_lanes(L.A.nb, L.A.bs)) continue;
+        SweepCopy &S = trans ? L.sweepT : L.sweep;
+        if (S.on) continue;
+        build_sweep(trans ? L.AT : L.A, trans ? L.faceT : L.face, L.dinv.get(), L.flist.get(), L.nF, S, s);
+    }
 }
 
 // FP32 copies of what the cycle reads (operators and Z of the non-coarsest
@@ -427,6 +440,8 @@ void make_fp32_copies(Hier &h, hipStream_t s) {
         }
         face_to_float(L.A, L.face, s);
         if (L.have_T) face_to_float(L.AT, L.faceT, s);
+        sweep_to_float(L.sweep, L.A.bs, s);
+        sweep_to_float(L.sweepT, L.A.bs, s);
     }
 }
 
@@ -446,6 +461,7 @@ void ensure_transposes(Hier &h, hipStream_t s) {
         }
         L.have_T = true;
     }
+    build_sweeps(h, true, s);
     if (h.prm.precision == 1) make_fp32_copies(h, s);
     NAIR_HIP(hipStreamSynchronize(s));
 }

@@ -44,7 +44,8 @@ class _Params(C.Structure):
                 ("drop", C.c_double), ("relax", C.c_int32), ("max_levels", C.c_int32),
                 ("max_coarse_dofs", C.c_int32), ("seed", C.c_uint64),
                 ("cf_override_host", C.c_void_p), ("precision", C.c_int32), ("tuning", C.c_void_p),
-                ("form", C.c_int32), ("cycle", C.c_int32), ("gmres", C.c_int32), ("faces", C.c_int32)]
+                ("form", C.c_int32), ("cycle", C.c_int32), ("gmres", C.c_int32), ("faces", C.c_int32),
+                ("sweep_copy", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -62,7 +63,7 @@ class _LevelView(C.Structure):
                 ("z_colidx", C.c_void_p), ("z_vals", C.c_void_p), ("dense_n", C.c_int32),
                 ("dense_inv", C.c_void_p), ("face_rmax", C.c_int32), ("face_cmax", C.c_int32),
                 ("face_meta", C.c_void_p), ("face_vals", C.c_void_p), ("face_dvals", C.c_void_p),
-                ("margin", C.c_int32 * 4)]
+                ("margin", C.c_int32 * 4), ("sweep_nnzb", C.c_int32)]
 
 
 _lib = None
@@ -164,6 +165,7 @@ class Params:
     cycle: str = "V"             # "V" or "F"
     gmres: int = 0               # 0: stationary iteration; m > 0: GMRES(m) preconditioned by the cycle
     faces: bool = True           # compact copy of the finest operator's face blocks for the cycle
+    sweep_copy: str = "auto"     # F rows in F order for the sweeps: "auto" (large levels), "off", "all"
 
 
 @dataclass
@@ -210,6 +212,9 @@ class Hierarchy:
         p.cycle = 1 if params.cycle == "F" else 0
         p.gmres = int(params.gmres)
         p.faces = 1 if params.faces else 0
+        if params.sweep_copy not in ("auto", "off", "all"):
+            raise ValueError("sweep_copy must be 'auto', 'off' or 'all'")
+        p.sweep_copy = {"auto": -1, "off": 0, "all": 1}[params.sweep_copy]
         cf = None
         if params.cf_override is not None:
             cf = np.ascontiguousarray(params.cf_override, dtype=np.int8)
@@ -394,7 +399,8 @@ class Hierarchy:
         bb = bs * bs
         want = (lambda k: True) if fields is None else (lambda k: k in fields)
         out = dict(nb=nb, bs=bs, nnzb=nnzb, coarsest=bool(v.coarsest), nc=v.nc, pmis_rounds=v.pmis_rounds,
-                   face_rmax=v.face_rmax, face_cmax=v.face_cmax, margin=tuple(int(m) for m in v.margin))
+                   face_rmax=v.face_rmax, face_cmax=v.face_cmax, margin=tuple(int(m) for m in v.margin),
+                   sweep_nnzb=v.sweep_nnzb)
         spec = [("rowptr", v.rowptr, torch.int32, nb + 1, None),
                 ("colidx", v.colidx, torch.int32, nnzb, None),
                 ("vals", v.vals, torch.float64, nnzb * bb, (nnzb, bs, bs))]

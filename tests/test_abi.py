@@ -64,7 +64,7 @@ def test_default_params_and_host_side_errors():
     assert L.nair_setup(4, 2, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.byref(p), None, C.byref(h)) == 1
     assert b"theta" in L.nair_last_error(None)
     L.nair_default_params(C.byref(p))
-    assert (p.precision, p.form, p.cycle, p.gmres, p.faces) == (0, 0, 0, 0, 1)
+    assert (p.precision, p.form, p.cycle, p.gmres, p.faces, p.sweep_copy) == (0, 0, 0, 0, 1, -1)
     p.gmres = 201   # longer than the largest GMRES restart cycle
     assert L.nair_setup(4, 2, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.byref(p), None, C.byref(h)) == 1
     assert b"gmres" in L.nair_last_error(None)
@@ -72,6 +72,10 @@ def test_default_params_and_host_side_errors():
     p.faces = 2
     assert L.nair_setup(4, 2, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.byref(p), None, C.byref(h)) == 1
     assert b"faces" in L.nair_last_error(None)
+    L.nair_default_params(C.byref(p))
+    p.sweep_copy = 2
+    assert L.nair_setup(4, 2, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.byref(p), None, C.byref(h)) == 1
+    assert b"sweep_copy" in L.nair_last_error(None)
     assert h.value is None
     # NULL handle
     assert L.nair_solve(None, C.c_void_p(8), C.c_void_p(8), 1e-10, 5, None, None) == 1
