@@ -180,9 +180,16 @@ void launch_rows_of(const int *rowptr, int nrows, int *rowid, hipStream_t s);
 void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipStream_t s);
 // O = S + W (union pattern, S's value first)
 void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s);
-// K = RA * P (P one-point through pmap), filtered by drop; returns the filtered K
-// margin[3] += off-diagonal blocks whose drop test is within 1e-12 relative
-void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevBSR &K, int *margin, hipStream_t s);
+// The Galerkin product K = R A P with R = [Z I] (identity at column cpts[i] of
+// row i) and P one-point through pmap, filtered by drop.  K block (i, J) is the
+// sum, in ascending fine column j, of the blocks (R A)_ij with pmap[j] = J, each
+// (R A)_ij formed as in spgemm.  For 9x9 and 16x16 blocks the R A blocks are
+// never stored: each K block is summed straight from their pair lists.
+// margin[3] += off-diagonal blocks whose drop test is within 1e-12 relative;
+// knext receives the block max-abs size of every kept block of K (the next
+// level's block norms).
+void galerkin(const DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int nc, double drop, DevBSR &K,
+              int *margin, DBuf<double> &knext, hipStream_t s);
 
 // ------------------------------------------------------------------ dense
 // For each segment k < nseg (host arrays): the dense operator of A's block rows

@@ -39,6 +39,7 @@ struct Level {
     DBuf<int64_t> doff_d;
     // setup products
     DBuf<double> dinv, bnorm;
+    bool bnorm_ready = false;       // bnorm came with the operator (the Galerkin step computes it)
     DBuf<uint8_t> mask;
     DBuf<int> lambda, cidx, pmap, dround, cpts, flist;
     DBuf<int> margin;               // decision-margin audit counts (theta, phi, one-point, drop)

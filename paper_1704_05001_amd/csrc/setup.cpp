@@ -220,7 +220,7 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         }
         const int64_t nz = L.A.nnzb;
         L.dinv.alloc(static_cast<size_t>(n) * bb);
-        L.bnorm.alloc(nz);
+        if (!L.bnorm_ready) L.bnorm.alloc(nz);
         L.mask.alloc(nz);
         L.lambda.alloc(n);
         L.cf.alloc(n);
@@ -232,7 +232,7 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         NAIR_HIP(hipMemsetAsync(L.lambda.get(), 0, sizeof(int) * n, s));
         L.margin.alloc(4);
         NAIR_HIP(hipMemsetAsync(L.margin.get(), 0, sizeof(int) * 4, s));
-        launch_block_maxabs(L.A.vals.get(), nz, bs, L.bnorm.get(), s);
+        if (!L.bnorm_ready) launch_block_maxabs(L.A.vals.get(), nz, bs, L.bnorm.get(), s);
         {
             TimerScope ts(TK_BLOCKINV, l, s);
             launch_block_inverse(L.A.rowptr.get(), L.A.colidx.get(), L.A.vals.get(), n, bs, L.direct.get(),
@@ -379,11 +379,10 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         L.Z.vals.alloc(static_cast<size_t>(L.Z.nnzb) * bb);
         launch_block_product(L.Z.nnzb, bs, Ssum.vals.get(), nullptr, L.dinv.get(), L.Z.colidx.get(), -1.0,
                              L.Z.vals.get(), s);
-        // Galerkin: R A with R = [Z I], then K = (R A) P, filtered
-        DevBSR RA;
-        spgemm(L.Z, L.cpts.get(), L.A, RA, s);
+        // Galerkin: K = R A P with R = [Z I], filtered; K's block sizes come along
         auto next = std::make_unique<Level>();
-        rap_merge_drop(RA, L.pmap.get(), nc, p.drop, next->A, L.margin.get(), s);
+        galerkin(L.Z, L.cpts.get(), L.A, L.pmap.get(), nc, p.drop, next->A, L.margin.get(), next->bnorm, s);
+        next->bnorm_ready = true;
         next->seg.assign(cseg.begin(), cseg.begin() + nsys + 1);
         next->mode.assign(nsys, 0);
         h.lv.push_back(std::move(next));

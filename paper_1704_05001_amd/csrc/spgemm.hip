@@ -489,61 +489,78 @@ __global__ __launch_bounds__(256) void k_spgemm_pairs(int64_t nnz, int bs_rt, co
 // Y's entries plainly, in their place in the pair order.
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
+// One block pair's operands as the MFMA steps take them: per step q the A
+// fragment (X row `row`, inner index 4q + kk) and the B fragment (Y inner index
+// 4q + kk, column `row`), zero beyond bs; for an identity pair Y's entries
+// (i, row), i = kk + 4q, added plainly.
+template <int BS>
+struct MfmaPair {
+    static constexpr int KQ = (BS + 3) / 4;
+    double a[KQ], b[KQ];
+    bool ident;
+};
+
+template <int BS>
+__device__ inline MfmaPair<BS> mfma_load(const int2 pr, const double *__restrict__ X, const double *__restrict__ Y,
+                                         int row, int kk) {
+    constexpr int bb = BS * BS;
+    constexpr int KQ = MfmaPair<BS>::KQ;
+    MfmaPair<BS> f;
+    const double *y = Y + static_cast<int64_t>(pr.y) * bb;
+    f.ident = pr.x < 0;
+    if (f.ident) {
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            const int i = kk + 4 * q;
+            f.a[q] = (i < BS && row < BS) ? y[i * BS + row] : 0.0;
+            f.b[q] = 0.0;
+        }
+    } else {
+        const double *x = X + static_cast<int64_t>(pr.x) * bb;
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            const int c = 4 * q + kk;
+            f.a[q] = (row < BS && c < BS) ? x[row * BS + c] : 0.0;
+            f.b[q] = (row < BS && c < BS) ? y[c * BS + row] : 0.0;
+        }
+    }
+    return f;
+}
+
+template <int BS>
+__device__ inline void mfma_apply(const MfmaPair<BS> &f, double4_t &acc, int row, int kk) {
+    constexpr int KQ = MfmaPair<BS>::KQ;
+    if (f.ident) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = kk + 4 * r;
+            if (r < KQ && i < BS && row < BS) acc[r] = acc[r] + f.a[r];
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(f.a[q], f.b[q], acc, 0, 0, 0);
+    }
+}
+
 template <int BS>
 __global__ __launch_bounds__(256) void k_spgemm_mfma(int64_t nnz, const int *__restrict__ pairptr,
                                                     const int2 *__restrict__ pairs, const double *__restrict__ X,
                                                     const double *__restrict__ Y, double *__restrict__ C) {
     constexpr int bb = BS * BS;
-    constexpr int KQ = (BS + 3) / 4;
+    constexpr int KQ = MfmaPair<BS>::KQ;
     const int lane = threadIdx.x & 63;
     const int row = lane & 15, kk = lane >> 4;   // A: row i, B: column j; both k = kk
     const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (t >= nnz) return;   // whole waves
     double4_t acc = {0.0, 0.0, 0.0, 0.0};
-    // operands of one pair: A and B fragments per step, or Y's entries for an
-    // identity pair; the next pair's load while this pair's steps run
-    struct Frag {
-        double a[KQ], b[KQ];
-        bool ident;
-    };
-    auto load = [&](const int2 pr) {
-        Frag f;
-        const double *y = Y + static_cast<int64_t>(pr.y) * bb;
-        f.ident = pr.x < 0;
-        if (f.ident) {
-#pragma unroll
-            for (int q = 0; q < KQ; ++q) {   // reuse a[] for Y's entries (i, row), i = kk + 4q
-                const int i = kk + 4 * q;
-                f.a[q] = (i < BS && row < BS) ? y[i * BS + row] : 0.0;
-                f.b[q] = 0.0;
-            }
-        } else {
-            const double *x = X + static_cast<int64_t>(pr.x) * bb;
-#pragma unroll
-            for (int q = 0; q < KQ; ++q) {
-                const int c = 4 * q + kk;
-                f.a[q] = (row < BS && c < BS) ? x[row * BS + c] : 0.0;
-                f.b[q] = (row < BS && c < BS) ? y[c * BS + row] : 0.0;
-            }
-        }
-        return f;
-    };
     const int k0 = pairptr[t], k1 = pairptr[t + 1];
     if (k0 < k1) {
-        Frag cur = load(pairs[k0]);
+        // the next pair's operands load while this pair's steps run
+        MfmaPair<BS> cur = mfma_load<BS>(pairs[k0], X, Y, row, kk);
         for (int k = k0; k < k1; ++k) {
-            Frag nxt = cur;
-            if (k + 1 < k1) nxt = load(pairs[k + 1]);
-            if (cur.ident) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = kk + 4 * r;
-                    if (r < KQ && i < BS && row < BS) acc[r] = acc[r] + cur.a[r];
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < KQ; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.a[q], cur.b[q], acc, 0, 0, 0);
-            }
+            MfmaPair<BS> nxt = cur;
+            if (k + 1 < k1) nxt = mfma_load<BS>(pairs[k + 1], X, Y, row, kk);
+            mfma_apply<BS>(cur, acc, row, kk);
             cur = nxt;
         }
     }
@@ -551,8 +568,85 @@ __global__ __launch_bounds__(256) void k_spgemm_mfma(int64_t nnz, const int *__r
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = kk + 4 * r;
-        if (i < BS && row < BS) out[i * BS + row] = acc[r];
+        if (r < KQ && i < BS && row < BS) out[i * BS + row] = acc[r];
     }
+}
+
+// The Galerkin blocks straight from the pair lists: K block t is the sum, in
+// list order, of the R A blocks klist[kptr[t]] ..., each formed in an
+// accumulator of its own from +0 over its pairs exactly as k_spgemm_mfma forms
+// it, then added into K's accumulator (K = 0 + RA_1 + RA_2 + ...: the sums of
+// the merge over stored R A blocks, without storing them).  One wave per K
+// block; the lanes hold up to 64 contributing blocks' pair ranges, and the
+// walk over their pairs loads the next pair (of the same or the next block)
+// while the current one's steps run.  Also writes the block's max-abs size.
+template <int BS>
+__global__ __launch_bounds__(256) void k_galerkin_mfma(int64_t nnz, const int *__restrict__ kptr,
+                                                      const int *__restrict__ klist, const int *__restrict__ pairptr,
+                                                      const int2 *__restrict__ pairs, const double *__restrict__ X,
+                                                      const double *__restrict__ Y, double *__restrict__ K,
+                                                      double *__restrict__ knorm) {
+    constexpr int bb = BS * BS;
+    constexpr int KQ = MfmaPair<BS>::KQ;
+    const int lane = threadIdx.x & 63;
+    const int row = lane & 15, kk = lane >> 4;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (t >= nnz) return;   // whole waves
+    double4_t kacc = {0.0, 0.0, 0.0, 0.0};
+    const int c0 = kptr[t], c1 = kptr[t + 1];
+    for (int base = c0; base < c1; base += 64) {
+        const int cnt = min(64, c1 - base);
+        int pb = 0, pe = 0;
+        if (lane < cnt) {
+            const int u = klist[base + lane];
+            pb = pairptr[u];
+            pe = pairptr[u + 1];
+        }
+        // (j, k): pair k of contributing block j; j, k and the ranges are the same in every lane
+        int j = 0;
+        int k = __shfl(pb, 0, 64), ke = __shfl(pe, 0, 64);
+        bool have = k < ke;
+        double4_t acc = {0.0, 0.0, 0.0, 0.0};
+        MfmaPair<BS> cur{};
+        if (have) cur = mfma_load<BS>(pairs[k], X, Y, row, kk);
+        while (j < cnt) {
+            int jn = j, kn = k + 1, ken = ke;
+            if (!have || kn >= ke) {   // block j ends with this pair
+                jn = j + 1;
+                if (jn < cnt) {
+                    kn = __shfl(pb, jn, 64);
+                    ken = __shfl(pe, jn, 64);
+                }
+            }
+            const bool haven = jn < cnt && kn < ken;
+            MfmaPair<BS> nxt = cur;
+            if (haven) nxt = mfma_load<BS>(pairs[kn], X, Y, row, kk);
+            if (have) mfma_apply<BS>(cur, acc, row, kk);
+            if (jn != j) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) kacc[r] = kacc[r] + acc[r];
+                acc = double4_t{0.0, 0.0, 0.0, 0.0};
+            }
+            j = jn;
+            k = kn;
+            ke = ken;
+            have = haven;
+            cur = nxt;
+        }
+    }
+    double *out = K + t * bb;
+    double m = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = kk + 4 * r;
+        if (r < KQ && i < BS && row < BS) {
+            out[i * BS + row] = kacc[r];
+            m = fmax(m, fabs(kacc[r]));
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane == 0) knorm[t] = m;
 }
 
 // ---------------------------------------------------- Galerkin merge lists
@@ -667,7 +761,17 @@ __global__ __launch_bounds__(256) void k_drop_mark(const int *__restrict__ krp, 
         default: KERNEL<0> __VA_ARGS__; break;       \
     }
 
-void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipStream_t s) {
+namespace {
+
+// The pair lists of a product's blocks (pairs[pairptr[t]] ... for block t).
+struct Pairs {
+    DBuf<int> pairptr;
+    DBuf<int2> pairs;
+};
+
+// C's pattern (rowptr, colidx, nnzb) and the pair lists of its blocks; C.vals
+// is left unallocated.
+void spgemm_structure(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, Pairs &P, hipStream_t s) {
     const int m = X.nb;
     const int bs = X.bs;
     C.nb = m;
@@ -678,7 +782,6 @@ void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipSt
         NAIR_HIP(hipMemsetAsync(C.rowptr.get(), 0, sizeof(int), s));
         C.nnzb = 0;
         C.colidx.alloc(0);
-        C.vals.alloc(0);
         return;
     }
     const int small_cap = kHashSmall / 2, large_cap = kHashLarge / 2;
@@ -710,10 +813,9 @@ void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipSt
                               std::to_string(large_cap) + ")");
     C.nnzb = nnz;
     C.colidx.alloc(nnz);
-    C.vals.alloc(static_cast<size_t>(nnz) * bs * bs);
     if (nnz == 0) return;
-    DBuf<int> pairptr(static_cast<size_t>(nnz) + 1);
-    DBuf<int2> pairs(npairs);
+    P.pairptr.alloc(static_cast<size_t>(nnz) + 1);
+    P.pairs.alloc(npairs);
     k_symbolic_small<<<gs, 256, 0, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(), Y.colidx.get(), m,
                                         ub.get(), small_cap, 1, nullptr, C.rowptr.get(), C.colidx.get());
     if (hflags[0] > 0)
@@ -722,27 +824,43 @@ void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipSt
                                                      C.rowptr.get(), C.colidx.get(), ub.get());
     k_pairs_small<<<cap_grid(m), 64, 0, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(), Y.colidx.get(), m,
                                              ub.get(), small_cap, C.rowptr.get(), C.colidx.get(), prow.get(),
-                                             pairptr.get(), pairs.get());
+                                             P.pairptr.get(), P.pairs.get());
     if (hflags[0] > 0)
         k_pairs_large<<<256, 256, 0, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(), Y.colidx.get(),
                                           big_list.get(), big_count, C.rowptr.get(), C.colidx.get(), prow.get(),
-                                          pairptr.get(), pairs.get());
+                                          P.pairptr.get(), P.pairs.get());
     NAIR_HIP(hipGetLastError());
-    const int64_t total = static_cast<int64_t>(nnz) * bs;
+}
+
+// C's values from its pair lists (C.vals allocated by the caller).
+void spgemm_values(const DevBSR &X, const DevBSR &Y, const Pairs &P, DevBSR &C, hipStream_t s) {
+    const int64_t nnz = C.nnzb;
+    const int bs = C.bs;
+    if (nnz == 0) return;
+    const int64_t total = nnz * bs;
     const unsigned grid = cap_grid((total + 255) / 256);
     TimerScope ts(TK_SPGEMM_NUM, g_timer_level, s);
-    const unsigned mgrid = static_cast<unsigned>((static_cast<int64_t>(nnz) + 3) / 4);   // four waves per workgroup
+    const unsigned mgrid = static_cast<unsigned>((nnz + 3) / 4);   // four waves per workgroup
     if (bs == 9) {
-        k_spgemm_mfma<9><<<mgrid, 256, 0, s>>>(nnz, pairptr.get(), pairs.get(), X.vals.get(), Y.vals.get(),
+        k_spgemm_mfma<9><<<mgrid, 256, 0, s>>>(nnz, P.pairptr.get(), P.pairs.get(), X.vals.get(), Y.vals.get(),
                                                C.vals.get());
     } else if (bs == 16) {
-        k_spgemm_mfma<16><<<mgrid, 256, 0, s>>>(nnz, pairptr.get(), pairs.get(), X.vals.get(), Y.vals.get(),
+        k_spgemm_mfma<16><<<mgrid, 256, 0, s>>>(nnz, P.pairptr.get(), P.pairs.get(), X.vals.get(), Y.vals.get(),
                                                 C.vals.get());
     } else {
-        NAIR_BS_DISPATCH(bs, k_spgemm_pairs, <<<grid, 256, 0, s>>>(nnz, bs, pairptr.get(), pairs.get(), X.vals.get(),
-                                                                   Y.vals.get(), C.vals.get()));
+        NAIR_BS_DISPATCH(bs, k_spgemm_pairs, <<<grid, 256, 0, s>>>(nnz, bs, P.pairptr.get(), P.pairs.get(),
+                                                                   X.vals.get(), Y.vals.get(), C.vals.get()));
     }
     NAIR_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipStream_t s) {
+    Pairs P;
+    spgemm_structure(X, xdiag, Y, C, P, s);
+    C.vals.alloc(static_cast<size_t>(C.nnzb) * C.bs * C.bs);
+    spgemm_values(X, Y, P, C, s);
 }
 
 void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s) {
@@ -771,10 +889,20 @@ void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s) {
     NAIR_HIP(hipGetLastError());
 }
 
-void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevBSR &K, int *margin, hipStream_t s) {
-    const int m = RA.nb;
+void galerkin(const DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int nc, double drop, DevBSR &K,
+              int *margin, DBuf<double> &knext, hipStream_t s) {
+    // R A's pattern and pair lists; its values only where no fused kernel takes the blocks
+    DevBSR RA;
+    Pairs P;
+    spgemm_structure(Z, cpts, A, RA, P, s);
     const int bs = RA.bs;
     const int bb = bs * bs;
+    const bool fused = bs == 9 || bs == 16;
+    if (!fused) {
+        RA.vals.alloc(static_cast<size_t>(RA.nnzb) * bb);
+        spgemm_values(Z, A, P, RA, s);
+    }
+    const int m = RA.nb;
     // flags: too-dense row, then the scans' totals (blocks, contributions), read in one copy
     DBuf<int> cnt(m), ccnt(m), krp(static_cast<size_t>(m) + 1), crow(static_cast<size_t>(m) + 1), flags(3);
     NAIR_HIP(hipMemsetAsync(flags.get(), 0, sizeof(int), s));
@@ -802,11 +930,24 @@ void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevB
     NAIR_HIP(hipGetLastError());
     if (nnz > 0) {
         TimerScope ts(TK_RAP, g_timer_level, s);
-        const int64_t total = static_cast<int64_t>(nnz) * bb;
-        k_rap_values<<<cap_grid((total + 255) / 256), 256, 0, s>>>(nnz, bb, kptr.get(), klist.get(), RA.vals.get(),
-                                                                  kval.get());
+        if (fused) {
+            const unsigned mgrid = static_cast<unsigned>((static_cast<int64_t>(nnz) + 3) / 4);
+            if (bs == 9)
+                k_galerkin_mfma<9><<<mgrid, 256, 0, s>>>(nnz, kptr.get(), klist.get(), P.pairptr.get(),
+                                                         P.pairs.get(), Z.vals.get(), A.vals.get(), kval.get(),
+                                                         knorm.get());
+            else
+                k_galerkin_mfma<16><<<mgrid, 256, 0, s>>>(nnz, kptr.get(), klist.get(), P.pairptr.get(),
+                                                          P.pairs.get(), Z.vals.get(), A.vals.get(), kval.get(),
+                                                          knorm.get());
+        } else {
+            const int64_t total = static_cast<int64_t>(nnz) * bb;
+            k_rap_values<<<cap_grid((total + 255) / 256), 256, 0, s>>>(nnz, bb, kptr.get(), klist.get(),
+                                                                      RA.vals.get(), kval.get());
+        }
+        NAIR_HIP(hipGetLastError());
     }
-    launch_block_maxabs(kval.get(), nnz, bs, knorm.get(), s);
+    if (!fused) launch_block_maxabs(kval.get(), nnz, bs, knorm.get(), s);
     k_drop_mark<<<grid_for(m, 256), 256, 0, s>>>(krp.get(), kcol.get(), knorm.get(), m, drop, keep.get(), kept.get(),
                                                  margin);
     NAIR_HIP(hipGetLastError());
@@ -819,11 +960,13 @@ void rap_merge_drop(const DevBSR &RA, const int *pmap, int nc, double drop, DevB
     K.nnzb = nk;
     K.colidx.alloc(nk);
     K.vals.alloc(static_cast<size_t>(nk) * bb);
+    knext.alloc(nk);
     DBuf<int> src(nk);
     k_compact_fill<<<grid_for(m, 256), 256, 0, s>>>(krp.get(), kcol.get(), keep.get(), m, K.rowptr.get(),
                                                     K.colidx.get(), src.get());
     NAIR_HIP(hipGetLastError());
     launch_block_gather(nk, bs, kval.get(), src.get(), K.vals.get(), s);
+    launch_block_gather(nk, 1, knorm.get(), src.get(), knext.get(), s);   // a block's size is its max-abs entry
 }
 
 }  // namespace nair
