@@ -97,58 +97,6 @@ __device__ inline void emit_sorted(const int *table, int slots, int *list, int *
     }
 }
 
-// Small rows: one wave per row, 4 rows per workgroup; rows with ub > small cap
-// are left to the large kernel.  mode 0: count into cnt[i]; mode 1: write sorted
-// columns at crowptr[i].
-__global__ __launch_bounds__(256) void k_symbolic_small(const int *__restrict__ xrowptr, const int *__restrict__ xcol,
-                                                       const int *__restrict__ xdiag, const int *__restrict__ yrowptr,
-                                                       const int *__restrict__ ycol, int m,
-                                                       const int *__restrict__ ub, int small_cap, int mode,
-                                                       int *__restrict__ cnt, const int *__restrict__ crowptr,
-                                                       int *__restrict__ ccol) {
-    __shared__ int tables[4][kHashSmall];
-    __shared__ int lists[4][kHashSmall / 2];
-    __shared__ int counts[4];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int *table = tables[w];
-    for (int i0 = blockIdx.x * 4; i0 < m; i0 += gridDim.x * 4) {
-        const int i = i0 + w;
-        const bool active = i < m && ub[i] <= small_cap;
-        // table of the next power of two >= 2 ub slots (at least one per lane)
-        int slots = kWave;
-        if (active)
-            while (slots < 2 * ub[i]) slots <<= 1;
-        for (int s = lane; s < slots; s += kWave) table[s] = kEmpty;
-        if (lane == 0) counts[w] = 0;
-        __syncthreads();
-        int added = 0;
-        if (active) added = insert_row_keys(i, xrowptr, xcol, xdiag, yrowptr, ycol, table, slots - 1, lane, kWave);
-        __syncthreads();
-        if (mode == 0) {
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) added += __shfl_xor(added, o, kWave);
-            if (active && lane == 0) cnt[i] = added;
-        } else {
-            // emit_sorted synchronises the whole workgroup, so every wave runs it
-            int *list = lists[w];
-            int *dst = active ? ccol + crowptr[i] : nullptr;
-            for (int s = lane; s < slots; s += kWave) {
-                const int k = table[s];
-                if (active && k != kEmpty) list[atomicAdd(&counts[w], 1)] = k;
-            }
-            __syncthreads();
-            const int n = active ? counts[w] : 0;
-            for (int a = lane; a < n; a += kWave) {
-                const int k = list[a];
-                int r = 0;
-                for (int b = 0; b < n; ++b) r += (list[b] < k) ? 1 : 0;
-                dst[r] = k;
-            }
-        }
-        __syncthreads();
-    }
-}
-
 // Large rows (listed in big_list): one 256-thread workgroup per row, 64 KB hash.
 __global__ __launch_bounds__(256) void k_symbolic_large(const int *__restrict__ xrowptr, const int *__restrict__ xcol,
                                                        const int *__restrict__ xdiag, const int *__restrict__ yrowptr,
@@ -389,29 +337,6 @@ __device__ inline void row_pairs(int i, const int *__restrict__ xrowptr, const i
     }
 }
 
-// Rows with ub <= small cap: one 64-thread workgroup per row.
-__global__ __launch_bounds__(64) void k_pairs_small(const int *__restrict__ xrowptr, const int *__restrict__ xcol,
-                                                   const int *__restrict__ xdiag, const int *__restrict__ yrowptr,
-                                                   const int *__restrict__ ycol, int m, const int *__restrict__ ub,
-                                                   int small_cap, const int *__restrict__ crowptr,
-                                                   const int *__restrict__ ccol, const int *__restrict__ prow,
-                                                   int *__restrict__ pairptr, int2 *__restrict__ pairs) {
-    __shared__ int cols[kHashSmall / 2];
-    __shared__ int cnt[kHashSmall / 2];
-    if (blockIdx.x == 0 && threadIdx.x == 0) pairptr[crowptr[m]] = prow[m];   // the end of the last block's pairs
-    for (int i = blockIdx.x; i < m; i += gridDim.x) {
-        if (ub[i] > small_cap) continue;
-        const int c0 = crowptr[i], nout = crowptr[i + 1] - c0;
-        for (int p = threadIdx.x; p < nout; p += 64) {
-            cols[p] = ccol[c0 + p];
-            cnt[p] = 0;
-        }
-        __syncthreads();
-        row_pairs(i, xrowptr, xcol, xdiag, yrowptr, ycol, c0, nout, prow[i], cols, cnt, pairptr, pairs);
-        __syncthreads();
-    }
-}
-
 // Rows listed in big_list: one 256-thread workgroup per row.
 __global__ __launch_bounds__(256) void k_pairs_large(const int *__restrict__ xrowptr, const int *__restrict__ xcol,
                                                     const int *__restrict__ xdiag, const int *__restrict__ yrowptr,
@@ -431,6 +356,188 @@ __global__ __launch_bounds__(256) void k_pairs_large(const int *__restrict__ xro
         }
         __syncthreads();
         row_pairs(i, xrowptr, xcol, xdiag, yrowptr, ycol, c0, nout, prow[i], cols, cnt, pairptr, pairs);
+        __syncthreads();
+    }
+}
+
+// Intra-wave ordering of LDS traffic (the rows of k_symbolic_flat are per
+// wave and take different numbers of steps, so no workgroup barrier fits).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Up to 64 inner slots of output row i, one per lane: slot base + lane of the
+// row's sorted inner indices (X's row with its implicit identity block merged
+// in at its column).  A lane holds its slot's X block (-1: the identity), the
+// first Y block of the slot's Y row and the row's length, and the number of
+// products of the chunk's slots before its own; `total` is the chunk's count.
+struct SlotChunk {
+    int q, ybeg, len, excl, total;
+};
+
+__device__ inline SlotChunk load_slots(int base, int nk, int q0, int dslot, int dcol, const int *__restrict__ xcol,
+                                       const int *__restrict__ yrowptr, int lane) {
+    SlotChunk c{-1, 0, 0, 0, 0};
+    const int qq = base + lane;
+    if (qq < nk) {
+        const bool ident = qq == dslot;
+        c.q = ident ? -1 : q0 + qq - ((dslot >= 0 && qq > dslot) ? 1 : 0);
+        const int K = ident ? dcol : xcol[c.q];
+        c.ybeg = yrowptr[K];
+        c.len = yrowptr[K + 1] - c.ybeg;
+    }
+    int x = c.len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    c.excl = x - c.len;
+    c.total = __shfl(x, 63, 64);
+    return c;
+}
+
+// Product p < c.total of a chunk: the slot j holding it (the last lane whose
+// excl <= p; empty slots share their successor's excl and lie before it) and
+// its (X block, Y block) pair.  Every lane of the wave must call it (it reads
+// other lanes' registers); p >= c.total gives a pair of no meaning.
+__device__ inline int2 locate(const SlotChunk &c, int p) {
+    int j = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int e = __shfl(c.excl, j + step, 64);
+        if (e <= p) j += step;
+    }
+    const int q = __shfl(c.q, j, 64);
+    const int u = __shfl(c.ybeg, j, 64) + (p - __shfl(c.excl, j, 64));
+    return make_int2(q, u);
+}
+
+// Rows with ub <= small cap, one wave per row (4 per workgroup): every product
+// of the row is enumerated flat across the wave's lanes (a chunk of up to 64
+// inner slots at a time), so the row's loads do not queue behind one another
+// slot by slot.  mode 0: cnt[i] = the row's distinct output columns.  mode 1:
+// the sorted columns at ccol + crowptr[i], and each output block's pair list
+// (pairs at prow[i] ..., block t's from pairptr[t]) in ascending inner index:
+// products are counted per block, the counts scanned, and then placed in flat
+// order 64 at a time, each lane after the lanes before it in the same step
+// that feed the same block (a Y row feeds a block at most once).
+__global__ __launch_bounds__(256) void k_symbolic_flat(const int *__restrict__ xrowptr, const int *__restrict__ xcol,
+                                                      const int *__restrict__ xdiag, const int *__restrict__ yrowptr,
+                                                      const int *__restrict__ ycol, int m, const int *__restrict__ ub,
+                                                      int small_cap, int mode, int *__restrict__ cnt,
+                                                      const int *__restrict__ crowptr, int *__restrict__ ccol,
+                                                      const int *__restrict__ prow, int *__restrict__ pairptr,
+                                                      int2 *__restrict__ pairs) {
+    __shared__ int tables[4][kHashSmall];
+    __shared__ int lists[4][kHashSmall / 2];
+    __shared__ int counts[4];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int *table = tables[w];
+    int *list = lists[w];
+    if (mode == 1 && blockIdx.x == 0 && threadIdx.x == 0) pairptr[crowptr[m]] = prow[m];   // end of the last list
+    for (int i0 = blockIdx.x * 4; i0 < m; i0 += gridDim.x * 4) {
+        const int i = i0 + w;
+        const bool active = i < m && ub[i] <= small_cap;
+        // table of the next power of two >= 2 ub slots (at least one per lane)
+        int slots = kWave;
+        if (active)
+            while (slots < 2 * ub[i]) slots <<= 1;
+        for (int t = lane; t < slots; t += kWave) table[t] = kEmpty;
+        if (lane == 0) counts[w] = 0;
+        __syncthreads();
+        int q0 = 0, nk = 0, dslot = -1, dcol = 0;
+        if (active) {
+            q0 = xrowptr[i];
+            const int q1 = xrowptr[i + 1];
+            nk = q1 - q0;
+            if (xdiag) {
+                dcol = xdiag[i];
+                dslot = identity_slot(xcol, q0, q1, dcol);
+                ++nk;
+            }
+        }
+        int added = 0;
+        for (int base = 0; base < nk; base += kWave) {
+            const SlotChunk c = load_slots(base, nk, q0, dslot, dcol, xcol, yrowptr, lane);
+            for (int r0 = 0; r0 < c.total; r0 += kWave) {
+                const int p = r0 + lane;
+                const int2 pr = locate(c, p);
+                if (p < c.total) added += hash_insert(table, slots - 1, ycol[pr.y]) ? 1 : 0;
+            }
+        }
+        __syncthreads();
+        if (mode == 0) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) added += __shfl_xor(added, o, kWave);
+            if (active && lane == 0) cnt[i] = added;
+        } else {
+            for (int t = lane; t < slots; t += kWave) {
+                const int k = table[t];
+                if (active && k != kEmpty) list[atomicAdd(&counts[w], 1)] = k;
+            }
+            __syncthreads();
+            const int n = active ? counts[w] : 0;
+            // the sorted columns go to ccol and to the table's first n slots
+            int *sorted = table;
+            int *off = table + kHashSmall / 2;
+            const int c0 = active ? crowptr[i] : 0;
+            for (int a = lane; a < n; a += kWave) {
+                const int k = list[a];
+                int r = 0;
+                for (int b = 0; b < n; ++b) r += (list[b] < k) ? 1 : 0;
+                sorted[r] = k;
+                ccol[c0 + r] = k;
+            }
+            for (int a = lane; a < n; a += kWave) off[a] = 0;
+            wave_sync();
+            // products per output block, then their offsets
+            for (int base = 0; base < nk; base += kWave) {
+                const SlotChunk c = load_slots(base, nk, q0, dslot, dcol, xcol, yrowptr, lane);
+                for (int r0 = 0; r0 < c.total; r0 += kWave) {
+                    const int p = r0 + lane;
+                    const int2 pr = locate(c, p);
+                    if (p < c.total) atomicAdd(&off[find_pos(sorted, n, ycol[pr.y])], 1);
+                }
+            }
+            wave_sync();
+            int carry = 0;
+            for (int base = 0; base < n; base += kWave) {
+                const int v = base + lane < n ? off[base + lane] : 0;
+                int x = v;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(x, o, 64);
+                    if (lane >= o) x += y;
+                }
+                if (base + lane < n) off[base + lane] = carry + x - v;
+                carry += __shfl(x, 63, 64);
+            }
+            wave_sync();
+            const int P0 = active ? prow[i] : 0;
+            for (int a = lane; a < n; a += kWave) pairptr[c0 + a] = P0 + off[a];
+            wave_sync();
+            for (int base = 0; base < nk; base += kWave) {
+                const SlotChunk c = load_slots(base, nk, q0, dslot, dcol, xcol, yrowptr, lane);
+                for (int r0 = 0; r0 < c.total; r0 += kWave) {
+                    const int p = r0 + lane;
+                    int pos = -1;
+                    const int2 pr = locate(c, p);
+                    if (p < c.total) pos = find_pos(sorted, n, ycol[pr.y]);
+                    int rank = 0;
+                    for (int l = 0; l < kWave; ++l) {
+                        const int pl = __shfl(pos, l, 64);
+                        rank += (l < lane && pl == pos) ? 1 : 0;
+                    }
+                    if (pos >= 0) pairs[P0 + off[pos] + rank] = pr;
+                    wave_sync();
+                    if (pos >= 0) atomicAdd(&off[pos], 1);
+                    wave_sync();
+                }
+            }
+        }
         __syncthreads();
     }
 }
@@ -794,8 +901,8 @@ void spgemm_structure(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR
                                                       too_dense);
     const unsigned gs = cap_grid((m + 3) / 4);
     const size_t lds_large = sizeof(int) * (kHashLarge + kHashLarge / 2);
-    k_symbolic_small<<<gs, 256, 0, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(), Y.colidx.get(), m,
-                                        ub.get(), small_cap, 0, cnt.get(), nullptr, nullptr);
+    k_symbolic_flat<<<gs, 256, 0, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(), Y.colidx.get(), m,
+                                       ub.get(), small_cap, 0, cnt.get(), nullptr, nullptr, nullptr, nullptr, nullptr);
     {
         TimerScope ts(TK_SPGEMM_SYM, g_timer_level, s);
         k_symbolic_large<<<256, 256, lds_large, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(),
@@ -816,15 +923,13 @@ void spgemm_structure(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR
     if (nnz == 0) return;
     P.pairptr.alloc(static_cast<size_t>(nnz) + 1);
     P.pairs.alloc(npairs);
-    k_symbolic_small<<<gs, 256, 0, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(), Y.colidx.get(), m,
-                                        ub.get(), small_cap, 1, nullptr, C.rowptr.get(), C.colidx.get());
+    k_symbolic_flat<<<gs, 256, 0, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(), Y.colidx.get(), m,
+                                       ub.get(), small_cap, 1, nullptr, C.rowptr.get(), C.colidx.get(), prow.get(),
+                                       P.pairptr.get(), P.pairs.get());
     if (hflags[0] > 0)
         k_symbolic_large<<<256, 256, lds_large, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(),
                                                      Y.colidx.get(), big_list.get(), big_count, large_cap, 1, nullptr,
                                                      C.rowptr.get(), C.colidx.get(), ub.get());
-    k_pairs_small<<<cap_grid(m), 64, 0, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(), Y.colidx.get(), m,
-                                             ub.get(), small_cap, C.rowptr.get(), C.colidx.get(), prow.get(),
-                                             P.pairptr.get(), P.pairs.get());
     if (hflags[0] > 0)
         k_pairs_large<<<256, 256, 0, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(), Y.colidx.get(),
                                           big_list.get(), big_count, C.rowptr.get(), C.colidx.get(), prow.get(),
