@@ -53,7 +53,7 @@ def measured_traffic(workload: str, grid_threads: int):
     None when there is none for this launch shape or the kernel source has
     changed since it was measured."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_relax_traffic_{workload}.json")
+    path = os.path.join(ROOT, "profiles", f"k_sweep_traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -395,7 +395,7 @@ def main(argv=None):
             G //= 2
         rows_per_wg = 256 // (G * lvl["bs"])
         grid_threads = -(-rb["nF"] // rows_per_wg) * 256
-        roof = {"bound": "hbm", "kernel": f"k_relax (level {args.roofline_level} F sweep)",
+        roof = {"bound": "hbm", "kernel": f"k_sweep (level {args.roofline_level} F sweep)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(args.workload, grid_threads),
