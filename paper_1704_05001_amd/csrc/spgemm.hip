@@ -1,13 +1,15 @@
-// Row-wise block SpGEMM (Gustavson order) with LDS hash tables for the
-// symbolic phase and LDS accumulators for the numeric phase; union-add of
-// two block matrices; and the one-point Galerkin merge K = (R A) P with the
-// drop filter.
+// Row-wise block SpGEMM (Gustavson order): LDS hash tables for the symbolic
+// phase (a row's products enumerated flat across a wave), per-output-block
+// pair lists in the fixed accumulation order, and numeric kernels that walk
+// them (FP64 matrix cores for 9x9 and 16x16 blocks, one thread per block row
+// otherwise); union-add of two block matrices; and the Galerkin product
+// K = R A P with the one-point P and the drop filter.
 //
 // Determinism: every output entry is one fma chain over the inner block
 // index K ascending (the order of X's sorted row, with X's implicit identity
 // block merged in at its column), c ascending within a block product,
-// starting from +0.  Rows are independent; inside a row the K steps are
-// separated by barriers, and within a step each output entry has one writer.
+// starting from +0.  Rows are independent, and each output block's pairs are
+// applied in list order by the one wave or thread that owns the block.
 #include <algorithm>
 
 #include "common.h"
@@ -19,10 +21,6 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kEmpty = -1;
-constexpr int kNumThreads = 256;     // numeric kernels
-constexpr int kOutColsLds = 2048;    // output columns kept in LDS (else searched in global memory)
-constexpr int kPosLds = 512;         // Y-row positions per chunk
-constexpr int kAccBytes = 32768;     // LDS accumulator budget per workgroup
 
 __device__ inline bool hash_insert(int *table, int mask, int key) {
     unsigned slot = (static_cast<unsigned>(key) * 2654435761u) & static_cast<unsigned>(mask);
