@@ -127,6 +127,9 @@ void read_ints(const int *dptr, int *host, int n, hipStream_t s);
 // total_copy (nullable) receives the total too, so several totals can sit
 // side by side and come back to the host in one copy
 void scan_exclusive(const int *in, int *out, int n, hipStream_t s, int *total_copy = nullptr);
+// Two scans in the same launches (lengths n0, n1; total0 / total1 as total_copy).
+void scan_exclusive2(const int *in0, int *out0, int n0, int *total0, const int *in1, int *out1, int n1, int *total1,
+                     hipStream_t s);
 
 // ---------------------------------------------------------- setup kernels
 void launch_block_maxabs(const double *vals, int64_t nnzb, int bs, double *out, hipStream_t s);

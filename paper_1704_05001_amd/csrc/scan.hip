@@ -1,5 +1,8 @@
 // Exclusive prefix sums of int32 arrays: one workgroup for small arrays, else three
-// phases (tile scan, tile-offset scan, add).
+// phases (tile scan, tile-offset scan, add).  Two arrays can be scanned by the
+// same launches (the workgroup's grid index picks the array).
+#include <algorithm>
+
 #include "common.h"
 
 namespace nair {
@@ -8,6 +11,16 @@ namespace {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kScanThreads * kScanItems;
+
+// Up to two scans done together: in[k][0..n[k]) -> out[k] (out[k][n[k]] =
+// total), the total also to total_copy[k] when that is not null.
+struct ScanJobs {
+    const int *in[2];
+    int *out[2];
+    int *total_copy[2];
+    int *tiles[2];
+    int n[2];
+};
 
 // Exclusive scan of one value per thread over a 256-thread block; returns the
 // prefix and writes the block total to *total.
@@ -38,9 +51,13 @@ __device__ int block_exclusive_scan(int v, int *lds_waves, int *total) {
     return res;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int *__restrict__ in, int *__restrict__ out,
-                                                            int n, int *__restrict__ tile_sums) {
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(ScanJobs J) {
     __shared__ int lds[kScanThreads / 64 + 1];
+    const int n = J.n[blockIdx.y];
+    if (static_cast<int64_t>(blockIdx.x) * kScanTile >= n) return;   // past this array's tiles (whole block)
+    const int *__restrict__ in = J.in[blockIdx.y];
+    int *__restrict__ out = J.out[blockIdx.y];
+    int *__restrict__ tile_sums = J.tiles[blockIdx.y];
     const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
     int v[kScanItems];
     int s = 0;
@@ -61,11 +78,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int *__restri
     if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
 }
 
-// One block scans the tile sums in chunks of 256 with a running carry.
-__global__ __launch_bounds__(kScanThreads) void k_scan_tile_sums(int *__restrict__ tile_sums, int ntiles,
-                                                                int *__restrict__ grand_total,
-                                                                int *__restrict__ total_copy) {
+// One block per array scans its tile sums in chunks of 256 with a running carry.
+__global__ __launch_bounds__(kScanThreads) void k_scan_tile_sums(ScanJobs J) {
     __shared__ int lds[kScanThreads / 64 + 1];
+    const int n = J.n[blockIdx.x];
+    const int ntiles = static_cast<int>((static_cast<int64_t>(n) + kScanTile - 1) / kScanTile);
+    int *__restrict__ tile_sums = J.tiles[blockIdx.x];
+    int *__restrict__ grand_total = J.out[blockIdx.x] + n;
+    int *__restrict__ total_copy = J.total_copy[blockIdx.x];
     int carry = 0;
     for (int c0 = 0; c0 < ntiles; c0 += kScanThreads) {
         int i = c0 + threadIdx.x;
@@ -81,8 +101,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tile_sums(int *__restrict
     }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_add(int *__restrict__ out, int n,
-                                                          const int *__restrict__ tile_sums) {
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(ScanJobs J) {
+    const int n = J.n[blockIdx.y];
+    if (static_cast<int64_t>(blockIdx.x) * kScanTile >= n) return;
+    int *__restrict__ out = J.out[blockIdx.y];
+    const int *__restrict__ tile_sums = J.tiles[blockIdx.y];
     const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
     const int add = tile_sums[blockIdx.x];
     for (int k = threadIdx.x; k < kScanTile; k += kScanThreads) {
@@ -99,9 +122,12 @@ constexpr int kSmallWaves = kSmallThreads / 64;
 constexpr int kSmallStrips = 16;                                  // strips of 64 per wave
 constexpr int kSmallMax = kSmallWaves * kSmallStrips * 64;
 
-__global__ __launch_bounds__(kSmallThreads) void k_scan_small(const int *__restrict__ in, int *__restrict__ out,
-                                                             int n, int *__restrict__ total_copy) {
+__global__ __launch_bounds__(kSmallThreads) void k_scan_small(ScanJobs J) {
     __shared__ int wsum[kSmallWaves + 1];
+    const int n = J.n[blockIdx.x];
+    const int *__restrict__ in = J.in[blockIdx.x];
+    int *__restrict__ out = J.out[blockIdx.x];
+    int *__restrict__ total_copy = J.total_copy[blockIdx.x];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int strips = (n + kSmallWaves * 64 - 1) / (kSmallWaves * 64);   // per wave, <= kSmallStrips
@@ -150,25 +176,66 @@ __global__ __launch_bounds__(kSmallThreads) void k_scan_small(const int *__restr
 
 }  // namespace
 
-void scan_exclusive(const int *in, int *out, int n, hipStream_t s, int *total_copy) {
-    if (n <= 0) {
-        NAIR_HIP(hipMemsetAsync(out, 0, sizeof(int), s));
-        if (total_copy) NAIR_HIP(hipMemsetAsync(total_copy, 0, sizeof(int), s));
-        return;
+namespace {
+
+// Jobs with n <= 0 just get out[0] = 0 (and their total copy); the others share launches.
+void scan_jobs(ScanJobs J, int njobs, hipStream_t s) {
+    ScanJobs K{};
+    int nk = 0, nmax = 0;
+    for (int k = 0; k < njobs; ++k) {
+        if (J.n[k] <= 0) {
+            NAIR_HIP(hipMemsetAsync(J.out[k], 0, sizeof(int), s));
+            if (J.total_copy[k]) NAIR_HIP(hipMemsetAsync(J.total_copy[k], 0, sizeof(int), s));
+            continue;
+        }
+        K.in[nk] = J.in[k];
+        K.out[nk] = J.out[k];
+        K.total_copy[nk] = J.total_copy[k];
+        K.n[nk] = J.n[k];
+        nmax = std::max(nmax, J.n[k]);
+        ++nk;
     }
-    if (n <= kSmallMax) {
-        k_scan_small<<<1, kSmallThreads, 0, s>>>(in, out, n, total_copy);
+    if (nk == 0) return;
+    if (nmax <= kSmallMax) {
+        k_scan_small<<<nk, kSmallThreads, 0, s>>>(K);
         NAIR_HIP(hipGetLastError());
         return;
     }
-    const int ntiles = static_cast<int>((static_cast<int64_t>(n) + kScanTile - 1) / kScanTile);
-    DBuf<int> tiles(ntiles);
-    k_scan_tiles<<<ntiles, kScanThreads, 0, s>>>(in, out, n, tiles.get());
-    k_scan_tile_sums<<<1, kScanThreads, 0, s>>>(tiles.get(), ntiles, out + n, total_copy);
-    k_scan_add<<<ntiles, kScanThreads, 0, s>>>(out, n, tiles.get());
+    const int ntiles = static_cast<int>((static_cast<int64_t>(nmax) + kScanTile - 1) / kScanTile);
+    DBuf<int> tiles(static_cast<size_t>(ntiles) * nk);
+    for (int k = 0; k < nk; ++k) K.tiles[k] = tiles.get() + static_cast<int64_t>(k) * ntiles;
+    const dim3 grid(static_cast<unsigned>(ntiles), static_cast<unsigned>(nk));
+    k_scan_tiles<<<grid, kScanThreads, 0, s>>>(K);
+    k_scan_tile_sums<<<nk, kScanThreads, 0, s>>>(K);
+    k_scan_add<<<grid, kScanThreads, 0, s>>>(K);
     NAIR_HIP(hipGetLastError());
     // `tiles` returns to the pool now; any later user of that memory is ordered after
     // these kernels on the same stream (the library runs one call at a time).
+}
+
+}  // namespace
+
+void scan_exclusive(const int *in, int *out, int n, hipStream_t s, int *total_copy) {
+    ScanJobs J{};
+    J.in[0] = in;
+    J.out[0] = out;
+    J.total_copy[0] = total_copy;
+    J.n[0] = n;
+    scan_jobs(J, 1, s);
+}
+
+void scan_exclusive2(const int *in0, int *out0, int n0, int *total0, const int *in1, int *out1, int n1, int *total1,
+                     hipStream_t s) {
+    ScanJobs J{};
+    J.in[0] = in0;
+    J.out[0] = out0;
+    J.total_copy[0] = total0;
+    J.n[0] = n0;
+    J.in[1] = in1;
+    J.out[1] = out1;
+    J.total_copy[1] = total1;
+    J.n[1] = n1;
+    scan_jobs(J, 2, s);
 }
 
 }  // namespace nair

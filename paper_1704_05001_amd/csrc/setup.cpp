@@ -330,9 +330,9 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         {
             DBuf<int> cntT(n), cntW(nc), dtot(2);
             launch_count_T(L.A.rowptr.get(), L.A.colidx.get(), L.mask.get(), L.cf.get(), n, cntT.get(), s);
-            scan_exclusive(cntT.get(), T.rowptr.get(), n, s, dtot.get());
             launch_count_Acf(L.A.rowptr.get(), L.A.colidx.get(), L.cf.get(), L.cpts.get(), nc, cntW.get(), s);
-            scan_exclusive(cntW.get(), W0.rowptr.get(), nc, s, dtot.get() + 1);
+            scan_exclusive2(cntT.get(), T.rowptr.get(), n, dtot.get(), cntW.get(), W0.rowptr.get(), nc, dtot.get() + 1,
+                            s);
             read_ints(dtot.get(), tot, 2, s);
         }
         const int nT = tot[0], nW = tot[1];

@@ -828,26 +828,46 @@ __global__ __launch_bounds__(256) void k_rap_values(int64_t nnz, int bb, const i
 }
 
 // Drop filter: keep the diagonal and blocks with size > drop * size(diagonal).
+// One wave per row, its lanes over the row's blocks.
 __global__ __launch_bounds__(256) void k_drop_mark(const int *__restrict__ krp, const int *__restrict__ kcol,
                                                   const double *__restrict__ knorm, int m, double drop,
                                                   uint8_t *__restrict__ keep, int *__restrict__ kept,
                                                   int *__restrict__ margin) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    double dn = 0.0;
-    for (int t = krp[i]; t < krp[i + 1]; ++t)
-        if (kcol[t] == i) dn = knorm[t];
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + static_cast<int>(threadIdx.x >> 6);
+    if (i >= m) return;   // whole waves
+    const int lo = krp[i], hi = krp[i + 1];
+    double dn = 0.0;   // the diagonal block's size (0 if the row has none)
+    for (int base = lo; base < hi; base += 64) {
+        const int t = base + lane;
+        const bool isd = t < hi && kcol[t] == i;
+        const double v = isd ? knorm[t] : 0.0;
+        const unsigned long long b = __ballot(isd);
+        if (b != 0ull) {
+            dn = __shfl(v, static_cast<int>(__builtin_ctzll(b)), 64);
+            break;
+        }
+    }
     const double thr = drop * dn;
     int c = 0, nties = 0;
-    for (int t = krp[i]; t < krp[i + 1]; ++t) {
-        const bool k = (kcol[t] == i) || (knorm[t] > thr);
+    for (int t = lo + lane; t < hi; t += 64) {
+        const bool diag = kcol[t] == i;
+        const double kn = knorm[t];
+        const bool k = diag || (kn > thr);
         keep[t] = k ? 1 : 0;
         c += k ? 1 : 0;
         // audit: the two sides of the drop test within 1e-12 relative
-        if (kcol[t] != i && fabs(knorm[t] - thr) <= 1e-12 * fmax(fabs(knorm[t]), fabs(thr))) ++nties;
+        if (!diag && fabs(kn - thr) <= 1e-12 * fmax(fabs(kn), fabs(thr))) ++nties;
     }
-    kept[i] = c;
-    if (nties) atomicAdd(margin + 3, nties);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        c += __shfl_xor(c, o, 64);
+        nties += __shfl_xor(nties, o, 64);
+    }
+    if (lane == 0) {
+        kept[i] = c;
+        if (nties) atomicAdd(margin + 3, nties);
+    }
 }
 
 
@@ -908,8 +928,7 @@ void spgemm_structure(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR
                                                      cnt.get(), nullptr, nullptr, ub.get());
     }
     NAIR_HIP(hipGetLastError());
-    scan_exclusive(cnt.get(), C.rowptr.get(), m, s, flags.get() + 2);
-    scan_exclusive(ub.get(), prow.get(), m, s, flags.get() + 3);
+    scan_exclusive2(cnt.get(), C.rowptr.get(), m, flags.get() + 2, ub.get(), prow.get(), m, flags.get() + 3, s);
     int hflags[4] = {0, 0, 0, 0};
     read_ints(flags.get(), hflags, 4, s);
     const int nnz = hflags[2], npairs = hflags[3];
@@ -1014,8 +1033,7 @@ void galerkin(const DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap
                                       flags.get());
     k_rap_count_contrib<<<grid_for(m, 256), 256, 0, s>>>(RA.rowptr.get(), RA.colidx.get(), pmap, m, ccnt.get());
     NAIR_HIP(hipGetLastError());
-    scan_exclusive(cnt.get(), krp.get(), m, s, flags.get() + 1);
-    scan_exclusive(ccnt.get(), crow.get(), m, s, flags.get() + 2);
+    scan_exclusive2(cnt.get(), krp.get(), m, flags.get() + 1, ccnt.get(), crow.get(), m, flags.get() + 2, s);
     int hflags[3] = {0, 0, 0};
     read_ints(flags.get(), hflags, 3, s);
     const int too_dense = hflags[0], nnz = hflags[1], ncontrib = hflags[2];
@@ -1051,8 +1069,8 @@ void galerkin(const DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap
         NAIR_HIP(hipGetLastError());
     }
     if (!fused) launch_block_maxabs(kval.get(), nnz, bs, knorm.get(), s);
-    k_drop_mark<<<grid_for(m, 256), 256, 0, s>>>(krp.get(), kcol.get(), knorm.get(), m, drop, keep.get(), kept.get(),
-                                                 margin);
+    k_drop_mark<<<static_cast<unsigned>(std::max((m + 3) / 4, 1)), 256, 0, s>>>(krp.get(), kcol.get(), knorm.get(), m, drop,
+                                                                    keep.get(), kept.get(), margin);
     NAIR_HIP(hipGetLastError());
     K.nb = nc;
     K.ncols = nc;
