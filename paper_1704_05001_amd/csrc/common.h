@@ -72,9 +72,13 @@ struct DBuf {
 };
 
 // Device block-CSR matrix: nb rows, ncols block columns, bs x bs row-major blocks.
+// nnzb < 0: the block count is only on the device (rowptr[nb]) and the arrays
+// hold cap blocks; it is read back with a later synchronisation.
 struct DevBSR {
     int nb = 0, ncols = 0, bs = 0;
     int64_t nnzb = 0;
+    int64_t cap = 0;
+    int64_t bound() const { return nnzb >= 0 ? nnzb : cap; }
     DBuf<int> rowptr, colidx;
     DBuf<double> vals;
     void alloc(int nb_, int ncols_, int bs_, int64_t nnzb_) {
@@ -170,9 +174,10 @@ void launch_count_Acf(const int *rowptr, const int *colidx, const int8_t *cf, co
                       int *cnt, hipStream_t s);
 void launch_fill_Acf(const int *rowptr, const int *colidx, const int8_t *cf, const int *cpts, int nc,
                      const int *wrowptr, int *wcol, int *wsrc, hipStream_t s);
-// out[t] = sign * (X[xi[t]] * Y[yi[t]]) for n blocks (fma chain, c ascending)
+// out[t] = sign * (X[xi[t]] * Y[yi[t]]) for n blocks (fma chain, c ascending);
+// count (device, nullable): only the first *count <= n blocks
 void launch_block_product(int64_t n, int bs, const double *X, const int *xi, const double *Y, const int *yi,
-                          double sign, double *out, hipStream_t s);
+                          double sign, double *out, hipStream_t s, const int *count = nullptr);
 // out[t] = Y[src[t]]
 void launch_block_gather(int64_t n, int bs, const double *Y, const int *src, double *out, hipStream_t s);
 void launch_rows_of(const int *rowptr, int nrows, int *rowid, hipStream_t s);
@@ -181,7 +186,8 @@ void launch_rows_of(const int *rowptr, int nrows, int *rowid, hipStream_t s);
 // C = X * Y (+ optional implicit identity block of X at column xdiag[i]).
 // Fixed accumulation order: inner index ascending, c ascending, one fma chain.
 void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipStream_t s);
-// O = S + W (union pattern, S's value first)
+// O = S + W (union pattern, S's value first).  O's block count stays on the
+// device (O.nnzb = -1, arrays of S.bound() + W.bound() blocks).
 void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s);
 // The Galerkin product K = R A P with R = [Z I] (identity at column cpts[i] of
 // row i) and P one-point through pmap, filtered by drop.  K block (i, J) is the
@@ -191,7 +197,8 @@ void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s);
 // margin[3] += off-diagonal blocks whose drop test is within 1e-12 relative;
 // knext receives the block max-abs size of every kept block of K (the next
 // level's block norms).
-void galerkin(const DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int nc, double drop, DevBSR &K,
+// A block count of Z left on the device is read back with the first synchronisation.
+void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int nc, double drop, DevBSR &K,
               int *margin, DBuf<double> &knext, hipStream_t s);
 
 // ------------------------------------------------------------------ dense

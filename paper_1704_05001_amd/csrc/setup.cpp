@@ -373,12 +373,13 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         L.Z.nb = nc;
         L.Z.ncols = n;
         L.Z.bs = bs;
-        L.Z.nnzb = Ssum.nnzb;
+        L.Z.nnzb = Ssum.nnzb;   // (on the device when S is a sum; the Galerkin step reads it back)
+        L.Z.cap = Ssum.bound();
         L.Z.rowptr = std::move(Ssum.rowptr);
         L.Z.colidx = std::move(Ssum.colidx);
-        L.Z.vals.alloc(static_cast<size_t>(L.Z.nnzb) * bb);
-        launch_block_product(L.Z.nnzb, bs, Ssum.vals.get(), nullptr, L.dinv.get(), L.Z.colidx.get(), -1.0,
-                             L.Z.vals.get(), s);
+        L.Z.vals.alloc(static_cast<size_t>(L.Z.cap) * bb);
+        launch_block_product(L.Z.cap, bs, Ssum.vals.get(), nullptr, L.dinv.get(), L.Z.colidx.get(), -1.0,
+                             L.Z.vals.get(), s, L.Z.nnzb < 0 ? L.Z.rowptr.get() + nc : nullptr);
         // Galerkin: K = R A P with R = [Z I], filtered; K's block sizes come along
         auto next = std::make_unique<Level>();
         galerkin(L.Z, L.cpts.get(), L.A, L.pmap.get(), nc, p.drop, next->A, L.margin.get(), next->bnorm, s);

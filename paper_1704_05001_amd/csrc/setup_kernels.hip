@@ -539,11 +539,11 @@ template <int BS>
 __global__ __launch_bounds__(256) void k_block_product(int64_t n, int bs_rt, const double *__restrict__ X,
                                                       const int *__restrict__ xi, const double *__restrict__ Y,
                                                       const int *__restrict__ yi, double sign,
-                                                      double *__restrict__ out) {
+                                                      double *__restrict__ out, const int *__restrict__ count) {
     constexpr int NB = BS > 0 ? BS : kMaxBs;
     const int bs = BS > 0 ? BS : bs_rt;
     const int bb = bs * bs;
-    const int64_t total = n * bs;
+    const int64_t total = (count ? *count : n) * bs;
     for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
          g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int64_t t = g / bs;
@@ -578,13 +578,13 @@ template <int BS>
 __global__ __launch_bounds__(256) void k_block_product_mfma(int64_t n, const double *__restrict__ X,
                                                            const int *__restrict__ xi, const double *__restrict__ Y,
                                                            const int *__restrict__ yi, double sign,
-                                                           double *__restrict__ out) {
+                                                           double *__restrict__ out, const int *__restrict__ count) {
     constexpr int bb = BS * BS;
     constexpr int KQ = (BS + 3) / 4;
     const int lane = threadIdx.x & 63;
     const int row = lane & 15, kk = lane >> 4;
     const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
-    if (t >= n) return;   // whole waves
+    if (t >= (count ? *count : n)) return;   // whole waves
     const double *x = X + static_cast<int64_t>(xi ? xi[t] : t) * bb;
     const double *y = Y + static_cast<int64_t>(yi[t]) * bb;
     double a[KQ], b[KQ];
@@ -739,22 +739,22 @@ void launch_fill_Acf(const int *rowptr, const int *colidx, const int8_t *cf, con
 }
 
 void launch_block_product(int64_t n, int bs, const double *X, const int *xi, const double *Y, const int *yi,
-                          double sign, double *out, hipStream_t s) {
+                          double sign, double *out, hipStream_t s, const int *count) {
     if (n <= 0) return;
     if (bs == 9 || bs == 16) {
         const unsigned mgrid = static_cast<unsigned>((n + 3) / 4);   // four waves (blocks) per workgroup
-        if (bs == 9) k_block_product_mfma<9><<<mgrid, 256, 0, s>>>(n, X, xi, Y, yi, sign, out);
-        else k_block_product_mfma<16><<<mgrid, 256, 0, s>>>(n, X, xi, Y, yi, sign, out);
+        if (bs == 9) k_block_product_mfma<9><<<mgrid, 256, 0, s>>>(n, X, xi, Y, yi, sign, out, count);
+        else k_block_product_mfma<16><<<mgrid, 256, 0, s>>>(n, X, xi, Y, yi, sign, out, count);
         NAIR_HIP(hipGetLastError());
         return;
     }
     const unsigned grid = cap_grid((n * bs + 255) / 256);
     switch (bs) {
-        case 4: k_block_product<4><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out); break;
-        case 9: k_block_product<9><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out); break;
-        case 16: k_block_product<16><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out); break;
-        case 25: k_block_product<25><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out); break;
-        default: k_block_product<0><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out); break;
+        case 4: k_block_product<4><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out, count); break;
+        case 9: k_block_product<9><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out, count); break;
+        case 16: k_block_product<16><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out, count); break;
+        case 25: k_block_product<25><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out, count); break;
+        default: k_block_product<0><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out, count); break;
     }
     NAIR_HIP(hipGetLastError());
 }

@@ -179,10 +179,11 @@ __global__ __launch_bounds__(256) void k_add_fill(const int *__restrict__ srp, c
     }
 }
 
-__global__ __launch_bounds__(256) void k_add_values(int64_t n, int bb, const double *__restrict__ S,
+// blocks t < *count of O (count on the device)
+__global__ __launch_bounds__(256) void k_add_values(const int *__restrict__ count, int bb, const double *__restrict__ S,
                                                    const int *__restrict__ srcS, const double *__restrict__ W,
                                                    const int *__restrict__ srcW, double *__restrict__ O) {
-    const int64_t total = n * bb;
+    const int64_t total = static_cast<int64_t>(*count) * bb;
     for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
          g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int64_t t = g / bb;
@@ -997,21 +998,23 @@ void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s) {
         k_add_count<<<grid_for(m, 256), 256, 0, s>>>(S.rowptr.get(), S.colidx.get(), W.rowptr.get(), W.colidx.get(),
                                                      m, cnt.get());
     scan_exclusive(cnt.get(), O.rowptr.get(), m, s);
-    const int nnz = read_int(O.rowptr.get() + m, s);
-    O.nnzb = nnz;
-    O.colidx.alloc(nnz);
-    O.vals.alloc(static_cast<size_t>(nnz) * bs * bs);
-    if (nnz == 0) return;
-    DBuf<int> srcS(nnz), srcW(nnz);
+    // the union has at most the two counts together; the exact count stays on the device
+    const int64_t cap = S.bound() + W.bound();
+    O.nnzb = -1;
+    O.cap = cap;
+    O.colidx.alloc(static_cast<size_t>(cap));
+    O.vals.alloc(static_cast<size_t>(cap) * bs * bs);
+    if (cap == 0 || m == 0) return;
+    DBuf<int> srcS(static_cast<size_t>(cap)), srcW(static_cast<size_t>(cap));
     k_add_fill<<<grid_for(m, 256), 256, 0, s>>>(S.rowptr.get(), S.colidx.get(), W.rowptr.get(), W.colidx.get(), m,
                                                 O.rowptr.get(), O.colidx.get(), srcS.get(), srcW.get());
-    const int64_t total = static_cast<int64_t>(nnz) * bs * bs;
-    k_add_values<<<cap_grid((total + 255) / 256), 256, 0, s>>>(nnz, bs * bs, S.vals.get(), srcS.get(), W.vals.get(),
-                                                              srcW.get(), O.vals.get());
+    const int64_t total = cap * bs * bs;
+    k_add_values<<<cap_grid((total + 255) / 256), 256, 0, s>>>(O.rowptr.get() + m, bs * bs, S.vals.get(),
+                                                              srcS.get(), W.vals.get(), srcW.get(), O.vals.get());
     NAIR_HIP(hipGetLastError());
 }
 
-void galerkin(const DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int nc, double drop, DevBSR &K,
+void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int nc, double drop, DevBSR &K,
               int *margin, DBuf<double> &knext, hipStream_t s) {
     // R A's pattern and pair lists; its values only where no fused kernel takes the blocks
     DevBSR RA;
@@ -1035,7 +1038,12 @@ void galerkin(const DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap
     NAIR_HIP(hipGetLastError());
     scan_exclusive2(cnt.get(), krp.get(), m, flags.get() + 1, ccnt.get(), crow.get(), m, flags.get() + 2, s);
     int hflags[3] = {0, 0, 0};
-    read_ints(flags.get(), hflags, 3, s);
+    int zcount = 0;
+    const bool zdev = Z.nnzb < 0;   // Z's block count comes back with this read
+    read_device({{flags.get(), hflags, sizeof(int) * 3},
+                 {zdev ? Z.rowptr.get() + Z.nb : nullptr, &zcount, zdev ? sizeof(int) : 0}},
+                s);
+    if (zdev) Z.nnzb = zcount;
     const int too_dense = hflags[0], nnz = hflags[1], ncontrib = hflags[2];
     if (too_dense > 0)
         fail(NAIR_ENOMEM, "Galerkin row has " + std::to_string(too_dense) + " blocks (limit " +
