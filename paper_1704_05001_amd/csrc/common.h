@@ -124,6 +124,7 @@ struct ReadItem {
     size_t bytes;
 };
 void read_device(std::initializer_list<ReadItem> items, hipStream_t s);
+void read_device(const ReadItem *items, size_t nitems, hipStream_t s);
 int read_int(const int *dptr, hipStream_t s);
 void read_ints(const int *dptr, int *host, int n, hipStream_t s);
 
@@ -148,7 +149,9 @@ void launch_strong_transpose(const int *rowptr, const int *colidx, const uint8_t
 // splitting states: -1 undecided, 0 F, 1 C, 2 block of a directly solved system
 void launch_pmis_init(const int *lambda, const int8_t *direct, int nb, int8_t *state, int *dround,
                       int *undecided0, hipStream_t s);
-// lbase (nullable): first block of each block's system; hashes use the index within the system
+// lbase (nullable): first block of each block's system; hashes use the index within the system.
+// undecided[0] receives the blocks still undecided after the round; when undecided[-1]
+// (the previous round's count, or the start's) is 0 the round does nothing.
 void launch_pmis_round(const int *rowptr, const int *colidx, const uint8_t *mask, const int *stptr,
                        const int *stidx, const int *lambda, const int *lbase, int nb, uint64_t seed, int level,
                        int round, int8_t *state, int8_t *newc, int *dround, int *undecided, hipStream_t s);

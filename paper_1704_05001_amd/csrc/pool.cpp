@@ -194,12 +194,13 @@ Stage &stage() {
 
 }  // namespace
 
-void read_device(std::initializer_list<ReadItem> items, hipStream_t s) {
+void read_device(const ReadItem *items, size_t nitems, hipStream_t s) {
     size_t total = 0;
-    for (const ReadItem &it : items) total += (it.bytes + 7) & ~static_cast<size_t>(7);
+    for (size_t k = 0; k < nitems; ++k) total += (items[k].bytes + 7) & ~static_cast<size_t>(7);
     if (total > kStageBytes) {   // large reads copy directly
-        for (const ReadItem &it : items)
-            if (it.bytes) NAIR_HIP(hipMemcpyAsync(it.host, it.dev, it.bytes, hipMemcpyDeviceToHost, s));
+        for (size_t k = 0; k < nitems; ++k)
+            if (items[k].bytes)
+                NAIR_HIP(hipMemcpyAsync(items[k].host, items[k].dev, items[k].bytes, hipMemcpyDeviceToHost, s));
         NAIR_HIP(hipStreamSynchronize(s));
         return;
     }
@@ -207,17 +208,20 @@ void read_device(std::initializer_list<ReadItem> items, hipStream_t s) {
     std::lock_guard<std::mutex> lk(st.mu);
     if (!st.buf) NAIR_HIP(hipHostMalloc(reinterpret_cast<void **>(&st.buf), kStageBytes, hipHostMallocPortable));
     size_t off = 0;
-    for (const ReadItem &it : items) {
-        if (it.bytes) NAIR_HIP(hipMemcpyAsync(st.buf + off, it.dev, it.bytes, hipMemcpyDeviceToHost, s));
-        off += (it.bytes + 7) & ~static_cast<size_t>(7);
+    for (size_t k = 0; k < nitems; ++k) {
+        if (items[k].bytes)
+            NAIR_HIP(hipMemcpyAsync(st.buf + off, items[k].dev, items[k].bytes, hipMemcpyDeviceToHost, s));
+        off += (items[k].bytes + 7) & ~static_cast<size_t>(7);
     }
     NAIR_HIP(hipStreamSynchronize(s));
     off = 0;
-    for (const ReadItem &it : items) {
-        if (it.bytes) std::memcpy(it.host, st.buf + off, it.bytes);
-        off += (it.bytes + 7) & ~static_cast<size_t>(7);
+    for (size_t k = 0; k < nitems; ++k) {
+        if (items[k].bytes) std::memcpy(items[k].host, st.buf + off, items[k].bytes);
+        off += (items[k].bytes + 7) & ~static_cast<size_t>(7);
     }
 }
+
+void read_device(std::initializer_list<ReadItem> items, hipStream_t s) { read_device(items.begin(), items.size(), s); }
 
 int read_int(const int *dptr, hipStream_t s) {
     int v = 0;

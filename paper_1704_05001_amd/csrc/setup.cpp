@@ -15,6 +15,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <initializer_list>
 #include <utility>
 
@@ -23,7 +24,7 @@
 namespace nair {
 namespace {
 
-constexpr int kRoundBatch = 4;
+constexpr int kRoundBatch = 8;
 constexpr int kMaxRounds = 4096;
 constexpr int kNoSingular = 0x7f7f7f7f;   // memset(0x7f) pattern
 
@@ -95,7 +96,10 @@ void make_direct(Level &L, int lvl, hipStream_t s) {
 }
 
 // C/F splitting by independent-set rounds; state ends as 1 (C) / 0 (F) in L.cf.
-void split(Hier &h, Level &L, int lvl, hipStream_t s) {
+// After each batch of rounds `enqueue` launches work whose results `extra`
+// reads back with the round counts (the last batch's are what the caller gets).
+void split(Hier &h, Level &L, int lvl, hipStream_t s, const std::function<void()> &enqueue,
+           const std::vector<ReadItem> &extra) {
     const int n = L.A.nb;
     const int64_t nz = L.A.nnzb;
     DBuf<int> stptr(static_cast<size_t>(n) + 1), fill(n), stidx(nz > 0 ? nz : 1);
@@ -107,22 +111,26 @@ void split(Hier &h, Level &L, int lvl, hipStream_t s) {
     DBuf<int> counts(kMaxRounds + 1);
     NAIR_HIP(hipMemsetAsync(counts.get(), 0, sizeof(int) * (kMaxRounds + 1), s));
     launch_pmis_init(L.lambda.get(), L.direct.get(), n, L.cf.get(), L.dround.get(), counts.get(), s);
-    int undecided0 = read_int(counts.get(), s);
+    // rounds go out kRoundBatch at a time (a round after the last one with undecided
+    // blocks returns at once), then one read of the counts before and after each
     L.rounds = 0;
-    if (undecided0 == 0) return;
     int r = 0;
     while (true) {
+        const int first = r;
         for (int b = 0; b < kRoundBatch; ++b) {
             ++r;
             launch_pmis_round(L.A.rowptr.get(), L.A.colidx.get(), L.mask.get(), stptr.get(), stidx.get(),
                               L.lambda.get(), L.lbase.get(), n, h.prm.seed, lvl, r, L.cf.get(), newc.get(),
                               L.dround.get(), counts.get() + r, s);
         }
-        int hc[kRoundBatch];
-        read_ints(counts.get() + r - kRoundBatch + 1, hc, kRoundBatch, s);
-        for (int b = 0; b < kRoundBatch; ++b)
+        int hc[kRoundBatch + 1];
+        enqueue();
+        std::vector<ReadItem> items{{counts.get() + first, hc, sizeof(hc)}};
+        items.insert(items.end(), extra.begin(), extra.end());
+        read_device(items.data(), items.size(), s);
+        for (int b = 0; b <= kRoundBatch; ++b)
             if (hc[b] == 0) {
-                L.rounds = r - kRoundBatch + 1 + b;
+                L.rounds = first + b;   // 0: nothing was undecided at the start
                 return;
             }
         if (r + kRoundBatch > kMaxRounds) fail(NAIR_ECOARSEN, "splitting did not finish");
@@ -248,25 +256,30 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
             if (L.direct.get()) launch_mark_direct(L.direct.get(), n, L.cf.get(), s);
             NAIR_HIP(hipStreamSynchronize(s));   // cfh is pageable host memory
             L.rounds = 0;
-        } else {
-            split(h, L, l, s);
         }
+        // coarse blocks per system (as offsets) and the singular flag: counted on the
+        // device after the splitting and read back with its last round counts
         DBuf<int> cflag(n), cscan(static_cast<size_t>(n) + 1);
         std::vector<int> cseg(nsys + 2);   // coarse blocks per system, as offsets; then the singular flag
         DBuf<int> cseg_d(nsys + 2);
-        auto count_c = [&]() {
+        cseg[0] = 0;
+        auto count_c_launch = [&]() {
             launch_cf_flags(L.cf.get(), n, 1, cflag.get(), s);
             scan_exclusive(cflag.get(), cscan.get(), n, s);
-            if (nsys == 1) {   // one system: its C count is the scan's total
-                cseg[0] = 0;
-                read_device({{cscan.get() + n, &cseg[1], sizeof(int)}, {sing.get(), &cseg[2], sizeof(int)}}, s);
-                return;
-            }
+            if (nsys == 1) return;   // one system: its C count is the scan's total
             launch_gather_int(cscan.get(), L.seg_d.get(), nsys + 1, cseg_d.get(), s);
             NAIR_HIP(hipMemcpyAsync(cseg_d.get() + nsys + 1, sing.get(), sizeof(int), hipMemcpyDeviceToDevice, s));
-            read_ints(cseg_d.get(), cseg.data(), nsys + 2, s);
         };
-        count_c();
+        const std::vector<ReadItem> count_c_items =
+            nsys == 1 ? std::vector<ReadItem>{{cscan.get() + n, &cseg[1], sizeof(int)},
+                                              {sing.get(), &cseg[2], sizeof(int)}}
+                      : std::vector<ReadItem>{{cseg_d.get(), cseg.data(), sizeof(int) * (nsys + 2)}};
+        auto count_c = [&]() {
+            count_c_launch();
+            read_device(count_c_items.data(), count_c_items.size(), s);
+        };
+        if (l == 0 && p.cf_override_host) count_c();
+        else split(h, L, l, s, count_c_launch, count_c_items);
         const int hsing = cseg[nsys + 1];
         if (hsing != kNoSingular)
             fail(NAIR_ESINGULAR, "diagonal block " + std::to_string(hsing) + " of level " + std::to_string(l) +

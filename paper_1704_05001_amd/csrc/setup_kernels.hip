@@ -333,7 +333,9 @@ __global__ __launch_bounds__(256) void k_pmis_select(const int *__restrict__ row
                                                     const uint8_t *__restrict__ mask, const int *__restrict__ stptr,
                                                     const int *__restrict__ stidx, const int *__restrict__ lambda,
                                                     const int *__restrict__ lbase, int nb, uint64_t seed, int level,
-                                                    const int8_t *__restrict__ state, int8_t *__restrict__ newc) {
+                                                    const int8_t *__restrict__ state, int8_t *__restrict__ newc,
+                                                    const int *__restrict__ prev) {
+    if (*prev == 0) return;   // nothing was left undecided: the round has nothing to do
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= nb) return;
     if (state[I] != kUnd) {
@@ -366,6 +368,7 @@ __global__ __launch_bounds__(256) void k_pmis_update(const int *__restrict__ row
                                                     const uint8_t *__restrict__ mask, int nb, int round,
                                                     int8_t *__restrict__ state, const int8_t *__restrict__ newc,
                                                     int *__restrict__ dround, int *__restrict__ undecided) {
+    if (undecided[-1] == 0) return;   // as k_pmis_select: the splitting has finished
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= nb) return;
     if (state[I] != kUnd) return;
@@ -670,7 +673,7 @@ void launch_pmis_round(const int *rowptr, const int *colidx, const uint8_t *mask
                        const int *lambda, const int *lbase, int nb, uint64_t seed, int level, int round,
                        int8_t *state, int8_t *newc, int *dround, int *undecided, hipStream_t s) {
     k_pmis_select<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, mask, stptr, stidx, lambda, lbase, nb, seed,
-                                                    level, state, newc);
+                                                    level, state, newc, undecided - 1);
     k_pmis_update<<<grid_for(nb, 256), 256, 0, s>>>(rowptr, colidx, mask, nb, round, state, newc, dround,
                                                     undecided);
     NAIR_HIP(hipGetLastError());
