@@ -181,8 +181,9 @@ void launch_fill_Acf(const int *rowptr, const int *colidx, const int8_t *cf, con
 // count (device, nullable): only the first *count <= n blocks
 void launch_block_product(int64_t n, int bs, const double *X, const int *xi, const double *Y, const int *yi,
                           double sign, double *out, hipStream_t s, const int *count = nullptr);
-// out[t] = Y[src[t]]
-void launch_block_gather(int64_t n, int bs, const double *Y, const int *src, double *out, hipStream_t s);
+// out[t] = Y[src[t]] for t < n (count, device, nullable: t < *count <= n)
+void launch_block_gather(int64_t n, int bs, const double *Y, const int *src, double *out, hipStream_t s,
+                         const int *count = nullptr);
 void launch_rows_of(const int *rowptr, int nrows, int *rowid, hipStream_t s);
 
 // ------------------------------------------------------------------ SpGEMM
@@ -199,8 +200,9 @@ void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s);
 // never stored: each K block is summed straight from their pair lists.
 // margin[3] += off-diagonal blocks whose drop test is within 1e-12 relative;
 // knext receives the block max-abs size of every kept block of K (the next
-// level's block norms).
-// A block count of Z left on the device is read back with the first synchronisation.
+// level's block norms).  K's block count stays on the device (K.nnzb = -1,
+// arrays of the unfiltered count).  A block count of Z left on the device is
+// read back with the first synchronisation.
 void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int nc, double drop, DevBSR &K,
               int *margin, DBuf<double> &knext, hipStream_t s);
 

@@ -101,7 +101,7 @@ void make_direct(Level &L, int lvl, hipStream_t s) {
 void split(Hier &h, Level &L, int lvl, hipStream_t s, const std::function<void()> &enqueue,
            const std::vector<ReadItem> &extra) {
     const int n = L.A.nb;
-    const int64_t nz = L.A.nnzb;
+    const int64_t nz = L.A.bound();
     DBuf<int> stptr(static_cast<size_t>(n) + 1), fill(n), stidx(nz > 0 ? nz : 1);
     scan_exclusive(L.lambda.get(), stptr.get(), n, s);
     NAIR_HIP(hipMemsetAsync(fill.get(), 0, sizeof(int) * n, s));
@@ -222,11 +222,12 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
             launch_seg_info(L.seg_d.get(), L.mode_d.get(), nsys, n, L.lbase.get(), L.direct.get(), L.bsys.get(), s);
         }
         if (ncont == 0) {
+            if (L.A.nnzb < 0) L.A.nnzb = read_int(L.A.rowptr.get() + n, s);
             L.coarsest = true;
             make_direct(L, l, s);
             break;
         }
-        const int64_t nz = L.A.nnzb;
+        const int64_t nz = L.A.bound();   // (the exact count comes back with the splitting's read)
         L.dinv.alloc(static_cast<size_t>(n) * bb);
         if (!L.bnorm_ready) L.bnorm.alloc(nz);
         L.mask.alloc(nz);
@@ -278,8 +279,12 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
             count_c_launch();
             read_device(count_c_items.data(), count_c_items.size(), s);
         };
+        int anz = 0;
+        std::vector<ReadItem> split_items = count_c_items;
+        if (L.A.nnzb < 0) split_items.push_back({L.A.rowptr.get() + n, &anz, sizeof(int)});
         if (l == 0 && p.cf_override_host) count_c();
-        else split(h, L, l, s, count_c_launch, count_c_items);
+        else split(h, L, l, s, count_c_launch, split_items);
+        if (L.A.nnzb < 0) L.A.nnzb = anz;
         const int hsing = cseg[nsys + 1];
         if (hsing != kNoSingular)
             fail(NAIR_ESINGULAR, "diagonal block " + std::to_string(hsing) + " of level " + std::to_string(l) +

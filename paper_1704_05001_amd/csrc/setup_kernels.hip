@@ -609,8 +609,9 @@ __global__ __launch_bounds__(256) void k_block_product_mfma(int64_t n, const dou
 }
 
 __global__ __launch_bounds__(256) void k_block_gather(int64_t n, int bb, const double *__restrict__ Y,
-                                                     const int *__restrict__ src, double *__restrict__ out) {
-    const int64_t total = n * bb;
+                                                     const int *__restrict__ src, double *__restrict__ out,
+                                                     const int *__restrict__ count) {
+    const int64_t total = (count ? *count : n) * bb;
     for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
          g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int64_t t = g / bb;
@@ -762,9 +763,10 @@ void launch_block_product(int64_t n, int bs, const double *X, const int *xi, con
     NAIR_HIP(hipGetLastError());
 }
 
-void launch_block_gather(int64_t n, int bs, const double *Y, const int *src, double *out, hipStream_t s) {
+void launch_block_gather(int64_t n, int bs, const double *Y, const int *src, double *out, hipStream_t s,
+                         const int *count) {
     if (n <= 0) return;
-    k_block_gather<<<cap_grid((n * bs * bs + 255) / 256), 256, 0, s>>>(n, bs * bs, Y, src, out);
+    k_block_gather<<<cap_grid((n * bs * bs + 255) / 256), 256, 0, s>>>(n, bs * bs, Y, src, out, count);
     NAIR_HIP(hipGetLastError());
 }
 

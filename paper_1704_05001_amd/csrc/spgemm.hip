@@ -1085,17 +1085,19 @@ void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int 
     K.bs = bs;
     K.rowptr.alloc(static_cast<size_t>(nc) + 1);
     scan_exclusive(kept.get(), K.rowptr.get(), m, s);
-    const int nk = read_int(K.rowptr.get() + m, s);
-    K.nnzb = nk;
-    K.colidx.alloc(nk);
-    K.vals.alloc(static_cast<size_t>(nk) * bb);
-    knext.alloc(nk);
-    DBuf<int> src(nk);
+    // the kept count stays on the device (the next level reads it back with its first read)
+    K.nnzb = -1;
+    K.cap = nnz;
+    K.colidx.alloc(static_cast<size_t>(nnz));
+    K.vals.alloc(static_cast<size_t>(nnz) * bb);
+    knext.alloc(static_cast<size_t>(nnz));
+    const int *nk = K.rowptr.get() + m;
+    DBuf<int> src(static_cast<size_t>(nnz));
     k_compact_fill<<<grid_for(m, 256), 256, 0, s>>>(krp.get(), kcol.get(), keep.get(), m, K.rowptr.get(),
                                                     K.colidx.get(), src.get());
     NAIR_HIP(hipGetLastError());
-    launch_block_gather(nk, bs, kval.get(), src.get(), K.vals.get(), s);
-    launch_block_gather(nk, 1, knorm.get(), src.get(), knext.get(), s);   // a block's size is its max-abs entry
+    launch_block_gather(nnz, bs, kval.get(), src.get(), K.vals.get(), s, nk);
+    launch_block_gather(nnz, 1, knorm.get(), src.get(), knext.get(), s, nk);   // a block's size is its max-abs entry
 }
 
 }  // namespace nair
