@@ -178,9 +178,11 @@ void launch_count_Acf(const int *rowptr, const int *colidx, const int8_t *cf, co
 void launch_fill_Acf(const int *rowptr, const int *colidx, const int8_t *cf, const int *cpts, int nc,
                      const int *wrowptr, int *wcol, int *wsrc, hipStream_t s);
 // out[t] = sign * (X[xi[t]] * Y[yi[t]]) for n blocks (fma chain, c ascending);
-// count (device, nullable): only the first *count <= n blocks
+// count (device, nullable): only the first *count <= n blocks; rmask
+// (nullable, 9x9 and 16x16 blocks): each product's nonzero rows as a bit mask
 void launch_block_product(int64_t n, int bs, const double *X, const int *xi, const double *Y, const int *yi,
-                          double sign, double *out, hipStream_t s, const int *count = nullptr);
+                          double sign, double *out, hipStream_t s, const int *count = nullptr,
+                          uint32_t *rmask = nullptr);
 // out[t] = Y[src[t]] for t < n (count, device, nullable: t < *count <= n)
 void launch_block_gather(int64_t n, int bs, const double *Y, const int *src, double *out, hipStream_t s,
                          const int *count = nullptr);
@@ -203,8 +205,10 @@ void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s);
 // level's block norms).  K's block count stays on the device (K.nnzb = -1,
 // arrays of the unfiltered count).  A block count of Z left on the device is
 // read back with the first synchronisation.
+// kmask receives the row masks of K's kept blocks where the fused kernel forms
+// them (9x9 and 16x16 blocks; left unallocated otherwise).
 void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int nc, double drop, DevBSR &K,
-              int *margin, DBuf<double> &knext, hipStream_t s);
+              int *margin, DBuf<double> &knext, DBuf<uint32_t> &kmask, hipStream_t s);
 
 // ------------------------------------------------------------------ dense
 // For each segment k < nseg (host arrays): the dense operator of A's block rows
@@ -247,13 +251,39 @@ struct FaceView {
     int cmax = 0, rc = 0;
 };
 
+// ------------------------------------------------------------ row blocks
+// A list of bs x bs blocks stored by their nonzero rows: block t keeps the
+// mask of its nonzero rows and those rows, whole and in ascending order, at
+// vals[off[t]] ... (popcount(mask) * bs entries).  Z's blocks are nonzero only
+// on the rows of the C element's nodes that face F neighbours.
+struct RowBlocks {
+    bool on = false;
+    DBuf<uint32_t> mask;
+    DBuf<int> off;   // [n + 1]
+    DBuf<double> vals;
+    DBuf<float> vals32;
+};
+// Blocks vals[src[d]] (src null: vals[d]) for d < *count (count null: n); the
+// others are left empty.  Returns false (building nothing) when n * bs * bs
+// exceeds int32 offsets.
+// masks (nullable): the blocks' row masks, indexed like vals (read instead of the entries).
+bool build_row_blocks(const double *vals, int64_t n, int bs, RowBlocks &R, hipStream_t s, const int *src = nullptr,
+                      const int *count = nullptr, const uint32_t *masks = nullptr);
+void row_blocks_to_float(RowBlocks &R, int64_t n, int bs, hipStream_t s);
+template <typename MT>
+struct RowBlockView {
+    const uint32_t *mask = nullptr;   // null: whole blocks
+    const int *off = nullptr;
+    const MT *vals = nullptr;
+};
+
 // ----------------------------------------------------------- sweep copy
 // What a Jacobi F sweep reads, stored in the order it reads it: the F rows of
 // a level operator (or of its transpose) in F-list order, each without its
 // diagonal block, and D_F^{-1} in the same order.  Row f (the F list's f-th
 // row) holds blocks rowptr[f] .. rowptr[f+1]-1 in the row's ascending column
-// order: whole [bs][bs] blocks, or, where the operator has a face-compressed
-// copy (rc > 0), that copy's masks and rmax x cmax rectangles.  Storage for
+// order: by their nonzero rows (RowBlocks), or, where the operator has a
+// face-compressed copy (rc > 0), that copy's masks and rmax x cmax rectangles.  Storage for
 // vals and colidx is sized by the operator's block count (the exact count is
 // rowptr[nF] on the device; nothing is read back).
 struct SweepCopy {
@@ -264,10 +294,12 @@ struct SweepCopy {
     DBuf<uint64_t> meta;
     DBuf<double> vals, dinv;
     DBuf<float> vals32;
+    RowBlocks rows;                  // the blocks by their nonzero rows (no face copy)
 };
 // Build S from A (and its face copy F when F.on) for the rows of flist.
+// amask (nullable): row masks of A's blocks.
 void build_sweep(const DevBSR &A, const FaceCopy &F, const double *dinv, const int *flist, int nF, SweepCopy &S,
-                 hipStream_t s);
+                 hipStream_t s, const uint32_t *amask = nullptr);
 void sweep_to_float(SweepCopy &S, int bs, hipStream_t s);
 
 template <typename MT>
@@ -277,6 +309,7 @@ struct SweepView {
     const MT *vals = nullptr;
     const double *dinv = nullptr;
     int cmax = 0, rc = 0;
+    RowBlockView<MT> rows{};          // else the blocks by their nonzero rows
 };
 
 // ------------------------------------------------------------------ cycle
@@ -291,6 +324,7 @@ struct MatView {
     int groups = 0;   // lane groups per block row for the kernel reading it (0: from the row length)
     FaceView<MT> face{};
     SweepView<MT> sweep{};   // F sweeps over the F list read this when rowptr != null
+    RowBlockView<MT> rows{};   // the same blocks by their nonzero rows, when the level keeps them
     MatView with_groups(int g) const {
         MatView v = *this;
         v.groups = g;
@@ -378,7 +412,8 @@ void launch_seg_init(const double *part, const int *cptr, int nsys, double *bn, 
 void launch_seg_check(const double *part, const int *cptr, int nsys, const double *bn, const double *rtol,
                       int hist_cap, double *hist, double *last, int *active, int *status, int *iters, int *it,
                       int *nact, int *nact_acc, hipStream_t s);
-void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s);
+// out[i] = (float) in[i] for i < n (count, device, nullable: i < min(n, *count))
+void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s, const int *count = nullptr);
 
 // ------------------------------------------------------------ scalar form
 // S = D^{-1} A as a scalar matrix (bs 1): identity diagonal blocks exact,

@@ -155,6 +155,53 @@ __device__ inline double row_part_face(const int *__restrict__ colidx, const Fac
     return acc0 + acc1;
 }
 
+// The same row product over blocks kept by their nonzero rows (RowBlockView):
+// block t's row a, when nonzero, is bs entries at vals[off[t] + rank(a) * bs],
+// summed exactly as row_part sums it; a zero row's products are exact zeros
+// and are left out, so for finite x the result equals row_part's bit for bit.
+template <int BS, typename MT, typename VT>
+__device__ inline double row_part_rows(const int *__restrict__ colidx, const RowBlockView<MT> &R, int lo, int hi,
+                                       int g, int G, int a, int bs_rt, const VT *__restrict__ x) {
+    const int bs = Bs<BS>::get(bs_rt);
+    const uint32_t below = (1u << a) - 1u;
+    double acc0 = 0.0, acc1 = 0.0;
+    int t = lo + g;
+    if (t >= hi) return acc0 + acc1;
+    // the next block's column, mask and offset load while this block's row and x do
+    int J = colidx[t];
+    uint32_t m = R.mask[t];
+    int o = R.off[t];
+    for (;;) {
+        const int tn = t + G;
+        int Jn = 0, on = 0;
+        uint32_t mn = 0u;
+        if (tn < hi) {
+            Jn = colidx[tn];
+            mn = R.mask[tn];
+            on = R.off[tn];
+        }
+        if ((m >> a) & 1u) {
+            const MT *blk = R.vals + o + __popc(m & below) * bs;
+            const VT *xj = x + static_cast<int64_t>(J) * bs;
+            if constexpr (BS > 0) {
+#pragma unroll
+                for (int c = 0; c < BS; c += 2) {
+                    acc0 += static_cast<double>(blk[c]) * static_cast<double>(xj[c]);
+                    if (c + 1 < BS) acc1 += static_cast<double>(blk[c + 1]) * static_cast<double>(xj[c + 1]);
+                }
+            } else {
+                for (int c = 0; c < bs; ++c) acc0 += static_cast<double>(blk[c]) * static_cast<double>(xj[c]);
+            }
+        }
+        if (tn >= hi) break;
+        t = tn;
+        J = Jn;
+        m = mn;
+        o = on;
+    }
+    return acc0 + acc1;
+}
+
 // Row I's product with x (SKIP: without its diagonal block).
 template <int BS, bool FACE, typename MT, typename VT, bool SKIP = false>
 __device__ inline double row_product(const int *__restrict__ colidx, const MT *__restrict__ vals,
@@ -322,7 +369,8 @@ __device__ inline void relax_rows(const int *__restrict__ rowptr, const int *__r
 }
 
 // The same sweep over the F list from a sweep copy: row f of the copy is F row
-// I = flist[f] without its diagonal block, D_I^{-1} sits at position f.  The
+// I = flist[f] without its diagonal block (face rectangles, or blocks by their
+// nonzero rows), D_I^{-1} sits at position f.  The
 // copy keeps each row's blocks in order, so with one lane group per row the
 // sums are relax_rows' bit for bit (with G > 1 the blocks are dealt to the
 // groups from the row's start, which moves the diagonal's gap).
@@ -353,7 +401,7 @@ __device__ inline void sweep_rows(const SweepView<MT> &S, const int *__restrict_
             acc = row_part_face<BS, MT, VT>(S.colidx, FaceView<MT>{S.meta, S.vals, nullptr, S.cmax, S.rc}, lo, hi,
                                             L.g, G, L.a, -1, bs, ein);
         else
-            acc = row_part<BS, MT, VT>(S.colidx, S.vals, lo, hi, L.g, G, L.a, bs, ein);
+            acc = row_part_rows<BS, MT, VT>(S.colidx, S.rows, lo, hi, L.g, G, L.a, bs, ein);
     }
     acc = reduce_groups(acc, L, G, bs, part);
     if (I >= 0 && L.g == 0) tb[L.lr * bs + L.a] = rv - acc;
@@ -469,18 +517,22 @@ __global__ __launch_bounds__(kThreads) void k_relax_interp(const int *__restrict
     }
 }
 
-// rc_i = r_{cpts[i]} + sum_t Z_it r_{col t}
-template <int BS, typename MT, typename VT>
+// rc_i = r_{cpts[i]} + sum_t Z_it r_{col t} (RB: Z's blocks by their nonzero rows)
+template <int BS, typename MT, typename VT, bool RB = false>
 __global__ __launch_bounds__(kThreads) void k_restrict(const int *__restrict__ zrp, const int *__restrict__ zcol,
                                                       const MT *__restrict__ zval, int nc, int bs_rt, int G,
                                                       const VT *__restrict__ r, const int *__restrict__ cpts,
-                                                      VT *__restrict__ rc, Gate gate) {
+                                                      VT *__restrict__ rc, Gate gate, RowBlockView<MT> zr) {
     __shared__ double part[kThreads];
     const int bs = Bs<BS>::get(bs_rt);
     const Lane L = lane_of(G, bs);
     const int i = blockIdx.x * (kThreads / (G * bs)) + L.lr;
     const bool act = L.valid && i < nc && live(gate, i);
-    double acc = act ? row_part<BS>(zcol, zval, zrp[i], zrp[i + 1], L.g, G, L.a, bs, r) : 0.0;
+    double acc = 0.0;
+    if (act) {
+        if constexpr (RB) acc = row_part_rows<BS, MT, VT>(zcol, zr, zrp[i], zrp[i + 1], L.g, G, L.a, bs, r);
+        else acc = row_part<BS>(zcol, zval, zrp[i], zrp[i + 1], L.g, G, L.a, bs, r);
+    }
     acc = reduce_groups(acc, L, G, bs, part);
     if (act && L.g == 0)
         rc[static_cast<int64_t>(i) * bs + L.a] =
@@ -705,7 +757,9 @@ __global__ void k_seg_tick(int reset, int *__restrict__ it, int *__restrict__ na
     *nact_acc = 0;
 }
 
-__global__ __launch_bounds__(256) void k_to_float(const double *__restrict__ in, float *__restrict__ out, int64_t n) {
+__global__ __launch_bounds__(256) void k_to_float(const double *__restrict__ in, float *__restrict__ out, int64_t n,
+                                                 const int *__restrict__ count) {
+    if (count && *count < n) n = *count;
     for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n;
          g += static_cast<int64_t>(gridDim.x) * blockDim.x)
         out[g] = static_cast<float>(in[g]);
@@ -740,7 +794,8 @@ unsigned grid_rows(int64_t rows, int G, int bs) { return grid_for(rows, kThreads
 // A launch must not read an operator the level does not hold.
 template <typename MT>
 void need(const MatView<MT> &A, const char *what) {
-    if (A.nb > 0 && (!A.rowptr || !A.colidx || !A.vals))
+    // (a row-compressed copy stands in for the blocks)
+    if (A.nb > 0 && (!A.rowptr || !A.colidx || (!A.vals && !A.rows.mask)))
         fail(NAIR_EDEVICE, std::string(what) + ": the level holds no such operator");
     if (A.face.meta && (!A.face.vals || !A.face.dvals || A.bs > 32))
         fail(NAIR_EDEVICE, std::string(what) + ": incomplete face-compressed copy");
@@ -761,7 +816,8 @@ void need(const MatView<MT> &A, const char *what) {
         default: KERNEL<0, MT, VT> __VA_ARGS__; break;       \
     }
 
-// Face-compressed instances: the block sizes of Q1..Q4 elements, others at run time.
+// Instances with the last flag set (face-compressed or row-compressed blocks):
+// the block sizes of Q1..Q4 elements, others at run time.
 #define NAIR_FACE_DISPATCH(bs, KERNEL, ...)                    \
     switch (bs) {                                              \
         case 4: KERNEL<4, MT, VT, true> __VA_ARGS__; break;    \
@@ -804,6 +860,8 @@ void launch_relax(const MatView<MT> &A, const double *dinv, bool dinv_trans, con
     const unsigned grid = grid_rows(N, G, A.bs);
     if (list && A.sweep.rowptr) {   // F sweep from the level's sweep copy (built for this F list)
         const SweepView<MT> &S = A.sweep;
+        if ((S.meta ? !S.vals : (!S.rows.mask || !S.rows.off || !S.rows.vals)) || !S.dinv || A.bs > 32)
+            fail(NAIR_EDEVICE, "launch_relax: incomplete sweep copy");
         if (dinv_trans && S.meta) {
             NAIR_FACE_DISPATCH(A.bs, k_sweep_T, <<<grid, kThreads, 0, s>>>(S, list, nlist, A.bs, G, r, ein, eout,
                                                                            gate));
@@ -854,8 +912,14 @@ void launch_restrict(const MatView<MT> &Z, const VT *r, const int *cpts, VT *rc,
     if (Z.nb <= 0) return;
     const int G = groups_for(Z);
     const unsigned grid = grid_rows(Z.nb, G, Z.bs);
-    NAIR_BS_DISPATCH(Z.bs, k_restrict, <<<grid, kThreads, 0, s>>>(Z.rowptr, Z.colidx, Z.vals, Z.nb, Z.bs, G, r, cpts,
-                                                                  rc, gate));
+    if (Z.rows.mask) {
+        if (!Z.rows.off || !Z.rows.vals || Z.bs > 32) fail(NAIR_EDEVICE, "launch_restrict: incomplete row copy of Z");
+        NAIR_FACE_DISPATCH(Z.bs, k_restrict, <<<grid, kThreads, 0, s>>>(Z.rowptr, Z.colidx, Z.vals, Z.nb, Z.bs, G, r,
+                                                                        cpts, rc, gate, Z.rows));
+    } else {
+        NAIR_BS_DISPATCH(Z.bs, k_restrict, <<<grid, kThreads, 0, s>>>(Z.rowptr, Z.colidx, Z.vals, Z.nb, Z.bs, G, r,
+                                                                      cpts, rc, gate, Z.rows));
+    }
     NAIR_HIP(hipGetLastError());
 }
 
@@ -968,10 +1032,10 @@ void launch_seg_check(const double *part, const int *cptr, int nsys, const doubl
     NAIR_HIP(hipGetLastError());
 }
 
-void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s) {
+void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s, const int *count) {
     if (n <= 0) return;
     const int64_t g = (n + 255) / 256;
-    k_to_float<<<static_cast<unsigned>(g > 1048576 ? 1048576 : g), 256, 0, s>>>(in, out, n);
+    k_to_float<<<static_cast<unsigned>(g > 1048576 ? 1048576 : g), 256, 0, s>>>(in, out, n, count);
     NAIR_HIP(hipGetLastError());
 }
 

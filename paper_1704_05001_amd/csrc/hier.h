@@ -65,6 +65,11 @@ struct Level {
     FaceCopy face, faceT;
     // F rows of A and A^T in F-list order without their diagonal blocks, for the sweeps
     SweepCopy sweep, sweepT;
+    // Z's blocks by their nonzero rows, for the restriction (levels with sweep copies)
+    RowBlocks zrows;
+    // bit masks of the nonzero rows of Z's and A's blocks, where the kernels
+    // that form those blocks produce them (9x9 and 16x16 blocks; A below level 0)
+    DBuf<uint32_t> zmask, amask;
 };
 
 // A_l (trans: A_l^T) as the cycle kernels read it: with its face-compressed
@@ -77,7 +82,8 @@ inline MatView<double> op_view(const Level &L, bool trans) {
     const SweepCopy &S = trans ? L.sweepT : L.sweep;
     if (S.on)
         v.sweep = SweepView<double>{S.rowptr.get(), S.colidx.get(), S.rc ? S.meta.get() : nullptr, S.vals.get(),
-                                    S.dinv.get(), S.cmax, S.rc};
+                                    S.dinv.get(), S.cmax, S.rc,
+                                    RowBlockView<double>{S.rows.mask.get(), S.rows.off.get(), S.rows.vals.get()}};
     return v;
 }
 inline MatView<float> op_view32(const Level &L, bool trans) {
@@ -87,7 +93,20 @@ inline MatView<float> op_view32(const Level &L, bool trans) {
     const SweepCopy &S = trans ? L.sweepT : L.sweep;
     if (S.on)
         v.sweep = SweepView<float>{S.rowptr.get(), S.colidx.get(), S.rc ? S.meta.get() : nullptr, S.vals32.get(),
-                                   S.dinv.get(), S.cmax, S.rc};
+                                   S.dinv.get(), S.cmax, S.rc,
+                                   RowBlockView<float>{S.rows.mask.get(), S.rows.off.get(), S.rows.vals32.get()}};
+    return v;
+}
+
+// Z as the restriction reads it: by its blocks' nonzero rows where the level keeps them.
+inline MatView<double> z_view(const Level &L) {
+    MatView<double> v = view(L.Z);
+    if (L.zrows.on) v.rows = RowBlockView<double>{L.zrows.mask.get(), L.zrows.off.get(), L.zrows.vals.get()};
+    return v;
+}
+inline MatView<float> z_view32(const Level &L) {
+    MatView<float> v = view(L.Z, L.z32.get());
+    if (L.zrows.on) v.rows = RowBlockView<float>{L.zrows.mask.get(), L.zrows.off.get(), L.zrows.vals32.get()};
     return v;
 }
 

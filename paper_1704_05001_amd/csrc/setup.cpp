@@ -396,11 +396,15 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         L.Z.rowptr = std::move(Ssum.rowptr);
         L.Z.colidx = std::move(Ssum.colidx);
         L.Z.vals.alloc(static_cast<size_t>(L.Z.cap) * bb);
+        const bool masks = bs == 9 || bs == 16;   // the matrix-core products give each block's nonzero rows
+        if (masks) L.zmask.alloc(static_cast<size_t>(L.Z.cap));
         launch_block_product(L.Z.cap, bs, Ssum.vals.get(), nullptr, L.dinv.get(), L.Z.colidx.get(), -1.0,
-                             L.Z.vals.get(), s, L.Z.nnzb < 0 ? L.Z.rowptr.get() + nc : nullptr);
+                             L.Z.vals.get(), s, L.Z.nnzb < 0 ? L.Z.rowptr.get() + nc : nullptr,
+                             masks ? L.zmask.get() : nullptr);
         // Galerkin: K = R A P with R = [Z I], filtered; K's block sizes come along
         auto next = std::make_unique<Level>();
-        galerkin(L.Z, L.cpts.get(), L.A, L.pmap.get(), nc, p.drop, next->A, L.margin.get(), next->bnorm, s);
+        galerkin(L.Z, L.cpts.get(), L.A, L.pmap.get(), nc, p.drop, next->A, L.margin.get(), next->bnorm,
+                 next->amask, s);
         next->bnorm_ready = true;
         next->seg.assign(cseg.begin(), cseg.begin() + nsys + 1);
         next->mode.assign(nsys, 0);
@@ -420,8 +424,12 @@ void build_sweeps(Hier &h, bool trans, hipStream_t s) {
         if (L.coarsest || L.nF <= 0) continue;
         if (h.prm.sweep_copy < 0 && few_lanes(L.A.nb, L.A.bs)) continue;
         SweepCopy &S = trans ? L.sweepT : L.sweep;
-        if (S.on) continue;
-        build_sweep(trans ? L.AT : L.A, trans ? L.faceT : L.face, L.dinv.get(), L.flist.get(), L.nF, S, s);
+        // (A's row masks, where the Galerkin step gave them, are no use for A^T)
+        if (!S.on)
+            build_sweep(trans ? L.AT : L.A, trans ? L.faceT : L.face, L.dinv.get(), L.flist.get(), L.nF, S, s,
+                        trans ? nullptr : L.amask.get());
+        if (!trans && !L.zrows.on && L.Z.nnzb > 0)
+            build_row_blocks(L.Z.vals.get(), L.Z.nnzb, L.Z.bs, L.zrows, s, nullptr, nullptr, L.zmask.get());
     }
 }
 
@@ -443,7 +451,7 @@ void make_fp32_copies(Hier &h, hipStream_t s) {
         if (!L.vals32.get()) {
             L.vals32.alloc(static_cast<size_t>(L.A.nnzb * bb));
             launch_to_float(L.A.vals.get(), L.vals32.get(), L.A.nnzb * bb, s);
-            if (!L.coarsest) {
+            if (!L.coarsest && !L.zrows.on) {   // (with a row-compressed Z the restriction reads only that)
                 L.z32.alloc(static_cast<size_t>(L.Z.nnzb * bb));
                 launch_to_float(L.Z.vals.get(), L.z32.get(), L.Z.nnzb * bb, s);
             }
@@ -460,6 +468,7 @@ void make_fp32_copies(Hier &h, hipStream_t s) {
         if (L.have_T) face_to_float(L.AT, L.faceT, s);
         sweep_to_float(L.sweep, L.A.bs, s);
         sweep_to_float(L.sweepT, L.A.bs, s);
+        row_blocks_to_float(L.zrows, L.Z.nnzb, L.A.bs, s);
     }
 }
 

@@ -581,7 +581,8 @@ template <int BS>
 __global__ __launch_bounds__(256) void k_block_product_mfma(int64_t n, const double *__restrict__ X,
                                                            const int *__restrict__ xi, const double *__restrict__ Y,
                                                            const int *__restrict__ yi, double sign,
-                                                           double *__restrict__ out, const int *__restrict__ count) {
+                                                           double *__restrict__ out, const int *__restrict__ count,
+                                                           uint32_t *__restrict__ rmask) {
     constexpr int bb = BS * BS;
     constexpr int KQ = (BS + 3) / 4;
     const int lane = threadIdx.x & 63;
@@ -601,10 +602,20 @@ __global__ __launch_bounds__(256) void k_block_product_mfma(int64_t n, const dou
 #pragma unroll
     for (int q = 0; q < KQ; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc, 0, 0, 0);
     double *o = out + t * bb;
+    uint32_t bits = 0u;   // this lane's nonzero rows, then the block's
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = kk + 4 * r;
-        if (i < BS && row < BS) o[i * BS + row] = sign * acc[r];
+        if (i < BS && row < BS) {
+            const double v = sign * acc[r];
+            o[i * BS + row] = v;
+            if (v != 0.0) bits |= 1u << i;
+        }
+    }
+    if (rmask) {
+#pragma unroll
+        for (int w = 32; w > 0; w >>= 1) bits |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(bits), w, 64));
+        if (lane == 0) rmask[t] = bits;
     }
 }
 
@@ -743,15 +754,16 @@ void launch_fill_Acf(const int *rowptr, const int *colidx, const int8_t *cf, con
 }
 
 void launch_block_product(int64_t n, int bs, const double *X, const int *xi, const double *Y, const int *yi,
-                          double sign, double *out, hipStream_t s, const int *count) {
+                          double sign, double *out, hipStream_t s, const int *count, uint32_t *rmask) {
     if (n <= 0) return;
     if (bs == 9 || bs == 16) {
         const unsigned mgrid = static_cast<unsigned>((n + 3) / 4);   // four waves (blocks) per workgroup
-        if (bs == 9) k_block_product_mfma<9><<<mgrid, 256, 0, s>>>(n, X, xi, Y, yi, sign, out, count);
-        else k_block_product_mfma<16><<<mgrid, 256, 0, s>>>(n, X, xi, Y, yi, sign, out, count);
+        if (bs == 9) k_block_product_mfma<9><<<mgrid, 256, 0, s>>>(n, X, xi, Y, yi, sign, out, count, rmask);
+        else k_block_product_mfma<16><<<mgrid, 256, 0, s>>>(n, X, xi, Y, yi, sign, out, count, rmask);
         NAIR_HIP(hipGetLastError());
         return;
     }
+    if (rmask) fail(NAIR_EDEVICE, "launch_block_product: row masks only for 9x9 and 16x16 blocks");
     const unsigned grid = cap_grid((n * bs + 255) / 256);
     switch (bs) {
         case 4: k_block_product<4><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out, count); break;

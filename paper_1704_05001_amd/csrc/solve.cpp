@@ -24,7 +24,7 @@ struct Store;
 template <>
 struct Store<double> {
     static MatView<double> A(const Level &L) { return op_view(L, false).with_groups(L.tune[TU_RELAX]); }
-    static MatView<double> Z(const Level &L) { return view(L.Z).with_groups(L.tune[TU_RESTRICT]); }
+    static MatView<double> Z(const Level &L) { return z_view(L).with_groups(L.tune[TU_RESTRICT]); }
     static MatView<double> AT(const Level &L) { return op_view(L, true).with_groups(L.tune[TU_RELAX_T]); }
     static MatView<double> ZT(const Level &L) { return view(L.ZT).with_groups(L.tune[TU_INTERP_T]); }
     static double *r(Level &L) { return L.r.get(); }
@@ -37,7 +37,7 @@ struct Store<double> {
 template <>
 struct Store<float> {
     static MatView<float> A(const Level &L) { return op_view32(L, false).with_groups(L.tune[TU_RELAX]); }
-    static MatView<float> Z(const Level &L) { return view(L.Z, L.z32.get()).with_groups(L.tune[TU_RESTRICT]); }
+    static MatView<float> Z(const Level &L) { return z_view32(L).with_groups(L.tune[TU_RESTRICT]); }
     static MatView<float> AT(const Level &L) { return op_view32(L, true).with_groups(L.tune[TU_RELAX_T]); }
     static MatView<float> ZT(const Level &L) { return view(L.ZT, L.zt32.get()).with_groups(L.tune[TU_INTERP_T]); }
     static float *r(Level &L) { return L.r32.get(); }

@@ -685,13 +685,14 @@ __global__ __launch_bounds__(256) void k_spgemm_mfma(int64_t nnz, const int *__r
 // the merge over stored R A blocks, without storing them).  One wave per K
 // block; the lanes hold up to 64 contributing blocks' pair ranges, and the
 // walk over their pairs loads the next pair (of the same or the next block)
-// while the current one's steps run.  Also writes the block's max-abs size.
+// while the current one's steps run.  Also writes the block's max-abs size
+// and the bit mask of its nonzero rows.
 template <int BS>
 __global__ __launch_bounds__(256) void k_galerkin_mfma(int64_t nnz, const int *__restrict__ kptr,
                                                       const int *__restrict__ klist, const int *__restrict__ pairptr,
                                                       const int2 *__restrict__ pairs, const double *__restrict__ X,
                                                       const double *__restrict__ Y, double *__restrict__ K,
-                                                      double *__restrict__ knorm) {
+                                                      double *__restrict__ knorm, uint32_t *__restrict__ kmask) {
     constexpr int bb = BS * BS;
     constexpr int KQ = MfmaPair<BS>::KQ;
     const int lane = threadIdx.x & 63;
@@ -742,17 +743,33 @@ __global__ __launch_bounds__(256) void k_galerkin_mfma(int64_t nnz, const int *_
     }
     double *out = K + t * bb;
     double m = 0.0;
+    uint32_t bits = 0u;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = kk + 4 * r;
         if (r < KQ && i < BS && row < BS) {
             out[i * BS + row] = kacc[r];
             m = fmax(m, fabs(kacc[r]));
+            if (kacc[r] != 0.0) bits |= 1u << i;
         }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-    if (lane == 0) knorm[t] = m;
+    for (int o = 32; o > 0; o >>= 1) {
+        m = fmax(m, __shfl_xor(m, o, 64));
+        bits |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(bits), o, 64));
+    }
+    if (lane == 0) {
+        knorm[t] = m;
+        kmask[t] = bits;
+    }
+}
+
+// out[t] = in[src[t]] for t < *count
+__global__ __launch_bounds__(256) void k_gather_mask(int64_t n, const uint32_t *__restrict__ in,
+                                                    const int *__restrict__ src, const int *__restrict__ count,
+                                                    uint32_t *__restrict__ out) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < n && t < *count) out[t] = in[src[t]];
 }
 
 // ---------------------------------------------------- Galerkin merge lists
@@ -1015,7 +1032,7 @@ void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s) {
 }
 
 void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int nc, double drop, DevBSR &K,
-              int *margin, DBuf<double> &knext, hipStream_t s) {
+              int *margin, DBuf<double> &knext, DBuf<uint32_t> &kmask, hipStream_t s) {
     // R A's pattern and pair lists; its values only where no fused kernel takes the blocks
     DevBSR RA;
     Pairs P;
@@ -1050,6 +1067,7 @@ void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int 
                               std::to_string(kHashSmall / 2) + ")");
     DBuf<int> kcol(nnz), kptr(static_cast<size_t>(nnz) + 1), klist(ncontrib);
     DBuf<double> kval(static_cast<size_t>(nnz) * bb), knorm(nnz);
+    DBuf<uint32_t> kbits(fused ? nnz : 0);
     DBuf<uint8_t> keep(nnz);
     DBuf<int> kept(m);
     k_rap_symbolic<<<gs, 256, 0, s>>>(RA.rowptr.get(), RA.colidx.get(), pmap, m, 1, nullptr, krp.get(), kcol.get(),
@@ -1064,11 +1082,11 @@ void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int 
             if (bs == 9)
                 k_galerkin_mfma<9><<<mgrid, 256, 0, s>>>(nnz, kptr.get(), klist.get(), P.pairptr.get(),
                                                          P.pairs.get(), Z.vals.get(), A.vals.get(), kval.get(),
-                                                         knorm.get());
+                                                         knorm.get(), kbits.get());
             else
                 k_galerkin_mfma<16><<<mgrid, 256, 0, s>>>(nnz, kptr.get(), klist.get(), P.pairptr.get(),
                                                           P.pairs.get(), Z.vals.get(), A.vals.get(), kval.get(),
-                                                          knorm.get());
+                                                          knorm.get(), kbits.get());
         } else {
             const int64_t total = static_cast<int64_t>(nnz) * bb;
             k_rap_values<<<cap_grid((total + 255) / 256), 256, 0, s>>>(nnz, bb, kptr.get(), klist.get(),
@@ -1098,6 +1116,11 @@ void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int 
     NAIR_HIP(hipGetLastError());
     launch_block_gather(nnz, bs, kval.get(), src.get(), K.vals.get(), s, nk);
     launch_block_gather(nnz, 1, knorm.get(), src.get(), knext.get(), s, nk);   // a block's size is its max-abs entry
+    if (fused && nnz > 0) {
+        kmask.alloc(static_cast<size_t>(nnz));
+        k_gather_mask<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, kbits.get(), src.get(), nk, kmask.get());
+        NAIR_HIP(hipGetLastError());
+    }
 }
 
 }  // namespace nair

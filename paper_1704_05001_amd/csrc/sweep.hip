@@ -7,6 +7,7 @@
 // column indices, blocks (or face masks and rectangles) and D^{-1} block with
 // consecutive lanes on consecutive words.  Nothing is read back to the host.
 #include <algorithm>
+#include <climits>
 
 #include "common.h"
 
@@ -24,15 +25,18 @@ __global__ __launch_bounds__(256) void k_sweep_count(const int *__restrict__ row
 }
 
 // One wave per F row f (I = flist[f]): blocks of A's row I other than the
-// diagonal go to positions orp[f] ... in order; w words per block (bs*bs, or
-// the face rectangle's rc); nothing is written at or past cap.
+// diagonal go to positions orp[f] ... in order: their column indices, and
+// with FACE the face copy's masks and rc-word rectangles, else the source
+// block index (osrc) for the row-compressed copy made next; D_I^{-1} goes to
+// position f.  Nothing is written at or past cap.
 template <bool FACE>
 __global__ __launch_bounds__(256) void k_sweep_fill(const int *__restrict__ rowptr, const int *__restrict__ colidx,
                                                    const double *__restrict__ src, const uint64_t *__restrict__ fmeta,
                                                    const double *__restrict__ dinv, const int *__restrict__ flist,
                                                    int nF, int w, int bb, int64_t cap, const int *__restrict__ orp,
                                                    int *__restrict__ ocol, uint64_t *__restrict__ ometa,
-                                                   double *__restrict__ ovals, double *__restrict__ odinv) {
+                                                   double *__restrict__ ovals, int *__restrict__ osrc,
+                                                   double *__restrict__ odinv) {
     const int lane = threadIdx.x & 63;
     const int f = blockIdx.x * 4 + static_cast<int>(threadIdx.x >> 6);
     if (f >= nF) return;   // whole waves
@@ -56,25 +60,114 @@ __global__ __launch_bounds__(256) void k_sweep_fill(const int *__restrict__ rowp
         if (t == dp || d >= cap) continue;
         ocol[d] = colidx[t];
         if constexpr (FACE) ometa[d] = fmeta[t];
+        else osrc[d] = t;
     }
-    const int64_t total = static_cast<int64_t>(n) * w;
-    for (int64_t e = lane; e < total; e += 64) {
-        const int k = static_cast<int>(e / w);
-        const int64_t q = e - static_cast<int64_t>(k) * w;
-        const int t = lo + k;
-        const int64_t d = static_cast<int64_t>(o) + k - (t > dp ? 1 : 0);
-        if (t == dp || d >= cap) continue;
-        ovals[d * w + q] = src[static_cast<int64_t>(t) * w + q];
+    if constexpr (FACE) {
+        const int64_t total = static_cast<int64_t>(n) * w;
+        for (int64_t e = lane; e < total; e += 64) {
+            const int k = static_cast<int>(e / w);
+            const int64_t q = e - static_cast<int64_t>(k) * w;
+            const int t = lo + k;
+            const int64_t d = static_cast<int64_t>(o) + k - (t > dp ? 1 : 0);
+            if (t == dp || d >= cap) continue;
+            ovals[d * w + q] = src[static_cast<int64_t>(t) * w + q];
+        }
     }
     const double *Di = dinv + static_cast<int64_t>(I) * bb;
     double *Do = odinv + static_cast<int64_t>(f) * bb;
     for (int e = lane; e < bb; e += 64) Do[e] = Di[e];
 }
 
+// mask[t] and size[t] = nonzero rows * bs of block src[t] (t < count; past it
+// empty): one thread per block row, combined in LDS.
+__global__ __launch_bounds__(256) void k_rb_mask(const double *__restrict__ vals, int64_t n, int bs,
+                                                const int *__restrict__ src, const int *__restrict__ count,
+                                                uint32_t *__restrict__ mask, int *__restrict__ size) {
+    __shared__ uint32_t m[256];
+    const int per = 256 / bs;
+    const int lb = threadIdx.x / bs;
+    const int a = threadIdx.x - lb * bs;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * per + lb;
+    const int64_t nn = count ? *count : n;
+    if (threadIdx.x < per) m[threadIdx.x] = 0u;
+    __syncthreads();
+    if (lb < per && t < nn) {
+        const double *row = vals + ((src ? src[t] : t) * static_cast<int64_t>(bs) + a) * bs;
+        bool nz = false;
+        for (int c = 0; c < bs; ++c) nz = nz || row[c] != 0.0;
+        if (nz) atomicOr(m + lb, 1u << a);
+    }
+    __syncthreads();
+    const int64_t tt = static_cast<int64_t>(blockIdx.x) * per + threadIdx.x;
+    if (threadIdx.x < per && tt < n) {
+        mask[tt] = m[threadIdx.x];
+        size[tt] = __popc(m[threadIdx.x]) * bs;
+    }
+}
+
+// mask[t] = masks[src[t]] (src null: masks[t]) and size[t] for t < count (past it empty).
+__global__ __launch_bounds__(256) void k_rb_take(const uint32_t *__restrict__ masks, int64_t n, int bs,
+                                                const int *__restrict__ src, const int *__restrict__ count,
+                                                uint32_t *__restrict__ mask, int *__restrict__ size) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const uint32_t m = t < (count ? *count : n) ? masks[src ? src[t] : t] : 0u;
+    mask[t] = m;
+    size[t] = __popc(m) * bs;
+}
+
+// Row a of block t, if nonzero, to out[off[t] + rank(a) * bs] ...; one thread per block row.
+__global__ __launch_bounds__(256) void k_rb_fill(const double *__restrict__ vals, int64_t n, int bs,
+                                                const int *__restrict__ src, const int *__restrict__ count,
+                                                const uint32_t *__restrict__ mask, const int *__restrict__ off,
+                                                double *__restrict__ out) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t t = g / bs;
+    const int a = static_cast<int>(g - t * bs);
+    if (t >= (count ? *count : n)) return;
+    const uint32_t m = mask[t];
+    if (!((m >> a) & 1u)) return;
+    const double *row = vals + ((src ? src[t] : t) * static_cast<int64_t>(bs) + a) * bs;
+    double *dst = out + off[t] + __popc(m & ((1u << a) - 1u)) * bs;
+    for (int c = 0; c < bs; ++c) dst[c] = row[c];
+}
+
 }  // namespace
 
+bool build_row_blocks(const double *vals, int64_t n, int bs, RowBlocks &R, hipStream_t s, const int *src,
+                      const int *count, const uint32_t *masks) {
+    R = RowBlocks();
+    const int64_t bb = static_cast<int64_t>(bs) * bs;
+    if (n <= 0 || bs < 1 || bs > 32 || n * bb > INT_MAX) return false;
+    R.mask.alloc(static_cast<size_t>(n));
+    R.off.alloc(static_cast<size_t>(n) + 1);
+    R.vals.alloc(static_cast<size_t>(n * bb));   // (the rows kept take less; the total is not read back)
+    DBuf<int> size(static_cast<size_t>(n));
+    if (masks) {   // the blocks' row masks are known: no pass over their entries
+        k_rb_take<<<grid_for(n, 256), 256, 0, s>>>(masks, n, bs, src, count, R.mask.get(), size.get());
+    } else {
+        const int per = 256 / bs;
+        k_rb_mask<<<static_cast<unsigned>((n + per - 1) / per), 256, 0, s>>>(vals, n, bs, src, count, R.mask.get(),
+                                                                             size.get());
+    }
+    NAIR_HIP(hipGetLastError());
+    scan_exclusive(size.get(), R.off.get(), static_cast<int>(n), s);
+    k_rb_fill<<<grid_for(n * bs, 256), 256, 0, s>>>(vals, n, bs, src, count, R.mask.get(), R.off.get(),
+                                                    R.vals.get());
+    NAIR_HIP(hipGetLastError());
+    R.on = true;
+    return true;
+}
+
+void row_blocks_to_float(RowBlocks &R, int64_t n, int bs, hipStream_t s) {
+    if (!R.on || R.vals32.get()) return;
+    const int64_t nv = n * bs * bs;
+    R.vals32.alloc(static_cast<size_t>(nv));
+    launch_to_float(R.vals.get(), R.vals32.get(), nv, s, R.off.get() + n);   // the rows kept: off[n] entries
+}
+
 void build_sweep(const DevBSR &A, const FaceCopy &F, const double *dinv, const int *flist, int nF, SweepCopy &S,
-                 hipStream_t s) {
+                 hipStream_t s, const uint32_t *amask) {
     S = SweepCopy();
     if (nF <= 0 || A.nb == 0 || !dinv || !flist) return;
     const int bs = A.bs;
@@ -89,8 +182,10 @@ void build_sweep(const DevBSR &A, const FaceCopy &F, const double *dinv, const i
     S.cap = std::max<int64_t>(A.nnzb - nF, 1);
     S.rowptr.alloc(static_cast<size_t>(nF) + 1);
     S.colidx.alloc(static_cast<size_t>(S.cap));
-    S.vals.alloc(static_cast<size_t>(S.cap) * w);
-    if (face) S.meta.alloc(static_cast<size_t>(S.cap));
+    if (face) {
+        S.vals.alloc(static_cast<size_t>(S.cap) * w);
+        S.meta.alloc(static_cast<size_t>(S.cap));
+    }
     S.dinv.alloc(static_cast<size_t>(nF) * bb);
     DBuf<int> cnt(static_cast<size_t>(nF));
     k_sweep_count<<<grid_for(nF, 256), 256, 0, s>>>(A.rowptr.get(), A.colidx.get(), flist, nF, cnt.get());
@@ -100,21 +195,29 @@ void build_sweep(const DevBSR &A, const FaceCopy &F, const double *dinv, const i
     if (face) {
         k_sweep_fill<true><<<grid, 256, 0, s>>>(A.rowptr.get(), A.colidx.get(), F.vals.get(), F.meta.get(), dinv,
                                                 flist, nF, w, bb, S.cap, S.rowptr.get(), S.colidx.get(),
-                                                S.meta.get(), S.vals.get(), S.dinv.get());
+                                                S.meta.get(), S.vals.get(), nullptr, S.dinv.get());
+        NAIR_HIP(hipGetLastError());
     } else {
-        k_sweep_fill<false><<<grid, 256, 0, s>>>(A.rowptr.get(), A.colidx.get(), A.vals.get(), nullptr, dinv, flist,
-                                                 nF, w, bb, S.cap, S.rowptr.get(), S.colidx.get(), nullptr,
-                                                 S.vals.get(), S.dinv.get());
+        DBuf<int> src(static_cast<size_t>(S.cap));
+        k_sweep_fill<false><<<grid, 256, 0, s>>>(A.rowptr.get(), A.colidx.get(), nullptr, nullptr, dinv, flist, nF,
+                                                 w, bb, S.cap, S.rowptr.get(), S.colidx.get(), nullptr, nullptr,
+                                                 src.get(), S.dinv.get());
+        NAIR_HIP(hipGetLastError());
+        if (!build_row_blocks(A.vals.get(), S.cap, bs, S.rows, s, src.get(), S.rowptr.get() + nF, amask)) return;
     }
-    NAIR_HIP(hipGetLastError());
     S.on = true;
 }
 
 void sweep_to_float(SweepCopy &S, int bs, hipStream_t s) {
-    if (!S.on || S.vals32.get()) return;
-    const int64_t nv = S.cap * (S.rc > 0 ? S.rc : static_cast<int64_t>(bs) * bs);
-    S.vals32.alloc(static_cast<size_t>(nv));
-    launch_to_float(S.vals.get(), S.vals32.get(), nv, s);
+    if (!S.on) return;
+    if (S.rc > 0) {
+        if (S.vals32.get()) return;
+        const int64_t nv = S.cap * S.rc;
+        S.vals32.alloc(static_cast<size_t>(nv));
+        launch_to_float(S.vals.get(), S.vals32.get(), nv, s);
+    } else {
+        row_blocks_to_float(S.rows, S.cap, bs, s);
+    }
 }
 
 }  // namespace nair

@@ -63,7 +63,7 @@ struct Vecs;
 template <>
 struct Vecs<double> {
     static MatView<double> A(const Level &L) { return op_view(L, false); }
-    static MatView<double> Z(const Level &L) { return view(L.Z); }
+    static MatView<double> Z(const Level &L) { return z_view(L); }
     static MatView<double> AT(const Level &L) { return op_view(L, true); }
     static MatView<double> ZT(const Level &L) { return view(L.ZT); }
     static double *r(Level &L) { return L.r.get(); }
@@ -74,7 +74,7 @@ struct Vecs<double> {
 template <>
 struct Vecs<float> {
     static MatView<float> A(const Level &L) { return op_view32(L, false); }
-    static MatView<float> Z(const Level &L) { return view(L.Z, L.z32.get()); }
+    static MatView<float> Z(const Level &L) { return z_view32(L); }
     static MatView<float> AT(const Level &L) { return op_view32(L, true); }
     static MatView<float> ZT(const Level &L) { return view(L.ZT, L.zt32.get()); }
     static float *r(Level &L) { return L.r32.get(); }
