@@ -49,18 +49,19 @@ def cpu_model():
 
 def measured_traffic(workload: str, grid_threads: int):
     """HBM bytes per launch of the level-0 sweep from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE runs, scaled by reference kernels), or
-    None when there is none for this launch shape or the kernel source has
-    changed since it was measured."""
+    summary (FETCH_SIZE and WRITE_SIZE runs per launch shape, scaled by
+    reference kernels), or None when there is none for this launch shape or
+    the kernel source has changed since it was measured."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_sweep_traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     src = open(os.path.join(ROOT, "paper_1704_05001_amd", "csrc", "cycle.hip"), "rb").read()
-    if d.get("cycle_hip_sha256") != hashlib.sha256(src).hexdigest() or d.get("grid") != grid_threads:
+    if d.get("cycle_hip_sha256") != hashlib.sha256(src).hexdigest():
         return None
-    return float(d["traffic_bytes"])
+    t = d.get("traffic_by_grid", {}).get(str(grid_threads))
+    return float(t) if t is not None else None
 
 
 def relax_level_bytes(lv: dict) -> dict:
@@ -71,7 +72,9 @@ def relax_level_bytes(lv: dict) -> dict:
     masks are read too, or from the level's sweep copy, which holds only the
     off-diagonal blocks); of e, the entries those blocks multiply, each once.
     With face rectangles an off-diagonal block costs the entries on its
-    nonzero rows and columns plus its 8-byte row/column masks."""
+    nonzero rows and columns plus its 8-byte row/column masks; a sweep copy
+    without them stores each block by its nonzero rows (full width) with a
+    4-byte row mask and a 4-byte offset."""
     import numpy as np
     rp = lv["rowptr"].cpu().numpy().astype(np.int64)
     cf = lv["cf"].cpu().numpy()
@@ -96,8 +99,12 @@ def relax_level_bytes(lv: dict) -> dict:
         cm = np.zeros(lv["nb"], dtype=np.uint64)
         np.bitwise_or.at(cm, ci[off], meta[off] >> np.uint64(32))
         bytes_e = int(np.bitwise_count(cm).astype(np.int64).sum()) * 8
+    elif copy:
+        nzr = nonzero_rows(lv["vals"])
+        bytes_A = int((nzr[off] * bs * 8 + 12).sum())
+        bytes_e = len(np.unique(ci[off])) * bs * 8
     else:
-        bytes_A = (0 if copy else nF * 4) + int(off.sum()) * (bb * 8 + 4)   # off-diagonal blocks (+ diagonal's index)
+        bytes_A = nF * 4 + int(off.sum()) * (bb * 8 + 4)   # off-diagonal blocks (+ diagonal's index)
         bytes_e = len(np.unique(ci[off])) * bs * 8
     bytes_D = nF * bb * 8                  # D_F^{-1}
     bytes_idx = nF * 4 + nF * 8            # F list, rowptr pairs
@@ -106,16 +113,28 @@ def relax_level_bytes(lv: dict) -> dict:
                 bytes_true_blocks=bytes_A + bytes_D, sweep_copy=copy)
 
 
+def nonzero_rows(vals):
+    """Rows with a nonzero entry, per block of a (nnzb, bs, bs) array (on the host)."""
+    v = vals.cpu().numpy()
+    return (v != 0).any(axis=2).sum(axis=1).astype("int64")
+
+
 def restrict_level_bytes(lv: dict) -> int:
     """Algorithmic HBM bytes of one restriction r_c = r_C + Z r_F on a level:
     Z's blocks and column indices, its row pointers, the C list, r_C read and
-    r_c written, r_F gathered once."""
+    r_c written, r_F gathered once.  Where the level has a sweep copy, Z is
+    read from its row-compressed copy: each block's nonzero rows at full
+    width, a 4-byte row mask and a 4-byte offset."""
     import numpy as np
     bs = lv["bs"]
     nc = int(lv["nc"])
     znnz = int(lv["z_rowptr"][-1].item()) if nc > 0 else 0
     nF = int((lv["cf"].cpu().numpy() == 0).sum())
-    return znnz * (bs * bs * 8 + 4) + (nc + 1) * 4 + nc * 4 + nc * bs * 16 + nF * bs * 8
+    if znnz > 0 and lv.get("sweep_nnzb", -1) >= 0:
+        bytes_Z = int((nonzero_rows(lv["z_vals"]) * bs * 8 + 12).sum())
+    else:
+        bytes_Z = znnz * (bs * bs * 8 + 4)
+    return bytes_Z + (nc + 1) * 4 + nc * 4 + nc * bs * 16 + nF * bs * 8
 
 
 def level_bandwidth(P, H, b, levels: int) -> list:
@@ -124,11 +143,11 @@ def level_bandwidth(P, H, b, levels: int) -> list:
     algorithmic GB/s."""
     out = []
     for l in range(levels):
-        lv = H.level(l, fields=("rowptr", "colidx", "cf", "z_rowptr"))
+        lv = H.level(l, fields=("rowptr", "colidx", "cf", "z_rowptr", "z_vals"))
         if lv["coarsest"]:
             break
         row = {"level": l, "nb": lv["nb"], "nnzb": lv["nnzb"]}
-        for kind, nbytes in (("relax", relax_level_bytes(H.level(l, fields=("rowptr", "colidx", "cf", "face_meta")))["bytes"]),
+        for kind, nbytes in (("relax", relax_level_bytes(H.level(l, fields=("rowptr", "colidx", "cf", "face_meta", "vals")))["bytes"]),
                              ("restrict", restrict_level_bytes(lv))):
             P.timer_select(kind, l)
             H.solve(b)
@@ -255,6 +274,8 @@ def main(argv=None):
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-angles leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default lane groups (no autotuning)")
+    ap.add_argument("--roofline-groups", type=int, default=0, metavar="G",
+                    help="lane groups per row of the roofline kernel's F sweep (0: as tuned, or the default)")
     ap.add_argument("--no-faces", action="store_true",
                     help="read whole blocks of the finest operator (no face-compressed copy)")
     ap.add_argument("--batch-only", action="store_true",
@@ -350,6 +371,14 @@ def main(argv=None):
         tuning = Ht.autotune(reps=20)
         Ht.close()
         params = P.Params(faces=not args.no_faces, degree=degree, tuning=tuning)
+    if args.roofline_groups > 0:
+        # the roofline kernel at a given launch shape (the rest as tuned or default)
+        if tuning is None:
+            tuning = np.zeros((64, len(P.TUNE_KINDS)), dtype=np.int8)
+        tuning = np.array(tuning, dtype=np.int8)
+        tuning[args.roofline_level][0] = args.roofline_groups
+        params = P.Params(faces=not args.no_faces, degree=degree, tuning=tuning)
+    if tuning is not None:
         for _ in range(max(1, args.warmup)):
             step(None, params).close()
 
