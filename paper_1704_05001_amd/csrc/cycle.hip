@@ -309,12 +309,13 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int *__restrict__ r
     const Lane L = lane_of(G, bs);
     const int I = blockIdx.x * (kThreads / (G * bs)) + L.lr;
     const bool act = L.valid && I < nb && live(gate, I);
+    const int64_t o = static_cast<int64_t>(I) * bs + L.a;
+    const double bv = (act && L.g == 0 && b) ? static_cast<double>(b[o]) : 0.0;   // loads during the product
     double acc = act ? row_product<BS, FACE>(colidx, vals, face, rowptr[I], rowptr[I + 1], L.g, G, L.a, I, bs, x)
                      : 0.0;
     acc = reduce_groups(acc, L, G, bs, part);
     if (act && L.g == 0) {
-        const int64_t o = static_cast<int64_t>(I) * bs + L.a;
-        const double rv = b ? static_cast<double>(b[o]) - acc : acc;
+        const double rv = b ? bv - acc : acc;
         r[o] = static_cast<VT>(rv);
         if (r_lo) r_lo[o] = static_cast<float>(rv);
     }
@@ -528,15 +529,16 @@ __global__ __launch_bounds__(kThreads) void k_restrict(const int *__restrict__ z
     const Lane L = lane_of(G, bs);
     const int i = blockIdx.x * (kThreads / (G * bs)) + L.lr;
     const bool act = L.valid && i < nc && live(gate, i);
+    // r_C loads while the row product runs
+    double rv = 0.0;
+    if (act && L.g == 0) rv = static_cast<double>(r[static_cast<int64_t>(cpts[i]) * bs + L.a]);
     double acc = 0.0;
     if (act) {
         if constexpr (RB) acc = row_part_rows<BS, MT, VT>(zcol, zr, zrp[i], zrp[i + 1], L.g, G, L.a, bs, r);
         else acc = row_part<BS>(zcol, zval, zrp[i], zrp[i + 1], L.g, G, L.a, bs, r);
     }
     acc = reduce_groups(acc, L, G, bs, part);
-    if (act && L.g == 0)
-        rc[static_cast<int64_t>(i) * bs + L.a] =
-            static_cast<VT>(static_cast<double>(r[static_cast<int64_t>(cpts[i]) * bs + L.a]) + acc);
+    if (act && L.g == 0) rc[static_cast<int64_t>(i) * bs + L.a] = static_cast<VT>(rv + acc);
 }
 
 // y_I += [I is C] yc_{cidx I} + sum_t (Z^T)_It yc_{col t}
@@ -550,13 +552,20 @@ __global__ __launch_bounds__(kThreads) void k_interp_T(const int *__restrict__ z
     const Lane L = lane_of(G, bs);
     const int I = blockIdx.x * (kThreads / (G * bs)) + L.lr;
     const bool act = L.valid && I < nb && live(gate, I);
+    // y_I and the C term load while the row product runs
+    const int64_t o = static_cast<int64_t>(I) * bs + L.a;
+    double yv = 0.0, cv = 0.0;
+    int ci = -1;
+    if (act && L.g == 0) {
+        yv = static_cast<double>(y[o]);
+        ci = cidx[I];
+        if (ci >= 0) cv = static_cast<double>(yc[static_cast<int64_t>(ci) * bs + L.a]);
+    }
     double acc = act ? row_part<BS>(ztcol, ztval, ztrp[I], ztrp[I + 1], L.g, G, L.a, bs, yc) : 0.0;
     acc = reduce_groups(acc, L, G, bs, part);
     if (act && L.g == 0) {
-        const int64_t o = static_cast<int64_t>(I) * bs + L.a;
-        const int ci = cidx[I];
-        if (ci >= 0) acc += static_cast<double>(yc[static_cast<int64_t>(ci) * bs + L.a]);
-        y[o] = static_cast<VT>(static_cast<double>(y[o]) + acc);
+        if (ci >= 0) acc += cv;
+        y[o] = static_cast<VT>(yv + acc);
     }
 }
 
