@@ -1,6 +1,9 @@
 """Sweep copies (nair_params.sweep_copy): the F rows of each selected level
 operator, in F-list order without their diagonal blocks, with D_F^{-1} in the
-same order, read by the Jacobi F sweeps.  The copy holds exactly the F rows'
+same order, read by the Jacobi F sweeps, and with them the row-compressed
+copies of Z (restriction) and of the coarse levels' sweep blocks, whose row
+masks come from the matrix-core kernels at 9x9 and 16x16 blocks and from a
+pass over the blocks at 4x4 and 25x25.  The copy holds exactly the F rows'
 off-diagonal blocks; with one lane group per row the solves are bit-identical
 with and without copies (forward, transposed, FC, FP32-stored, batched, face
 rectangles on level 0); with the default launch shapes they match the oracle
@@ -60,6 +63,8 @@ def same_solves(on, off, b, trans=False):
                                        ("dg_q2_256_curved", 14, dict(faces=False)),
                                        ("dg_q1_32", None, dict(cycle="F")),
                                        ("dg_q2_256_curved", 12, dict(gmres=8)),
+                                       ("dg_q3_256_curved_sigma", 10, {}),
+                                       ("dg_q3_256_curved_sigma", 8, dict(precision="fp32")),
                                        ("dg_q4_512_jitter", 6, {})])
 def test_sweep_copy_changes_no_bit_at_one_group(name, N, kw):
     _say(f"test: sweep copy on/off {name} N={N} {kw}")
