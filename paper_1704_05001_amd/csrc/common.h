@@ -164,6 +164,13 @@ void launch_seg_info(const int *seg, const int8_t *mode, int nsys, int nb, int *
                      hipStream_t s);
 void launch_mark_direct(const int8_t *direct, int nb, int8_t *state, hipStream_t s);
 void launch_gather_int(const int *v, const int *idx, int n, int *out, hipStream_t s);
+// p[i] = v for i < n, for up to four (p, n, v) arrays in one launch
+struct FillInts {
+    int *p;
+    int64_t n;
+    int v;
+};
+void launch_fill_ints(std::initializer_list<FillInts> jobs, hipStream_t s);
 // margin[2] += F rows whose chosen C block has a rival within 1e-12 relative
 void launch_one_point(const int *rowptr, const int *colidx, const double *bnorm, const int8_t *cf,
                       const int *cidx, int nb, int *pmap, int *margin, hipStream_t s);

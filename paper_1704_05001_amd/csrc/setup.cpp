@@ -103,13 +103,12 @@ void split(Hier &h, Level &L, int lvl, hipStream_t s, const std::function<void()
     const int n = L.A.nb;
     const int64_t nz = L.A.bound();
     DBuf<int> stptr(static_cast<size_t>(n) + 1), fill(n), stidx(nz > 0 ? nz : 1);
-    scan_exclusive(L.lambda.get(), stptr.get(), n, s);
-    NAIR_HIP(hipMemsetAsync(fill.get(), 0, sizeof(int) * n, s));
-    launch_strong_transpose(L.A.rowptr.get(), L.A.colidx.get(), L.mask.get(), n, stptr.get(), fill.get(),
-                            stidx.get(), s);
     DBuf<int8_t> newc(n);
     DBuf<int> counts(kMaxRounds + 1);
-    NAIR_HIP(hipMemsetAsync(counts.get(), 0, sizeof(int) * (kMaxRounds + 1), s));
+    launch_fill_ints({{fill.get(), n, 0}, {counts.get(), kMaxRounds + 1, 0}}, s);
+    scan_exclusive(L.lambda.get(), stptr.get(), n, s);
+    launch_strong_transpose(L.A.rowptr.get(), L.A.colidx.get(), L.mask.get(), n, stptr.get(), fill.get(),
+                            stidx.get(), s);
     launch_pmis_init(L.lambda.get(), L.direct.get(), n, L.cf.get(), L.dround.get(), counts.get(), s);
     // rounds go out kRoundBatch at a time (a round after the last one with undecided
     // blocks returns at once), then one read of the counts before and after each
@@ -237,10 +236,8 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         L.pmap.alloc(n);
         L.dround.alloc(n);
         DBuf<int> sing(1);
-        NAIR_HIP(hipMemsetAsync(sing.get(), 0x7f, sizeof(int), s));
-        NAIR_HIP(hipMemsetAsync(L.lambda.get(), 0, sizeof(int) * n, s));
         L.margin.alloc(4);
-        NAIR_HIP(hipMemsetAsync(L.margin.get(), 0, sizeof(int) * 4, s));
+        launch_fill_ints({{sing.get(), 1, kNoSingular}, {L.lambda.get(), n, 0}, {L.margin.get(), 4, 0}}, s);
         if (!L.bnorm_ready) launch_block_maxabs(L.A.vals.get(), nz, bs, L.bnorm.get(), s);
         {
             TimerScope ts(TK_BLOCKINV, l, s);

@@ -434,6 +434,20 @@ __global__ __launch_bounds__(256) void k_mark_direct(const int8_t *__restrict__ 
     if (I < nb && direct[I]) state[I] = kD;
 }
 
+struct FillJobs {
+    int *p[4];
+    int64_t n[4];
+    int v[4];
+    int k;
+};
+
+__global__ __launch_bounds__(256) void k_fill_ints(FillJobs J) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int j = 0; j < J.k; ++j)
+        for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < J.n[j]; i += stride)
+            J.p[j][i] = J.v[j];
+}
+
 // out[i] = v[idx[i]] for i < n
 __global__ __launch_bounds__(256) void k_gather_int(const int *__restrict__ v, const int *__restrict__ idx, int n,
                                                    int *__restrict__ out) {
@@ -712,6 +726,23 @@ void launch_seg_info(const int *seg, const int8_t *mode, int nsys, int nb, int *
 void launch_mark_direct(const int8_t *direct, int nb, int8_t *state, hipStream_t s) {
     if (nb <= 0) return;
     k_mark_direct<<<grid_for(nb, 256), 256, 0, s>>>(direct, nb, state);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_fill_ints(std::initializer_list<FillInts> jobs, hipStream_t s) {
+    FillJobs J{};
+    int64_t most = 0;
+    for (const FillInts &f : jobs) {
+        if (J.k == 4) fail(NAIR_EDEVICE, "launch_fill_ints: more than four arrays");
+        if (f.n <= 0) continue;
+        J.p[J.k] = f.p;
+        J.n[J.k] = f.n;
+        J.v[J.k] = f.v;
+        most = std::max(most, f.n);
+        ++J.k;
+    }
+    if (J.k == 0) return;
+    k_fill_ints<<<cap_grid((most + 255) / 256), 256, 0, s>>>(J);
     NAIR_HIP(hipGetLastError());
 }
 

@@ -116,20 +116,21 @@ __global__ __launch_bounds__(256) void k_rb_take(const uint32_t *__restrict__ ma
     size[t] = __popc(m) * bs;
 }
 
-// Row a of block t, if nonzero, to out[off[t] + rank(a) * bs] ...; one thread per block row.
+// Entry (a, c) of block t, if row a is nonzero, to out[off[t] + rank(a) * bs + c];
+// one thread per block entry, so consecutive threads copy consecutive words.
 __global__ __launch_bounds__(256) void k_rb_fill(const double *__restrict__ vals, int64_t n, int bs,
                                                 const int *__restrict__ src, const int *__restrict__ count,
                                                 const uint32_t *__restrict__ mask, const int *__restrict__ off,
                                                 double *__restrict__ out) {
+    const int64_t bb = static_cast<int64_t>(bs) * bs;
     const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t t = g / bs;
-    const int a = static_cast<int>(g - t * bs);
+    const int64_t t = g / bb;
     if (t >= (count ? *count : n)) return;
+    const int e = static_cast<int>(g - t * bb);
+    const int a = e / bs;
     const uint32_t m = mask[t];
     if (!((m >> a) & 1u)) return;
-    const double *row = vals + ((src ? src[t] : t) * static_cast<int64_t>(bs) + a) * bs;
-    double *dst = out + off[t] + __popc(m & ((1u << a) - 1u)) * bs;
-    for (int c = 0; c < bs; ++c) dst[c] = row[c];
+    out[off[t] + __popc(m & ((1u << a) - 1u)) * bs + (e - a * bs)] = vals[(src ? src[t] : t) * bb + e];
 }
 
 }  // namespace
@@ -152,7 +153,7 @@ bool build_row_blocks(const double *vals, int64_t n, int bs, RowBlocks &R, hipSt
     }
     NAIR_HIP(hipGetLastError());
     scan_exclusive(size.get(), R.off.get(), static_cast<int>(n), s);
-    k_rb_fill<<<grid_for(n * bs, 256), 256, 0, s>>>(vals, n, bs, src, count, R.mask.get(), R.off.get(),
+    k_rb_fill<<<grid_for(n * bb, 256), 256, 0, s>>>(vals, n, bs, src, count, R.mask.get(), R.off.get(),
                                                     R.vals.get());
     NAIR_HIP(hipGetLastError());
     R.on = true;
