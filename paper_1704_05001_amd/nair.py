@@ -126,6 +126,51 @@ def _stream_ptr(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
+def _check_vector(t, n: int, name: str, device, out: bool = False):
+    """Raise ValueError unless t is a contiguous float64 tensor of n entries on
+    `device` (the library reads or writes exactly n doubles through its pointer)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} must hold {n} entries (nb * bs), got {t.numel()}")
+    if t.device != torch.device(device):
+        raise ValueError(f"{name} is on {t.device}, the hierarchy on {device}")
+    if out and t.requires_grad:
+        raise ValueError(f"{name} is written by the library and must not require grad")
+
+
+def _check_pattern(rowptr, colidx, vals, bs: int):
+    """Raise ValueError unless rowptr/colidx are contiguous int32 and vals a
+    contiguous float64 [nnzb, bs, bs] tensor on one device, with colidx and
+    vals sized by rowptr[-1] (one 4-byte device read)."""
+    import torch
+    for t, dt, name in ((rowptr, torch.int32, "rowptr"), (colidx, torch.int32, "colidx"),
+                        (vals, torch.float64, "vals")):
+        if not isinstance(t, torch.Tensor) or t.dtype != dt or not t.is_contiguous():
+            raise ValueError("rowptr/colidx must be contiguous int32 and vals float64 tensors "
+                             f"({name} is not)")
+    if not rowptr.is_cuda or colidx.device != rowptr.device or vals.device != rowptr.device:
+        raise ValueError("rowptr, colidx and vals must be on the same HIP device")
+    if rowptr.numel() < 1:
+        raise ValueError("rowptr must hold nb + 1 >= 1 entries")
+    _check_block_sizes(int(rowptr[-1].item()), colidx.numel(), vals.numel(), bs)
+
+
+def _check_block_sizes(nnzb: int, ncolidx: int, nvals: int, bs: int):
+    """colidx must hold nnzb = rowptr[-1] entries and vals nnzb * bs * bs."""
+    if int(bs) < 1:
+        raise ValueError("bs >= 1 required")
+    if ncolidx != nnzb:
+        raise ValueError(f"colidx holds {ncolidx} entries, rowptr[-1] = {nnzb}")
+    if nvals != nnzb * int(bs) * int(bs):
+        raise ValueError(f"vals holds {nvals} entries, nnzb * bs * bs = {nnzb * int(bs) * int(bs)}")
+
+
 def _dcopy(ptr: int, dtype, count: int, device):
     """Copy `count` elements at device pointer `ptr` into a new torch tensor."""
     import torch
@@ -188,10 +233,8 @@ class Hierarchy:
                  sys_nb=None):
         import torch
         params = params or Params()
+        _check_pattern(rowptr, colidx, vals, bs)
         L = lib()
-        for t, dt in ((rowptr, torch.int32), (colidx, torch.int32), (vals, torch.float64)):
-            if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
-                raise ValueError("rowptr/colidx must be contiguous int32 and vals float64 device tensors")
         self.nb = rowptr.numel() - 1
         self.bs = int(bs)
         self.device = rowptr.device
@@ -266,8 +309,12 @@ class Hierarchy:
 
     def _solve(self, fn, name, b, x, rtol, max_iter, stream, raise_on):
         import torch
+        _check_vector(b, self.n, "right-hand side", self.device)
         if x is None:
             x = torch.empty_like(b)
+        _check_vector(x, self.n, "solution", self.device, out=True)
+        if x.data_ptr() == b.data_ptr():
+            raise ValueError("the solution must not share memory with the right-hand side")
         res = _Result()
         st = fn(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), float(rtol), int(max_iter),
                 C.byref(res), _stream_ptr(stream))
@@ -280,21 +327,26 @@ class Hierarchy:
               raise_on=("EINVAL", "EDEVICE", "ENOMEM")):
         """x = A^{-1} b by nAIR cycles (the stationary iteration, or GMRES(m)
         preconditioned by the cycle when Params.gmres = m > 0).  Returns (x, Result)."""
-        return self._solve(lib().nair_solve, "nair_solve", b, x, rtol, max_iter, stream, raise_on)
+        return self._solve(lambda *a: lib().nair_solve(*a), "nair_solve", b, x, rtol, max_iter, stream, raise_on)
 
     def solve_T(self, g, y=None, rtol=1e-10, max_iter=200, stream=None,
                 raise_on=("EINVAL", "EDEVICE", "ENOMEM")):
         """y = A^{-T} g by transposed nAIR cycles (GMRES(m) with Params.gmres = m).
         Returns (y, Result)."""
-        return self._solve(lib().nair_solve_T, "nair_solve_T", g, y, rtol, max_iter, stream, raise_on)
+        return self._solve(lambda *a: lib().nair_solve_T(*a), "nair_solve_T", g, y, rtol, max_iter, stream,
+                           raise_on)
 
     def solve_batch(self, b, x=None, rtol=1e-10, max_iter=200, trans=False, graph=True, stream=None,
                     raise_on=("EINVAL", "EDEVICE", "ENOMEM")):
         """Every system to its own relative residual (A x = b, or A^T x = b with
         trans), one graph-captured iteration replayed.  Returns (x, [Result per system])."""
         import torch
+        _check_vector(b, self.n, "right-hand side", self.device)
         if x is None:
             x = torch.empty_like(b)
+        _check_vector(x, self.n, "solution", self.device, out=True)
+        if x.data_ptr() == b.data_ptr():
+            raise ValueError("the solution must not share memory with the right-hand side")
         res = (_Result * self.nsys)()
         st = lib().nair_solve_batch(self._h, 1 if trans else 0, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
                                     float(rtol), int(max_iter), 1 if graph else 0, C.cast(res, C.c_void_p),
@@ -348,6 +400,7 @@ class Hierarchy:
 
     def vcycle(self, r, stream=None):
         import torch
+        _check_vector(r, self.n, "residual", self.device)
         e = torch.empty_like(r)
         st = lib().nair_vcycle(self._h, C.c_void_p(r.data_ptr()), C.c_void_p(e.data_ptr()), _stream_ptr(stream))
         if st != 0:
@@ -356,6 +409,7 @@ class Hierarchy:
 
     def vcycle_T(self, g, stream=None):
         import torch
+        _check_vector(g, self.n, "right-hand side", self.device)
         y = torch.empty_like(g)
         st = lib().nair_vcycle_T(self._h, C.c_void_p(g.data_ptr()), C.c_void_p(y.data_ptr()), _stream_ptr(stream))
         if st != 0:
@@ -466,8 +520,17 @@ def timer_read():
 def grad_vals(rowptr, colidx, ybar, x, bs: int, stream=None):
     """-ybar_I x_J^T on the block pattern (device tensors), as [nnzb, bs, bs]."""
     import torch
+    for t, name in ((rowptr, "rowptr"), (colidx, "colidx")):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.int32 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous int32 tensor")
     nb = rowptr.numel() - 1
+    if nb < 0 or int(bs) < 1:
+        raise ValueError("bs >= 1 and rowptr of nb + 1 >= 1 entries required")
+    _check_vector(ybar, nb * int(bs), "ybar", rowptr.device)
+    _check_vector(x, nb * int(bs), "x", rowptr.device)
     nnzb = colidx.numel()
+    if colidx.device != rowptr.device or int(rowptr[-1].item()) != nnzb:
+        raise ValueError("colidx must be on rowptr's device and hold rowptr[-1] entries")
     out = torch.empty((nnzb, bs, bs), dtype=torch.float64, device=x.device)
     st = lib().nair_grad_vals(nb, bs, C.c_void_p(rowptr.data_ptr()), C.c_void_p(colidx.data_ptr()),
                               C.c_void_p(ybar.data_ptr()), C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
