@@ -113,6 +113,17 @@ def relax_level_bytes(lv: dict) -> dict:
                 bytes_true_blocks=bytes_A + bytes_D, sweep_copy=copy)
 
 
+def host_relres(S, x) -> float:
+    """||b - A x||_2 / ||b||_2 in FP64 on the host (numpy block products), an
+    independent check of a GPU solution."""
+    import numpy as np
+    xb = x.detach().cpu().numpy().reshape(S.nb, S.bs)
+    prod = np.einsum("tij,tj->ti", S.vals, xb[S.colidx])
+    Ax = np.add.reduceat(prod, S.rowptr[:-1].astype(np.int64), axis=0)
+    r = S.rhs - Ax.reshape(-1)
+    return float(np.linalg.norm(r) / np.linalg.norm(S.rhs))
+
+
 def nonzero_rows(vals):
     """Rows with a nonzero entry, per block of a (nnzb, bs, bs) array (on the host)."""
     v = vals.cpu().numpy()
@@ -158,6 +169,103 @@ def level_bandwidth(P, H, b, levels: int) -> list:
             row[f"{kind}_MB"] = round(nbytes / 1e6, 2)
             row[f"{kind}_GBs"] = round(nbytes / (us * 1e-6) / 1e9, 1) if n else None
         out.append(row)
+    return out
+
+
+FP64_PEAK_TFS = 78.6   # MI355X dense FP64 (matrix cores and vector units alike)
+
+
+def setup_work(H, degree: int) -> dict:
+    """Algorithmic work of one setup of hierarchy H, from its levels' patterns
+    (host scipy on the block patterns; no values): block pairs of the Neumann
+    products W_i = W_{i-1} T (T: the phi-strong F-F blocks, W_0 = A_cf) and of
+    R A (R = [Z I]), the single block products T = -D^-1 A_ff and Z = -S D^-1,
+    the block inverses, and the compulsory bytes of each (operands read once,
+    outputs written once, 8-byte pair entries).  Flops: 2 bs^3 per block pair
+    or block product, 2 bs^3 per block inverse (LU and the inverse from it)."""
+    import numpy as np
+    import scipy.sparse as sp
+    info = H.info()
+    w = {k: 0 for k in ("pairs_W", "pairs_RA", "ident_RA", "blocks_T", "blocks_Z", "blocks_W", "blocks_Wprev",
+                        "blocks_K", "blocks_A", "nb_inv")}
+    bs = None
+    for l in range(info["levels"]):
+        lv = H.level(l, fields=("rowptr", "colidx", "mask", "cf", "z_rowptr", "z_colidx"))
+        if lv["coarsest"]:
+            break
+        bs = lv["bs"]
+        nb = lv["nb"]
+        rp = lv["rowptr"].cpu().numpy().astype(np.int64)
+        ci = lv["colidx"].cpu().numpy().astype(np.int64)
+        mask = lv["mask"].cpu().numpy()
+        cf = lv["cf"].cpu().numpy()
+        rows = np.repeat(np.arange(nb), np.diff(rp))
+        F = cf == 0
+        tm = F[rows] & F[ci] & (rows != ci) & ((mask & 2) != 0)
+        T = sp.csr_matrix((np.ones(int(tm.sum())), (rows[tm], ci[tm])), shape=(nb, nb))
+        cm = (cf[rows] == 1) & F[ci]
+        W = sp.csr_matrix((np.ones(int(cm.sum())), (rows[cm], ci[cm])), shape=(nb, nb))
+        tlen = np.diff(T.indptr)
+        for _ in range(degree):
+            w["pairs_W"] += int(tlen[W.indices].sum())
+            w["blocks_Wprev"] += W.nnz
+            W = (W @ T).tocsr()
+            W.data[:] = 1.0
+            w["blocks_W"] += W.nnz
+        alen = np.diff(rp)
+        zc = lv["z_colidx"].cpu().numpy().astype(np.int64)
+        w["pairs_RA"] += int(alen[zc].sum()) + int(alen[cf == 1].sum())
+        w["ident_RA"] += int((cf == 1).sum())
+        w["blocks_T"] += T.nnz
+        w["blocks_Z"] += len(zc)
+        w["blocks_A"] += len(ci)
+        w["nb_inv"] += nb
+        w["blocks_K"] += H.level(l + 1, fields=())["nnzb"]
+    w["bs"] = bs
+    return w
+
+
+def setup_roofline(P, make_hier, work: dict, reps: int = 1) -> list:
+    """Per setup kernel kind: total launch time over `reps` setups (the
+    library's HIP-event timer, all levels), the algorithmic flops and bytes of
+    one setup (setup_work), and both fractions of MI355X's peaks; `bound` names
+    the larger, the resource the kernel is nearer to."""
+    bs = work["bs"]
+    bb8 = 8 * bs * bs
+    f3 = 2.0 * bs ** 3
+    kinds = {
+        "galerkin": dict(kernel="k_galerkin_mfma (R A products summed into K blocks)",
+                         flops=(work["pairs_RA"] - work["ident_RA"]) * f3,
+                         bytes=(work["blocks_Z"] + work["blocks_A"] + work["blocks_K"]) * bb8 + 8 * work["pairs_RA"]),
+        "spgemm_numeric": dict(kernel="k_spgemm_mfma (Neumann products W_i = W_(i-1) T)",
+                               flops=work["pairs_W"] * f3,
+                               bytes=(work["blocks_Wprev"] + work["blocks_T"] + work["blocks_W"]) * bb8
+                               + 8 * work["pairs_W"]),
+        "block_product": dict(kernel="k_block_product_mfma (T = -D^-1 A_ff, Z = -S D^-1)",
+                              flops=(work["blocks_T"] + work["blocks_Z"]) * f3,
+                              bytes=(work["blocks_T"] + work["blocks_Z"]) * 3 * bb8),
+        "block_inverse": dict(kernel="k_block_inverse (D^-1 by LU)", flops=work["nb_inv"] * f3,
+                              bytes=work["nb_inv"] * 2 * bb8),
+    }
+    out = []
+    for kind, d in kinds.items():
+        P.timer_read()
+        P.timer_select(kind, -1)
+        for _ in range(reps):
+            make_hier().close()
+        P.timer_select(None)
+        n, ms = P.timer_read()
+        if n == 0 or ms <= 0:
+            continue
+        t = ms * 1e-3 / reps
+        tf = d["flops"] / t / 1e12
+        gb = d["bytes"] / t / 1e9
+        fm, fh = tf / FP64_PEAK_TFS, gb / HBM_PEAK_GBS
+        out.append({"kind": kind, "kernel": d["kernel"], "ms_per_setup": round(ms / reps, 3),
+                    "launches_per_setup": n // reps, "gflop": round(d["flops"] / 1e9, 2),
+                    "MB": round(d["bytes"] / 1e6, 1), "TFLOPs": round(tf, 2), "GBs": round(gb, 1),
+                    "frac_fp64_peak": round(fm, 4), "frac_hbm_peak": round(fh, 4),
+                    "bound": "mfma" if fm >= fh else "hbm"})
     return out
 
 
@@ -263,17 +371,19 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="dg_q2_256_curved")
+    ap.add_argument("--workload", default="dg_q4_512_jitter")
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--roofline-kernel", default="relax")
     ap.add_argument("--roofline-level", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-hierarchy leg")
-    ap.add_argument("--cpu-sample", default="full", help="'full' or a mesh size N for the oracle sample")
+    ap.add_argument("--cpu-sample", default="auto",
+                    help="'full', a mesh size N for the oracle sample, or 'auto' (full up to 1M DOFs, else N = 96)")
     ap.add_argument("--batch-workload", default="dg_q2_angles64_uneven")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-angles leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default lane groups (no autotuning)")
+    ap.add_argument("--no-setup-roofline", action="store_true", help="skip the per-kernel setup timing")
     ap.add_argument("--roofline-groups", type=int, default=0, metavar="G",
                     help="lane groups per row of the roofline kernel's F sweep (0: as tuned, or the default)")
     ap.add_argument("--no-faces", action="store_true",
@@ -434,10 +544,31 @@ def main(argv=None):
     Hl = P.Hierarchy(rp, ci, va, S.bs, params)
     P.timer_read()
     levels_bw = level_bandwidth(P, Hl, b, info["levels"])
-    Hl.close()
+    Hl_work = Hl
     for r in levels_bw:
         log(f"level {r['level']}: relax {r['relax_us']} us {r['relax_GBs']} GB/s, "
             f"restrict {r['restrict_us']} us {r['restrict_GBs']} GB/s")
+
+    rT = recs[-1][2]
+    r0 = recs[-1][1]
+    import math as _m
+    conv = {"iters": iters, "rho_avg": r0.rho_avg, "rho_last5": r0.rho_last5, "cc": round(info["cc"], 4),
+            "oc": round(info["oc"], 4),
+            "wpd": round(-info["cc"] / _m.log10(r0.rho_avg), 3) if 0 < r0.rho_avg < 1 else None,
+            "iters_T": itersT, "rho_avg_T": rT.rho_avg, "rho_last5_T": rT.rho_last5,
+            "what": "rho_avg = h_K^(1/K), rho_last5 = (h_K/h_(K-5))^(1/5), WPD = -CC/log10(rho_avg); "
+                    "CC, OC in work units of one level-0 SpMV"}
+    log(f"convergence: {iters} iterations, rho_avg {r0.rho_avg:.3f}, rho_last5 {r0.rho_last5:.3f}, "
+        f"CC {info['cc']:.2f}, WPD {conv['wpd']}")
+
+    setup_roof = None
+    if not args.no_setup_roofline:
+        work = setup_work(Hl_work, degree)
+        setup_roof = setup_roofline(P, lambda: P.Hierarchy(rp, ci, va, S.bs, params), work)
+        for r in setup_roof:
+            log(f"setup {r['kind']}: {r['ms_per_setup']} ms, {r['TFLOPs']} TFLOP/s ({r['frac_fp64_peak']:.3f}), "
+                f"{r['GBs']} GB/s ({r['frac_hbm_peak']:.3f})")
+    Hl_work.close()
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "DOFs/s", "n_gpus": 1,
@@ -453,6 +584,8 @@ def main(argv=None):
         "solve_T_ms": round(float(solveT_ms), 3), "iters": iters, "iters_T": itersT,
         "step": "setup + solve + transposed solve; value = dofs / (setup + solve)",
         "roofline": roof,
+        "convergence": conv,
+        "setup_roofline": setup_roof,
         "decision_margin_audit": dict(zip(("theta", "phi", "one_point", "drop"), audit)),
         "levels_bandwidth": levels_bw,
         "tuned": tuning is not None,
@@ -488,6 +621,7 @@ def main(argv=None):
                             "solve_T_ms": round(float(t32), 3), "iters": recs32[-1][1].iters,
                             "iters_T": recs32[-1][2].iters, "relres": recs32[-1][1].relres,
                             "max_rel_diff_x_vs_fp64": err_x, "max_rel_diff_y_vs_fp64": err_y,
+                            "relres_host_fp64": host_relres(S, x32), "relres_host_fp64_of_fp64_x": host_relres(S, x),
                             "speedup_vs_fp64": round((setup_ms + solve_ms) / (s32 + v32), 3)}
         log(f"fp32 hierarchy: {out['fp32_hier']['value']:.0f} DOFs/s, {out['fp32_hier']['iters']} iterations")
 
@@ -496,12 +630,17 @@ def main(argv=None):
 
     if not args.no_cpu_baseline:
         import oracle
-        if args.cpu_sample == "full":
+        cs = args.cpu_sample
+        if cs == "auto":
+            cs = "full" if S.n <= 1_000_000 else "96"
+        if cs == "full":
             So, dego = S, degree
             sample = f"full {args.workload} ({S.n} DOFs): one oracle setup + solve to {args.rtol:g}"
         else:
-            So, dego = make_config(args.workload, N=int(args.cpu_sample))
-            sample = f"{args.workload} at N={args.cpu_sample} ({So.n} DOFs): one oracle setup + solve"
+            So, dego = make_config(args.workload, N=int(cs))
+            sample = (f"{args.workload} recipe at N={cs} ({So.n} DOFs, {So.nb} blocks of {So.bs}x{So.bs}): one "
+                      f"oracle setup + solve to {args.rtol:g}; DOFs/s of that sample (its iteration count differs "
+                      f"from the full mesh's)")
         log(f"cpu baseline: {sample}")
         c0 = time.perf_counter()
         O = oracle.Hierarchy(So.nb, So.bs, So.rowptr, So.colidx, So.vals, oracle.Params(degree=dego))
@@ -519,6 +658,20 @@ def main(argv=None):
             if "fp32_hier" in out:
                 out["fp32_hier"]["max_rel_err_x_vs_fp64_oracle"] = float(
                     np.abs(x32.cpu().numpy() - xo).max() / np.abs(xo).max())
+        else:
+            # the GPU paths on the same sample, against the oracle's solution there
+            srp, sci, sva, sb = (torch.from_numpy(a).to(dev) for a in (So.rowptr, So.colidx, So.vals, So.rhs))
+            cmp = {}
+            for prec in ("fp64", "fp32"):
+                Hs = P.Hierarchy(srp, sci, sva, So.bs, P.Params(faces=not args.no_faces, degree=dego, precision=prec))
+                xs, rs = Hs.solve(sb, rtol=args.rtol)
+                Hs.close()
+                cmp[prec] = {"max_rel_err_x_vs_fp64_oracle": float(np.abs(xs.cpu().numpy() - xo).max()
+                                                                   / np.abs(xo).max()),
+                             "iters": rs.iters, "oracle_iters": len(ho)}
+            out["cpu_baseline"]["gpu_on_sample"] = cmp
+            if "fp32_hier" in out:
+                out["fp32_hier"]["max_rel_err_x_vs_fp64_oracle_on_sample"] = cmp["fp32"]["max_rel_err_x_vs_fp64_oracle"]
     print(json.dumps(out), flush=True)
     return 0
 

@@ -102,6 +102,12 @@ typedef struct {
                                  either way; with one lane group per row (nair_params.tuning) the
                                  results are bit-identical with and without copies.  Costs about
                                  the F rows' share of each selected operator in memory. */
+    int32_t matrix_cores;     /* 1 (default): the setup's dense block products (Neumann products,
+                                 T = -D^-1 A_ff, Z = -S D^-1 and the Galerkin blocks) of 9x9, 16x16
+                                 and 25x25 blocks run on the FP64 matrix cores; 0: on the vector
+                                 units.  Both evaluate every entry as the fma chain over the inner
+                                 index in ascending order, so the hierarchies are identical (a zero
+                                 may differ in sign); 0 is the reference for that check. */
 } nair_params;
 
 typedef struct {
@@ -292,7 +298,8 @@ nair_status nair_pool_trim(void);
  * sweep from zero, which reads no matrix, are not timed), 1 outer residual,
  * 2 restriction, 3 interpolation, 4 SpGEMM numeric, 5 SpGEMM symbolic,
  * 6 block inverse,
- * 7 Galerkin merge, 8 dense coarsest product.  nair_timer_read (host outputs)
+ * 7 Galerkin blocks (with the R A products where they are fused), 8 dense
+ * coarsest product, 9 single block products of the setup (T, Z).  nair_timer_read (host outputs)
  * synchronises the device and returns the number of timed launches and their
  * total duration in milliseconds, then resets the counters.  Host only; one
  * timed kernel at a time.

@@ -76,6 +76,7 @@ nair_status nair_default_params(nair_params *p) {
     p->gmres = 0;
     p->faces = 1;
     p->sweep_copy = -1;
+    p->matrix_cores = 1;
     return NAIR_OK;
 }
 
@@ -100,6 +101,7 @@ static nair_status setup_common(int32_t nsys, const int32_t *sys_nb, int32_t nb,
     if (p->cycle != 0 && p->cycle != 1) return bad(nullptr, "cycle must be 0 (V) or 1 (F)");
     if (p->faces != 0 && p->faces != 1) return bad(nullptr, "faces must be 0 or 1");
     if (p->sweep_copy < -1 || p->sweep_copy > 1) return bad(nullptr, "sweep_copy must be -1, 0 or 1");
+    if (p->matrix_cores != 0 && p->matrix_cores != 1) return bad(nullptr, "matrix_cores must be 0 or 1");
     if (p->gmres < 0 || p->gmres > nair::kMaxGmres)
         return bad(nullptr, "gmres must be 0 (stationary iteration) or a restart length in [1, 200]");
     if (p->max_levels < 1 || p->max_levels > nair::kMaxLevels) return bad(nullptr, "max_levels must be in [1, 64]");
@@ -111,6 +113,7 @@ static nair_status setup_common(int32_t nsys, const int32_t *sys_nb, int32_t nb,
     nair_status st = guarded(h, [&]() -> nair_status {
         NAIR_HIP(hipGetDevice(&h->h.device));
         h->h.prm = *p;
+        nair::g_matrix_cores = p->matrix_cores != 0;
         nair::build_hierarchy(h->h, nsys, sys_nb, nb, bs, rowptr, colidx, vals, s);
         if (p->tuning) nair::apply_tuning(h->h, p->tuning);
         h->h.prm.cf_override_host = nullptr;   // host pointers not kept past the call
@@ -335,7 +338,7 @@ void nair_destroy(nair_hier h) {
 }
 
 nair_status nair_timer_select(int32_t kernel, int32_t level) {
-    if (kernel < -1 || kernel > nair::TK_DENSE) return bad(nullptr, "unknown kernel id");
+    if (kernel < -1 || kernel > nair::TK_BLOCKPROD) return bad(nullptr, "unknown kernel id");
     nair::timer_select(kernel, level);
     return NAIR_OK;
 }

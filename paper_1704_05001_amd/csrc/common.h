@@ -94,7 +94,7 @@ struct DevBSR {
 
 // ----------------------------------------------------------- kernel timer
 enum TimedKernel { TK_RELAX = 0, TK_RESIDUAL = 1, TK_RESTRICT = 2, TK_INTERP = 3, TK_SPGEMM_NUM = 4,
-                   TK_SPGEMM_SYM = 5, TK_BLOCKINV = 6, TK_RAP = 7, TK_DENSE = 8 };
+                   TK_SPGEMM_SYM = 5, TK_BLOCKINV = 6, TK_RAP = 7, TK_DENSE = 8, TK_BLOCKPROD = 9 };
 // Brackets launches of the selected (kernel, level) with events; no-ops otherwise.
 struct TimerScope {
     bool on;
@@ -106,6 +106,10 @@ struct TimerScope {
 void timer_select(int kernel, int level);
 void timer_read(int64_t *launches, double *total_ms);
 extern thread_local int g_timer_level;   // level the host code is working on
+// Setup block products of 9x9, 16x16 and 25x25 blocks on the FP64 matrix cores
+// (nair_params.matrix_cores, set per setup call); false: the vector-unit kernels.
+extern thread_local bool g_matrix_cores;
+inline bool use_matrix_cores(int bs) { return g_matrix_cores && (bs == 9 || bs == 16 || bs == 25); }
 extern thread_local bool g_capturing;    // launches are being captured into a graph (timer off)
 
 // ------------------------------------------------------------- utilities
@@ -138,6 +142,11 @@ void scan_exclusive2(const int *in0, int *out0, int n0, int *total0, const int *
 
 // ---------------------------------------------------------- setup kernels
 void launch_block_maxabs(const double *vals, int64_t nnzb, int bs, double *out, hipStream_t s);
+// Per block t < n (vals block src[t] if src, empty at or past *count if count):
+// max-abs entry, nonzero rows | nonzero columns << 32, nonzero rows, and the
+// nonzero rows times bs; each output may be null.  1 <= bs <= 32.
+void launch_block_scan(const double *vals, int64_t n, int bs, const int *src, const int *count, double *maxabs,
+                       uint64_t *meta, uint32_t *rmask, int *rsize, hipStream_t s);
 // skip (nullable): blocks whose inverse is not needed (directly solved systems)
 void launch_block_inverse(const int *rowptr, const int *colidx, const double *vals, int nb, int bs,
                           const int8_t *skip, double *dinv, int *singular_min, hipStream_t s);
@@ -287,7 +296,9 @@ struct RowBlockView {
 // ----------------------------------------------------------- sweep copy
 // What a Jacobi F sweep reads, stored in the order it reads it: the F rows of
 // a level operator (or of its transpose) in F-list order, each without its
-// diagonal block, and D_F^{-1} in the same order.  Row f (the F list's f-th
+// diagonal block, and D_F^{-1} in the same order with the coefficient of input
+// c for output a at c * bs + a (D^{-1} transposed for the forward sweeps,
+// D^{-1} itself for the transposed ones, which apply D^{-T}).  Row f (the F list's f-th
 // row) holds blocks rowptr[f] .. rowptr[f+1]-1 in the row's ascending column
 // order: by their nonzero rows (RowBlocks), or, where the operator has a
 // face-compressed copy (rc > 0), that copy's masks and rmax x cmax rectangles.  Storage for
@@ -305,8 +316,9 @@ struct SweepCopy {
 };
 // Build S from A (and its face copy F when F.on) for the rows of flist.
 // amask (nullable): row masks of A's blocks.
+// trans: the copy of A^T for the transposed sweeps (D^{-T} applied).
 void build_sweep(const DevBSR &A, const FaceCopy &F, const double *dinv, const int *flist, int nF, SweepCopy &S,
-                 hipStream_t s, const uint32_t *amask = nullptr);
+                 hipStream_t s, bool trans, const uint32_t *amask = nullptr);
 void sweep_to_float(SweepCopy &S, int bs, hipStream_t s);
 
 template <typename MT>

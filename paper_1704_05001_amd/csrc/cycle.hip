@@ -387,7 +387,9 @@ __device__ inline void sweep_rows(const SweepView<MT> &S, const int *__restrict_
     int I = -1;
     if (L.valid && f < nF) I = flist[f];
     if (I >= 0 && !live(gate, I)) I = -1;
-    DinvRow<BS, TRANS> dr;
+    // the copy's inverse block holds the coefficient of input c for output a at
+    // c * bs + a in both directions (D^{-1} transposed, or D^{-1} for D^{-T})
+    DinvRow<BS, true> dr;
     const double *D = S.dinv + static_cast<int64_t>(f) * bs * bs;
     const int64_t o = static_cast<int64_t>(I) * bs + L.a;
     double rv = 0.0;

@@ -20,30 +20,6 @@ __device__ inline int nth_set_bit(uint32_t m, int k) {
     return __ffs(static_cast<int>(m)) - 1;
 }
 
-// meta[t] = nonzero rows | nonzero columns << 32: one thread per row of a
-// block (a block's rows are contiguous in memory), the rows of a block
-// combined in LDS, one store per block.
-__global__ __launch_bounds__(256) void k_face_masks(const double *__restrict__ vals, int64_t nnzb, int bs,
-                                                   unsigned long long *__restrict__ meta) {
-    __shared__ unsigned long long m[256];
-    const int per = 256 / bs;
-    const int lb = threadIdx.x / bs;
-    const int a = threadIdx.x - lb * bs;
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * per + lb;
-    if (threadIdx.x < per) m[threadIdx.x] = 0ull;
-    __syncthreads();
-    if (lb < per && t < nnzb) {
-        const double *row = vals + (t * bs + a) * bs;
-        uint32_t cm = 0u;
-        for (int c = 0; c < bs; ++c)
-            if (row[c] != 0.0) cm |= 1u << c;
-        if (cm != 0u) atomicOr(m + lb, (static_cast<unsigned long long>(cm) << 32) | (1ull << a));
-    }
-    __syncthreads();
-    const int64_t to = static_cast<int64_t>(blockIdx.x) * per + threadIdx.x;
-    if (threadIdx.x < per && to < nnzb) meta[to] = m[threadIdx.x];
-}
-
 // Per block row: where its diagonal block sits (its meta cleared: kept whole),
 // and the largest nonzero row and column counts of its off-diagonal blocks,
 // combined per workgroup before one atomic each.
@@ -123,9 +99,8 @@ void build_face(const DevBSR &A, FaceCopy &F, hipStream_t s) {
     NAIR_HIP(hipMemsetAsync(maxrc.get(), 0, sizeof(int) * 2, s));
     NAIR_HIP(hipMemsetAsync(diagpos.get(), 0, sizeof(int) * A.nb, s));   // (every validated row has its diagonal)
     auto *m64 = reinterpret_cast<unsigned long long *>(meta.get());
-    const int per = 256 / bs;
-    k_face_masks<<<static_cast<unsigned>((A.nnzb + per - 1) / per), 256, 0, s>>>(A.vals.get(), A.nnzb, bs, m64);
-    NAIR_HIP(hipGetLastError());
+    // meta[t] = nonzero rows | nonzero columns << 32
+    launch_block_scan(A.vals.get(), A.nnzb, bs, nullptr, nullptr, nullptr, meta.get(), nullptr, nullptr, s);
     k_face_rows<<<blocks_for(A.nb), 256, 0, s>>>(A.rowptr.get(), A.colidx.get(), A.nb, m64, diagpos.get(),
                                                   maxrc.get());
     NAIR_HIP(hipGetLastError());

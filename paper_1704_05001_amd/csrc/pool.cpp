@@ -104,6 +104,7 @@ void pool_trim() {
 // ------------------------------------------------------------ kernel timer
 
 thread_local int g_timer_level = 0;
+thread_local bool g_matrix_cores = true;
 thread_local bool g_capturing = false;
 
 namespace {

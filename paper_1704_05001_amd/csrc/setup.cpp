@@ -358,6 +358,7 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
             DBuf<int> trow(nT), tsrc(nT);
             launch_fill_T(L.A.rowptr.get(), L.A.colidx.get(), L.mask.get(), L.cf.get(), n, T.rowptr.get(),
                           T.colidx.get(), trow.get(), tsrc.get(), s);
+            TimerScope ts(TK_BLOCKPROD, l, s);
             launch_block_product(nT, bs, L.dinv.get(), trow.get(), L.A.vals.get(), tsrc.get(), -1.0, T.vals.get(),
                                  s);
         }
@@ -393,11 +394,14 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         L.Z.rowptr = std::move(Ssum.rowptr);
         L.Z.colidx = std::move(Ssum.colidx);
         L.Z.vals.alloc(static_cast<size_t>(L.Z.cap) * bb);
-        const bool masks = bs == 9 || bs == 16;   // the matrix-core products give each block's nonzero rows
+        const bool masks = use_matrix_cores(bs);   // the matrix-core products give each block's nonzero rows
         if (masks) L.zmask.alloc(static_cast<size_t>(L.Z.cap));
-        launch_block_product(L.Z.cap, bs, Ssum.vals.get(), nullptr, L.dinv.get(), L.Z.colidx.get(), -1.0,
-                             L.Z.vals.get(), s, L.Z.nnzb < 0 ? L.Z.rowptr.get() + nc : nullptr,
-                             masks ? L.zmask.get() : nullptr);
+        {
+            TimerScope ts(TK_BLOCKPROD, l, s);
+            launch_block_product(L.Z.cap, bs, Ssum.vals.get(), nullptr, L.dinv.get(), L.Z.colidx.get(), -1.0,
+                                 L.Z.vals.get(), s, L.Z.nnzb < 0 ? L.Z.rowptr.get() + nc : nullptr,
+                                 masks ? L.zmask.get() : nullptr);
+        }
         // Galerkin: K = R A P with R = [Z I], filtered; K's block sizes come along
         auto next = std::make_unique<Level>();
         galerkin(L.Z, L.cpts.get(), L.A, L.pmap.get(), nc, p.drop, next->A, L.margin.get(), next->bnorm,
@@ -423,7 +427,7 @@ void build_sweeps(Hier &h, bool trans, hipStream_t s) {
         SweepCopy &S = trans ? L.sweepT : L.sweep;
         // (A's row masks, where the Galerkin step gave them, are no use for A^T)
         if (!S.on)
-            build_sweep(trans ? L.AT : L.A, trans ? L.faceT : L.face, L.dinv.get(), L.flist.get(), L.nF, S, s,
+            build_sweep(trans ? L.AT : L.A, trans ? L.faceT : L.face, L.dinv.get(), L.flist.get(), L.nF, S, s, trans,
                         trans ? nullptr : L.amask.get());
         if (!trans && !L.zrows.on && L.Z.nnzb > 0)
             build_row_blocks(L.Z.vals.get(), L.Z.nnzb, L.Z.bs, L.zrows, s, nullptr, nullptr, L.zmask.get());

@@ -3,6 +3,7 @@
 // restriction.  Values that feed later comparisons are computed in one fixed
 // order (fma chains, c ascending), with no implicit contraction.
 #include "common.h"
+#include "mfma_tile.h"
 
 #pragma clang fp contract(off)
 
@@ -19,28 +20,46 @@ __device__ inline double wave_max(double v) {
 
 // ----------------------------------------------------------- block sizes
 
-// out[b] = max_e |vals[b][e]|; one wave per block, four blocks per workgroup.
-// ||block||_max: one thread per block row (a row's bs entries are contiguous),
-// the rows of a block combined in LDS.  max is exact, so the order is free.
-__global__ __launch_bounds__(256) void k_block_maxabs(const double *__restrict__ vals, int64_t nnzb, int bs,
-                                                     double *__restrict__ out) {
-    __shared__ double m[256];
-    const int per = 256 / bs;
-    const int lb = threadIdx.x / bs;
-    const int a = threadIdx.x - lb * bs;
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * per + lb;
-    double v = 0.0;
-    if (lb < per && t < nnzb) {
-        const double *row = vals + (t * bs + a) * bs;
-        for (int c = 0; c < bs; ++c) v = fmax(v, fabs(row[c]));
+// One pass over n blocks that gives, per block, its max-abs entry (entries that
+// are NaN are ignored, as fmax ignores them), the mask of its nonzero rows and
+// the mask of its nonzero columns.  L lanes share a block (L: the power of two
+// >= bs*bs, at most 64), so a block's entries are read as consecutive words;
+// the lanes' partial results meet by shuffles (max and or are exact, so the
+// order is free).  Block t is vals[src[t]] when src is given; with count,
+// blocks at or past *count are empty (zero results).  Outputs may be null.
+__global__ __launch_bounds__(256) void k_block_scan(const double *__restrict__ vals, int64_t n, int bs, int L,
+                                                   const int *__restrict__ src, const int *__restrict__ count,
+                                                   double *__restrict__ maxabs, unsigned long long *__restrict__ meta,
+                                                   uint32_t *__restrict__ rmask, int *__restrict__ rsize) {
+    const int per = 256 / L;
+    const int sub = static_cast<int>(threadIdx.x) & (L - 1);
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * per + static_cast<int>(threadIdx.x) / L;
+    const int bb = bs * bs;
+    const int64_t nn = count ? min(static_cast<int64_t>(*count), n) : n;
+    double m = 0.0;
+    uint32_t rm = 0u, cm = 0u;
+    if (t < nn) {
+        const double *blk = vals + (src ? static_cast<int64_t>(src[t]) : t) * bb;
+        for (int e = sub; e < bb; e += L) {
+            const double x = blk[e];
+            if (x != 0.0) {
+                const int r = e / bs;
+                rm |= 1u << r;
+                cm |= 1u << (e - r * bs);
+            }
+            m = fmax(m, fabs(x));
+        }
     }
-    m[threadIdx.x] = v;
-    __syncthreads();
-    const int64_t to = static_cast<int64_t>(blockIdx.x) * per + threadIdx.x;
-    if (threadIdx.x < per && to < nnzb) {
-        double r = 0.0;
-        for (int q = 0; q < bs; ++q) r = fmax(r, m[threadIdx.x * bs + q]);
-        out[to] = r;
+    for (int o = L >> 1; o > 0; o >>= 1) {
+        m = fmax(m, __shfl_xor(m, o, kWave));
+        rm |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(rm), o, kWave));
+        cm |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(cm), o, kWave));
+    }
+    if (sub == 0 && t < n) {
+        if (maxabs) maxabs[t] = m;
+        if (meta) meta[t] = (static_cast<unsigned long long>(cm) << 32) | rm;
+        if (rmask) rmask[t] = rm;
+        if (rsize) rsize[t] = __popc(rm) * bs;
     }
 }
 
@@ -585,12 +604,11 @@ __global__ __launch_bounds__(256) void k_block_product(int64_t n, int bs_rt, con
     }
 }
 
-// The same on the FP64 matrix cores (bs 9 and 16): one wave per block, the
-// product in a 16x16 accumulator (entry (i, j) in lane j + 16 (i%4), register
-// i/4) built by ceil(bs/4) 16x16x4 steps, each the ascending fma chain over its
-// four inner indices, from +0; then the sign.  Bit-identical to the chain above.
-typedef double double4_t __attribute__((ext_vector_type(4)));
-
+// The same on the FP64 matrix cores (bs 9, 16, 25; mfma_tile.h): one wave per
+// block, the product in 16x16 accumulator tiles built by ceil(bs/4) 16x16x4
+// steps per tile, each the ascending fma chain over its four inner indices,
+// from +0; then the sign.  Bit-identical to the chain above (up to the sign of
+// a zero, see mfma_tile.h).  Also the mask of the block's nonzero rows.
 template <int BS>
 __global__ __launch_bounds__(256) void k_block_product_mfma(int64_t n, const double *__restrict__ X,
                                                            const int *__restrict__ xi, const double *__restrict__ Y,
@@ -598,34 +616,24 @@ __global__ __launch_bounds__(256) void k_block_product_mfma(int64_t n, const dou
                                                            double *__restrict__ out, const int *__restrict__ count,
                                                            uint32_t *__restrict__ rmask) {
     constexpr int bb = BS * BS;
-    constexpr int KQ = (BS + 3) / 4;
     const int lane = threadIdx.x & 63;
     const int row = lane & 15, kk = lane >> 4;
     const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (t >= (count ? *count : n)) return;   // whole waves
     const double *x = X + static_cast<int64_t>(xi ? xi[t] : t) * bb;
     const double *y = Y + static_cast<int64_t>(yi[t]) * bb;
-    double a[KQ], b[KQ];
-#pragma unroll
-    for (int q = 0; q < KQ; ++q) {
-        const int c = 4 * q + kk;
-        a[q] = (row < BS && c < BS) ? x[row * BS + c] : 0.0;
-        b[q] = (row < BS && c < BS) ? y[c * BS + row] : 0.0;
-    }
-    double4_t acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int q = 0; q < KQ; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc, 0, 0, 0);
+    MfmaOperands<BS> op;
+    op.load_product(x, y, row, kk);
+    MfmaAcc<BS> acc;
+    acc.zero();
+    op.apply_product(acc);
     double *o = out + t * bb;
     uint32_t bits = 0u;   // this lane's nonzero rows, then the block's
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = kk + 4 * r;
-        if (i < BS && row < BS) {
-            const double v = sign * acc[r];
-            o[i * BS + row] = v;
-            if (v != 0.0) bits |= 1u << i;
-        }
-    }
+    mfma_for_entries<BS>(acc, row, kk, [&](int i, int j, double v) {
+        const double w = sign * v;
+        o[i * BS + j] = w;
+        if (w != 0.0) bits |= 1u << i;
+    });
     if (rmask) {
 #pragma unroll
         for (int w = 32; w > 0; w >>= 1) bits |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(bits), w, 64));
@@ -655,11 +663,20 @@ unsigned cap_grid(int64_t g) { return static_cast<unsigned>(g > 65536 * 16 ? 655
 
 }  // namespace
 
-void launch_block_maxabs(const double *vals, int64_t nnzb, int bs, double *out, hipStream_t s) {
-    if (nnzb <= 0) return;
-    const int per = 256 / bs;
-    k_block_maxabs<<<static_cast<unsigned>((nnzb + per - 1) / per), 256, 0, s>>>(vals, nnzb, bs, out);
+void launch_block_scan(const double *vals, int64_t n, int bs, const int *src, const int *count, double *maxabs,
+                       uint64_t *meta, uint32_t *rmask, int *rsize, hipStream_t s) {
+    if (n <= 0) return;
+    if (bs < 1 || bs > 32) fail(NAIR_EINVAL, "block scan: bs must be in 1..32");
+    int L = 1;
+    while (L < bs * bs && L < kWave) L <<= 1;
+    const int per = 256 / L;
+    k_block_scan<<<grid_for(n, per), 256, 0, s>>>(vals, n, bs, L, src, count, maxabs,
+                                                  reinterpret_cast<unsigned long long *>(meta), rmask, rsize);
     NAIR_HIP(hipGetLastError());
+}
+
+void launch_block_maxabs(const double *vals, int64_t nnzb, int bs, double *out, hipStream_t s) {
+    launch_block_scan(vals, nnzb, bs, nullptr, nullptr, out, nullptr, nullptr, nullptr, s);
 }
 
 void launch_block_inverse(const int *rowptr, const int *colidx, const double *vals, int nb, int bs,
@@ -787,14 +804,15 @@ void launch_fill_Acf(const int *rowptr, const int *colidx, const int8_t *cf, con
 void launch_block_product(int64_t n, int bs, const double *X, const int *xi, const double *Y, const int *yi,
                           double sign, double *out, hipStream_t s, const int *count, uint32_t *rmask) {
     if (n <= 0) return;
-    if (bs == 9 || bs == 16) {
+    if (use_matrix_cores(bs)) {
         const unsigned mgrid = static_cast<unsigned>((n + 3) / 4);   // four waves (blocks) per workgroup
         if (bs == 9) k_block_product_mfma<9><<<mgrid, 256, 0, s>>>(n, X, xi, Y, yi, sign, out, count, rmask);
-        else k_block_product_mfma<16><<<mgrid, 256, 0, s>>>(n, X, xi, Y, yi, sign, out, count, rmask);
+        else if (bs == 16) k_block_product_mfma<16><<<mgrid, 256, 0, s>>>(n, X, xi, Y, yi, sign, out, count, rmask);
+        else k_block_product_mfma<25><<<mgrid, 256, 0, s>>>(n, X, xi, Y, yi, sign, out, count, rmask);
         NAIR_HIP(hipGetLastError());
         return;
     }
-    if (rmask) fail(NAIR_EDEVICE, "launch_block_product: row masks only for 9x9 and 16x16 blocks");
+    if (rmask) fail(NAIR_EDEVICE, "launch_block_product: row masks only from the matrix-core products");
     const unsigned grid = cap_grid((n * bs + 255) / 256);
     switch (bs) {
         case 4: k_block_product<4><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out, count); break;

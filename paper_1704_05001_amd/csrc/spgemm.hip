@@ -13,6 +13,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "mfma_tile.h"
 
 #pragma clang fp contract(off)
 
@@ -586,66 +587,18 @@ __global__ __launch_bounds__(256) void k_spgemm_pairs(int64_t nnz, int bs_rt, co
     }
 }
 
-// The same products on the matrix cores (bs <= 16): one wave per output block
-// holds it in a 16x16 FP64 MFMA accumulator (entry (i, j) in lane j + 16 (i%4),
-// register i/4); each pair contributes ceil(bs/4) 16x16x4 steps over c = 4q ..
-// 4q+3, zero beyond bs.  A 16x16x4 FP64 step updates each entry as the fma
-// chain over its four c in ascending order, so the sums are the same, bit for
-// bit, as the per-thread chains (padding adds exact zeros); identity pairs add
-// Y's entries plainly, in their place in the pair order.
-typedef double double4_t __attribute__((ext_vector_type(4)));
-
-// One block pair's operands as the MFMA steps take them: per step q the A
-// fragment (X row `row`, inner index 4q + kk) and the B fragment (Y inner index
-// 4q + kk, column `row`), zero beyond bs; for an identity pair Y's entries
-// (i, row), i = kk + 4q, added plainly.
+// The same products on the matrix cores (bs 9, 16, 25; mfma_tile.h): one wave
+// per output block holds it in 16x16 FP64 accumulator tiles; each pair adds
+// ceil(bs/4) 16x16x4 steps per tile over c = 4q .. 4q+3, zero beyond bs.  A
+// 16x16x4 FP64 step updates each entry as the fma chain over its four c in
+// ascending order, so the sums are the per-thread chains above (padding adds
+// exact zeros); identity pairs add Y's entries plainly, in their place in the
+// pair order.
 template <int BS>
-struct MfmaPair {
-    static constexpr int KQ = (BS + 3) / 4;
-    double a[KQ], b[KQ];
-    bool ident;
-};
-
-template <int BS>
-__device__ inline MfmaPair<BS> mfma_load(const int2 pr, const double *__restrict__ X, const double *__restrict__ Y,
-                                         int row, int kk) {
-    constexpr int bb = BS * BS;
-    constexpr int KQ = MfmaPair<BS>::KQ;
-    MfmaPair<BS> f;
-    const double *y = Y + static_cast<int64_t>(pr.y) * bb;
-    f.ident = pr.x < 0;
-    if (f.ident) {
-#pragma unroll
-        for (int q = 0; q < KQ; ++q) {
-            const int i = kk + 4 * q;
-            f.a[q] = (i < BS && row < BS) ? y[i * BS + row] : 0.0;
-            f.b[q] = 0.0;
-        }
-    } else {
-        const double *x = X + static_cast<int64_t>(pr.x) * bb;
-#pragma unroll
-        for (int q = 0; q < KQ; ++q) {
-            const int c = 4 * q + kk;
-            f.a[q] = (row < BS && c < BS) ? x[row * BS + c] : 0.0;
-            f.b[q] = (row < BS && c < BS) ? y[c * BS + row] : 0.0;
-        }
-    }
-    return f;
-}
-
-template <int BS>
-__device__ inline void mfma_apply(const MfmaPair<BS> &f, double4_t &acc, int row, int kk) {
-    constexpr int KQ = MfmaPair<BS>::KQ;
-    if (f.ident) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = kk + 4 * r;
-            if (r < KQ && i < BS && row < BS) acc[r] = acc[r] + f.a[r];
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < KQ; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(f.a[q], f.b[q], acc, 0, 0, 0);
-    }
+__device__ inline void mfma_load_pair(MfmaOperands<BS> &f, const int2 pr, const double *__restrict__ X,
+                                      const double *__restrict__ Y, int row, int kk) {
+    constexpr int64_t bb = BS * BS;
+    f.load(pr.x < 0 ? nullptr : X + pr.x * bb, Y + pr.y * bb, row, kk);
 }
 
 template <int BS>
@@ -653,29 +606,26 @@ __global__ __launch_bounds__(256) void k_spgemm_mfma(int64_t nnz, const int *__r
                                                     const int2 *__restrict__ pairs, const double *__restrict__ X,
                                                     const double *__restrict__ Y, double *__restrict__ C) {
     constexpr int bb = BS * BS;
-    constexpr int KQ = MfmaPair<BS>::KQ;
     const int lane = threadIdx.x & 63;
     const int row = lane & 15, kk = lane >> 4;   // A: row i, B: column j; both k = kk
     const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (t >= nnz) return;   // whole waves
-    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    MfmaAcc<BS> acc;
+    acc.zero();
     const int k0 = pairptr[t], k1 = pairptr[t + 1];
     if (k0 < k1) {
         // the next pair's operands load while this pair's steps run
-        MfmaPair<BS> cur = mfma_load<BS>(pairs[k0], X, Y, row, kk);
+        MfmaOperands<BS> cur;
+        mfma_load_pair<BS>(cur, pairs[k0], X, Y, row, kk);
         for (int k = k0; k < k1; ++k) {
-            MfmaPair<BS> nxt = cur;
-            if (k + 1 < k1) nxt = mfma_load<BS>(pairs[k + 1], X, Y, row, kk);
-            mfma_apply<BS>(cur, acc, row, kk);
+            MfmaOperands<BS> nxt = cur;
+            if (k + 1 < k1) mfma_load_pair<BS>(nxt, pairs[k + 1], X, Y, row, kk);
+            cur.apply(acc, row, kk);
             cur = nxt;
         }
     }
     double *out = C + t * bb;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = kk + 4 * r;
-        if (r < KQ && i < BS && row < BS) out[i * BS + row] = acc[r];
-    }
+    mfma_for_entries<BS>(acc, row, kk, [&](int i, int j, double v) { out[i * BS + j] = v; });
 }
 
 // The Galerkin blocks straight from the pair lists: K block t is the sum, in
@@ -694,12 +644,12 @@ __global__ __launch_bounds__(256) void k_galerkin_mfma(int64_t nnz, const int *_
                                                       const double *__restrict__ Y, double *__restrict__ K,
                                                       double *__restrict__ knorm, uint32_t *__restrict__ kmask) {
     constexpr int bb = BS * BS;
-    constexpr int KQ = MfmaPair<BS>::KQ;
     const int lane = threadIdx.x & 63;
     const int row = lane & 15, kk = lane >> 4;
     const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (t >= nnz) return;   // whole waves
-    double4_t kacc = {0.0, 0.0, 0.0, 0.0};
+    MfmaAcc<BS> kacc;
+    kacc.zero();
     const int c0 = kptr[t], c1 = kptr[t + 1];
     for (int base = c0; base < c1; base += 64) {
         const int cnt = min(64, c1 - base);
@@ -713,9 +663,10 @@ __global__ __launch_bounds__(256) void k_galerkin_mfma(int64_t nnz, const int *_
         int j = 0;
         int k = __shfl(pb, 0, 64), ke = __shfl(pe, 0, 64);
         bool have = k < ke;
-        double4_t acc = {0.0, 0.0, 0.0, 0.0};
-        MfmaPair<BS> cur{};
-        if (have) cur = mfma_load<BS>(pairs[k], X, Y, row, kk);
+        MfmaAcc<BS> acc;
+        acc.zero();
+        MfmaOperands<BS> cur{};
+        if (have) mfma_load_pair<BS>(cur, pairs[k], X, Y, row, kk);
         while (j < cnt) {
             int jn = j, kn = k + 1, ken = ke;
             if (!have || kn >= ke) {   // block j ends with this pair
@@ -726,13 +677,12 @@ __global__ __launch_bounds__(256) void k_galerkin_mfma(int64_t nnz, const int *_
                 }
             }
             const bool haven = jn < cnt && kn < ken;
-            MfmaPair<BS> nxt = cur;
-            if (haven) nxt = mfma_load<BS>(pairs[kn], X, Y, row, kk);
-            if (have) mfma_apply<BS>(cur, acc, row, kk);
+            MfmaOperands<BS> nxt = cur;
+            if (haven) mfma_load_pair<BS>(nxt, pairs[kn], X, Y, row, kk);
+            if (have) cur.apply(acc, row, kk);
             if (jn != j) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) kacc[r] = kacc[r] + acc[r];
-                acc = double4_t{0.0, 0.0, 0.0, 0.0};
+                kacc.add(acc);
+                acc.zero();
             }
             j = jn;
             k = kn;
@@ -744,15 +694,11 @@ __global__ __launch_bounds__(256) void k_galerkin_mfma(int64_t nnz, const int *_
     double *out = K + t * bb;
     double m = 0.0;
     uint32_t bits = 0u;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = kk + 4 * r;
-        if (r < KQ && i < BS && row < BS) {
-            out[i * BS + row] = kacc[r];
-            m = fmax(m, fabs(kacc[r]));
-            if (kacc[r] != 0.0) bits |= 1u << i;
-        }
-    }
+    mfma_for_entries<BS>(kacc, row, kk, [&](int i, int jj, double v) {
+        out[i * BS + jj] = v;
+        m = fmax(m, fabs(v));
+        if (v != 0.0) bits |= 1u << i;
+    });
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         m = fmax(m, __shfl_xor(m, o, 64));
@@ -981,12 +927,16 @@ void spgemm_values(const DevBSR &X, const DevBSR &Y, const Pairs &P, DevBSR &C, 
     const unsigned grid = cap_grid((total + 255) / 256);
     TimerScope ts(TK_SPGEMM_NUM, g_timer_level, s);
     const unsigned mgrid = static_cast<unsigned>((nnz + 3) / 4);   // four waves per workgroup
-    if (bs == 9) {
-        k_spgemm_mfma<9><<<mgrid, 256, 0, s>>>(nnz, P.pairptr.get(), P.pairs.get(), X.vals.get(), Y.vals.get(),
-                                               C.vals.get());
-    } else if (bs == 16) {
-        k_spgemm_mfma<16><<<mgrid, 256, 0, s>>>(nnz, P.pairptr.get(), P.pairs.get(), X.vals.get(), Y.vals.get(),
-                                                C.vals.get());
+    if (use_matrix_cores(bs)) {
+        if (bs == 9)
+            k_spgemm_mfma<9><<<mgrid, 256, 0, s>>>(nnz, P.pairptr.get(), P.pairs.get(), X.vals.get(), Y.vals.get(),
+                                                   C.vals.get());
+        else if (bs == 16)
+            k_spgemm_mfma<16><<<mgrid, 256, 0, s>>>(nnz, P.pairptr.get(), P.pairs.get(), X.vals.get(), Y.vals.get(),
+                                                    C.vals.get());
+        else
+            k_spgemm_mfma<25><<<mgrid, 256, 0, s>>>(nnz, P.pairptr.get(), P.pairs.get(), X.vals.get(), Y.vals.get(),
+                                                    C.vals.get());
     } else {
         NAIR_BS_DISPATCH(bs, k_spgemm_pairs, <<<grid, 256, 0, s>>>(nnz, bs, P.pairptr.get(), P.pairs.get(),
                                                                    X.vals.get(), Y.vals.get(), C.vals.get()));
@@ -1039,7 +989,7 @@ void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int 
     spgemm_structure(Z, cpts, A, RA, P, s);
     const int bs = RA.bs;
     const int bb = bs * bs;
-    const bool fused = bs == 9 || bs == 16;
+    const bool fused = use_matrix_cores(bs);
     if (!fused) {
         RA.vals.alloc(static_cast<size_t>(RA.nnzb) * bb);
         spgemm_values(Z, A, P, RA, s);
@@ -1083,8 +1033,12 @@ void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int 
                 k_galerkin_mfma<9><<<mgrid, 256, 0, s>>>(nnz, kptr.get(), klist.get(), P.pairptr.get(),
                                                          P.pairs.get(), Z.vals.get(), A.vals.get(), kval.get(),
                                                          knorm.get(), kbits.get());
-            else
+            else if (bs == 16)
                 k_galerkin_mfma<16><<<mgrid, 256, 0, s>>>(nnz, kptr.get(), klist.get(), P.pairptr.get(),
+                                                          P.pairs.get(), Z.vals.get(), A.vals.get(), kval.get(),
+                                                          knorm.get(), kbits.get());
+            else
+                k_galerkin_mfma<25><<<mgrid, 256, 0, s>>>(nnz, kptr.get(), klist.get(), P.pairptr.get(),
                                                           P.pairs.get(), Z.vals.get(), A.vals.get(), kval.get(),
                                                           knorm.get(), kbits.get());
         } else {

@@ -28,18 +28,22 @@ __global__ __launch_bounds__(256) void k_sweep_count(const int *__restrict__ row
 // diagonal go to positions orp[f] ... in order: their column indices, and
 // with FACE the face copy's masks and rc-word rectangles, else the source
 // block index (osrc) for the row-compressed copy made next; D_I^{-1} goes to
-// position f.  Nothing is written at or past cap.
+// position f with the coefficient of input c for output a at c * bb/bs + a
+// (dtrans: D_I^{-1} transposed; else as it is, for the sweeps that apply
+// D^{-T}).  Nothing is written at or past cap.
 template <bool FACE>
 __global__ __launch_bounds__(256) void k_sweep_fill(const int *__restrict__ rowptr, const int *__restrict__ colidx,
                                                    const double *__restrict__ src, const uint64_t *__restrict__ fmeta,
                                                    const double *__restrict__ dinv, const int *__restrict__ flist,
-                                                   int nF, int w, int bb, int64_t cap, const int *__restrict__ orp,
+                                                   int nF, int w, int bs, bool dtrans, int64_t cap,
+                                                   const int *__restrict__ orp,
                                                    int *__restrict__ ocol, uint64_t *__restrict__ ometa,
                                                    double *__restrict__ ovals, int *__restrict__ osrc,
                                                    double *__restrict__ odinv) {
     const int lane = threadIdx.x & 63;
     const int f = blockIdx.x * 4 + static_cast<int>(threadIdx.x >> 6);
     if (f >= nF) return;   // whole waves
+    const int bb = bs * bs;
     const int I = flist[f];
     const int lo = rowptr[I], hi = rowptr[I + 1];
     const int o = orp[f];
@@ -75,33 +79,9 @@ __global__ __launch_bounds__(256) void k_sweep_fill(const int *__restrict__ rowp
     }
     const double *Di = dinv + static_cast<int64_t>(I) * bb;
     double *Do = odinv + static_cast<int64_t>(f) * bb;
-    for (int e = lane; e < bb; e += 64) Do[e] = Di[e];
-}
-
-// mask[t] and size[t] = nonzero rows * bs of block src[t] (t < count; past it
-// empty): one thread per block row, combined in LDS.
-__global__ __launch_bounds__(256) void k_rb_mask(const double *__restrict__ vals, int64_t n, int bs,
-                                                const int *__restrict__ src, const int *__restrict__ count,
-                                                uint32_t *__restrict__ mask, int *__restrict__ size) {
-    __shared__ uint32_t m[256];
-    const int per = 256 / bs;
-    const int lb = threadIdx.x / bs;
-    const int a = threadIdx.x - lb * bs;
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * per + lb;
-    const int64_t nn = count ? *count : n;
-    if (threadIdx.x < per) m[threadIdx.x] = 0u;
-    __syncthreads();
-    if (lb < per && t < nn) {
-        const double *row = vals + ((src ? src[t] : t) * static_cast<int64_t>(bs) + a) * bs;
-        bool nz = false;
-        for (int c = 0; c < bs; ++c) nz = nz || row[c] != 0.0;
-        if (nz) atomicOr(m + lb, 1u << a);
-    }
-    __syncthreads();
-    const int64_t tt = static_cast<int64_t>(blockIdx.x) * per + threadIdx.x;
-    if (threadIdx.x < per && tt < n) {
-        mask[tt] = m[threadIdx.x];
-        size[tt] = __popc(m[threadIdx.x]) * bs;
+    for (int e = lane; e < bb; e += 64) {
+        const int c = e / bs, a = e - c * bs;   // output position: input c, output a
+        Do[e] = dtrans ? Di[a * bs + c] : Di[e];
     }
 }
 
@@ -146,12 +126,10 @@ bool build_row_blocks(const double *vals, int64_t n, int bs, RowBlocks &R, hipSt
     DBuf<int> size(static_cast<size_t>(n));
     if (masks) {   // the blocks' row masks are known: no pass over their entries
         k_rb_take<<<grid_for(n, 256), 256, 0, s>>>(masks, n, bs, src, count, R.mask.get(), size.get());
-    } else {
-        const int per = 256 / bs;
-        k_rb_mask<<<static_cast<unsigned>((n + per - 1) / per), 256, 0, s>>>(vals, n, bs, src, count, R.mask.get(),
-                                                                             size.get());
+        NAIR_HIP(hipGetLastError());
+    } else {   // mask[t] and size[t] = nonzero rows * bs of block src[t] (t < count; past it empty)
+        launch_block_scan(vals, n, bs, src, count, nullptr, nullptr, R.mask.get(), size.get(), s);
     }
-    NAIR_HIP(hipGetLastError());
     scan_exclusive(size.get(), R.off.get(), static_cast<int>(n), s);
     k_rb_fill<<<grid_for(n * bb, 256), 256, 0, s>>>(vals, n, bs, src, count, R.mask.get(), R.off.get(),
                                                     R.vals.get());
@@ -168,7 +146,7 @@ void row_blocks_to_float(RowBlocks &R, int64_t n, int bs, hipStream_t s) {
 }
 
 void build_sweep(const DevBSR &A, const FaceCopy &F, const double *dinv, const int *flist, int nF, SweepCopy &S,
-                 hipStream_t s, const uint32_t *amask) {
+                 hipStream_t s, bool trans, const uint32_t *amask) {
     S = SweepCopy();
     if (nF <= 0 || A.nb == 0 || !dinv || !flist) return;
     const int bs = A.bs;
@@ -195,14 +173,14 @@ void build_sweep(const DevBSR &A, const FaceCopy &F, const double *dinv, const i
     const unsigned grid = static_cast<unsigned>((nF + 3) / 4);
     if (face) {
         k_sweep_fill<true><<<grid, 256, 0, s>>>(A.rowptr.get(), A.colidx.get(), F.vals.get(), F.meta.get(), dinv,
-                                                flist, nF, w, bb, S.cap, S.rowptr.get(), S.colidx.get(),
+                                                flist, nF, w, bs, !trans, S.cap, S.rowptr.get(), S.colidx.get(),
                                                 S.meta.get(), S.vals.get(), nullptr, S.dinv.get());
         NAIR_HIP(hipGetLastError());
     } else {
         DBuf<int> src(static_cast<size_t>(S.cap));
         k_sweep_fill<false><<<grid, 256, 0, s>>>(A.rowptr.get(), A.colidx.get(), nullptr, nullptr, dinv, flist, nF,
-                                                 w, bb, S.cap, S.rowptr.get(), S.colidx.get(), nullptr, nullptr,
-                                                 src.get(), S.dinv.get());
+                                                 w, bs, !trans, S.cap, S.rowptr.get(), S.colidx.get(), nullptr,
+                                                 nullptr, src.get(), S.dinv.get());
         NAIR_HIP(hipGetLastError());
         if (!build_row_blocks(A.vals.get(), S.cap, bs, S.rows, s, src.get(), S.rowptr.get() + nF, amask)) return;
     }

@@ -29,7 +29,7 @@ EXPORTED = ["nair_default_params", "nair_setup", "nair_solve", "nair_solve_T", "
 TUNE_KINDS = ("relax", "relax_T", "residual_T", "restrict", "interp_T", "residual")
 
 KERNELS = {"relax": 0, "residual": 1, "restrict": 2, "interp": 3, "spgemm_numeric": 4,
-           "spgemm_symbolic": 5, "block_inverse": 6, "galerkin": 7, "dense": 8}
+           "spgemm_symbolic": 5, "block_inverse": 6, "galerkin": 7, "dense": 8, "block_product": 9}
 
 
 class NairError(RuntimeError):
@@ -45,7 +45,7 @@ class _Params(C.Structure):
                 ("max_coarse_dofs", C.c_int32), ("seed", C.c_uint64),
                 ("cf_override_host", C.c_void_p), ("precision", C.c_int32), ("tuning", C.c_void_p),
                 ("form", C.c_int32), ("cycle", C.c_int32), ("gmres", C.c_int32), ("faces", C.c_int32),
-                ("sweep_copy", C.c_int32)]
+                ("sweep_copy", C.c_int32), ("matrix_cores", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -211,6 +211,7 @@ class Params:
     gmres: int = 0               # 0: stationary iteration; m > 0: GMRES(m) preconditioned by the cycle
     faces: bool = True           # compact copy of the finest operator's face blocks for the cycle
     sweep_copy: str = "auto"     # F rows in F order for the sweeps: "auto" (large levels), "off", "all"
+    matrix_cores: bool = True    # setup block products of 9x9/16x16/25x25 blocks on the FP64 matrix cores
 
 
 @dataclass
@@ -258,6 +259,7 @@ class Hierarchy:
         if params.sweep_copy not in ("auto", "off", "all"):
             raise ValueError("sweep_copy must be 'auto', 'off' or 'all'")
         p.sweep_copy = {"auto": -1, "off": 0, "all": 1}[params.sweep_copy]
+        p.matrix_cores = 1 if params.matrix_cores else 0
         cf = None
         if params.cf_override is not None:
             cf = np.ascontiguousarray(params.cf_override, dtype=np.int8)

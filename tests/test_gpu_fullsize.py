@@ -1,7 +1,9 @@
 """GPU parity at full workload sizes, in the launch configuration bench.py times.
 
-* 256x256 Q2 curved flow (589,824 DOFs, the bench workload): the whole
-  hierarchy, the solve and the transposed solve against the oracle.
+* 256x256 Q2 curved flow (589,824 DOFs): the whole hierarchy, the solve and
+  the transposed solve against the oracle.
+* The 512x512 jittered Q4 recipe at N = 128 (409,600 DOFs, every default path
+  of the full-size workload active): the same complete comparison.
 * 512x512 jittered Q4 (6,553,600 DOFs, 25x25 blocks): too large for the oracle
   to set up in a test, so sampled outputs the oracle computes one by one (block
   inverses), brute-force definitions on sampled rows (block sizes, strength,
@@ -27,6 +29,27 @@ def test_fullsize_bench_workload_parity():
     _say("test: full-size dg_q2_256_curved parity (hierarchy, solve, transposed solve)")
     S, k = make_config("dg_q2_256_curved")
     G, O = build_pair(S.nb, S.bs, S.rowptr, S.colidx, S.vals, degree=k)
+    compare_hierarchies(G, O)
+    _say("  hierarchy identical; solving")
+    check_solve(G, O, S.rhs)
+    g = np.random.Generator(np.random.PCG64(300)).uniform(-1, 1, S.n)
+    check_solve(G, O, g, trans=True)
+
+
+def test_q4_jittered_128_full_hierarchy_parity():
+    """The Q4 recipe (25x25 blocks, jittered mesh) at N = 128: 409,600 DOFs,
+    large enough that every default path of the full-size workload fires on
+    the finest levels (face rectangles, F-ordered sweep copies with
+    column-major row-compressed blocks, row-compressed Z, the 25x25
+    matrix-core products), small enough for the oracle.  Every level, the
+    solve and the transposed solve against the oracle."""
+    import paper_1704_05001_amd as P
+    _say("test: dg_q4_512_jitter recipe at N=128, full hierarchy parity")
+    S, k = make_config("dg_q4_512_jitter", N=128)
+    G, O = build_pair(S.nb, S.bs, S.rowptr, S.colidx, S.vals, degree=k)
+    lv0 = G.level(0, fields=())
+    assert lv0["face_rmax"] == 5 and lv0["sweep_nnzb"] >= 0
+    assert G.level(1, fields=())["sweep_nnzb"] >= 0
     compare_hierarchies(G, O)
     _say("  hierarchy identical; solving")
     check_solve(G, O, S.rhs)
