@@ -65,6 +65,111 @@ __global__ __launch_bounds__(256) void k_block_scan(const double *__restrict__ v
 
 // -------------------------------------------------- diagonal block inverse
 
+// The same LU recipe with one wave per block and four blocks per workgroup,
+// for block sizes known at compile time: the factorisation in the wave's LDS
+// slot (lanes over the trailing entries, pivot search by shuffles), then lane j
+// < BS keeps column j of the inverse in registers through the forward and
+// back substitution, reading the factors from LDS (every lane the same word)
+// and writing row i of the inverse with consecutive lanes on consecutive
+// words.  The operations and their order are those of k_block_inverse.
+template <int BS>
+__global__ __launch_bounds__(256) void k_block_inverse_wave(const int *__restrict__ rowptr,
+                                                           const int *__restrict__ colidx,
+                                                           const double *__restrict__ vals, int nb,
+                                                           const int8_t *__restrict__ skip, double *__restrict__ dinv,
+                                                           int *__restrict__ singular_min) {
+    constexpr int BB = BS * BS;
+    __shared__ double slot[4][BB];
+    __shared__ int pslot[4][BS];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    double *a = slot[w];
+    int *perm = pslot[w];
+    const int I = blockIdx.x * 4 + w;
+    if (I >= nb || (skip && skip[I])) return;   // whole waves; no workgroup barrier below
+    int dpos = -1;
+    for (int t = rowptr[I] + lane; t < rowptr[I + 1]; t += kWave)
+        if (colidx[t] == I) dpos = t;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dpos = max(dpos, __shfl_xor(dpos, o, kWave));
+    if (dpos < 0) {   // validated before; never taken for valid input
+        if (lane == 0) atomicMin(singular_min, I);
+        return;
+    }
+    const double *src = vals + static_cast<int64_t>(dpos) * BB;
+    for (int e = lane; e < BB; e += kWave) a[e] = src[e];
+    if (lane < BS) perm[lane] = lane;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int k = 0; k < BS; ++k) {
+        double v = -1.0;
+        int idx = BS;
+        if (k + lane < BS) {
+            v = fabs(a[(k + lane) * BS + k]);
+            idx = k + lane;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(v, o, kWave);
+            const int oi = __shfl_xor(idx, o, kWave);
+            if (ov > v || (ov == v && oi < idx)) {
+                v = ov;
+                idx = oi;
+            }
+        }
+        if (!(v > 0.0)) {
+            if (lane == 0) atomicMin(singular_min, I);
+            return;
+        }
+        if (idx != k) {
+            if (lane < BS) {
+                const double tmp = a[k * BS + lane];
+                a[k * BS + lane] = a[idx * BS + lane];
+                a[idx * BS + lane] = tmp;
+            }
+            if (lane == 0) {
+                const int tp = perm[k];
+                perm[k] = perm[idx];
+                perm[idx] = tp;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const double piv = a[k * BS + k];
+        if (k + 1 + lane < BS) a[(k + 1 + lane) * BS + k] = a[(k + 1 + lane) * BS + k] / piv;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int m = BS - k - 1;
+        for (int e = lane; e < m * m; e += kWave) {
+            const int i = k + 1 + e / m;
+            const int j = k + 1 + e % m;
+            a[i * BS + j] = __builtin_fma(-a[i * BS + k], a[k * BS + j], a[i * BS + j]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (lane >= BS) return;
+    const int j = lane;
+    double y[BS];
+#pragma unroll
+    for (int i = 0; i < BS; ++i) {
+        double sacc = (perm[i] == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int mm = 0; mm < i; ++mm) sacc = __builtin_fma(-a[i * BS + mm], y[mm], sacc);
+        y[i] = sacc;
+    }
+#pragma unroll
+    for (int i = BS - 1; i >= 0; --i) {
+        double sacc = y[i];
+#pragma unroll
+        for (int mm = i + 1; mm < BS; ++mm) sacc = __builtin_fma(-a[i * BS + mm], y[mm], sacc);
+        y[i] = sacc / a[i * BS + i];
+    }
+    double *dst = dinv + static_cast<int64_t>(I) * BB;
+#pragma unroll
+    for (int i = 0; i < BS; ++i) dst[i * BS + j] = y[i];
+}
+
 // One wave per block row.  LU with partial pivoting (first row of largest
 // |a_ik|, whole-row exchange), multipliers by division, trailing update
 // a_ij = fma(-a_ik, a_kj, a_ij); then column j of the inverse by forward
@@ -687,6 +792,12 @@ void launch_block_inverse(const int *rowptr, const int *colidx, const double *va
         k_block_inverse_thread<9><<<grid, 64, 0, s>>>(rowptr, colidx, vals, nb, skip, dinv, singular_min);
     } else if (bs == 4) {
         k_block_inverse_thread<4><<<grid, 64, 0, s>>>(rowptr, colidx, vals, nb, skip, dinv, singular_min);
+    } else if (bs == 16 || bs == 25) {
+        const unsigned wgrid = static_cast<unsigned>((nb + 3) / 4);   // four waves (blocks) per workgroup
+        if (bs == 16)
+            k_block_inverse_wave<16><<<wgrid, 256, 0, s>>>(rowptr, colidx, vals, nb, skip, dinv, singular_min);
+        else
+            k_block_inverse_wave<25><<<wgrid, 256, 0, s>>>(rowptr, colidx, vals, nb, skip, dinv, singular_min);
     } else {
         const size_t lds = sizeof(double) * 2 * bs * bs + sizeof(int) * bs;
         k_block_inverse<<<cap_grid(nb), 64, lds, s>>>(rowptr, colidx, vals, nb, bs, skip, dinv, singular_min);

@@ -710,6 +710,155 @@ __global__ __launch_bounds__(256) void k_galerkin_mfma(int64_t nnz, const int *_
     }
 }
 
+// The same Galerkin sums with each block pair's operands staged through LDS.
+// Per pair the wave reads both blocks with consecutive lanes on consecutive
+// words (ceil(bs^2/64) loads per lane and block, instead of ceil(bs/4) strided
+// fragment loads per tile row and column), writes them to its LDS slot, and
+// takes the matrix-core fragments from there; the next pair's blocks are
+// loaded into registers while the current pair's steps run, and the pair
+// index after that one is loaded a step earlier still, so no load waits on
+// an address that has just been read.  Same steps, same order, same sums as
+// k_galerkin_mfma, bit for bit (the fragments are the same numbers).
+template <int BS>
+__global__ __launch_bounds__(256) void k_galerkin_lds(int64_t nnz, const int *__restrict__ kptr,
+                                                     const int *__restrict__ klist, const int *__restrict__ pairptr,
+                                                     const int2 *__restrict__ pairs, const double *__restrict__ X,
+                                                     const double *__restrict__ Y, double *__restrict__ K,
+                                                     double *__restrict__ knorm, uint32_t *__restrict__ kmask) {
+    constexpr int BB = BS * BS;
+    constexpr int NL = (BB + 63) / 64;   // loads per lane and block
+    constexpr int NT = MfmaShape<BS>::NT, KQ = MfmaShape<BS>::KQ;
+    __shared__ double slot[4][2 * BB];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int row = lane & 15, kk = lane >> 4;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + w;
+    if (t >= nnz) return;   // whole waves; no workgroup barrier below
+    double *xs = slot[w], *ys = slot[w] + BB;
+    MfmaAcc<BS> kacc, acc;
+    kacc.zero();
+    const int c0 = kptr[t], c1 = kptr[t + 1];
+    for (int base = c0; base < c1; base += 64) {
+        const int cnt = min(64, c1 - base);
+        int pb = 0, pe = 0;
+        if (lane < cnt) {
+            const int u = klist[base + lane];
+            pb = pairptr[u];
+            pe = pairptr[u + 1];
+        }
+        // walk positions (j, k): pair k of contributing block j (the same in every lane)
+        auto first = [&](int &j, int &k, int &ke) {
+            while (j < cnt) {
+                k = __shfl(pb, j, 64);
+                ke = __shfl(pe, j, 64);
+                if (k < ke) return;
+                ++j;
+            }
+        };
+        auto next = [&](int &j, int &k, int &ke) {
+            if (++k < ke) return;
+            ++j;
+            first(j, k, ke);
+        };
+        int j = 0, k = 0, ke = 0;
+        first(j, k, ke);
+        if (j >= cnt) continue;
+        acc.zero();
+        int j1 = j, k1 = k, ke1 = ke;
+        next(j1, k1, ke1);
+        int2 pr = pairs[k];
+        int2 pr1 = j1 < cnt ? pairs[k1] : int2{0, 0};
+        double xv[NL], yv[NL];
+        auto load = [&](const int2 q) {
+            const double *y = Y + static_cast<int64_t>(q.y) * BB;
+            const double *x = X + static_cast<int64_t>(q.x < 0 ? 0 : q.x) * BB;
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                const int e = lane + 64 * i;
+                yv[i] = e < BB ? y[e] : 0.0;
+                xv[i] = (e < BB && q.x >= 0) ? x[e] : 0.0;
+            }
+        };
+        load(pr);
+        while (j < cnt) {
+            // this pair's blocks to LDS (the previous pair's fragment reads were issued before)
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                const int e = lane + 64 * i;
+                if (e < BB) {
+                    xs[e] = xv[i];
+                    ys[e] = yv[i];
+                }
+            }
+            // the next pair's blocks and the index after it load while this pair's steps run
+            int j2 = j1, k2 = k1, ke2 = ke1;
+            int2 pr2 = {0, 0};
+            if (j1 < cnt) {
+                load(pr1);
+                next(j2, k2, ke2);
+                if (j2 < cnt) pr2 = pairs[k2];
+            }
+            if (pr.x < 0) {   // identity pair: Y's entries added plainly
+#pragma unroll
+                for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int i = 16 * ti + kk + 4 * r, jj = 16 * tj + row;
+                            if (i < BS && jj < BS) acc.t[ti][tj][r] = acc.t[ti][tj][r] + ys[i * BS + jj];
+                        }
+            } else {
+#pragma unroll
+                for (int q = 0; q < KQ; ++q) {
+                    const int c = 4 * q + kk;
+                    double a[NT], b[NT];
+#pragma unroll
+                    for (int u = 0; u < NT; ++u) {
+                        const int i = 16 * u + row;
+                        a[u] = (i < BS && c < BS) ? xs[i * BS + c] : 0.0;
+                        b[u] = (i < BS && c < BS) ? ys[c * BS + i] : 0.0;
+                    }
+#pragma unroll
+                    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                        for (int tj = 0; tj < NT; ++tj)
+                            acc.t[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj], acc.t[ti][tj], 0, 0, 0);
+                }
+            }
+            if (j1 != j) {   // block j ends with this pair
+                kacc.add(acc);
+                acc.zero();
+            }
+            j = j1;
+            k = k1;
+            ke = ke1;
+            pr = pr1;
+            j1 = j2;
+            k1 = k2;
+            ke1 = ke2;
+            pr1 = pr2;
+        }
+    }
+    double *out = K + t * BB;
+    double m = 0.0;
+    uint32_t bits = 0u;
+    mfma_for_entries<BS>(kacc, row, kk, [&](int i, int jj, double v) {
+        out[i * BS + jj] = v;
+        m = fmax(m, fabs(v));
+        if (v != 0.0) bits |= 1u << i;
+    });
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        m = fmax(m, __shfl_xor(m, o, 64));
+        bits |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(bits), o, 64));
+    }
+    if (lane == 0) {
+        knorm[t] = m;
+        kmask[t] = bits;
+    }
+}
+
 // out[t] = in[src[t]] for t < *count
 __global__ __launch_bounds__(256) void k_gather_mask(int64_t n, const uint32_t *__restrict__ in,
                                                     const int *__restrict__ src, const int *__restrict__ count,
@@ -1038,9 +1187,9 @@ void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int 
                                                           P.pairs.get(), Z.vals.get(), A.vals.get(), kval.get(),
                                                           knorm.get(), kbits.get());
             else
-                k_galerkin_mfma<25><<<mgrid, 256, 0, s>>>(nnz, kptr.get(), klist.get(), P.pairptr.get(),
-                                                          P.pairs.get(), Z.vals.get(), A.vals.get(), kval.get(),
-                                                          knorm.get(), kbits.get());
+                k_galerkin_lds<25><<<mgrid, 256, 0, s>>>(nnz, kptr.get(), klist.get(), P.pairptr.get(),
+                                                         P.pairs.get(), Z.vals.get(), A.vals.get(), kval.get(),
+                                                         knorm.get(), kbits.get());
         } else {
             const int64_t total = static_cast<int64_t>(nnz) * bb;
             k_rap_values<<<cap_grid((total + 255) / 256), 256, 0, s>>>(nnz, bb, kptr.get(), klist.get(),
