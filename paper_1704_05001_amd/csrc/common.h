@@ -293,6 +293,47 @@ struct RowBlockView {
     const MT *vals = nullptr;
 };
 
+// ------------------------------------------------------- transposed rows
+// An operator M read as M^T for the transposed cycle, each block stored by M's
+// nonzero rows: output row I (a block column of M) lists the blocks M_JI of the
+// selected rows J of M in ascending J; entry t holds J, the mask of M_JI's
+// nonzero rows and, at vals[off[t]] ..., those rows whole and in ascending
+// order (popcount(mask) * bs entries, row-major).  Lane a of output row I then
+// forms (M^T x)_I[a] = sum_t sum_k M_JI[c_k][a] x_J[c_k] over the nonzero rows
+// c_k: consecutive lanes read consecutive words of a stored row, and the zero
+// rows of M's blocks (most of a coarse block, all but the face rows of a DG
+// face block) are neither stored nor read.  A whole transposed block would
+// store every column of M's block as a row.
+struct TransRows {
+    bool on = false;
+    int nrows = 0;                 // output rows (M's block columns)
+    int64_t nent = 0;              // entries (blocks)
+    DBuf<int> rowptr, colidx, off;
+    DBuf<uint32_t> mask;
+    DBuf<double> vals;
+    DBuf<float> vals32;
+};
+// M^T of M's blocks in rows J with keep_cf == null or cf[J] == keep_cf; mmask
+// (nullable): the nonzero-row masks of M's blocks, else found from the values.
+// Returns false (building nothing) when the kept rows exceed int32 offsets.
+bool build_trans_rows(const DevBSR &M, const int8_t *cf, int keep_cf, const uint32_t *mmask, TransRows &T,
+                      hipStream_t s);
+void trans_rows_to_float(TransRows &T, int bs, hipStream_t s);
+template <typename MT>
+struct TransRowsView {
+    int nrows = 0, bs = 0;
+    int64_t nent = 0;
+    const int *rowptr = nullptr, *colidx = nullptr, *off = nullptr;
+    const uint32_t *mask = nullptr;
+    const MT *vals = nullptr;
+    int groups = 0;   // lane groups per output row (0: from the row length)
+    TransRowsView with_groups(int g) const {
+        TransRowsView v = *this;
+        v.groups = g;
+        return v;
+    }
+};
+
 // ----------------------------------------------------------- sweep copy
 // What a Jacobi F sweep reads, stored in the order it reads it: the F rows of
 // a level operator (or of its transpose) in F-list order, each without its
@@ -401,6 +442,19 @@ void launch_relax_interp(const MatView<MT> &A, const double *dinv, const VT *r, 
                          const int8_t *cf, VT *e0, VT *e1, hipStream_t s, Gate gate = Gate());
 template <typename MT, typename VT>
 void launch_interp_T(const MatView<MT> &ZT, const int *cidx, const VT *yc, VT *y, hipStream_t s, Gate g = Gate());
+// The transposed cycle's products read from TransRows copies (coarse levels):
+// s = g - A^T y on every row, with y zero outside the copy's source rows
+template <typename MT, typename VT>
+void launch_residual_tr(const TransRowsView<MT> &T, const VT *g, const VT *y, VT *sout, hipStream_t s,
+                        Gate gate = Gate());
+// transposed Jacobi F sweep over `list`: y_out_I = D_I^{-T}(g_I - sum_{J != I} (A^T)_IJ y_in_J)
+template <typename MT, typename VT>
+void launch_sweep_tr(const TransRowsView<MT> &T, const double *dinv, const VT *g, const VT *yin, VT *yout,
+                     const int *list, int nlist, hipStream_t s, Gate gate = Gate());
+// y_I += [I is C] yc_{cidx I} + (Z^T yc)_I
+template <typename MT, typename VT>
+void launch_interp_tr(const TransRowsView<MT> &T, const int *cidx, const VT *yc, VT *y, hipStream_t s,
+                      Gate gate = Gate());
 template <typename VT>
 void launch_init_T(const double *dinv, const VT *g, const int8_t *cf, int fc, VT *y0, VT *y1, int nb, int bs,
                    hipStream_t s, Gate gate = Gate());

@@ -202,6 +202,32 @@ __device__ inline double row_part_rows(const int *__restrict__ colidx, const Row
     return acc0 + acc1;
 }
 
+// The same row product read transposed from a TransRows copy: output row I's
+// entries t = lo+g, lo+g+G, ... < hi each hold source block M_JI by its
+// nonzero rows c_k; lane a adds M_JI[c_k][a] x_J[c_k] (with SKIP, the entry
+// with J == skip is left out).
+template <int BS, typename MT, typename VT, bool SKIP = false>
+__device__ inline double row_part_tr(const TransRowsView<MT> &T, int lo, int hi, int g, int G, int a, int bs_rt,
+                                     const VT *__restrict__ x, int skip = -1) {
+    const int bs = Bs<BS>::get(bs_rt);
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int t = lo + g; t < hi; t += G) {
+        const int J = T.colidx[t];
+        if constexpr (SKIP) {
+            if (J == skip) continue;
+        }
+        uint32_t m = T.mask[t];
+        const MT *v = T.vals + T.off[t] + a;
+        const VT *xj = x + static_cast<int64_t>(J) * bs;
+        for (int k = 0; m != 0u; m &= m - 1u, ++k) {
+            const int c = __ffs(static_cast<int>(m)) - 1;
+            if (k & 1) acc1 += static_cast<double>(v[k * bs]) * static_cast<double>(xj[c]);
+            else acc0 += static_cast<double>(v[k * bs]) * static_cast<double>(xj[c]);
+        }
+    }
+    return acc0 + acc1;
+}
+
 // Row I's product with x (SKIP: without its diagonal block).
 template <int BS, bool FACE, typename MT, typename VT, bool SKIP = false>
 __device__ inline double row_product(const int *__restrict__ colidx, const MT *__restrict__ vals,
@@ -571,6 +597,81 @@ __global__ __launch_bounds__(kThreads) void k_interp_T(const int *__restrict__ z
     }
 }
 
+// The transposed cycle's products from TransRows copies (coarse levels):
+// s = g - A^T y for every row, where y vanishes outside the source rows the
+// copy keeps (the F rows: the transposed F sweeps change only those)
+template <int BS, typename MT, typename VT>
+__global__ __launch_bounds__(kThreads) void k_residual_tr(TransRowsView<MT> T, int bs_rt, int G,
+                                                         const VT *__restrict__ g, const VT *__restrict__ y,
+                                                         VT *__restrict__ sout, Gate gate) {
+    __shared__ double part[kThreads];
+    const int bs = Bs<BS>::get(bs_rt);
+    const Lane L = lane_of(G, bs);
+    const int I = blockIdx.x * (kThreads / (G * bs)) + L.lr;
+    const bool act = L.valid && I < T.nrows && live(gate, I);
+    const int64_t o = static_cast<int64_t>(I) * bs + L.a;
+    const double gv = (act && L.g == 0) ? static_cast<double>(g[o]) : 0.0;
+    double acc = act ? row_part_tr<BS, MT, VT>(T, T.rowptr[I], T.rowptr[I + 1], L.g, G, L.a, bs, y) : 0.0;
+    acc = reduce_groups(acc, L, G, bs, part);
+    if (act && L.g == 0) sout[o] = static_cast<VT>(gv - acc);
+}
+
+// transposed F sweep over the listed rows: y_out_I = D_I^{-T}(g_I - sum_{J != I} (A^T)_IJ y_in_J)
+template <int BS, typename MT, typename VT>
+__global__ __launch_bounds__(kThreads) void k_sweep_tr(TransRowsView<MT> T, const double *__restrict__ dinv,
+                                                      const int *__restrict__ list, int nlist, int bs_rt, int G,
+                                                      const VT *__restrict__ g, const VT *__restrict__ yin,
+                                                      VT *__restrict__ yout, Gate gate) {
+    __shared__ double part[kThreads];
+    __shared__ double tb[kThreads];
+    const int bs = Bs<BS>::get(bs_rt);
+    const Lane L = lane_of(G, bs);
+    const int f = blockIdx.x * (kThreads / (G * bs)) + L.lr;
+    int I = -1;
+    if (L.valid && f < nlist) I = list[f];
+    if (I >= 0 && !live(gate, I)) I = -1;
+    DinvRow<BS, true> dr;   // D_I^{-T}: the coefficient of input c for output a is D^{-1}[c][a]
+    const double *D = dinv + static_cast<int64_t>(I) * bs * bs;
+    const int64_t o = static_cast<int64_t>(I) * bs + L.a;
+    double gv = 0.0;
+    if (I >= 0 && L.g == 0) {
+        gv = static_cast<double>(g[o]);
+        dr.load(D, L.a);
+    }
+    double acc = I >= 0 ? row_part_tr<BS, MT, VT, true>(T, T.rowptr[I], T.rowptr[I + 1], L.g, G, L.a, bs, yin, I)
+                        : 0.0;
+    acc = reduce_groups(acc, L, G, bs, part);
+    if (I >= 0 && L.g == 0) tb[L.lr * bs + L.a] = gv - acc;
+    __syncthreads();
+    if (I >= 0 && L.g == 0) yout[o] = static_cast<VT>(dr.apply(D, tb + L.lr * bs, L.a, bs));
+}
+
+// y_I += [I is C] yc_{cidx I} + (Z^T yc)_I from Z's TransRows copy
+template <int BS, typename MT, typename VT>
+__global__ __launch_bounds__(kThreads) void k_interp_tr(TransRowsView<MT> T, int bs_rt, int G,
+                                                       const int *__restrict__ cidx, const VT *__restrict__ yc,
+                                                       VT *__restrict__ y, Gate gate) {
+    __shared__ double part[kThreads];
+    const int bs = Bs<BS>::get(bs_rt);
+    const Lane L = lane_of(G, bs);
+    const int I = blockIdx.x * (kThreads / (G * bs)) + L.lr;
+    const bool act = L.valid && I < T.nrows && live(gate, I);
+    const int64_t o = static_cast<int64_t>(I) * bs + L.a;
+    double yv = 0.0, cv = 0.0;
+    int ci = -1;
+    if (act && L.g == 0) {
+        yv = static_cast<double>(y[o]);
+        ci = cidx[I];
+        if (ci >= 0) cv = static_cast<double>(yc[static_cast<int64_t>(ci) * bs + L.a]);
+    }
+    double acc = act ? row_part_tr<BS, MT, VT>(T, T.rowptr[I], T.rowptr[I + 1], L.g, G, L.a, bs, yc) : 0.0;
+    acc = reduce_groups(acc, L, G, bs, part);
+    if (act && L.g == 0) {
+        if (ci >= 0) acc += cv;
+        y[o] = static_cast<VT>(yv + acc);
+    }
+}
+
 template <typename VT>
 __global__ __launch_bounds__(kThreads) void k_interp(const int *__restrict__ pmap, const VT *__restrict__ ec,
                                                     VT *__restrict__ e0, VT *__restrict__ e1, int nb, int bs,
@@ -782,22 +883,24 @@ __global__ __launch_bounds__(256) void k_to_float(const double *__restrict__ in,
 // chain of dependent loads, not bandwidth, sets the time (at most 256 lanes
 // per row either way).
 template <typename MT>
-int groups_for(const MatView<MT> &A) {
+int groups_for_len(const MatView<MT> &A, double avg) {
     int G;
     if (A.groups > 0) {
         G = A.groups;
     } else if (few_lanes(A.nb, A.bs)) {
         // enough groups for rows several times the average length (the longest
         // row sets the time), within what a row can take
-        const double avg = A.nb > 0 ? static_cast<double>(A.nnzb) / A.nb : 1.0;
         G = 1;
         while (G < max_groups(A.bs) && G < 4.0 * avg) G *= 2;
     } else {
-        const double avg = A.nb > 0 ? static_cast<double>(A.nnzb) / A.nb : 1.0;
         G = avg <= 3.5 ? 1 : (avg <= 7.0 ? 2 : (avg <= 14.0 ? 4 : 8));
     }
     while (G > 1 && G * A.bs > kThreads) G >>= 1;
     return G;
+}
+template <typename MT>
+int groups_for(const MatView<MT> &A) {
+    return groups_for_len(A, A.nb > 0 ? static_cast<double>(A.nnzb) / A.nb : 1.0);
 }
 
 unsigned grid_rows(int64_t rows, int G, int bs) { return grid_for(rows, kThreads / (G * bs)); }
@@ -972,6 +1075,54 @@ void launch_interp_T(const MatView<MT> &ZT, const int *cidx, const VT *yc, VT *y
     NAIR_HIP(hipGetLastError());
 }
 
+// Lane groups of a TransRows product: the tuned count, else as groups_for.
+template <typename MT>
+int groups_for_tr(const TransRowsView<MT> &T) {
+    MatView<MT> v;
+    v.nb = T.nrows;
+    v.bs = T.bs;
+    v.groups = T.groups;
+    return groups_for_len(v, T.nrows > 0 ? static_cast<double>(T.nent) / T.nrows : 1.0);   // entries per row
+}
+
+template <typename MT>
+void need_tr(const TransRowsView<MT> &T, const char *what) {
+    if (T.nrows > 0 && (!T.rowptr || (T.nent > 0 && (!T.colidx || !T.mask || !T.off || !T.vals))) || T.bs > 32)
+        fail(NAIR_EDEVICE, std::string(what) + ": incomplete transposed row copy");
+}
+
+template <typename MT, typename VT>
+void launch_residual_tr(const TransRowsView<MT> &T, const VT *g, const VT *y, VT *sout, hipStream_t s, Gate gate) {
+    need_tr(T, "launch_residual_tr");
+    if (T.nrows <= 0) return;
+    const int G = groups_for_tr(T);
+    const unsigned grid = grid_rows(T.nrows, G, T.bs);
+    NAIR_BS_DISPATCH(T.bs, k_residual_tr, <<<grid, kThreads, 0, s>>>(T, T.bs, G, g, y, sout, gate));
+    NAIR_HIP(hipGetLastError());
+}
+
+template <typename MT, typename VT>
+void launch_sweep_tr(const TransRowsView<MT> &T, const double *dinv, const VT *g, const VT *yin, VT *yout,
+                     const int *list, int nlist, hipStream_t s, Gate gate) {
+    need_tr(T, "launch_sweep_tr");
+    if (nlist <= 0) return;
+    const int G = groups_for_tr(T);
+    const unsigned grid = grid_rows(nlist, G, T.bs);
+    NAIR_BS_DISPATCH(T.bs, k_sweep_tr, <<<grid, kThreads, 0, s>>>(T, dinv, list, nlist, T.bs, G, g, yin, yout,
+                                                                  gate));
+    NAIR_HIP(hipGetLastError());
+}
+
+template <typename MT, typename VT>
+void launch_interp_tr(const TransRowsView<MT> &T, const int *cidx, const VT *yc, VT *y, hipStream_t s, Gate gate) {
+    need_tr(T, "launch_interp_tr");
+    if (T.nrows <= 0) return;
+    const int G = groups_for_tr(T);
+    const unsigned grid = grid_rows(T.nrows, G, T.bs);
+    NAIR_BS_DISPATCH(T.bs, k_interp_tr, <<<grid, kThreads, 0, s>>>(T, T.bs, G, cidx, yc, y, gate));
+    NAIR_HIP(hipGetLastError());
+}
+
 template <typename VT>
 void launch_init_T(const double *dinv, const VT *g, const int8_t *cf, int fc, VT *y0, VT *y1, int nb, int bs,
                    hipStream_t s, Gate gate) {
@@ -1064,6 +1215,12 @@ void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s, con
                                            hipStream_t, Gate);                                                       \
     template void launch_restrict_T<VT>(const int *, const int *, const VT *, VT *, int, int, hipStream_t, Gate);    \
     template void launch_interp_T<MT, VT>(const MatView<MT> &, const int *, const VT *, VT *, hipStream_t, Gate);    \
+    template void launch_residual_tr<MT, VT>(const TransRowsView<MT> &, const VT *, const VT *, VT *, hipStream_t,  \
+                                             Gate);                                                                  \
+    template void launch_sweep_tr<MT, VT>(const TransRowsView<MT> &, const double *, const VT *, const VT *, VT *,  \
+                                          const int *, int, hipStream_t, Gate);                                      \
+    template void launch_interp_tr<MT, VT>(const TransRowsView<MT> &, const int *, const VT *, VT *, hipStream_t,    \
+                                           Gate);                                                                    \
     template void launch_init_T<VT>(const double *, const VT *, const int8_t *, int, VT *, VT *, int, int,           \
                                     hipStream_t, Gate);                                                              \
     template void launch_axpy<VT>(double *, const VT *, int64_t, hipStream_t);                                       \

@@ -48,9 +48,12 @@ struct Level {
     DevBSR Z;                       // R = [Z I]: nc rows, fine F columns
     int dense_n = 0;                // order of the dense inverse when one system covers the level
     DBuf<double> dense_inv, dense_invT;
-    // transposed cycle (built on first use)
+    // transposed cycle (built on first use): A^T where its face copy, the
+    // F-cycle's coarse residuals or small blocks need it, else A's F rows (all
+    // rows with FC relaxation) and Z read transposed by their nonzero rows
     bool have_T = false;
     DevBSR AT, ZT;
+    TransRows atF, zt;
     DBuf<int> ptptr, ptidx;
     // cycle vectors
     DBuf<double> r, e0, e1, tmp;
@@ -96,6 +99,15 @@ inline MatView<float> op_view32(const Level &L, bool trans) {
                                    S.dinv.get(), S.cmax, S.rc,
                                    RowBlockView<float>{S.rows.mask.get(), S.rows.off.get(), S.rows.vals32.get()}};
     return v;
+}
+
+inline TransRowsView<double> tr_view(const TransRows &T, int bs) {
+    return TransRowsView<double>{T.nrows,       bs,           T.nent,        T.rowptr.get(), T.colidx.get(),
+                                 T.off.get(),   T.mask.get(), T.vals.get(), 0};
+}
+inline TransRowsView<float> tr_view32(const TransRows &T, int bs) {
+    return TransRowsView<float>{T.nrows,       bs,           T.nent,          T.rowptr.get(), T.colidx.get(),
+                                T.off.get(),   T.mask.get(), T.vals32.get(), 0};
 }
 
 // Z as the restriction reads it: by its blocks' nonzero rows where the level keeps them.

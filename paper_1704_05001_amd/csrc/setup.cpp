@@ -424,6 +424,7 @@ void build_sweeps(Hier &h, bool trans, hipStream_t s) {
         Level &L = *Lp;
         if (L.coarsest || L.nF <= 0) continue;
         if (h.prm.sweep_copy < 0 && few_lanes(L.A.nb, L.A.bs)) continue;
+        if (trans && (L.atF.on || !L.AT.rowptr.get())) continue;   // the transposed sweeps read A's rows
         SweepCopy &S = trans ? L.sweepT : L.sweep;
         // (A's row masks, where the Galerkin step gave them, are no use for A^T)
         if (!S.on)
@@ -457,16 +458,18 @@ void make_fp32_copies(Hier &h, hipStream_t s) {
                 launch_to_float(L.Z.vals.get(), L.z32.get(), L.Z.nnzb * bb, s);
             }
         }
-        if (L.have_T && !L.at32.get()) {
+        if (L.have_T && L.AT.rowptr.get() && !L.at32.get()) {
             L.at32.alloc(static_cast<size_t>(L.AT.nnzb * bb));
             launch_to_float(L.AT.vals.get(), L.at32.get(), L.AT.nnzb * bb, s);
-            if (!L.coarsest) {
-                L.zt32.alloc(static_cast<size_t>(L.ZT.nnzb * bb));
-                launch_to_float(L.ZT.vals.get(), L.zt32.get(), L.ZT.nnzb * bb, s);
-            }
+        }
+        if (L.have_T && !L.coarsest && L.ZT.rowptr.get() && !L.zt32.get()) {
+            L.zt32.alloc(static_cast<size_t>(L.ZT.nnzb * bb));
+            launch_to_float(L.ZT.vals.get(), L.zt32.get(), L.ZT.nnzb * bb, s);
         }
         face_to_float(L.A, L.face, s);
         if (L.have_T) face_to_float(L.AT, L.faceT, s);
+        trans_rows_to_float(L.atF, L.A.bs, s);
+        trans_rows_to_float(L.zt, L.A.bs, s);
         sweep_to_float(L.sweep, L.A.bs, s);
         sweep_to_float(L.sweepT, L.A.bs, s);
         row_blocks_to_float(L.zrows, L.Z.nnzb, L.A.bs, s);
@@ -478,13 +481,24 @@ void ensure_transposes(Hier &h, hipStream_t s) {
         bsr_transpose(h.A0, h.A0T, s);
         h.have_A0T = true;
     }
-    for (auto &Lp : h.lv) {
-        Level &L = *Lp;
+    for (size_t l = 0; l < h.lv.size(); ++l) {
+        Level &L = *h.lv[l];
         if (L.have_T) continue;
-        bsr_transpose(L.A, L.AT, s);
-        if (L.face.on) build_face(L.AT, L.faceT, s);   // A^T's blocks have the transposed faces
+        // below the face-compressed finest level, the transposed sweeps and
+        // residual read A's rows transposed by their nonzero rows (only the F
+        // rows: with F relaxation the transposed sweeps leave y zero on C rows)
+        const bool rows_tr = L.A.bs >= 4 && !L.coarsest;
+        if (rows_tr && !L.face.on)
+            build_trans_rows(L.A, h.prm.relax == 1 ? nullptr : L.cf.get(), 0, L.amask.get(), L.atF, s);
+        // A^T itself: the finest level (face copy, outer residual), the F-cycle's
+        // coarse residuals, small blocks and the coarsest level
+        if (!L.atF.on || l == 0 || h.prm.cycle == 1) {
+            bsr_transpose(L.A, L.AT, s);
+            if (L.face.on) build_face(L.AT, L.faceT, s);   // A^T's blocks have the transposed faces
+        }
         if (!L.coarsest) {
-            bsr_transpose(L.Z, L.ZT, s);
+            if (rows_tr) build_trans_rows(L.Z, nullptr, 0, L.zmask.get(), L.zt, s);
+            if (!L.zt.on) bsr_transpose(L.Z, L.ZT, s);
             pmap_transpose(L.pmap.get(), L.A.nb, L.nc, L.ptptr, L.ptidx, s);
         }
         L.have_T = true;

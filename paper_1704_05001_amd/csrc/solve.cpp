@@ -27,6 +27,11 @@ struct Store<double> {
     static MatView<double> Z(const Level &L) { return z_view(L).with_groups(L.tune[TU_RESTRICT]); }
     static MatView<double> AT(const Level &L) { return op_view(L, true).with_groups(L.tune[TU_RELAX_T]); }
     static MatView<double> ZT(const Level &L) { return view(L.ZT).with_groups(L.tune[TU_INTERP_T]); }
+    static TransRowsView<double> ATs(const Level &L) { return tr_view(L.atF, L.A.bs).with_groups(L.tune[TU_RELAX_T]); }
+    static TransRowsView<double> ATr(const Level &L) {
+        return tr_view(L.atF, L.A.bs).with_groups(L.tune[TU_RESIDUAL_T]);
+    }
+    static TransRowsView<double> ZTr(const Level &L) { return tr_view(L.zt, L.A.bs).with_groups(L.tune[TU_INTERP_T]); }
     static double *r(Level &L) { return L.r.get(); }
     static double *e0(Level &L) { return L.e0.get(); }
     static double *e1(Level &L) { return L.e1.get(); }
@@ -40,6 +45,11 @@ struct Store<float> {
     static MatView<float> Z(const Level &L) { return z_view32(L).with_groups(L.tune[TU_RESTRICT]); }
     static MatView<float> AT(const Level &L) { return op_view32(L, true).with_groups(L.tune[TU_RELAX_T]); }
     static MatView<float> ZT(const Level &L) { return view(L.ZT, L.zt32.get()).with_groups(L.tune[TU_INTERP_T]); }
+    static TransRowsView<float> ATs(const Level &L) { return tr_view32(L.atF, L.A.bs).with_groups(L.tune[TU_RELAX_T]); }
+    static TransRowsView<float> ATr(const Level &L) {
+        return tr_view32(L.atF, L.A.bs).with_groups(L.tune[TU_RESIDUAL_T]);
+    }
+    static TransRowsView<float> ZTr(const Level &L) { return tr_view32(L.zt, L.A.bs).with_groups(L.tune[TU_INTERP_T]); }
     static float *r(Level &L) { return L.r32.get(); }
     static float *e0(Level &L) { return L.e0_32.get(); }
     static float *e1(Level &L) { return L.e1_32.get(); }
@@ -132,7 +142,8 @@ const T *cycle_T(Hier &h, int l, bool fcyc, hipStream_t s) {
         return S::e0(L);
     }
     Level &C = *h.lv[l + 1];
-    const MatView<T> AT = S::AT(L);
+    const bool tr = L.atF.on;   // A^T's products from the transposed row copy of A's (F) rows
+    const MatView<T> AT = tr ? MatView<T>{} : S::AT(L);
     T *cur = S::e0(L), *oth = S::e1(L);
     int k0 = 0;
     if (h.prm.relax == 1) {   // C sweep first: y_C = D_C^{-T} g_C
@@ -145,16 +156,23 @@ const T *cycle_T(Hier &h, int l, bool fcyc, hipStream_t s) {
     {
         TimerScope ts(TK_RELAX, l, s, h.prm.degree + 1 - k0);
         for (int k = k0; k <= h.prm.degree; ++k) {
-            launch_relax<T, T>(AT, L.dinv.get(), true, S::r(L), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s,
-                               gate(h, L));
+            if (tr)
+                launch_sweep_tr<T, T>(S::ATs(L), L.dinv.get(), S::r(L), cur, oth, L.flist.get(), L.nF, s, gate(h, L));
+            else
+                launch_relax<T, T>(AT, L.dinv.get(), true, S::r(L), cur, oth, L.flist.get(), L.nF, L.cf.get(), 0, s,
+                                   gate(h, L));
             std::swap(cur, oth);
         }
     }
-    launch_residual<T, T>(AT.with_groups(L.tune[TU_RESIDUAL_T]), S::r(L), cur, S::tmp(L), nullptr, s,
-                          gate(h, L));
+    if (tr)
+        launch_residual_tr<T, T>(S::ATr(L), S::r(L), cur, S::tmp(L), s, gate(h, L));
+    else
+        launch_residual<T, T>(AT.with_groups(L.tune[TU_RESIDUAL_T]), S::r(L), cur, S::tmp(L), nullptr, s,
+                              gate(h, L));
     launch_restrict_T<T>(L.ptptr.get(), L.ptidx.get(), S::tmp(L), S::r(C), L.nc, bs, s, gate(h, C));
     const T *yc = coarse_solve_T<T>(h, l + 1, fcyc, s);
-    launch_interp_T<T, T>(S::ZT(L), L.cidx.get(), yc, cur, s, gate(h, L));
+    if (L.zt.on) launch_interp_tr<T, T>(S::ZTr(L), L.cidx.get(), yc, cur, s, gate(h, L));
+    else launch_interp_T<T, T>(S::ZT(L), L.cidx.get(), yc, cur, s, gate(h, L));
     g_timer_level = l;
     direct_solves<T>(h, L, true, S::r(L), cur, s);   // systems that end on this level
     return cur;

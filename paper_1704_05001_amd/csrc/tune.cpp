@@ -66,6 +66,8 @@ struct Vecs<double> {
     static MatView<double> Z(const Level &L) { return z_view(L); }
     static MatView<double> AT(const Level &L) { return op_view(L, true); }
     static MatView<double> ZT(const Level &L) { return view(L.ZT); }
+    static TransRowsView<double> ATr(const Level &L) { return tr_view(L.atF, L.A.bs); }
+    static TransRowsView<double> ZTr(const Level &L) { return tr_view(L.zt, L.A.bs); }
     static double *r(Level &L) { return L.r.get(); }
     static double *e0(Level &L) { return L.e0.get(); }
     static double *e1(Level &L) { return L.e1.get(); }
@@ -77,6 +79,8 @@ struct Vecs<float> {
     static MatView<float> Z(const Level &L) { return z_view32(L); }
     static MatView<float> AT(const Level &L) { return op_view32(L, true); }
     static MatView<float> ZT(const Level &L) { return view(L.ZT, L.zt32.get()); }
+    static TransRowsView<float> ATr(const Level &L) { return tr_view32(L.atF, L.A.bs); }
+    static TransRowsView<float> ZTr(const Level &L) { return tr_view32(L.zt, L.A.bs); }
     static float *r(Level &L) { return L.r32.get(); }
     static float *e0(Level &L) { return L.e0_32.get(); }
     static float *e1(Level &L) { return L.e1_32.get(); }
@@ -103,30 +107,53 @@ void tune_levels(Hier &h, int reps, hipStream_t s) {
         // back to back with warm caches does not predict them inside a cycle
         if (few_lanes(L.A.nb, L.A.bs)) continue;
         const int bs = L.A.bs;
-        const MatView<T> A = V::A(L), AT = V::AT(L), Z = V::Z(L), ZT = V::ZT(L);
+        const MatView<T> A = V::A(L), Z = V::Z(L);
         L.tune[TU_RELAX] = pick(
             [&](int G) {
                 launch_relax<T, T>(A.with_groups(G), L.dinv.get(), false, V::r(L), V::e0(L), V::e1(L),
                                    L.flist.get(), L.nF, L.cf.get(), 0, s);
             },
             bs, reps, ev, s);
-        L.tune[TU_RELAX_T] = pick(
-            [&](int G) {
-                launch_relax<T, T>(AT.with_groups(G), L.dinv.get(), true, V::r(L), V::e0(L), V::e1(L),
-                                   L.flist.get(), L.nF, L.cf.get(), 0, s);
-            },
-            bs, reps, ev, s);
-        L.tune[TU_RESIDUAL_T] = pick(
-            [&](int G) {
-                launch_residual<T, T>(AT.with_groups(G), V::r(L), V::e0(L), V::tmp(L), nullptr, s);
-            },
-            bs, reps, ev, s);
+        // the transposed cycle's kernels: from the transposed row copies where the level has them
+        if (L.atF.on) {
+            const TransRowsView<T> ATr = V::ATr(L);
+            L.tune[TU_RELAX_T] = pick(
+                [&](int G) {
+                    launch_sweep_tr<T, T>(ATr.with_groups(G), L.dinv.get(), V::r(L), V::e0(L), V::e1(L),
+                                          L.flist.get(), L.nF, s);
+                },
+                bs, reps, ev, s);
+            L.tune[TU_RESIDUAL_T] = pick(
+                [&](int G) { launch_residual_tr<T, T>(ATr.with_groups(G), V::r(L), V::e0(L), V::tmp(L), s); }, bs,
+                reps, ev, s);
+        } else {
+            const MatView<T> AT = V::AT(L);
+            L.tune[TU_RELAX_T] = pick(
+                [&](int G) {
+                    launch_relax<T, T>(AT.with_groups(G), L.dinv.get(), true, V::r(L), V::e0(L), V::e1(L),
+                                       L.flist.get(), L.nF, L.cf.get(), 0, s);
+                },
+                bs, reps, ev, s);
+            L.tune[TU_RESIDUAL_T] = pick(
+                [&](int G) {
+                    launch_residual<T, T>(AT.with_groups(G), V::r(L), V::e0(L), V::tmp(L), nullptr, s);
+                },
+                bs, reps, ev, s);
+        }
         L.tune[TU_RESTRICT] = pick(
             [&](int G) { launch_restrict<T, T>(Z.with_groups(G), V::r(L), L.cpts.get(), V::r(C), s); }, bs, reps,
             ev, s);
-        L.tune[TU_INTERP_T] = pick(
-            [&](int G) { launch_interp_T<T, T>(ZT.with_groups(G), L.cidx.get(), V::e0(C), V::e1(L), s); }, bs,
-            reps, ev, s);
+        if (L.zt.on) {
+            const TransRowsView<T> ZTr = V::ZTr(L);
+            L.tune[TU_INTERP_T] = pick(
+                [&](int G) { launch_interp_tr<T, T>(ZTr.with_groups(G), L.cidx.get(), V::e0(C), V::e1(L), s); },
+                bs, reps, ev, s);
+        } else {
+            const MatView<T> ZT = V::ZT(L);
+            L.tune[TU_INTERP_T] = pick(
+                [&](int G) { launch_interp_T<T, T>(ZT.with_groups(G), L.cidx.get(), V::e0(C), V::e1(L), s); }, bs,
+                reps, ev, s);
+        }
     }
     // the outer residual is FP64 in both precisions (the scalar form's runs on the caller's blocks, untuned)
     Level &L0 = *h.lv[0];
