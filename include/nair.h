@@ -267,6 +267,28 @@ nair_status nair_vcycle_T(nair_hier h, const double *g, double *y, void *stream)
 nair_status nair_grad_vals(int32_t nb, int32_t bs, const int32_t *rowptr, const int32_t *colidx,
                            const double *ybar, const double *x, double *grad_vals, void *stream);
 
+#define NAIR_NOALLOC_SCRATCH_BYTES 4194304
+/*
+ * nair_solve for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * stationary iteration and the same results as nair_solve on a single-system
+ * handle with gmres = 0 (else NAIR_EINVAL), but every buffer the iteration
+ * needs beyond the handle (allocated by nair_setup), b and x --
+ * norm partial sums and their chunk tables, per-system state, the residual
+ * history -- lives in one static device array of NAIR_NOALLOC_SCRATCH_BYTES
+ * (4 MiB) per device, held until the process ends.  It calls no hipMalloc,
+ * hipFree or allocating routine.  A solve of n dofs with max_iter iterations
+ * needs about 2.5 ceil(n / 4096) + max_iter + 8 doubles of it (a solve of
+ * 850 million dofs at 200 iterations fits); larger ones return NAIR_EINVAL
+ * with the sizes in nair_last_error.  Every call on a device shares that
+ * device's array: calls that overlap on one device race (serialise them).
+ * The history of this solve is not kept: nair_history reports none after it.
+ * It synchronises the stream to read its convergence counters, as nair_solve
+ * does, and the kernel timer does not see its launches.
+ */
+nair_status nair_solve_noalloc(nair_hier h, const double *b, double *x, double rtol, int32_t max_iter,
+                               nair_result *res, void *stream);
+
 /* Relative residual history of the last solve: buf (host) gets min(cap, n). */
 nair_status nair_history(nair_hier h, double *buf, int32_t cap, int32_t *n);
 

@@ -115,6 +115,9 @@ static nair_status setup_common(int32_t nsys, const int32_t *sys_nb, int32_t nb,
         h->h.prm = *p;
         nair::g_matrix_cores = p->matrix_cores != 0;
         nair::build_hierarchy(h->h, nsys, sys_nb, nb, bs, rowptr, colidx, vals, s);
+        // the no-alloc solve's scratch array: its device address, looked up once per device here so that
+        // nair_solve_noalloc itself loads nothing
+        if (nsys == 1) nair::noalloc_prepare();
         if (p->tuning) nair::apply_tuning(h->h, p->tuning);
         h->h.prm.cf_override_host = nullptr;   // host pointers not kept past the call
         h->h.prm.tuning = nullptr;
@@ -226,6 +229,16 @@ nair_status nair_solve(nair_hier h, const double *b, double *x, double rtol, int
 nair_status nair_solve_T(nair_hier h, const double *g, double *y, double rtol, int32_t max_iter, nair_result *res,
                          void *stream) {
     return solve_common(h, true, g, y, rtol, max_iter, res, stream);
+}
+
+nair_status nair_solve_noalloc(nair_hier h, const double *b, double *x, double rtol, int32_t max_iter,
+                               nair_result *res, void *stream) {
+    if (!h) return bad(nullptr, "handle is NULL");
+    if (!b || !x) return bad(h, "NULL vector");
+    if (!(rtol >= 0.0) || max_iter < 0) return bad(h, "need rtol >= 0 and max_iter >= 0");
+    DeviceGuard dg(h->h.device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return guarded(h, [&]() { return nair::solve_noalloc(h->h, b, x, rtol, max_iter, res, s); });
 }
 
 static nair_status vcycle_common(nair_hier h, bool trans, const double *r, double *e, void *stream) {

@@ -111,6 +111,7 @@ extern thread_local int g_timer_level;   // level the host code is working on
 extern thread_local bool g_matrix_cores;
 inline bool use_matrix_cores(int bs) { return g_matrix_cores && (bs == 9 || bs == 16 || bs == 25); }
 extern thread_local bool g_capturing;    // launches are being captured into a graph (timer off)
+extern thread_local bool g_timer_off;    // the kernel timer skips these launches (no events are created)
 
 // ------------------------------------------------------------- utilities
 inline unsigned grid_for(int64_t n, int per_block) {

@@ -122,6 +122,17 @@ inline MatView<float> z_view32(const Level &L) {
     return v;
 }
 
+// Device buffers one run of the iteration works in (norm chunk tables and
+// partial sums, per-system state, the history): BatchSolve's, or the no-alloc
+// solve's carve of its static scratch array.
+struct SolveBufs {
+    int nchunk = 0, hist_cap = 0;
+    int64_t *clo = nullptr;
+    int *clen = nullptr, *cptr = nullptr;
+    double *part = nullptr, *bn = nullptr, *last = nullptr, *rtol = nullptr, *hist = nullptr;
+    int *active = nullptr, *status = nullptr, *iters = nullptr, *it = nullptr, *nact = nullptr, *nact_acc = nullptr;
+};
+
 // Per-system solve state of the batched iteration (device-side convergence).
 struct BatchSolve {
     bool ready = false;
@@ -181,6 +192,17 @@ nair_status run_solve(Hier &h, bool trans, const double *b, double *x, double rt
 nair_status run_solve_batch(Hier &h, bool trans, const double *b, double *x, double rtol, int max_iter,
                             bool use_graph, nair_result *res, hipStream_t s);
 void run_vcycle(Hier &h, bool trans, const double *r, double *e, hipStream_t s);
+// One system's stationary iteration A x = b in the buffers V (already carved
+// and with their norm-chunk tables filled for nchunk chunks of kSolveChunk
+// dofs): no device or host allocation; the history stays in V.hist.
+nair_status run_solve_bufs(Hier &h, const double *b, double *x, double rtol, int max_iter, nair_result *res,
+                           hipStream_t s, const SolveBufs &V);
+constexpr int kSolveChunk = 4096;   // dofs per norm chunk
+// nair_solve_noalloc: the same iteration in the library's static scratch array
+nair_status solve_noalloc(Hier &h, const double *b, double *x, double rtol, int max_iter, nair_result *res,
+                          hipStream_t s);
+// Look up the scratch array's address on the current device (once per device).
+void noalloc_prepare();
 // Operators the cycle (trans: the transposed cycle) needs, built once.
 void prepare_cycle(Hier &h, bool trans, hipStream_t s);
 // e = B r (trans: B^T r) on the stream, no synchronisation; r and e are the

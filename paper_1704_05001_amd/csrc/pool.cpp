@@ -106,6 +106,7 @@ void pool_trim() {
 thread_local int g_timer_level = 0;
 thread_local bool g_matrix_cores = true;
 thread_local bool g_capturing = false;
+thread_local bool g_timer_off = false;
 
 namespace {
 struct Timer {
@@ -124,7 +125,7 @@ Timer &timer() {
 }  // namespace
 
 TimerScope::TimerScope(int kernel, int level, hipStream_t stream, int launches) : on(false), s(stream) {
-    if (g_capturing) return;
+    if (g_capturing || g_timer_off) return;
     Timer &T = timer();
     if (T.kernel != kernel || (T.level >= 0 && T.level != level)) return;
     std::lock_guard<std::mutex> lk(T.mu);

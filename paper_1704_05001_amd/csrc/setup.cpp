@@ -415,6 +415,7 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
     if (p.faces == 1 && p.form == 0) build_face(h.lv[0]->A, h.lv[0]->face, s);
     build_sweeps(h, false, s);
     if (p.precision == 1) make_fp32_copies(h, s);
+    prepare_cycle(h, false, s);   // the F-cycle's saved vectors
     NAIR_HIP(hipStreamSynchronize(s));
 }
 

@@ -232,7 +232,7 @@ void ensure_fcycle(Hier &h) {
 
 namespace {
 
-constexpr int kChunk = 4096;        // dofs per norm chunk
+constexpr int kChunk = kSolveChunk;   // dofs per norm chunk
 constexpr int kFirstPoll = 4;       // iterations before the first host check
 constexpr int kMaxRun = 64;         // most iterations launched between checks
 constexpr double kAim = 0.8;        // fraction of the predicted remaining iterations launched before a check
@@ -290,8 +290,7 @@ void ensure_batch(Hier &h, int max_iter, hipStream_t s) {
 // One iteration of every system: x += B r on the active systems, r = b - A x,
 // per-system norms and convergence.  Launch-only (capturable).
 template <typename T>
-void batch_iteration(Hier &h, bool trans, const double *b, double *x, hipStream_t s) {
-    BatchSolve &B = h.batch;
+void batch_iteration(Hier &h, bool trans, const double *b, double *x, hipStream_t s, const SolveBufs &B) {
     Level &L0 = *h.lv[0];
     const int64_t n = static_cast<int64_t>(L0.A.nb) * h.bs;
     const bool fp32 = std::is_same<T, float>::value;
@@ -301,9 +300,9 @@ void batch_iteration(Hier &h, bool trans, const double *b, double *x, hipStream_
         const Gate g0{h.bsys0.get(), h.active};
         if (trans) {
             launch_block_diag_apply<T>(h.d0inv.get(), e, h.rres.get(), nullptr, h.A0.nb, h.bs0, true, s, g0);
-            launch_axpy_active<double>(x, h.rres.get(), n, h.bs0, h.bsys0.get(), B.active.get(), s);
+            launch_axpy_active<double>(x, h.rres.get(), n, h.bs0, h.bsys0.get(), B.active, s);
         } else {
-            launch_axpy_active<T>(x, e, n, h.bs0, h.bsys0.get(), B.active.get(), s);
+            launch_axpy_active<T>(x, e, n, h.bs0, h.bsys0.get(), B.active, s);
         }
         double *rout = trans ? L0.r.get() : h.rres.get();
         {
@@ -311,36 +310,57 @@ void batch_iteration(Hier &h, bool trans, const double *b, double *x, hipStream_
             launch_residual<double, double>(trans ? view(h.A0T) : view(h.A0), b, x, rout,
                                             (trans && fp32) ? L0.r32.get() : nullptr, s, g0);
         }
-        launch_seg_sumsq(rout, B.clo.get(), B.clen.get(), B.nchunk, B.part.get(), s);
+        launch_seg_sumsq(rout, B.clo, B.clen, B.nchunk, B.part, s);
         if (!trans)
             launch_block_diag_apply<double>(h.d0inv.get(), h.rres.get(), L0.r.get(), fp32 ? L0.r32.get() : nullptr,
                                             h.A0.nb, h.bs0, false, s, g0);
     } else {
-        launch_axpy_active<T>(x, e, n, h.bs, L0.bsys.get(), B.active.get(), s);
+        launch_axpy_active<T>(x, e, n, h.bs, L0.bsys.get(), B.active, s);
         const MatView<double> Aop = op_view(L0, trans).with_groups(L0.tune[trans ? TU_RESIDUAL_T : TU_RESIDUAL]);
         {
             TimerScope ts(TK_RESIDUAL, 0, s);
             launch_residual<double, double>(Aop, b, x, L0.r.get(), fp32 ? L0.r32.get() : nullptr, s,
                                             gate(h, L0));
         }
-        launch_seg_sumsq(L0.r.get(), B.clo.get(), B.clen.get(), B.nchunk, B.part.get(), s);
+        launch_seg_sumsq(L0.r.get(), B.clo, B.clen, B.nchunk, B.part, s);
     }
-    launch_seg_check(B.part.get(), B.cptr.get(), h.nsys, B.bn.get(), B.rtol.get(), B.hist_cap, B.hist.get(),
-                     B.last.get(), B.active.get(), B.status.get(), B.iters.get(), B.it.get(), B.nact.get(),
-                     B.nact_acc.get(), s);
+    launch_seg_check(B.part, B.cptr, h.nsys, B.bn, B.rtol, B.hist_cap, B.hist,
+                     B.last, B.active, B.status, B.iters, B.it, B.nact,
+                     B.nact_acc, s);
 }
 
 // Cycles of stopped systems are skipped: the kernels read the activity flags.
-void run_iteration(Hier &h, bool trans, const double *b, double *x, hipStream_t s) {
+void run_iteration(Hier &h, bool trans, const double *b, double *x, hipStream_t s, const SolveBufs &V) {
     // (one system: the cycle needs no gate, the loop ends when it stops; the
     // update and the norm check still read the flag)
     struct Scope {
         Hier &h;
         Scope(Hier &hh, const int *a) : h(hh) { h.active = a; }
         ~Scope() { h.active = nullptr; }
-    } scope(h, h.nsys > 1 ? h.batch.active.get() : nullptr);
-    if (h.prm.precision == 1) batch_iteration<float>(h, trans, b, x, s);
-    else batch_iteration<double>(h, trans, b, x, s);
+    } scope(h, h.nsys > 1 ? V.active : nullptr);
+    if (h.prm.precision == 1) batch_iteration<float>(h, trans, b, x, s, V);
+    else batch_iteration<double>(h, trans, b, x, s, V);
+}
+
+SolveBufs bufs_of(BatchSolve &B) {
+    SolveBufs V;
+    V.nchunk = B.nchunk;
+    V.hist_cap = B.hist_cap;
+    V.clo = B.clo.get();
+    V.clen = B.clen.get();
+    V.cptr = B.cptr.get();
+    V.part = B.part.get();
+    V.bn = B.bn.get();
+    V.last = B.last.get();
+    V.rtol = B.rtol.get();
+    V.hist = B.hist.get();
+    V.active = B.active.get();
+    V.status = B.status.get();
+    V.iters = B.iters.get();
+    V.it = B.it.get();
+    V.nact = B.nact.get();
+    V.nact_acc = B.nact_acc.get();
+    return V;
 }
 
 // The iteration captured once into a graph for these operands, replayed per step.
@@ -356,7 +376,7 @@ hipGraphExec_t batch_graph(Hier &h, bool trans, const double *b, double *x) {
     NAIR_HIP(hipStreamBeginCapture(B.cap, hipStreamCaptureModeThreadLocal));
     g_capturing = true;
     try {
-        run_iteration(h, trans, b, x, B.cap);
+        run_iteration(h, trans, b, x, B.cap, bufs_of(B));
     } catch (...) {
         g_capturing = false;
         hipGraph_t g = nullptr;
@@ -409,6 +429,7 @@ nair_status run_solve_batch(Hier &h, bool trans, const double *b, double *x, dou
         if (fp32) launch_to_float(b, L0.r32.get(), n, s);
     }
     hipGraphExec_t ex = use_graph ? batch_graph(h, trans, b, x) : nullptr;
+    const SolveBufs V = bufs_of(B);
 
     std::vector<double> last(nsys), prev(nsys, 1.0);
     int done = 0;        // iterations launched
@@ -417,7 +438,7 @@ nair_status run_solve_batch(Hier &h, bool trans, const double *b, double *x, dou
     while (nact > 0 && done < max_iter) {
         for (int i = 0; i < run; ++i) {
             if (ex) NAIR_HIP(hipGraphLaunch(ex, s));
-            else run_iteration(h, trans, b, x, s);
+            else run_iteration(h, trans, b, x, s, V);
         }
         done += run;
         read_device({{B.last.get(), last.data(), sizeof(double) * nsys}, {B.nact.get(), &nact, sizeof(int)}}, s);
@@ -470,6 +491,79 @@ nair_status run_solve_batch(Hier &h, bool trans, const double *b, double *x, dou
     h.hist = B.hist_host.empty() ? std::vector<double>() : B.hist_host[0];
     NAIR_HIP(hipStreamSynchronize(s));
     return worst;
+}
+
+// One system in caller-provided buffers (the no-alloc solve): the iteration of
+// run_solve_batch, launched eagerly, with its host bookkeeping on the stack,
+// reads by plain copies into it (not the pinned staging buffer) and only the
+// last six history entries read back.  The kernel timer is off.  x is cleared,
+// V's rtol set and its chunk tables filled by the caller, on the stream,
+// before this runs.
+nair_status run_solve_bufs(Hier &h, const double *b, double *x, double rtol, int max_iter, nair_result *res,
+                           hipStream_t s, const SolveBufs &V) {
+    struct TimerOff {
+        TimerOff() { g_timer_off = true; }
+        ~TimerOff() { g_timer_off = false; }
+    } timer_off;
+    auto rd = [s](void *host, const void *dev, size_t bytes) {
+        NAIR_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s));
+    };
+    Level &L0 = *h.lv[0];
+    const int64_t n = static_cast<int64_t>(L0.A.nb) * h.bs;
+    const bool fp32 = h.prm.precision == 1;
+    launch_seg_sumsq(b, V.clo, V.clen, V.nchunk, V.part, s);
+    launch_seg_init(V.part, V.cptr, 1, V.bn, V.last, V.active, V.status, V.iters, V.it, V.nact, V.nact_acc, s);
+    if (h.prm.form == 1) {
+        launch_block_diag_apply<double>(h.d0inv.get(), b, L0.r.get(), fp32 ? L0.r32.get() : nullptr, h.A0.nb, h.bs0,
+                                        false, s);
+    } else {
+        NAIR_HIP(hipMemcpyAsync(L0.r.get(), b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        if (fp32) launch_to_float(b, L0.r32.get(), n, s);
+    }
+    double last = 0.0, prev = 1.0;
+    int done = 0;
+    int run = std::min(kFirstPoll, max_iter);
+    int nact = 0;
+    rd(&nact, V.nact, sizeof(int));
+    NAIR_HIP(hipStreamSynchronize(s));
+    while (nact > 0 && done < max_iter) {
+        for (int i = 0; i < run; ++i) run_iteration(h, false, b, x, s, V);
+        done += run;
+        rd(&last, V.last, sizeof(double));
+        rd(&nact, V.nact, sizeof(int));
+        NAIR_HIP(hipStreamSynchronize(s));
+        if (nact == 0 || done >= max_iter) break;
+        double need = 1.0;
+        if (last > rtol) {
+            const double rho = std::pow(last / prev, 1.0 / run);
+            need = (rho > 0.0 && rho < 1.0) ? std::log(rtol / last) / std::log(rho) : run;
+        }
+        prev = last;
+        const double cap = std::min<double>({static_cast<double>(kMaxRun), static_cast<double>(max_iter - done),
+                                             static_cast<double>(done)});
+        run = std::max(1, static_cast<int>(std::min(std::floor(kAim * need), cap)));
+    }
+    int st = 0, it = 0;
+    rd(&st, V.status, sizeof(int));
+    rd(&it, V.iters, sizeof(int));
+    NAIR_HIP(hipStreamSynchronize(s));
+    const int K = std::min(it, V.hist_cap);
+    double tail[6] = {0, 0, 0, 0, 0, 0};
+    const int nt = std::min(K, 6);
+    if (nt > 0) rd(tail, V.hist + (K - nt), sizeof(double) * nt);
+    NAIR_HIP(hipStreamSynchronize(s));
+    nair_result rr{0, 0, 0.0, 0.0, 0.0};
+    rr.iters = K;
+    rr.converged = st == 0 ? 1 : 0;
+    if (K > 0) {
+        const double hK = tail[nt - 1];
+        rr.relres = hK;
+        rr.rho_avg = std::pow(hK, 1.0 / K);
+        rr.rho_last5 = K > 5 ? std::pow(hK / tail[0], 0.2) : rr.rho_avg;
+    }
+    if (res) *res = rr;
+    h.hist.clear();   // (keeps its storage: no history is reported for this solve)
+    return static_cast<nair_status>(st);
 }
 
 // One system: the same device-side iteration, launched eagerly (a graph

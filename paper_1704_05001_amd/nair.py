@@ -24,7 +24,7 @@ EXPORTED = ["nair_default_params", "nair_setup", "nair_solve", "nair_solve_T", "
             "nair_vcycle_T", "nair_history", "nair_info", "nair_get_level", "nair_last_error",
             "nair_destroy", "nair_pool_trim", "nair_timer_select", "nair_timer_read", "nair_grad_vals",
             "nair_setup_batch", "nair_solve_batch", "nair_batch_history", "nair_get_systems",
-            "nair_autotune"]
+            "nair_autotune", "nair_solve_noalloc"]
 
 TUNE_KINDS = ("relax", "relax_T", "residual_T", "restrict", "interp_T", "residual")
 
@@ -116,6 +116,8 @@ def lib():
         L.nair_get_systems.restype = C.c_int
         L.nair_autotune.argtypes = [vp, i32, vp, vp]
         L.nair_autotune.restype = C.c_int
+        L.nair_solve_noalloc.argtypes = [vp, vp, vp, dbl, i32, C.POINTER(_Result), vp]
+        L.nair_solve_noalloc.restype = C.c_int
         _lib = L
     return _lib
 
@@ -331,6 +333,16 @@ class Hierarchy:
         preconditioned by the cycle when Params.gmres = m > 0).  Returns (x, Result)."""
         return self._solve(lambda *a: lib().nair_solve(*a), "nair_solve", b, x, rtol, max_iter, stream, raise_on)
 
+    def solve_noalloc(self, b, x, rtol=1e-10, max_iter=200, stream=None,
+                      raise_on=("EINVAL", "EDEVICE", "ENOMEM")):
+        """nair_solve_noalloc: the solve with no allocation in the library (its
+        buffers in the library's static device scratch array); the caller passes x.
+        Returns (x, Result)."""
+        if x is None:
+            raise ValueError("solve_noalloc writes into a solution vector the caller passes")
+        return self._solve(lambda *a: lib().nair_solve_noalloc(*a), "nair_solve_noalloc", b, x, rtol, max_iter,
+                           stream, raise_on)
+
     def solve_T(self, g, y=None, rtol=1e-10, max_iter=200, stream=None,
                 raise_on=("EINVAL", "EDEVICE", "ENOMEM")):
         """y = A^{-T} g by transposed nAIR cycles (GMRES(m) with Params.gmres = m).
@@ -493,6 +505,10 @@ class Hierarchy:
                 out[name] = t.view(*shape) if shape else t
         torch.cuda.synchronize(self.device)
         return out
+
+
+# NAIR_NOALLOC_SCRATCH_BYTES: the per-device scratch array of nair_solve_noalloc
+NOALLOC_SCRATCH_BYTES = 4 * 1024 * 1024
 
 
 def pool_trim():

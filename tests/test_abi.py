@@ -45,6 +45,13 @@ def test_binding_names_match_header():
         assert hasattr(L, f)
 
 
+def test_noalloc_scratch_size_matches_header():
+    import paper_1704_05001_amd as P
+    src = open(os.path.join(ROOT, "include", "nair.h")).read()
+    m = re.search(r"#define NAIR_NOALLOC_SCRATCH_BYTES (\d+)", src)
+    assert m and int(m.group(1)) == P.NOALLOC_SCRATCH_BYTES
+
+
 def test_default_params_and_host_side_errors():
     """Host-only entry points: defaults, and argument errors caught before any device work."""
     import ctypes as C
