@@ -256,11 +256,12 @@ __device__ inline double apply_dinv(const double *__restrict__ D, const double *
 }
 
 // This lane's row of a D^{-1} block (column for D^{-T}): in registers for small
-// blocks, loaded before the row product so its latency overlaps it; apply()
+// blocks (up to 25 with WIDE: the face-compressed sweep, whose row product is
+// short), loaded before the row product so its latency overlaps it; apply()
 // gives apply_dinv's sums either way.
-template <int BS, bool TRANS>
+template <int BS, bool TRANS, bool WIDE = false>
 struct DinvRow {
-    static constexpr bool kPre = BS > 0 && BS <= 16;
+    static constexpr bool kPre = BS > 0 && (BS <= 16 || (WIDE && BS <= 25));
     double d[kPre ? BS : 1];
     __device__ void load(const double *D, int a) {
         if constexpr (kPre) {
@@ -415,7 +416,7 @@ __device__ inline void sweep_rows(const SweepView<MT> &S, const int *__restrict_
     if (I >= 0 && !live(gate, I)) I = -1;
     // the copy's inverse block holds the coefficient of input c for output a at
     // c * bs + a in both directions (D^{-1} transposed, or D^{-1} for D^{-T})
-    DinvRow<BS, true> dr;
+    DinvRow<BS, true, FACE> dr;
     const double *D = S.dinv + static_cast<int64_t>(f) * bs * bs;
     const int64_t o = static_cast<int64_t>(I) * bs + L.a;
     double rv = 0.0;
@@ -567,6 +568,98 @@ __global__ __launch_bounds__(kThreads) void k_restrict(const int *__restrict__ z
     }
     acc = reduce_groups(acc, L, G, bs, part);
     if (act && L.g == 0) rc[static_cast<int64_t>(i) * bs + L.a] = static_cast<VT>(rv + acc);
+}
+
+// The same restriction with one lane per stored row of Z (block sizes >= 8,
+// where a block row's lanes would mostly wait: a Z block has a few nonzero
+// rows, a face's worth).  The R coarse rows of a workgroup own the stored rows
+// [q0, q1) of their blocks, contiguous and in block order (RB: Z's blocks by
+// their nonzero rows, row k of block t at q = off[t] / bs + k; else all bs
+// rows of block t at q = t bs + a).  In passes of up to kCrCap stored rows:
+// (1) each block's lane writes the block's column against its stored rows in
+// LDS; (2) each lane forms one stored row's product with r_J (split by column
+// parity as the row products are); (3) output lane (i, a) adds the products of
+// row i's blocks that store row a, in block order, to its total.
+constexpr int kCrCap = 1024;
+
+template <int BS, typename MT, typename VT, bool RB>
+__global__ __launch_bounds__(kThreads) void k_restrict_cr(const int *__restrict__ zrp, const int *__restrict__ zcol,
+                                                         const MT *__restrict__ zval, int nc, int bs_rt, int R,
+                                                         const VT *__restrict__ r, const int *__restrict__ cpts,
+                                                         VT *__restrict__ rc, Gate gate, RowBlockView<MT> zr) {
+    __shared__ double dot[kCrCap];
+    __shared__ int qcol[kCrCap];
+    const int bs = Bs<BS>::get(bs_rt);
+    const int i0 = blockIdx.x * R;
+    if (i0 >= nc) return;   // (the whole workgroup)
+    const int i1 = min(nc, i0 + R);
+    const int t0 = zrp[i0], t1 = zrp[i1];
+    const MT *vals = RB ? zr.vals : zval;
+    auto first_row = [&](int t) { return RB ? zr.off[t] / bs : t * bs; };
+    const int q0 = first_row(t0), q1 = first_row(t1);
+    const int nout = (i1 - i0) * bs;   // <= 2 kThreads (host)
+    double acc[2] = {0.0, 0.0};
+    for (int qc = q0; qc < q1; qc += kCrCap) {
+        const int qe = min(q1, qc + kCrCap);
+        for (int t = t0 + static_cast<int>(threadIdx.x); t < t1; t += kThreads) {
+            const int lo = max(first_row(t), qc), hi = min(first_row(t + 1), qe);
+            if (lo < hi) {
+                const int J = zcol[t];
+                for (int q = lo; q < hi; ++q) qcol[q - qc] = J;
+            }
+        }
+        __syncthreads();
+        for (int q = qc + static_cast<int>(threadIdx.x); q < qe; q += kThreads) {
+            const MT *v = vals + static_cast<int64_t>(q) * bs;
+            const VT *x = r + static_cast<int64_t>(qcol[q - qc]) * bs;
+            double a0 = 0.0, a1 = 0.0;
+            if constexpr (BS > 0) {
+#pragma unroll
+                for (int c = 0; c < BS; c += 2) {
+                    a0 += static_cast<double>(v[c]) * static_cast<double>(x[c]);
+                    if (c + 1 < BS) a1 += static_cast<double>(v[c + 1]) * static_cast<double>(x[c + 1]);
+                }
+            } else {
+                for (int c = 0; c < bs; c += 2) {
+                    a0 += static_cast<double>(v[c]) * static_cast<double>(x[c]);
+                    if (c + 1 < bs) a1 += static_cast<double>(v[c + 1]) * static_cast<double>(x[c + 1]);
+                }
+            }
+            dot[q - qc] = a0 + a1;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int k = static_cast<int>(threadIdx.x) + j * kThreads;
+            if (k < nout) {
+                const int i = i0 + k / bs, a = k - (k / bs) * bs;
+                const int hi = zrp[i + 1];
+                for (int t = zrp[i]; t < hi; ++t) {
+                    int q;
+                    if constexpr (RB) {
+                        const uint32_t m = zr.mask[t];
+                        if (!((m >> a) & 1u)) continue;
+                        q = zr.off[t] / bs + __popc(m & ((1u << a) - 1u));
+                    } else {
+                        q = t * bs + a;
+                    }
+                    if (q >= qc && q < qe) acc[j] += dot[q - qc];
+                }
+            }
+        }
+        if (qe < q1) __syncthreads();   // the next pass rewrites the LDS rows
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int k = static_cast<int>(threadIdx.x) + j * kThreads;
+        if (k < nout) {
+            const int i = i0 + k / bs, a = k - (k / bs) * bs;
+            if (live(gate, i)) {
+                const double rv = static_cast<double>(r[static_cast<int64_t>(cpts[i]) * bs + a]);
+                rc[static_cast<int64_t>(i) * bs + a] = static_cast<VT>(rv + acc[j]);
+            }
+        }
+    }
 }
 
 // y_I += [I is C] yc_{cidx I} + sum_t (Z^T)_It yc_{col t}
@@ -1025,6 +1118,31 @@ void launch_restrict(const MatView<MT> &Z, const VT *r, const int *cpts, VT *rc,
     need(Z, "launch_restrict");
     if (Z.nb <= 0) return;
     const int G = groups_for(Z);
+    if (Z.bs >= 8 && !few_lanes(Z.nb, Z.bs)) {
+        // one lane per stored row; the lane-group count sets the coarse rows per workgroup
+        const int R = std::max(1, 2 * kThreads / (G * Z.bs));
+        const unsigned grid = grid_for(Z.nb, R);
+        const bool rb = Z.rows.mask != nullptr;
+        if (rb && (!Z.rows.off || !Z.rows.vals || Z.bs > 32)) fail(NAIR_EDEVICE, "launch_restrict: incomplete row copy of Z");
+#define NAIR_CR(BS)                                                                                                 \
+    do {                                                                                                            \
+        if (rb)                                                                                                     \
+            k_restrict_cr<BS, MT, VT, true><<<grid, kThreads, 0, s>>>(Z.rowptr, Z.colidx, Z.vals, Z.nb, Z.bs, R, r,  \
+                                                                      cpts, rc, gate, Z.rows);                      \
+        else                                                                                                        \
+            k_restrict_cr<BS, MT, VT, false><<<grid, kThreads, 0, s>>>(Z.rowptr, Z.colidx, Z.vals, Z.nb, Z.bs, R, r, \
+                                                                       cpts, rc, gate, Z.rows);                     \
+    } while (0)
+        switch (Z.bs) {
+            case 9: NAIR_CR(9); break;
+            case 16: NAIR_CR(16); break;
+            case 25: NAIR_CR(25); break;
+            default: NAIR_CR(0); break;
+        }
+#undef NAIR_CR
+        NAIR_HIP(hipGetLastError());
+        return;
+    }
     const unsigned grid = grid_rows(Z.nb, G, Z.bs);
     if (Z.rows.mask) {
         if (!Z.rows.off || !Z.rows.vals || Z.bs > 32) fail(NAIR_EDEVICE, "launch_restrict: incomplete row copy of Z");
