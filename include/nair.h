@@ -51,7 +51,7 @@ typedef struct nair_hier_s *nair_hier;
 typedef struct {
     int32_t degree;           /* Neumann degree k >= 0 of the restriction (section 4.1);
                                  the F-relaxation does nu = k+1 Jacobi sweeps (section 5.1) */
-    double theta;             /* strength threshold of the C/F splitting, in [0,1): 0.25 */
+    double theta;             /* strength threshold of the C/F splitting, in [0,1): 0.75 */
     double phi;               /* strength threshold of the Neumann expansion, in [0,1): 0.025 */
     double drop;              /* drop tolerance of coarse operators, in [0,1): 1e-3 (section 5.2) */
     int32_t relax;            /* 0: F-relaxation; 1: F then one C sweep (FC) */
@@ -156,7 +156,7 @@ typedef struct {
                                       -1 when its F sweeps read A itself */
 } nair_level_view;
 
-/* Fill *p with the defaults (degree 1, theta 0.25, phi 0.025, drop 1e-3, F
+/* Fill *p with the defaults (degree 1, theta 0.75, phi 0.025, drop 1e-3, F
  * relaxation, 30 levels, 128 dense DOFs, seed 0, FP64 cycle).  Host only. */
 nair_status nair_default_params(nair_params *p);
 

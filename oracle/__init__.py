@@ -105,7 +105,7 @@ class OracleError(RuntimeError):
 @dataclass
 class Params:
     degree: int = 1
-    theta: float = 0.25
+    theta: float = 0.75
     phi: float = 0.025
     drop: float = 1e-3
     relax: int = 0            # 0 = F, 1 = FC

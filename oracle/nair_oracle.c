@@ -790,7 +790,7 @@ static void dense_solve_T(const level_t *L, const double *r, double *x) {
 
 void ora_default_params(ora_params *p) {
     p->degree = 1;
-    p->theta = 0.25;
+    p->theta = 0.75;
     p->phi = 0.025;
     p->drop = 1e-3;
     p->relax = 0;

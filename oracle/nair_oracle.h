@@ -42,7 +42,7 @@ enum {
 
 typedef struct {
     int32_t degree;           /* Neumann degree k >= 0; nu = k+1 Jacobi F sweeps */
-    double theta;             /* strength threshold for splitting (classical 0.25) */
+    double theta;             /* strength threshold for splitting (default 0.75) */
     double phi;               /* strength threshold of the Neumann mask (0.025) */
     double drop;              /* coarse-operator drop tolerance (1e-3) */
     int32_t relax;            /* 0: F-relaxation, 1: F then one C sweep (FC) */

@@ -61,7 +61,7 @@ extern "C" {
 nair_status nair_default_params(nair_params *p) {
     if (!p) return NAIR_EINVAL;
     p->degree = 1;
-    p->theta = 0.25;
+    p->theta = 0.75;
     p->phi = 0.025;
     p->drop = 1e-3;
     p->relax = 0;

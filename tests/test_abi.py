@@ -60,7 +60,7 @@ def test_default_params_and_host_side_errors():
     p = N._Params()
     assert L.nair_default_params(C.byref(p)) == 0
     assert (p.degree, p.theta, p.phi, p.drop, p.relax, p.max_levels, p.max_coarse_dofs) == \
-        (1, 0.25, 0.025, 1e-3, 0, 30, 128)
+        (1, 0.75, 0.025, 1e-3, 0, 30, 128)
     h = C.c_void_p()
     # bs out of range, negative degree, theta outside [0,1): rejected on the host
     assert L.nair_setup(4, 0, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.byref(p), None, C.byref(h)) == 1

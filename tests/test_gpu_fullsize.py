@@ -88,6 +88,7 @@ def test_fullsize_q4_512_sampled():
     rp, ci = np_(L["rowptr"]), np_(L["colidx"])
     assert np.array_equal(rp, S.rowptr) and np.array_equal(ci, S.colidx)
     bnorm, mask, cf, pmap = np_(L["bnorm"]), np_(L["mask"]), np_(L["cf"]), np_(L["pmap"])
+    theta, phi = P.Params().theta, P.Params().phi   # the defaults the hierarchy was built with
     rng = np.random.default_rng(0)
     rows = rng.choice(S.nb, size=200, replace=False)
     dinv = np_(L["dinv"][torch.from_numpy(rows).cuda().long()])
@@ -102,8 +103,8 @@ def test_fullsize_q4_512_sampled():
         assert np.array_equal(size, bnorm[lo:hi])
         off = ci[lo:hi] != I
         m = size[off].max() if off.any() else 0.0
-        st = off & (m > 0) & (size >= 0.25 * m)
-        sp_ = off & (m > 0) & (size >= 0.025 * m)
+        st = off & (m > 0) & (size >= theta * m)
+        sp_ = off & (m > 0) & (size >= phi * m)
         assert np.array_equal(mask[lo:hi] & 1, st.astype(np.uint8))
         assert np.array_equal((mask[lo:hi] >> 1) & 1, sp_.astype(np.uint8))
         if cf[I] == 1:

@@ -115,7 +115,7 @@ def test_dinv_of_every_level():
 
 # ----------------------------------------------------------- strength
 
-@pytest.mark.parametrize("theta,phi", [(0.25, 0.025), (0.5, 0.1), (0.0, 0.0)])
+@pytest.mark.parametrize("theta,phi", [(0.75, 0.025), (0.25, 0.025), (0.5, 0.1), (0.0, 0.0)])
 def test_strength_definition(theta, phi):
     """Brute force of: a block is strong when its max-abs size is >= threshold
     times the largest off-diagonal block size of its row (sections 4.1, 4.2)."""
