@@ -304,13 +304,18 @@ struct RowBlockView {
 // c_k: consecutive lanes read consecutive words of a stored row, and the zero
 // rows of M's blocks (most of a coarse block, all but the face rows of a DG
 // face block) are neither stored nor read.  A whole transposed block would
-// store every column of M's block as a row.
+// store every column of M's block as a row.  The products walk the stored rows
+// flat: output row I owns stored rows qptr[I] .. qptr[I+1]-1 (entry by entry,
+// each entry's rows in ascending c_k), and stored row q multiplies x at
+// src[q] = J bs + c_k.
 struct TransRows {
     bool on = false;
     int nrows = 0;                 // output rows (M's block columns)
     int64_t nent = 0;              // entries (blocks)
+    int64_t nq = 0;                // stored rows
     DBuf<int> rowptr, colidx, off;
     DBuf<uint32_t> mask;
+    DBuf<int> qptr, src;
     DBuf<double> vals;
     DBuf<float> vals32;
 };
@@ -323,9 +328,10 @@ void trans_rows_to_float(TransRows &T, int bs, hipStream_t s);
 template <typename MT>
 struct TransRowsView {
     int nrows = 0, bs = 0;
-    int64_t nent = 0;
+    int64_t nent = 0, nq = 0;
     const int *rowptr = nullptr, *colidx = nullptr, *off = nullptr;
     const uint32_t *mask = nullptr;
+    const int *qptr = nullptr, *src = nullptr;
     const MT *vals = nullptr;
     int groups = 0;   // lane groups per output row (0: from the row length)
     TransRowsView with_groups(int g) const {

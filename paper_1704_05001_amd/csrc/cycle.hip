@@ -202,28 +202,51 @@ __device__ inline double row_part_rows(const int *__restrict__ colidx, const Row
     return acc0 + acc1;
 }
 
-// The same row product read transposed from a TransRows copy: output row I's
-// entries t = lo+g, lo+g+G, ... < hi each hold source block M_JI by its
-// nonzero rows c_k; lane a adds M_JI[c_k][a] x_J[c_k] (with SKIP, the entry
-// with J == skip is left out).
+// The same row product read transposed from a TransRows copy: output row I
+// owns the stored rows q = qptr[I] + g, + G, ... < qptr[I+1], row q being
+// M_JI[c][.] of some source block, to be multiplied by x at src[q] = J bs + c;
+// lane a adds M_JI[c][a] x_J[c] (with SKIP, rows with J == skip are left out).
+// Four rows per step load together; the sums alternate between two
+// accumulators in walk order.
 template <int BS, typename MT, typename VT, bool SKIP = false>
-__device__ inline double row_part_tr(const TransRowsView<MT> &T, int lo, int hi, int g, int G, int a, int bs_rt,
+__device__ inline double row_part_tr(const TransRowsView<MT> &T, int I, int g, int G, int a, int bs_rt,
                                      const VT *__restrict__ x, int skip = -1) {
     const int bs = Bs<BS>::get(bs_rt);
+    const int hi = T.qptr[I + 1];
     double acc0 = 0.0, acc1 = 0.0;
-    for (int t = lo + g; t < hi; t += G) {
-        const int J = T.colidx[t];
+    int q = T.qptr[I] + g;
+    for (; q + 3 * G < hi; q += 4 * G) {
+        int s[4];
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            s[u] = T.src[q + u * G];
+            v[u] = static_cast<double>(T.vals[static_cast<int64_t>(q + u * G) * bs + a]);
+        }
         if constexpr (SKIP) {
-            if (J == skip) continue;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (s[u] / bs == skip) continue;
+                if (u & 1) acc1 += v[u] * static_cast<double>(x[s[u]]);
+                else acc0 += v[u] * static_cast<double>(x[s[u]]);
+            }
+        } else {
+            const double x0 = static_cast<double>(x[s[0]]), x1 = static_cast<double>(x[s[1]]);
+            const double x2 = static_cast<double>(x[s[2]]), x3 = static_cast<double>(x[s[3]]);
+            acc0 += v[0] * x0;
+            acc1 += v[1] * x1;
+            acc0 += v[2] * x2;
+            acc1 += v[3] * x3;
         }
-        uint32_t m = T.mask[t];
-        const MT *v = T.vals + T.off[t] + a;
-        const VT *xj = x + static_cast<int64_t>(J) * bs;
-        for (int k = 0; m != 0u; m &= m - 1u, ++k) {
-            const int c = __ffs(static_cast<int>(m)) - 1;
-            if (k & 1) acc1 += static_cast<double>(v[k * bs]) * static_cast<double>(xj[c]);
-            else acc0 += static_cast<double>(v[k * bs]) * static_cast<double>(xj[c]);
+    }
+    for (int u = 0; q < hi; q += G, ++u) {
+        const int s = T.src[q];
+        const double v = static_cast<double>(T.vals[static_cast<int64_t>(q) * bs + a]);
+        if constexpr (SKIP) {
+            if (s / bs == skip) continue;
         }
+        if (u & 1) acc1 += v * static_cast<double>(x[s]);
+        else acc0 += v * static_cast<double>(x[s]);
     }
     return acc0 + acc1;
 }
@@ -704,7 +727,7 @@ __global__ __launch_bounds__(kThreads) void k_residual_tr(TransRowsView<MT> T, i
     const bool act = L.valid && I < T.nrows && live(gate, I);
     const int64_t o = static_cast<int64_t>(I) * bs + L.a;
     const double gv = (act && L.g == 0) ? static_cast<double>(g[o]) : 0.0;
-    double acc = act ? row_part_tr<BS, MT, VT>(T, T.rowptr[I], T.rowptr[I + 1], L.g, G, L.a, bs, y) : 0.0;
+    double acc = act ? row_part_tr<BS, MT, VT>(T, I, L.g, G, L.a, bs, y) : 0.0;
     acc = reduce_groups(acc, L, G, bs, part);
     if (act && L.g == 0) sout[o] = static_cast<VT>(gv - acc);
 }
@@ -731,8 +754,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_tr(TransRowsView<MT> T, cons
         gv = static_cast<double>(g[o]);
         dr.load(D, L.a);
     }
-    double acc = I >= 0 ? row_part_tr<BS, MT, VT, true>(T, T.rowptr[I], T.rowptr[I + 1], L.g, G, L.a, bs, yin, I)
-                        : 0.0;
+    double acc = I >= 0 ? row_part_tr<BS, MT, VT, true>(T, I, L.g, G, L.a, bs, yin, I) : 0.0;
     acc = reduce_groups(acc, L, G, bs, part);
     if (I >= 0 && L.g == 0) tb[L.lr * bs + L.a] = gv - acc;
     __syncthreads();
@@ -757,7 +779,7 @@ __global__ __launch_bounds__(kThreads) void k_interp_tr(TransRowsView<MT> T, int
         ci = cidx[I];
         if (ci >= 0) cv = static_cast<double>(yc[static_cast<int64_t>(ci) * bs + L.a]);
     }
-    double acc = act ? row_part_tr<BS, MT, VT>(T, T.rowptr[I], T.rowptr[I + 1], L.g, G, L.a, bs, yc) : 0.0;
+    double acc = act ? row_part_tr<BS, MT, VT>(T, I, L.g, G, L.a, bs, yc) : 0.0;
     acc = reduce_groups(acc, L, G, bs, part);
     if (act && L.g == 0) {
         if (ci >= 0) acc += cv;
@@ -1200,12 +1222,14 @@ int groups_for_tr(const TransRowsView<MT> &T) {
     v.nb = T.nrows;
     v.bs = T.bs;
     v.groups = T.groups;
-    return groups_for_len(v, T.nrows > 0 ? static_cast<double>(T.nent) / T.nrows : 1.0);   // entries per row
+    // (a stored row costs about a fifth of a whole block row's lane work)
+    return groups_for_len(v, T.nrows > 0 ? static_cast<double>(T.nq) / (5.0 * T.nrows) : 1.0);
 }
 
 template <typename MT>
 void need_tr(const TransRowsView<MT> &T, const char *what) {
-    if (T.nrows > 0 && (!T.rowptr || (T.nent > 0 && (!T.colidx || !T.mask || !T.off || !T.vals))) || T.bs > 32)
+    if (T.nrows > 0 && (!T.rowptr || !T.qptr || (T.nent > 0 && (!T.colidx || !T.mask || !T.off || !T.src || !T.vals))) ||
+        T.bs > 32)
         fail(NAIR_EDEVICE, std::string(what) + ": incomplete transposed row copy");
 }
 

@@ -102,12 +102,14 @@ inline MatView<float> op_view32(const Level &L, bool trans) {
 }
 
 inline TransRowsView<double> tr_view(const TransRows &T, int bs) {
-    return TransRowsView<double>{T.nrows,       bs,           T.nent,        T.rowptr.get(), T.colidx.get(),
-                                 T.off.get(),   T.mask.get(), T.vals.get(), 0};
+    return TransRowsView<double>{T.nrows,      bs,          T.nent,         T.nq,         T.rowptr.get(),
+                                 T.colidx.get(), T.off.get(), T.mask.get(), T.qptr.get(), T.src.get(),
+                                 T.vals.get(), 0};
 }
 inline TransRowsView<float> tr_view32(const TransRows &T, int bs) {
-    return TransRowsView<float>{T.nrows,       bs,           T.nent,          T.rowptr.get(), T.colidx.get(),
-                                T.off.get(),   T.mask.get(), T.vals32.get(), 0};
+    return TransRowsView<float>{T.nrows,      bs,          T.nent,         T.nq,         T.rowptr.get(),
+                                T.colidx.get(), T.off.get(), T.mask.get(), T.qptr.get(), T.src.get(),
+                                T.vals32.get(), 0};
 }
 
 // Z as the restriction reads it: by its blocks' nonzero rows where the level keeps them.

@@ -485,11 +485,13 @@ void ensure_transposes(Hier &h, hipStream_t s) {
     for (size_t l = 0; l < h.lv.size(); ++l) {
         Level &L = *h.lv[l];
         if (L.have_T) continue;
-        // below the face-compressed finest level, the transposed sweeps and
-        // residual read A's rows transposed by their nonzero rows (only the F
-        // rows: with F relaxation the transposed sweeps leave y zero on C rows)
+        // below the finest level, the transposed sweeps and residual read A's
+        // rows transposed by their nonzero rows (only the F rows: with F
+        // relaxation the transposed sweeps leave y zero on C rows); the finest
+        // level reads A^T (its face copy, or its sweep copy), as the forward
+        // cycle reads A, whether or not it is face-shaped
         const bool rows_tr = L.A.bs >= 4 && !L.coarsest;
-        if (rows_tr && !L.face.on)
+        if (rows_tr && l > 0)
             build_trans_rows(L.A, h.prm.relax == 1 ? nullptr : L.cf.get(), 0, L.amask.get(), L.atF, s);
         // A^T itself: the finest level (face copy, outer residual), the F-cycle's
         // coarse residuals, small blocks and the coarsest level

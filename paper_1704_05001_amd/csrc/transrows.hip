@@ -52,6 +52,24 @@ __global__ __launch_bounds__(256) void k_tr_sort(const int *__restrict__ trp, in
     }
 }
 
+// The flat walk: src of each stored row (one thread per entry) ...
+__global__ __launch_bounds__(256) void k_tr_src(const int *__restrict__ colidx, const uint32_t *__restrict__ mask,
+                                               const int *__restrict__ off, int64_t nent, int bs,
+                                               int *__restrict__ src) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nent) return;
+    const int base = colidx[t] * bs;
+    int q = off[t] / bs;
+    for (uint32_t m = mask[t]; m != 0u; m &= m - 1u) src[q++] = base + __ffs(static_cast<int>(m)) - 1;
+}
+
+// ... and each output row's first stored row
+__global__ __launch_bounds__(256) void k_tr_qptr(const int *__restrict__ rowptr, const int *__restrict__ off, int nrows,
+                                                int bs, int *__restrict__ qptr) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I <= nrows) qptr[I] = off[rowptr[I]] / bs;
+}
+
 }  // namespace
 
 bool build_trans_rows(const DevBSR &M, const int8_t *cf, int keep_cf, const uint32_t *mmask, TransRows &T,
@@ -93,6 +111,18 @@ bool build_trans_rows(const DevBSR &M, const int8_t *cf, int keep_cf, const uint
         T.mask = std::move(R.mask);
         T.off = std::move(R.off);
         T.vals = std::move(R.vals);
+    }
+    // the flat walk over stored rows
+    T.qptr.alloc(static_cast<size_t>(nout) + 1);
+    if (nent > 0) {
+        T.nq = read_int(T.off.get() + nent, s) / bs;
+        T.src.alloc(static_cast<size_t>(std::max<int64_t>(T.nq, 1)));
+        k_tr_src<<<grid_for(nent, 256), 256, 0, s>>>(T.colidx.get(), T.mask.get(), T.off.get(), nent, bs, T.src.get());
+        k_tr_qptr<<<grid_for(static_cast<int64_t>(nout) + 1, 256), 256, 0, s>>>(T.rowptr.get(), T.off.get(), nout, bs,
+                                                                               T.qptr.get());
+        NAIR_HIP(hipGetLastError());
+    } else {
+        NAIR_HIP(hipMemsetAsync(T.qptr.get(), 0, sizeof(int) * (static_cast<size_t>(nout) + 1), s));
     }
     T.on = true;
     return true;
