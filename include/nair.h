@@ -144,7 +144,7 @@ typedef struct {
     const uint64_t *face_meta;     /* [nnzb] nonzero rows (bits 0..31), columns (bits 32..63); 0 on
                                       diagonal blocks */
     const double *face_vals;       /* [nnzb][rmax][cmax] entries on those rows x columns, ascending */
-    const double *face_dvals;      /* [nb][bs][bs] diagonal blocks */
+    const double *face_dvals;      /* [nb][bs][bs] diagonal blocks by columns: entry (a, c) at c * bs + a */
     int32_t margin[4];             /* decision-margin audit (host copy): comparisons whose two sides lie
                                       within 1e-12 relative in the theta and phi strength tests, F rows
                                       whose one-point choice has a rival that close, and drop tests of

@@ -246,7 +246,9 @@ void pmap_transpose(const int *pmap, int nb, int nc, DBuf<int> &ptptr, DBuf<int>
 // (bits 0..31) and nonzero columns (bits 32..63); its rmax x cmax rectangle
 // vals[t * rc + p * cmax + q] holds the entry of its p-th nonzero row and q-th
 // nonzero column (zero past its own counts).  Diagonal blocks (meta 0) are
-// kept whole in dvals [nb][bs][bs].  vals32 / dvals32: the same in float.
+// kept whole in dvals [nb][bs][bs] by columns (entry (a, c) at c * bs + a, so
+// the lanes of a block row read consecutive words).  vals32 / dvals32: the
+// same in float.
 struct FaceCopy {
     bool on = false;
     int rmax = 0, cmax = 0, rc = 0;

@@ -53,6 +53,29 @@ struct PmapSrc {
         return p >= 0 ? ec + static_cast<int64_t>(p) * bs : nullptr;
     }
 };
+// One block row's product with x_J: sum over c of blk[c] x_J[c], the even and
+// the odd c summed apart and then added.  Every row product below adds these
+// per-block sums in block order, whichever lanes form them, so the kernels that
+// read a level's blocks whole, face-compressed, by their nonzero rows or one
+// lane per stored row agree bit for bit (at one lane group per row).
+template <int BS, typename MT, typename VT>
+__device__ inline double block_row_dot(const MT *__restrict__ blk, const VT *__restrict__ xj, int bs) {
+    double p0 = 0.0, p1 = 0.0;
+    if constexpr (BS > 0) {
+#pragma unroll
+        for (int c = 0; c < BS; c += 2) {
+            p0 += static_cast<double>(blk[c]) * static_cast<double>(xj[c]);
+            if (c + 1 < BS) p1 += static_cast<double>(blk[c + 1]) * static_cast<double>(xj[c + 1]);
+        }
+    } else {
+        for (int c = 0; c < bs; c += 2) {
+            p0 += static_cast<double>(blk[c]) * static_cast<double>(xj[c]);
+            if (c + 1 < bs) p1 += static_cast<double>(blk[c + 1]) * static_cast<double>(xj[c + 1]);
+        }
+    }
+    return p0 + p1;
+}
+
 // sum over blocks t = lo+g, lo+g+G, ... < hi of (block t row a) . x[col t];
 // with SKIP, the block in column `skip` (the row's diagonal block) is left out.
 template <int BS, typename MT, typename VT, typename SRC, bool SKIP = false>
@@ -60,7 +83,7 @@ __device__ inline double row_part_src(const int *__restrict__ colidx, const MT *
                                       int g, int G, int a, int bs_rt, const SRC &src, int skip = -1) {
     const int bs = Bs<BS>::get(bs_rt);
     const int64_t bb = static_cast<int64_t>(bs) * bs;
-    double acc0 = 0.0, acc1 = 0.0;
+    double acc = 0.0;
     for (int t = lo + g; t < hi; t += G) {
         const MT *blk = vals + t * bb + a * bs;
         const int J = colidx[t];
@@ -71,18 +94,9 @@ __device__ inline double row_part_src(const int *__restrict__ colidx, const MT *
         if constexpr (SRC::kMaySkip) {
             if (xj == nullptr) continue;
         }
-        if constexpr (BS > 0) {
-#pragma unroll
-            for (int c = 0; c < BS; c += 2) {
-                acc0 += static_cast<double>(blk[c]) * static_cast<double>(xj[c]);
-                if (c + 1 < BS) acc1 += static_cast<double>(blk[c + 1]) * static_cast<double>(xj[c + 1]);
-            }
-        } else {
-#pragma unroll 4
-            for (int c = 0; c < bs; ++c) acc0 += static_cast<double>(blk[c]) * static_cast<double>(xj[c]);
-        }
+        acc += block_row_dot<BS>(blk, xj, bs);
     }
-    return acc0 + acc1;
+    return acc;
 }
 
 template <int BS, typename MT, typename VT, bool SKIP = false>
@@ -103,9 +117,9 @@ __device__ inline double row_part_face(const int *__restrict__ colidx, const Fac
                                        int G, int a, int I, int bs_rt, const VT *__restrict__ x) {
     const int bs = Bs<BS>::get(bs_rt);
     const int64_t bb = static_cast<int64_t>(bs) * bs;
-    double acc0 = 0.0, acc1 = 0.0;
+    double acc = 0.0;
     int t = lo + g;
-    if (t >= hi) return acc0 + acc1;
+    if (t >= hi) return acc;
     // the next block's column and masks load while this block's values and x do
     int J = colidx[t];
     uint64_t m = F.meta[t];
@@ -125,34 +139,41 @@ __device__ inline double row_part_face(const int *__restrict__ colidx, const Fac
                 m = mn;
                 continue;
             }
-            const MT *blk = F.dvals + static_cast<int64_t>(I) * bb + a * bs;
+            const MT *blk = F.dvals + static_cast<int64_t>(I) * bb + a;   // by columns
+            double p0 = 0.0, p1 = 0.0;
             if constexpr (BS > 0) {
 #pragma unroll
                 for (int c = 0; c < BS; c += 2) {
-                    acc0 += static_cast<double>(blk[c]) * static_cast<double>(xj[c]);
-                    if (c + 1 < BS) acc1 += static_cast<double>(blk[c + 1]) * static_cast<double>(xj[c + 1]);
+                    p0 += static_cast<double>(blk[c * BS]) * static_cast<double>(xj[c]);
+                    if (c + 1 < BS) p1 += static_cast<double>(blk[(c + 1) * BS]) * static_cast<double>(xj[c + 1]);
                 }
             } else {
-                for (int c = 0; c < bs; ++c) acc0 += static_cast<double>(blk[c]) * static_cast<double>(xj[c]);
+                for (int c = 0; c < bs; c += 2) {
+                    p0 += static_cast<double>(blk[c * bs]) * static_cast<double>(xj[c]);
+                    if (c + 1 < bs) p1 += static_cast<double>(blk[(c + 1) * bs]) * static_cast<double>(xj[c + 1]);
+                }
             }
+            acc += p0 + p1;
         } else {
             const uint32_t rm = static_cast<uint32_t>(m);
             if ((rm >> a) & 1u) {
                 const uint32_t cm = static_cast<uint32_t>(m >> 32);
                 const MT *row = F.vals + static_cast<int64_t>(t) * F.rc + __popc(rm & ((1u << a) - 1u)) * F.cmax;
+                double p0 = 0.0, p1 = 0.0;
                 int q = 0;
                 for (uint32_t mm = cm; mm != 0u; mm &= mm - 1u, ++q) {
                     const int c = __ffs(static_cast<int>(mm)) - 1;
-                    if (BS > 0 && (c & 1)) acc1 += static_cast<double>(row[q]) * static_cast<double>(xj[c]);
-                    else acc0 += static_cast<double>(row[q]) * static_cast<double>(xj[c]);
+                    if (c & 1) p1 += static_cast<double>(row[q]) * static_cast<double>(xj[c]);
+                    else p0 += static_cast<double>(row[q]) * static_cast<double>(xj[c]);
                 }
+                acc += p0 + p1;
             }
         }
         if (tn >= hi) break;
         J = Jn;
         m = mn;
     }
-    return acc0 + acc1;
+    return acc;
 }
 
 // The same row product over blocks kept by their nonzero rows (RowBlockView):
@@ -164,9 +185,9 @@ __device__ inline double row_part_rows(const int *__restrict__ colidx, const Row
                                        int g, int G, int a, int bs_rt, const VT *__restrict__ x) {
     const int bs = Bs<BS>::get(bs_rt);
     const uint32_t below = (1u << a) - 1u;
-    double acc0 = 0.0, acc1 = 0.0;
+    double acc = 0.0;
     int t = lo + g;
-    if (t >= hi) return acc0 + acc1;
+    if (t >= hi) return acc;
     // the next block's column, mask and offset load while this block's row and x do
     int J = colidx[t];
     uint32_t m = R.mask[t];
@@ -180,26 +201,14 @@ __device__ inline double row_part_rows(const int *__restrict__ colidx, const Row
             mn = R.mask[tn];
             on = R.off[tn];
         }
-        if ((m >> a) & 1u) {
-            const MT *blk = R.vals + o + __popc(m & below) * bs;
-            const VT *xj = x + static_cast<int64_t>(J) * bs;
-            if constexpr (BS > 0) {
-#pragma unroll
-                for (int c = 0; c < BS; c += 2) {
-                    acc0 += static_cast<double>(blk[c]) * static_cast<double>(xj[c]);
-                    if (c + 1 < BS) acc1 += static_cast<double>(blk[c + 1]) * static_cast<double>(xj[c + 1]);
-                }
-            } else {
-                for (int c = 0; c < bs; ++c) acc0 += static_cast<double>(blk[c]) * static_cast<double>(xj[c]);
-            }
-        }
+        if ((m >> a) & 1u) acc += block_row_dot<BS>(R.vals + o + __popc(m & below) * bs, x + static_cast<int64_t>(J) * bs, bs);
         if (tn >= hi) break;
         t = tn;
         J = Jn;
         m = mn;
         o = on;
     }
-    return acc0 + acc1;
+    return acc;
 }
 
 // The same row product read transposed from a TransRows copy: output row I
@@ -632,24 +641,9 @@ __global__ __launch_bounds__(kThreads) void k_restrict_cr(const int *__restrict_
             }
         }
         __syncthreads();
-        for (int q = qc + static_cast<int>(threadIdx.x); q < qe; q += kThreads) {
-            const MT *v = vals + static_cast<int64_t>(q) * bs;
-            const VT *x = r + static_cast<int64_t>(qcol[q - qc]) * bs;
-            double a0 = 0.0, a1 = 0.0;
-            if constexpr (BS > 0) {
-#pragma unroll
-                for (int c = 0; c < BS; c += 2) {
-                    a0 += static_cast<double>(v[c]) * static_cast<double>(x[c]);
-                    if (c + 1 < BS) a1 += static_cast<double>(v[c + 1]) * static_cast<double>(x[c + 1]);
-                }
-            } else {
-                for (int c = 0; c < bs; c += 2) {
-                    a0 += static_cast<double>(v[c]) * static_cast<double>(x[c]);
-                    if (c + 1 < bs) a1 += static_cast<double>(v[c + 1]) * static_cast<double>(x[c + 1]);
-                }
-            }
-            dot[q - qc] = a0 + a1;
-        }
+        for (int q = qc + static_cast<int>(threadIdx.x); q < qe; q += kThreads)
+            dot[q - qc] = block_row_dot<BS>(vals + static_cast<int64_t>(q) * bs, r + static_cast<int64_t>(qcol[q - qc]) * bs,
+                                            bs);
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -680,6 +674,97 @@ __global__ __launch_bounds__(kThreads) void k_restrict_cr(const int *__restrict_
             if (live(gate, i)) {
                 const double rv = static_cast<double>(r[static_cast<int64_t>(cpts[i]) * bs + a]);
                 rc[static_cast<int64_t>(i) * bs + a] = static_cast<VT>(rv + acc[j]);
+            }
+        }
+    }
+}
+
+// The F sweep from a sweep copy stored by nonzero rows, one lane per stored
+// row (block sizes >= 8 on the larger levels), as k_restrict_cr forms Z r: the
+// R F rows f0 .. of a workgroup own the stored rows of their blocks; per pass
+// each lane forms one stored row's product with e_in, and output lane (f, a)
+// adds those of row f's blocks that store row a, in block order (the sums
+// sweep_rows forms at one lane group).  Then t = r_I - sum goes to LDS and
+// e_out_I = D^{-1} t (or D^{-T} t: the copy's inverse block holds the
+// coefficient of input c for output a at c bs + a either way).
+template <int BS, typename MT, typename VT>
+__global__ __launch_bounds__(kThreads) void k_sweep_cr(SweepView<MT> S, const int *__restrict__ flist, int nF,
+                                                      int bs_rt, int R, const VT *__restrict__ r,
+                                                      const VT *__restrict__ ein, VT *__restrict__ eout, Gate gate) {
+    __shared__ double dot[kCrCap];
+    __shared__ int qcol[kCrCap];
+    __shared__ double tb[2 * kThreads];
+    const int bs = Bs<BS>::get(bs_rt);
+    const int f0 = blockIdx.x * R;
+    if (f0 >= nF) return;   // (the whole workgroup)
+    const int f1 = min(nF, f0 + R);
+    const int t0 = S.rowptr[f0], t1 = S.rowptr[f1];
+    const RowBlockView<MT> &RB = S.rows;
+    const int q0 = RB.off[t0] / bs, q1 = RB.off[t1] / bs;
+    const int nout = (f1 - f0) * bs;   // <= 2 kThreads (host)
+    double acc[2] = {0.0, 0.0};
+    for (int qc = q0; qc < q1; qc += kCrCap) {
+        const int qe = min(q1, qc + kCrCap);
+        for (int t = t0 + static_cast<int>(threadIdx.x); t < t1; t += kThreads) {
+            const int lo = max(RB.off[t] / bs, qc), hi = min(RB.off[t + 1] / bs, qe);
+            if (lo < hi) {
+                const int J = S.colidx[t];
+                for (int q = lo; q < hi; ++q) qcol[q - qc] = J;
+            }
+        }
+        __syncthreads();
+        for (int q = qc + static_cast<int>(threadIdx.x); q < qe; q += kThreads)
+            dot[q - qc] = block_row_dot<BS>(RB.vals + static_cast<int64_t>(q) * bs,
+                                            ein + static_cast<int64_t>(qcol[q - qc]) * bs, bs);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int k = static_cast<int>(threadIdx.x) + j * kThreads;
+            if (k < nout) {
+                const int f = f0 + k / bs, a = k - (k / bs) * bs;
+                const int hi = S.rowptr[f + 1];
+                for (int t = S.rowptr[f]; t < hi; ++t) {
+                    const uint32_t m = RB.mask[t];
+                    if (!((m >> a) & 1u)) continue;
+                    const int q = RB.off[t] / bs + __popc(m & ((1u << a) - 1u));
+                    if (q >= qc && q < qe) acc[j] += dot[q - qc];
+                }
+            }
+        }
+        if (qe < q1) __syncthreads();   // the next pass rewrites the LDS rows
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int k = static_cast<int>(threadIdx.x) + j * kThreads;
+        if (k < nout) {
+            const int I = flist[f0 + k / bs], a = k - (k / bs) * bs;
+            tb[k] = static_cast<double>(r[static_cast<int64_t>(I) * bs + a]) - acc[j];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int k = static_cast<int>(threadIdx.x) + j * kThreads;
+        if (k < nout) {
+            const int fl = k / bs, a = k - fl * bs;
+            const int I = flist[f0 + fl];
+            if (live(gate, I)) {
+                const double *D = S.dinv + static_cast<int64_t>(f0 + fl) * bs * bs + a;
+                const double *t = tb + fl * bs;
+                double d0 = 0.0, d1 = 0.0;
+                if constexpr (BS > 0) {
+#pragma unroll
+                    for (int c = 0; c < BS; c += 2) {
+                        d0 += D[c * BS] * t[c];
+                        if (c + 1 < BS) d1 += D[(c + 1) * BS] * t[c + 1];
+                    }
+                } else {
+                    for (int c = 0; c < bs; c += 2) {
+                        d0 += D[c * bs] * t[c];
+                        if (c + 1 < bs) d1 += D[(c + 1) * bs] * t[c + 1];
+                    }
+                }
+                eout[static_cast<int64_t>(I) * bs + a] = static_cast<VT>(d0 + d1);
             }
         }
     }
@@ -1091,6 +1176,18 @@ void launch_relax(const MatView<MT> &A, const double *dinv, bool dinv_trans, con
         const SweepView<MT> &S = A.sweep;
         if ((S.meta ? !S.vals : (!S.rows.mask || !S.rows.off || !S.rows.vals)) || !S.dinv || A.bs > 32)
             fail(NAIR_EDEVICE, "launch_relax: incomplete sweep copy");
+        if (!S.meta && A.bs >= 8 && !few_lanes(nlist, A.bs)) {   // one lane per stored row
+            const int R = std::max(1, 2 * kThreads / (G * A.bs));
+            const unsigned grid_cr = grid_for(nlist, R);
+            switch (A.bs) {
+                case 9: k_sweep_cr<9, MT, VT><<<grid_cr, kThreads, 0, s>>>(S, list, nlist, A.bs, R, r, ein, eout, gate); break;
+                case 16: k_sweep_cr<16, MT, VT><<<grid_cr, kThreads, 0, s>>>(S, list, nlist, A.bs, R, r, ein, eout, gate); break;
+                case 25: k_sweep_cr<25, MT, VT><<<grid_cr, kThreads, 0, s>>>(S, list, nlist, A.bs, R, r, ein, eout, gate); break;
+                default: k_sweep_cr<0, MT, VT><<<grid_cr, kThreads, 0, s>>>(S, list, nlist, A.bs, R, r, ein, eout, gate); break;
+            }
+            NAIR_HIP(hipGetLastError());
+            return;
+        }
         if (dinv_trans && S.meta) {
             NAIR_FACE_DISPATCH(A.bs, k_sweep_T, <<<grid, kThreads, 0, s>>>(S, list, nlist, A.bs, G, r, ein, eout,
                                                                            gate));

@@ -75,14 +75,15 @@ __global__ __launch_bounds__(256) void k_face_fill(const double *__restrict__ va
     out[g] = v;
 }
 
-// dvals[I] = A_II, one thread per entry.
+// dvals[I] = A_II by columns (entry (a, c) at c * bs + a), one thread per entry.
 __global__ __launch_bounds__(256) void k_face_diag(const double *__restrict__ vals, const int *__restrict__ diagpos,
                                                   int nb, int bs, double *__restrict__ dvals) {
     const int64_t bb = static_cast<int64_t>(bs) * bs;
     const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= static_cast<int64_t>(nb) * bb) return;
     const int64_t I = g / bb;
-    dvals[g] = vals[static_cast<int64_t>(diagpos[I]) * bb + (g - I * bb)];
+    const int e = static_cast<int>(g - I * bb), c = e / bs, a = e - c * bs;
+    dvals[g] = vals[static_cast<int64_t>(diagpos[I]) * bb + a * bs + c];
 }
 
 unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + 255) / 256); }

@@ -48,7 +48,8 @@ def check_face_copy(G, rp, ci, va):
         rect = np.zeros((rmax, cmax))
         rect[:len(r), :len(c)] = va[t][np.ix_(r, c)]
         assert np.array_equal(fv[t], rect), t
-    assert np.array_equal(np_(v["face_dvals"]), va[diag][np.argsort(rows[diag])])
+    # the diagonal blocks by columns
+    assert np.array_equal(np_(v["face_dvals"]), va[diag][np.argsort(rows[diag])].transpose(0, 2, 1))
     return rmax, cmax
 
 
