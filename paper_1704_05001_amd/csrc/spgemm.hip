@@ -718,9 +718,11 @@ __global__ __launch_bounds__(256) void k_galerkin_mfma(int64_t nnz, const int *_
 // loaded into registers while the current pair's steps run, and the pair
 // index after that one is loaded a step earlier still, so no load waits on
 // an address that has just been read.  Same steps, same order, same sums as
-// k_galerkin_mfma, bit for bit (the fragments are the same numbers).
+// k_galerkin_mfma, bit for bit (the fragments are the same numbers).  The
+// register budget is held to three waves per SIMD (no spills at bs 25): with
+// two, too few waves were left to cover the loads.
 template <int BS>
-__global__ __launch_bounds__(256) void k_galerkin_lds(int64_t nnz, const int *__restrict__ kptr,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_galerkin_lds(int64_t nnz, const int *__restrict__ kptr,
                                                      const int *__restrict__ klist, const int *__restrict__ pairptr,
                                                      const int2 *__restrict__ pairs, const double *__restrict__ X,
                                                      const double *__restrict__ Y, double *__restrict__ K,
