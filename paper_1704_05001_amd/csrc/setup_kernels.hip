@@ -758,6 +758,21 @@ __global__ __launch_bounds__(256) void k_block_gather(int64_t n, int bb, const d
     }
 }
 
+// The same with one wave per block (blocks of 64 entries or more): the block
+// index and its source are read once per block and the entries need no division.
+__global__ __launch_bounds__(256) void k_block_gather_wave(int64_t n, int bb, const double *__restrict__ Y,
+                                                          const int *__restrict__ src, double *__restrict__ out,
+                                                          const int *__restrict__ count) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nblk = count ? *count : n;
+    const int64_t stride = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    for (int64_t t = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; t < nblk; t += stride) {
+        const double *y = Y + static_cast<int64_t>(src[t]) * bb;
+        double *o = out + t * bb;
+        for (int e = lane; e < bb; e += 64) o[e] = y[e];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_rows_of(const int *__restrict__ rowptr, int nrows, int *__restrict__ rowid) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nrows) return;
@@ -938,7 +953,10 @@ void launch_block_product(int64_t n, int bs, const double *X, const int *xi, con
 void launch_block_gather(int64_t n, int bs, const double *Y, const int *src, double *out, hipStream_t s,
                          const int *count) {
     if (n <= 0) return;
-    k_block_gather<<<cap_grid((n * bs * bs + 255) / 256), 256, 0, s>>>(n, bs * bs, Y, src, out, count);
+    if (bs * bs >= 64)
+        k_block_gather_wave<<<cap_grid((n + 3) / 4), 256, 0, s>>>(n, bs * bs, Y, src, out, count);
+    else
+        k_block_gather<<<cap_grid((n * bs * bs + 255) / 256), 256, 0, s>>>(n, bs * bs, Y, src, out, count);
     NAIR_HIP(hipGetLastError());
 }
 

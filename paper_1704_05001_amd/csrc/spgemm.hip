@@ -198,6 +198,29 @@ __global__ __launch_bounds__(256) void k_add_values(const int *__restrict__ coun
     }
 }
 
+// The same with one wave per block (blocks of 64 entries or more).
+__global__ __launch_bounds__(256) void k_add_values_wave(const int *__restrict__ count, int bb,
+                                                        const double *__restrict__ S, const int *__restrict__ srcS,
+                                                        const double *__restrict__ W, const int *__restrict__ srcW,
+                                                        double *__restrict__ O) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nblk = *count;
+    const int64_t stride = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    for (int64_t t = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; t < nblk; t += stride) {
+        const int a = srcS[t], b = srcW[t];
+        const double *sp = S + static_cast<int64_t>(a < 0 ? 0 : a) * bb;
+        const double *wp = W + static_cast<int64_t>(b < 0 ? 0 : b) * bb;
+        double *o = O + t * bb;
+        for (int e = lane; e < bb; e += 64) {
+            double v;
+            if (a >= 0 && b >= 0) v = sp[e] + wp[e];
+            else if (a >= 0) v = sp[e];
+            else v = wp[e];
+            o[e] = v;
+        }
+    }
+}
+
 // ------------------------------------------------- one-point Galerkin merge
 
 // Keys of K's row i: pmap of RA's row columns (>= 0).  Wave per row.
@@ -1127,8 +1150,12 @@ void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s) {
     k_add_fill<<<grid_for(m, 256), 256, 0, s>>>(S.rowptr.get(), S.colidx.get(), W.rowptr.get(), W.colidx.get(), m,
                                                 O.rowptr.get(), O.colidx.get(), srcS.get(), srcW.get());
     const int64_t total = cap * bs * bs;
-    k_add_values<<<cap_grid((total + 255) / 256), 256, 0, s>>>(O.rowptr.get() + m, bs * bs, S.vals.get(),
-                                                              srcS.get(), W.vals.get(), srcW.get(), O.vals.get());
+    if (bs * bs >= 64)
+        k_add_values_wave<<<cap_grid((cap + 3) / 4), 256, 0, s>>>(O.rowptr.get() + m, bs * bs, S.vals.get(),
+                                                                   srcS.get(), W.vals.get(), srcW.get(), O.vals.get());
+    else
+        k_add_values<<<cap_grid((total + 255) / 256), 256, 0, s>>>(O.rowptr.get() + m, bs * bs, S.vals.get(),
+                                                                  srcS.get(), W.vals.get(), srcW.get(), O.vals.get());
     NAIR_HIP(hipGetLastError());
 }
 
