@@ -48,7 +48,7 @@ def cpu_model():
 
 
 def measured_traffic(workload: str, grid_threads: int):
-    """HBM bytes per launch of the level-0 sweep from the committed counter
+    """HBM bytes per launch of an F sweep, pre-recorded: the committed counter
     summary (FETCH_SIZE and WRITE_SIZE runs per launch shape, scaled by
     reference kernels), or None when there is none for this launch shape or
     the kernel source has changed since it was measured."""
@@ -111,6 +111,31 @@ def relax_level_bytes(lv: dict) -> dict:
     bytes_vec = bytes_e + nF * bs * 8 * 2  # e gathered (each needed entry once), r_F, e_out_F
     return dict(bytes=bytes_A + bytes_D + bytes_idx + bytes_vec, nF=nF, nnzF=nnzF,
                 bytes_true_blocks=bytes_A + bytes_D, sweep_copy=copy)
+
+
+def sweep_launch_shape(lv: dict, nF: int, tuning, level: int):
+    """The F sweep launch on a level as the library issues it: (kernel, lane
+    groups, grid threads).  A face-compressed copy runs k_sweep with G groups of
+    bs lanes per row; a copy stored by nonzero rows with bs >= 8 on a level of
+    32,768 lanes or more runs k_sweep_cr, R = max(1, 512 / (G bs)) rows per
+    256-thread workgroup."""
+    G = int(tuning[level][0]) if tuning is not None and len(tuning) > level else 0
+    if G <= 0:
+        avg_row = lv["nnzb"] / max(1, lv["nb"])
+        G = 1 if avg_row <= 3.5 else (2 if avg_row <= 7.0 else (4 if avg_row <= 14.0 else 8))
+    bs = lv["bs"]
+    while G > 1 and G * bs > 256:
+        G //= 2
+    stored_rows = lv.get("face_meta") is None and lv.get("sweep_nnzb", -1) >= 0
+    if stored_rows and bs >= 8 and nF * bs >= 32768:
+        R = max(1, 512 // (G * bs))
+        return "k_sweep_cr", G, -(-nF // R) * 256
+    rows_per_wg = 256 // (G * bs)
+    return "k_sweep", G, -(-nF // rows_per_wg) * 256
+
+
+def H_level0_fields(H):
+    return H.level(0, fields=("rowptr", "colidx", "cf", "face_meta", "vals"))
 
 
 def host_relres(S, x) -> float:
@@ -374,7 +399,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="dg_q4_512_jitter")
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--roofline-kernel", default="relax")
-    ap.add_argument("--roofline-level", type=int, default=0)
+    ap.add_argument("--roofline-level", type=int, default=1,
+                    help="level of the roofline F sweep (1: the stored-row sweep, the step's dominant kernel)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-hierarchy leg")
     ap.add_argument("--cpu-sample", default="auto",
@@ -520,26 +546,23 @@ def main(argv=None):
     itersT = recs[-1][2].iters
     value = S.n / ((setup_ms + solve_ms) * 1e-3)
 
-    roof = None
-    if args.roofline_kernel == "relax" and launches > 0:
-        rb = relax_level_bytes(lvl)
-        avg_ms = kernel_ms / launches
+    def sweep_roof(level, lv, avg_ms, nlaunch):
+        """Roofline entry of a level's forward F sweep from its average launch time."""
+        rb = relax_level_bytes(lv)
         achieved = rb["bytes"] / (avg_ms * 1e-3) / 1e9
-        # launch shape of the timed kernel: G lane groups of bs lanes per block row, 256-thread workgroups
-        G = int(tuning[args.roofline_level][0]) if tuning is not None and len(tuning) > args.roofline_level else 0
-        if G <= 0:
-            avg_row = lvl["nnzb"] / max(1, lvl["nb"])
-            G = 1 if avg_row <= 3.5 else (2 if avg_row <= 7.0 else (4 if avg_row <= 14.0 else 8))
-        while G > 1 and G * lvl["bs"] > 256:
-            G //= 2
-        rows_per_wg = 256 // (G * lvl["bs"])
-        grid_threads = -(-rb["nF"] // rows_per_wg) * 256
-        roof = {"bound": "hbm", "kernel": f"k_sweep (level {args.roofline_level} F sweep)",
+        name, G, grid_threads = sweep_launch_shape(lv, rb["nF"], tuning, level)
+        return {"bound": "hbm", "kernel": f"{name} (level {level} F sweep)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(args.workload, grid_threads),
+                "traffic_source": "pre-recorded rocprofv3 FETCH_SIZE + WRITE_SIZE of this launch shape "
+                                  "(profiles/), null when the kernel source changed since",
                 "bytes_per_launch": rb["bytes"], "avg_launch_us": round(avg_ms * 1e3, 2),
-                "launches": launches, "lane_groups": G, "grid_threads": grid_threads}
+                "launches": nlaunch, "lane_groups": G, "grid_threads": grid_threads}
+
+    roof = None
+    if args.roofline_kernel == "relax" and launches > 0:
+        roof = sweep_roof(args.roofline_level, lvl, kernel_ms / launches, launches)
 
     Hl = P.Hierarchy(rp, ci, va, S.bs, params)
     P.timer_read()
@@ -548,6 +571,10 @@ def main(argv=None):
     for r in levels_bw:
         log(f"level {r['level']}: relax {r['relax_us']} us {r['relax_GBs']} GB/s, "
             f"restrict {r['restrict_us']} us {r['restrict_GBs']} GB/s")
+    # the finest level's face-compressed sweep, beside the roofline kernel
+    roof0 = None
+    if args.roofline_level != 0 and levels_bw and levels_bw[0].get("relax_us"):
+        roof0 = sweep_roof(0, H_level0_fields(Hl), levels_bw[0]["relax_us"] * 1e-3, None)
 
     rT = recs[-1][2]
     r0 = recs[-1][1]
@@ -584,6 +611,7 @@ def main(argv=None):
         "solve_T_ms": round(float(solveT_ms), 3), "iters": iters, "iters_T": itersT,
         "step": "setup + solve + transposed solve; value = dofs / (setup + solve)",
         "roofline": roof,
+        "roofline_level0_sweep": roof0,
         "convergence": conv,
         "setup_roofline": setup_roof,
         "decision_margin_audit": dict(zip(("theta", "phi", "one_point", "drop"), audit)),

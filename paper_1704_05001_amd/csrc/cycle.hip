@@ -625,6 +625,9 @@ __global__ __launch_bounds__(kThreads) void k_restrict_cr(const int *__restrict_
     const int i0 = blockIdx.x * R;
     if (i0 >= nc) return;   // (the whole workgroup)
     const int i1 = min(nc, i0 + R);
+    // a workgroup whose rows all belong to stopped systems does nothing
+    if (gate.active && !__syncthreads_or(static_cast<int>(threadIdx.x) < i1 - i0 && live(gate, i0 + threadIdx.x)))
+        return;
     const int t0 = zrp[i0], t1 = zrp[i1];
     const MT *vals = RB ? zr.vals : zval;
     auto first_row = [&](int t) { return RB ? zr.off[t] / bs : t * bs; };
@@ -698,6 +701,10 @@ __global__ __launch_bounds__(kThreads) void k_sweep_cr(SweepView<MT> S, const in
     const int f0 = blockIdx.x * R;
     if (f0 >= nF) return;   // (the whole workgroup)
     const int f1 = min(nF, f0 + R);
+    // a workgroup whose rows all belong to stopped systems does nothing
+    if (gate.active &&
+        !__syncthreads_or(static_cast<int>(threadIdx.x) < f1 - f0 && live(gate, flist[f0 + threadIdx.x])))
+        return;
     const int t0 = S.rowptr[f0], t1 = S.rowptr[f1];
     const RowBlockView<MT> &RB = S.rows;
     const int q0 = RB.off[t0] / bs, q1 = RB.off[t1] / bs;
