@@ -1208,13 +1208,13 @@ void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int 
         if (fused) {
             const unsigned mgrid = static_cast<unsigned>((static_cast<int64_t>(nnz) + 3) / 4);
             if (bs == 9)
-                k_galerkin_mfma<9><<<mgrid, 256, 0, s>>>(nnz, kptr.get(), klist.get(), P.pairptr.get(),
+                k_galerkin_lds<9><<<mgrid, 256, 0, s>>>(nnz, kptr.get(), klist.get(), P.pairptr.get(),
+                                                        P.pairs.get(), Z.vals.get(), A.vals.get(), kval.get(),
+                                                        knorm.get(), kbits.get());
+            else if (bs == 16)
+                k_galerkin_lds<16><<<mgrid, 256, 0, s>>>(nnz, kptr.get(), klist.get(), P.pairptr.get(),
                                                          P.pairs.get(), Z.vals.get(), A.vals.get(), kval.get(),
                                                          knorm.get(), kbits.get());
-            else if (bs == 16)
-                k_galerkin_mfma<16><<<mgrid, 256, 0, s>>>(nnz, kptr.get(), klist.get(), P.pairptr.get(),
-                                                          P.pairs.get(), Z.vals.get(), A.vals.get(), kval.get(),
-                                                          knorm.get(), kbits.get());
             else
                 k_galerkin_lds<25><<<mgrid, 256, 0, s>>>(nnz, kptr.get(), klist.get(), P.pairptr.get(),
                                                          P.pairs.get(), Z.vals.get(), A.vals.get(), kval.get(),
