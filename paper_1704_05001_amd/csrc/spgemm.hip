@@ -12,6 +12,8 @@
 // applied in list order by the one wave or thread that owns the block.
 #include <algorithm>
 
+#include <climits>
+
 #include "common.h"
 #include "mfma_tile.h"
 
@@ -21,6 +23,48 @@ namespace nair {
 namespace {
 
 constexpr int kWave = 64;
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sort a wave's n distinct keys list[0 .. n) ascending in place (n <= cap, the
+// list's room): up to 64 keys by rank (a key per lane), more by a bitonic
+// network over the next power of two, padded with INT_MAX.
+__device__ inline void wave_sort(int *list, int n, int cap, int lane) {
+    if (n <= kWave) {
+        const int k = lane < n ? list[lane] : 0;
+        int r = 0;
+        if (lane < n)
+            for (int b = 0; b < n; ++b) r += (list[b] < k) ? 1 : 0;
+        wave_sync();
+        if (lane < n) list[r] = k;
+        wave_sync();
+        return;
+    }
+    int n2 = kWave;
+    while (n2 < n) n2 <<= 1;
+    if (n2 > cap) n2 = cap;   // (n <= cap, a power of two)
+    for (int a = n + lane; a < n2; a += kWave) list[a] = INT_MAX;
+    wave_sync();
+    for (int k = 2; k <= n2; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int a = lane; a < n2; a += kWave) {
+                const int b = a ^ j;
+                if (b > a) {
+                    const int x = list[a], y = list[b];
+                    if ((x > y) == ((a & k) == 0)) {
+                        list[a] = y;
+                        list[b] = x;
+                    }
+                }
+            }
+            wave_sync();
+        }
+}
+
 constexpr int kEmpty = -1;
 
 __device__ inline bool hash_insert(int *table, int mask, int key) {
@@ -242,14 +286,14 @@ __global__ __launch_bounds__(256) void k_rap_symbolic(const int *__restrict__ ra
             while (slots < 2 * (rarp[i + 1] - rarp[i])) slots <<= 1;
         for (int s = lane; s < slots; s += kWave) table[s] = kEmpty;
         if (lane == 0) counts[w] = 0;
-        __syncthreads();
+        wave_sync();   // (every LDS array here is the wave's own)
         int added = 0;
         if (active)
             for (int u = rarp[i] + lane; u < rarp[i + 1]; u += kWave) {
                 const int t = pmap[racol[u]];
                 if (t >= 0) added += hash_insert(table, slots - 1, t) ? 1 : 0;
             }
-        __syncthreads();
+        wave_sync();
         if (mode == 0) {
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) added += __shfl_xor(added, o, kWave);
@@ -260,17 +304,13 @@ __global__ __launch_bounds__(256) void k_rap_symbolic(const int *__restrict__ ra
                 const int k = table[s];
                 if (active && k != kEmpty) list[atomicAdd(&counts[w], 1)] = k;
             }
-            __syncthreads();
+            wave_sync();
             const int n = active ? counts[w] : 0;
             int *dst = active ? kcol + krp[i] : nullptr;
-            for (int a = lane; a < n; a += kWave) {
-                const int k = list[a];
-                int r = 0;
-                for (int b = 0; b < n; ++b) r += (list[b] < k) ? 1 : 0;
-                dst[r] = k;
-            }
+            wave_sort(list, n, kHashSmall / 2, lane);
+            for (int a = lane; a < n; a += kWave) dst[a] = list[a];
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -385,12 +425,6 @@ __global__ __launch_bounds__(256) void k_pairs_large(const int *__restrict__ xro
 
 // Intra-wave ordering of LDS traffic (the rows of k_symbolic_flat are per
 // wave and take different numbers of steps, so no workgroup barrier fits).
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Up to 64 inner slots of output row i, one per lane: slot base + lane of the
 // row's sorted inner indices (X's row with its implicit identity block merged
 // in at its column).  A lane holds its slot's X block (-1: the identity), the
@@ -470,7 +504,7 @@ __global__ __launch_bounds__(256) void k_symbolic_flat(const int *__restrict__ x
             while (slots < 2 * ub[i]) slots <<= 1;
         for (int t = lane; t < slots; t += kWave) table[t] = kEmpty;
         if (lane == 0) counts[w] = 0;
-        __syncthreads();
+        wave_sync();   // (every LDS array here is the wave's own)
         int q0 = 0, nk = 0, dslot = -1, dcol = 0;
         if (active) {
             q0 = xrowptr[i];
@@ -491,7 +525,7 @@ __global__ __launch_bounds__(256) void k_symbolic_flat(const int *__restrict__ x
                 if (p < c.total) added += hash_insert(table, slots - 1, ycol[pr.y]) ? 1 : 0;
             }
         }
-        __syncthreads();
+        wave_sync();
         if (mode == 0) {
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) added += __shfl_xor(added, o, kWave);
@@ -501,18 +535,16 @@ __global__ __launch_bounds__(256) void k_symbolic_flat(const int *__restrict__ x
                 const int k = table[t];
                 if (active && k != kEmpty) list[atomicAdd(&counts[w], 1)] = k;
             }
-            __syncthreads();
+            wave_sync();
             const int n = active ? counts[w] : 0;
             // the sorted columns go to ccol and to the table's first n slots
             int *sorted = table;
             int *off = table + kHashSmall / 2;
             const int c0 = active ? crowptr[i] : 0;
+            wave_sort(list, n, kHashSmall / 2, lane);
             for (int a = lane; a < n; a += kWave) {
-                const int k = list[a];
-                int r = 0;
-                for (int b = 0; b < n; ++b) r += (list[b] < k) ? 1 : 0;
-                sorted[r] = k;
-                ccol[c0 + r] = k;
+                sorted[a] = list[a];
+                ccol[c0 + a] = list[a];
             }
             for (int a = lane; a < n; a += kWave) off[a] = 0;
             wave_sync();
@@ -561,7 +593,7 @@ __global__ __launch_bounds__(256) void k_symbolic_flat(const int *__restrict__ x
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
