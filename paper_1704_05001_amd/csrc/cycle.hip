@@ -112,9 +112,34 @@ __device__ inline double row_part(const int *__restrict__ colidx, const MT *__re
 // entries left out are exact zeros and every product kept goes to the
 // accumulator row_part gives it (column parity), in the same order, so for
 // finite x the result equals row_part's bit for bit.
-template <int BS, typename MT, typename VT, bool SKIP = false>
+// The diagonal block's part of row_part_face (column-major dvals), for a
+// caller that loads it before the row's other blocks.
+template <int BS, typename MT, typename VT>
+__device__ inline double face_diag_dot(const FaceView<MT> &F, int I, int a, int bs_rt, const VT *__restrict__ x) {
+    const int bs = Bs<BS>::get(bs_rt);
+    const MT *blk = F.dvals + static_cast<int64_t>(I) * bs * bs + a;
+    const VT *xj = x + static_cast<int64_t>(I) * bs;
+    double p0 = 0.0, p1 = 0.0;
+    if constexpr (BS > 0) {
+#pragma unroll
+        for (int c = 0; c < BS; c += 2) {
+            p0 += static_cast<double>(blk[c * BS]) * static_cast<double>(xj[c]);
+            if (c + 1 < BS) p1 += static_cast<double>(blk[(c + 1) * BS]) * static_cast<double>(xj[c + 1]);
+        }
+    } else {
+        for (int c = 0; c < bs; c += 2) {
+            p0 += static_cast<double>(blk[c * bs]) * static_cast<double>(xj[c]);
+            if (c + 1 < bs) p1 += static_cast<double>(blk[(c + 1) * bs]) * static_cast<double>(xj[c + 1]);
+        }
+    }
+    return p0 + p1;
+}
+
+// (PRE: the diagonal block's part is given as `pre`, added at its place in block
+// order; NODIAG: the blocks hold no diagonal block, as in a sweep copy)
+template <int BS, typename MT, typename VT, bool SKIP = false, bool PRE = false, bool NODIAG = false>
 __device__ inline double row_part_face(const int *__restrict__ colidx, const FaceView<MT> &F, int lo, int hi, int g,
-                                       int G, int a, int I, int bs_rt, const VT *__restrict__ x) {
+                                       int G, int a, int I, int bs_rt, const VT *__restrict__ x, double pre = 0.0) {
     const int bs = Bs<BS>::get(bs_rt);
     const int64_t bb = static_cast<int64_t>(bs) * bs;
     double acc = 0.0;
@@ -132,28 +157,15 @@ __device__ inline double row_part_face(const int *__restrict__ colidx, const Fac
             mn = F.meta[tn];
         }
         const VT *xj = x + static_cast<int64_t>(J) * bs;
-        if (J == I) {
+        if (!NODIAG && J == I) {
             if constexpr (SKIP) {
                 if (tn >= hi) break;
                 J = Jn;
                 m = mn;
                 continue;
             }
-            const MT *blk = F.dvals + static_cast<int64_t>(I) * bb + a;   // by columns
-            double p0 = 0.0, p1 = 0.0;
-            if constexpr (BS > 0) {
-#pragma unroll
-                for (int c = 0; c < BS; c += 2) {
-                    p0 += static_cast<double>(blk[c * BS]) * static_cast<double>(xj[c]);
-                    if (c + 1 < BS) p1 += static_cast<double>(blk[(c + 1) * BS]) * static_cast<double>(xj[c + 1]);
-                }
-            } else {
-                for (int c = 0; c < bs; c += 2) {
-                    p0 += static_cast<double>(blk[c * bs]) * static_cast<double>(xj[c]);
-                    if (c + 1 < bs) p1 += static_cast<double>(blk[(c + 1) * bs]) * static_cast<double>(xj[c + 1]);
-                }
-            }
-            acc += p0 + p1;
+            if constexpr (PRE) acc += pre;
+            else acc += face_diag_dot<BS, MT, VT>(F, I, a, bs, x);
         } else {
             const uint32_t rm = static_cast<uint32_t>(m);
             if ((rm >> a) & 1u) {
@@ -370,8 +382,18 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int *__restrict__ r
     const bool act = L.valid && I < nb && live(gate, I);
     const int64_t o = static_cast<int64_t>(I) * bs + L.a;
     const double bv = (act && L.g == 0 && b) ? static_cast<double>(b[o]) : 0.0;   // loads during the product
-    double acc = act ? row_product<BS, FACE>(colidx, vals, face, rowptr[I], rowptr[I + 1], L.g, G, L.a, I, bs, x)
-                     : 0.0;
+    double acc = 0.0;
+    if constexpr (FACE) {
+        if (act && G == 1) {   // the diagonal block (most of the row's bytes) loads first, at a known place
+            const double pd = face_diag_dot<BS, MT, VT>(face, I, L.a, bs, x);
+            acc = row_part_face<BS, MT, VT, false, true>(colidx, face, rowptr[I], rowptr[I + 1], 0, 1, L.a, I, bs, x,
+                                                         pd);
+        } else if (act) {
+            acc = row_part_face<BS, MT, VT>(colidx, face, rowptr[I], rowptr[I + 1], L.g, G, L.a, I, bs, x);
+        }
+    } else {
+        acc = act ? row_product<BS, FACE>(colidx, vals, face, rowptr[I], rowptr[I + 1], L.g, G, L.a, I, bs, x) : 0.0;
+    }
     acc = reduce_groups(acc, L, G, bs, part);
     if (act && L.g == 0) {
         const double rv = b ? bv - acc : acc;
@@ -460,8 +482,8 @@ __device__ inline void sweep_rows(const SweepView<MT> &S, const int *__restrict_
     if (I >= 0) {
         const int lo = S.rowptr[f], hi = S.rowptr[f + 1];
         if constexpr (FACE)
-            acc = row_part_face<BS, MT, VT>(S.colidx, FaceView<MT>{S.meta, S.vals, nullptr, S.cmax, S.rc}, lo, hi,
-                                            L.g, G, L.a, -1, bs, ein);
+            acc = row_part_face<BS, MT, VT, false, false, true>(
+                S.colidx, FaceView<MT>{S.meta, S.vals, nullptr, S.cmax, S.rc}, lo, hi, L.g, G, L.a, -1, bs, ein);
         else
             acc = row_part_rows<BS, MT, VT>(S.colidx, S.rows, lo, hi, L.g, G, L.a, bs, ein);
     }
@@ -613,6 +635,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict(const int *__restrict__ z
 // parity as the row products are); (3) output lane (i, a) adds the products of
 // row i's blocks that store row a, in block order, to its total.
 constexpr int kCrCap = 1024;
+constexpr int kCrBlk = 512;   // blocks of a workgroup whose row masks and first rows are staged in LDS
 
 template <int BS, typename MT, typename VT, bool RB>
 __global__ __launch_bounds__(kThreads) void k_restrict_cr(const int *__restrict__ zrp, const int *__restrict__ zcol,
@@ -621,6 +644,9 @@ __global__ __launch_bounds__(kThreads) void k_restrict_cr(const int *__restrict_
                                                          VT *__restrict__ rc, Gate gate, RowBlockView<MT> zr) {
     __shared__ double dot[kCrCap];
     __shared__ int qcol[kCrCap];
+    __shared__ uint32_t bmask[kCrBlk];
+    __shared__ int bq[kCrBlk + 1];
+    __shared__ int rowb[2 * kThreads / 8 + 1];
     const int bs = Bs<BS>::get(bs_rt);
     const int i0 = blockIdx.x * R;
     if (i0 >= nc) return;   // (the whole workgroup)
@@ -630,9 +656,29 @@ __global__ __launch_bounds__(kThreads) void k_restrict_cr(const int *__restrict_
         return;
     const int t0 = zrp[i0], t1 = zrp[i1];
     const MT *vals = RB ? zr.vals : zval;
-    auto first_row = [&](int t) { return RB ? zr.off[t] / bs : t * bs; };
-    const int q0 = first_row(t0), q1 = first_row(t1);
+    auto first_row_g = [&](int t) { return RB ? zr.off[t] / bs : t * bs; };
+    // the rows' block ranges and (when few enough) the blocks' masks and first stored rows, in LDS
+    const bool staged = t1 - t0 <= kCrBlk;
+    for (int k = threadIdx.x; k <= i1 - i0; k += kThreads) rowb[k] = zrp[i0 + k];
+    if (staged)
+        for (int t = t0 + static_cast<int>(threadIdx.x); t <= t1; t += kThreads) {
+            bq[t - t0] = first_row_g(t);
+            if (RB && t < t1) bmask[t - t0] = zr.mask[t];
+        }
     const int nout = (i1 - i0) * bs;   // <= 2 kThreads (host)
+    // r_C loads while the products run
+    double rv[2] = {0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int k = static_cast<int>(threadIdx.x) + j * kThreads;
+        if (k < nout) {
+            const int i = i0 + k / bs, a = k - (k / bs) * bs;
+            rv[j] = static_cast<double>(r[static_cast<int64_t>(cpts[i]) * bs + a]);
+        }
+    }
+    __syncthreads();
+    auto first_row = [&](int t) { return staged ? bq[t - t0] : first_row_g(t); };
+    const int q0 = first_row(t0), q1 = first_row(t1);
     double acc[2] = {0.0, 0.0};
     for (int qc = q0; qc < q1; qc += kCrCap) {
         const int qe = min(q1, qc + kCrCap);
@@ -652,14 +698,14 @@ __global__ __launch_bounds__(kThreads) void k_restrict_cr(const int *__restrict_
         for (int j = 0; j < 2; ++j) {
             const int k = static_cast<int>(threadIdx.x) + j * kThreads;
             if (k < nout) {
-                const int i = i0 + k / bs, a = k - (k / bs) * bs;
-                const int hi = zrp[i + 1];
-                for (int t = zrp[i]; t < hi; ++t) {
+                const int il = k / bs, a = k - (k / bs) * bs;
+                const int hi = rowb[il + 1];
+                for (int t = rowb[il]; t < hi; ++t) {
                     int q;
                     if constexpr (RB) {
-                        const uint32_t m = zr.mask[t];
+                        const uint32_t m = staged ? bmask[t - t0] : zr.mask[t];
                         if (!((m >> a) & 1u)) continue;
-                        q = zr.off[t] / bs + __popc(m & ((1u << a) - 1u));
+                        q = first_row(t) + __popc(m & ((1u << a) - 1u));
                     } else {
                         q = t * bs + a;
                     }
@@ -674,10 +720,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict_cr(const int *__restrict_
         const int k = static_cast<int>(threadIdx.x) + j * kThreads;
         if (k < nout) {
             const int i = i0 + k / bs, a = k - (k / bs) * bs;
-            if (live(gate, i)) {
-                const double rv = static_cast<double>(r[static_cast<int64_t>(cpts[i]) * bs + a]);
-                rc[static_cast<int64_t>(i) * bs + a] = static_cast<VT>(rv + acc[j]);
-            }
+            if (live(gate, i)) rc[static_cast<int64_t>(i) * bs + a] = static_cast<VT>(rv[j] + acc[j]);
         }
     }
 }
@@ -697,6 +740,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep_cr(SweepView<MT> S, const in
     __shared__ double dot[kCrCap];
     __shared__ int qcol[kCrCap];
     __shared__ double tb[2 * kThreads];
+    __shared__ uint32_t bmask[kCrBlk];
+    __shared__ int bq[kCrBlk + 1];
+    __shared__ int rowb[2 * kThreads / 8 + 1];
     const int bs = Bs<BS>::get(bs_rt);
     const int f0 = blockIdx.x * R;
     if (f0 >= nF) return;   // (the whole workgroup)
@@ -707,13 +753,30 @@ __global__ __launch_bounds__(kThreads) void k_sweep_cr(SweepView<MT> S, const in
         return;
     const int t0 = S.rowptr[f0], t1 = S.rowptr[f1];
     const RowBlockView<MT> &RB = S.rows;
-    const int q0 = RB.off[t0] / bs, q1 = RB.off[t1] / bs;
+    // the rows' block ranges and (when few enough) the blocks' masks and first stored rows, in LDS
+    const bool staged = t1 - t0 <= kCrBlk;
+    for (int k = threadIdx.x; k <= f1 - f0; k += kThreads) rowb[k] = S.rowptr[f0 + k];
+    if (staged)
+        for (int t = t0 + static_cast<int>(threadIdx.x); t <= t1; t += kThreads) {
+            bq[t - t0] = RB.off[t] / bs;
+            if (t < t1) bmask[t - t0] = RB.mask[t];
+        }
     const int nout = (f1 - f0) * bs;   // <= 2 kThreads (host)
+    // r_I loads while the products run
+    double rv[2] = {0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int k = static_cast<int>(threadIdx.x) + j * kThreads;
+        if (k < nout) rv[j] = static_cast<double>(r[static_cast<int64_t>(flist[f0 + k / bs]) * bs + (k - (k / bs) * bs)]);
+    }
+    __syncthreads();
+    auto first_row = [&](int t) { return staged ? bq[t - t0] : RB.off[t] / bs; };
+    const int q0 = first_row(t0), q1 = first_row(t1);
     double acc[2] = {0.0, 0.0};
     for (int qc = q0; qc < q1; qc += kCrCap) {
         const int qe = min(q1, qc + kCrCap);
         for (int t = t0 + static_cast<int>(threadIdx.x); t < t1; t += kThreads) {
-            const int lo = max(RB.off[t] / bs, qc), hi = min(RB.off[t + 1] / bs, qe);
+            const int lo = max(first_row(t), qc), hi = min(first_row(t + 1), qe);
             if (lo < hi) {
                 const int J = S.colidx[t];
                 for (int q = lo; q < hi; ++q) qcol[q - qc] = J;
@@ -728,12 +791,12 @@ __global__ __launch_bounds__(kThreads) void k_sweep_cr(SweepView<MT> S, const in
         for (int j = 0; j < 2; ++j) {
             const int k = static_cast<int>(threadIdx.x) + j * kThreads;
             if (k < nout) {
-                const int f = f0 + k / bs, a = k - (k / bs) * bs;
-                const int hi = S.rowptr[f + 1];
-                for (int t = S.rowptr[f]; t < hi; ++t) {
-                    const uint32_t m = RB.mask[t];
+                const int fl = k / bs, a = k - (k / bs) * bs;
+                const int hi = rowb[fl + 1];
+                for (int t = rowb[fl]; t < hi; ++t) {
+                    const uint32_t m = staged ? bmask[t - t0] : RB.mask[t];
                     if (!((m >> a) & 1u)) continue;
-                    const int q = RB.off[t] / bs + __popc(m & ((1u << a) - 1u));
+                    const int q = first_row(t) + __popc(m & ((1u << a) - 1u));
                     if (q >= qc && q < qe) acc[j] += dot[q - qc];
                 }
             }
@@ -743,10 +806,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_cr(SweepView<MT> S, const in
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int k = static_cast<int>(threadIdx.x) + j * kThreads;
-        if (k < nout) {
-            const int I = flist[f0 + k / bs], a = k - (k / bs) * bs;
-            tb[k] = static_cast<double>(r[static_cast<int64_t>(I) * bs + a]) - acc[j];
-        }
+        if (k < nout) tb[k] = rv[j] - acc[j];
     }
     __syncthreads();
 #pragma unroll
