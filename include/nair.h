@@ -47,6 +47,23 @@ typedef enum {
 
 typedef struct nair_hier_s *nair_hier;
 
+/*
+ * Device memory from the caller (for instance torch's caching allocator), in
+ * place of the library's own caching pool.  alloc returns `bytes` of device
+ * memory on the handle's device for use on `stream` (the stream of the call
+ * that needs it), or NULL on failure (the call then returns NAIR_ENOMEM);
+ * free returns a block alloc gave.  Every device buffer of a handle set up with
+ * it -- the hierarchy, its copies, the solve's vectors and temporaries -- comes
+ * from it, during nair_setup and during later calls on the handle, and goes
+ * back to it by nair_destroy at the latest.  The struct is copied at setup;
+ * alloc, free and ctx must stay valid until nair_destroy returns.
+ */
+typedef struct nair_allocator {
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, void *stream, void *ctx);
+    void *ctx;
+} nair_allocator;
+
 /* Setup parameters (section 5.1 and 5.2 of the paper for the defaults). */
 typedef struct {
     int32_t degree;           /* Neumann degree k >= 0 of the restriction (section 4.1);
@@ -108,6 +125,8 @@ typedef struct {
                                  units.  Both evaluate every entry as the fma chain over the inner
                                  index in ascending order, so the hierarchies are identical (a zero
                                  may differ in sign); 0 is the reference for that check. */
+    const nair_allocator *allocator; /* optional, host: device memory from the caller (copied at
+                                 setup); NULL (default): the library's caching pool */
 } nair_params;
 
 typedef struct {

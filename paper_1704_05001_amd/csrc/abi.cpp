@@ -4,11 +4,13 @@
 #include <exception>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "hier.h"
 
 struct nair_hier_s {
+    nair::ExtAlloc ext;   // (declared before h: h's buffers go back to it when h is destroyed)
     nair::Hier h;
 };
 
@@ -28,7 +30,9 @@ struct DeviceGuard {
 };
 
 template <typename F>
-nair_status guarded(nair_hier h, F &&body) {
+nair_status guarded_on(nair_hier h, void *stream, F &&body) {
+    // device memory from the handle's allocator, if it has one, for use on the call's stream
+    nair::AllocScope scope(h && h->ext.on ? &h->ext : nullptr, stream);
     try {
         return body();
     } catch (const nair::Error &e) {
@@ -44,6 +48,11 @@ nair_status guarded(nair_hier h, F &&body) {
         if (h) h->h.err = g_last_error;
         return NAIR_EDEVICE;
     }
+}
+
+template <typename F>
+nair_status guarded(nair_hier h, F &&body) {
+    return guarded_on(h, nullptr, std::forward<F>(body));
 }
 
 nair_status bad(nair_hier h, const std::string &msg) {
@@ -77,6 +86,7 @@ nair_status nair_default_params(nair_params *p) {
     p->faces = 1;
     p->sweep_copy = -1;
     p->matrix_cores = 1;
+    p->allocator = nullptr;
     return NAIR_OK;
 }
 
@@ -107,10 +117,16 @@ static nair_status setup_common(int32_t nsys, const int32_t *sys_nb, int32_t nb,
     if (p->max_levels < 1 || p->max_levels > nair::kMaxLevels) return bad(nullptr, "max_levels must be in [1, 64]");
     if (p->max_coarse_dofs < 0 || p->max_coarse_dofs > nair::kStallDenseDofs)
         return bad(nullptr, "max_coarse_dofs must be in [0, 4096]");
+    if (p->allocator && (!p->allocator->alloc || !p->allocator->free))
+        return bad(nullptr, "allocator needs both alloc and free");
     nair_hier h = new (std::nothrow) nair_hier_s();
     if (!h) return NAIR_ENOMEM;
+    if (p->allocator) {
+        h->ext.on = true;
+        h->ext.a = *p->allocator;
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    nair_status st = guarded(h, [&]() -> nair_status {
+    nair_status st = guarded_on(h, stream, [&]() -> nair_status {
         NAIR_HIP(hipGetDevice(&h->h.device));
         h->h.prm = *p;
         nair::g_matrix_cores = p->matrix_cores != 0;
@@ -121,6 +137,7 @@ static nair_status setup_common(int32_t nsys, const int32_t *sys_nb, int32_t nb,
         if (p->tuning) nair::apply_tuning(h->h, p->tuning);
         h->h.prm.cf_override_host = nullptr;   // host pointers not kept past the call
         h->h.prm.tuning = nullptr;
+        h->h.prm.allocator = nullptr;          // (copied into the handle)
         return NAIR_OK;
     });
     if (st != NAIR_OK) {
@@ -162,7 +179,7 @@ static nair_status solve_common(nair_hier h, bool trans, const double *b, double
     if (h->h.nsys != 1) return bad(h, "the handle holds several systems: use nair_solve_batch");
     DeviceGuard dg(h->h.device);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return guarded(h, [&]() { return nair::run_solve(h->h, trans, b, x, rtol, max_iter, res, s); });
+    return guarded_on(h, stream, [&]() { return nair::run_solve(h->h, trans, b, x, rtol, max_iter, res, s); });
 }
 
 nair_status nair_solve_batch(nair_hier h, int32_t trans, const double *b, double *x, double rtol, int32_t max_iter,
@@ -174,7 +191,7 @@ nair_status nair_solve_batch(nair_hier h, int32_t trans, const double *b, double
     if (h->h.prm.gmres > 0) return bad(h, "GMRES acceleration solves one system: use nair_solve / nair_solve_T");
     DeviceGuard dg(h->h.device);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return guarded(h, [&]() {
+    return guarded_on(h, stream, [&]() {
         return nair::run_solve_batch(h->h, trans != 0, b, x, rtol, max_iter, use_graph != 0, res, s);
     });
 }
@@ -183,7 +200,7 @@ nair_status nair_autotune(nair_hier h, int32_t reps, int8_t *table, void *stream
     if (!h) return bad(nullptr, "handle is NULL");
     if (reps < 1 || reps > 10000) return bad(h, "reps must be in [1, 10000]");
     DeviceGuard dg(h->h.device);
-    return guarded(h, [&]() {
+    return guarded_on(h, stream, [&]() {
         nair::autotune(h->h, reps, table, static_cast<hipStream_t>(stream));
         return NAIR_OK;
     });
@@ -246,7 +263,7 @@ static nair_status vcycle_common(nair_hier h, bool trans, const double *r, doubl
     if (!r || !e) return bad(h, "NULL vector");
     DeviceGuard dg(h->h.device);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return guarded(h, [&]() {
+    return guarded_on(h, stream, [&]() {
         nair::run_vcycle(h->h, trans, r, e, s);
         return NAIR_OK;
     });
@@ -347,7 +364,7 @@ const char *nair_last_error(nair_hier h) { return h ? h->h.err.c_str() : g_last_
 void nair_destroy(nair_hier h) {
     if (!h) return;
     DeviceGuard dg(h->h.device);
-    delete h;
+    delete h;   // (buffers from a caller's allocator go back to it, by pointer, as h->h is destroyed)
 }
 
 nair_status nair_timer_select(int32_t kernel, int32_t level) {

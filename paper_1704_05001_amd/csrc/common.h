@@ -37,6 +37,20 @@ void check_hip(hipError_t e, const char *what);
 void *pool_alloc(size_t bytes);
 void pool_free(void *p);
 void pool_trim();
+// A handle's caller-supplied allocator (nair_allocator).  While an AllocScope
+// names one on a thread, pool_alloc takes device memory from it (for use on
+// the scope's stream) instead of the pool; pool_free returns every block to
+// where it came from, whatever scope is active then.
+struct ExtAlloc {
+    bool on = false;
+    nair_allocator a{};
+};
+struct AllocScope {
+    const ExtAlloc *prev;
+    void *prev_stream;
+    AllocScope(const ExtAlloc *e, void *stream);
+    ~AllocScope();
+};
 
 template <typename T>
 struct DBuf {

@@ -37,7 +37,11 @@ struct Pool {
     std::mutex mu;
     std::unordered_map<void *, std::pair<int, size_t>> live;         // ptr -> (device, class)
     std::map<std::pair<int, size_t>, std::vector<void *>> free_list;  // (device, class) -> ptrs
+    std::unordered_map<void *, std::pair<const ExtAlloc *, void *>> ext_live;   // caller's blocks -> (allocator, stream)
 };
+
+thread_local const ExtAlloc *g_ext = nullptr;
+thread_local void *g_ext_stream = nullptr;
 
 Pool &pool() {
     static Pool *p = new Pool();   // never destroyed: frees at exit would race the runtime teardown
@@ -46,7 +50,26 @@ Pool &pool() {
 
 }  // namespace
 
+AllocScope::AllocScope(const ExtAlloc *e, void *stream) : prev(g_ext), prev_stream(g_ext_stream) {
+    g_ext = e;
+    g_ext_stream = stream;
+}
+
+AllocScope::~AllocScope() {
+    g_ext = prev;
+    g_ext_stream = prev_stream;
+}
+
 void *pool_alloc(size_t bytes) {
+    if (g_ext) {   // the handle's caller-supplied allocator
+        const size_t n = bytes ? bytes : 1;
+        void *p = g_ext->a.alloc(n, g_ext_stream, g_ext->a.ctx);
+        if (!p) fail(NAIR_ENOMEM, "the caller's allocator returned no memory for " + std::to_string(n) + " bytes");
+        Pool &P = pool();
+        std::lock_guard<std::mutex> lk(P.mu);
+        P.ext_live[p] = {g_ext, g_ext_stream};
+        return p;
+    }
     int dev = 0;
     NAIR_HIP(hipGetDevice(&dev));
     size_t cls = size_class(bytes ? bytes : 1);
@@ -81,7 +104,16 @@ void *pool_alloc(size_t bytes) {
 void pool_free(void *p) {
     if (!p) return;
     Pool &P = pool();
-    std::lock_guard<std::mutex> lk(P.mu);
+    std::unique_lock<std::mutex> lk(P.mu);
+    auto xt = P.ext_live.find(p);
+    if (xt != P.ext_live.end()) {
+        const ExtAlloc *e = xt->second.first;
+        void *stream = xt->second.second;
+        P.ext_live.erase(xt);
+        lk.unlock();
+        e->a.free(p, stream, e->a.ctx);
+        return;
+    }
     auto it = P.live.find(p);
     if (it == P.live.end()) return;
     P.free_list[it->second].push_back(p);

@@ -45,7 +45,37 @@ class _Params(C.Structure):
                 ("max_coarse_dofs", C.c_int32), ("seed", C.c_uint64),
                 ("cf_override_host", C.c_void_p), ("precision", C.c_int32), ("tuning", C.c_void_p),
                 ("form", C.c_int32), ("cycle", C.c_int32), ("gmres", C.c_int32), ("faces", C.c_int32),
-                ("sweep_copy", C.c_int32), ("matrix_cores", C.c_int32)]
+                ("sweep_copy", C.c_int32), ("matrix_cores", C.c_int32), ("allocator", C.c_void_p)]
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class _Allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
+
+
+def _torch_allocator(device):
+    """nair_allocator callbacks on torch's caching allocator (device memory for
+    the library's buffers; torch counts it in memory_allocated).  The returned
+    objects must outlive the handle."""
+    import torch
+    dev = torch.device(device).index or 0
+
+    def alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream or 0))
+        except Exception:
+            return None   # (the library reports NAIR_ENOMEM)
+
+    def free(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a = _Allocator()
+    keep = (_ALLOC_FN(alloc), _FREE_FN(free))
+    a.alloc, a.free, a.ctx = keep[0], keep[1], None
+    return a, keep
 
 
 class _Result(C.Structure):
@@ -214,6 +244,7 @@ class Params:
     faces: bool = True           # compact copy of the finest operator's face blocks for the cycle
     sweep_copy: str = "auto"     # F rows in F order for the sweeps: "auto" (large levels), "off", "all"
     matrix_cores: bool = True    # setup block products of 9x9/16x16/25x25 blocks on the FP64 matrix cores
+    allocator: str = "pool"      # device memory: "pool" (the library's caching pool) or "torch" (torch's caching allocator)
 
 
 @dataclass
@@ -236,6 +267,8 @@ class Hierarchy:
                  sys_nb=None):
         import torch
         params = params or Params()
+        if params.allocator not in ("pool", "torch"):
+            raise ValueError("allocator must be 'pool' or 'torch'")
         _check_pattern(rowptr, colidx, vals, bs)
         L = lib()
         self.nb = rowptr.numel() - 1
@@ -262,6 +295,11 @@ class Hierarchy:
             raise ValueError("sweep_copy must be 'auto', 'off' or 'all'")
         p.sweep_copy = {"auto": -1, "off": 0, "all": 1}[params.sweep_copy]
         p.matrix_cores = 1 if params.matrix_cores else 0
+        self._alloc_keep = None   # the callbacks stay alive as long as the handle
+        if params.allocator == "torch":
+            alloc, keep = _torch_allocator(self.device)
+            self._alloc_keep = (alloc, keep)
+            p.allocator = C.addressof(alloc)
         cf = None
         if params.cf_override is not None:
             cf = np.ascontiguousarray(params.cf_override, dtype=np.int8)
@@ -295,8 +333,9 @@ class Hierarchy:
     def close(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib().nair_destroy(h)
+            lib().nair_destroy(h)   # (returns its buffers to the allocator, whose callbacks are still held)
         self._h = None
+        self._alloc_keep = None
 
     def __del__(self):
         try:

@@ -45,6 +45,25 @@ def test_binding_names_match_header():
         assert hasattr(L, f)
 
 
+def test_allocator_field_defaults_to_the_pool():
+    import ctypes as C
+    import paper_1704_05001_amd as P
+    from paper_1704_05001_amd import nair as N
+    p = N._Params()
+    assert P.lib().nair_default_params(C.byref(p)) == 0
+    assert p.allocator is None
+    src = open(os.path.join(ROOT, "include", "nair.h")).read()
+    assert "const nair_allocator *allocator;" in src and "typedef struct nair_allocator" in src
+    with pytest.raises(ValueError, match="allocator"):
+        P.Hierarchy.__init__(object.__new__(P.Hierarchy), *_tiny_pattern(), 1, P.Params(allocator="bogus"))
+
+
+def _tiny_pattern():
+    import torch
+    return (torch.tensor([0, 1], dtype=torch.int32), torch.tensor([0], dtype=torch.int32),
+            torch.ones(1, dtype=torch.float64))
+
+
 def test_noalloc_scratch_size_matches_header():
     import paper_1704_05001_amd as P
     src = open(os.path.join(ROOT, "include", "nair.h")).read()

@@ -205,11 +205,12 @@ def test_batch_rejects_coupled_systems():
 
 def test_batch_full_size_angles():
     """The 64-angle uneven-mesh workload (17.7M DOFs): FP64 and FP32-stored
-    hierarchies, every system converged; the first two systems (64^2 and
-    128^2 meshes) and one 256^2 system against their own oracle hierarchies."""
+    hierarchies, every system converged; systems 0, 1 and 3 (64^2, 128^2 and
+    256^2 meshes) against their own oracle hierarchies."""
     systems, k = make_batch(BATCH, workers=8, check_acyclic=False)
     _say(f"test: full batch ({sum(S.n for S in systems)} DOFs, {len(systems)} systems)")
-    check = (0, 1)
+    check = (0, 1, 3)
+    assert [systems[j].N for j in check] == [64, 128, 256]
     rp, ci, va, rhs, sys_nb = concat_systems(systems)
     d_rp, d_ci, d_va = to_dev(rp, ci, va)
     bt = torch.from_numpy(rhs).cuda()
