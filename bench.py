@@ -204,18 +204,19 @@ def setup_work(H, degree: int) -> dict:
     """Algorithmic work of one setup of hierarchy H, from its levels' patterns
     (host scipy on the block patterns; no values): block pairs of the Neumann
     products W_i = W_{i-1} T (T: the phi-strong F-F blocks, W_0 = A_cf) and of
-    R A (R = [Z I]), the single block products T = -D^-1 A_ff and Z = -S D^-1,
+    the coarse operator R (A P) (R = [Z I]; A P merges A's columns through the
+    one-point map), the single block products T = -D^-1 A_ff and Z = -S D^-1,
     the block inverses, and the compulsory bytes of each (operands read once,
     outputs written once, 8-byte pair entries).  Flops: 2 bs^3 per block pair
     or block product, 2 bs^3 per block inverse (LU and the inverse from it)."""
     import numpy as np
     import scipy.sparse as sp
     info = H.info()
-    w = {k: 0 for k in ("pairs_W", "pairs_RA", "ident_RA", "blocks_T", "blocks_Z", "blocks_W", "blocks_Wprev",
-                        "blocks_K", "blocks_A", "nb_inv")}
+    w = {k: 0 for k in ("pairs_W", "pairs_RAP", "ident_RAP", "blocks_T", "blocks_Z", "blocks_W", "blocks_Wprev",
+                        "blocks_K", "blocks_AP", "nb_inv")}
     bs = None
     for l in range(info["levels"]):
-        lv = H.level(l, fields=("rowptr", "colidx", "mask", "cf", "z_rowptr", "z_colidx"))
+        lv = H.level(l, fields=("rowptr", "colidx", "mask", "cf", "pmap", "z_rowptr", "z_colidx"))
         if lv["coarsest"]:
             break
         bs = lv["bs"]
@@ -237,13 +238,17 @@ def setup_work(H, degree: int) -> dict:
             W = (W @ T).tocsr()
             W.data[:] = 1.0
             w["blocks_W"] += W.nnz
-        alen = np.diff(rp)
+        pm = lv["pmap"].cpu().numpy().astype(np.int64)
+        kp = pm[ci] >= 0
+        AP = sp.csr_matrix((np.ones(int(kp.sum())), (rows[kp], pm[ci[kp]])), shape=(nb, int(lv["nc"])))
+        AP.sum_duplicates()
+        aplen = np.diff(AP.indptr)
         zc = lv["z_colidx"].cpu().numpy().astype(np.int64)
-        w["pairs_RA"] += int(alen[zc].sum()) + int(alen[cf == 1].sum())
-        w["ident_RA"] += int((cf == 1).sum())
+        w["pairs_RAP"] += int(aplen[zc].sum())         # Z_ik (A P)_k. products
+        w["ident_RAP"] += int(aplen[cf == 1].sum())    # (A P)_c. blocks added plainly
         w["blocks_T"] += T.nnz
         w["blocks_Z"] += len(zc)
-        w["blocks_A"] += len(ci)
+        w["blocks_AP"] += AP.nnz
         w["nb_inv"] += nb
         w["blocks_K"] += H.level(l + 1, fields=())["nnzb"]
     w["bs"] = bs
@@ -259,9 +264,10 @@ def setup_roofline(P, make_hier, work: dict, reps: int = 1) -> list:
     bb8 = 8 * bs * bs
     f3 = 2.0 * bs ** 3
     kinds = {
-        "galerkin": dict(kernel="k_galerkin_mfma (R A products summed into K blocks)",
-                         flops=(work["pairs_RA"] - work["ident_RA"]) * f3,
-                         bytes=(work["blocks_Z"] + work["blocks_A"] + work["blocks_K"]) * bb8 + 8 * work["pairs_RA"]),
+        "galerkin": dict(kernel="k_galerkin_lds (R (A P) block products summed into K blocks)",
+                         flops=work["pairs_RAP"] * f3,
+                         bytes=(work["blocks_Z"] + work["blocks_AP"] + work["blocks_K"]) * bb8
+                         + 8 * (work["pairs_RAP"] + work["ident_RAP"])),
         "spgemm_numeric": dict(kernel="k_spgemm_mfma (Neumann products W_i = W_(i-1) T)",
                                flops=work["pairs_W"] * f3,
                                bytes=(work["blocks_Wprev"] + work["blocks_T"] + work["blocks_W"]) * bb8

@@ -605,31 +605,21 @@ static int neumann_Z(level_t *L, int32_t degree) {
 /* ------------------------------------------------------------- Galerkin RAP */
 
 /*
- * Coarse operator K = R A P (eq. "rap") with R = [Z I] and one-point P, then
- * the drop filter of section 5.2.
- *   RA_i = sum over R's row i in ascending column K of R_iK A_K (the identity
- *          block at C column cpts[i] is added plainly);
- *   K_{i,t} = sum over RA blocks (i,J), J ascending, with pmap(J) = t >= 0;
- *   off-diagonal K blocks with ||K_it||_max <= drop * ||K_ii||_max are removed.
- * Reading: the filter applies to the coarse operators only, never to the
- * input matrix or to R; block max-abs norms; "<=" as printed.
+ * M P for one-point P given by pmap (column J of M goes to column pmap(J), or
+ * is dropped when pmap(J) < 0): row i of the result holds, at each column t,
+ * the blocks M_iJ with pmap(J) = t summed in ascending J (entry by entry, from
+ * +0).  Columns ascending.
  */
-static int galerkin(level_t *L, double drop, bsr_t *Kout) {
-    const bsr_t *A = &L->A;
-    int32_t bs = A->bs, bb = bs * bs, nc = L->nc;
-    bsr_t RA;
-    int st = spgemm(&L->Z, L->cpts, A, &RA);
-    if (st != ORA_OK) return st;
-    int32_t *slot = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
-    int32_t *cols = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
-    for (int32_t j = 0; j < nc; ++j) slot[j] = -1;
-    /* unfiltered K, row by row, then filtered copy */
-    int32_t *cnt = (int32_t *)xcalloc((size_t)nc + 1, sizeof(int32_t));
+static int merge_columns(const bsr_t *M, const int32_t *pmap, int32_t ncols, bsr_t *out) {
+    int32_t bs = M->bs, bb = bs * bs, m = M->nb;
+    int32_t *slot = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ncols > 0 ? ncols : 1));
+    int32_t *cols = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ncols > 0 ? ncols : 1));
+    for (int32_t j = 0; j < ncols; ++j) slot[j] = -1;
     int64_t total = 0;
-    for (int32_t i = 0; i < nc; ++i) {
+    for (int32_t i = 0; i < m; ++i) {
         int32_t nt = 0;
-        for (int32_t u = RA.rowptr[i]; u < RA.rowptr[i + 1]; ++u) {
-            int32_t t = L->pmap[RA.colidx[u]];
+        for (int32_t u = M->rowptr[i]; u < M->rowptr[i + 1]; ++u) {
+            int32_t t = pmap[M->colidx[u]];
             if (t >= 0 && slot[t] < 0) {
                 slot[t] = 0;
                 cols[nt++] = t;
@@ -638,14 +628,17 @@ static int galerkin(level_t *L, double drop, bsr_t *Kout) {
         for (int32_t q = 0; q < nt; ++q) slot[cols[q]] = -1;
         total += nt;
     }
-    bsr_t K;
-    if ((st = bsr_alloc(&K, nc, nc, bs, total)) != ORA_OK) return st;
+    int st = bsr_alloc(out, m, ncols, bs, total);
+    if (st != ORA_OK) {
+        free(slot);
+        free(cols);
+        return st;
+    }
     int64_t o = 0;
-    double *kn = NULL;
-    for (int32_t i = 0; i < nc; ++i) {
+    for (int32_t i = 0; i < m; ++i) {
         int32_t nt = 0;
-        for (int32_t u = RA.rowptr[i]; u < RA.rowptr[i + 1]; ++u) {
-            int32_t t = L->pmap[RA.colidx[u]];
+        for (int32_t u = M->rowptr[i]; u < M->rowptr[i + 1]; ++u) {
+            int32_t t = pmap[M->colidx[u]];
             if (t >= 0 && slot[t] < 0) {
                 slot[t] = 0;
                 cols[nt++] = t;
@@ -654,21 +647,49 @@ static int galerkin(level_t *L, double drop, bsr_t *Kout) {
         qsort(cols, (size_t)nt, sizeof(int32_t), cmp_i32);
         for (int32_t q = 0; q < nt; ++q) {
             slot[cols[q]] = (int32_t)(o + q);
-            K.colidx[o + q] = cols[q];
+            out->colidx[o + q] = cols[q];
         }
-        for (int32_t u = RA.rowptr[i]; u < RA.rowptr[i + 1]; ++u) {
-            int32_t t = L->pmap[RA.colidx[u]];
+        for (int32_t u = M->rowptr[i]; u < M->rowptr[i + 1]; ++u) {
+            int32_t t = pmap[M->colidx[u]];
             if (t < 0) continue;
-            double *dst = K.vals + (size_t)slot[t] * bb;
-            const double *src = RA.vals + (size_t)u * bb;
+            double *dst = out->vals + (size_t)slot[t] * bb;
+            const double *src = M->vals + (size_t)u * bb;
             for (int32_t e = 0; e < bb; ++e) dst[e] = dst[e] + src[e];
         }
         for (int32_t q = 0; q < nt; ++q) slot[cols[q]] = -1;
         o += nt;
-        K.rowptr[i + 1] = (int32_t)o;
+        out->rowptr[i + 1] = (int32_t)o;
     }
-    cnt[0] = 0;
-    kn = (double *)xcalloc((size_t)total, sizeof(double));
+    free(slot);
+    free(cols);
+    return ORA_OK;
+}
+
+/*
+ * Coarse operator K = R A P (eq. "rap") with R = [Z I] and one-point P, then
+ * the drop filter of section 5.2.
+ *   AP = A P: each row of A with its columns merged through pmap (a sum of
+ *        A's blocks per coarse column; P has one unit block per row, so A P
+ *        is formed before the product with R -- reading: the association
+ *        R (A P), which needs fewer block products than (R A) P);
+ *   K_i = sum over R's row i in ascending column of R_iK AP_K (the identity
+ *        block at C column cpts[i] is added plainly);
+ *   off-diagonal K blocks with ||K_it||_max <= drop * ||K_ii||_max are removed.
+ * Reading: the filter applies to the coarse operators only, never to the
+ * input matrix or to R; block max-abs norms; "<=" as printed.
+ */
+static int galerkin(level_t *L, double drop, bsr_t *Kout) {
+    const bsr_t *A = &L->A;
+    int32_t bs = A->bs, bb = bs * bs, nc = L->nc;
+    (void)bb;
+    bsr_t AP, K;
+    int st = merge_columns(A, L->pmap, nc, &AP);
+    if (st != ORA_OK) return st;
+    st = spgemm(&L->Z, L->cpts, &AP, &K);
+    bsr_free(&AP);
+    if (st != ORA_OK) return st;
+    int64_t total = K.rowptr[nc];
+    double *kn = (double *)xcalloc((size_t)(total > 0 ? total : 1), sizeof(double));
     int64_t kept = 0;
     for (int32_t i = 0; i < nc; ++i) {
         double dn = 0.0;
@@ -682,8 +703,12 @@ static int galerkin(level_t *L, double drop, bsr_t *Kout) {
             if (K.colidx[t] != i) L->margin[3] += near_tie(kn[t], thr);
         }
     }
-    if ((st = bsr_alloc(Kout, nc, nc, bs, kept)) != ORA_OK) return st;
-    o = 0;
+    if ((st = bsr_alloc(Kout, nc, nc, bs, kept)) != ORA_OK) {
+        free(kn);
+        bsr_free(&K);
+        return st;
+    }
+    int64_t o = 0;
     for (int32_t i = 0; i < nc; ++i) {
         double dn = 0.0;
         for (int32_t t = K.rowptr[i]; t < K.rowptr[i + 1]; ++t)
@@ -698,11 +723,7 @@ static int galerkin(level_t *L, double drop, bsr_t *Kout) {
         Kout->rowptr[i + 1] = (int32_t)o;
     }
     free(kn);
-    free(cnt);
-    free(slot);
-    free(cols);
     bsr_free(&K);
-    bsr_free(&RA);
     return ORA_OK;
 }
 

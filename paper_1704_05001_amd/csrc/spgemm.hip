@@ -794,12 +794,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     double *xs = slot[w], *ys = slot[w] + BB;
     MfmaAcc<BS> kacc, acc;
     kacc.zero();
-    const int c0 = kptr[t], c1 = kptr[t + 1];
+    // (kptr == nullptr: every block is its own single contributor)
+    const int c0 = kptr ? kptr[t] : static_cast<int>(t), c1 = kptr ? kptr[t + 1] : static_cast<int>(t) + 1;
     for (int base = c0; base < c1; base += 64) {
         const int cnt = min(64, c1 - base);
         int pb = 0, pe = 0;
         if (lane < cnt) {
-            const int u = klist[base + lane];
+            const int u = klist ? klist[base + lane] : base + lane;
             pb = pairptr[u];
             pe = pairptr[u + 1];
         }
@@ -997,6 +998,22 @@ __global__ __launch_bounds__(256) void k_rap_values(int64_t nnz, int bb, const i
     }
 }
 
+// The same with one wave per block (blocks of 64 entries or more).
+__global__ __launch_bounds__(256) void k_rap_values_wave(int64_t nnz, int bb, const int *__restrict__ kptr,
+                                                        const int *__restrict__ klist, const double *__restrict__ RA,
+                                                        double *__restrict__ K) {
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    for (int64_t t = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; t < nnz; t += stride) {
+        const int k0 = kptr[t], k1 = kptr[t + 1];
+        for (int e = lane; e < bb; e += 64) {
+            double v = 0.0;
+            for (int k = k0; k < k1; ++k) v = v + RA[static_cast<int64_t>(klist[k]) * bb + e];
+            K[t * bb + e] = v;
+        }
+    }
+}
+
 // Drop filter: keep the diagonal and blocks with size > drop * size(diagonal).
 // One wave per row, its lanes over the row's blocks.
 __global__ __launch_bounds__(256) void k_drop_mark(const int *__restrict__ krp, const int *__restrict__ kcol,
@@ -1191,76 +1208,108 @@ void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s) {
     NAIR_HIP(hipGetLastError());
 }
 
-void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int nc, double drop, DevBSR &K,
-              int *margin, DBuf<double> &knext, DBuf<uint32_t> &kmask, hipStream_t s) {
-    // R A's pattern and pair lists; its values only where no fused kernel takes the blocks
-    DevBSR RA;
-    Pairs P;
-    spgemm_structure(Z, cpts, A, RA, P, s);
-    const int bs = RA.bs;
-    const int bb = bs * bs;
-    const bool fused = use_matrix_cores(bs);
-    if (!fused) {
-        RA.vals.alloc(static_cast<size_t>(RA.nnzb) * bb);
-        spgemm_values(Z, A, P, RA, s);
-    }
-    const int m = RA.nb;
-    // flags: too-dense row, then the scans' totals (blocks, contributions), read in one copy
-    DBuf<int> cnt(m), ccnt(m), krp(static_cast<size_t>(m) + 1), crow(static_cast<size_t>(m) + 1), flags(3);
+namespace {
+
+// AP = A P for one-point P: A's columns merged through pmap, each AP block the
+// sum of its A blocks in ascending column (from +0).  Z's block count comes
+// back with the same read when it is still on the device.
+void merge_columns(const DevBSR &A, const int *pmap, int nc, DevBSR &Z, DevBSR &AP, hipStream_t s) {
+    const int m = A.nb, bs = A.bs, bb = bs * bs;
+    AP.nb = m;
+    AP.ncols = nc;
+    AP.bs = bs;
+    DBuf<int> cnt(m), ccnt(m), crow(static_cast<size_t>(m) + 1), flags(3);
+    AP.rowptr.alloc(static_cast<size_t>(m) + 1);
     NAIR_HIP(hipMemsetAsync(flags.get(), 0, sizeof(int), s));
     const unsigned gs = cap_grid((m + 3) / 4);
-    k_rap_symbolic<<<gs, 256, 0, s>>>(RA.rowptr.get(), RA.colidx.get(), pmap, m, 0, cnt.get(), nullptr, nullptr,
+    k_rap_symbolic<<<gs, 256, 0, s>>>(A.rowptr.get(), A.colidx.get(), pmap, m, 0, cnt.get(), nullptr, nullptr,
                                       flags.get());
-    k_rap_count_contrib<<<grid_for(m, 256), 256, 0, s>>>(RA.rowptr.get(), RA.colidx.get(), pmap, m, ccnt.get());
+    k_rap_count_contrib<<<grid_for(m, 256), 256, 0, s>>>(A.rowptr.get(), A.colidx.get(), pmap, m, ccnt.get());
     NAIR_HIP(hipGetLastError());
-    scan_exclusive2(cnt.get(), krp.get(), m, flags.get() + 1, ccnt.get(), crow.get(), m, flags.get() + 2, s);
+    scan_exclusive2(cnt.get(), AP.rowptr.get(), m, flags.get() + 1, ccnt.get(), crow.get(), m, flags.get() + 2, s);
     int hflags[3] = {0, 0, 0};
     int zcount = 0;
-    const bool zdev = Z.nnzb < 0;   // Z's block count comes back with this read
+    const bool zdev = Z.nnzb < 0;
     read_device({{flags.get(), hflags, sizeof(int) * 3},
                  {zdev ? Z.rowptr.get() + Z.nb : nullptr, &zcount, zdev ? sizeof(int) : 0}},
                 s);
     if (zdev) Z.nnzb = zcount;
-    const int too_dense = hflags[0], nnz = hflags[1], ncontrib = hflags[2];
-    if (too_dense > 0)
-        fail(NAIR_ENOMEM, "Galerkin row has " + std::to_string(too_dense) + " blocks (limit " +
+    if (hflags[0] > 0)
+        fail(NAIR_ENOMEM, "operator row has " + std::to_string(hflags[0]) + " blocks (limit " +
                               std::to_string(kHashSmall / 2) + ")");
-    DBuf<int> kcol(nnz), kptr(static_cast<size_t>(nnz) + 1), klist(ncontrib);
-    DBuf<double> kval(static_cast<size_t>(nnz) * bb), knorm(nnz);
-    DBuf<uint32_t> kbits(fused ? nnz : 0);
-    DBuf<uint8_t> keep(nnz);
-    DBuf<int> kept(m);
-    k_rap_symbolic<<<gs, 256, 0, s>>>(RA.rowptr.get(), RA.colidx.get(), pmap, m, 1, nullptr, krp.get(), kcol.get(),
-                                      flags.get());
-    k_rap_contrib<<<cap_grid(m), 64, 0, s>>>(RA.rowptr.get(), RA.colidx.get(), pmap, m, krp.get(), kcol.get(),
-                                             crow.get(), kptr.get(), klist.get());
+    const int nnz = hflags[1], ncontrib = hflags[2];
+    AP.nnzb = nnz;
+    AP.colidx.alloc(static_cast<size_t>(nnz));
+    AP.vals.alloc(static_cast<size_t>(nnz) * bb);
+    if (nnz == 0) return;
+    DBuf<int> kptr(static_cast<size_t>(nnz) + 1), klist(static_cast<size_t>(ncontrib));
+    k_rap_symbolic<<<gs, 256, 0, s>>>(A.rowptr.get(), A.colidx.get(), pmap, m, 1, nullptr, AP.rowptr.get(),
+                                      AP.colidx.get(), flags.get());
+    k_rap_contrib<<<cap_grid(m), 64, 0, s>>>(A.rowptr.get(), A.colidx.get(), pmap, m, AP.rowptr.get(),
+                                             AP.colidx.get(), crow.get(), kptr.get(), klist.get());
+    if (bb >= 64)
+        k_rap_values_wave<<<cap_grid((static_cast<int64_t>(nnz) + 3) / 4), 256, 0, s>>>(nnz, bb, kptr.get(),
+                                                                                      klist.get(), A.vals.get(),
+                                                                                      AP.vals.get());
+    else
+        k_rap_values<<<cap_grid((static_cast<int64_t>(nnz) * bb + 255) / 256), 256, 0, s>>>(
+            nnz, bb, kptr.get(), klist.get(), A.vals.get(), AP.vals.get());
     NAIR_HIP(hipGetLastError());
-    if (nnz > 0) {
-        TimerScope ts(TK_RAP, g_timer_level, s);
-        if (fused) {
+}
+
+}  // namespace
+
+void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int nc, double drop, DevBSR &K,
+              int *margin, DBuf<double> &knext, DBuf<uint32_t> &kmask, hipStream_t s) {
+    // A P first (P is one unit block per row: a merge of A's columns), then
+    // K = R (A P) with R = [Z I]: its pattern and pair lists, and each block's
+    // sum on the matrix cores (with its size and row mask) or by pairs
+    DevBSR AP;
+    merge_columns(A, pmap, nc, Z, AP, s);
+    DevBSR RK;
+    Pairs P;
+    spgemm_structure(Z, cpts, AP, RK, P, s);
+    const int bs = A.bs;
+    const int bb = bs * bs;
+    const bool fused = use_matrix_cores(bs);
+    const int m = nc;
+    const int nnz = static_cast<int>(RK.nnzb);
+    DBuf<double> kval, knorm(static_cast<size_t>(nnz));
+    DBuf<uint32_t> kbits(fused ? nnz : 0);
+    DBuf<uint8_t> keep(static_cast<size_t>(nnz));
+    DBuf<int> kept(static_cast<size_t>(m));
+    if (fused) {
+        kval.alloc(static_cast<size_t>(nnz) * bb);
+        if (nnz > 0) {
+            TimerScope ts(TK_RAP, g_timer_level, s);
             const unsigned mgrid = static_cast<unsigned>((static_cast<int64_t>(nnz) + 3) / 4);
             if (bs == 9)
-                k_galerkin_lds<9><<<mgrid, 256, 0, s>>>(nnz, kptr.get(), klist.get(), P.pairptr.get(),
-                                                        P.pairs.get(), Z.vals.get(), A.vals.get(), kval.get(),
-                                                        knorm.get(), kbits.get());
+                k_galerkin_lds<9><<<mgrid, 256, 0, s>>>(nnz, nullptr, nullptr, P.pairptr.get(), P.pairs.get(),
+                                                        Z.vals.get(), AP.vals.get(), kval.get(), knorm.get(),
+                                                        kbits.get());
             else if (bs == 16)
-                k_galerkin_lds<16><<<mgrid, 256, 0, s>>>(nnz, kptr.get(), klist.get(), P.pairptr.get(),
-                                                         P.pairs.get(), Z.vals.get(), A.vals.get(), kval.get(),
-                                                         knorm.get(), kbits.get());
+                k_galerkin_lds<16><<<mgrid, 256, 0, s>>>(nnz, nullptr, nullptr, P.pairptr.get(), P.pairs.get(),
+                                                         Z.vals.get(), AP.vals.get(), kval.get(), knorm.get(),
+                                                         kbits.get());
             else
-                k_galerkin_lds<25><<<mgrid, 256, 0, s>>>(nnz, kptr.get(), klist.get(), P.pairptr.get(),
-                                                         P.pairs.get(), Z.vals.get(), A.vals.get(), kval.get(),
-                                                         knorm.get(), kbits.get());
-        } else {
-            const int64_t total = static_cast<int64_t>(nnz) * bb;
-            k_rap_values<<<cap_grid((total + 255) / 256), 256, 0, s>>>(nnz, bb, kptr.get(), klist.get(),
-                                                                      RA.vals.get(), kval.get());
+                k_galerkin_lds<25><<<mgrid, 256, 0, s>>>(nnz, nullptr, nullptr, P.pairptr.get(), P.pairs.get(),
+                                                         Z.vals.get(), AP.vals.get(), kval.get(), knorm.get(),
+                                                         kbits.get());
+            NAIR_HIP(hipGetLastError());
         }
-        NAIR_HIP(hipGetLastError());
+    } else {
+        RK.vals.alloc(static_cast<size_t>(nnz) * bb);
+        {
+            TimerScope ts(TK_RAP, g_timer_level, s);
+            spgemm_values(Z, AP, P, RK, s);
+        }
+        kval = std::move(RK.vals);
+        launch_block_maxabs(kval.get(), nnz, bs, knorm.get(), s);
     }
-    if (!fused) launch_block_maxabs(kval.get(), nnz, bs, knorm.get(), s);
-    k_drop_mark<<<static_cast<unsigned>(std::max((m + 3) / 4, 1)), 256, 0, s>>>(krp.get(), kcol.get(), knorm.get(), m, drop,
-                                                                    keep.get(), kept.get(), margin);
+    const int *krp = RK.rowptr.get();
+    const int *kcol = RK.colidx.get();
+    k_drop_mark<<<static_cast<unsigned>(std::max((m + 3) / 4, 1)), 256, 0, s>>>(krp, kcol, knorm.get(), m, drop,
+                                                                               keep.get(), kept.get(), margin);
     NAIR_HIP(hipGetLastError());
     K.nb = nc;
     K.ncols = nc;
@@ -1275,8 +1324,8 @@ void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int 
     knext.alloc(static_cast<size_t>(nnz));
     const int *nk = K.rowptr.get() + m;
     DBuf<int> src(static_cast<size_t>(nnz));
-    k_compact_fill<<<grid_for(m, 256), 256, 0, s>>>(krp.get(), kcol.get(), keep.get(), m, K.rowptr.get(),
-                                                    K.colidx.get(), src.get());
+    k_compact_fill<<<grid_for(m, 256), 256, 0, s>>>(krp, kcol, keep.get(), m, K.rowptr.get(), K.colidx.get(),
+                                                    src.get());
     NAIR_HIP(hipGetLastError());
     launch_block_gather(nnz, bs, kval.get(), src.get(), K.vals.get(), s, nk);
     launch_block_gather(nnz, 1, knorm.get(), src.get(), knext.get(), s, nk);   // a block's size is its max-abs entry

@@ -3,14 +3,16 @@
 A block row of a sparse product whose candidate products (the summed lengths
 of the right operand's rows it touches) exceed 1,024 leaves the per-wave LDS
 hash for one workgroup with a larger table (k_symbolic_large) and has its pair
-list built by k_pairs_large.  The matrices here make R A (R = [Z I]) produce
-such a row: a "collector" C block depends on many F blocks, each of which
-depends on the same few C blocks, so the collector's row of R A touches
-thousands of candidate products that merge into a few hundred blocks.  The
+list built by k_pairs_large.  The matrices here make the coarse operator's
+product R (A P) (R = [Z I]) produce such a row: a "collector" C block depends
+on many F blocks, each of which depends on the same few C blocks, so the
+collector's row touches thousands of candidate products that merge into a
+few blocks.  The
 hierarchy must equal the oracle's bit for bit (patterns, pair order, values).
 
 Past 4,096 candidate products a row is refused (NAIR_ENOMEM, with the count in
-the message), and so is a Galerkin row of R A with more than 1,024 blocks.
+the message), and so is an operator row of more than 1,024 blocks (the merge
+of A's columns into A P).
 """
 import numpy as np
 import pytest
@@ -51,8 +53,9 @@ def test_long_rows_match_the_oracle(bs):
     _need_gpu()
     nf, nsrc = 400, 5
     nb, rp, ci, va, cf = arrow(nf, nsrc, bs, seed=bs)
-    # the collector's R A row: its own row (1 + nf blocks) plus, per F block, its row (1 + nsrc)
-    candidates = (1 + nf) + nf * (1 + nsrc)
+    # the collector's row of R (A P): its own A P row (nsrc + 1 coarse columns) plus, per F
+    # block of Z, that block's A P row (its nsrc sources)
+    candidates = (nsrc + 1) + nf * nsrc
     assert 1024 < candidates <= 4096
     _say(f"test: long sparse-product row (bs {bs}, {candidates} candidate products)")
     G, O = build_pair(nb, bs, rp, ci, va, degree=1, cf_override=cf, max_coarse_dofs=8 * bs, drop=0.0)
@@ -63,31 +66,45 @@ def test_long_rows_match_the_oracle(bs):
 
 
 def test_row_past_the_product_limit_is_refused():
+    """The collector's row of R (A P): nf F blocks of Z, each meeting an A P row
+    with its nsrc source columns, so about nf * nsrc candidates."""
+    import re
     import paper_1704_05001_amd as P
     _need_gpu()
-    nf, nsrc = 800, 5
+    nf, nsrc = 1000, 5
     nb, rp, ci, va, cf = arrow(nf, nsrc, 2)
-    candidates = (1 + nf) + nf * (1 + nsrc)
-    assert candidates > 4096
-    _say(f"test: sparse-product row past the limit ({candidates} candidates)")
+    assert nf * nsrc > 4096
+    _say(f"test: sparse-product row past the limit (about {nf * nsrc} candidates)")
     with pytest.raises(P.NairError) as e:
         P.Hierarchy(*to_dev(rp, ci, va), 2, P.Params(degree=1, cf_override=cf, max_coarse_dofs=16))
     assert e.value.status == "ENOMEM"
-    assert f"{candidates} candidate blocks (limit 4096)" in str(e.value)
+    m = re.search(r"sparse product row has (\d+) candidate blocks \(limit 4096\)", str(e.value))
+    assert m and int(m.group(1)) > 4096
     # the library stays usable
     nb, rp, ci, va, cf = arrow(50, 2, 2)
     G, O = build_pair(nb, 2, rp, ci, va, degree=1, cf_override=cf, max_coarse_dofs=16)
     compare_hierarchies(G, O)
 
 
-def test_galerkin_row_past_its_limit_is_refused():
+def test_operator_row_past_its_limit_is_refused():
+    """A P merges an operator row in one wave's LDS hash: a row of more than
+    1,024 blocks is refused (NAIR_ENOMEM, with the count in the message)."""
     import paper_1704_05001_amd as P
     _need_gpu()
-    nf, nsrc = 1100, 1
-    nb, rp, ci, va, cf = arrow(nf, nsrc, 2)
-    assert (1 + nf) + nf * (1 + nsrc) <= 4096   # the product itself fits; R A's row has 1 + nf + nsrc blocks
-    _say("test: Galerkin row past 1024 blocks")
+    n = 1200
+    nb = n + 1
+    # block 0 depends on blocks 1..n (a long row); the others on nothing
+    rows = [list(range(0, n + 1))] + [[J] for J in range(1, n + 1)]
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    ci = np.concatenate([np.array(r) for r in rows]).astype(np.int32)
+    rng = np.random.default_rng(5)
+    va = rng.uniform(-1, 1, size=(len(ci), 2, 2)) / n
+    rowid = np.repeat(np.arange(nb), np.diff(rp))
+    va[rowid == ci] += 2.0 * np.eye(2)
+    cf = np.ones(nb, dtype=np.int8)
+    cf[0] = 0                       # the long row is an F row; its row of A keeps all 1 + n blocks
+    _say("test: operator row past 1024 blocks")
     with pytest.raises(P.NairError) as e:
         P.Hierarchy(*to_dev(rp, ci, va), 2, P.Params(degree=1, cf_override=cf, max_coarse_dofs=16))
     assert e.value.status == "ENOMEM"
-    assert f"Galerkin row has {1 + nf + nsrc} blocks (limit 1024)" in str(e.value)
+    assert f"operator row has {1 + n} blocks (limit 1024)" in str(e.value)
