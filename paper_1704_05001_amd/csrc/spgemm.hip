@@ -781,7 +781,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                                                      const int *__restrict__ klist, const int *__restrict__ pairptr,
                                                      const int2 *__restrict__ pairs, const double *__restrict__ X,
                                                      const double *__restrict__ Y, double *__restrict__ K,
-                                                     double *__restrict__ knorm, uint32_t *__restrict__ kmask) {
+                                                     double *__restrict__ knorm, uint32_t *__restrict__ kmask,
+                                                     const double *__restrict__ Y2 = nullptr) {
     constexpr int BB = BS * BS;
     constexpr int NL = (BB + 63) / 64;   // loads per lane and block
     constexpr int NT = MfmaShape<BS>::NT, KQ = MfmaShape<BS>::KQ;
@@ -828,7 +829,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         int2 pr1 = j1 < cnt ? pairs[k1] : int2{0, 0};
         double xv[NL], yv[NL];
         auto load = [&](const int2 q) {
-            const double *y = Y + static_cast<int64_t>(q.y) * BB;
+            // (a pair's y < 0 names block -y-1 of the second store)
+            const double *y = q.y >= 0 ? Y + static_cast<int64_t>(q.y) * BB : Y2 + static_cast<int64_t>(-q.y - 1) * BB;
             const double *x = X + static_cast<int64_t>(q.x < 0 ? 0 : q.x) * BB;
 #pragma unroll
             for (int i = 0; i < NL; ++i) {
@@ -911,7 +913,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         m = fmax(m, __shfl_xor(m, o, 64));
         bits |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(bits), o, 64));
     }
-    if (lane == 0) {
+    if (lane == 0 && knorm) {   // (a plain sparse product takes no sizes)
         knorm[t] = m;
         kmask[t] = bits;
     }
@@ -1014,6 +1016,48 @@ __global__ __launch_bounds__(256) void k_rap_values_wave(int64_t nnz, int bb, co
     }
 }
 
+// A P blocks with one contributor are that A block itself; the others (flag 1)
+// are summed into a second store.  ymap[t]: the A block, or -(merged index)-1.
+__global__ __launch_bounds__(256) void k_ap_flags(int64_t nnz, const int *__restrict__ kptr, int *__restrict__ flag) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < nnz) flag[t] = (kptr[t + 1] - kptr[t] > 1) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_ap_map(int64_t nnz, const int *__restrict__ kptr,
+                                               const int *__restrict__ klist, const int *__restrict__ midx,
+                                               int *__restrict__ ymap, int *__restrict__ mblk) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nnz) return;
+    if (kptr[t + 1] - kptr[t] > 1) {
+        ymap[t] = -midx[t] - 1;
+        mblk[midx[t]] = static_cast<int>(t);
+    } else {
+        ymap[t] = klist[kptr[t]];
+    }
+}
+
+// merged block q = sum of A P block mblk[q]'s contributors, one wave per block
+__global__ __launch_bounds__(256) void k_ap_merged(int nm, int bb, const int *__restrict__ mblk,
+                                                  const int *__restrict__ kptr, const int *__restrict__ klist,
+                                                  const double *__restrict__ A, double *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    for (int64_t q = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; q < nm; q += stride) {
+        const int t = mblk[q];
+        const int k0 = kptr[t], k1 = kptr[t + 1];
+        for (int e = lane; e < bb; e += 64) {
+            double v = 0.0;
+            for (int k = k0; k < k1; ++k) v = v + A[static_cast<int64_t>(klist[k]) * bb + e];
+            out[q * bb + e] = v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_remap_y(int64_t n, const int *__restrict__ ymap, int2 *__restrict__ pairs) {
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p < n) pairs[p].y = ymap[pairs[p].y];
+}
+
 // Drop filter: keep the diagonal and blocks with size > drop * size(diagonal).
 // One wave per row, its lanes over the row's blocks.
 __global__ __launch_bounds__(256) void k_drop_mark(const int *__restrict__ krp, const int *__restrict__ kcol,
@@ -1079,6 +1123,7 @@ namespace {
 struct Pairs {
     DBuf<int> pairptr;
     DBuf<int2> pairs;
+    int64_t n = 0;   // pairs
 };
 
 // C's pattern (rowptr, colidx, nnzb) and the pair lists of its blocks; C.vals
@@ -1127,6 +1172,7 @@ void spgemm_structure(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR
     if (nnz == 0) return;
     P.pairptr.alloc(static_cast<size_t>(nnz) + 1);
     P.pairs.alloc(npairs);
+    P.n = npairs;
     k_symbolic_flat<<<gs, 256, 0, s>>>(X.rowptr.get(), X.colidx.get(), xdiag, Y.rowptr.get(), Y.colidx.get(), m,
                                        ub.get(), small_cap, 1, nullptr, C.rowptr.get(), C.colidx.get(), prow.get(),
                                        P.pairptr.get(), P.pairs.get());
@@ -1151,15 +1197,16 @@ void spgemm_values(const DevBSR &X, const DevBSR &Y, const Pairs &P, DevBSR &C, 
     TimerScope ts(TK_SPGEMM_NUM, g_timer_level, s);
     const unsigned mgrid = static_cast<unsigned>((nnz + 3) / 4);   // four waves per workgroup
     if (use_matrix_cores(bs)) {
+        // the LDS-staged kernel with each block its own single contributor: the same sums
         if (bs == 9)
-            k_spgemm_mfma<9><<<mgrid, 256, 0, s>>>(nnz, P.pairptr.get(), P.pairs.get(), X.vals.get(), Y.vals.get(),
-                                                   C.vals.get());
+            k_galerkin_lds<9><<<mgrid, 256, 0, s>>>(nnz, nullptr, nullptr, P.pairptr.get(), P.pairs.get(),
+                                                    X.vals.get(), Y.vals.get(), C.vals.get(), nullptr, nullptr);
         else if (bs == 16)
-            k_spgemm_mfma<16><<<mgrid, 256, 0, s>>>(nnz, P.pairptr.get(), P.pairs.get(), X.vals.get(), Y.vals.get(),
-                                                    C.vals.get());
+            k_galerkin_lds<16><<<mgrid, 256, 0, s>>>(nnz, nullptr, nullptr, P.pairptr.get(), P.pairs.get(),
+                                                     X.vals.get(), Y.vals.get(), C.vals.get(), nullptr, nullptr);
         else
-            k_spgemm_mfma<25><<<mgrid, 256, 0, s>>>(nnz, P.pairptr.get(), P.pairs.get(), X.vals.get(), Y.vals.get(),
-                                                    C.vals.get());
+            k_galerkin_lds<25><<<mgrid, 256, 0, s>>>(nnz, nullptr, nullptr, P.pairptr.get(), P.pairs.get(),
+                                                     X.vals.get(), Y.vals.get(), C.vals.get(), nullptr, nullptr);
     } else {
         NAIR_BS_DISPATCH(bs, k_spgemm_pairs, <<<grid, 256, 0, s>>>(nnz, bs, P.pairptr.get(), P.pairs.get(),
                                                                    X.vals.get(), Y.vals.get(), C.vals.get()));
@@ -1212,8 +1259,12 @@ namespace {
 
 // AP = A P for one-point P: A's columns merged through pmap, each AP block the
 // sum of its A blocks in ascending column (from +0).  Z's block count comes
-// back with the same read when it is still on the device.
-void merge_columns(const DevBSR &A, const int *pmap, int nc, DevBSR &Z, DevBSR &AP, hipStream_t s) {
+// back with the same read when it is still on the device.  With `ymap`, only
+// the blocks with several contributors are summed (into `merged`); ymap[t]
+// names block t's values: A's block, or -(merged index)-1 (a lone block is
+// its A block, up to the sign of a zero entry).
+void merge_columns(const DevBSR &A, const int *pmap, int nc, DevBSR &Z, DevBSR &AP, hipStream_t s,
+                   DBuf<int> *ymap = nullptr, DBuf<double> *merged = nullptr) {
     const int m = A.nb, bs = A.bs, bb = bs * bs;
     AP.nb = m;
     AP.ncols = nc;
@@ -1240,13 +1291,28 @@ void merge_columns(const DevBSR &A, const int *pmap, int nc, DevBSR &Z, DevBSR &
     const int nnz = hflags[1], ncontrib = hflags[2];
     AP.nnzb = nnz;
     AP.colidx.alloc(static_cast<size_t>(nnz));
-    AP.vals.alloc(static_cast<size_t>(nnz) * bb);
+    if (!ymap) AP.vals.alloc(static_cast<size_t>(nnz) * bb);
     if (nnz == 0) return;
     DBuf<int> kptr(static_cast<size_t>(nnz) + 1), klist(static_cast<size_t>(ncontrib));
     k_rap_symbolic<<<gs, 256, 0, s>>>(A.rowptr.get(), A.colidx.get(), pmap, m, 1, nullptr, AP.rowptr.get(),
                                       AP.colidx.get(), flags.get());
     k_rap_contrib<<<cap_grid(m), 64, 0, s>>>(A.rowptr.get(), A.colidx.get(), pmap, m, AP.rowptr.get(),
                                              AP.colidx.get(), crow.get(), kptr.get(), klist.get());
+    if (ymap) {
+        DBuf<int> flag(static_cast<size_t>(nnz)), midx(static_cast<size_t>(nnz) + 1);
+        k_ap_flags<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, kptr.get(), flag.get());
+        scan_exclusive(flag.get(), midx.get(), nnz, s);
+        const int nm = read_int(midx.get() + nnz, s);
+        ymap->alloc(static_cast<size_t>(nnz));
+        merged->alloc(static_cast<size_t>(std::max(nm, 1)) * bb);
+        DBuf<int> mblk(static_cast<size_t>(std::max(nm, 1)));
+        k_ap_map<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, kptr.get(), klist.get(), midx.get(), ymap->get(), mblk.get());
+        if (nm > 0)
+            k_ap_merged<<<cap_grid((static_cast<int64_t>(nm) + 3) / 4), 256, 0, s>>>(
+                nm, bb, mblk.get(), kptr.get(), klist.get(), A.vals.get(), merged->get());
+        NAIR_HIP(hipGetLastError());
+        return;
+    }
     if (bb >= 64)
         k_rap_values_wave<<<cap_grid((static_cast<int64_t>(nnz) + 3) / 4), 256, 0, s>>>(nnz, bb, kptr.get(),
                                                                                       klist.get(), A.vals.get(),
@@ -1264,14 +1330,20 @@ void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int 
     // A P first (P is one unit block per row: a merge of A's columns), then
     // K = R (A P) with R = [Z I]: its pattern and pair lists, and each block's
     // sum on the matrix cores (with its size and row mask) or by pairs
-    DevBSR AP;
-    merge_columns(A, pmap, nc, Z, AP, s);
-    DevBSR RK;
-    Pairs P;
-    spgemm_structure(Z, cpts, AP, RK, P, s);
     const int bs = A.bs;
     const int bb = bs * bs;
     const bool fused = use_matrix_cores(bs);
+    DevBSR AP;
+    DBuf<int> ymap;
+    DBuf<double> merged;
+    merge_columns(A, pmap, nc, Z, AP, s, fused ? &ymap : nullptr, fused ? &merged : nullptr);
+    DevBSR RK;
+    Pairs P;
+    spgemm_structure(Z, cpts, AP, RK, P, s);
+    if (fused && P.n > 0) {   // the pairs name A's block or a merged block
+        k_remap_y<<<grid_for(P.n, 256), 256, 0, s>>>(P.n, ymap.get(), P.pairs.get());
+        NAIR_HIP(hipGetLastError());
+    }
     const int m = nc;
     const int nnz = static_cast<int>(RK.nnzb);
     DBuf<double> kval, knorm(static_cast<size_t>(nnz));
@@ -1285,16 +1357,16 @@ void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int 
             const unsigned mgrid = static_cast<unsigned>((static_cast<int64_t>(nnz) + 3) / 4);
             if (bs == 9)
                 k_galerkin_lds<9><<<mgrid, 256, 0, s>>>(nnz, nullptr, nullptr, P.pairptr.get(), P.pairs.get(),
-                                                        Z.vals.get(), AP.vals.get(), kval.get(), knorm.get(),
-                                                        kbits.get());
+                                                        Z.vals.get(), A.vals.get(), kval.get(), knorm.get(),
+                                                        kbits.get(), merged.get());
             else if (bs == 16)
                 k_galerkin_lds<16><<<mgrid, 256, 0, s>>>(nnz, nullptr, nullptr, P.pairptr.get(), P.pairs.get(),
-                                                         Z.vals.get(), AP.vals.get(), kval.get(), knorm.get(),
-                                                         kbits.get());
+                                                         Z.vals.get(), A.vals.get(), kval.get(), knorm.get(),
+                                                         kbits.get(), merged.get());
             else
                 k_galerkin_lds<25><<<mgrid, 256, 0, s>>>(nnz, nullptr, nullptr, P.pairptr.get(), P.pairs.get(),
-                                                         Z.vals.get(), AP.vals.get(), kval.get(), knorm.get(),
-                                                         kbits.get());
+                                                         Z.vals.get(), A.vals.get(), kval.get(), knorm.get(),
+                                                         kbits.get(), merged.get());
             NAIR_HIP(hipGetLastError());
         }
     } else {
