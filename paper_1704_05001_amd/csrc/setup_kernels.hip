@@ -170,6 +170,115 @@ __global__ __launch_bounds__(256) void k_block_inverse_wave(const int *__restric
     for (int i = 0; i < BS; ++i) dst[i * BS + j] = y[i];
 }
 
+// The same LU recipe with each block on a half wave and its rows in registers
+// (bs 16 and 25; lane r of the half holds row r): the pivot search is a
+// shuffle reduction over the half, the whole-row exchange and the broadcast of
+// the pivot row are shuffles, and lane r updates its own row -- no LDS and no
+// barriers through the 25 elimination steps.  The factors then go to the
+// half's LDS slot and lane j forms column j of the inverse by the same forward
+// and back substitution as k_block_inverse_wave.  Same operations, same order,
+// same bits.
+template <int BS>
+__global__ __launch_bounds__(256) void k_block_inverse_rows(const int *__restrict__ rowptr,
+                                                           const int *__restrict__ colidx,
+                                                           const double *__restrict__ vals, int nb,
+                                                           const int8_t *__restrict__ skip, double *__restrict__ dinv,
+                                                           int *__restrict__ singular_min) {
+    static_assert(BS >= 2 && BS <= 32, "a block row per lane of a half wave");
+    constexpr int BB = BS * BS;
+    __shared__ double slot[8][BB];
+    __shared__ int pslot[8][32];
+    const int h = threadIdx.x >> 5;           // half wave: one block
+    const int r = threadIdx.x & 31;           // its row
+    const int base = threadIdx.x & 32;        // first lane of the half in the wave
+    const int I = blockIdx.x * 8 + h;
+    const bool on = I < nb && !(skip && skip[I]);
+    // the diagonal block's position in row I
+    int dpos = -1;
+    if (on)
+        for (int t = rowptr[I] + r; t < rowptr[I + 1]; t += 32)
+            if (colidx[t] == I) dpos = t;
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) dpos = max(dpos, __shfl_xor(dpos, o, kWave));
+    bool live = on && dpos >= 0;
+    if (on && dpos < 0 && r == 0) atomicMin(singular_min, I);   // validated before; never taken for valid input
+    double a[BS];
+    int perm = r;
+    {
+        const double *src = vals + static_cast<int64_t>(live ? dpos : 0) * BB + (r < BS ? r : 0) * BS;
+#pragma unroll
+        for (int c = 0; c < BS; ++c) a[c] = (live && r < BS) ? src[c] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < BS; ++k) {
+        // pivot: the first row >= k of largest |a_rk|
+        double v = -1.0;
+        int idx = BS;
+        if (r >= k && r < BS) {
+            v = fabs(a[k]);
+            idx = r;
+        }
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(v, o, kWave);
+            const int oi = __shfl_xor(idx, o, kWave);
+            if (ov > v || (ov == v && oi < idx)) {
+                v = ov;
+                idx = oi;
+            }
+        }
+        if (live && !(v > 0.0)) {
+            if (r == 0) atomicMin(singular_min, I);
+            live = false;
+        }
+        // whole-row exchange of rows k and idx
+        const int from = base + (r == k ? idx : (r == idx ? k : r));
+        if (__any(idx != k)) {
+#pragma unroll
+            for (int c = 0; c < BS; ++c) a[c] = __shfl(a[c], from, kWave);
+            perm = __shfl(perm, from, kWave);
+        }
+        // multipliers and the trailing update with the pivot row broadcast
+        const double piv = __shfl(a[k], base + k, kWave);
+        if (r > k && r < BS) a[k] = a[k] / piv;
+#pragma unroll
+        for (int j = k + 1; j < BS; ++j) {
+            const double akj = __shfl(a[j], base + k, kWave);
+            if (r > k && r < BS) a[j] = __builtin_fma(-a[k], akj, a[j]);
+        }
+    }
+    double *fac = slot[h];
+    int *pm = pslot[h];
+    if (r < BS) {
+#pragma unroll
+        for (int c = 0; c < BS; ++c) fac[r * BS + c] = a[c];
+        pm[r] = perm;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (!live || r >= BS) return;
+    const int j = r;
+    double y[BS];
+#pragma unroll
+    for (int i = 0; i < BS; ++i) {
+        double sacc = (pm[i] == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int mm = 0; mm < i; ++mm) sacc = __builtin_fma(-fac[i * BS + mm], y[mm], sacc);
+        y[i] = sacc;
+    }
+#pragma unroll
+    for (int i = BS - 1; i >= 0; --i) {
+        double sacc = y[i];
+#pragma unroll
+        for (int mm = i + 1; mm < BS; ++mm) sacc = __builtin_fma(-fac[i * BS + mm], y[mm], sacc);
+        y[i] = sacc / fac[i * BS + i];
+    }
+    double *dst = dinv + static_cast<int64_t>(I) * BB;
+#pragma unroll
+    for (int i = 0; i < BS; ++i) dst[i * BS + j] = y[i];
+}
+
 // One wave per block row.  LU with partial pivoting (first row of largest
 // |a_ik|, whole-row exchange), multipliers by division, trailing update
 // a_ij = fma(-a_ik, a_kj, a_ij); then column j of the inverse by forward
@@ -808,11 +917,11 @@ void launch_block_inverse(const int *rowptr, const int *colidx, const double *va
     } else if (bs == 4) {
         k_block_inverse_thread<4><<<grid, 64, 0, s>>>(rowptr, colidx, vals, nb, skip, dinv, singular_min);
     } else if (bs == 16 || bs == 25) {
-        const unsigned wgrid = static_cast<unsigned>((nb + 3) / 4);   // four waves (blocks) per workgroup
+        const unsigned hgrid = static_cast<unsigned>((nb + 7) / 8);   // eight half waves (blocks) per workgroup
         if (bs == 16)
-            k_block_inverse_wave<16><<<wgrid, 256, 0, s>>>(rowptr, colidx, vals, nb, skip, dinv, singular_min);
+            k_block_inverse_rows<16><<<hgrid, 256, 0, s>>>(rowptr, colidx, vals, nb, skip, dinv, singular_min);
         else
-            k_block_inverse_wave<25><<<wgrid, 256, 0, s>>>(rowptr, colidx, vals, nb, skip, dinv, singular_min);
+            k_block_inverse_rows<25><<<hgrid, 256, 0, s>>>(rowptr, colidx, vals, nb, skip, dinv, singular_min);
     } else {
         const size_t lds = sizeof(double) * 2 * bs * bs + sizeof(int) * bs;
         k_block_inverse<<<cap_grid(nb), 64, lds, s>>>(rowptr, colidx, vals, nb, bs, skip, dinv, singular_min);
