@@ -170,14 +170,45 @@ __global__ __launch_bounds__(256) void k_block_inverse_wave(const int *__restric
     for (int i = 0; i < BS; ++i) dst[i * BS + j] = y[i];
 }
 
+// Lane-to-lane moves within groups of a half wave for the pivot search: DPP
+// for the quad and row patterns, a swizzle for the two 16-lane rows.
+template <int CTRL>
+__device__ inline int dpp_move(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = dpp_move<CTRL>(static_cast<int>(u)), hi = dpp_move<CTRL>(static_cast<int>(u >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+constexpr int kSwizzleXor16 = 0x401F;   // bit mode: lane i of 32 reads lane i ^ 16
+__device__ inline int swz16(int v) { return __builtin_amdgcn_ds_swizzle(v, kSwizzleXor16); }
+__device__ inline double swz16(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = swz16(static_cast<int>(u)), hi = swz16(static_cast<int>(u >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+// (v, key) takes (ov, okey) when that one is larger, or equal with a smaller key
+__device__ inline void pivot_take(double &v, int &key, double ov, int okey) {
+    if (ov > v || (ov == v && okey < key)) {
+        v = ov;
+        key = okey;
+    }
+}
+
 // The same LU recipe with each block on a half wave and its rows in registers
-// (bs 16 and 25; lane r of the half holds row r): the pivot search is a
-// shuffle reduction over the half, the whole-row exchange and the broadcast of
-// the pivot row are shuffles, and lane r updates its own row -- no LDS and no
-// barriers through the 25 elimination steps.  The factors then go to the
-// half's LDS slot and lane j forms column j of the inverse by the same forward
-// and back substitution as k_block_inverse_wave.  Same operations, same order,
-// same bits.
+// (bs 16 and 25).  Lane r holds row r of the block for the whole factorisation
+// and tracks the position `pos` that row has in the pivoted order, so a row
+// exchange is two position updates instead of moving the rows.  Step k: the
+// first position >= k of largest |a_.k| wins (a reduction over the half by DPP
+// and one swizzle, keyed by position), its lane and the lane at position k
+// trade positions, the pivot row -- final from here on -- is written once to
+// row k of the half's LDS factor slot, and every lane at a later position
+// forms its multiplier and updates its row from that LDS row.  Lane j then
+// forms column j of the inverse by the forward and back substitution of
+// k_block_inverse_wave.  Same operations on the same values in the same order:
+// the same bits.
 template <int BS>
 __global__ __launch_bounds__(256) void k_block_inverse_rows(const int *__restrict__ rowptr,
                                                            const int *__restrict__ colidx,
@@ -186,11 +217,11 @@ __global__ __launch_bounds__(256) void k_block_inverse_rows(const int *__restric
                                                            int *__restrict__ singular_min) {
     static_assert(BS >= 2 && BS <= 32, "a block row per lane of a half wave");
     constexpr int BB = BS * BS;
+    constexpr int kNone = (64 << 5) | 31;     // key of a lane that is no candidate
     __shared__ double slot[8][BB];
     __shared__ int pslot[8][32];
     const int h = threadIdx.x >> 5;           // half wave: one block
     const int r = threadIdx.x & 31;           // its row
-    const int base = threadIdx.x & 32;        // first lane of the half in the wave
     const int I = blockIdx.x * 8 + h;
     const bool on = I < nb && !(skip && skip[I]);
     // the diagonal block's position in row I
@@ -203,57 +234,51 @@ __global__ __launch_bounds__(256) void k_block_inverse_rows(const int *__restric
     bool live = on && dpos >= 0;
     if (on && dpos < 0 && r == 0) atomicMin(singular_min, I);   // validated before; never taken for valid input
     double a[BS];
-    int perm = r;
     {
         const double *src = vals + static_cast<int64_t>(live ? dpos : 0) * BB + (r < BS ? r : 0) * BS;
 #pragma unroll
         for (int c = 0; c < BS; ++c) a[c] = (live && r < BS) ? src[c] : 0.0;
     }
+    double *fac = slot[h];
+    int *pm = pslot[h];
+    int pos = r;   // lanes r >= BS keep positions >= BS: never candidates, never updated
 #pragma unroll
     for (int k = 0; k < BS; ++k) {
-        // pivot: the first row >= k of largest |a_rk|
         double v = -1.0;
-        int idx = BS;
-        if (r >= k && r < BS) {
+        int key = kNone;
+        if (pos >= k && pos < BS) {
             v = fabs(a[k]);
-            idx = r;
+            key = (pos << 5) | r;
         }
-#pragma unroll
-        for (int o = 16; o > 0; o >>= 1) {
-            const double ov = __shfl_xor(v, o, kWave);
-            const int oi = __shfl_xor(idx, o, kWave);
-            if (ov > v || (ov == v && oi < idx)) {
-                v = ov;
-                idx = oi;
-            }
-        }
+        pivot_take(v, key, dpp_move<0xB1>(v), dpp_move<0xB1>(key));     // quad_perm 1,0,3,2
+        pivot_take(v, key, dpp_move<0x4E>(v), dpp_move<0x4E>(key));     // quad_perm 2,3,0,1
+        pivot_take(v, key, dpp_move<0x141>(v), dpp_move<0x141>(key));   // row_half_mirror
+        pivot_take(v, key, dpp_move<0x140>(v), dpp_move<0x140>(key));   // row_mirror
+        pivot_take(v, key, swz16(v), swz16(key));
         if (live && !(v > 0.0)) {
             if (r == 0) atomicMin(singular_min, I);
             live = false;
         }
-        // whole-row exchange of rows k and idx
-        const int from = base + (r == k ? idx : (r == idx ? k : r));
-        if (__any(idx != k)) {
+        // exchange positions k and wpos (the pivot row's lane p moves to k)
+        const int wpos = key >> 5, p = key & 31;
+        if (pos == k)
+            pos = wpos;
+        else if (r == p)
+            pos = k;
+        if (pos == k) {
 #pragma unroll
-            for (int c = 0; c < BS; ++c) a[c] = __shfl(a[c], from, kWave);
-            perm = __shfl(perm, from, kWave);
+            for (int c = 0; c < BS; ++c) fac[k * BS + c] = a[c];
         }
-        // multipliers and the trailing update with the pivot row broadcast
-        const double piv = __shfl(a[k], base + k, kWave);
-        if (r > k && r < BS) a[k] = a[k] / piv;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (pos > k && pos < BS) {
+            a[k] = a[k] / fac[k * BS + k];
 #pragma unroll
-        for (int j = k + 1; j < BS; ++j) {
-            const double akj = __shfl(a[j], base + k, kWave);
-            if (r > k && r < BS) a[j] = __builtin_fma(-a[k], akj, a[j]);
+            for (int j = k + 1; j < BS; ++j) a[j] = __builtin_fma(-a[k], fac[k * BS + j], a[j]);
         }
     }
-    double *fac = slot[h];
-    int *pm = pslot[h];
-    if (r < BS) {
-#pragma unroll
-        for (int c = 0; c < BS; ++c) fac[r * BS + c] = a[c];
-        pm[r] = perm;
-    }
+    if (r < BS && pos < BS) pm[pos] = r;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

@@ -790,7 +790,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int row = lane & 15, kk = lane >> 4;
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + w;
+    const int64_t t = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
     if (t >= nnz) return;   // whole waves; no workgroup barrier below
     double *xs = slot[w], *ys = slot[w] + BB;
     MfmaAcc<BS> kacc, acc;

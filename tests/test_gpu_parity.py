@@ -133,6 +133,47 @@ def test_block_inverse_and_strength_bit_exact():
     compare_hierarchies(G, O)
 
 
+def _tied_blocks(nb, bs, seed):
+    """nb nonsingular bs x bs blocks of small integers, so that the pivot search
+    meets many ties in |a_ik| (equal values and opposite signs) and zeros."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((nb, bs, bs))
+    n = 0
+    while n < nb:
+        B = rng.integers(-2, 3, size=(bs, bs)).astype(np.float64)
+        if abs(np.linalg.det(B)) < 0.5 or np.linalg.cond(B) > 1e6:
+            continue
+        out[n] = B
+        n += 1
+    return out
+
+
+@pytest.mark.parametrize("bs", [4, 7, 9, 16, 25])
+def test_block_inverse_pivot_ties_bit_exact(bs):
+    """D^-1 of blocks full of pivot ties against the oracle's LU, block by block:
+    the first row of largest magnitude must win on every kernel that forms D^-1
+    (one thread per block at bs 4 and 9, a half wave per block at 16 and 25,
+    one wave per block otherwise)."""
+    import paper_1704_05001_amd as P
+    _need_gpu()
+    nb = 100
+    _say(f"test: block inverse with pivot ties (bs {bs}, {nb} blocks)")
+    diag = _tied_blocks(nb, bs, seed=bs)
+    # block lower bidiagonal: block I also depends on block I - 1 (weakly)
+    rows = [[0]] + [[I - 1, I] for I in range(1, nb)]
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    ci = np.concatenate([np.array(r) for r in rows]).astype(np.int32)
+    va = np.random.default_rng(1).uniform(-1, 1, size=(len(ci), bs, bs)) * 1e-3
+    rowid = np.repeat(np.arange(nb), np.diff(rp))
+    va[rowid == ci] = diag
+    # (two levels: the second is solved directly, whatever the splitting gives)
+    G = P.Hierarchy(*to_dev(rp, ci, va), bs, P.Params(degree=1, max_coarse_dofs=bs, max_levels=2))
+    dinv = G.level(0, fields=("dinv",))["dinv"].cpu().numpy().reshape(nb, bs, bs)
+    for I in range(nb):
+        assert np.array_equal(oracle.block_inverse(diag[I]), dinv[I]), I
+    G.close()
+
+
 @pytest.mark.parametrize("name,N", [("dg_q1_32", None), ("dg_q2_256_curved", 24), ("dg_q4_512_jitter", 6),
                                     ("dg_q3_256_curved_sigma", 8)])
 def test_setup_parity_configs(name, N):
