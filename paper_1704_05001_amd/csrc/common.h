@@ -214,6 +214,14 @@ void launch_fill_Acf(const int *rowptr, const int *colidx, const int8_t *cf, con
 void launch_block_product(int64_t n, int bs, const double *X, const int *xi, const double *Y, const int *yi,
                           double sign, double *out, hipStream_t s, const int *count = nullptr,
                           uint32_t *rmask = nullptr);
+// out[t] = sign * ((S[srcS[t]] + W[srcW[t]]) * Y[yi[t]]) for the first *count
+// <= n blocks of a sum's pattern (srcS / srcW = -1: that term is absent), the
+// sum added entry by entry as bsr_add adds it and the product formed as
+// launch_block_product forms it, without storing the sum (9x9, 16x16 and 25x25
+// blocks, matrix cores); rmask as there
+void launch_sum_product(int64_t n, int bs, const double *S, const int *srcS, const double *W, const int *srcW,
+                        const double *Y, const int *yi, double sign, double *out, hipStream_t s, const int *count,
+                        uint32_t *rmask);
 // out[t] = Y[src[t]] for t < n (count, device, nullable: t < *count <= n)
 void launch_block_gather(int64_t n, int bs, const double *Y, const int *src, double *out, hipStream_t s,
                          const int *count = nullptr);
@@ -225,7 +233,11 @@ void launch_rows_of(const int *rowptr, int nrows, int *rowid, hipStream_t s);
 void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipStream_t s);
 // O = S + W (union pattern, S's value first).  O's block count stays on the
 // device (O.nnzb = -1, arrays of S.bound() + W.bound() blocks).
-void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s);
+// With srcS and srcW given, only the pattern is formed: O.vals stays empty and
+// block t of the sum is S's block (*srcS)[t] plus W's block (*srcW)[t] (-1:
+// absent), for launch_sum_product.
+void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s, DBuf<int> *srcS = nullptr,
+             DBuf<int> *srcW = nullptr);
 // The Galerkin product K = R A P with R = [Z I] (identity at column cpts[i] of
 // row i) and P one-point through pmap, filtered by drop.  K block (i, J) is the
 // sum, in ascending fine column j, of the blocks (R A)_ij with pmap[j] = J, each

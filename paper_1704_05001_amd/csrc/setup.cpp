@@ -371,20 +371,29 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
                             W0.colidx.get(), wsrc.get(), s);
             launch_block_gather(nW, bs, L.A.vals.get(), wsrc.get(), W0.vals.get(), s);
         }
-        // S = ((W_0 + W_1) + W_2) + ...,  W_i = W_{i-1} T
+        // S = ((W_0 + W_1) + W_2) + ...,  W_i = W_{i-1} T.  On the matrix cores the
+        // last sum is not stored: Z's product below adds its two terms itself.
+        const bool masks = use_matrix_cores(bs);   // the matrix-core products give each block's nonzero rows
         DevBSR Wprev = std::move(W0);
-        DevBSR S;
+        DevBSR S, Slast;
+        DBuf<int> srcS, srcW;
         bool s_is_wprev = true;
         for (int d = 1; d <= p.degree; ++d) {
             DevBSR Wd;
             spgemm(Wprev, nullptr, T, Wd, s);
             DevBSR Snew;
-            bsr_add(s_is_wprev ? Wprev : S, Wd, Snew, s);
+            if (masks && d == p.degree) {
+                Slast = std::move(s_is_wprev ? Wprev : S);
+                bsr_add(Slast, Wd, Snew, s, &srcS, &srcW);
+            } else {
+                bsr_add(s_is_wprev ? Wprev : S, Wd, Snew, s);
+            }
             S = std::move(Snew);
             s_is_wprev = false;
             Wprev = std::move(Wd);
         }
         DevBSR &Ssum = s_is_wprev ? Wprev : S;
+        const bool fused_sum = srcS.get() != nullptr;   // Ssum.vals not stored: Slast + Wprev
         // Z_IJ = -(S_IJ Dinv_J)
         L.Z.nb = nc;
         L.Z.ncols = n;
@@ -394,13 +403,16 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         L.Z.rowptr = std::move(Ssum.rowptr);
         L.Z.colidx = std::move(Ssum.colidx);
         L.Z.vals.alloc(static_cast<size_t>(L.Z.cap) * bb);
-        const bool masks = use_matrix_cores(bs);   // the matrix-core products give each block's nonzero rows
         if (masks) L.zmask.alloc(static_cast<size_t>(L.Z.cap));
         {
             TimerScope ts(TK_BLOCKPROD, l, s);
-            launch_block_product(L.Z.cap, bs, Ssum.vals.get(), nullptr, L.dinv.get(), L.Z.colidx.get(), -1.0,
-                                 L.Z.vals.get(), s, L.Z.nnzb < 0 ? L.Z.rowptr.get() + nc : nullptr,
-                                 masks ? L.zmask.get() : nullptr);
+            const int *zcount = L.Z.nnzb < 0 ? L.Z.rowptr.get() + nc : nullptr;
+            if (fused_sum)
+                launch_sum_product(L.Z.cap, bs, Slast.vals.get(), srcS.get(), Wprev.vals.get(), srcW.get(),
+                                   L.dinv.get(), L.Z.colidx.get(), -1.0, L.Z.vals.get(), s, zcount, L.zmask.get());
+            else
+                launch_block_product(L.Z.cap, bs, Ssum.vals.get(), nullptr, L.dinv.get(), L.Z.colidx.get(), -1.0,
+                                     L.Z.vals.get(), s, zcount, masks ? L.zmask.get() : nullptr);
         }
         // Galerkin: K = R A P with R = [Z I], filtered; K's block sizes come along
         auto next = std::make_unique<Level>();

@@ -880,6 +880,44 @@ __global__ __launch_bounds__(256) void k_block_product_mfma(int64_t n, const dou
     }
 }
 
+// The same product with X the blocks of a sum S + W that is never stored: block
+// t adds S's block srcS[t] and W's block srcW[t] (-1: absent) entry by entry as
+// the sum's own kernel does, so the results equal storing the sum first.
+template <int BS>
+__global__ __launch_bounds__(256) void k_sum_product_mfma(int64_t n, const double *__restrict__ S,
+                                                         const int *__restrict__ srcS, const double *__restrict__ W,
+                                                         const int *__restrict__ srcW, const double *__restrict__ Y,
+                                                         const int *__restrict__ yi, double sign,
+                                                         double *__restrict__ out, const int *__restrict__ count,
+                                                         uint32_t *__restrict__ rmask) {
+    constexpr int bb = BS * BS;
+    const int lane = threadIdx.x & 63;
+    const int row = lane & 15, kk = lane >> 4;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (t >= (count ? *count : n)) return;   // whole waves
+    const int ia = srcS[t], ib = srcW[t];
+    const double *x1 = S + static_cast<int64_t>(ia < 0 ? 0 : ia) * bb;
+    const double *x2 = W + static_cast<int64_t>(ib < 0 ? 0 : ib) * bb;
+    const double *y = Y + static_cast<int64_t>(yi[t]) * bb;
+    MfmaOperands<BS> op;
+    op.load_sum_product(x1, ia >= 0, x2, ib >= 0, y, row, kk);
+    MfmaAcc<BS> acc;
+    acc.zero();
+    op.apply_product(acc);
+    double *o = out + t * bb;
+    uint32_t bits = 0u;
+    mfma_for_entries<BS>(acc, row, kk, [&](int i, int j, double v) {
+        const double w = sign * v;
+        o[i * BS + j] = w;
+        if (w != 0.0) bits |= 1u << i;
+    });
+    if (rmask) {
+#pragma unroll
+        for (int w = 32; w > 0; w >>= 1) bits |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(bits), w, 64));
+        if (lane == 0) rmask[t] = bits;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_block_gather(int64_t n, int bb, const double *__restrict__ Y,
                                                      const int *__restrict__ src, double *__restrict__ out,
                                                      const int *__restrict__ count) {
@@ -1081,6 +1119,21 @@ void launch_block_product(int64_t n, int bs, const double *X, const int *xi, con
         case 25: k_block_product<25><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out, count); break;
         default: k_block_product<0><<<grid, 256, 0, s>>>(n, bs, X, xi, Y, yi, sign, out, count); break;
     }
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_sum_product(int64_t n, int bs, const double *S, const int *srcS, const double *W, const int *srcW,
+                        const double *Y, const int *yi, double sign, double *out, hipStream_t s, const int *count,
+                        uint32_t *rmask) {
+    if (n <= 0) return;
+    if (!use_matrix_cores(bs)) fail(NAIR_EDEVICE, "launch_sum_product: matrix-core block sizes only");
+    const unsigned mgrid = static_cast<unsigned>((n + 3) / 4);   // four waves (blocks) per workgroup
+    if (bs == 9)
+        k_sum_product_mfma<9><<<mgrid, 256, 0, s>>>(n, S, srcS, W, srcW, Y, yi, sign, out, count, rmask);
+    else if (bs == 16)
+        k_sum_product_mfma<16><<<mgrid, 256, 0, s>>>(n, S, srcS, W, srcW, Y, yi, sign, out, count, rmask);
+    else
+        k_sum_product_mfma<25><<<mgrid, 256, 0, s>>>(n, S, srcS, W, srcW, Y, yi, sign, out, count, rmask);
     NAIR_HIP(hipGetLastError());
 }
 

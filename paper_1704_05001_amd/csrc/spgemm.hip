@@ -1223,7 +1223,7 @@ void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipSt
     spgemm_values(X, Y, P, C, s);
 }
 
-void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s) {
+void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s, DBuf<int> *srcS_out, DBuf<int> *srcW_out) {
     const int m = S.nb;
     const int bs = S.bs;
     O.nb = m;
@@ -1240,11 +1240,18 @@ void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s) {
     O.nnzb = -1;
     O.cap = cap;
     O.colidx.alloc(static_cast<size_t>(cap));
-    O.vals.alloc(static_cast<size_t>(cap) * bs * bs);
+    const bool pattern_only = srcS_out && srcW_out;
+    if (!pattern_only) O.vals.alloc(static_cast<size_t>(cap) * bs * bs);
     if (cap == 0 || m == 0) return;
     DBuf<int> srcS(static_cast<size_t>(cap)), srcW(static_cast<size_t>(cap));
     k_add_fill<<<grid_for(m, 256), 256, 0, s>>>(S.rowptr.get(), S.colidx.get(), W.rowptr.get(), W.colidx.get(), m,
                                                 O.rowptr.get(), O.colidx.get(), srcS.get(), srcW.get());
+    if (pattern_only) {
+        NAIR_HIP(hipGetLastError());
+        *srcS_out = std::move(srcS);
+        *srcW_out = std::move(srcW);
+        return;
+    }
     const int64_t total = cap * bs * bs;
     if (bs * bs >= 64)
         k_add_values_wave<<<cap_grid((cap + 3) / 4), 256, 0, s>>>(O.rowptr.get() + m, bs * bs, S.vals.get(),
