@@ -214,14 +214,27 @@ void launch_fill_Acf(const int *rowptr, const int *colidx, const int8_t *cf, con
 void launch_block_product(int64_t n, int bs, const double *X, const int *xi, const double *Y, const int *yi,
                           double sign, double *out, hipStream_t s, const int *count = nullptr,
                           uint32_t *rmask = nullptr);
-// out[t] = sign * ((S[srcS[t]] + W[srcW[t]]) * Y[yi[t]]) for the first *count
-// <= n blocks of a sum's pattern (srcS / srcW = -1: that term is absent), the
-// sum added entry by entry as bsr_add adds it and the product formed as
-// launch_block_product forms it, without storing the sum (9x9, 16x16 and 25x25
-// blocks, matrix cores); rmask as there
-void launch_sum_product(int64_t n, int bs, const double *S, const int *srcS, const double *W, const int *srcW,
-                        const double *Y, const int *yi, double sign, double *out, hipStream_t s, const int *count,
-                        uint32_t *rmask);
+// The terms of a sum of block matrices that is not stored: block t of the sum
+// is the sum, in term order, of vals[i]'s block map[i][t] over the terms with
+// map[i][t] >= 0 (the first present term, then each later one added to it: the
+// order of repeated bsr_add).
+constexpr int kMaxSumTerms = 17;   // Neumann degree 16 and W_0
+struct SumTerms {
+    const double *vals[kMaxSumTerms] = {};
+    const int *map[kMaxSumTerms] = {};
+    int n = 0;
+};
+// out[t] = sign * ((sum of the terms' blocks) * Y[yi[t]]) for the first *count
+// <= n blocks of the sum's pattern, the sum added entry by entry as bsr_add adds
+// it and the product formed as launch_block_product forms it (9x9, 16x16 and
+// 25x25 blocks, matrix cores); rmask as there
+void launch_sum_product(int64_t n, int bs, const SumTerms &terms, const double *Y, const int *yi, double sign,
+                        double *out, hipStream_t s, const int *count, uint32_t *rmask);
+// After O = S + W (pattern only, srcS from bsr_add): maps[i] (term i's block of
+// each S block) become term i's block of each O block (-1 where srcS is -1),
+// for the first *count <= cap blocks of O.
+void compose_term_maps(int64_t cap, const int *count, const int *srcS, std::vector<DBuf<int>> &maps,
+                       hipStream_t s);
 // out[t] = Y[src[t]] for t < n (count, device, nullable: t < *count <= n)
 void launch_block_gather(int64_t n, int bs, const double *Y, const int *src, double *out, hipStream_t s,
                          const int *count = nullptr);

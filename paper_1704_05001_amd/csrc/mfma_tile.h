@@ -74,27 +74,6 @@ struct MfmaOperands {
             }
     }
 
-    // (X1 + X2) Y with the sum taken entry by entry (a term may be absent), X1 + X2 not
-    // stored
-    __device__ void load_sum_product(const double *__restrict__ x1, bool has1, const double *__restrict__ x2,
-                                     bool has2, const double *__restrict__ y, int row, int kk) {
-        ident = false;
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-            for (int q = 0; q < KQ; ++q) {
-                const int c = 4 * q + kk;
-                const int i = 16 * t + row;
-                double v = 0.0;
-                if (i < BS && c < BS) {
-                    const int e = i * BS + c;
-                    v = (has1 && has2) ? x1[e] + x2[e] : (has1 ? x1[e] : x2[e]);
-                }
-                a[t][q] = v;
-                b[t][q] = (i < BS && c < BS) ? y[c * BS + i] : 0.0;
-            }
-    }
-
     // the steps of a product loaded by load_product
     __device__ void apply_product(MfmaAcc<BS> &acc) const {
 #pragma unroll

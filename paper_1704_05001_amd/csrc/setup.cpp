@@ -371,29 +371,39 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
                             W0.colidx.get(), wsrc.get(), s);
             launch_block_gather(nW, bs, L.A.vals.get(), wsrc.get(), W0.vals.get(), s);
         }
-        // S = ((W_0 + W_1) + W_2) + ...,  W_i = W_{i-1} T.  On the matrix cores the
-        // last sum is not stored: Z's product below adds its two terms itself.
+        // S = ((W_0 + W_1) + W_2) + ...,  W_i = W_{i-1} T.  On the matrix cores S
+        // is not stored: its pattern comes with one map per term (term i's block
+        // of each S block, or -1), and Z's product below adds the terms itself.
         const bool masks = use_matrix_cores(bs);   // the matrix-core products give each block's nonzero rows
-        DevBSR Wprev = std::move(W0);
-        DevBSR S, Slast;
-        DBuf<int> srcS, srcW;
-        bool s_is_wprev = true;
+        const bool fused_sum = masks && p.degree >= 1;
+        std::vector<DevBSR> terms;   // W_0 .. W_k (fused) or the last W (stored sums)
+        std::vector<DBuf<int>> tmaps;
+        terms.push_back(std::move(W0));
+        DevBSR S;
+        bool s_is_w0 = true;
         for (int d = 1; d <= p.degree; ++d) {
             DevBSR Wd;
-            spgemm(Wprev, nullptr, T, Wd, s);
+            spgemm(terms.back(), nullptr, T, Wd, s);
             DevBSR Snew;
-            if (masks && d == p.degree) {
-                Slast = std::move(s_is_wprev ? Wprev : S);
-                bsr_add(Slast, Wd, Snew, s, &srcS, &srcW);
+            if (fused_sum) {
+                DBuf<int> mS, mW;
+                bsr_add(s_is_w0 ? terms[0] : S, Wd, Snew, s, &mS, &mW);
+                if (d == 1 || !mS.get()) {   // (no blocks: maps stay empty)
+                    tmaps.clear();
+                    tmaps.push_back(std::move(mS));
+                } else {
+                    compose_term_maps(Snew.bound(), Snew.rowptr.get() + nc, mS.get(), tmaps, s);
+                }
+                tmaps.push_back(std::move(mW));
+                terms.push_back(std::move(Wd));
             } else {
-                bsr_add(s_is_wprev ? Wprev : S, Wd, Snew, s);
+                bsr_add(s_is_w0 ? terms[0] : S, Wd, Snew, s);
+                terms.back() = std::move(Wd);
             }
             S = std::move(Snew);
-            s_is_wprev = false;
-            Wprev = std::move(Wd);
+            s_is_w0 = false;
         }
-        DevBSR &Ssum = s_is_wprev ? Wprev : S;
-        const bool fused_sum = srcS.get() != nullptr;   // Ssum.vals not stored: Slast + Wprev
+        DevBSR &Ssum = s_is_w0 ? terms[0] : S;
         // Z_IJ = -(S_IJ Dinv_J)
         L.Z.nb = nc;
         L.Z.ncols = n;
@@ -407,10 +417,18 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         {
             TimerScope ts(TK_BLOCKPROD, l, s);
             const int *zcount = L.Z.nnzb < 0 ? L.Z.rowptr.get() + nc : nullptr;
-            if (fused_sum)
-                launch_sum_product(L.Z.cap, bs, Slast.vals.get(), srcS.get(), Wprev.vals.get(), srcW.get(),
-                                   L.dinv.get(), L.Z.colidx.get(), -1.0, L.Z.vals.get(), s, zcount, L.zmask.get());
-            else
+            if (fused_sum) {
+                if (L.Z.cap > 0) {
+                    SumTerms st;
+                    st.n = static_cast<int>(terms.size());
+                    for (int i = 0; i < st.n; ++i) {
+                        st.vals[i] = terms[i].vals.get();
+                        st.map[i] = tmaps[i].get();
+                    }
+                    launch_sum_product(L.Z.cap, bs, st, L.dinv.get(), L.Z.colidx.get(), -1.0, L.Z.vals.get(), s,
+                                       zcount, L.zmask.get());
+                }
+            } else
                 launch_block_product(L.Z.cap, bs, Ssum.vals.get(), nullptr, L.dinv.get(), L.Z.colidx.get(), -1.0,
                                      L.Z.vals.get(), s, zcount, masks ? L.zmask.get() : nullptr);
         }

@@ -880,27 +880,54 @@ __global__ __launch_bounds__(256) void k_block_product_mfma(int64_t n, const dou
     }
 }
 
-// The same product with X the blocks of a sum S + W that is never stored: block
-// t adds S's block srcS[t] and W's block srcW[t] (-1: absent) entry by entry as
-// the sum's own kernel does, so the results equal storing the sum first.
+// The same product with X the blocks of a sum that is never stored: block t
+// of X is the sum, in term order, of the present terms' blocks, added entry by
+// entry as repeated bsr_add adds them, so the results equal storing the sum
+// first.  (Presence is per block: the branches are uniform over the wave.)
 template <int BS>
-__global__ __launch_bounds__(256) void k_sum_product_mfma(int64_t n, const double *__restrict__ S,
-                                                         const int *__restrict__ srcS, const double *__restrict__ W,
-                                                         const int *__restrict__ srcW, const double *__restrict__ Y,
-                                                         const int *__restrict__ yi, double sign,
-                                                         double *__restrict__ out, const int *__restrict__ count,
-                                                         uint32_t *__restrict__ rmask) {
+__global__ __launch_bounds__(256) void k_sum_product_mfma(int64_t n, const SumTerms terms,
+                                                         const double *__restrict__ Y, const int *__restrict__ yi,
+                                                         double sign, double *__restrict__ out,
+                                                         const int *__restrict__ count, uint32_t *__restrict__ rmask) {
     constexpr int bb = BS * BS;
+    constexpr int NT = MfmaShape<BS>::NT, KQ = MfmaShape<BS>::KQ;
     const int lane = threadIdx.x & 63;
     const int row = lane & 15, kk = lane >> 4;
     const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (t >= (count ? *count : n)) return;   // whole waves
-    const int ia = srcS[t], ib = srcW[t];
-    const double *x1 = S + static_cast<int64_t>(ia < 0 ? 0 : ia) * bb;
-    const double *x2 = W + static_cast<int64_t>(ib < 0 ? 0 : ib) * bb;
-    const double *y = Y + static_cast<int64_t>(yi[t]) * bb;
     MfmaOperands<BS> op;
-    op.load_sum_product(x1, ia >= 0, x2, ib >= 0, y, row, kk);
+    op.ident = false;
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) op.a[u][q] = 0.0;
+    bool first = true;
+    for (int k = 0; k < terms.n; ++k) {
+        const int src = terms.map[k][t];
+        if (src < 0) continue;
+        const double *x = terms.vals[k] + static_cast<int64_t>(src) * bb;
+#pragma unroll
+        for (int u = 0; u < NT; ++u)
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) {
+                const int c = 4 * q + kk;
+                const int i = 16 * u + row;
+                if (i < BS && c < BS) {
+                    const double v = x[i * BS + c];
+                    op.a[u][q] = first ? v : op.a[u][q] + v;
+                }
+            }
+        first = false;
+    }
+    const double *y = Y + static_cast<int64_t>(yi[t]) * bb;
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            const int c = 4 * q + kk;
+            const int i = 16 * u + row;
+            op.b[u][q] = (i < BS && c < BS) ? y[c * BS + i] : 0.0;
+        }
     MfmaAcc<BS> acc;
     acc.zero();
     op.apply_product(acc);
@@ -916,6 +943,20 @@ __global__ __launch_bounds__(256) void k_sum_product_mfma(int64_t n, const doubl
         for (int w = 32; w > 0; w >>= 1) bits |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(bits), w, 64));
         if (lane == 0) rmask[t] = bits;
     }
+}
+
+// maps[i][t] = srcS[t] >= 0 ? old[i][srcS[t]] : -1 for every term i
+struct MapsIO {
+    const int *old[kMaxSumTerms] = {};
+    int *out[kMaxSumTerms] = {};
+    int n = 0;
+};
+__global__ __launch_bounds__(256) void k_compose_maps(int64_t cap, const int *__restrict__ count,
+                                                     const int *__restrict__ srcS, const MapsIO io) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= cap || t >= *count) return;
+    const int a = srcS[t];
+    for (int i = 0; i < io.n; ++i) io.out[i][t] = a >= 0 ? io.old[i][a] : -1;
 }
 
 __global__ __launch_bounds__(256) void k_block_gather(int64_t n, int bb, const double *__restrict__ Y,
@@ -1122,19 +1163,39 @@ void launch_block_product(int64_t n, int bs, const double *X, const int *xi, con
     NAIR_HIP(hipGetLastError());
 }
 
-void launch_sum_product(int64_t n, int bs, const double *S, const int *srcS, const double *W, const int *srcW,
-                        const double *Y, const int *yi, double sign, double *out, hipStream_t s, const int *count,
-                        uint32_t *rmask) {
+void launch_sum_product(int64_t n, int bs, const SumTerms &terms, const double *Y, const int *yi, double sign,
+                        double *out, hipStream_t s, const int *count, uint32_t *rmask) {
     if (n <= 0) return;
     if (!use_matrix_cores(bs)) fail(NAIR_EDEVICE, "launch_sum_product: matrix-core block sizes only");
+    if (terms.n < 1 || terms.n > kMaxSumTerms) fail(NAIR_EDEVICE, "launch_sum_product: 1 to 17 terms");
+    for (int i = 0; i < terms.n; ++i)
+        if (!terms.map[i]) fail(NAIR_EDEVICE, "launch_sum_product: a term without its map");
     const unsigned mgrid = static_cast<unsigned>((n + 3) / 4);   // four waves (blocks) per workgroup
     if (bs == 9)
-        k_sum_product_mfma<9><<<mgrid, 256, 0, s>>>(n, S, srcS, W, srcW, Y, yi, sign, out, count, rmask);
+        k_sum_product_mfma<9><<<mgrid, 256, 0, s>>>(n, terms, Y, yi, sign, out, count, rmask);
     else if (bs == 16)
-        k_sum_product_mfma<16><<<mgrid, 256, 0, s>>>(n, S, srcS, W, srcW, Y, yi, sign, out, count, rmask);
+        k_sum_product_mfma<16><<<mgrid, 256, 0, s>>>(n, terms, Y, yi, sign, out, count, rmask);
     else
-        k_sum_product_mfma<25><<<mgrid, 256, 0, s>>>(n, S, srcS, W, srcW, Y, yi, sign, out, count, rmask);
+        k_sum_product_mfma<25><<<mgrid, 256, 0, s>>>(n, terms, Y, yi, sign, out, count, rmask);
     NAIR_HIP(hipGetLastError());
+}
+
+void compose_term_maps(int64_t cap, const int *count, const int *srcS, std::vector<DBuf<int>> &maps,
+                       hipStream_t s) {
+    if (static_cast<int>(maps.size()) + 1 > kMaxSumTerms) fail(NAIR_EDEVICE, "compose_term_maps: too many terms");
+    std::vector<DBuf<int>> out(maps.size());
+    MapsIO io;
+    io.n = static_cast<int>(maps.size());
+    for (int i = 0; i < io.n; ++i) {
+        out[i].alloc(static_cast<size_t>(std::max<int64_t>(cap, 1)));
+        io.old[i] = maps[i].get();
+        io.out[i] = out[i].get();
+    }
+    if (cap > 0) {
+        k_compose_maps<<<grid_for(cap, 256), 256, 0, s>>>(cap, count, srcS, io);
+        NAIR_HIP(hipGetLastError());
+    }
+    maps = std::move(out);
 }
 
 void launch_block_gather(int64_t n, int bs, const double *Y, const int *src, double *out, hipStream_t s,
