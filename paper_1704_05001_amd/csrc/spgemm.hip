@@ -642,147 +642,35 @@ __global__ __launch_bounds__(256) void k_spgemm_pairs(int64_t nnz, int bs_rt, co
     }
 }
 
-// The same products on the matrix cores (bs 9, 16, 25; mfma_tile.h): one wave
-// per output block holds it in 16x16 FP64 accumulator tiles; each pair adds
+// The same sums on the matrix cores (bs 9, 16, 25; mfma_tile.h).  One wave
+// holds one output block in 16x16 FP64 accumulator tiles; each pair adds
 // ceil(bs/4) 16x16x4 steps per tile over c = 4q .. 4q+3, zero beyond bs.  A
 // 16x16x4 FP64 step updates each entry as the fma chain over its four c in
 // ascending order, so the sums are the per-thread chains above (padding adds
 // exact zeros); identity pairs add Y's entries plainly, in their place in the
-// pair order.
-template <int BS>
-__device__ inline void mfma_load_pair(MfmaOperands<BS> &f, const int2 pr, const double *__restrict__ X,
-                                      const double *__restrict__ Y, int row, int kk) {
-    constexpr int64_t bb = BS * BS;
-    f.load(pr.x < 0 ? nullptr : X + pr.x * bb, Y + pr.y * bb, row, kk);
+// pair order.  The block is written as 0 + the accumulator.
+//
+// A pair's two blocks are read with consecutive lanes on consecutive words
+// (ceil(bs^2/64) loads per lane and block), written to the wave's LDS slot,
+// and the fragments taken from there.  The sums are short (a few pairs per
+// block), so a wave that started each block from its index would wait on
+// three dependent loads per block (the pair range, the pair, the blocks):
+// instead each workgroup owns a contiguous range of output blocks (ranges
+// ordered so that each XCD runs a contiguous part of the output), its four
+// waves take every fourth block of it, and each wave keeps ahead of itself --
+// the pair range two blocks on, the pair indices of the next block, and the
+// next pair's blocks (of this block or the next) in registers while the
+// current pair's steps run.  Also writes each block's max-abs size and the bit
+// mask of its nonzero rows (knorm == nullptr: neither).
+__device__ inline int2 shfl_pair(int2 v, int src) {
+    return int2{__shfl(v.x, src, 64), __shfl(v.y, src, 64)};
 }
 
 template <int BS>
-__global__ __launch_bounds__(256) void k_spgemm_mfma(int64_t nnz, const int *__restrict__ pairptr,
-                                                    const int2 *__restrict__ pairs, const double *__restrict__ X,
-                                                    const double *__restrict__ Y, double *__restrict__ C) {
-    constexpr int bb = BS * BS;
-    const int lane = threadIdx.x & 63;
-    const int row = lane & 15, kk = lane >> 4;   // A: row i, B: column j; both k = kk
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
-    if (t >= nnz) return;   // whole waves
-    MfmaAcc<BS> acc;
-    acc.zero();
-    const int k0 = pairptr[t], k1 = pairptr[t + 1];
-    if (k0 < k1) {
-        // the next pair's operands load while this pair's steps run
-        MfmaOperands<BS> cur;
-        mfma_load_pair<BS>(cur, pairs[k0], X, Y, row, kk);
-        for (int k = k0; k < k1; ++k) {
-            MfmaOperands<BS> nxt = cur;
-            if (k + 1 < k1) mfma_load_pair<BS>(nxt, pairs[k + 1], X, Y, row, kk);
-            cur.apply(acc, row, kk);
-            cur = nxt;
-        }
-    }
-    double *out = C + t * bb;
-    mfma_for_entries<BS>(acc, row, kk, [&](int i, int j, double v) { out[i * BS + j] = v; });
-}
-
-// The Galerkin blocks straight from the pair lists: K block t is the sum, in
-// list order, of the R A blocks klist[kptr[t]] ..., each formed in an
-// accumulator of its own from +0 over its pairs exactly as k_spgemm_mfma forms
-// it, then added into K's accumulator (K = 0 + RA_1 + RA_2 + ...: the sums of
-// the merge over stored R A blocks, without storing them).  One wave per K
-// block; the lanes hold up to 64 contributing blocks' pair ranges, and the
-// walk over their pairs loads the next pair (of the same or the next block)
-// while the current one's steps run.  Also writes the block's max-abs size
-// and the bit mask of its nonzero rows.
-template <int BS>
-__global__ __launch_bounds__(256) void k_galerkin_mfma(int64_t nnz, const int *__restrict__ kptr,
-                                                      const int *__restrict__ klist, const int *__restrict__ pairptr,
-                                                      const int2 *__restrict__ pairs, const double *__restrict__ X,
-                                                      const double *__restrict__ Y, double *__restrict__ K,
-                                                      double *__restrict__ knorm, uint32_t *__restrict__ kmask) {
-    constexpr int bb = BS * BS;
-    const int lane = threadIdx.x & 63;
-    const int row = lane & 15, kk = lane >> 4;
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
-    if (t >= nnz) return;   // whole waves
-    MfmaAcc<BS> kacc;
-    kacc.zero();
-    const int c0 = kptr[t], c1 = kptr[t + 1];
-    for (int base = c0; base < c1; base += 64) {
-        const int cnt = min(64, c1 - base);
-        int pb = 0, pe = 0;
-        if (lane < cnt) {
-            const int u = klist[base + lane];
-            pb = pairptr[u];
-            pe = pairptr[u + 1];
-        }
-        // (j, k): pair k of contributing block j; j, k and the ranges are the same in every lane
-        int j = 0;
-        int k = __shfl(pb, 0, 64), ke = __shfl(pe, 0, 64);
-        bool have = k < ke;
-        MfmaAcc<BS> acc;
-        acc.zero();
-        MfmaOperands<BS> cur{};
-        if (have) mfma_load_pair<BS>(cur, pairs[k], X, Y, row, kk);
-        while (j < cnt) {
-            int jn = j, kn = k + 1, ken = ke;
-            if (!have || kn >= ke) {   // block j ends with this pair
-                jn = j + 1;
-                if (jn < cnt) {
-                    kn = __shfl(pb, jn, 64);
-                    ken = __shfl(pe, jn, 64);
-                }
-            }
-            const bool haven = jn < cnt && kn < ken;
-            MfmaOperands<BS> nxt = cur;
-            if (haven) mfma_load_pair<BS>(nxt, pairs[kn], X, Y, row, kk);
-            if (have) cur.apply(acc, row, kk);
-            if (jn != j) {
-                kacc.add(acc);
-                acc.zero();
-            }
-            j = jn;
-            k = kn;
-            ke = ken;
-            have = haven;
-            cur = nxt;
-        }
-    }
-    double *out = K + t * bb;
-    double m = 0.0;
-    uint32_t bits = 0u;
-    mfma_for_entries<BS>(kacc, row, kk, [&](int i, int jj, double v) {
-        out[i * BS + jj] = v;
-        m = fmax(m, fabs(v));
-        if (v != 0.0) bits |= 1u << i;
-    });
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        m = fmax(m, __shfl_xor(m, o, 64));
-        bits |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(bits), o, 64));
-    }
-    if (lane == 0) {
-        knorm[t] = m;
-        kmask[t] = bits;
-    }
-}
-
-// The same Galerkin sums with each block pair's operands staged through LDS.
-// Per pair the wave reads both blocks with consecutive lanes on consecutive
-// words (ceil(bs^2/64) loads per lane and block, instead of ceil(bs/4) strided
-// fragment loads per tile row and column), writes them to its LDS slot, and
-// takes the matrix-core fragments from there; the next pair's blocks are
-// loaded into registers while the current pair's steps run, and the pair
-// index after that one is loaded a step earlier still, so no load waits on
-// an address that has just been read.  Same steps, same order, same sums as
-// k_galerkin_mfma, bit for bit (the fragments are the same numbers).  The
-// register budget is held to three waves per SIMD (no spills at bs 25): with
-// two, too few waves were left to cover the loads.
-template <int BS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_galerkin_lds(int64_t nnz, const int *__restrict__ kptr,
-                                                     const int *__restrict__ klist, const int *__restrict__ pairptr,
-                                                     const int2 *__restrict__ pairs, const double *__restrict__ X,
-                                                     const double *__restrict__ Y, double *__restrict__ K,
-                                                     double *__restrict__ knorm, uint32_t *__restrict__ kmask,
-                                                     const double *__restrict__ Y2 = nullptr) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_pair_sums(
+    int64_t nnz, int64_t per_wg, const int *__restrict__ pairptr, const int2 *__restrict__ pairs,
+    const double *__restrict__ X, const double *__restrict__ Y, const double *__restrict__ Y2,
+    double *__restrict__ K, double *__restrict__ knorm, uint32_t *__restrict__ kmask) {
     constexpr int BB = BS * BS;
     constexpr int NL = (BB + 63) / 64;   // loads per lane and block
     constexpr int NT = MfmaShape<BS>::NT, KQ = MfmaShape<BS>::KQ;
@@ -790,57 +678,50 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int row = lane & 15, kk = lane >> 4;
-    const int64_t t = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
-    if (t >= nnz) return;   // whole waves; no workgroup barrier below
+    const int64_t lo = xcd_block(blockIdx.x, gridDim.x) * per_wg;
+    const int64_t hi = lo + per_wg < nnz ? lo + per_wg : nnz;
+    int64_t t = lo + w;
+    if (t >= hi) return;   // whole waves; no workgroup barrier below
     double *xs = slot[w], *ys = slot[w] + BB;
-    MfmaAcc<BS> kacc, acc;
-    kacc.zero();
-    // (kptr == nullptr: every block is its own single contributor)
-    const int c0 = kptr ? kptr[t] : static_cast<int>(t), c1 = kptr ? kptr[t + 1] : static_cast<int>(t) + 1;
-    for (int base = c0; base < c1; base += 64) {
-        const int cnt = min(64, c1 - base);
-        int pb = 0, pe = 0;
-        if (lane < cnt) {
-            const int u = klist ? klist[base + lane] : base + lane;
-            pb = pairptr[u];
-            pe = pairptr[u + 1];
-        }
-        // walk positions (j, k): pair k of contributing block j (the same in every lane)
-        auto first = [&](int &j, int &k, int &ke) {
-            while (j < cnt) {
-                k = __shfl(pb, j, 64);
-                ke = __shfl(pe, j, 64);
-                if (k < ke) return;
-                ++j;
-            }
-        };
-        auto next = [&](int &j, int &k, int &ke) {
-            if (++k < ke) return;
-            ++j;
-            first(j, k, ke);
-        };
-        int j = 0, k = 0, ke = 0;
-        first(j, k, ke);
-        if (j >= cnt) continue;
-        acc.zero();
-        int j1 = j, k1 = k, ke1 = ke;
-        next(j1, k1, ke1);
-        int2 pr = pairs[k];
-        int2 pr1 = j1 < cnt ? pairs[k1] : int2{0, 0};
-        double xv[NL], yv[NL];
-        auto load = [&](const int2 q) {
-            // (a pair's y < 0 names block -y-1 of the second store)
-            const double *y = q.y >= 0 ? Y + static_cast<int64_t>(q.y) * BB : Y2 + static_cast<int64_t>(-q.y - 1) * BB;
-            const double *x = X + static_cast<int64_t>(q.x < 0 ? 0 : q.x) * BB;
+    double xv[NL], yv[NL];
+    auto load = [&](const int2 q) {
+        // (a pair's y < 0 names block -y-1 of the second store)
+        const double *y = q.y >= 0 ? Y + static_cast<int64_t>(q.y) * BB : Y2 + static_cast<int64_t>(-q.y - 1) * BB;
+        const double *x = X + static_cast<int64_t>(q.x < 0 ? 0 : q.x) * BB;
 #pragma unroll
-            for (int i = 0; i < NL; ++i) {
-                const int e = lane + 64 * i;
-                yv[i] = e < BB ? y[e] : 0.0;
-                xv[i] = (e < BB && q.x >= 0) ? x[e] : 0.0;
-            }
-        };
-        load(pr);
-        while (j < cnt) {
+        for (int i = 0; i < NL; ++i) {
+            const int e = lane + 64 * i;
+            yv[i] = e < BB ? y[e] : 0.0;
+            xv[i] = (e < BB && q.x >= 0) ? x[e] : 0.0;
+        }
+    };
+    auto chunk = [&](int from, int end) { return from + lane < end ? pairs[from + lane] : int2{0, 0}; };
+    // this block: pair range and the first 64 pair indices
+    int pb = pairptr[t], pe = pairptr[t + 1];
+    int2 cp = chunk(pb, pe);
+    // the next block: range and pair indices; the one after: range
+    int64_t tn = t + 4;
+    int npb = 0, npe = 0;
+    if (tn < hi) {
+        npb = pairptr[tn];
+        npe = pairptr[tn + 1];
+    }
+    int2 ncp = tn < hi ? chunk(npb, npe) : int2{0, 0};
+    int64_t tnn = tn + 4;
+    int nnpb = 0, nnpe = 0;
+    if (tnn < hi) {
+        nnpb = pairptr[tnn];
+        nnpe = pairptr[tnn + 1];
+    }
+    bool pend = false;   // xv / yv hold (or are loading) the next pair to run
+    for (;;) {
+        const int cnt = pe - pb;
+        MfmaAcc<BS> acc;
+        acc.zero();
+        for (int j = 0; j < cnt; ++j) {
+            if (j > 0 && (j & 63) == 0) cp = chunk(pb + j, pe);   // (more than 64 pairs: the next 64)
+            const int2 pr = shfl_pair(cp, j & 63);
+            if (!pend) load(pr);
             // this pair's blocks to LDS (the previous pair's fragment reads were issued before)
 #pragma unroll
             for (int i = 0; i < NL; ++i) {
@@ -850,13 +731,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                     ys[e] = yv[i];
                 }
             }
-            // the next pair's blocks and the index after it load while this pair's steps run
-            int j2 = j1, k2 = k1, ke2 = ke1;
-            int2 pr2 = {0, 0};
-            if (j1 < cnt) {
-                load(pr1);
-                next(j2, k2, ke2);
-                if (j2 < cnt) pr2 = pairs[k2];
+            pend = false;
+            // the following pair's blocks load while this pair's steps run
+            if (j + 1 < cnt) {
+                if (((j + 1) & 63) != 0) {
+                    load(shfl_pair(cp, (j + 1) & 63));
+                    pend = true;
+                }
+            } else if (tn < hi && npe > npb) {
+                load(shfl_pair(ncp, 0));
+                pend = true;
             }
             if (pr.x < 0) {   // identity pair: Y's entries added plainly
 #pragma unroll
@@ -886,37 +770,65 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                             acc.t[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj], acc.t[ti][tj], 0, 0, 0);
                 }
             }
-            if (j1 != j) {   // block j ends with this pair
-                kacc.add(acc);
-                acc.zero();
+        }
+        double *out = K + t * BB;
+        double m = 0.0;
+        uint32_t bits = 0u;
+        mfma_for_entries<BS>(acc, row, kk, [&](int i, int jj, double v) {
+            const double o = 0.0 + v;
+            out[i * BS + jj] = o;
+            m = fmax(m, fabs(o));
+            if (o != 0.0) bits |= 1u << i;
+        });
+        if (knorm) {   // (a plain sparse product takes no sizes)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                m = fmax(m, __shfl_xor(m, o, 64));
+                bits |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(bits), o, 64));
             }
-            j = j1;
-            k = k1;
-            ke = ke1;
-            pr = pr1;
-            j1 = j2;
-            k1 = k2;
-            ke1 = ke2;
-            pr1 = pr2;
+            if (lane == 0) {
+                knorm[t] = m;
+                kmask[t] = bits;
+            }
+        }
+        // on to the next block
+        t = tn;
+        if (t >= hi) break;
+        pb = npb;
+        pe = npe;
+        cp = ncp;
+        tn = tnn;
+        npb = nnpb;
+        npe = nnpe;
+        ncp = tn < hi ? chunk(npb, npe) : int2{0, 0};
+        tnn = tn + 4;
+        if (tnn < hi) {
+            nnpb = pairptr[tnn];
+            nnpe = pairptr[tnn + 1];
         }
     }
-    double *out = K + t * BB;
-    double m = 0.0;
-    uint32_t bits = 0u;
-    mfma_for_entries<BS>(kacc, row, kk, [&](int i, int jj, double v) {
-        out[i * BS + jj] = v;
-        m = fmax(m, fabs(v));
-        if (v != 0.0) bits |= 1u << i;
-    });
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        m = fmax(m, __shfl_xor(m, o, 64));
-        bits |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(bits), o, 64));
-    }
-    if (lane == 0 && knorm) {   // (a plain sparse product takes no sizes)
-        knorm[t] = m;
-        kmask[t] = bits;
-    }
+}
+
+// Sums of pair lists for nnz output blocks on the matrix cores (bs 9, 16, 25).
+void launch_pair_sums(int bs, int64_t nnz, const int *pairptr, const int2 *pairs, const double *X, const double *Y,
+                      const double *Y2, double *K, double *knorm, uint32_t *kmask, hipStream_t s) {
+    if (nnz <= 0) return;
+    // up to 3,072 workgroups of contiguous ranges (four per resident slot: the tail balances)
+    const int64_t nwg = std::min<int64_t>((nnz + 3) / 4, 3072);
+    const int64_t per_wg = (nnz + nwg - 1) / nwg;
+    const int64_t grid = (nnz + per_wg - 1) / per_wg;
+    if (bs == 9)
+        k_pair_sums<9><<<static_cast<unsigned>(grid), 256, 0, s>>>(nnz, per_wg, pairptr, pairs, X, Y, Y2, K, knorm,
+                                                                   kmask);
+    else if (bs == 16)
+        k_pair_sums<16><<<static_cast<unsigned>(grid), 256, 0, s>>>(nnz, per_wg, pairptr, pairs, X, Y, Y2, K, knorm,
+                                                                    kmask);
+    else if (bs == 25)
+        k_pair_sums<25><<<static_cast<unsigned>(grid), 256, 0, s>>>(nnz, per_wg, pairptr, pairs, X, Y, Y2, K, knorm,
+                                                                    kmask);
+    else
+        fail(NAIR_EDEVICE, "launch_pair_sums: matrix-core block sizes only");
+    NAIR_HIP(hipGetLastError());
 }
 
 // out[t] = in[src[t]] for t < *count
@@ -1195,18 +1107,9 @@ void spgemm_values(const DevBSR &X, const DevBSR &Y, const Pairs &P, DevBSR &C, 
     const int64_t total = nnz * bs;
     const unsigned grid = cap_grid((total + 255) / 256);
     TimerScope ts(TK_SPGEMM_NUM, g_timer_level, s);
-    const unsigned mgrid = static_cast<unsigned>((nnz + 3) / 4);   // four waves per workgroup
     if (use_matrix_cores(bs)) {
-        // the LDS-staged kernel with each block its own single contributor: the same sums
-        if (bs == 9)
-            k_galerkin_lds<9><<<mgrid, 256, 0, s>>>(nnz, nullptr, nullptr, P.pairptr.get(), P.pairs.get(),
-                                                    X.vals.get(), Y.vals.get(), C.vals.get(), nullptr, nullptr);
-        else if (bs == 16)
-            k_galerkin_lds<16><<<mgrid, 256, 0, s>>>(nnz, nullptr, nullptr, P.pairptr.get(), P.pairs.get(),
-                                                     X.vals.get(), Y.vals.get(), C.vals.get(), nullptr, nullptr);
-        else
-            k_galerkin_lds<25><<<mgrid, 256, 0, s>>>(nnz, nullptr, nullptr, P.pairptr.get(), P.pairs.get(),
-                                                     X.vals.get(), Y.vals.get(), C.vals.get(), nullptr, nullptr);
+        launch_pair_sums(bs, nnz, P.pairptr.get(), P.pairs.get(), X.vals.get(), Y.vals.get(), nullptr, C.vals.get(),
+                         nullptr, nullptr, s);
     } else {
         NAIR_BS_DISPATCH(bs, k_spgemm_pairs, <<<grid, 256, 0, s>>>(nnz, bs, P.pairptr.get(), P.pairs.get(),
                                                                    X.vals.get(), Y.vals.get(), C.vals.get()));
@@ -1361,20 +1264,8 @@ void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int 
         kval.alloc(static_cast<size_t>(nnz) * bb);
         if (nnz > 0) {
             TimerScope ts(TK_RAP, g_timer_level, s);
-            const unsigned mgrid = static_cast<unsigned>((static_cast<int64_t>(nnz) + 3) / 4);
-            if (bs == 9)
-                k_galerkin_lds<9><<<mgrid, 256, 0, s>>>(nnz, nullptr, nullptr, P.pairptr.get(), P.pairs.get(),
-                                                        Z.vals.get(), A.vals.get(), kval.get(), knorm.get(),
-                                                        kbits.get(), merged.get());
-            else if (bs == 16)
-                k_galerkin_lds<16><<<mgrid, 256, 0, s>>>(nnz, nullptr, nullptr, P.pairptr.get(), P.pairs.get(),
-                                                         Z.vals.get(), A.vals.get(), kval.get(), knorm.get(),
-                                                         kbits.get(), merged.get());
-            else
-                k_galerkin_lds<25><<<mgrid, 256, 0, s>>>(nnz, nullptr, nullptr, P.pairptr.get(), P.pairs.get(),
-                                                         Z.vals.get(), A.vals.get(), kval.get(), knorm.get(),
-                                                         kbits.get(), merged.get());
-            NAIR_HIP(hipGetLastError());
+            launch_pair_sums(bs, nnz, P.pairptr.get(), P.pairs.get(), Z.vals.get(), A.vals.get(), merged.get(),
+                             kval.get(), knorm.get(), kbits.get(), s);
         }
     } else {
         RK.vals.alloc(static_cast<size_t>(nnz) * bb);
