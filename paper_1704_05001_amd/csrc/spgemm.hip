@@ -768,6 +768,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 #pragma unroll
                         for (int tj = 0; tj < NT; ++tj)
                             acc.t[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj], acc.t[ti][tj], 0, 0, 0);
+                    // (fragments are read one step ahead at most: registers for four waves per SIMD)
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
         }

@@ -96,21 +96,29 @@ __global__ __launch_bounds__(256) void k_rb_take(const uint32_t *__restrict__ ma
     size[t] = __popc(m) * bs;
 }
 
-// Entry (a, c) of block t, if row a is nonzero, to out[off[t] + rank(a) * bs + c];
-// one thread per block entry, so consecutive threads copy consecutive words.
+// Block t's nonzero rows, in order, to out[off[t] ...]: one wave per block
+// (four per workgroup), lane q of the stored entries taking entry c of the
+// block's (q / bs)-th nonzero row, so consecutive lanes read consecutive
+// words of a row and write consecutive words of the copy.
 __global__ __launch_bounds__(256) void k_rb_fill(const double *__restrict__ vals, int64_t n, int bs,
                                                 const int *__restrict__ src, const int *__restrict__ count,
                                                 const uint32_t *__restrict__ mask, const int *__restrict__ off,
                                                 double *__restrict__ out) {
     const int64_t bb = static_cast<int64_t>(bs) * bs;
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t t = g / bb;
+    const int lane = threadIdx.x & 63;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (t >= (count ? *count : n)) return;
-    const int e = static_cast<int>(g - t * bb);
-    const int a = e / bs;
     const uint32_t m = mask[t];
-    if (!((m >> a) & 1u)) return;
-    out[off[t] + __popc(m & ((1u << a) - 1u)) * bs + (e - a * bs)] = vals[(src ? src[t] : t) * bb + e];
+    const int stored = __popc(m) * bs;
+    const double *blk = vals + (src ? src[t] : t) * bb;
+    double *o = out + off[t];
+    for (int q = lane; q < stored; q += 64) {
+        const int k = q / bs, c = q - k * bs;
+        uint32_t mm = m;
+        for (int j = 0; j < k; ++j) mm &= mm - 1u;   // drop the k lower nonzero rows
+        const int a = __ffs(static_cast<int>(mm)) - 1;
+        o[q] = blk[a * bs + c];
+    }
 }
 
 }  // namespace
@@ -131,8 +139,7 @@ bool build_row_blocks(const double *vals, int64_t n, int bs, RowBlocks &R, hipSt
         launch_block_scan(vals, n, bs, src, count, nullptr, nullptr, R.mask.get(), size.get(), s);
     }
     scan_exclusive(size.get(), R.off.get(), static_cast<int>(n), s);
-    k_rb_fill<<<grid_for(n * bb, 256), 256, 0, s>>>(vals, n, bs, src, count, R.mask.get(), R.off.get(),
-                                                    R.vals.get());
+    k_rb_fill<<<grid_for(n, 4), 256, 0, s>>>(vals, n, bs, src, count, R.mask.get(), R.off.get(), R.vals.get());
     NAIR_HIP(hipGetLastError());
     R.on = true;
     return true;
