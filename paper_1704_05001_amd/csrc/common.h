@@ -230,6 +230,8 @@ struct SumTerms {
 // 25x25 blocks, matrix cores); rmask as there
 void launch_sum_product(int64_t n, int bs, const SumTerms &terms, const double *Y, const int *yi, double sign,
                         double *out, hipStream_t s, const int *count, uint32_t *rmask);
+// map[t] = map[t] >= 0 ? through[map[t]] : -1 for the first *count <= n entries
+void launch_map_through(int64_t n, const int *count, int *map, const int *through, hipStream_t s);
 // After O = S + W (pattern only, srcS from bsr_add): maps[i] (term i's block of
 // each S block) become term i's block of each O block (-1 where srcS is -1),
 // for the first *count <= cap blocks of O.
@@ -243,7 +245,9 @@ void launch_rows_of(const int *rowptr, int nrows, int *rowid, hipStream_t s);
 // ------------------------------------------------------------------ SpGEMM
 // C = X * Y (+ optional implicit identity block of X at column xdiag[i]).
 // Fixed accumulation order: inner index ascending, c ascending, one fma chain.
-void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipStream_t s);
+// (xmap: X's values are not stored with it; X's block x is block xmap[x] of xvals)
+void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipStream_t s,
+            const double *xvals = nullptr, const int *xmap = nullptr);
 // O = S + W (union pattern, S's value first).  O's block count stays on the
 // device (O.nnzb = -1, arrays of S.bound() + W.bound() blocks).
 // With srcS and srcW given, only the pattern is formed: O.vals stays empty and
@@ -297,7 +301,9 @@ struct FaceCopy {
 };
 // Build F for A when its off-diagonal blocks' nonzero rectangles hold at most
 // half a block (F.on stays false otherwise).  Synchronises the stream once.
-void build_face(const DevBSR &A, FaceCopy &F, hipStream_t s);
+// (meta: the blocks' nonzero-row and nonzero-column masks when already known,
+// taken over; else a pass over A's entries finds them)
+void build_face(const DevBSR &A, FaceCopy &F, hipStream_t s, DBuf<uint64_t> *meta_known = nullptr);
 void face_to_float(const DevBSR &A, FaceCopy &F, hipStream_t s);
 
 // What the face-compressed kernels read (meta == nullptr: the plain BSR values).

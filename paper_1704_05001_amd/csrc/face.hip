@@ -90,18 +90,24 @@ unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + 255) / 256); 
 
 }  // namespace
 
-void build_face(const DevBSR &A, FaceCopy &F, hipStream_t s) {
+void build_face(const DevBSR &A, FaceCopy &F, hipStream_t s, DBuf<uint64_t> *meta_known) {
     F = FaceCopy();
     const int bs = A.bs;
     if (bs < 2 || bs > 32 || A.nb == 0 || A.nnzb == 0) return;
     const int64_t bb = static_cast<int64_t>(bs) * bs;
-    DBuf<uint64_t> meta(static_cast<size_t>(A.nnzb));
+    DBuf<uint64_t> meta;
+    const bool known = meta_known && meta_known->get();
+    if (known)
+        meta = std::move(*meta_known);
+    else
+        meta.alloc(static_cast<size_t>(A.nnzb));
     DBuf<int> diagpos(static_cast<size_t>(A.nb)), maxrc(2);
     NAIR_HIP(hipMemsetAsync(maxrc.get(), 0, sizeof(int) * 2, s));
     NAIR_HIP(hipMemsetAsync(diagpos.get(), 0, sizeof(int) * A.nb, s));   // (every validated row has its diagonal)
     auto *m64 = reinterpret_cast<unsigned long long *>(meta.get());
     // meta[t] = nonzero rows | nonzero columns << 32
-    launch_block_scan(A.vals.get(), A.nnzb, bs, nullptr, nullptr, nullptr, meta.get(), nullptr, nullptr, s);
+    if (!known)
+        launch_block_scan(A.vals.get(), A.nnzb, bs, nullptr, nullptr, nullptr, meta.get(), nullptr, nullptr, s);
     k_face_rows<<<blocks_for(A.nb), 256, 0, s>>>(A.rowptr.get(), A.colidx.get(), A.nb, m64, diagpos.get(),
                                                   maxrc.get());
     NAIR_HIP(hipGetLastError());

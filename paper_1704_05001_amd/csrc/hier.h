@@ -40,6 +40,7 @@ struct Level {
     // setup products
     DBuf<double> dinv, bnorm;
     bool bnorm_ready = false;       // bnorm came with the operator (the Galerkin step computes it)
+    DBuf<uint64_t> facemeta;        // level 0: the face masks, from the same pass over A as bnorm
     DBuf<uint8_t> mask;
     DBuf<int> lambda, cidx, pmap, dround, cpts, flist;
     DBuf<int> margin;               // decision-margin audit counts (theta, phi, one-point, drop)

@@ -238,7 +238,15 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         DBuf<int> sing(1);
         L.margin.alloc(4);
         launch_fill_ints({{sing.get(), 1, kNoSingular}, {L.lambda.get(), n, 0}, {L.margin.get(), 4, 0}}, s);
-        if (!L.bnorm_ready) launch_block_maxabs(L.A.vals.get(), nz, bs, L.bnorm.get(), s);
+        if (!L.bnorm_ready) {
+            if (l == 0 && p.faces == 1 && p.form == 0) {   // the face copy's masks come from the same pass
+                L.facemeta.alloc(static_cast<size_t>(nz));
+                launch_block_scan(L.A.vals.get(), nz, bs, nullptr, nullptr, L.bnorm.get(), L.facemeta.get(), nullptr,
+                                  nullptr, s);
+            } else {
+                launch_block_maxabs(L.A.vals.get(), nz, bs, L.bnorm.get(), s);
+            }
+        }
         {
             TimerScope ts(TK_BLOCKINV, l, s);
             launch_block_inverse(L.A.rowptr.get(), L.A.colidx.get(), L.A.vals.get(), n, bs, L.direct.get(),
@@ -362,19 +370,20 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
             launch_block_product(nT, bs, L.dinv.get(), trow.get(), L.A.vals.get(), tsrc.get(), -1.0, T.vals.get(),
                                  s);
         }
+        // (on the matrix cores W_0 keeps no values of its own: its block t is A's block wsrc[t])
+        const bool masks = use_matrix_cores(bs);   // the matrix-core products give each block's nonzero rows
         W0.nnzb = nW;
         W0.colidx.alloc(nW);
-        W0.vals.alloc(static_cast<size_t>(nW) * bb);
-        {
-            DBuf<int> wsrc(nW);
-            launch_fill_Acf(L.A.rowptr.get(), L.A.colidx.get(), L.cf.get(), L.cpts.get(), nc, W0.rowptr.get(),
-                            W0.colidx.get(), wsrc.get(), s);
+        DBuf<int> wsrc(nW);
+        launch_fill_Acf(L.A.rowptr.get(), L.A.colidx.get(), L.cf.get(), L.cpts.get(), nc, W0.rowptr.get(),
+                        W0.colidx.get(), wsrc.get(), s);
+        if (!masks) {
+            W0.vals.alloc(static_cast<size_t>(nW) * bb);
             launch_block_gather(nW, bs, L.A.vals.get(), wsrc.get(), W0.vals.get(), s);
         }
         // S = ((W_0 + W_1) + W_2) + ...,  W_i = W_{i-1} T.  On the matrix cores S
         // is not stored: its pattern comes with one map per term (term i's block
         // of each S block, or -1), and Z's product below adds the terms itself.
-        const bool masks = use_matrix_cores(bs);   // the matrix-core products give each block's nonzero rows
         const bool fused_sum = masks && p.degree >= 1;
         std::vector<DevBSR> terms;   // W_0 .. W_k (fused) or the last W (stored sums)
         std::vector<DBuf<int>> tmaps;
@@ -383,7 +392,10 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         bool s_is_w0 = true;
         for (int d = 1; d <= p.degree; ++d) {
             DevBSR Wd;
-            spgemm(terms.back(), nullptr, T, Wd, s);
+            if (masks && d == 1)
+                spgemm(terms[0], nullptr, T, Wd, s, L.A.vals.get(), wsrc.get());
+            else
+                spgemm(terms.back(), nullptr, T, Wd, s);
             DevBSR Snew;
             if (fused_sum) {
                 DBuf<int> mS, mW;
@@ -419,18 +431,24 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
             const int *zcount = L.Z.nnzb < 0 ? L.Z.rowptr.get() + nc : nullptr;
             if (fused_sum) {
                 if (L.Z.cap > 0) {
+                    // term 0 (W_0) is read from A's blocks
+                    launch_map_through(L.Z.cap, zcount, tmaps[0].get(), wsrc.get(), s);
                     SumTerms st;
                     st.n = static_cast<int>(terms.size());
                     for (int i = 0; i < st.n; ++i) {
-                        st.vals[i] = terms[i].vals.get();
+                        st.vals[i] = i == 0 ? L.A.vals.get() : terms[i].vals.get();
                         st.map[i] = tmaps[i].get();
                     }
                     launch_sum_product(L.Z.cap, bs, st, L.dinv.get(), L.Z.colidx.get(), -1.0, L.Z.vals.get(), s,
                                        zcount, L.zmask.get());
                 }
-            } else
+            } else if (masks) {   // degree 0: Z = -(W_0 D^-1) with W_0's blocks read from A
+                launch_block_product(L.Z.cap, bs, L.A.vals.get(), wsrc.get(), L.dinv.get(), L.Z.colidx.get(), -1.0,
+                                     L.Z.vals.get(), s, zcount, L.zmask.get());
+            } else {
                 launch_block_product(L.Z.cap, bs, Ssum.vals.get(), nullptr, L.dinv.get(), L.Z.colidx.get(), -1.0,
-                                     L.Z.vals.get(), s, zcount, masks ? L.zmask.get() : nullptr);
+                                     L.Z.vals.get(), s, zcount, nullptr);
+            }
         }
         // Galerkin: K = R A P with R = [Z I], filtered; K's block sizes come along
         auto next = std::make_unique<Level>();
@@ -442,7 +460,7 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         h.lv.push_back(std::move(next));
     }
     // the finest operator is read by every cycle: a compact copy of its face blocks
-    if (p.faces == 1 && p.form == 0) build_face(h.lv[0]->A, h.lv[0]->face, s);
+    if (p.faces == 1 && p.form == 0) build_face(h.lv[0]->A, h.lv[0]->face, s, &h.lv[0]->facemeta);
     build_sweeps(h, false, s);
     if (p.precision == 1) make_fp32_copies(h, s);
     prepare_cycle(h, false, s);   // the F-cycle's saved vectors

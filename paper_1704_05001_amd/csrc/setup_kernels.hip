@@ -945,6 +945,14 @@ __global__ __launch_bounds__(256) void k_sum_product_mfma(int64_t n, const SumTe
     }
 }
 
+__global__ __launch_bounds__(256) void k_map_through(int64_t n, const int *__restrict__ count, int *__restrict__ map,
+                                                    const int *__restrict__ through) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n || (count && t >= *count)) return;
+    const int v = map[t];
+    map[t] = v >= 0 ? through[v] : -1;
+}
+
 // maps[i][t] = srcS[t] >= 0 ? old[i][srcS[t]] : -1 for every term i
 struct MapsIO {
     const int *old[kMaxSumTerms] = {};
@@ -1177,6 +1185,12 @@ void launch_sum_product(int64_t n, int bs, const SumTerms &terms, const double *
         k_sum_product_mfma<16><<<mgrid, 256, 0, s>>>(n, terms, Y, yi, sign, out, count, rmask);
     else
         k_sum_product_mfma<25><<<mgrid, 256, 0, s>>>(n, terms, Y, yi, sign, out, count, rmask);
+    NAIR_HIP(hipGetLastError());
+}
+
+void launch_map_through(int64_t n, const int *count, int *map, const int *through, hipStream_t s) {
+    if (n <= 0) return;
+    k_map_through<<<grid_for(n, 256), 256, 0, s>>>(n, count, map, through);
     NAIR_HIP(hipGetLastError());
 }
 

@@ -967,6 +967,14 @@ __global__ __launch_bounds__(256) void k_ap_merged(int nm, int bb, const int *__
     }
 }
 
+// pairs[k].x = xmap[pairs[k].x] where x >= 0 (identity pairs keep x < 0)
+__global__ __launch_bounds__(256) void k_remap_x(int64_t n, const int *__restrict__ xmap, int2 *__restrict__ pairs) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int x = pairs[k].x;
+    if (x >= 0) pairs[k].x = xmap[x];
+}
+
 __global__ __launch_bounds__(256) void k_remap_y(int64_t n, const int *__restrict__ ymap, int2 *__restrict__ pairs) {
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p < n) pairs[p].y = ymap[pairs[p].y];
@@ -1102,7 +1110,7 @@ void spgemm_structure(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR
 }
 
 // C's values from its pair lists (C.vals allocated by the caller).
-void spgemm_values(const DevBSR &X, const DevBSR &Y, const Pairs &P, DevBSR &C, hipStream_t s) {
+void spgemm_values(const double *xvals, const DevBSR &Y, const Pairs &P, DevBSR &C, hipStream_t s) {
     const int64_t nnz = C.nnzb;
     const int bs = C.bs;
     if (nnz == 0) return;
@@ -1110,22 +1118,27 @@ void spgemm_values(const DevBSR &X, const DevBSR &Y, const Pairs &P, DevBSR &C, 
     const unsigned grid = cap_grid((total + 255) / 256);
     TimerScope ts(TK_SPGEMM_NUM, g_timer_level, s);
     if (use_matrix_cores(bs)) {
-        launch_pair_sums(bs, nnz, P.pairptr.get(), P.pairs.get(), X.vals.get(), Y.vals.get(), nullptr, C.vals.get(),
-                         nullptr, nullptr, s);
+        launch_pair_sums(bs, nnz, P.pairptr.get(), P.pairs.get(), xvals, Y.vals.get(), nullptr, C.vals.get(), nullptr,
+                         nullptr, s);
     } else {
-        NAIR_BS_DISPATCH(bs, k_spgemm_pairs, <<<grid, 256, 0, s>>>(nnz, bs, P.pairptr.get(), P.pairs.get(),
-                                                                   X.vals.get(), Y.vals.get(), C.vals.get()));
+        NAIR_BS_DISPATCH(bs, k_spgemm_pairs, <<<grid, 256, 0, s>>>(nnz, bs, P.pairptr.get(), P.pairs.get(), xvals,
+                                                                   Y.vals.get(), C.vals.get()));
     }
     NAIR_HIP(hipGetLastError());
 }
 
 }  // namespace
 
-void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipStream_t s) {
+void spgemm(const DevBSR &X, const int *xdiag, const DevBSR &Y, DevBSR &C, hipStream_t s, const double *xvals,
+            const int *xmap) {
     Pairs P;
     spgemm_structure(X, xdiag, Y, C, P, s);
+    if (xmap && P.n > 0) {   // X's block x is block xmap[x] of xvals
+        k_remap_x<<<grid_for(P.n, 256), 256, 0, s>>>(P.n, xmap, P.pairs.get());
+        NAIR_HIP(hipGetLastError());
+    }
     C.vals.alloc(static_cast<size_t>(C.nnzb) * C.bs * C.bs);
-    spgemm_values(X, Y, P, C, s);
+    spgemm_values(xmap ? xvals : X.vals.get(), Y, P, C, s);
 }
 
 void bsr_add(const DevBSR &S, const DevBSR &W, DevBSR &O, hipStream_t s, DBuf<int> *srcS_out, DBuf<int> *srcW_out) {
@@ -1273,7 +1286,7 @@ void galerkin(DevBSR &Z, const int *cpts, const DevBSR &A, const int *pmap, int 
         RK.vals.alloc(static_cast<size_t>(nnz) * bb);
         {
             TimerScope ts(TK_RAP, g_timer_level, s);
-            spgemm_values(Z, AP, P, RK, s);
+            spgemm_values(Z.vals.get(), AP, P, RK, s);
         }
         kval = std::move(RK.vals);
         launch_block_maxabs(kval.get(), nnz, bs, knorm.get(), s);
