@@ -159,9 +159,10 @@ void scan_exclusive2(const int *in0, int *out0, int n0, int *total0, const int *
 void launch_block_maxabs(const double *vals, int64_t nnzb, int bs, double *out, hipStream_t s);
 // Per block t < n (vals block src[t] if src, empty at or past *count if count):
 // max-abs entry, nonzero rows | nonzero columns << 32, nonzero rows, and the
-// nonzero rows times bs; each output may be null.  1 <= bs <= 32.
+// nonzero rows times bs; each output may be null.  1 <= bs <= 32.  copy (nullable,
+// no src or count): the blocks are also copied there, read once for both.
 void launch_block_scan(const double *vals, int64_t n, int bs, const int *src, const int *count, double *maxabs,
-                       uint64_t *meta, uint32_t *rmask, int *rsize, hipStream_t s);
+                       uint64_t *meta, uint32_t *rmask, int *rsize, hipStream_t s, double *copy = nullptr);
 // skip (nullable): blocks whose inverse is not needed (directly solved systems)
 void launch_block_inverse(const int *rowptr, const int *colidx, const double *vals, int nb, int bs,
                           const int8_t *skip, double *dinv, int *singular_min, hipStream_t s);

@@ -169,8 +169,11 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
                             hipMemcpyDeviceToDevice, s));
     NAIR_HIP(hipMemcpyAsync(Ain.colidx.get(), colidx, sizeof(int) * static_cast<size_t>(nnzb),
                             hipMemcpyDeviceToDevice, s));
-    NAIR_HIP(hipMemcpyAsync(Ain.vals.get(), vals, sizeof(double) * static_cast<size_t>(nnzb) * bb,
-                            hipMemcpyDeviceToDevice, s));
+    // (block form: the values are copied by the first pass over them, the finest level's block sizes)
+    const double *copy_from = p.form == 1 ? nullptr : vals;   // (null once copied)
+    if (!copy_from)
+        NAIR_HIP(hipMemcpyAsync(Ain.vals.get(), vals, sizeof(double) * static_cast<size_t>(nnzb) * bb,
+                                hipMemcpyDeviceToDevice, s));
     if (p.form == 1) {
         // scalar form: D^{-1} of the caller's blocks, S = D^{-1} A as the scalar level 0
         h.d0inv.alloc(static_cast<size_t>(nb) * bb);
@@ -221,6 +224,11 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
             launch_seg_info(L.seg_d.get(), L.mode_d.get(), nsys, n, L.lbase.get(), L.direct.get(), L.bsys.get(), s);
         }
         if (ncont == 0) {
+            if (copy_from) {   // solved directly at the finest level: no pass over the values to copy them
+                NAIR_HIP(hipMemcpyAsync(L.A.vals.get(), copy_from, sizeof(double) * static_cast<size_t>(nnzb) * bb,
+                                        hipMemcpyDeviceToDevice, s));
+                copy_from = nullptr;
+            }
             if (L.A.nnzb < 0) L.A.nnzb = read_int(L.A.rowptr.get() + n, s);
             L.coarsest = true;
             make_direct(L, l, s);
@@ -239,10 +247,11 @@ void build_hierarchy(Hier &h, int nsys, const int *sys_nb, int nb, int bs, const
         L.margin.alloc(4);
         launch_fill_ints({{sing.get(), 1, kNoSingular}, {L.lambda.get(), n, 0}, {L.margin.get(), 4, 0}}, s);
         if (!L.bnorm_ready) {
-            if (l == 0 && p.faces == 1 && p.form == 0) {   // the face copy's masks come from the same pass
-                L.facemeta.alloc(static_cast<size_t>(nz));
-                launch_block_scan(L.A.vals.get(), nz, bs, nullptr, nullptr, L.bnorm.get(), L.facemeta.get(), nullptr,
-                                  nullptr, s);
+            if (l == 0 && copy_from) {   // the caller's values: copied here; the face copy's masks come along
+                if (p.faces == 1) L.facemeta.alloc(static_cast<size_t>(nz));
+                launch_block_scan(copy_from, nz, bs, nullptr, nullptr, L.bnorm.get(), L.facemeta.get(), nullptr,
+                                  nullptr, s, L.A.vals.get());
+                copy_from = nullptr;
             } else {
                 launch_block_maxabs(L.A.vals.get(), nz, bs, L.bnorm.get(), s);
             }

@@ -26,11 +26,13 @@ __device__ inline double wave_max(double v) {
 // >= bs*bs, at most 64), so a block's entries are read as consecutive words;
 // the lanes' partial results meet by shuffles (max and or are exact, so the
 // order is free).  Block t is vals[src[t]] when src is given; with count,
-// blocks at or past *count are empty (zero results).  Outputs may be null.
+// blocks at or past *count are empty (zero results).  Outputs may be null;
+// copy (no src, no count) receives the blocks as they are read.
 __global__ __launch_bounds__(256) void k_block_scan(const double *__restrict__ vals, int64_t n, int bs, int L,
                                                    const int *__restrict__ src, const int *__restrict__ count,
                                                    double *__restrict__ maxabs, unsigned long long *__restrict__ meta,
-                                                   uint32_t *__restrict__ rmask, int *__restrict__ rsize) {
+                                                   uint32_t *__restrict__ rmask, int *__restrict__ rsize,
+                                                   double *__restrict__ copy) {
     const int per = 256 / L;
     const int sub = static_cast<int>(threadIdx.x) & (L - 1);
     const int64_t t = static_cast<int64_t>(blockIdx.x) * per + static_cast<int>(threadIdx.x) / L;
@@ -42,6 +44,7 @@ __global__ __launch_bounds__(256) void k_block_scan(const double *__restrict__ v
         const double *blk = vals + (src ? static_cast<int64_t>(src[t]) : t) * bb;
         for (int e = sub; e < bb; e += L) {
             const double x = blk[e];
+            if (copy) copy[t * bb + e] = x;
             if (x != 0.0) {
                 const int r = e / bs;
                 rm |= 1u << r;
@@ -1005,14 +1008,15 @@ unsigned cap_grid(int64_t g) { return static_cast<unsigned>(g > 65536 * 16 ? 655
 }  // namespace
 
 void launch_block_scan(const double *vals, int64_t n, int bs, const int *src, const int *count, double *maxabs,
-                       uint64_t *meta, uint32_t *rmask, int *rsize, hipStream_t s) {
+                       uint64_t *meta, uint32_t *rmask, int *rsize, hipStream_t s, double *copy) {
     if (n <= 0) return;
     if (bs < 1 || bs > 32) fail(NAIR_EINVAL, "block scan: bs must be in 1..32");
+    if (copy && (src || count)) fail(NAIR_EDEVICE, "block scan: a copy only of blocks in place");
     int L = 1;
     while (L < bs * bs && L < kWave) L <<= 1;
     const int per = 256 / L;
     k_block_scan<<<grid_for(n, per), 256, 0, s>>>(vals, n, bs, L, src, count, maxabs,
-                                                  reinterpret_cast<unsigned long long *>(meta), rmask, rsize);
+                                                  reinterpret_cast<unsigned long long *>(meta), rmask, rsize, copy);
     NAIR_HIP(hipGetLastError());
 }
 
