@@ -75,15 +75,27 @@ __global__ __launch_bounds__(256) void k_face_fill(const double *__restrict__ va
     out[g] = v;
 }
 
-// dvals[I] = A_II by columns (entry (a, c) at c * bs + a), one thread per entry.
+// dvals[I] = A_II by columns (entry (a, c) at c * bs + a)
 __global__ __launch_bounds__(256) void k_face_diag(const double *__restrict__ vals, const int *__restrict__ diagpos,
                                                   int nb, int bs, double *__restrict__ dvals) {
-    const int64_t bb = static_cast<int64_t>(bs) * bs;
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= static_cast<int64_t>(nb) * bb) return;
-    const int64_t I = g / bb;
-    const int e = static_cast<int>(g - I * bb), c = e / bs, a = e - c * bs;
-    dvals[g] = vals[static_cast<int64_t>(diagpos[I]) * bb + a * bs + c];
+    // one wave per block: read as stored (consecutive lanes, consecutive words)
+    // into the wave's LDS tile, written by columns the same way
+    __shared__ double tile[4][32 * 32];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t I = static_cast<int64_t>(blockIdx.x) * 4 + w;
+    if (I >= nb) return;   // whole waves; no workgroup barrier below
+    const int bb = bs * bs;
+    const double *src = vals + static_cast<int64_t>(diagpos[I]) * bb;
+    double *tl = tile[w];
+    for (int e = lane; e < bb; e += 64) tl[e] = src[e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double *dst = dvals + I * bb;
+    for (int g = lane; g < bb; g += 64) {
+        const int c = g / bs, a = g - c * bs;
+        dst[g] = tl[a * bs + c];
+    }
 }
 
 unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + 255) / 256); }
@@ -124,8 +136,8 @@ void build_face(const DevBSR &A, FaceCopy &F, hipStream_t s, DBuf<uint64_t> *met
     k_face_fill<<<blocks_for(A.nnzb * F.rc), 256, 0, s>>>(A.vals.get(), m64, A.nnzb, bs, F.cmax, F.rc,
                                                          F.vals.get());
     NAIR_HIP(hipGetLastError());
-    k_face_diag<<<blocks_for(static_cast<int64_t>(A.nb) * bb), 256, 0, s>>>(A.vals.get(), diagpos.get(), A.nb, bs,
-                                                                           F.dvals.get());
+    k_face_diag<<<static_cast<unsigned>((A.nb + 3) / 4), 256, 0, s>>>(A.vals.get(), diagpos.get(), A.nb, bs,
+                                                                     F.dvals.get());
     NAIR_HIP(hipGetLastError());
     F.on = true;
 }

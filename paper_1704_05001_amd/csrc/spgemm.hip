@@ -959,10 +959,24 @@ __global__ __launch_bounds__(256) void k_ap_merged(int nm, int bb, const int *__
     for (int64_t q = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; q < nm; q += stride) {
         const int t = mblk[q];
         const int k0 = kptr[t], k1 = kptr[t + 1];
-        for (int e = lane; e < bb; e += 64) {
-            double v = 0.0;
-            for (int k = k0; k < k1; ++k) v = v + A[static_cast<int64_t>(klist[k]) * bb + e];
-            out[q * bb + e] = v;
+        // contributors outermost: each one's entries load together (one wait per
+        // contributor, not per entry); every entry still sums its contributors in order
+        constexpr int kChunks = 16;   // bs <= 32: at most 1024 entries
+        double v[kChunks];
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) v[i] = 0.0;
+        for (int k = k0; k < k1; ++k) {
+            const double *a = A + static_cast<int64_t>(klist[k]) * bb;
+#pragma unroll
+            for (int i = 0; i < kChunks; ++i) {
+                const int e = lane + 64 * i;
+                if (e < bb) v[i] = v[i] + a[e];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) {
+            const int e = lane + 64 * i;
+            if (e < bb) out[q * bb + e] = v[i];
         }
     }
 }
