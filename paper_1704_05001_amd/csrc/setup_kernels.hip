@@ -213,7 +213,7 @@ __device__ inline void pivot_take(double &v, int &key, double ov, int okey) {
 // k_block_inverse_wave.  Same operations on the same values in the same order:
 // the same bits.
 template <int BS>
-__global__ __launch_bounds__(256) void k_block_inverse_rows(const int *__restrict__ rowptr,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_block_inverse_rows(const int *__restrict__ rowptr,
                                                            const int *__restrict__ colidx,
                                                            const double *__restrict__ vals, int nb,
                                                            const int8_t *__restrict__ skip, double *__restrict__ dinv,
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256) void k_block_inverse_rows(const int *__restric
     constexpr int BB = BS * BS;
     constexpr int kNone = (64 << 5) | 31;     // key of a lane that is no candidate
     __shared__ double slot[8][BB];
-    __shared__ int pslot[8][32];
+    __shared__ int8_t pslot[8][32];   // (bytes: four workgroups' slots fit one CU's LDS)
     const int h = threadIdx.x >> 5;           // half wave: one block
     const int r = threadIdx.x & 31;           // its row
     const int I = blockIdx.x * 8 + h;
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void k_block_inverse_rows(const int *__restric
         for (int c = 0; c < BS; ++c) a[c] = (live && r < BS) ? src[c] : 0.0;
     }
     double *fac = slot[h];
-    int *pm = pslot[h];
+    int8_t *pm = pslot[h];
     int pos = r;   // lanes r >= BS keep positions >= BS: never candidates, never updated
 #pragma unroll
     for (int k = 0; k < BS; ++k) {
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) void k_block_inverse_rows(const int *__restric
             for (int j = k + 1; j < BS; ++j) a[j] = __builtin_fma(-a[k], fac[k * BS + j], a[j]);
         }
     }
-    if (r < BS && pos < BS) pm[pos] = r;
+    if (r < BS && pos < BS) pm[pos] = static_cast<int8_t>(r);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
