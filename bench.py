@@ -205,7 +205,8 @@ def setup_work(H, degree: int) -> dict:
     (host scipy on the block patterns; no values): block pairs of the Neumann
     products W_i = W_{i-1} T (T: the phi-strong F-F blocks, W_0 = A_cf) and of
     the coarse operator R (A P) (R = [Z I]; A P merges A's columns through the
-    one-point map), the single block products T = -D^-1 A_ff and Z = -S D^-1,
+    one-point map), the single block products T = -D^-1 A_ff and Z = -S D^-1
+    (S = W_0 + ... + W_k, never stored: Z's product reads the k+1 terms),
     the block inverses, and the compulsory bytes of each (operands read once,
     outputs written once, 8-byte pair entries).  Flops: 2 bs^3 per block pair
     or block product, 2 bs^3 per block inverse (LU and the inverse from it)."""
@@ -213,7 +214,7 @@ def setup_work(H, degree: int) -> dict:
     import scipy.sparse as sp
     info = H.info()
     w = {k: 0 for k in ("pairs_W", "pairs_RAP", "ident_RAP", "blocks_T", "blocks_Z", "blocks_W", "blocks_Wprev",
-                        "blocks_K", "blocks_AP", "nb_inv")}
+                        "blocks_W0", "blocks_K", "blocks_AP", "nb_inv")}
     bs = None
     for l in range(info["levels"]):
         lv = H.level(l, fields=("rowptr", "colidx", "mask", "cf", "pmap", "z_rowptr", "z_colidx"))
@@ -232,6 +233,7 @@ def setup_work(H, degree: int) -> dict:
         cm = (cf[rows] == 1) & F[ci]
         W = sp.csr_matrix((np.ones(int(cm.sum())), (rows[cm], ci[cm])), shape=(nb, nb))
         tlen = np.diff(T.indptr)
+        w["blocks_W0"] += W.nnz
         for _ in range(degree):
             w["pairs_W"] += int(tlen[W.indices].sum())
             w["blocks_Wprev"] += W.nnz
@@ -264,18 +266,21 @@ def setup_roofline(P, make_hier, work: dict, reps: int = 1) -> list:
     bb8 = 8 * bs * bs
     f3 = 2.0 * bs ** 3
     kinds = {
-        "galerkin": dict(kernel="k_galerkin_lds (R (A P) block products summed into K blocks)",
+        "galerkin": dict(kernel="k_pair_sums (R (A P) block products summed into K blocks)",
                          flops=work["pairs_RAP"] * f3,
                          bytes=(work["blocks_Z"] + work["blocks_AP"] + work["blocks_K"]) * bb8
                          + 8 * (work["pairs_RAP"] + work["ident_RAP"])),
-        "spgemm_numeric": dict(kernel="k_spgemm_mfma (Neumann products W_i = W_(i-1) T)",
+        "spgemm_numeric": dict(kernel="k_pair_sums (Neumann products W_i = W_(i-1) T)",
                                flops=work["pairs_W"] * f3,
                                bytes=(work["blocks_Wprev"] + work["blocks_T"] + work["blocks_W"]) * bb8
                                + 8 * work["pairs_W"]),
-        "block_product": dict(kernel="k_block_product_mfma (T = -D^-1 A_ff, Z = -S D^-1)",
+        # Z's product adds the terms W_0 .. W_k of the unstored sum S itself: each term block read once
+        "block_product": dict(kernel="k_block_product_mfma (T = -D^-1 A_ff), k_sum_product_mfma "
+                                     "(Z = -(W_0 + ... + W_k) D^-1)",
                               flops=(work["blocks_T"] + work["blocks_Z"]) * f3,
-                              bytes=(work["blocks_T"] + work["blocks_Z"]) * 3 * bb8),
-        "block_inverse": dict(kernel="k_block_inverse (D^-1 by LU)", flops=work["nb_inv"] * f3,
+                              bytes=(3 * work["blocks_T"] + work["blocks_W0"] + work["blocks_W"]
+                                     + 2 * work["blocks_Z"]) * bb8),
+        "block_inverse": dict(kernel="k_block_inverse_rows (D^-1 by LU)", flops=work["nb_inv"] * f3,
                               bytes=work["nb_inv"] * 2 * bb8),
     }
     out = []
