@@ -469,17 +469,6 @@ __device__ inline bool live(const Gate &g, int row) {
     return g.active == nullptr || g.active[g.bsys ? g.bsys[row] : 0] != 0;
 }
 
-// The chip hands workgroup b of a launch to XCD b mod 8, each XCD with its own
-// L2.  This renumbers the n workgroups so that each XCD runs one contiguous
-// range of them (neighbouring work shares operands in one L2): a bijection of
-// [0, n), so any kernel may use it in place of blockIdx.x.
-constexpr int kXcds = 8;
-__device__ inline int64_t xcd_block(int64_t b, int64_t n) {
-    const int64_t q = n / kXcds, r = n % kXcds;
-    const int64_t x = b % kXcds, i = b / kXcds;
-    return x * q + (x < r ? x : r) + i;
-}
-
 // r = b - A x (b == nullptr: r = A x), plus a float copy if r_lo
 template <typename MT, typename VT>
 void launch_residual(const MatView<MT> &A, const VT *b, const VT *x, VT *r, float *r_lo, hipStream_t s,

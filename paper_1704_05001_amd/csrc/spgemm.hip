@@ -655,8 +655,7 @@ __global__ __launch_bounds__(256) void k_spgemm_pairs(int64_t nnz, int bs_rt, co
 // and the fragments taken from there.  The sums are short (a few pairs per
 // block), so a wave that started each block from its index would wait on
 // three dependent loads per block (the pair range, the pair, the blocks):
-// instead each workgroup owns a contiguous range of output blocks (ranges
-// ordered so that each XCD runs a contiguous part of the output), its four
+// instead each workgroup owns a contiguous range of output blocks, its four
 // waves take every fourth block of it, and each wave keeps ahead of itself --
 // the pair range two blocks on, the pair indices of the next block, and the
 // next pair's blocks (of this block or the next) in registers while the
@@ -678,7 +677,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int row = lane & 15, kk = lane >> 4;
-    const int64_t lo = xcd_block(blockIdx.x, gridDim.x) * per_wg;
+    const int64_t lo = static_cast<int64_t>(blockIdx.x) * per_wg;
     const int64_t hi = lo + per_wg < nnz ? lo + per_wg : nnz;
     int64_t t = lo + w;
     if (t >= hi) return;   // whole waves; no workgroup barrier below
