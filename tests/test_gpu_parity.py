@@ -195,6 +195,19 @@ def test_parity_variants(relax, degree):
     check_solve(G, O, g, trans=True)
 
 
+@pytest.mark.parametrize("name,N,degree", [("dg_q2_256_curved", 16, 6), ("dg_q2_256_curved", 12, 16),
+                                           ("dg_q4_512_jitter", 8, 4)])
+def test_high_neumann_degree(name, N, degree):
+    """Neumann degrees past the usual few (up to the limit, 16): the sum of the
+    k + 1 terms that Z's product forms without storing it, through the term
+    maps composed over k pattern unions, against the oracle's stored sums."""
+    _say(f"test: Neumann degree {degree} ({name} N={N})")
+    S, _ = make_config(name, N=N)
+    G, O = build_pair(S.nb, S.bs, S.rowptr, S.colidx, S.vals, degree=degree, max_coarse_dofs=4 * S.bs)
+    compare_hierarchies(G, O)
+    check_solve(G, O, S.rhs)
+
+
 def test_parity_random_matrices():
     _say("test: random block matrices")
     rp, ci, va, order, layer = layered_block_triangular(300, 3, 12, deps=3, seed=7, zero_entries=0.3)
