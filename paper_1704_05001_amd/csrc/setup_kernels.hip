@@ -1016,7 +1016,19 @@ __global__ __launch_bounds__(256) void k_block_gather_wave(int64_t n, int bb, co
     for (int64_t t = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; t < nblk; t += stride) {
         const double *y = Y + static_cast<int64_t>(src[t]) * bb;
         double *o = out + t * bb;
-        for (int e = lane; e < bb; e += 64) o[e] = y[e];
+        // every load of the block first, then the stores (bb <= 1024: at most 16 per lane)
+        constexpr int kChunks = 16;
+        double v[kChunks];
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) {
+            const int e = lane + 64 * i;
+            v[i] = e < bb ? y[e] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) {
+            const int e = lane + 64 * i;
+            if (e < bb) o[e] = v[i];
+        }
     }
 }
 

@@ -112,12 +112,25 @@ __global__ __launch_bounds__(256) void k_rb_fill(const double *__restrict__ vals
     const int stored = __popc(m) * bs;
     const double *blk = vals + (src ? src[t] : t) * bb;
     double *o = out + off[t];
-    for (int q = lane; q < stored; q += 64) {
-        const int k = q / bs, c = q - k * bs;
-        uint32_t mm = m;
-        for (int j = 0; j < k; ++j) mm &= mm - 1u;   // drop the k lower nonzero rows
-        const int a = __ffs(static_cast<int>(mm)) - 1;
-        o[q] = blk[a * bs + c];
+    // every load first, then the stores (at most bs * bs <= 1024 entries: 16 per lane)
+    constexpr int kChunks = 16;
+    double v[kChunks];
+#pragma unroll
+    for (int i = 0; i < kChunks; ++i) {
+        const int q = lane + 64 * i;
+        v[i] = 0.0;
+        if (q < stored) {
+            const int k = q / bs, c = q - k * bs;
+            uint32_t mm = m;
+            for (int j = 0; j < k; ++j) mm &= mm - 1u;   // drop the k lower nonzero rows
+            const int a = __ffs(static_cast<int>(mm)) - 1;
+            v[i] = blk[a * bs + c];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kChunks; ++i) {
+        const int q = lane + 64 * i;
+        if (q < stored) o[q] = v[i];
     }
 }
 
