@@ -857,28 +857,66 @@ __global__ __launch_bounds__(256) void k_block_product_mfma(int64_t n, const dou
                                                            const int *__restrict__ yi, double sign,
                                                            double *__restrict__ out, const int *__restrict__ count,
                                                            uint32_t *__restrict__ rmask) {
+    // both blocks read with consecutive lanes on consecutive words into the
+    // wave's LDS slot, the matrix-core fragments taken from there
     constexpr int bb = BS * BS;
+    constexpr int NL = (bb + 63) / 64;   // loads per lane and block
+    constexpr int NT = MfmaShape<BS>::NT, KQ = MfmaShape<BS>::KQ;
+    __shared__ double slot[4][2 * bb];
+    const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int row = lane & 15, kk = lane >> 4;
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
-    if (t >= (count ? *count : n)) return;   // whole waves
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + w;
+    if (t >= (count ? *count : n)) return;   // whole waves; no workgroup barrier below
+    double *xs = slot[w], *ys = slot[w] + bb;
     const double *x = X + static_cast<int64_t>(xi ? xi[t] : t) * bb;
     const double *y = Y + static_cast<int64_t>(yi[t]) * bb;
-    MfmaOperands<BS> op;
-    op.load_product(x, y, row, kk);
+    double xv[NL], yv[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int e = lane + 64 * i;
+        xv[i] = e < bb ? x[e] : 0.0;
+        yv[i] = e < bb ? y[e] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int e = lane + 64 * i;
+        if (e < bb) {
+            xs[e] = xv[i];
+            ys[e] = yv[i];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     MfmaAcc<BS> acc;
     acc.zero();
-    op.apply_product(acc);
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+        const int c = 4 * q + kk;
+        double a[NT], b[NT];
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const int i = 16 * u + row;
+            a[u] = (i < BS && c < BS) ? xs[i * BS + c] : 0.0;
+            b[u] = (i < BS && c < BS) ? ys[c * BS + i] : 0.0;
+        }
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < NT; ++tj)
+                acc.t[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj], acc.t[ti][tj], 0, 0, 0);
+    }
     double *o = out + t * bb;
     uint32_t bits = 0u;   // this lane's nonzero rows, then the block's
     mfma_for_entries<BS>(acc, row, kk, [&](int i, int j, double v) {
-        const double w = sign * v;
-        o[i * BS + j] = w;
-        if (w != 0.0) bits |= 1u << i;
+        const double wv = sign * v;
+        o[i * BS + j] = wv;
+        if (wv != 0.0) bits |= 1u << i;
     });
     if (rmask) {
 #pragma unroll
-        for (int w = 32; w > 0; w >>= 1) bits |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(bits), w, 64));
+        for (int o2 = 32; o2 > 0; o2 >>= 1) bits |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(bits), o2, 64));
         if (lane == 0) rmask[t] = bits;
     }
 }
