@@ -30,6 +30,24 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Inclusive prefix sum of x over the wave's 64 lanes by DPP moves (no LDS
+// round trips): shifts by 1, 2, 4, 8 within each row of 16 lanes, then each
+// row's last lane added into the rows after it.  A lane whose source lies
+// outside its row (or a row the step leaves out) receives 0.
+template <int CTRL, int ROWS = 0xF>
+__device__ inline int dpp_add(int x) {
+    return x + __builtin_amdgcn_update_dpp(0, x, CTRL, ROWS, 0xF, false);
+}
+__device__ inline int wave_incl_scan(int x) {
+    x = dpp_add<0x111>(x);          // row_shr:1
+    x = dpp_add<0x112>(x);          // row_shr:2
+    x = dpp_add<0x114>(x);          // row_shr:4
+    x = dpp_add<0x118>(x);          // row_shr:8
+    x = dpp_add<0x142, 0xA>(x);     // row_bcast:15 into rows 1 and 3
+    x = dpp_add<0x143, 0xC>(x);     // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
 // Sort a wave's n distinct keys list[0 .. n) ascending in place (n <= cap, the
 // list's room): up to 64 keys by rank (a key per lane), more by a bitonic
 // network over the next power of two, padded with INT_MAX.
@@ -353,14 +371,9 @@ __device__ inline void wave0_scan(int *cnt, int n) {
     int carry = 0;
     for (int base = 0; base < n; base += 64) {
         const int v = (base + lane < n) ? cnt[base + lane] : 0;
-        int x = v;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
+        const int x = wave_incl_scan(v);
         if (base + lane < n) cnt[base + lane] = carry + x - v;
-        carry += __shfl(x, 63, 64);
+        carry += __builtin_amdgcn_readlane(x, 63);
     }
 }
 
@@ -445,14 +458,9 @@ __device__ inline SlotChunk load_slots(int base, int nk, int q0, int dslot, int 
         c.ybeg = yrowptr[K];
         c.len = yrowptr[K + 1] - c.ybeg;
     }
-    int x = c.len;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
+    const int x = wave_incl_scan(c.len);
     c.excl = x - c.len;
-    c.total = __shfl(x, 63, 64);
+    c.total = __builtin_amdgcn_readlane(x, 63);
     return c;
 }
 
@@ -561,14 +569,9 @@ __global__ __launch_bounds__(256) void k_symbolic_flat(const int *__restrict__ x
             int carry = 0;
             for (int base = 0; base < n; base += kWave) {
                 const int v = base + lane < n ? off[base + lane] : 0;
-                int x = v;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int y = __shfl_up(x, o, 64);
-                    if (lane >= o) x += y;
-                }
+                const int x = wave_incl_scan(v);
                 if (base + lane < n) off[base + lane] = carry + x - v;
-                carry += __shfl(x, 63, 64);
+                carry += __builtin_amdgcn_readlane(x, 63);
             }
             wave_sync();
             const int P0 = active ? prow[i] : 0;
