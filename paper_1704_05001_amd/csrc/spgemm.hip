@@ -586,7 +586,7 @@ __global__ __launch_bounds__(256) void k_symbolic_flat(const int *__restrict__ x
                     if (p < c.total) pos = find_pos(sorted, n, ycol[pr.y]);
                     int rank = 0;
                     for (int l = 0; l < kWave; ++l) {
-                        const int pl = __shfl(pos, l, 64);
+                        const int pl = __builtin_amdgcn_readlane(pos, l);   // (l is the same in every lane)
                         rank += (l < lane && pl == pos) ? 1 : 0;
                     }
                     if (pos >= 0) pairs[P0 + off[pos] + rank] = pr;
@@ -664,8 +664,9 @@ __global__ __launch_bounds__(256) void k_spgemm_pairs(int64_t nnz, int bs_rt, co
 // next pair's blocks (of this block or the next) in registers while the
 // current pair's steps run.  Also writes each block's max-abs size and the bit
 // mask of its nonzero rows (knorm == nullptr: neither).
+// lane src's pair (src the same in every lane: a read of one lane's registers)
 __device__ inline int2 shfl_pair(int2 v, int src) {
-    return int2{__shfl(v.x, src, 64), __shfl(v.y, src, 64)};
+    return int2{__builtin_amdgcn_readlane(v.x, src), __builtin_amdgcn_readlane(v.y, src)};
 }
 
 template <int BS>
@@ -891,7 +892,7 @@ __global__ __launch_bounds__(64) void k_rap_contrib(const int *__restrict__ rarp
             }
             int rank = 0;
             for (int l = 0; l < 64; ++l) {
-                const int pl = __shfl(p, l, 64);
+                const int pl = __builtin_amdgcn_readlane(p, l);   // (l is the same in every lane)
                 rank += (l < lane && pl == p) ? 1 : 0;
             }
             if (p >= 0) klist[R0 + off[p] + rank] = r0 + u;
