@@ -68,111 +68,6 @@ __global__ __launch_bounds__(256) void k_block_scan(const double *__restrict__ v
 
 // -------------------------------------------------- diagonal block inverse
 
-// The same LU recipe with one wave per block and four blocks per workgroup,
-// for block sizes known at compile time: the factorisation in the wave's LDS
-// slot (lanes over the trailing entries, pivot search by shuffles), then lane j
-// < BS keeps column j of the inverse in registers through the forward and
-// back substitution, reading the factors from LDS (every lane the same word)
-// and writing row i of the inverse with consecutive lanes on consecutive
-// words.  The operations and their order are those of k_block_inverse.
-template <int BS>
-__global__ __launch_bounds__(256) void k_block_inverse_wave(const int *__restrict__ rowptr,
-                                                           const int *__restrict__ colidx,
-                                                           const double *__restrict__ vals, int nb,
-                                                           const int8_t *__restrict__ skip, double *__restrict__ dinv,
-                                                           int *__restrict__ singular_min) {
-    constexpr int BB = BS * BS;
-    __shared__ double slot[4][BB];
-    __shared__ int pslot[4][BS];
-    const int w = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    double *a = slot[w];
-    int *perm = pslot[w];
-    const int I = blockIdx.x * 4 + w;
-    if (I >= nb || (skip && skip[I])) return;   // whole waves; no workgroup barrier below
-    int dpos = -1;
-    for (int t = rowptr[I] + lane; t < rowptr[I + 1]; t += kWave)
-        if (colidx[t] == I) dpos = t;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) dpos = max(dpos, __shfl_xor(dpos, o, kWave));
-    if (dpos < 0) {   // validated before; never taken for valid input
-        if (lane == 0) atomicMin(singular_min, I);
-        return;
-    }
-    const double *src = vals + static_cast<int64_t>(dpos) * BB;
-    for (int e = lane; e < BB; e += kWave) a[e] = src[e];
-    if (lane < BS) perm[lane] = lane;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    for (int k = 0; k < BS; ++k) {
-        double v = -1.0;
-        int idx = BS;
-        if (k + lane < BS) {
-            v = fabs(a[(k + lane) * BS + k]);
-            idx = k + lane;
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const double ov = __shfl_xor(v, o, kWave);
-            const int oi = __shfl_xor(idx, o, kWave);
-            if (ov > v || (ov == v && oi < idx)) {
-                v = ov;
-                idx = oi;
-            }
-        }
-        if (!(v > 0.0)) {
-            if (lane == 0) atomicMin(singular_min, I);
-            return;
-        }
-        if (idx != k) {
-            if (lane < BS) {
-                const double tmp = a[k * BS + lane];
-                a[k * BS + lane] = a[idx * BS + lane];
-                a[idx * BS + lane] = tmp;
-            }
-            if (lane == 0) {
-                const int tp = perm[k];
-                perm[k] = perm[idx];
-                perm[idx] = tp;
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const double piv = a[k * BS + k];
-        if (k + 1 + lane < BS) a[(k + 1 + lane) * BS + k] = a[(k + 1 + lane) * BS + k] / piv;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const int m = BS - k - 1;
-        for (int e = lane; e < m * m; e += kWave) {
-            const int i = k + 1 + e / m;
-            const int j = k + 1 + e % m;
-            a[i * BS + j] = __builtin_fma(-a[i * BS + k], a[k * BS + j], a[i * BS + j]);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-    }
-    if (lane >= BS) return;
-    const int j = lane;
-    double y[BS];
-#pragma unroll
-    for (int i = 0; i < BS; ++i) {
-        double sacc = (perm[i] == j) ? 1.0 : 0.0;
-#pragma unroll
-        for (int mm = 0; mm < i; ++mm) sacc = __builtin_fma(-a[i * BS + mm], y[mm], sacc);
-        y[i] = sacc;
-    }
-#pragma unroll
-    for (int i = BS - 1; i >= 0; --i) {
-        double sacc = y[i];
-#pragma unroll
-        for (int mm = i + 1; mm < BS; ++mm) sacc = __builtin_fma(-a[i * BS + mm], y[mm], sacc);
-        y[i] = sacc / a[i * BS + i];
-    }
-    double *dst = dinv + static_cast<int64_t>(I) * BB;
-#pragma unroll
-    for (int i = 0; i < BS; ++i) dst[i * BS + j] = y[i];
-}
-
 // Lane-to-lane moves within groups of a half wave for the pivot search: DPP
 // for the quad and row patterns, a swizzle for the two 16-lane rows.
 template <int CTRL>
@@ -209,9 +104,11 @@ __device__ inline void pivot_take(double &v, int &key, double ov, int okey) {
 // trade positions, the pivot row -- final from here on -- is written once to
 // row k of the half's LDS factor slot, and every lane at a later position
 // forms its multiplier and updates its row from that LDS row.  Lane j then
-// forms column j of the inverse by the forward and back substitution of
-// k_block_inverse_wave.  Same operations on the same values in the same order:
-// the same bits.
+// keeps column j of the inverse in registers through the forward and back
+// substitution, reading the factors from LDS (every lane of the half the same
+// word), and writes row i of the inverse with consecutive lanes on
+// consecutive words.  The operations and their order are those of
+// k_block_inverse: the same bits.
 template <int BS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_block_inverse_rows(const int *__restrict__ rowptr,
                                                            const int *__restrict__ colidx,
