@@ -690,12 +690,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     auto load = [&](const int2 q) {
         // (a pair's y < 0 names block -y-1 of the second store)
         const double *y = q.y >= 0 ? Y + static_cast<int64_t>(q.y) * BB : Y2 + static_cast<int64_t>(-q.y - 1) * BB;
-        const double *x = X + static_cast<int64_t>(q.x < 0 ? 0 : q.x) * BB;
+        // (an identity pair's x is never read: it loads its y block again, so that every
+        // load is unconditional -- as are the words past the block, read from its last)
+        const double *x = q.x >= 0 ? X + static_cast<int64_t>(q.x) * BB : y;
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
-            const int e = lane + 64 * i;
-            yv[i] = e < BB ? y[e] : 0.0;
-            xv[i] = (e < BB && q.x >= 0) ? x[e] : 0.0;
+            const int e = lane + 64 * i < BB ? lane + 64 * i : BB - 1;
+            yv[i] = y[e];
+            xv[i] = x[e];
         }
     };
     auto chunk = [&](int from, int end) { return from + lane < end ? pairs[from + lane] : int2{0, 0}; };
@@ -771,7 +773,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 #pragma unroll
                         for (int tj = 0; tj < NT; ++tj)
                             acc.t[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj], acc.t[ti][tj], 0, 0, 0);
-                    // (fragments are read one step ahead at most: registers for four waves per SIMD)
+                    // (one step's fragments at a time: the LDS reads are not hoisted past its MFMAs)
                     __builtin_amdgcn_sched_barrier(0);
                 }
             }
