@@ -40,7 +40,33 @@ __global__ __launch_bounds__(256) void k_block_scan(const double *__restrict__ v
     const int64_t nn = count ? min(static_cast<int64_t>(*count), n) : n;
     double m = 0.0;
     uint32_t rm = 0u, cm = 0u;
-    if (t < nn) {
+    if (t < nn && L == kWave) {
+        // a wave per block (more than 32 entries; bs <= 32, so at most 16 words per lane):
+        // every load first, then the copy and the sizes -- one memory wait per block
+        // instead of one per word
+        constexpr int kChunks = 16;
+        const double *blk = vals + (src ? static_cast<int64_t>(src[t]) : t) * bb;
+        double v[kChunks];
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) {
+            const int e = sub + kWave * i;
+            v[i] = blk[e < bb ? e : bb - 1];   // (words past the block repeat its last, unused)
+        }
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) {
+            const int e = sub + kWave * i;
+            if (e < bb) {
+                const double x = v[i];
+                if (copy) copy[t * bb + e] = x;
+                if (x != 0.0) {
+                    const int r = e / bs;
+                    rm |= 1u << r;
+                    cm |= 1u << (e - r * bs);
+                }
+                m = fmax(m, fabs(x));
+            }
+        }
+    } else if (t < nn) {
         const double *blk = vals + (src ? static_cast<int64_t>(src[t]) : t) * bb;
         for (int e = sub; e < bb; e += L) {
             const double x = blk[e];
