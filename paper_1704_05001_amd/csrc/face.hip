@@ -87,14 +87,31 @@ __global__ __launch_bounds__(256) void k_face_diag(const double *__restrict__ va
     const int bb = bs * bs;
     const double *src = vals + static_cast<int64_t>(diagpos[I]) * bb;
     double *tl = tile[w];
-    for (int e = lane; e < bb; e += 64) tl[e] = src[e];
+    // every load of the block first (bs <= 32: at most 16 words per lane; words past
+    // the block repeat its last, unused), then the tile, then the stores
+    constexpr int kChunks = 16;
+    double v[kChunks];
+#pragma unroll
+    for (int i = 0; i < kChunks; ++i) {
+        const int e = lane + 64 * i;
+        v[i] = src[e < bb ? e : bb - 1];
+    }
+#pragma unroll
+    for (int i = 0; i < kChunks; ++i) {
+        const int e = lane + 64 * i;
+        if (e < bb) tl[e] = v[i];
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     double *dst = dvals + I * bb;
-    for (int g = lane; g < bb; g += 64) {
-        const int c = g / bs, a = g - c * bs;
-        dst[g] = tl[a * bs + c];
+#pragma unroll
+    for (int i = 0; i < kChunks; ++i) {
+        const int g = lane + 64 * i;
+        if (g < bb) {
+            const int c = g / bs, a = g - c * bs;
+            dst[g] = tl[a * bs + c];
+        }
     }
 }
 
