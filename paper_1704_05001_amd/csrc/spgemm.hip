@@ -958,6 +958,8 @@ __global__ __launch_bounds__(256) void k_ap_map(int64_t nnz, const int *__restri
 }
 
 // merged block q = sum of A P block mblk[q]'s contributors, one wave per block
+// (NCH: 64-word chunks that cover a block, at most 16 for bs <= 32)
+template <int NCH>
 __global__ __launch_bounds__(256) void k_ap_merged(int nm, int bb, const int *__restrict__ mblk,
                                                   const int *__restrict__ kptr, const int *__restrict__ klist,
                                                   const double *__restrict__ A, double *__restrict__ out) {
@@ -966,13 +968,28 @@ __global__ __launch_bounds__(256) void k_ap_merged(int nm, int bb, const int *__
     for (int64_t q = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; q < nm; q += stride) {
         const int t = mblk[q];
         const int k0 = kptr[t], k1 = kptr[t + 1];
-        // contributors outermost: each one's entries load together (one wait per
-        // contributor, not per entry); every entry still sums its contributors in order
-        constexpr int kChunks = 16;   // bs <= 32: at most 1024 entries
+        // contributors outermost, two at a time: their entries load together (one wait
+        // per two contributors, not per entry); every entry still sums its contributors
+        // in order.  (Words past a block repeat its last, unused.)
+        constexpr int kChunks = NCH;
         double v[kChunks];
 #pragma unroll
         for (int i = 0; i < kChunks; ++i) v[i] = 0.0;
-        for (int k = k0; k < k1; ++k) {
+        int k = k0;
+        for (; k + 1 < k1; k += 2) {
+            const double *a0 = A + static_cast<int64_t>(klist[k]) * bb;
+            const double *a1 = A + static_cast<int64_t>(klist[k + 1]) * bb;
+            double u0[kChunks], u1[kChunks];
+#pragma unroll
+            for (int i = 0; i < kChunks; ++i) {
+                const int e = lane + 64 * i < bb ? lane + 64 * i : bb - 1;
+                u0[i] = a0[e];
+                u1[i] = a1[e];
+            }
+#pragma unroll
+            for (int i = 0; i < kChunks; ++i) v[i] = (v[i] + u0[i]) + u1[i];
+        }
+        if (k < k1) {
             const double *a = A + static_cast<int64_t>(klist[k]) * bb;
 #pragma unroll
             for (int i = 0; i < kChunks; ++i) {
@@ -1253,9 +1270,16 @@ void merge_columns(const DevBSR &A, const int *pmap, int nc, DevBSR &Z, DevBSR &
         merged->alloc(static_cast<size_t>(std::max(nm, 1)) * bb);
         DBuf<int> mblk(static_cast<size_t>(std::max(nm, 1)));
         k_ap_map<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, kptr.get(), klist.get(), midx.get(), ymap->get(), mblk.get());
-        if (nm > 0)
-            k_ap_merged<<<cap_grid((static_cast<int64_t>(nm) + 3) / 4), 256, 0, s>>>(
-                nm, bb, mblk.get(), kptr.get(), klist.get(), A.vals.get(), merged->get());
+        if (nm > 0) {
+            const unsigned g = cap_grid((static_cast<int64_t>(nm) + 3) / 4);
+            switch ((bb + 63) / 64) {
+                case 1: k_ap_merged<1><<<g, 256, 0, s>>>(nm, bb, mblk.get(), kptr.get(), klist.get(), A.vals.get(), merged->get()); break;
+                case 2: k_ap_merged<2><<<g, 256, 0, s>>>(nm, bb, mblk.get(), kptr.get(), klist.get(), A.vals.get(), merged->get()); break;
+                case 4: k_ap_merged<4><<<g, 256, 0, s>>>(nm, bb, mblk.get(), kptr.get(), klist.get(), A.vals.get(), merged->get()); break;
+                case 10: k_ap_merged<10><<<g, 256, 0, s>>>(nm, bb, mblk.get(), kptr.get(), klist.get(), A.vals.get(), merged->get()); break;
+                default: k_ap_merged<16><<<g, 256, 0, s>>>(nm, bb, mblk.get(), kptr.get(), klist.get(), A.vals.get(), merged->get()); break;
+            }
+        }
         NAIR_HIP(hipGetLastError());
         return;
     }
