@@ -968,27 +968,36 @@ __global__ __launch_bounds__(256) void k_block_gather(int64_t n, int bb, const d
 
 // The same with one wave per block (blocks of 64 entries or more): the block
 // index and its source are read once per block and the entries need no division.
+// Each wave takes two blocks per round and issues every load of both before the
+// stores (NCH: the 64-word chunks that cover a block, at most 16 for bs <= 32;
+// words past a block repeat its last, unused).
+template <int NCH>
 __global__ __launch_bounds__(256) void k_block_gather_wave(int64_t n, int bb, const double *__restrict__ Y,
                                                           const int *__restrict__ src, double *__restrict__ out,
                                                           const int *__restrict__ count) {
     const int lane = threadIdx.x & 63;
     const int64_t nblk = count ? *count : n;
     const int64_t stride = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
-    for (int64_t t = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; t < nblk; t += stride) {
-        const double *y = Y + static_cast<int64_t>(src[t]) * bb;
-        double *o = out + t * bb;
-        // every load of the block first, then the stores (bb <= 1024: at most 16 per lane)
-        constexpr int kChunks = 16;
-        double v[kChunks];
+    for (int64_t t = ((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6) * 2; t < nblk;
+         t += 2 * stride) {
+        const bool two = t + 1 < nblk;
+        const double *y0 = Y + static_cast<int64_t>(src[t]) * bb;
+        const double *y1 = two ? Y + static_cast<int64_t>(src[t + 1]) * bb : y0;
+        double v0[NCH], v1[NCH];
 #pragma unroll
-        for (int i = 0; i < kChunks; ++i) {
-            const int e = lane + 64 * i;
-            v[i] = e < bb ? y[e] : 0.0;
+        for (int i = 0; i < NCH; ++i) {
+            const int e = lane + 64 * i < bb ? lane + 64 * i : bb - 1;
+            v0[i] = y0[e];
+            v1[i] = y1[e];
         }
+        double *o = out + t * bb;
 #pragma unroll
-        for (int i = 0; i < kChunks; ++i) {
+        for (int i = 0; i < NCH; ++i) {
             const int e = lane + 64 * i;
-            if (e < bb) o[e] = v[i];
+            if (e < bb) {
+                o[e] = v0[i];
+                if (two) o[bb + e] = v1[i];
+            }
         }
     }
 }
@@ -1215,10 +1224,18 @@ void compose_term_maps(int64_t cap, const int *count, const int *srcS, std::vect
 void launch_block_gather(int64_t n, int bs, const double *Y, const int *src, double *out, hipStream_t s,
                          const int *count) {
     if (n <= 0) return;
-    if (bs * bs >= 64)
-        k_block_gather_wave<<<cap_grid((n + 3) / 4), 256, 0, s>>>(n, bs * bs, Y, src, out, count);
-    else
+    if (bs * bs >= 64) {
+        const unsigned g = cap_grid((n + 7) / 8);
+        const int bb = bs * bs;
+        switch ((bb + 63) / 64) {
+            case 2: k_block_gather_wave<2><<<g, 256, 0, s>>>(n, bb, Y, src, out, count); break;
+            case 4: k_block_gather_wave<4><<<g, 256, 0, s>>>(n, bb, Y, src, out, count); break;
+            case 10: k_block_gather_wave<10><<<g, 256, 0, s>>>(n, bb, Y, src, out, count); break;
+            default: k_block_gather_wave<16><<<g, 256, 0, s>>>(n, bb, Y, src, out, count); break;
+        }
+    } else {
         k_block_gather<<<cap_grid((n * bs * bs + 255) / 256), 256, 0, s>>>(n, bs * bs, Y, src, out, count);
+    }
     NAIR_HIP(hipGetLastError());
 }
 
