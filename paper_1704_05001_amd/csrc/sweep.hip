@@ -79,9 +79,20 @@ __global__ __launch_bounds__(256) void k_sweep_fill(const int *__restrict__ rowp
     }
     const double *Di = dinv + static_cast<int64_t>(I) * bb;
     double *Do = odinv + static_cast<int64_t>(f) * bb;
-    for (int e = lane; e < bb; e += 64) {
+    // every load of the inverse first (bs <= 32: at most 16 words per lane; words past
+    // the block repeat its last, unused), then the stores
+    constexpr int kChunks = 16;
+    double v[kChunks];
+#pragma unroll
+    for (int i = 0; i < kChunks; ++i) {
+        const int e = lane + 64 * i < bb ? lane + 64 * i : bb - 1;
         const int c = e / bs, a = e - c * bs;   // output position: input c, output a
-        Do[e] = dtrans ? Di[a * bs + c] : Di[e];
+        v[i] = Di[dtrans ? a * bs + c : e];
+    }
+#pragma unroll
+    for (int i = 0; i < kChunks; ++i) {
+        const int e = lane + 64 * i;
+        if (e < bb) Do[e] = v[i];
     }
 }
 
