@@ -1225,14 +1225,16 @@ void launch_block_gather(int64_t n, int bs, const double *Y, const int *src, dou
                          const int *count) {
     if (n <= 0) return;
     if (bs * bs >= 64) {
-        const unsigned g = cap_grid((n + 7) / 8);
+        // the instance for blocks of at most 128, 256 or 640 entries, else 16 chunks
         const int bb = bs * bs;
+        void (*kern)(int64_t, int, const double *, const int *, double *, const int *) = k_block_gather_wave<16>;
         switch ((bb + 63) / 64) {
-            case 2: k_block_gather_wave<2><<<g, 256, 0, s>>>(n, bb, Y, src, out, count); break;
-            case 4: k_block_gather_wave<4><<<g, 256, 0, s>>>(n, bb, Y, src, out, count); break;
-            case 10: k_block_gather_wave<10><<<g, 256, 0, s>>>(n, bb, Y, src, out, count); break;
-            default: k_block_gather_wave<16><<<g, 256, 0, s>>>(n, bb, Y, src, out, count); break;
+            case 2: kern = k_block_gather_wave<2>; break;
+            case 4: kern = k_block_gather_wave<4>; break;
+            case 10: kern = k_block_gather_wave<10>; break;
+            default: break;
         }
+        kern<<<cap_grid((n + 7) / 8), 256, 0, s>>>(n, bb, Y, src, out, count);
     } else {
         k_block_gather<<<cap_grid((n * bs * bs + 255) / 256), 256, 0, s>>>(n, bs * bs, Y, src, out, count);
     }

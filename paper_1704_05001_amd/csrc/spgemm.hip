@@ -1271,14 +1271,17 @@ void merge_columns(const DevBSR &A, const int *pmap, int nc, DevBSR &Z, DevBSR &
         DBuf<int> mblk(static_cast<size_t>(std::max(nm, 1)));
         k_ap_map<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, kptr.get(), klist.get(), midx.get(), ymap->get(), mblk.get());
         if (nm > 0) {
-            const unsigned g = cap_grid((static_cast<int64_t>(nm) + 3) / 4);
+            // the instance for blocks of at most 64, 128, 256 or 640 entries, else 16 chunks
+            void (*kern)(int, int, const int *, const int *, const int *, const double *, double *) = k_ap_merged<16>;
             switch ((bb + 63) / 64) {
-                case 1: k_ap_merged<1><<<g, 256, 0, s>>>(nm, bb, mblk.get(), kptr.get(), klist.get(), A.vals.get(), merged->get()); break;
-                case 2: k_ap_merged<2><<<g, 256, 0, s>>>(nm, bb, mblk.get(), kptr.get(), klist.get(), A.vals.get(), merged->get()); break;
-                case 4: k_ap_merged<4><<<g, 256, 0, s>>>(nm, bb, mblk.get(), kptr.get(), klist.get(), A.vals.get(), merged->get()); break;
-                case 10: k_ap_merged<10><<<g, 256, 0, s>>>(nm, bb, mblk.get(), kptr.get(), klist.get(), A.vals.get(), merged->get()); break;
-                default: k_ap_merged<16><<<g, 256, 0, s>>>(nm, bb, mblk.get(), kptr.get(), klist.get(), A.vals.get(), merged->get()); break;
+                case 1: kern = k_ap_merged<1>; break;
+                case 2: kern = k_ap_merged<2>; break;
+                case 4: kern = k_ap_merged<4>; break;
+                case 10: kern = k_ap_merged<10>; break;
+                default: break;
             }
+            kern<<<cap_grid((static_cast<int64_t>(nm) + 3) / 4), 256, 0, s>>>(nm, bb, mblk.get(), kptr.get(),
+                                                                             klist.get(), A.vals.get(), merged->get());
         }
         NAIR_HIP(hipGetLastError());
         return;
