@@ -113,20 +113,14 @@ __device__ inline double swz16(double v) {
     const int lo = swz16(static_cast<int>(u)), hi = swz16(static_cast<int>(u >> 32));
     return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
 }
-// (v, key) takes (ov, okey) when that one is larger, or equal with a smaller key
-__device__ inline void pivot_take(double &v, int &key, double ov, int okey) {
-    if (ov > v || (ov == v && okey < key)) {
-        v = ov;
-        key = okey;
-    }
-}
 
 // The same LU recipe with each block on a half wave and its rows in registers
 // (bs 16 and 25).  Lane r holds row r of the block for the whole factorisation
 // and tracks the position `pos` that row has in the pivoted order, so a row
 // exchange is two position updates instead of moving the rows.  Step k: the
-// first position >= k of largest |a_.k| wins (a reduction over the half by DPP
-// and one swizzle, keyed by position), its lane and the lane at position k
+// first position >= k of largest |a_.k| wins (the largest value, then the
+// smallest position among the lanes that hold it, each a reduction over the
+// half by DPP and one swizzle), its lane and the lane at position k
 // trade positions, the pivot row -- final from here on -- is written once to
 // row k of the half's LDS factor slot, and every lane at a later position
 // forms its multiplier and updates its row from that LDS row.  Lane j then
@@ -170,17 +164,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     int pos = r;   // lanes r >= BS keep positions >= BS: never candidates, never updated
 #pragma unroll
     for (int k = 0; k < BS; ++k) {
-        double v = -1.0;
-        int key = kNone;
-        if (pos >= k && pos < BS) {
-            v = fabs(a[k]);
-            key = (pos << 5) | r;
-        }
-        pivot_take(v, key, dpp_move<0xB1>(v), dpp_move<0xB1>(key));     // quad_perm 1,0,3,2
-        pivot_take(v, key, dpp_move<0x4E>(v), dpp_move<0x4E>(key));     // quad_perm 2,3,0,1
-        pivot_take(v, key, dpp_move<0x141>(v), dpp_move<0x141>(key));   // row_half_mirror
-        pivot_take(v, key, dpp_move<0x140>(v), dpp_move<0x140>(key));   // row_mirror
-        pivot_take(v, key, swz16(v), swz16(key));
+        // the largest candidate |a_.k| over the half, then the smallest key (position)
+        // among the lanes that hold it: the first position of the largest, as before
+        const bool cand = pos >= k && pos < BS;
+        const double own = cand ? fabs(a[k]) : -1.0;
+        double v = own;
+        v = fmax(v, dpp_move<0xB1>(v));     // quad_perm 1,0,3,2
+        v = fmax(v, dpp_move<0x4E>(v));     // quad_perm 2,3,0,1
+        v = fmax(v, dpp_move<0x141>(v));    // row_half_mirror
+        v = fmax(v, dpp_move<0x140>(v));    // row_mirror
+        v = fmax(v, swz16(v));
+        int key = (cand && own == v) ? (pos << 5) | r : kNone;
+        key = min(key, dpp_move<0xB1>(key));
+        key = min(key, dpp_move<0x4E>(key));
+        key = min(key, dpp_move<0x141>(key));
+        key = min(key, dpp_move<0x140>(key));
+        key = min(key, swz16(key));
         if (live && !(v > 0.0)) {
             if (r == 0) atomicMin(singular_min, I);
             live = false;
