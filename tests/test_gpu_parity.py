@@ -220,6 +220,22 @@ def test_parity_random_matrices():
     compare_hierarchies(G, O)
 
 
+@pytest.mark.parametrize("bs", [8, 12, 32])
+def test_parity_generic_block_sizes(bs):
+    """Block sizes off the specialised instances (the gather of kept blocks with
+    sixteen 64-word chunks, the generic block kernels, bs 32 at the limit): the
+    whole hierarchy bit for bit and the solve against the oracle."""
+    _need_gpu()
+    _say(f"test: random block matrix at bs {bs}")
+    nb = 200
+    rp, ci, va, order, layer = layered_block_triangular(nb, bs, 10, deps=3, seed=bs, zero_entries=0.3)
+    G, O = build_pair(nb, bs, rp, ci, va, degree=2, max_coarse_dofs=20 * bs)
+    assert O.num_levels >= 3   # (two Galerkin products, so two gathers of kept blocks)
+    compare_hierarchies(G, O)
+    b = np.random.default_rng(5).uniform(-1, 1, nb * bs)
+    check_solve(G, O, b)
+
+
 def test_cf_override_and_seed():
     _say("test: cf override and seed")
     S, k = make_config("dg_q1_32", N=10)
